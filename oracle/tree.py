@@ -1,0 +1,203 @@
+"""Index-tree bookkeeping of the oracle (test infrastructure, never product code).
+
+Follows the paper's definitions:
+  * Def. 3 (index tree): each internal node is the disjoint union of its children
+    (the "contains" of the definition is read as equality; free modes are rejected).
+  * Def. 4 / Def. 5 (dummy nodes): a childless node above the deepest level is a leaf;
+    dummies carry identity DRMs and projectors and are never materialised.
+  * Fig. 1 labels: nodes are numbered level by level, left to right by smallest mode,
+    root = 0.
+  * Sec. 5 (STTNN ordering) and Fig. 5: node t reuses the contractions of the set
+    S_t = preceding siblings of t together with the preceding siblings of every
+    ancestor of t (the reading that reproduces all nine panels of Fig. 5).
+
+Tree specs are nested Python tuples of 1-based modes: an int is a one-mode leaf,
+a frozenset of ints a multi-mode leaf, a tuple an internal node whose children are
+listed left to right.  Every node must cover a contiguous interval of modes.
+"""
+
+from dataclasses import dataclass, field
+
+
+class TreeError(ValueError):
+    pass
+
+
+@dataclass
+class Node:
+    id: int
+    modes: tuple          # 1-based modes, ascending, contiguous
+    level: int
+    parent: int           # -1 for the root
+    children: list = field(default_factory=list)
+    rank: int = 0         # r_t (unused at the root)
+    over: int = 0         # p_t (unused at the root)
+
+    @property
+    def first(self):
+        return self.modes[0]
+
+    @property
+    def last(self):
+        return self.modes[-1]
+
+    @property
+    def is_leaf(self):
+        return not self.children
+
+    @property
+    def k(self):
+        """Column count of the left DRM, r_t + p_t (eq. "sketch" of Sec. 4)."""
+        return self.rank + self.over
+
+
+def _modes_of(spec):
+    if isinstance(spec, int):
+        return (spec,)
+    if isinstance(spec, frozenset):
+        return tuple(sorted(spec))
+    if isinstance(spec, tuple):
+        out = ()
+        for c in spec:
+            out += _modes_of(c)
+        return out
+    raise TreeError(f"bad tree spec element {spec!r}")
+
+
+class Tree:
+    """A validated index tree with level-order numbering.
+
+    rank / over may be ints (same for every non-root node) or dicts keyed by the
+    tuple of modes of a node.
+    """
+
+    def __init__(self, spec, dims, rank, over):
+        self.dims = tuple(int(n) for n in dims)
+        self.d = len(self.dims)
+        if self.d < 2:
+            raise TreeError("order must be at least 2")
+        if not isinstance(spec, tuple):
+            raise TreeError("root must be an internal node")
+        root_modes = _modes_of(spec)
+        if sorted(root_modes) != list(range(1, self.d + 1)):
+            raise TreeError("root must cover every mode exactly once")
+
+        # breadth-first traversal with children left to right gives level order
+        self.nodes = []
+        queue = [(spec, -1, 0)]
+        while queue:
+            nxt = []
+            for s, par, lev in queue:
+                modes = _modes_of(s)
+                if list(modes) != list(range(modes[0], modes[-1] + 1)):
+                    raise TreeError(f"node {modes} is not a contiguous interval in order")
+                nid = len(self.nodes)
+                node = Node(nid, modes, lev, par)
+                self.nodes.append(node)
+                if par >= 0:
+                    self.nodes[par].children.append(nid)
+                if isinstance(s, tuple):
+                    if len(s) < 1:
+                        raise TreeError("internal node without children")
+                    if len(s) == 1 and lev > 0:
+                        raise TreeError("internal node with a single child equal to itself")
+                    for c in s:
+                        nxt.append((c, nid, lev + 1))
+            queue = nxt
+        # within a level, order is by smallest mode: true by construction, check anyway
+        for a, b in zip(self.nodes, self.nodes[1:]):
+            if a.level == b.level and a.first >= b.first:
+                raise TreeError("level order violated")
+        self.depth = max(n.level for n in self.nodes)
+
+        for n in self.nodes[1:]:
+            key = n.modes
+            n.rank = int(rank[key] if isinstance(rank, dict) else rank)
+            n.over = int(over[key] if isinstance(over, dict) else over)
+            if n.rank < 1 or n.over < 0:
+                raise TreeError("ranks must be >= 1 and oversamples >= 0")
+
+    # ------------------------------------------------------------------ helpers
+    def __len__(self):
+        return len(self.nodes)
+
+    def __getitem__(self, i):
+        return self.nodes[i]
+
+    def n_of(self, node_id):
+        """n_{I_t}: product of the mode sizes of node t."""
+        p = 1
+        for m in self.nodes[node_id].modes:
+            p *= self.dims[m - 1]
+        return p
+
+    def by_modes(self, modes):
+        for n in self.nodes:
+            if n.modes == tuple(modes):
+                return n.id
+        raise KeyError(modes)
+
+    def ancestors(self, t):
+        out = []
+        p = self.nodes[t].parent
+        while p >= 0:
+            out.append(p)
+            p = self.nodes[p].parent
+        return out
+
+    def preceding_siblings(self, t):
+        p = self.nodes[t].parent
+        if p < 0:
+            return []
+        sib = self.nodes[p].children
+        return sib[: sib.index(t)]
+
+    def S(self, t):
+        """STTNN set S_t (Sec. 5, Fig. 5), ordered left to right by smallest mode."""
+        if t == 0:
+            return []
+        out = list(self.preceding_siblings(t))
+        for a in self.ancestors(t):
+            out += self.preceding_siblings(a)
+        return sorted(out, key=lambda s: self.nodes[s].first)
+
+    def x_rows_ttnn(self, t):
+        """Rows of X_t in TTNN: n_{D \\ I_t} (eq. "sketch" of Sec. 4)."""
+        p = 1
+        for m in range(1, self.d + 1):
+            if m not in self.nodes[t].modes:
+                p *= self.dims[m - 1]
+        return p
+
+    def x_shape_sttnn(self, t):
+        """Index sizes of the rows of X_t in STTNN, first index fastest.
+
+        The contracted tensor keeps every contracted group in place as a single
+        index of size r_s + p_s; the row index of X_t runs over all indices of that
+        tensor except those of I_t, in positional order.
+        """
+        node = self.nodes[t]
+        sizes = []
+        covered = set()
+        for s in self.S(t):
+            sizes.append(self.nodes[s].k)
+            covered.update(self.nodes[s].modes)
+        for m in range(1, self.d + 1):
+            if m in node.modes or m in covered:
+                continue
+            sizes.append(self.dims[m - 1])
+        return sizes
+
+    def x_rows(self, t, variant):
+        if variant == "ttnn":
+            return self.x_rows_ttnn(t)
+        p = 1
+        for s in self.x_shape_sttnn(t):
+            p *= s
+        return p
+
+
+# Trees used by the paper and by the workloads --------------------------------
+TOY = (((1, 2), 3), 4, (5, 6))          # Fig. 1
+T4 = ((1, 2), (3, 4))                   # balanced binary tree on four modes
+T5 = (((1, 2), 3), (4, 5))              # order-5 tree of the streaming workload
