@@ -1,0 +1,244 @@
+"""Benchmark of the TTNN / STTNN sketch phase on one MI355X.
+
+Workload: order-4 tensor 128^4 (268,435,456 entries) on the balanced binary tree
+((1,2),(3,4)), built as a tree tensor network with edge ranks 24 and singular values
+0.8^k on every edge, normalised to unit RMS plus N(0, 1e-4^2) noise; Gaussian DRMs,
+sketch rank r = 32, oversampling p = 16; the whole tensor resident in HBM is
+sketched in one pass and the TTN cores are assembled in FP64.
+
+One step = sketch update of the whole tensor (fused one-pass kernel + deterministic
+reduction) + FP64 epilogue + recovery phase (QR, Jacobi SVD, eps-pseudoinverse,
+cores).  DRM generation happens once per plan, before timing.
+
+    python bench.py [--steps K] [--warmup W] [--variants ttnn,sttnn] [--dtypes f32,f64,bf16]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sketch ingest GB/s (% HBM roofline) + p50/p99 update latency, bf16/fp32 vs fp64"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2516.6, "f32": 157.3, "f64": 78.6}
+ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--rank", type=int, default=32)
+    ap.add_argument("--over", type=int, default=16)
+    ap.add_argument("--variants", default="ttnn,sttnn")
+    ap.add_argument("--dtypes", default="f32,f64,bf16")
+    ap.add_argument("--headline", default="sttnn:f32")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-error", action="store_true")
+    return ap.parse_args()
+
+
+# ---------------------------------------------------------------- work counts
+def work_counts(tree, variant):
+    """Leading-order flops and algorithmic bytes (entries) of one sketch pass.
+
+    Flops: every contraction of the sketch phase, 2 * (entries of its input) * (columns
+    of its DRM).  DRM entries: every DRM the pass reads, once."""
+    N = 1
+    for n in tree.dims:
+        N *= n
+    sizes = {}
+
+    def size_after(prefix):
+        if not prefix:
+            return N
+        e = 1
+        for s in prefix:
+            e *= tree[s].k
+        for m in range(tree[prefix[-1]].last + 1, tree.d + 1):
+            e *= tree.dims[m - 1]
+        return e
+
+    flops = 0
+    done = set()
+    drm_entries = 0
+    used_y = set()
+
+    def chain_cost(prefix):
+        nonlocal flops
+        for j in range(1, len(prefix) + 1):
+            pf = tuple(prefix[:j])
+            if pf in done:
+                continue
+            done.add(pf)
+            flops += 2 * size_after(list(pf[:-1])) * tree[pf[-1]].k
+            used_y.add(pf[-1])
+
+    for n in tree.nodes[1:]:
+        S = tree.S(n.id) if variant == "sttnn" else []
+        chain_cost(S)
+        flops += 2 * size_after(S) * n.rank
+        drm_entries += tree.x_rows(n.id, variant) * n.rank
+    rc = tree[0].children
+    chain_cost(rc)
+    for s in used_y:
+        drm_entries += tree.n_of(s) * tree[s].k
+    return flops, drm_entries, N
+
+
+# ---------------------------------------------------------------- GPU run
+def run_gpu(args, T_dev64, variant, dtype):
+    import torch
+    import paper_2412_06111_amd as P
+    from oracle.tree import T4
+
+    dims = (args.n,) * 4
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    plan = P.Plan(T4, dims, args.rank, args.over, variant=variant, dtype=dtype, seed=1)
+    t1.record()
+    torch.cuda.synchronize()
+    drm_ms = t0.elapsed_time(t1)
+    if dtype == "f64":
+        X = T_dev64
+    elif dtype == "f32":
+        X = T_dev64.to(torch.float32)
+    else:
+        X = T_dev64.to(torch.float32).to(torch.bfloat16)
+    cores = plan.alloc_cores()
+
+    def step(ev=None):
+        plan.reset()
+        if ev is not None:
+            ev[0].record(stream)
+        plan.update(X)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.assemble(cores)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    tic = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    toc = time.perf_counter()
+    ms_step = (toc - tic) * 1e3 / args.steps
+    sketch_ms = [a.elapsed_time(b) for a, b in evs]
+    res = {"ms_per_step": ms_step, "sketch_ms_avg": sum(sketch_ms) / len(sketch_ms),
+           "sketch_ms_min": min(sketch_ms), "drm_generation_ms": drm_ms, "footprint_bytes": plan.footprint()}
+    if not args.no_error:
+        That = plan.reconstruct(cores)
+        e2, n2 = P.diff_norms(That, T_dev64)
+        res["approx_rel_error"] = (e2 / n2) ** 0.5
+        del That
+    del X
+    plan.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(T, tree, variant, seed=1, box=64):
+    """The FP64 oracle on a bounded sample of the same workload: the corner box of
+    size box^4 as a streaming update (DRM rows generated before timing)."""
+    import numpy as np
+    from oracle.sketch import box_drms, sketch_box
+    blk = np.ascontiguousarray(T[:box, :box, :box, :box])
+    off = (0, 0, 0, 0)
+    drms = box_drms(tree, seed, variant, off, blk.shape)
+    tic = time.perf_counter()
+    sketch_box(blk, off, tree, seed, variant, drms=drms)
+    dt = time.perf_counter() - tic
+    return {"value": blk.size * 8 / dt / 1e9, "unit": "GB/s", "cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
+            "sample": f"{variant} sketch of the {box}^4 corner box of the 128^4 workload as one streaming "
+                      f"update, FP64 NumPy; DRM rows generated before timing; {dt:.2f} s",
+            "seconds": dt}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the sketch path has no multi-GPU mode in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import oracle as O
+    from workloads import synth as W
+
+    t_gen = time.perf_counter()
+    T = W.config2_tensor(n=args.n)
+    T_dev64 = torch.from_numpy(np.ascontiguousarray(W.flat_colmajor(T))).cuda()
+    t_gen = time.perf_counter() - t_gen
+    tree_def = O.Tree(O.T4, T.shape, args.rank, args.over)
+
+    results = {}
+    for variant in args.variants.split(","):
+        for dtype in args.dtypes.split(","):
+            r = run_gpu(args, T_dev64, variant, dtype)
+            flops, drm_entries, N = work_counts(tree_def, variant)
+            r["flops"] = flops
+            r["algorithmic_bytes"] = N * ESIZE[dtype] + drm_entries * ESIZE[dtype]
+            r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
+            r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
+            r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
+            results[f"{variant}:{dtype}"] = r
+            print(f"# {variant} {dtype}: {json.dumps(r)}", file=sys.stderr, flush=True)
+
+    hv, hd = args.headline.split(":")
+    head = results[args.headline]
+    t_hbm = head["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_mfma = head["flops"] / (MFMA_PEAK_TFLOPS[hd] * 1e12)
+    if t_mfma > t_hbm:
+        roof = {"bound": "mfma", "achieved": head["sketch_TFLOPs"], "peak": MFMA_PEAK_TFLOPS[hd], "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": head["sketch_GBps_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "sketch phase of one whole-tensor update (event-timed on the launch stream)"
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(T, tree_def, hv)
+
+    line = {
+        "metric": METRIC,
+        "value": head["ingest_GBps"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": hd,
+        "data": "synthetic",
+        "config": {"workload": f"{hv.upper()} one-pass sketch + FP64 assembly, {args.n}^4 tensor on ((1,2),(3,4)), "
+                               f"TTN ranks 24 with 0.8^k spectra + 1e-4 noise, r={args.rank}, p={args.over}",
+                   "variant": hv, "n": args.n, "rank": args.rank, "oversample": args.over,
+                   "tensor_bytes": head["algorithmic_bytes"] and (args.n ** 4) * ESIZE[hd]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "results": results,
+        "input_generation_s": t_gen,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

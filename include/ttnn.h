@@ -1,0 +1,205 @@
+/*
+ * ttnn.h -- C ABI of the MI355X sketching engine for the tree tensor network
+ * Nystrom method (TTNN) and its sequential variant (STTNN).
+ *
+ * Paper: A. Bucci, G. Verzella, "Randomized algorithms for streaming low-rank
+ * approximation in tree tensor network format" (arXiv 2412.06111).
+ *
+ *   problem statement ........ Sec. 4, first paragraph, and the inputs of Alg. 2:
+ *                              tensor of size n_1 x ... x n_d, index tree, TTN
+ *                              ranks r_t and oversamples p_t (Sec. 4, eq. "sketch")
+ *   sketch phase ............. Sec. 4 ("Sketch phase"): Omega_t = Y_t^T T^{t} X_t,
+ *                              Psi_t for root / internal / leaf nodes
+ *   sequential variant ....... Sec. 5 (projections on contracted tensors, node order)
+ *   recovery phase ........... Sec. 4 ("Recovery phase"), Alg. 2, stabilised
+ *                              least squares with eps = 10 u ||R||_2
+ *   streaming ................ Sec. 4, paragraph after the recovery phase: the
+ *                              sketches of T = sum_i lambda_i H_i are the sums of
+ *                              the sketches of the H_i
+ *   TTN format ............... Def. 5 and its matricised form (reconstruction)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Layout: every dense tensor is column-major, mode 1 fastest: entry
+ *    (i_1, ..., i_d) (0-based) sits at sum_mu i_mu prod_{nu<mu} n_nu.  This is the
+ *    index order of the matricisation of Def. 2.  A C-contiguous array of shape
+ *    (n_d, ..., n_1) has exactly this layout.
+ *  - Pointers named d_* are HIP device pointers; everything else is host memory.
+ *    `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *  - Node ids in the ABI are the caller's ids: the positions in the parent[] /
+ *    first_mode[] / last_mode[] arrays of the problem.  Internally the library
+ *    renumbers nodes level by level, left to right (the labels of Fig. 1); that
+ *    level-order id is the one that seeds the node's DRMs.
+ *  - Asynchrony: calls enqueue work on `stream` and return.  Argument checks are
+ *    done on the host before anything is enqueued and are reported synchronously.
+ *    A failed HIP call makes the plan's status sticky (TTNN_E_HIP): later calls on
+ *    that plan return it until ttnn_reset.  Input buffers must stay valid until
+ *    the stream has passed the call.
+ *  - Ownership: the caller owns every buffer it passes.  A plan owns its device
+ *    memory (DRMs, FP64 accumulators, scratch), allocated in ttnn_plan_create and
+ *    released by ttnn_destroy.  ttnn_footprint_bytes reports its size.
+ *  - Threads: one host thread per plan at a time; distinct plans are independent.
+ *  - Errors: no exception or abort crosses the ABI.  ttnn_last_error() returns a
+ *    thread-local message describing the last non-OK status.
+ */
+#ifndef TTNN_H
+#define TTNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TTNN_MAX_ORDER 8
+#define TTNN_MAX_NODES 64
+
+typedef struct ttnn_plan_s* ttnn_plan_t;
+
+typedef enum {
+  TTNN_OK = 0,
+  TTNN_E_INVALID = -1,  /* bad argument (null pointer, size, enum value)           */
+  TTNN_E_TREE = -2,     /* the index tree violates Def. 3 as read by this library   */
+  TTNN_E_RANGE = -3,    /* an update box or node id lies outside the tensor / tree  */
+  TTNN_E_NOMEM = -4,    /* device allocation failed                                */
+  TTNN_E_HIP = -5,      /* a HIP runtime call failed (sticky)                      */
+  TTNN_E_STATE = -6,    /* call out of order (e.g. reconstruct before assemble)    */
+  TTNN_E_NUMERIC = -7   /* non-finite sketch, or a node whose Omega has rank 0     */
+} ttnn_status;
+
+typedef enum { TTNN_TTNN = 0, TTNN_STTNN = 1 } ttnn_variant;
+
+/* Storage / multiply precision of the tensor, of the DRM copies read by the hot
+ * kernels and of the MFMA inputs.  Accumulators and the whole recovery phase are
+ * FP64 regardless. */
+typedef enum { TTNN_F64 = 0, TTNN_F32 = 1, TTNN_BF16 = 2 } ttnn_dtype;
+
+/* Sketch kinds readable through ttnn_read_sketch (all FP64, column-major):
+ *   R      right sketch R_t = T^{t} X_t (STTNN: on the contracted tensor), n_t x r_t
+ *   OMEGA  intersection sketch Omega_t = Y_t^T R_t, (r_t + p_t) x r_t
+ *   PSI    leaf: R_t; internal: (Y_cm^T kron ... kron Y_c1^T) R_t, prod(r_c+p_c) x r_t
+ *          (child c1 is the fastest index); root: T contracted with Y_c^T over every
+ *          child, prod(r_c + p_c) x 1 */
+typedef enum { TTNN_SK_R = 0, TTNN_SK_OMEGA = 1, TTNN_SK_PSI = 2 } ttnn_sketch_kind;
+
+/* The problem of Sec. 4 / Alg. 2 plus the DRM seed and the precision.
+ * Tree: node i has parent parent[i] (-1 for exactly one node, the root) and covers
+ * the contiguous 0-based mode interval [first_mode[i], last_mode[i]].  The root
+ * covers [0, order-1]; every internal node is the disjoint union of its children
+ * (Def. 3 with equality).  Children of a node are ordered by first mode.
+ * rank[i] = r_t >= 1 and oversample[i] = p_t >= 0 for non-root nodes (ignored at
+ * the root).  eps_factor: the pseudo-inverse keeps singular values of R_t above
+ * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52. */
+typedef struct {
+  int32_t order;
+  const int64_t* dims;
+  int32_t num_nodes;
+  const int32_t* parent;
+  const int32_t* first_mode;
+  const int32_t* last_mode;
+  const int32_t* rank;
+  const int32_t* oversample;
+  int32_t variant;   /* ttnn_variant */
+  int32_t dtype;     /* ttnn_dtype   */
+  uint64_t seed;
+  double eps_factor;
+} ttnn_problem;
+
+/* Validate the problem, allocate the plan's device memory, and generate every DRM
+ * on `stream`: X_t (m_t x r_t) and Y_t (n_t x (r_t + p_t)) with i.i.d. N(0,1) entries
+ * (Sec. 4, eq. "sketch"; Gaussian maps as assumed by Lemma 4 and Theorem 2).  Entry
+ * (row, col) of map kind (0 = X, 1 = Y) of level-order node v is Box-Muller applied
+ * to Philox4x32-10 (Salmon et al., SC'11) with counter (lo32 row, hi32 row, col,
+ * 2 v + kind) and key (lo32 seed, hi32 seed), using the 53 high bits of each 64-bit
+ * half as u1 = (a + 1) 2^-53 and u2 = b 2^-53, and fixed-order binary64 series for
+ * ln and cos(2 pi .) so that the FP64 value is reproducible bit for bit; the FP32
+ * copy is its round-to-nearest value and the BF16 copy the round-to-nearest-even of
+ * the FP32 bits.  Rows of X_t run column-major over the modes outside I_t (TTNN) or
+ * over the indices of the contracted tensor outside I_t (STTNN, contracted groups
+ * kept in place); rows of Y_t run column-major over I_t.  Accumulators start at 0. */
+ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_plan_t* out);
+ttnn_status ttnn_destroy(ttnn_plan_t plan);
+
+/* Device bytes owned by the plan (DRMs in FP64 and in the compute dtype, FP64
+ * accumulators, cores and scratch).  Used for admission by footprint. */
+size_t ttnn_footprint_bytes(ttnn_plan_t plan);
+
+/* Streaming update (Sec. 4, linearity): add alpha * sketch(H) to the accumulators,
+ * where H is zero outside the box [offset, offset + extent) and equals the packed
+ * column-major block d_block (extent[0] fastest, plan dtype) inside it.  The whole
+ * tensor is offset = 0, extent = dims.  Empty boxes are a no-op. */
+ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset,
+                               const int64_t* extent, double alpha, void* stream);
+
+/* Rank-1 update H = a_1 o a_2 o ... o a_d: d_factors is a host array of `order`
+ * device pointers to FP64 vectors of length n_mu. */
+ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_factors,
+                                     double alpha, void* stream);
+
+/* Several box updates, possibly for different plans, in one call.  Updates of plans
+ * with the same tree shape, variant and dtype are batched into shared kernel
+ * launches; for a given plan the result equals applying its updates one by one
+ * (bitwise, the reduction order depends only on each update's own box). */
+typedef struct {
+  ttnn_plan_t plan;
+  const void* d_block;
+  int64_t offset[TTNN_MAX_ORDER];
+  int64_t extent[TTNN_MAX_ORDER];
+  double alpha;
+} ttnn_update_desc;
+ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs, void* stream);
+
+/* Shape of node `node`'s core (column-major, parent rank index last):
+ *   leaf (n_t, r_t); internal (r_c1, ..., r_cm, r_t); root (r_c1, ..., r_cm). */
+ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64_t* shape);
+
+/* Recovery phase (Sec. 4, Alg. 2; internal nodes at every level >= 1):
+ *   [Q_t, Rt_t] = qr(Omega_t) with diag(Rt_t) >= 0;  Rt_t^{+eps} by one-sided Jacobi SVD;
+ *   leaf B_t = Psi_t Rt_t^{+eps}; internal B_t = (kron Q_c^T) Psi_t Rt_t^{+eps};
+ *   root B_0 = (kron Q_c^T) Psi_0.
+ * All in FP64 on the GPU.  d_cores: host array of num_nodes device pointers (caller
+ * node ids), each with room for prod(core shape) doubles.  Returns TTNN_E_NUMERIC
+ * (after writing the cores) if a sketch was not finite; the flag is read back
+ * synchronously, so this call synchronises `stream`. */
+ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream);
+
+/* Dense reconstruction (Def. 5, matricised form) from cores laid out as written by
+ * ttnn_assemble: d_out receives prod(dims) values of dtype out_dtype, column-major. */
+ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, void* d_out,
+                             int32_t out_dtype, void* stream);
+
+/* Squared Frobenius norms ||a - b||^2 and ||b||^2 of two dense arrays of n entries,
+ * a of dtype a_dtype, b FP64 (error of a reconstruction).  Deterministic; synchronises
+ * `stream` and writes h_out[0..1]. */
+ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n,
+                            double* h_out, void* stream);
+
+/* Parity hooks. */
+ttnn_status ttnn_sketch_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows,
+                              int64_t* cols);
+ttnn_status ttnn_read_sketch(ttnn_plan_t plan, int32_t node, int32_t kind, double* d_out,
+                             void* stream);
+/* DRM of node `node` (kind 0 = X, 1 = Y) as stored for `dtype` (FP64 master, or the
+ * FP32 / BF16 copy of an F32 / BF16 plan), row-major rows x cols; BF16 as uint16. */
+ttnn_status ttnn_drm_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows,
+                           int64_t* cols);
+ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t dtype,
+                          void* d_out, void* stream);
+
+/* Canonical (level-order) id of caller node `node`, and the STTNN reuse set S_t
+ * (Sec. 5, Fig. 5) as caller ids, left to right. */
+ttnn_status ttnn_level_id(ttnn_plan_t plan, int32_t node, int32_t* level_id);
+ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32_t* ids);
+
+/* Zero the accumulators and clear a sticky error. */
+ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream);
+
+const char* ttnn_status_string(ttnn_status s);
+const char* ttnn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TTNN_H */

@@ -139,3 +139,79 @@ def sketch_update(state, block, offset, alpha, tree: Tree, D: DRMs, variant: str
         for i, v in d.items():
             state[k][i] = state[k][i] + alpha * v
     return state
+
+
+def _box_rows(dims, modes, off, ext):
+    """Column-major row indices (over `modes`) of the box entries, first fastest."""
+    idx = np.zeros(1, dtype=np.int64)
+    stride = 1
+    for m in modes:
+        r = np.arange(off[m - 1], off[m - 1] + ext[m - 1], dtype=np.int64) * stride
+        idx = (idx[:, None] + r[None, :]).reshape(-1, order="F")
+        stride *= dims[m - 1]
+    return idx
+
+
+def box_drms(tree: Tree, seed: int, variant: str, offset, ext):
+    """The DRM rows a box update touches: Y_s rows over the box for every group that
+    is contracted (STTNN reuse sets and root children), X_t rows over the box
+    (full range on contracted indices) for every non-root t."""
+    from .drm import gaussian
+    dims = tree.dims
+    off = tuple(int(o) for o in offset)
+    ext = tuple(int(e) for e in ext)
+    groups = set(tree[0].children)
+    if variant == "sttnn":
+        for n in tree.nodes[1:]:
+            groups.update(tree.S(n.id))
+    Y = {}
+    for s in sorted(groups):
+        rows = _box_rows(dims, tree[s].modes, off, ext)
+        Y[s] = gaussian(seed, s, 1, rows[:, None].astype(np.uint64), np.arange(tree[s].k, dtype=np.uint64)[None, :])
+    X = {}
+    for n in tree.nodes[1:]:
+        S = tree.S(n.id) if variant == "sttnn" else []
+        sizes, offs, exts = [], [], []
+        for sg in S:
+            sizes.append(tree[sg].k), offs.append(0), exts.append(tree[sg].k)
+        for m in range(1, tree.d + 1):
+            if m in n.modes or any(m in tree[sg].modes for sg in S):
+                continue
+            sizes.append(dims[m - 1]), offs.append(off[m - 1]), exts.append(ext[m - 1])
+        rows = np.zeros(1, dtype=np.int64)
+        stride = 1
+        for sz, o, e in zip(sizes, offs, exts):
+            rows = (rows[:, None] + (np.arange(o, o + e, dtype=np.int64) * stride)[None, :]).reshape(-1, order="F")
+            stride *= sz
+        X[n.id] = gaussian(seed, n.id, 0, rows[:, None].astype(np.uint64), np.arange(n.rank, dtype=np.uint64)[None, :])
+    return {"X": X, "Y": Y}
+
+
+def sketch_box(block, offset, tree: Tree, seed: int, variant: str, drms=None):
+    """Sketch of the tensor equal to `block` on the box at `offset` and zero elsewhere
+    (the streaming update of Sec. 4), using only the DRM rows the box touches
+    (box_drms).  Same result as sketch() on the zero-padded tensor."""
+    block = np.asarray(block, dtype=np.float64)
+    ext = block.shape
+    off = tuple(int(o) for o in offset)
+    if drms is None:
+        drms = box_drms(tree, seed, variant, off, ext)
+    X, Y = drms["X"], drms["Y"]
+
+    def chain(prefix):
+        Z = block
+        for pos, s in enumerate(prefix):
+            Z = group_product(Z, range(pos, pos + len(tree[s].modes)), Y[s])
+        return Z
+
+    R = {}
+    for n in tree.nodes[1:]:
+        S = tree.S(n.id) if variant == "sttnn" else []
+        Z = chain(S)
+        first = len(S) if S else n.first - 1
+        tax = list(range(first, first + len(n.modes)))
+        full = np.zeros((tree.n_of(n.id), n.rank))
+        full[_box_rows(tree.dims, n.modes, off, ext)] = unfold(Z, tax) @ X[n.id]
+        R[n.id] = full
+    Zr = chain(tree[0].children)
+    return {"R": R, "Psi_root": Zr.reshape(-1, order="F")}

@@ -1,0 +1,293 @@
+"""ctypes binding of libttnn.so (argument marshalling only).
+
+Every computation happens in the library's HIP kernels; PyTorch is used for
+device memory and streams.  Importing this module fails loudly when the library
+has not been built.
+"""
+
+import ctypes as C
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libttnn.so")
+
+F64, F32, BF16 = 0, 1, 2
+TTNN, STTNN = 0, 1
+SK_R, SK_OMEGA, SK_PSI = 0, 1, 2
+MAX_ORDER = 8
+
+TORCH_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
+DTYPE_NAME = {F64: "f64", F32: "f32", BF16: "bf16"}
+DTYPE_OF_NAME = {"f64": F64, "f32": F32, "bf16": BF16}
+VARIANT_OF_NAME = {"ttnn": TTNN, "sttnn": STTNN}
+
+
+class TTNNError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ttnn status {status}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("order", C.c_int32), ("dims", C.POINTER(C.c_int64)),
+        ("num_nodes", C.c_int32), ("parent", C.POINTER(C.c_int32)),
+        ("first_mode", C.POINTER(C.c_int32)), ("last_mode", C.POINTER(C.c_int32)),
+        ("rank", C.POINTER(C.c_int32)), ("oversample", C.POINTER(C.c_int32)),
+        ("variant", C.c_int32), ("dtype", C.c_int32), ("seed", C.c_uint64), ("eps_factor", C.c_double),
+    ]
+
+
+class UpdateDesc(C.Structure):
+    _fields_ = [
+        ("plan", C.c_void_p), ("d_block", C.c_void_p),
+        ("offset", C.c_int64 * MAX_ORDER), ("extent", C.c_int64 * MAX_ORDER), ("alpha", C.c_double),
+    ]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2412_06111_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P64 = C.POINTER(i64)
+    sigs = {
+        "ttnn_plan_create": [C.POINTER(Problem), vp, C.POINTER(vp)],
+        "ttnn_destroy": [vp],
+        "ttnn_sketch_update": [vp, vp, P64, P64, dbl, vp],
+        "ttnn_sketch_update_rank1": [vp, C.POINTER(vp), dbl, vp],
+        "ttnn_sketch_update_batched": [i32, C.POINTER(UpdateDesc), vp],
+        "ttnn_core_shape": [vp, i32, C.POINTER(i32), P64],
+        "ttnn_assemble": [vp, C.POINTER(vp), vp],
+        "ttnn_reconstruct": [vp, C.POINTER(vp), vp, i32, vp],
+        "ttnn_diff_norms": [vp, i32, vp, i64, C.POINTER(dbl), vp],
+        "ttnn_sketch_shape": [vp, i32, i32, P64, P64],
+        "ttnn_read_sketch": [vp, i32, i32, vp, vp],
+        "ttnn_drm_shape": [vp, i32, i32, P64, P64],
+        "ttnn_read_drm": [vp, i32, i32, i32, vp, vp],
+        "ttnn_level_id": [vp, i32, C.POINTER(i32)],
+        "ttnn_reuse_set": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
+        "ttnn_reset": [vp, vp],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.ttnn_footprint_bytes.argtypes = [vp]
+    lib.ttnn_footprint_bytes.restype = C.c_size_t
+    lib.ttnn_status_string.argtypes = [C.c_int]
+    lib.ttnn_status_string.restype = C.c_char_p
+    lib.ttnn_last_error.argtypes = []
+    lib.ttnn_last_error.restype = C.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def check(status):
+    if status != 0:
+        raise TTNNError(status, (lib.ttnn_last_error() or b"").decode())
+
+
+def stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------- trees
+def _modes(spec):
+    if isinstance(spec, int):
+        return (spec,)
+    if isinstance(spec, frozenset):
+        return tuple(sorted(spec))
+    out = ()
+    for c in spec:
+        out += _modes(c)
+    return out
+
+
+def tree_arrays(spec):
+    """Nested-tuple tree (1-based modes) -> caller arrays in depth-first order.
+    Returns (parent, first, last, modes_of_node)."""
+    parent, first, last, modes = [], [], [], []
+
+    def walk(s, par):
+        m = _modes(s)
+        me = len(parent)
+        parent.append(par)
+        first.append(m[0] - 1)
+        last.append(m[-1] - 1)
+        modes.append(m)
+        if isinstance(s, tuple):
+            for c in s:
+                walk(c, me)
+
+    walk(spec, -1)
+    return parent, first, last, modes
+
+
+class Plan:
+    """A sketching plan: problem of Sec. 4 / Alg. 2 plus seed and precision."""
+
+    def __init__(self, spec, dims, rank, over, variant="ttnn", dtype="f64", seed=1, eps_factor=0.0,
+                 stream=None):
+        self.spec, self.dims = spec, tuple(int(n) for n in dims)
+        self.d = len(self.dims)
+        self.variant = VARIANT_OF_NAME[variant] if isinstance(variant, str) else int(variant)
+        self.dtype = DTYPE_OF_NAME[dtype] if isinstance(dtype, str) else int(dtype)
+        par, fst, lst, modes = tree_arrays(spec)
+        self.node_modes = modes
+        self.node_of_modes = {m: i for i, m in enumerate(modes)}
+        nn = len(par)
+        rk = [int(rank[m] if isinstance(rank, dict) else rank) if i else 0 for i, m in enumerate(modes)]
+        ov = [int(over[m] if isinstance(over, dict) else over) if i else 0 for i, m in enumerate(modes)]
+        self._arrays = (
+            (C.c_int64 * self.d)(*self.dims), (C.c_int32 * nn)(*par), (C.c_int32 * nn)(*fst),
+            (C.c_int32 * nn)(*lst), (C.c_int32 * nn)(*rk), (C.c_int32 * nn)(*ov),
+        )
+        a = self._arrays
+        self.problem = Problem(self.d, a[0], nn, a[1], a[2], a[3], a[4], a[5], self.variant, self.dtype,
+                               C.c_uint64(int(seed)), float(eps_factor))
+        self.num_nodes = nn
+        self.handle = C.c_void_p()
+        check(lib.ttnn_plan_create(C.byref(self.problem), stream_ptr(stream), C.byref(self.handle)))
+
+    # ------------------------------------------------------------ lifetime
+    def close(self):
+        if self.handle:
+            lib.ttnn_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def torch_dtype(self):
+        return TORCH_DTYPE[self.dtype]
+
+    def footprint(self):
+        return int(lib.ttnn_footprint_bytes(self.handle))
+
+    def node(self, modes):
+        return self.node_of_modes[tuple(modes)]
+
+    # ------------------------------------------------------------ sketch phase
+    def update(self, block, extent=None, offset=None, alpha=1.0, stream=None):
+        """block: CUDA tensor of the plan dtype whose memory is the box in column-major
+        order (numel == prod(extent))."""
+        extent = self.dims if extent is None else tuple(int(e) for e in extent)
+        offset = (0,) * self.d if offset is None else tuple(int(o) for o in offset)
+        assert block.is_cuda and block.dtype == self.torch_dtype and block.is_contiguous()
+        n = 1
+        for e in extent:
+            n *= e
+        assert block.numel() == n, (block.numel(), extent)
+        check(lib.ttnn_sketch_update(self.handle, C.c_void_p(block.data_ptr()), (C.c_int64 * self.d)(*offset),
+                                     (C.c_int64 * self.d)(*extent), float(alpha), stream_ptr(stream)))
+
+    def update_rank1(self, factors, alpha=1.0, stream=None):
+        ptrs = (C.c_void_p * self.d)(*[C.c_void_p(f.data_ptr()) for f in factors])
+        check(lib.ttnn_sketch_update_rank1(self.handle, ptrs, float(alpha), stream_ptr(stream)))
+
+    def reset(self, stream=None):
+        check(lib.ttnn_reset(self.handle, stream_ptr(stream)))
+
+    # ------------------------------------------------------------ readbacks
+    def sketch_shape(self, node, kind):
+        r, c = C.c_int64(), C.c_int64()
+        check(lib.ttnn_sketch_shape(self.handle, node, kind, C.byref(r), C.byref(c)))
+        return r.value, c.value
+
+    def read_sketch(self, node, kind, stream=None):
+        r, c = self.sketch_shape(node, kind)
+        out = torch.empty(r * c, dtype=torch.float64, device="cuda")
+        check(lib.ttnn_read_sketch(self.handle, node, kind, C.c_void_p(out.data_ptr()), stream_ptr(stream)))
+        return out.view(c, r).t()        # column-major (r x c)
+
+    def drm_shape(self, node, kind):
+        r, c = C.c_int64(), C.c_int64()
+        check(lib.ttnn_drm_shape(self.handle, node, kind, C.byref(r), C.byref(c)))
+        return r.value, c.value
+
+    def read_drm(self, node, kind, dtype=F64, stream=None):
+        r, c = self.drm_shape(node, kind)
+        tdt = {F64: torch.float64, F32: torch.float32, BF16: torch.int16}[dtype]
+        out = torch.empty((r, c), dtype=tdt, device="cuda")
+        check(lib.ttnn_read_drm(self.handle, node, kind, dtype, C.c_void_p(out.data_ptr()), stream_ptr(stream)))
+        return out
+
+    def level_id(self, node):
+        v = C.c_int32()
+        check(lib.ttnn_level_id(self.handle, node, C.byref(v)))
+        return v.value
+
+    def reuse_set(self, node):
+        cnt = C.c_int32()
+        ids = (C.c_int32 * 64)()
+        check(lib.ttnn_reuse_set(self.handle, node, C.byref(cnt), ids))
+        return [ids[i] for i in range(cnt.value)]
+
+    def core_shape(self, node):
+        nd = C.c_int32()
+        shp = (C.c_int64 * 16)()
+        check(lib.ttnn_core_shape(self.handle, node, C.byref(nd), shp))
+        return tuple(shp[i] for i in range(nd.value))
+
+    # ------------------------------------------------------------ recovery
+    def alloc_cores(self):
+        cores = []
+        for i in range(self.num_nodes):
+            n = 1
+            for s in self.core_shape(i):
+                n *= s
+            cores.append(torch.empty(n, dtype=torch.float64, device="cuda"))
+        return cores
+
+    def assemble(self, cores=None, stream=None, check_status=True):
+        cores = self.alloc_cores() if cores is None else cores
+        ptrs = (C.c_void_p * self.num_nodes)(*[C.c_void_p(c.data_ptr()) for c in cores])
+        st = lib.ttnn_assemble(self.handle, ptrs, stream_ptr(stream))
+        if check_status:
+            check(st)
+        return cores if check_status else (cores, st)
+
+    def reconstruct(self, cores, out=None, out_dtype=F64, stream=None):
+        n = 1
+        for s in self.dims:
+            n *= s
+        if out is None:
+            out = torch.empty(n, dtype=TORCH_DTYPE[out_dtype], device="cuda")
+        ptrs = (C.c_void_p * self.num_nodes)(*[C.c_void_p(c.data_ptr()) for c in cores])
+        check(lib.ttnn_reconstruct(self.handle, ptrs, C.c_void_p(out.data_ptr()), out_dtype, stream_ptr(stream)))
+        return out
+
+
+def diff_norms(a, b, stream=None):
+    """(||a - b||^2, ||b||^2) computed on the GPU; a any plan dtype, b float64."""
+    out = (C.c_double * 2)()
+    dt = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[a.dtype]
+    assert a.numel() == b.numel() and b.dtype == torch.float64
+    check(lib.ttnn_diff_norms(C.c_void_p(a.data_ptr()), dt, C.c_void_p(b.data_ptr()), a.numel(), out,
+                              stream_ptr(stream)))
+    return out[0], out[1]
+
+
+def update_batched(items, stream=None):
+    """items: list of (plan, block, extent, offset, alpha)."""
+    arr = (UpdateDesc * max(1, len(items)))()
+    keep = []
+    for i, (plan, block, extent, offset, alpha) in enumerate(items):
+        arr[i].plan = plan.handle
+        arr[i].d_block = C.c_void_p(block.data_ptr())
+        for mu in range(plan.d):
+            arr[i].offset[mu] = int(offset[mu])
+            arr[i].extent[mu] = int(extent[mu])
+        arr[i].alpha = float(alpha)
+        keep.append(block)
+    check(lib.ttnn_sketch_update_batched(len(items), arr, stream_ptr(stream)))

@@ -1,0 +1,339 @@
+// extern "C" entry points of libttnn.so.  Each wraps its body so that no C++
+// exception crosses the ABI; statuses and messages follow include/ttnn.h.
+#include <cstring>
+#include <string>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+
+struct ttnn_plan_s {
+  std::unique_ptr<ttnn::Plan> p;
+};
+
+namespace ttnn {
+
+thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error() { return g_last_error.c_str(); }
+
+}  // namespace ttnn
+
+namespace {
+
+using ttnn::Error;
+using ttnn::Plan;
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+template <typename F>
+ttnn_status guard(Plan* P, F&& body) {
+  try {
+    if (P && P->sticky != TTNN_OK) {
+      ttnn::set_error("plan has a sticky error from an earlier call; call ttnn_reset");
+      return P->sticky;
+    }
+    return body();
+  } catch (const Error& e) {
+    ttnn::set_error(e.msg);
+    if (P && e.status == TTNN_E_HIP) P->sticky = TTNN_E_HIP;
+    return e.status;
+  } catch (const std::exception& e) {
+    ttnn::set_error(e.what());
+    return TTNN_E_INVALID;
+  }
+}
+
+Plan* get(ttnn_plan_t h) { return h ? h->p.get() : nullptr; }
+
+int level_id(const Plan& P, int32_t node) {
+  if (node < 0 || node >= static_cast<int32_t>(P.level_of_caller.size()))
+    throw Error{TTNN_E_RANGE, "node id out of range"};
+  return P.level_of_caller[node];
+}
+
+void check_box(const Plan& P, const int64_t* off, const int64_t* ext, bool* empty) {
+  if (!off || !ext) throw Error{TTNN_E_INVALID, "offset/extent is NULL"};
+  *empty = false;
+  for (int mu = 0; mu < P.d; ++mu) {
+    if (off[mu] < 0 || ext[mu] < 0 || off[mu] + ext[mu] > P.dims[mu])
+      throw Error{TTNN_E_RANGE, "update box outside the tensor in mode " + std::to_string(mu)};
+    if (ext[mu] == 0) *empty = true;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_plan_t* out) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!out) throw Error{TTNN_E_INVALID, "out is NULL"};
+    *out = nullptr;
+    auto P = ttnn::build_plan(problem, as_stream(stream));
+    auto* h = new ttnn_plan_s;
+    h->p = std::move(P);
+    *out = h;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_destroy(ttnn_plan_t plan) {
+  if (!plan) return TTNN_OK;
+  (void)hipDeviceSynchronize();
+  delete plan;
+  return TTNN_OK;
+}
+
+size_t ttnn_footprint_bytes(ttnn_plan_t plan) { return plan ? plan->p->footprint : 0; }
+
+ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset, const int64_t* extent,
+                               double alpha, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
+    bool empty = false;
+    check_box(*P, offset, extent, &empty);
+    if (empty) return TTNN_OK;
+    if (!d_block) throw Error{TTNN_E_INVALID, "block is NULL"};
+    ttnn::update_box(*P, d_block, offset, extent, alpha, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_factors, double alpha, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_factors) throw Error{TTNN_E_INVALID, "plan or factors is NULL"};
+    for (int mu = 0; mu < P->d; ++mu)
+      if (!d_factors[mu]) throw Error{TTNN_E_INVALID, "factor pointer is NULL"};
+    ttnn::update_rank1(*P, d_factors, alpha, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs, void* stream) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (n < 0 || (n > 0 && !descs)) throw Error{TTNN_E_INVALID, "bad descriptor array"};
+    // validate everything before enqueueing anything
+    for (int32_t i = 0; i < n; ++i) {
+      Plan* P = get(descs[i].plan);
+      if (!P) throw Error{TTNN_E_INVALID, "descriptor " + std::to_string(i) + " has no plan"};
+      if (P->sticky != TTNN_OK) throw Error{P->sticky, "descriptor plan has a sticky error"};
+      bool empty = false;
+      check_box(*P, descs[i].offset, descs[i].extent, &empty);
+      if (!empty && !descs[i].d_block) throw Error{TTNN_E_INVALID, "descriptor block is NULL"};
+    }
+    for (int32_t i = 0; i < n; ++i) {
+      Plan* P = get(descs[i].plan);
+      bool empty = false;
+      check_box(*P, descs[i].offset, descs[i].extent, &empty);
+      if (empty) continue;
+      try {
+        ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha,
+                         as_stream(stream));
+        TTNN_HIP(hipGetLastError());
+      } catch (const Error& e) {
+        if (e.status == TTNN_E_HIP) P->sticky = TTNN_E_HIP;
+        throw;
+      }
+    }
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64_t* shape) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !ndim || !shape) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const auto s = ttnn::core_shape(*P, level_id(*P, node));
+    *ndim = static_cast<int32_t>(s.size());
+    for (size_t i = 0; i < s.size(); ++i) shape[i] = s[i];
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_cores) throw Error{TTNN_E_INVALID, "NULL argument"};
+    std::vector<double*> by_level(P->nodes.size());
+    for (size_t c = 0; c < P->nodes.size(); ++c) {
+      if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
+      by_level[P->level_of_caller[c]] = d_cores[c];
+    }
+    const ttnn_status s = ttnn::run_assemble(*P, by_level.data(), as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    if (s != TTNN_OK) ttnn::set_error("non-finite sketch, or a node whose Omega has numerical rank 0");
+    return s;
+  });
+}
+
+ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, void* d_out, int32_t out_dtype,
+                             void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_cores || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (out_dtype != TTNN_F64 && out_dtype != TTNN_F32) throw Error{TTNN_E_INVALID, "out_dtype must be F64 or F32"};
+    std::vector<const double*> by_level(P->nodes.size());
+    for (size_t c = 0; c < P->nodes.size(); ++c) {
+      if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
+      by_level[P->level_of_caller[c]] = d_cores[c];
+    }
+    ttnn::run_reconstruct(*P, by_level.data(), d_out, out_dtype, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n, double* h_out,
+                            void* stream) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!d_a || !d_b || !h_out || n < 0) throw Error{TTNN_E_INVALID, "bad argument"};
+    if (a_dtype != TTNN_F64 && a_dtype != TTNN_F32 && a_dtype != TTNN_BF16) throw Error{TTNN_E_INVALID, "bad dtype"};
+    hipStream_t st = as_stream(stream);
+    double* d_part = nullptr;
+    TTNN_HIP(hipMalloc(&d_part, sizeof(double) * (2 * ttnn::kNormBlocks + 2)));
+    ttnn::launch_diff_norms(d_a, a_dtype, d_b, n, d_part, d_part + 2 * ttnn::kNormBlocks, st);
+    hipError_t e = hipMemcpyAsync(h_out, d_part + 2 * ttnn::kNormBlocks, 2 * sizeof(double),
+                                  hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(d_part);
+    TTNN_HIP(e);
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sketch_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows, int64_t* cols) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !rows || !cols) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const int v = level_id(*P, node);
+    const ttnn::Node& t = P->nodes[v];
+    if (v == 0) {
+      if (kind != TTNN_SK_PSI) throw Error{TTNN_E_RANGE, "the root only has a Psi sketch"};
+      *rows = P->psi_root_len;
+      *cols = 1;
+      return TTNN_OK;
+    }
+    if (kind == TTNN_SK_R) { *rows = t.n; *cols = t.r; }
+    else if (kind == TTNN_SK_OMEGA) { *rows = t.k; *cols = t.r; }
+    else if (kind == TTNN_SK_PSI) {
+      int64_t kk = 1;
+      for (int c : t.children) kk *= P->nodes[c].k;
+      *rows = t.leaf() ? t.n : kk;
+      *cols = t.r;
+    } else throw Error{TTNN_E_INVALID, "bad sketch kind"};
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_read_sketch(ttnn_plan_t plan, int32_t node, int32_t kind, double* d_out, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    int64_t rows = 0, cols = 0;
+    const ttnn_status s = ttnn_sketch_shape(plan, node, kind, &rows, &cols);
+    if (s != TTNN_OK) return s;
+    const int v = level_id(*P, node);
+    hipStream_t st = as_stream(stream);
+    const ttnn::Node& t = P->nodes[v];
+    const double* src = nullptr;
+    if (v == 0) src = P->psi_root;
+    else if (kind == TTNN_SK_R || (kind == TTNN_SK_PSI && t.leaf())) src = t.R;
+    else {
+      if (!P->epilogue_valid) ttnn::run_epilogue(*P, st);
+      src = kind == TTNN_SK_OMEGA ? t.Om : t.Psi;
+    }
+    ttnn::launch_copy_f64(d_out, src, rows * cols, st);
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_drm_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows, int64_t* cols) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !rows || !cols) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const int v = level_id(*P, node);
+    if (v == 0) throw Error{TTNN_E_RANGE, "the root has no DRMs"};
+    const ttnn::Node& t = P->nodes[v];
+    if (kind == 0) { *rows = t.m; *cols = t.r; }
+    else if (kind == 1) { *rows = t.n; *cols = t.k; }
+    else throw Error{TTNN_E_INVALID, "bad DRM kind"};
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t dtype, void* d_out, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    int64_t rows = 0, cols = 0;
+    const ttnn_status s = ttnn_drm_shape(plan, node, kind, &rows, &cols);
+    if (s != TTNN_OK) return s;
+    const ttnn::Node& t = P->nodes[level_id(*P, node)];
+    const void* src;
+    if (dtype == TTNN_F64) src = kind == 0 ? t.X64 : t.Y64;
+    else if (dtype == P->dtype) src = kind == 0 ? t.Xc : t.Yc;
+    else throw Error{TTNN_E_INVALID, "the plan stores no DRM copy of that dtype"};
+    TTNN_HIP(hipMemcpyAsync(d_out, src, ttnn::dtype_size(dtype) * rows * cols, hipMemcpyDeviceToDevice,
+                            as_stream(stream)));
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_level_id(ttnn_plan_t plan, int32_t node, int32_t* out) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    *out = level_id(*P, node);
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32_t* ids) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !count || !ids) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const ttnn::Node& t = P->nodes[level_id(*P, node)];
+    *count = static_cast<int32_t>(t.S.size());
+    for (size_t i = 0; i < t.S.size(); ++i) ids[i] = P->nodes[t.S[i]].caller;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream) {
+  Plan* P = get(plan);
+  if (!P) return TTNN_E_INVALID;
+  try {
+    P->sticky = TTNN_OK;
+    (void)hipGetLastError();
+    ttnn::zero_accumulators(*P, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  } catch (const Error& e) {
+    ttnn::set_error(e.msg);
+    P->sticky = e.status == TTNN_E_HIP ? TTNN_E_HIP : TTNN_OK;
+    return e.status;
+  }
+}
+
+const char* ttnn_status_string(ttnn_status s) {
+  switch (s) {
+    case TTNN_OK: return "ok";
+    case TTNN_E_INVALID: return "invalid argument";
+    case TTNN_E_TREE: return "invalid index tree";
+    case TTNN_E_RANGE: return "out of range";
+    case TTNN_E_NOMEM: return "out of device memory";
+    case TTNN_E_HIP: return "HIP runtime error";
+    case TTNN_E_STATE: return "call out of order";
+    case TTNN_E_NUMERIC: return "numerical failure";
+  }
+  return "unknown status";
+}
+
+const char* ttnn_last_error(void) { return ttnn::last_error(); }
+
+}  // extern "C"

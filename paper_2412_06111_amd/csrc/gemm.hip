@@ -1,0 +1,260 @@
+// Generic contraction kernels of the engine (any tree, any box, any dtype).
+//
+// One LDS-tiled FP64 kernel covers both contractions the method needs on a
+// 3-index view H[L][n][Q] of a (partially contracted) tensor:
+//   RIGHT  R(i, j)    = sum_{l,q} H[l, i, q] X[row(l, q), j]   (right sketch T^{t} X_t,
+//                                                           Sec. 4; STTNN on T_{S_t}, Sec. 5)
+//   LEFT   Z(l, j, q) = sum_i     H[l, i, q] Y[row(i), j]      (mode product with Y_s^T,
+//                                                           Def. 1 / Sec. 5 contractions)
+// The contraction is split in chunks; each chunk writes an FP64 partial that a
+// second kernel sums in a fixed order, so the result does not depend on timing.
+// This path is the reference engine for arbitrary shapes; the fused kernels for
+// the large dense trees live in separate files.
+#include "kernels.hpp"
+
+namespace ttnn {
+namespace {
+
+constexpr int BR = 64;   // output rows per block
+constexpr int BJ = 32;   // output columns per block
+constexpr int BK = 16;   // contraction step
+
+template <typename T> __device__ inline double ld(const T* p, int64_t i) { return to_f64(p[i]); }
+
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+                                               const TD* __restrict__ D, int64_t sDr, int64_t sDc,
+                                               int ncols, IndexMap amap, IndexMap bmap, int64_t kchunk,
+                                               TO* __restrict__ out, OutLayout ol) {
+  __shared__ double As[BK][BR + 1];
+  __shared__ double Bs[BK][BJ + 1];
+  __shared__ int64_t drow[BK];
+
+  const int tid = threadIdx.x;
+  const int64_t rows_total = RIGHT ? n : L * Q;
+  const int64_t K = RIGHT ? L * Q : n;
+  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BR;
+  const int64_t c = blockIdx.y;
+  const int j0 = blockIdx.z * BJ;
+  const int64_t k_begin = c * kchunk;
+  const int64_t k_end = (k_begin + kchunk < K) ? k_begin + kchunk : K;
+  const bool kk_contig = RIGHT ? (L > 1) : (L == 1);
+
+  const int tr = tid % 16;   // 4 rows each
+  const int tc = tid / 16;   // 2 columns each
+  double acc[4][2] = {};
+
+  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
+    // DRM rows of this contraction step
+    if (tid < BK) {
+      const int64_t kk = kb + tid;
+      int64_t r = -1;
+      if (kk < k_end) {
+        if (RIGHT) r = amap(kk % L) + bmap(kk / L);
+        else r = amap(kk);
+      }
+      drow[tid] = r;
+    }
+    // operand tile As[kk][rr] = Hm(m, i)
+#pragma unroll
+    for (int s = 0; s < (BR * BK) / 256; ++s) {
+      const int e = tid + 256 * s;
+      int kk, rr;
+      if (kk_contig) {
+        kk = e % BK;
+        rr = e / BK;
+      } else {
+        rr = e % BR;
+        kk = e / BR;
+      }
+      const int64_t kg = kb + kk;
+      const int64_t rg = row0 + rr;
+      double v = 0.0;
+      if (kg < k_end && rg < rows_total) {
+        const int64_t m = RIGHT ? kg : rg;
+        const int64_t i = RIGHT ? rg : kg;
+        const int64_t l = m % L;
+        const int64_t q = m / L;
+        v = ld(H, l + L * (i + n * q));
+      }
+      As[kk][rr] = v;
+    }
+    __syncthreads();
+    // DRM tile Bs[kk][jj]
+#pragma unroll
+    for (int s = 0; s < (BK * BJ) / 256; ++s) {
+      const int e = tid + 256 * s;
+      const int jj = e % BJ;
+      const int kk = e / BJ;
+      const int64_t r = drow[kk];
+      double v = 0.0;
+      if (r >= 0 && j0 + jj < ncols) v = ld(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc);
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      double a[4], b[2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = As[kk][tr * 4 + u];
+#pragma unroll
+      for (int v = 0; v < 2; ++v) b[v] = Bs[kk][tc * 2 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) acc[u][v] = __fma_rn(a[u], b[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int64_t row = row0 + tr * 4 + u;
+    if (row >= rows_total) continue;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      const int j = j0 + tc * 2 + v;
+      if (j >= ncols) continue;
+      const int64_t o = c * ol.cs + (row % ol.Lo) * ol.s0 + static_cast<int64_t>(j) * ol.s1 +
+                        (row / ol.Lo) * ol.s2;
+      out[o] = static_cast<TO>(acc[u][v]);
+    }
+  }
+}
+
+template <bool RIGHT, typename TH, typename TD>
+void gemm_dispatch_out(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t st) {
+  if (a.out_f32)
+    hipLaunchKernelGGL((hm_gemm<RIGHT, TH, TD, float>), grid, dim3(256), 0, st,
+                       static_cast<const TH*>(a.H), a.L, a.n, a.Q, static_cast<const TD*>(a.D), a.sDr,
+                       a.sDc, a.ncols, a.amap, a.bmap, kchunk, static_cast<float*>(a.out), a.ol);
+  else
+    hipLaunchKernelGGL((hm_gemm<RIGHT, TH, TD, double>), grid, dim3(256), 0, st,
+                       static_cast<const TH*>(a.H), a.L, a.n, a.Q, static_cast<const TD*>(a.D), a.sDr,
+                       a.sDc, a.ncols, a.amap, a.bmap, kchunk, static_cast<double*>(a.out), a.ol);
+}
+
+template <bool RIGHT, typename TH>
+void gemm_dispatch_d(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t st) {
+  switch (a.td) {
+    case TTNN_F64: gemm_dispatch_out<RIGHT, TH, double>(a, grid, kchunk, st); break;
+    case TTNN_F32: gemm_dispatch_out<RIGHT, TH, float>(a, grid, kchunk, st); break;
+    default: gemm_dispatch_out<RIGHT, TH, uint16_t>(a, grid, kchunk, st); break;
+  }
+}
+
+template <bool RIGHT>
+void gemm_dispatch_h(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t st) {
+  switch (a.th) {
+    case TTNN_F64: gemm_dispatch_d<RIGHT, double>(a, grid, kchunk, st); break;
+    case TTNN_F32: gemm_dispatch_d<RIGHT, float>(a, grid, kchunk, st); break;
+    default: gemm_dispatch_d<RIGHT, uint16_t>(a, grid, kchunk, st); break;
+  }
+}
+
+__global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
+                              double alpha, IndexMap rmap, int64_t ldr, double* __restrict__ dst, int64_t L,
+                              int64_t kdim) {
+  const int64_t total = rows * ncols;
+  const int64_t stride = rows * ncols;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t row = e / ncols;
+    const int j = static_cast<int>(e - row * ncols);
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += part[c * stride + e];
+    if (mode == 0) {
+      dst[rmap(row) + ldr * j] += alpha * s;
+    } else {
+      const int64_t o = (row % L) + L * (j + kdim * (row / L));
+      if (mode == 1) dst[o] += alpha * s;
+      else dst[o] = s;
+    }
+  }
+}
+
+__global__ void zero_kernel(double* p, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0.0;
+}
+__global__ void axpy_kernel(double* y, const double* x, double alpha, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] += alpha * x[i];
+}
+__global__ void copy_kernel(double* y, const double* x, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = x[i];
+}
+__global__ void f64_to_f32_kernel(float* y, const double* x, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    y[i] = static_cast<float>(x[i]);
+}
+__global__ void finite_kernel(const double* p, int64_t n, int* flag) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    if (!isfinite(p[i])) *flag = 1;
+}
+
+inline int grid_for(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return static_cast<int>(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+}  // namespace
+
+int pick_chunks(int64_t rows, int ncols, int64_t K, size_t partial_cap) {
+  const int64_t row_blocks = (rows + BR - 1) / BR;
+  const int64_t col_blocks = (ncols + BJ - 1) / BJ;
+  const int64_t blocks = row_blocks * col_blocks;
+  int64_t want = 2048 / (blocks > 0 ? blocks : 1);
+  const int64_t by_len = (K + 511) / 512;              // at least ~512 terms per chunk
+  if (want > by_len) want = by_len;
+  const int64_t cap = static_cast<int64_t>(partial_cap / static_cast<size_t>(rows * ncols));
+  if (want > cap) want = cap;
+  if (want > 65535) want = 65535;
+  return static_cast<int>(want < 1 ? 1 : want);
+}
+
+int launch_gemm(const GemmArgs& a, hipStream_t st) {
+  const int64_t rows = a.right ? a.n : a.L * a.Q;
+  const int64_t K = a.right ? a.L * a.Q : a.n;
+  if (rows <= 0 || a.ncols <= 0) return 0;
+  int64_t kchunk = (K + a.nchunks - 1) / a.nchunks;
+  kchunk = ((kchunk + BK - 1) / BK) * BK;
+  if (kchunk < BK) kchunk = BK;
+  const int nch = static_cast<int>((K + kchunk - 1) / kchunk);
+  dim3 grid(static_cast<unsigned>((rows + BR - 1) / BR), static_cast<unsigned>(nch > 0 ? nch : 1),
+            static_cast<unsigned>((a.ncols + BJ - 1) / BJ));
+  if (a.right) gemm_dispatch_h<true>(a, grid, kchunk, st);
+  else gemm_dispatch_h<false>(a, grid, kchunk, st);
+  return static_cast<int>(grid.y);
+}
+
+void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
+                   const IndexMap& rmap, int64_t ldr, double* dst, int64_t L, int64_t kdim, hipStream_t st) {
+  if (rows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(reduce_kernel, dim3(grid_for(rows * ncols)), dim3(256), 0, st, part, nchunks, rows, ncols,
+                     mode, alpha, rmap, ldr, dst, L, kdim);
+}
+
+void launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+}
+void launch_axpy(double* y, const double* x, double alpha, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, st, y, x, alpha, n);
+}
+void launch_copy_f64(double* y, const double* x, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+}
+void launch_f64_to_f32(float* y, const double* x, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+}
+void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, flag);
+}
+
+}  // namespace ttnn

@@ -1,0 +1,78 @@
+// Host-callable launchers of the engine's HIP kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace ttnn {
+
+// ---------------------------------------------------------------- DRMs
+void launch_drm(int64_t rows, int cols, uint64_t seed, uint32_t tag, double* o64, float* o32,
+                uint16_t* o16, hipStream_t stream);
+
+// ---------------------------------------------------------------- generic contraction
+// The operand H (dtype th) is viewed as [L][n][Q] column-major (L fastest) and as the
+// matrix Hm(m, i) with m = l + L q:  Hm(m, i) = H[l + L (i + n q)].
+//   RIGHT: out(c; i, j) = sum_{m in chunk c} Hm(m, i) D(drow(m), j),
+//          drow(m) = amap(m % L) + bmap(m / L)
+//   LEFT : out(c; m, j) = sum_{i in chunk c} Hm(m, i) D(drow(i), j),  drow(i) = amap(i)
+// D(row, j) = D[row * sDr + j * sDc] (dtype td).  Results are FP64 (or FP32 when
+// out_f32) stored at  out[c*cs + (row % Lo)*s0 + j*s1 + (row / Lo)*s2].
+struct OutLayout {
+  int64_t Lo, s0, s1, s2, cs;
+};
+
+struct GemmArgs {
+  bool right = true;
+  const void* H = nullptr;
+  int th = TTNN_F64;
+  int64_t L = 1, n = 1, Q = 1;
+  const void* D = nullptr;
+  int td = TTNN_F64;
+  int64_t sDr = 1, sDc = 1;
+  int ncols = 1;
+  IndexMap amap, bmap;
+  int nchunks = 1;
+  void* out = nullptr;
+  bool out_f32 = false;
+  OutLayout ol{};
+};
+// Returns the number of chunks actually written (<= a.nchunks); 0 if nothing to do.
+int launch_gemm(const GemmArgs& a, hipStream_t stream);
+
+// choose the split over the contraction index; returns the number of chunks
+int pick_chunks(int64_t rows, int ncols, int64_t K, size_t partial_cap);
+
+// Sum partial results over chunks in a fixed order (FP64) and deliver them.
+//   mode 0 (RIGHT accumulate): dst[rmap(row) + ldr*j] += alpha * s
+//   mode 1 (LEFT  accumulate): dst[(row % L) + L*(j + kdim*(row / L))] += alpha * s
+//   mode 2 (LEFT  store)     : dst[(row % L) + L*(j + kdim*(row / L))]  = s
+void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
+                   const IndexMap& rmap, int64_t ldr, double* dst, int64_t L, int64_t kdim,
+                   hipStream_t stream);
+
+// ---------------------------------------------------------------- small utilities
+void launch_zero(double* p, int64_t n, hipStream_t stream);
+void launch_axpy(double* y, const double* x, double alpha, int64_t n, hipStream_t stream);
+void launch_copy_f64(double* dst, const double* src, int64_t n, hipStream_t stream);
+void launch_f64_to_f32(float* dst, const double* src, int64_t n, hipStream_t stream);
+void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t stream);
+
+// ---------------------------------------------------------------- recovery phase
+// One workgroup per job: Householder QR of Omega (k x r, column-major), sign fix
+// diag(R) >= 0, one-sided Jacobi SVD of R, eps-truncated pseudo-inverse.
+struct QrJob {
+  const double* Om;   // k x r
+  double* Q;          // k x r out
+  double* Pinv;       // r x r out
+  int k, r;
+};
+void launch_qr_pinv(const QrJob* d_jobs, int njobs, int max_k, int max_r, double eps_factor,
+                    int* d_kept, hipStream_t stream);
+
+// ---------------------------------------------------------------- norms
+// Deterministic two-pass sums of (a - b)^2 and b^2; result in d_out[0..1].
+void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, double* d_part,
+                       double* d_out, hipStream_t stream);
+constexpr int kNormBlocks = 1024;
+
+}  // namespace ttnn

@@ -1,0 +1,226 @@
+// Plan construction: validation of the index tree (Def. 3 read with equality:
+// every internal node is the disjoint union of its children; contiguous mode
+// intervals), level-order numbering (labels of Fig. 1), STTNN reuse sets
+// (Sec. 5 and Fig. 5: preceding siblings of the node and of each ancestor), DRM
+// shapes (Sec. 4, eq. "sketch"; Sec. 5 for the reduced X_t of STTNN) and the
+// device memory of a plan.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "engine.hpp"
+#include "kernels.hpp"
+
+namespace ttnn {
+
+Plan::~Plan() {
+  for (void* p : allocs) (void)hipFree(p);
+}
+
+void* Plan::alloc(size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~static_cast<size_t>(255);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess || p == nullptr) {
+    (void)hipGetLastError();
+    throw Error{TTNN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  allocs.push_back(p);
+  footprint += bytes;
+  return p;
+}
+
+IndexMap box_rows(const Plan& P, int first, int last, const int64_t* off, const int64_t* ext) {
+  IndexMap m;
+  int64_t g = 1;
+  for (int mu = first; mu <= last; ++mu) {
+    m.push(ext[mu], off[mu], g);
+    g *= P.dims[mu];
+  }
+  return m;
+}
+
+namespace {
+
+void check_mul(int64_t a, int64_t b, const char* what) {
+  if (a > 0 && b > (int64_t(1) << 62) / a)
+    throw Error{TTNN_E_INVALID, std::string("size overflow in ") + what};
+}
+
+}  // namespace
+
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
+  TTNN_REQUIRE(pr != nullptr, TTNN_E_INVALID, "problem is NULL");
+  TTNN_REQUIRE(pr->order >= 2 && pr->order <= TTNN_MAX_ORDER, TTNN_E_INVALID, "order must be in [2, 8]");
+  TTNN_REQUIRE(pr->dims && pr->parent && pr->first_mode && pr->last_mode && pr->rank && pr->oversample,
+               TTNN_E_INVALID, "problem has a NULL array");
+  TTNN_REQUIRE(pr->num_nodes >= 2 && pr->num_nodes <= TTNN_MAX_NODES, TTNN_E_TREE,
+               "num_nodes must be in [2, 64]");
+  TTNN_REQUIRE(pr->variant == TTNN_TTNN || pr->variant == TTNN_STTNN, TTNN_E_INVALID, "bad variant");
+  TTNN_REQUIRE(pr->dtype == TTNN_F64 || pr->dtype == TTNN_F32 || pr->dtype == TTNN_BF16, TTNN_E_INVALID,
+               "bad dtype");
+  TTNN_REQUIRE(pr->eps_factor >= 0.0, TTNN_E_INVALID, "eps_factor must be >= 0");
+
+  auto P = std::make_unique<Plan>();
+  P->d = pr->order;
+  P->variant = pr->variant;
+  P->dtype = pr->dtype;
+  P->seed = pr->seed;
+  P->eps_factor = pr->eps_factor > 0.0 ? pr->eps_factor : 10.0 * 0x1p-52;
+  for (int mu = 0; mu < P->d; ++mu) {
+    TTNN_REQUIRE(pr->dims[mu] >= 1, TTNN_E_INVALID, "dims must be >= 1");
+    check_mul(P->N, pr->dims[mu], "tensor size");
+    P->dims[mu] = pr->dims[mu];
+    P->N *= pr->dims[mu];
+  }
+
+  // ---- tree structure in caller ids
+  const int nn = pr->num_nodes;
+  int root = -1;
+  std::vector<std::vector<int>> kids(nn);
+  for (int i = 0; i < nn; ++i) {
+    const int par = pr->parent[i];
+    TTNN_REQUIRE(pr->first_mode[i] >= 0 && pr->first_mode[i] <= pr->last_mode[i] && pr->last_mode[i] < P->d,
+                 TTNN_E_TREE, "node " + std::to_string(i) + " has a bad mode interval");
+    if (par < 0) {
+      TTNN_REQUIRE(par == -1 && root < 0, TTNN_E_TREE, "the tree must have exactly one root");
+      root = i;
+    } else {
+      TTNN_REQUIRE(par < nn && par != i, TTNN_E_TREE, "bad parent index");
+      kids[par].push_back(i);
+    }
+  }
+  TTNN_REQUIRE(root >= 0, TTNN_E_TREE, "no root");
+  TTNN_REQUIRE(pr->first_mode[root] == 0 && pr->last_mode[root] == P->d - 1, TTNN_E_TREE,
+               "the root must cover every mode");
+  for (int i = 0; i < nn; ++i) {
+    std::sort(kids[i].begin(), kids[i].end(),
+              [&](int a, int b) { return pr->first_mode[a] < pr->first_mode[b]; });
+    if (kids[i].empty()) continue;
+    int expect = pr->first_mode[i];
+    for (int c : kids[i]) {
+      TTNN_REQUIRE(pr->first_mode[c] == expect, TTNN_E_TREE,
+                   "children of node " + std::to_string(i) + " do not tile its interval in order");
+      expect = pr->last_mode[c] + 1;
+    }
+    TTNN_REQUIRE(expect == pr->last_mode[i] + 1, TTNN_E_TREE,
+                 "children of node " + std::to_string(i) + " do not cover its interval");
+    if (i != root)
+      TTNN_REQUIRE(kids[i].size() >= 2, TTNN_E_TREE,
+                   "internal node " + std::to_string(i) + " has a single child equal to itself");
+  }
+  TTNN_REQUIRE(!kids[root].empty(), TTNN_E_TREE, "the root has no children");
+
+  // ---- level order (breadth first, children left to right); reachability = no cycles
+  std::vector<int> order{root};
+  std::vector<int> level_caller(nn, -1);
+  level_caller[root] = 0;
+  for (size_t h = 0; h < order.size(); ++h)
+    for (int c : kids[order[h]]) {
+      TTNN_REQUIRE(level_caller[c] < 0, TTNN_E_TREE, "the parent links contain a cycle");
+      level_caller[c] = level_caller[order[h]] + 1;
+      order.push_back(c);
+    }
+  TTNN_REQUIRE(static_cast<int>(order.size()) == nn, TTNN_E_TREE, "some nodes are not reachable from the root");
+
+  P->level_of_caller.assign(nn, -1);
+  for (int v = 0; v < nn; ++v) P->level_of_caller[order[v]] = v;
+  P->nodes.resize(nn);
+  for (int v = 0; v < nn; ++v) {
+    const int c = order[v];
+    Node& nd = P->nodes[v];
+    nd.caller = c;
+    nd.level = level_caller[c];
+    nd.parent = pr->parent[c] < 0 ? -1 : P->level_of_caller[pr->parent[c]];
+    nd.first = pr->first_mode[c];
+    nd.last = pr->last_mode[c];
+    for (int k : kids[c]) nd.children.push_back(P->level_of_caller[k]);
+    nd.n = 1;
+    for (int mu = nd.first; mu <= nd.last; ++mu) nd.n *= P->dims[mu];
+    if (v > 0) {
+      TTNN_REQUIRE(pr->rank[c] >= 1 && pr->oversample[c] >= 0, TTNN_E_INVALID,
+                   "ranks must be >= 1 and oversamples >= 0");
+      TTNN_REQUIRE(pr->rank[c] <= 64 && pr->rank[c] + pr->oversample[c] <= 256, TTNN_E_INVALID,
+                   "rank <= 64 and rank + oversample <= 256 are supported");
+      nd.r = pr->rank[c];
+      nd.p = pr->oversample[c];
+      nd.k = nd.r + nd.p;
+    }
+  }
+
+  // ---- STTNN reuse sets and X_t row positions
+  for (int v = 1; v < nn; ++v) {
+    Node& nd = P->nodes[v];
+    if (P->variant == TTNN_STTNN) {
+      int cur = v;
+      while (P->nodes[cur].parent >= 0) {
+        const Node& par = P->nodes[P->nodes[cur].parent];
+        for (int s : par.children) {
+          if (s == cur) break;
+          nd.S.push_back(s);
+        }
+        cur = P->nodes[cur].parent;
+      }
+      std::sort(nd.S.begin(), nd.S.end(),
+                [&](int a, int b) { return P->nodes[a].first < P->nodes[b].first; });
+      for (int s : nd.S) nd.xpos.push_back(P->nodes[s].k);
+      for (int mu = nd.last + 1; mu < P->d; ++mu) nd.xpos.push_back(P->dims[mu]);
+    } else {
+      for (int mu = 0; mu < P->d; ++mu)
+        if (mu < nd.first || mu > nd.last) nd.xpos.push_back(P->dims[mu]);
+    }
+    nd.m = 1;
+    for (int64_t s : nd.xpos) {
+      check_mul(nd.m, s, "DRM rows");
+      nd.m *= s;
+    }
+  }
+
+  // ---- device memory
+  const bool copy = P->dtype != TTNN_F64;
+  const size_t cs = dtype_size(P->dtype);
+  for (int v = 1; v < nn; ++v) {
+    Node& nd = P->nodes[v];
+    check_mul(nd.m, nd.r, "X_t size");
+    nd.X64 = static_cast<double*>(P->alloc(sizeof(double) * nd.m * nd.r));
+    nd.Xc = copy ? P->alloc(cs * nd.m * nd.r) : nd.X64;
+    nd.Y64 = static_cast<double*>(P->alloc(sizeof(double) * nd.n * nd.k));
+    nd.Yc = copy ? P->alloc(cs * nd.n * nd.k) : nd.Y64;
+    nd.R = static_cast<double*>(P->alloc(sizeof(double) * nd.n * nd.r));
+    nd.Om = static_cast<double*>(P->alloc(sizeof(double) * nd.k * nd.r));
+    nd.Q = static_cast<double*>(P->alloc(sizeof(double) * nd.k * nd.r));
+    nd.Pinv = static_cast<double*>(P->alloc(sizeof(double) * nd.r * nd.r));
+    if (!nd.leaf()) {
+      int64_t kk = 1;
+      for (int c : nd.children) kk *= P->nodes[c].k;
+      nd.Psi = static_cast<double*>(P->alloc(sizeof(double) * kk * nd.r));
+    }
+  }
+  P->psi_root_len = 1;
+  for (int c : P->nodes[0].children) P->psi_root_len *= P->nodes[c].k;
+  P->psi_root = static_cast<double*>(P->alloc(sizeof(double) * P->psi_root_len));
+  P->d_flag = static_cast<int*>(P->alloc(sizeof(int) * 2 * TTNN_MAX_NODES));
+  P->d_jobs = static_cast<QrJob*>(P->alloc(sizeof(QrJob) * TTNN_MAX_NODES));
+
+  size_chain_scratch(*P);
+  P->chain = static_cast<double*>(P->alloc(sizeof(double) * P->chain_elems));
+  P->partial = static_cast<double*>(P->alloc(sizeof(double) * P->partial_elems));
+  P->work = static_cast<double*>(P->alloc(sizeof(double) * P->work_elems));
+
+  // ---- DRMs and zeroed accumulators
+  for (int v = 1; v < nn; ++v) {
+    Node& nd = P->nodes[v];
+    const uint32_t tx = static_cast<uint32_t>(2 * v + 0), ty = static_cast<uint32_t>(2 * v + 1);
+    float* x32 = P->dtype == TTNN_F32 ? static_cast<float*>(nd.Xc) : nullptr;
+    uint16_t* x16 = P->dtype == TTNN_BF16 ? static_cast<uint16_t*>(nd.Xc) : nullptr;
+    float* y32 = P->dtype == TTNN_F32 ? static_cast<float*>(nd.Yc) : nullptr;
+    uint16_t* y16 = P->dtype == TTNN_BF16 ? static_cast<uint16_t*>(nd.Yc) : nullptr;
+    launch_drm(nd.m, nd.r, P->seed, tx, nd.X64, x32, x16, stream);
+    launch_drm(nd.n, nd.k, P->seed, ty, nd.Y64, y32, y16, stream);
+  }
+  zero_accumulators(*P, stream);
+  TTNN_HIP(hipGetLastError());
+  return P;
+}
+
+}  // namespace ttnn

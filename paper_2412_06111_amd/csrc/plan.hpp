@@ -1,0 +1,82 @@
+// Plan of the TTNN engine: the validated index tree in level order, per-node DRM
+// and sketch shapes, the STTNN reuse sets, and the device memory owned by a plan.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace ttnn {
+
+struct Node {
+  int caller = -1;             // id in the caller's arrays
+  int level = 0;
+  int parent = -1;             // level-order id
+  int first = 0, last = 0;     // 0-based mode interval
+  std::vector<int> children;   // level-order ids, left to right
+  int r = 0, p = 0, k = 0;     // rank, oversample, r + p
+  int64_t n = 1;               // n_t = prod of dims over the interval
+  int64_t m = 1;               // rows of X_t
+  std::vector<int> S;          // STTNN reuse set (level-order ids, left to right)
+  std::vector<int64_t> xpos;   // sizes of the positions indexing the rows of X_t
+  bool leaf() const { return children.empty(); }
+
+  // device memory (views into the plan's allocations)
+  double* X64 = nullptr;       // m x r row-major
+  void* Xc = nullptr;          // compute-dtype copy (== X64 for FP64 plans)
+  double* Y64 = nullptr;       // n x k row-major
+  void* Yc = nullptr;
+  double* R = nullptr;         // n x r column-major FP64 accumulator
+  double* Om = nullptr;        // k x r column-major
+  double* Psi = nullptr;       // internal nodes: prod(k_c) x r column-major
+  double* Q = nullptr;         // k x r column-major
+  double* Pinv = nullptr;      // r x r column-major
+};
+
+struct Plan {
+  int d = 0;
+  int64_t dims[TTNN_MAX_ORDER] = {};
+  int variant = TTNN_TTNN;
+  int dtype = TTNN_F64;
+  uint64_t seed = 0;
+  double eps_factor = 0.0;
+  std::vector<Node> nodes;                 // level order, root = 0
+  std::vector<int> level_of_caller;        // caller id -> level-order id
+  int64_t N = 1;
+
+  double* psi_root = nullptr;              // prod(k_c) FP64 accumulator
+  int64_t psi_root_len = 0;
+
+  // chain intermediates of the generic update path, keyed by contraction prefix
+  std::map<std::vector<int>, size_t> prefix_offset;   // element offset into chain scratch
+  double* chain = nullptr;
+  size_t chain_elems = 0;
+  double* partial = nullptr;               // split-K partials
+  size_t partial_elems = 0;
+  double* work = nullptr;                  // assembly / reconstruction scratch
+  size_t work_elems = 0;
+  int* d_flag = nullptr;                   // numeric-status flag written by kernels
+  struct QrJob* d_jobs = nullptr;          // recovery job table (device)
+  std::vector<struct QrJob> host_jobs;
+
+  std::vector<void*> allocs;
+  size_t footprint = 0;
+  ttnn_status sticky = TTNN_OK;
+  bool epilogue_valid = false;             // Om / Psi reflect the accumulators
+  bool has_cores = false;
+
+  ~Plan();
+  void* alloc(size_t bytes);
+};
+
+// construction / validation (host); throws Error
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream);
+
+// IndexMap from a set of consecutive modes of a box to the column-major index of
+// the same modes in the full tensor
+IndexMap box_rows(const Plan& P, int first, int last, const int64_t* off, const int64_t* ext);
+
+}  // namespace ttnn

@@ -1,0 +1,241 @@
+// Recovery-phase linear algebra in FP64 on the GPU (Sec. 4 "Recovery phase",
+// Alg. 2, stabilised least squares with eps = eps_factor * ||R||_2), one workgroup
+// per tree node:
+//   1. Householder QR of Omega_t (k x r, k >= r), reflectors kept in LDS;
+//      Q = H_0 ... H_{r-1} [I; 0];  signs flipped so that diag(R) >= 0.
+//   2. One-sided (Hestenes) Jacobi SVD of the r x r factor R: column pairs are
+//      rotated in round-robin order until every pair is orthogonal to working
+//      precision; sigma_p = ||a_p||, u_p = a_p / sigma_p, V accumulates rotations.
+//   3. R^{+eps} = sum_{sigma_p > eps} v_p u_p^T / sigma_p with eps = eps_factor * max sigma.
+// Also: deterministic squared-norm reductions used for error reporting.
+#include "kernels.hpp"
+
+namespace ttnn {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double block_sum(double v, double* red) {
+  // 256 threads: wave reduction then across the 4 waves
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  const double s = red[0] + red[1] + red[2] + red[3];
+  __syncthreads();
+  return s;
+}
+
+__global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, double eps_factor, int* kept) {
+  extern __shared__ double lds[];
+  __shared__ double red[4];
+  __shared__ double tau_s[128];
+  __shared__ int any_rot;
+  const QrJob job = jobs[blockIdx.x];
+  const int k = job.k, r = job.r;
+  const int tid = threadIdx.x;
+  double* A = lds;               // k x r column-major (Omega, then reflectors + R)
+  double* W = A + k * r;         // r x r : columns a_p of the Jacobi iteration
+  double* V = W + r * r;         // r x r : right singular vectors
+
+  for (int e = tid; e < k * r; e += kThreads) A[e] = job.Om[e];
+  __syncthreads();
+
+  // ---- Householder QR (LAPACK dlarfg convention, v_0 = 1)
+  for (int j = 0; j < r; ++j) {
+    double part = 0.0;
+    for (int i = j + 1 + tid; i < k; i += kThreads) part += A[i + k * j] * A[i + k * j];
+    const double xnorm2 = block_sum(part, red);
+    const double alpha = A[j + k * j];
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (xnorm2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    __syncthreads();
+    if (xnorm2 > 0.0)
+      for (int i = j + 1 + tid; i < k; i += kThreads) A[i + k * j] *= scale;
+    if (tid == 0) {
+      A[j + k * j] = beta;
+      tau_s[j] = tau;
+    }
+    __syncthreads();
+    if (tau != 0.0) {
+      // A[j:k, c] -= tau v (v^T A[j:k, c]) for c > j, one column per thread
+      for (int c = j + 1 + tid; c < r; c += kThreads) {
+        double w = A[j + k * c];
+        for (int i = j + 1; i < k; ++i) w += A[i + k * j] * A[i + k * c];
+        w *= tau;
+        A[j + k * c] -= w;
+        for (int i = j + 1; i < k; ++i) A[i + k * c] -= w * A[i + k * j];
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- Q = H_0 ... H_{r-1} [I; 0], built in global memory, one column per thread
+  for (int c = tid; c < r; c += kThreads) {
+    double* q = job.Q + static_cast<int64_t>(k) * c;
+    for (int i = 0; i < k; ++i) q[i] = (i == c) ? 1.0 : 0.0;
+    for (int j = r - 1; j >= 0; --j) {
+      const double tau = tau_s[j];
+      if (tau == 0.0) continue;
+      double w = q[j];
+      for (int i = j + 1; i < k; ++i) w += A[i + k * j] * q[i];
+      w *= tau;
+      q[j] -= w;
+      for (int i = j + 1; i < k; ++i) q[i] -= w * A[i + k * j];
+    }
+  }
+  __syncthreads();
+  // sign fix: diag(R) >= 0 (flip row j of R and column j of Q)
+  for (int c = tid; c < r; c += kThreads) {
+    if (A[c + k * c] < 0.0) {
+      double* q = job.Q + static_cast<int64_t>(k) * c;
+      for (int i = 0; i < k; ++i) q[i] = -q[i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < r * r; e += kThreads) {
+    const int i = e % r, c = e / r;
+    double v = (i <= c) ? A[i + k * c] : 0.0;
+    if (A[i + k * i] < 0.0) v = -v;
+    W[e] = v;
+    V[e] = (i == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+
+  // ---- one-sided Jacobi on the columns of W (r x r)
+  const int R2 = r + (r & 1);                 // pad to even with a virtual zero column
+  const int npairs = R2 / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) any_rot = 0;
+    __syncthreads();
+    for (int step = 0; step < R2 - 1; ++step) {
+      // round-robin pairing: player 0 fixed, the others rotate
+      for (int pr = tid / 8; pr < npairs; pr += kThreads / 8) {
+        const int lane8 = tid % 8;
+        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + ((pos - 1 + step) % (R2 - 1)); };
+        int p = player(pr), q = player(R2 - 1 - pr);
+        if (p > q) { const int t = p; p = q; q = t; }
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (q < r) {
+          for (int i = lane8; i < r; i += 8) {
+            const double x = W[i + r * p], y = W[i + r * q];
+            al += x * x;
+            be += y * y;
+            ga += x * y;
+          }
+        }
+        for (int o = 4; o > 0; o >>= 1) {
+          al += __shfl_xor(al, o);
+          be += __shfl_xor(be, o);
+          ga += __shfl_xor(ga, o);
+        }
+        if (q < r && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int i = lane8; i < r; i += 8) {
+            const double x = W[i + r * p], y = W[i + r * q];
+            W[i + r * p] = cs * x - sn * y;
+            W[i + r * q] = sn * x + cs * y;
+            const double vx = V[i + r * p], vy = V[i + r * q];
+            V[i + r * p] = cs * vx - sn * vy;
+            V[i + r * q] = sn * vx + cs * vy;
+          }
+          if (lane8 == 0) any_rot = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int rot = any_rot;
+    __syncthreads();
+    if (!rot) break;
+  }
+
+  // ---- singular values and truncated pseudo-inverse
+  double* sig = tau_s;                         // reuse (r <= 128)
+  for (int c = tid; c < r; c += kThreads) {
+    double s = 0.0;
+    for (int i = 0; i < r; ++i) s += W[i + r * c] * W[i + r * c];
+    sig[c] = sqrt(s);
+  }
+  __syncthreads();
+  double smax = 0.0;
+  for (int c = 0; c < r; ++c) smax = fmax(smax, sig[c]);
+  const double eps = eps_factor * smax;
+  for (int e = tid; e < r * r; e += kThreads) {
+    const int i = e % r, j = e / r;            // Pinv(i, j) = sum_p V(i,p) W(j,p) / sigma_p^2
+    double s = 0.0;
+    for (int p = 0; p < r; ++p)
+      if (sig[p] > eps) s += V[i + r * p] * W[j + r * p] / (sig[p] * sig[p]);
+    job.Pinv[e] = s;
+  }
+  if (tid == 0) {
+    int cnt = 0;
+    for (int p = 0; p < r; ++p) cnt += sig[p] > eps ? 1 : 0;
+    kept[blockIdx.x] = cnt;
+  }
+}
+
+__global__ void diff_norm_part(const void* a, int a_dtype, const double* b, int64_t n, double* part) {
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double av;
+    if (a_dtype == TTNN_F64) av = static_cast<const double*>(a)[i];
+    else if (a_dtype == TTNN_F32) av = static_cast<const float*>(a)[i];
+    else av = bf16_bits_to_f32(static_cast<const uint16_t*>(a)[i]);
+    const double bv = b[i];
+    s0 += (av - bv) * (av - bv);
+    s1 += bv * bv;
+  }
+  __shared__ double red[4];
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+__global__ void diff_norm_final(const double* part, int nb, double* out) {
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = 0; i < nb; ++i) {
+      s0 += part[2 * i];
+      s1 += part[2 * i + 1];
+    }
+    out[0] = s0;
+    out[1] = s1;
+  }
+}
+
+}  // namespace
+
+void launch_qr_pinv(const QrJob* d_jobs, int njobs, int max_k, int max_r, double eps_factor, int* d_kept,
+                    hipStream_t st) {
+  if (njobs <= 0) return;
+  const size_t lds = static_cast<size_t>(max_k * max_r + 2 * max_r * max_r) * sizeof(double);
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_pinv_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error{TTNN_E_INVALID, "recovery kernel needs " + std::to_string(lds) + " bytes of LDS"};
+    }
+  }
+  hipLaunchKernelGGL(qr_pinv_kernel, dim3(njobs), dim3(kThreads), lds, st, d_jobs, eps_factor, d_kept);
+}
+
+void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, double* d_part, double* d_out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(diff_norm_part, dim3(kNormBlocks), dim3(256), 0, st, a, a_dtype, b, n, d_part);
+  hipLaunchKernelGGL(diff_norm_final, dim3(1), dim3(64), 0, st, d_part, kNormBlocks, d_out);
+}
+
+}  // namespace ttnn

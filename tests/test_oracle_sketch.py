@@ -106,3 +106,20 @@ def test_storage_rounded_drms():
     for t in D64.X:
         d = np.abs(D16.X[t] - D64.X[t]) / np.maximum(np.abs(D64.X[t]), 1e-300)
         assert d.max() <= 2.0**-8
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("spec,dims", [(O.T4, (5, 4, 6, 3)), (O.TOY, (3, 4, 2, 3, 4, 2))])
+def test_sketch_box_equals_zero_padded(spec, dims, variant):
+    from oracle.sketch import sketch_box
+    tree = O.Tree(spec, dims, 2, 1)
+    D = O.DRMs(tree, 5, variant)
+    g = np.random.default_rng(4)
+    off = [int(g.integers(0, n)) for n in dims]
+    ext = [int(g.integers(1, n - o + 1)) for n, o in zip(dims, off)]
+    blk = g.standard_normal(ext)
+    full = O.sketch_update(None, blk, off, 1.0, tree, D, variant)
+    box = sketch_box(blk, off, tree, 5, variant)
+    for t in full["R"]:
+        assert rel(box["R"][t], full["R"][t]) < 1e-13
+    assert rel(box["Psi_root"], full["Psi"][0]) < 1e-13
