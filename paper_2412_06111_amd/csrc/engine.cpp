@@ -160,10 +160,14 @@ void zero_accumulators(Plan& P, hipStream_t st) {
 void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
                 hipStream_t st) {
   P.epilogue_valid = false;
-  if (try_fused_update(P, block, off, ext, alpha, st)) return;
+  std::vector<int> fused_nodes;
+  std::vector<std::vector<int>> fused_prefixes;
+  if (P.allow_fused)
+    try_fused_update(P, block, off, ext, alpha, st, &fused_nodes, &fused_prefixes);
 
   const int cd = P.dtype;                       // dtype of the block and of the DRM copies
   std::map<std::vector<int>, bool> done;        // prefixes computed for this update
+  for (const auto& pf : fused_prefixes) done[pf] = true;
 
   // returns the operand after contracting `prefix` (FP64 intermediate, or the block)
   auto operand = [&](const std::vector<int>& prefix, int& th) -> const void* {
@@ -206,6 +210,7 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
   };
 
   for (size_t v = 1; v < P.nodes.size(); ++v) {
+    if (std::find(fused_nodes.begin(), fused_nodes.end(), static_cast<int>(v)) != fused_nodes.end()) continue;
     Node& t = P.nodes[v];
     const std::vector<int>& pre = t.S;          // empty for TTNN
     int th = cd;

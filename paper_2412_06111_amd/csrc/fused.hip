@@ -1,10 +1,525 @@
-// Fused one-pass sketch kernels (filled in for the dense binary trees).
+// Fused one-pass STTNN sketch for trees whose first root child A covers modes
+// (1, 2) with two one-mode leaf children (e.g. ((1,2),(3,4)) and ((1,2),(3,(4,5)))).
+//
+// With M = T^{A} (n_A x n_B, n_A = n_1 n_2, column-major), the nodes A, {1}, {2}
+// have S = {}, {}, {{1}} (Sec. 5, Fig. 5), so one pass over M produces
+//   R_A = M X_A                                   (Sec. 5: A is sketched on T itself)
+//   Z_A = Y_A^T M       -- the contraction T x_A Y_A^T reused by every node right of A
+//   R_1 = T^{1} X_1     -- sum over columns of (n_1 x n_2 slab) . X_1 rows
+//   R_2 = (T x_1 Y_1^T)^{2} X_2  -- Z1 = Y_1^T slab kept on chip, then Z1 . X_2 rows
+// R_B and the right subtree (and the root sketch) follow from Z_A on the generic path.
+//
+// Each workgroup streams a tile of M (B2 whole i1-slabs x BB columns) through LDS
+// once; every product is an MFMA chain on that LDS tile:
+//   (a)+(c) share the A fragments of the slab (rows i1, K = columns) against
+//           [X_A | X_1] rows;  (b)+(d1) share its B fragments (K = i1) against
+//           [Y_A | Y_1] rows;  (d2) contracts the LDS-staged Z1 over (j1, column).
+// Partial sums are written per tile in the accumulation precision and summed in a
+// fixed order into the FP64 accumulators by fused_reduce.
 #include "fused.hpp"
 
-namespace ttnn {
+#include "engine.hpp"
+#include "kernels.hpp"
+#include "mfma.hpp"
 
-bool try_fused_update(Plan&, const void*, const int64_t*, const int64_t*, double, hipStream_t) {
-  return false;
+namespace ttnn {
+namespace {
+
+constexpr int N1 = 128;
+
+struct SttnnArgs {
+  const void* T;
+  int64_t n2, nA, nB;
+  int TA, TB, CB;
+  const void *XA, *X1, *YA, *Y1, *X2;
+  void *PRA, *PZA, *PR1, *PR2;
+};
+
+template <typename P>
+__device__ inline typename P::Frag frag_contig(const typename P::T* p) {
+  if constexpr (P::KPL == 8) return P::load8(p);
+  else return *p;
+}
+
+template <int DT, int R, int KP, int B2, int SC>
+__global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
+  using P = Pol<DT>;
+  using T = typename P::T;
+  using Acc = typename P::Acc;
+  using Frag = typename P::Frag;
+  using CFrag = typename P::CFrag;
+  constexpr int KPL = P::KPL, KSTEP = P::KSTEP;
+  constexpr int PAD = 16 / P::ESZ;
+  constexpr int S = N1 + PAD;               // LDS column stride (elements)
+  constexpr int CBR = R / 16;               // 16-wide column blocks of an R-wide output
+  constexpr int KB = KP / 16;               // 16-row blocks of KP
+  constexpr int NCB = SC / 16;              // 16-wide column blocks of a sub-tile
+  static_assert(NCB == 4 || NCB == 2, "sub-tile width");
+  constexpr int KT = KP * SC;               // (d2) contraction length per sub-tile column block
+  constexpr int KW = KT / 4;                // per wave
+  constexpr int VPC = N1 * P::ESZ / 16;     // 16-byte vectors per column of a slab
+  constexpr int NVEC = VPC * SC / 256;
+  static_assert(NVEC * 256 == VPC * SC, "slab split");
+  static_assert(4 * 16 * R * sizeof(Acc) <= SC * S * sizeof(T), "reduction scratch aliases the slab");
+
+  __shared__ __align__(16) T Ms[SC * S];
+  __shared__ __align__(16) T Z1s[B2 * KT];
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+
+  // tile of this workgroup; tiles of one column band share an XCD (L2) when possible
+  int tA, tB;
+  {
+    const int w = blockIdx.x;
+    if (a.TB % 8 == 0) {
+      const int x = w % 8, j = w / 8, bpx = a.TB / 8;
+      tB = x * bpx + j / a.TA;
+      tA = j % a.TA;
+    } else {
+      tB = w / a.TA;
+      tA = w % a.TA;
+    }
+  }
+  const int64_t i2_0 = static_cast<int64_t>(tA) * B2;
+  const int64_t c_tile = static_cast<int64_t>(tB) * a.CB * SC;
+  const T* Tg = static_cast<const T*>(a.T);
+  const T* XA = static_cast<const T*>(a.XA);
+  const T* X1 = static_cast<const T*>(a.X1);
+  const T* YA = static_cast<const T*>(a.YA);
+  const T* Y1 = static_cast<const T*>(a.Y1);
+  const T* X2 = static_cast<const T*>(a.X2);
+  const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
+
+  uint4 pre[NVEC];
+  auto load_sub = [&](int s) {
+    const int cb = s / B2, i2l = s % B2;
+    const int64_t col0 = c_tile + static_cast<int64_t>(cb) * SC;
+    const int64_t base = (i2_0 + i2l) * N1;
+#pragma unroll
+    for (int u = 0; u < NVEC; ++u) {
+      const int vid = tid + 256 * u;
+      const int col = vid / VPC, part = vid % VPC;
+      pre[u] = *reinterpret_cast<const uint4*>(Tg + base + nA * (col0 + col) + part * (16 / P::ESZ));
+    }
+  };
+  auto store_sub = [&]() {
+#pragma unroll
+    for (int u = 0; u < NVEC; ++u) {
+      const int vid = tid + 256 * u;
+      const int col = vid / VPC, part = vid % VPC;
+      *reinterpret_cast<uint4*>(&Ms[col * S + part * (16 / P::ESZ)]) = pre[u];
+    }
+  };
+
+  CFrag rA[B2][2][CBR];
+  CFrag r1[2][CBR];
+  CFrag r2[CBR];
+  CFrag zA[KB];
+  const CFrag zero = {};
+#pragma unroll
+  for (int i = 0; i < B2; ++i)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int c = 0; c < CBR; ++c) rA[i][rb][c] = zero;
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int c = 0; c < CBR; ++c) r1[rb][c] = zero;
+#pragma unroll
+  for (int c = 0; c < CBR; ++c) r2[c] = zero;
+
+  const int nsub = a.CB * B2;
+  load_sub(0);
+  for (int cb = 0; cb < a.CB; ++cb) {
+    const int64_t iBbase = c_tile + static_cast<int64_t>(cb) * SC;
+#pragma unroll
+    for (int rb = 0; rb < KB; ++rb) zA[rb] = zero;
+
+#pragma unroll
+    for (int i2l = 0; i2l < B2; ++i2l) {
+      const int s = cb * B2 + i2l;
+      const int64_t i2 = i2_0 + i2l;
+      __syncthreads();
+      store_sub();
+      __syncthreads();
+      if (s + 1 < nsub) load_sub(s + 1);
+
+      // (a) R_A rows of this slab and (c) R_1: A = slab (rows i1, K = columns)
+#pragma unroll 2
+      for (int ks = 0; ks < SC / KSTEP; ++ks) {
+        const int kk = ks * KSTEP + KPL * lg;
+        Frag af[2];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          const int i1 = 32 * wave + 16 * rb + l16;
+          if constexpr (KPL == 8) {
+            u16x8_t v;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = Ms[(kk + e) * S + i1];
+            af[rb] = __builtin_bit_cast(Frag, v);
+          } else {
+            af[rb] = Ms[kk * S + i1];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < CBR; ++c) {
+          const int j = 16 * c + l16;
+          Frag bA, b1;
+          if constexpr (KPL == 8) {
+            bA = P::load8(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
+            b1 = P::load8(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
+          } else {
+            bA = XA[(iBbase + kk) * R + j];
+            b1 = X1[(i2 + n2 * (iBbase + kk)) * R + j];
+          }
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb) {
+            rA[i2l][rb][c] = P::mfma(af[rb], bA, rA[i2l][rb][c]);
+            r1[rb][c] = P::mfma(af[rb], b1, r1[rb][c]);
+          }
+        }
+      }
+
+      // (b) Z_A += Y_A^T slab and (d1) Z1 = Y_1^T slab: B = slab (K = i1, columns)
+      const bool do_zA = (NCB == 4) || wave < 2;
+      const bool do_z1 = (NCB == 4) || wave >= 2;
+      const int cblk = (NCB == 4) ? wave : (wave & 1);
+      CFrag z1[KB];
+#pragma unroll
+      for (int rb = 0; rb < KB; ++rb) z1[rb] = zero;
+#pragma unroll 2
+      for (int ks = 0; ks < N1 / KSTEP; ++ks) {
+        const int kk = ks * KSTEP + KPL * lg;
+        const int iBl = 16 * cblk + l16;
+        const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll
+        for (int rb = 0; rb < KB; ++rb) {
+          const int jr = 16 * rb + l16;
+          if (do_zA) {
+            Frag aY;
+            if constexpr (KPL == 8) aY = P::load8(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
+            else aY = YA[(i2 * N1 + kk) * KP + jr];
+            zA[rb] = P::mfma(aY, bM, zA[rb]);
+          }
+          if (do_z1) {
+            Frag a1;
+            if constexpr (KPL == 8) a1 = P::load8(Y1 + static_cast<int64_t>(jr) * N1 + kk);
+            else a1 = Y1[kk * KP + jr];
+            z1[rb] = P::mfma(a1, bM, z1[rb]);
+          }
+        }
+      }
+      if (do_z1) {
+        const int iBl = 16 * cblk + l16;
+#pragma unroll
+        for (int rb = 0; rb < KB; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j1 = 16 * rb + P::crow(lane, v);
+            Z1s[i2l * KT + iBl * KP + j1] = P::from_acc(z1[rb][v]);
+          }
+      }
+    }  // i2l
+    __syncthreads();
+
+    // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (j1, column)) . X_2 rows (j1 + k column)
+#pragma unroll 2
+    for (int ks = 0; ks < KW / KSTEP; ++ks) {
+      const int K = wave * KW + ks * KSTEP + KPL * lg;
+      Frag az;
+      if (l16 < B2) az = frag_contig<P>(&Z1s[l16 * KT + K]);
+      else az = Frag{};
+      const int iBl = K / KP, j1 = K % KP;
+#pragma unroll
+      for (int c = 0; c < CBR; ++c) {
+        const int j = 16 * c + l16;
+        Frag bx;
+        if constexpr (KPL == 8) bx = P::load8(X2 + (static_cast<int64_t>(j) * nB + iBbase + iBl) * KP + j1);
+        else bx = X2[((iBbase + iBl) * KP + j1) * R + j];
+        r2[c] = P::mfma(az, bx, r2[c]);
+      }
+    }
+
+    // Z_A partial of this tile's row range for the sub-block's columns
+    {
+      Acc* PZA = static_cast<Acc*>(a.PZA);
+      const bool do_zA = (NCB == 4) || wave < 2;
+      if (do_zA) {
+        const int cblk = (NCB == 4) ? wave : (wave & 1);
+        const int64_t iB = iBbase + 16 * cblk + l16;
+#pragma unroll
+        for (int rb = 0; rb < KB; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int jA = 16 * rb + P::crow(lane, v);
+            PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
+          }
+      }
+    }
+  }  // cb
+
+  // ---- partial results of the tile
+  {
+    Acc* PRA = static_cast<Acc*>(a.PRA);
+    Acc* PR1 = static_cast<Acc*>(a.PR1);
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int c = 0; c < CBR; ++c)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i1 = 32 * wave + 16 * rb + P::crow(lane, v);
+          const int j = 16 * c + l16;
+#pragma unroll
+          for (int i2l = 0; i2l < B2; ++i2l) {
+            const int64_t iA = (i2_0 + i2l) * N1 + i1;
+            PRA[(static_cast<int64_t>(tB) * nA + iA) * R + j] = rA[i2l][rb][c][v];
+          }
+          PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[rb][c][v];
+        }
+  }
+  __syncthreads();
+  Acc* red = reinterpret_cast<Acc*>(Ms);            // 4 waves x 16 rows x R
+#pragma unroll
+  for (int c = 0; c < CBR; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(wave * 16 + P::crow(lane, v)) * R + 16 * c + l16] = r2[c][v];
+  __syncthreads();
+  {
+    Acc* PR2 = static_cast<Acc*>(a.PR2);
+    for (int e = tid; e < B2 * R; e += 256) {
+      const int row = e / R, j = e % R;
+      const Acc s = red[(0 * 16 + row) * R + j] + red[(1 * 16 + row) * R + j] + red[(2 * 16 + row) * R + j] +
+                    red[(3 * 16 + row) * R + j];
+      PR2[(static_cast<int64_t>(tB) * n2 + i2_0 + row) * R + j] = s;
+    }
+  }
+}
+
+// Sum the tile partials in a fixed order into the FP64 state.
+template <typename Acc>
+__global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2, int TA, int TB,
+                                int64_t n2, int64_t nA, int64_t nB, int R, int KP, int k, double alpha, double* RA,
+                                double* ZA, double* R1, double* R2) {
+  const int64_t nRA = nA * R, nZA = static_cast<int64_t>(k) * nB, nR1 = static_cast<int64_t>(N1) * R, nR2 = n2 * R;
+  const int64_t total = nRA + nZA + nR1 + nR2;
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (e < nRA) {
+      const int64_t iA = e / R, j = e % R;
+      double s = 0.0;
+      for (int t = 0; t < TB; ++t) s += static_cast<double>(PRA[(t * nA + iA) * R + j]);
+      RA[iA + nA * j] += alpha * s;
+    } else if (e < nRA + nZA) {
+      const int64_t f = e - nRA;
+      const int64_t iB = f / k, jA = f % k;
+      double s = 0.0;
+      for (int t = 0; t < TA; ++t) s += static_cast<double>(PZA[(t * static_cast<int64_t>(KP) + jA) * nB + iB]);
+      ZA[jA + k * iB] = s;
+    } else if (e < nRA + nZA + nR1) {
+      const int64_t f = e - nRA - nZA;
+      const int64_t i1 = f / R, j = f % R;
+      double s = 0.0;
+      for (int t = 0; t < TA * TB; ++t) s += static_cast<double>(PR1[(t * static_cast<int64_t>(N1) + i1) * R + j]);
+      R1[i1 + N1 * j] += alpha * s;
+    } else {
+      const int64_t f = e - nRA - nZA - nR1;
+      const int64_t i2 = f / R, j = f % R;
+      double s = 0.0;
+      for (int t = 0; t < TB; ++t) s += static_cast<double>(PR2[(t * n2 + i2) * R + j]);
+      R2[i2 + n2 * j] += alpha * s;
+    }
+  }
+}
+
+// out[i0 + d0 (i1 + d1 i2)] = (valid) ? round(src[i0 s0 + i1 s1 + i2 s2]) : 0,
+// valid: the coordinate `cdim` is below `lim`.
+template <typename TO>
+__global__ void gather_copy(const double* src, TO* out, int64_t d0, int64_t d1, int64_t d2, int64_t s0, int64_t s1,
+                            int64_t s2, int cdim, int64_t lim) {
+  const int64_t total = d0 * d1 * d2;
+  for (int64_t o = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; o < total;
+       o += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t i0 = o % d0, t = o / d0, i1 = t % d1, i2 = t / d1;
+    const int64_t c = cdim == 0 ? i0 : cdim == 1 ? i1 : i2;
+    double v = 0.0;
+    if (c < lim) v = src[i0 * s0 + i1 * s1 + i2 * s2];
+    if constexpr (sizeof(TO) == 2) {
+      const uint32_t b = __float_as_uint(static_cast<float>(v));
+      out[o] = static_cast<uint16_t>((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+    } else {
+      out[o] = static_cast<TO>(v);
+    }
+  }
+}
+
+void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, int64_t d2, int64_t s0, int64_t s1,
+                 int64_t s2, int cdim, int64_t lim, hipStream_t st) {
+  const int64_t total = d0 * d1 * d2;
+  const int blocks = static_cast<int>(std::min<int64_t>((total + 255) / 256, 16384));
+  if (dt == TTNN_BF16)
+    hipLaunchKernelGGL(gather_copy<uint16_t>, dim3(blocks), dim3(256), 0, st, src, static_cast<uint16_t*>(out), d0,
+                       d1, d2, s0, s1, s2, cdim, lim);
+  else if (dt == TTNN_F32)
+    hipLaunchKernelGGL(gather_copy<float>, dim3(blocks), dim3(256), 0, st, src, static_cast<float*>(out), d0, d1, d2,
+                       s0, s1, s2, cdim, lim);
+  else
+    hipLaunchKernelGGL(gather_copy<double>, dim3(blocks), dim3(256), 0, st, src, static_cast<double*>(out), d0, d1,
+                       d2, s0, s1, s2, cdim, lim);
+}
+
+struct Shape {
+  int B2, SC;
+};
+
+Shape shape_for(int dt, int R) {
+  if (dt == TTNN_F64) return {R >= 64 ? 2 : 4, 32};
+  return {R >= 64 ? 4 : 8, 64};
+}
+
+template <int DT, int R, int KP>
+void launch_sttnn(const SttnnArgs& a, hipStream_t st) {
+  constexpr int B2 = (DT == TTNN_F64) ? (R >= 64 ? 2 : 4) : (R >= 64 ? 4 : 8);
+  constexpr int SC = (DT == TTNN_F64) ? 32 : 64;
+  hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC>), dim3(a.TA * a.TB), dim3(256), 0, st, a);
+}
+
+template <int DT>
+void launch_sttnn_dt(int R, const SttnnArgs& a, hipStream_t st) {
+  if (R == 16) launch_sttnn<DT, 16, 32>(a, st);
+  else if (R == 32) launch_sttnn<DT, 32, 48>(a, st);
+  else launch_sttnn<DT, 64, 96>(a, st);
+}
+
+int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- plan-time setup
+void fused_prepare(Plan& P, hipStream_t st) {
+  FusedT4& F = P.fused;
+  F.enabled = false;
+  if (P.variant != TTNN_STTNN || P.d < 3) return;
+  const Node& root = P.nodes[0];
+  if (root.children.size() < 2) return;
+  const int A = root.children[0];
+  const Node& nA_ = P.nodes[A];
+  if (nA_.first != 0 || nA_.last != 1 || nA_.children.size() != 2) return;
+  const int c1 = nA_.children[0], c2 = nA_.children[1];
+  const Node &L1 = P.nodes[c1], &L2 = P.nodes[c2];
+  if (!L1.leaf() || !L2.leaf()) return;
+  const int R = nA_.r;
+  if (L1.r != R || L2.r != R || L1.k != nA_.k || L2.k != nA_.k) return;
+  int KP = 0;
+  if (R == 16 && nA_.k <= 32) KP = 32;
+  else if (R == 32 && nA_.k <= 48) KP = 48;
+  else if (R == 64 && nA_.k <= 96) KP = 96;
+  if (KP == 0) return;
+  if (P.dims[0] != N1) return;
+  const Shape sh = shape_for(P.dtype, R);
+  const int64_t n2 = P.dims[1], nAs = N1 * n2, nB = P.N / nAs;
+  if (n2 % sh.B2 != 0 || nB % sh.SC != 0) return;
+  const int TA = static_cast<int>(n2 / sh.B2);
+  // column tiles: the fewest that give every compute unit a tile (else as many as divide)
+  int TB = 0;
+  for (int cand = 1; cand <= 256; cand *= 2) {
+    if (nB % (static_cast<int64_t>(sh.SC) * cand) != 0) continue;
+    TB = cand;
+    if (static_cast<int64_t>(TA) * cand >= 256) break;
+  }
+  if (TB == 0) return;
+  F.R = R;
+  F.KP = KP;
+  F.k = nA_.k;
+  F.B2 = sh.B2;
+  F.SC = sh.SC;
+  F.TA = TA;
+  F.TB = TB;
+  F.CB = static_cast<int>(nB / (static_cast<int64_t>(sh.SC) * TB));
+  F.n2 = n2;
+  F.nA = nAs;
+  F.nB = nB;
+  F.node_A = A;
+  F.node_1 = c1;
+  F.node_2 = c2;
+
+  const int dt = P.dtype;
+  const int64_t es = elem_size(dt);
+  const bool k8 = dt == TTNN_BF16;
+  // DRM copies in the fragment layouts of the kernel (values rounded like the compute copies)
+  F.XA = P.alloc(es * nB * R);
+  F.X1 = P.alloc(es * nAs / N1 * nB * R);
+  F.YA = P.alloc(es * nAs * KP);
+  F.Y1 = P.alloc(es * N1 * KP);
+  F.X2 = P.alloc(es * nB * KP * R);
+  const Node& NA = P.nodes[A];
+  const int k = nA_.k;
+  if (k8) {
+    copy_layout(NA.X64, F.XA, dt, nB, R, 1, R, 1, 0, 0, nB, st);                     // [j][iB]
+    copy_layout(L1.X64, F.X1, dt, nB, n2, R, n2 * R, R, 1, 0, nB, st);               // [j][i2][iB]
+    copy_layout(NA.Y64, F.YA, dt, nAs, KP, 1, k, 1, 0, 1, k, st);                    // [jA][iA]
+    copy_layout(L1.Y64, F.Y1, dt, N1, KP, 1, k, 1, 0, 1, k, st);                     // [j1][i1]
+    copy_layout(L2.X64, F.X2, dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
+  } else {
+    copy_layout(NA.X64, F.XA, dt, R, nB, 1, 1, R, 0, 0, R, st);                      // [iB][j]
+    copy_layout(L1.X64, F.X1, dt, R, nAs / N1 * nB, 1, 1, R, 0, 0, R, st);           // rows (i2 + n2 iB)
+    copy_layout(NA.Y64, F.YA, dt, KP, nAs, 1, 1, k, 0, 0, k, st);                    // [iA][jA]
+    copy_layout(L1.Y64, F.Y1, dt, KP, N1, 1, 1, k, 0, 0, k, st);                     // [i1][j1]
+    copy_layout(L2.X64, F.X2, dt, R, KP, nB, 1, R, static_cast<int64_t>(k) * R, 1, k, st);  // [iB][j1][j]
+  }
+  const int64_t as = dt == TTNN_F64 ? 8 : 4;
+  F.PRA = P.alloc(as * TB * nAs * R);
+  F.PZA = P.alloc(as * TA * KP * nB);
+  F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
+  F.PR2 = P.alloc(as * TB * n2 * R);
+  F.enabled = true;
+}
+
+bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
+                      hipStream_t st, std::vector<int>* done_nodes, std::vector<std::vector<int>>* done_prefixes) {
+  const FusedT4& F = P.fused;
+  if (!F.enabled) return false;
+  for (int mu = 0; mu < P.d; ++mu)
+    if (off[mu] != 0 || ext[mu] != P.dims[mu]) return false;
+  SttnnArgs a;
+  a.T = block;
+  a.n2 = F.n2;
+  a.nA = F.nA;
+  a.nB = F.nB;
+  a.TA = F.TA;
+  a.TB = F.TB;
+  a.CB = F.CB;
+  a.XA = F.XA;
+  a.X1 = F.X1;
+  a.YA = F.YA;
+  a.Y1 = F.Y1;
+  a.X2 = F.X2;
+  a.PRA = F.PRA;
+  a.PZA = F.PZA;
+  a.PR1 = F.PR1;
+  a.PR2 = F.PR2;
+  if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, a, st);
+  else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, a, st);
+  else launch_sttnn_dt<TTNN_F64>(F.R, a, st);
+
+  const std::vector<int> pre{F.node_A};
+  double* ZA = P.chain + P.prefix_offset.at(pre);
+  const int64_t total = F.nA * F.R + static_cast<int64_t>(F.k) * F.nB + static_cast<int64_t>(N1) * F.R + F.n2 * F.R;
+  const int blocks = static_cast<int>(std::min<int64_t>((total + 255) / 256, 8192));
+  if (P.dtype == TTNN_F64)
+    hipLaunchKernelGGL(sttnn_t4_reduce<double>, dim3(blocks), dim3(256), 0, st, static_cast<const double*>(F.PRA),
+                       static_cast<const double*>(F.PZA), static_cast<const double*>(F.PR1),
+                       static_cast<const double*>(F.PR2), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[F.node_2].R);
+  else
+    hipLaunchKernelGGL(sttnn_t4_reduce<float>, dim3(blocks), dim3(256), 0, st, static_cast<const float*>(F.PRA),
+                       static_cast<const float*>(F.PZA), static_cast<const float*>(F.PR1),
+                       static_cast<const float*>(F.PR2), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[F.node_2].R);
+  done_nodes->assign({F.node_A, F.node_1, F.node_2});
+  done_prefixes->assign({pre});
+  return true;
 }
 
 }  // namespace ttnn

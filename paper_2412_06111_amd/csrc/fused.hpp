@@ -1,13 +1,20 @@
 // Fused one-pass sketch kernels for large dense updates (see fused.hip).
 #pragma once
 
+#include <vector>
+
 #include "plan.hpp"
 
 namespace ttnn {
 
-// Runs the whole sketch phase of a box update with the fused kernels when the
-// plan and the box have a shape they cover; returns false (doing nothing) otherwise.
+// Plan-time setup: decides whether the plan's shape is covered and, if so, builds
+// the DRM copies in the kernel's fragment layouts and the partial-sum buffers.
+void fused_prepare(Plan& P, hipStream_t stream);
+
+// Runs the fused part of the sketch phase of a box update when covered; reports
+// the nodes whose accumulators it updated and the contraction prefixes it stored
+// in the chain scratch.  Returns false (doing nothing) otherwise.
 bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                      hipStream_t stream);
+                      hipStream_t stream, std::vector<int>* done_nodes, std::vector<std::vector<int>>* done_prefixes);
 
 }  // namespace ttnn

@@ -5,10 +5,12 @@
 // shapes (Sec. 4, eq. "sketch"; Sec. 5 for the reduced X_t of STTNN) and the
 // device memory of a plan.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
 #include "engine.hpp"
+#include "fused.hpp"
 #include "kernels.hpp"
 
 namespace ttnn {
@@ -218,6 +220,10 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
     launch_drm(nd.m, nd.r, P->seed, tx, nd.X64, x32, x16, stream);
     launch_drm(nd.n, nd.k, P->seed, ty, nd.Y64, y32, y16, stream);
   }
+  // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
+  const char* nf = std::getenv("TTNN_DISABLE_FUSED");
+  P->allow_fused = !(nf && nf[0] == '1');
+  if (P->allow_fused) fused_prepare(*P, stream);
   zero_accumulators(*P, stream);
   TTNN_HIP(hipGetLastError());
   return P;

@@ -36,6 +36,16 @@ struct Node {
   double* Pinv = nullptr;      // r x r column-major
 };
 
+// Fused one-pass STTNN kernel state (trees whose first root child is ({1},{2}))
+struct FusedT4 {
+  bool enabled = false;
+  int R = 0, KP = 0, k = 0, B2 = 0, SC = 0, TA = 0, TB = 0, CB = 0;
+  int64_t n2 = 0, nA = 0, nB = 0;
+  int node_A = -1, node_1 = -1, node_2 = -1;
+  void *XA = nullptr, *X1 = nullptr, *YA = nullptr, *Y1 = nullptr, *X2 = nullptr;
+  void *PRA = nullptr, *PZA = nullptr, *PR1 = nullptr, *PR2 = nullptr;
+};
+
 struct Plan {
   int d = 0;
   int64_t dims[TTNN_MAX_ORDER] = {};
@@ -67,6 +77,8 @@ struct Plan {
   ttnn_status sticky = TTNN_OK;
   bool epilogue_valid = false;             // Om / Psi reflect the accumulators
   bool has_cores = false;
+  FusedT4 fused;
+  bool allow_fused = true;                 // off: every update takes the generic path
 
   ~Plan();
   void* alloc(size_t bytes);

@@ -1,0 +1,78 @@
+"""GPU parity of the fused one-pass STTNN kernel (first root child ({1},{2}),
+n_1 = 128) against the oracle and against the generic HIP path, through the C ABI."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import TOL, rel, sketch_errors, to_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2412_06111_amd as P
+    return P
+
+
+def generic_plan(P, *args, **kw):
+    os.environ["TTNN_DISABLE_FUSED"] = "1"
+    try:
+        return P.Plan(*args, **kw)
+    finally:
+        del os.environ["TTNN_DISABLE_FUSED"]
+
+
+SHAPES = [
+    (O.T4, (128, 16, 8, 32)),
+    (O.T4, (128, 8, 16, 16)),
+    (((1, 2), (3, (4, 5))), (128, 8, 4, 8, 8)),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=["t4a", "t4b", "deep"])
+@pytest.mark.parametrize("r", [16, 32, 64])
+@pytest.mark.parametrize("dtype", ["bf16", "f32", "f64"])
+def test_fused_sttnn_parity(P, shape, r, dtype):
+    spec, dims = shape
+    p = r // 2
+    T = np.random.default_rng(11).standard_normal(dims)
+    dev, consumed = to_device(T, dtype)
+    plan = P.Plan(spec, dims, r, p, variant="sttnn", dtype=dtype, seed=4)
+    plan.update(dev)
+    tree = O.Tree(spec, dims, r, p)
+    sk = O.sketch(consumed, tree, O.DRMs(tree, 4, "sttnn"), "sttnn")
+    errs = sketch_errors(plan, tree, sk)
+    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    assert not bad, bad
+    gen = generic_plan(P, spec, dims, r, p, variant="sttnn", dtype=dtype, seed=4)
+    gen.update(dev)
+    for n in tree.nodes:
+        for kind in ((0, 1, 2) if n.id else (2,)):
+            a = plan.read_sketch(plan.node(n.modes), kind).cpu().numpy()
+            b = gen.read_sketch(gen.node(n.modes), kind).cpu().numpy()
+            assert rel(a, b) <= TOL[dtype], (n.modes, kind, rel(a, b))
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_fused_streaming_mix(P, dtype):
+    """Whole-tensor updates take the fused path, boxes the generic one; the sum of
+    both kinds equals the one-shot sketch of the summed tensor."""
+    spec, dims, r, p = O.T4, (128, 16, 8, 32), 32, 16
+    g = np.random.default_rng(12)
+    T1, T2 = g.standard_normal(dims), g.standard_normal(dims)
+    d1, c1 = to_device(T1, dtype)
+    box = T2[10:90, 3:12, 2:7, 5:30]
+    db, cb = to_device(box, dtype)
+    plan = P.Plan(spec, dims, r, p, variant="sttnn", dtype=dtype, seed=5)
+    plan.update(d1, alpha=2.0)
+    plan.update(db, extent=box.shape, offset=(10, 3, 2, 5), alpha=-1.0)
+    full = 2.0 * c1
+    full[10:90, 3:12, 2:7, 5:30] -= cb
+    tree = O.Tree(spec, dims, r, p)
+    sk = O.sketch(full, tree, O.DRMs(tree, 5, "sttnn"), "sttnn")
+    errs = sketch_errors(plan, tree, sk)
+    assert max(errs.values()) <= TOL[dtype], errs
