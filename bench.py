@@ -199,8 +199,9 @@ def main():
             results[f"{variant}:{dtype}"] = r
             print(f"# {variant} {dtype}: {json.dumps(r)}", file=sys.stderr, flush=True)
 
-    hv, hd = args.headline.split(":")
-    head = results[args.headline]
+    key = args.headline if args.headline in results else next(iter(results))
+    hv, hd = key.split(":")
+    head = results[key]
     t_hbm = head["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
     t_mfma = head["flops"] / (MFMA_PEAK_TFLOPS[hd] * 1e12)
     if t_mfma > t_hbm:

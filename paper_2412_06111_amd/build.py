@@ -27,6 +27,9 @@ COMMON = [
 ]
 # sources whose floating-point results must not depend on FMA contraction
 NO_CONTRACT = {"drm.hip"}
+# per-source extra flags: the fused kernels keep their accumulator arrays in registers
+# (LDS is reserved for the staged operands)
+EXTRA = {"fused.hip": ["-mllvm", "-disable-promote-alloca-to-lds"]}
 
 
 def _hipcc():
@@ -42,6 +45,7 @@ def _compile(src):
     flags = list(COMMON)
     if name in NO_CONTRACT:
         flags.append("-ffp-contract=off")
+    flags += EXTRA.get(name, [])
     if name.endswith(".hip"):
         cmd = [_hipcc(), "-x", "hip", *flags, "-c", src, "-o", obj]
     else:

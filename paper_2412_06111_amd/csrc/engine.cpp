@@ -51,8 +51,8 @@ int position_of_mode(const std::vector<Pos>& ps, int mode) {
   return -1;
 }
 
-// Store (or accumulate) a LEFT contraction, splitting the contraction when the
-// output is small.  mode: 2 = store, 1 = accumulate alpha * result.
+// Store (or accumulate) a LEFT contraction on the generic kernel, splitting the
+// contraction when the output is small.  mode: 2 = store, 1 = accumulate alpha * result.
 void left_op(Plan& P, GemmArgs g, double* dst, int mode, double alpha, hipStream_t st) {
   g.right = false;
   const int64_t rows = g.L * g.Q;
@@ -73,27 +73,106 @@ void left_op(Plan& P, GemmArgs g, double* dst, int mode, double alpha, hipStream
   launch_reduce(P.partial, nch, rows, g.ncols, mode, alpha, none, 0, dst, g.L, g.ncols, st);
 }
 
+// Dense FP64 mode product as a batched-GEMM job: the operand H is [L][n][Q]
+// (L fastest); out[l][j][q] = (acc ? out : 0) + alpha * sum_i H[l][i][q] M(i, j),
+// M(i, j) = M[i sMi + j sMj], j < c.
+GJob left_job(const double* H, int64_t L, int64_t n, int64_t Q, const double* M, int64_t sMi, int64_t sMj,
+              int64_t c, double* out, int acc, double alpha) {
+  GJob j;
+  j.K = n;
+  j.N = c;
+  j.B = M;
+  j.sBk = sMi;
+  j.sBn = sMj;
+  j.A = H;
+  j.C = out;
+  j.accumulate = acc;
+  j.alpha = alpha;
+  if (L == 1) {            // one GEMM: rows q
+    j.M = Q;
+    j.sAm = n;
+    j.sAk = 1;
+    j.sCm = c;
+    j.sCn = 1;
+  } else {                 // one GEMM per q
+    j.M = L;
+    j.nbC = static_cast<int>(Q);
+    j.sAm = 1;
+    j.sAk = L;
+    j.sAc = L * n;
+    j.sCm = 1;
+    j.sCn = L;
+    j.sCc = L * c;
+  }
+  return j;
+}
+
+// Dense FP64 right sketch as a job: R(i, j) += alpha * sum_{l,q} H[l][i][q] X[(l + L q) r + j]
+// with R column-major n x r.
+GJob right_job(const double* H, int64_t L, int64_t n, int64_t Q, const double* X, int64_t r, double* R,
+               double alpha) {
+  GJob j;
+  j.M = n;
+  j.N = r;
+  j.A = H;
+  j.B = X;
+  j.C = R;
+  j.sCm = 1;
+  j.sCn = n;
+  j.sBn = 1;
+  j.accumulate = 1;
+  j.alpha = alpha;
+  if (L == 1) {
+    j.K = Q;
+    j.sAm = 1;
+    j.sAk = n;
+    j.sBk = r;
+  } else {
+    j.K = L;
+    j.nbK = static_cast<int>(Q);
+    j.sAm = L;
+    j.sAk = 1;
+    j.sAkb = L * n;
+    j.sBk = r;
+    j.sBkb = L * r;
+  }
+  return j;
+}
+
+// Jobs collected between dependency points and launched together.
+struct Batch {
+  Plan& P;
+  hipStream_t st;
+  std::vector<GJob> jobs;
+  std::vector<const void*> outs;
+  Batch(Plan& p, hipStream_t s) : P(p), st(s) {}
+  void add(const GJob& j) {
+    jobs.push_back(j);
+    outs.push_back(j.C);
+  }
+  bool writes(const void* p) const { return std::find(outs.begin(), outs.end(), p) != outs.end(); }
+  void flush() {
+    if (jobs.empty()) return;
+    launch_bgemm64(jobs, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+    jobs.clear();
+    outs.clear();
+  }
+};
+
 // FP64 dense mode product on an operand with positions `sizes` (first fastest):
 // contract position p with M (rows = sizes[p]; M(i, j) at M[i*sMi + j*sMj]), j < ncols.
-void mode_product(Plan& P, const double* in, const std::vector<int64_t>& sizes, int p, const double* M,
-                  int64_t sMi, int64_t sMj, int ncols, double* out, hipStream_t st) {
-  GemmArgs g;
-  g.H = in;
-  g.th = TTNN_F64;
-  g.L = 1;
-  for (int i = 0; i < p; ++i) g.L *= sizes[i];
-  g.n = sizes[p];
-  g.Q = 1;
-  for (size_t i = p + 1; i < sizes.size(); ++i) g.Q *= sizes[i];
-  g.D = M;
-  g.td = TTNN_F64;
-  g.sDr = sMi;
-  g.sDc = sMj;
-  g.ncols = ncols;
-  IndexMap id;
-  id.push(g.n, 0, 1);
-  g.amap = id;
-  left_op(P, g, out, 2, 1.0, st);
+GJob mode_job(const double* in, const std::vector<int64_t>& sizes, int p, const double* M, int64_t sMi,
+              int64_t sMj, int64_t ncols, double* out) {
+  int64_t L = 1, Q = 1;
+  for (int i = 0; i < p; ++i) L *= sizes[i];
+  for (size_t i = p + 1; i < sizes.size(); ++i) Q *= sizes[i];
+  return left_job(in, L, sizes[p], Q, M, sMi, sMj, ncols, out, 0, 1.0);
+}
+
+bool whole_box(const Plan& P, const int64_t* off, const int64_t* ext) {
+  for (int mu = 0; mu < P.d; ++mu)
+    if (off[mu] != 0 || ext[mu] != P.dims[mu]) return false;
+  return true;
 }
 
 }  // namespace
@@ -120,34 +199,42 @@ void size_chain_scratch(Plan& P) {
   P.chain_elems = std::max<size_t>(total, 1);
 
   size_t part = size_t(1) << 22;
-  size_t work = 1, ustore = 0, inter = 1;
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     const Node& nd = P.nodes[v];
     part = std::max(part, static_cast<size_t>(nd.n * nd.r));
     part = std::max(part, static_cast<size_t>(nd.k * nd.r));
   }
+  part = std::max(part, static_cast<size_t>(P.psi_root_len));
+  P.partial_elems = part;
+
+  // work buffer: every intermediate of the epilogue chains, of the core chains, and
+  // the reconstruction's U_t plus two ping-pong buffers
+  size_t epi = 0, core = 0, ustore = 0, rinter = 1;
   for (size_t v = 0; v < P.nodes.size(); ++v) {
     const Node& nd = P.nodes[v];
     if (nd.leaf()) continue;
+    const size_t m = nd.children.size();
     const int64_t rt = v == 0 ? 1 : nd.r;
-    // epilogue / cores: prod_{<=i} k * prod_{>i} n * r  and  prod_{<=i} r_c * prod_{>i} k * r
-    for (size_t i = 0; i < nd.children.size(); ++i) {
-      int64_t a = rt, b = rt, c = rt;
-      for (size_t j = 0; j < nd.children.size(); ++j) {
-        const Node& ch = P.nodes[nd.children[j]];
-        a *= j <= i ? ch.k : ch.n;
-        b *= j <= i ? ch.r : ch.k;
-        c *= j <= i ? ch.n : ch.r;     // reconstruction
-      }
-      inter = std::max<size_t>(inter, std::max<int64_t>(a, b));
-      if (v != 0 || i + 1 < nd.children.size()) inter = std::max<size_t>(inter, c);
+    for (size_t step = 0; step + 1 < m; ++step) {          // epilogue: after step s, k for <= s, n after
+      if (v == 0) break;
+      int64_t e = rt;
+      for (size_t j = 0; j < m; ++j) e *= j <= step ? P.nodes[nd.children[j]].k : P.nodes[nd.children[j]].n;
+      epi += static_cast<size_t>(e);
+    }
+    const size_t nsteps = m + (v > 0 ? 1 : 0);
+    for (size_t step = 0; step + 1 < nsteps; ++step) {     // cores: r for <= s, k after
+      int64_t e = rt;
+      for (size_t j = 0; j < m; ++j) e *= j <= step ? P.nodes[nd.children[j]].r : P.nodes[nd.children[j]].k;
+      core += static_cast<size_t>(e);
+    }
+    for (size_t step = 0; step + 1 < m; ++step) {          // reconstruction: n for <= s, r after
+      int64_t e = rt;
+      for (size_t j = 0; j < m; ++j) e *= j <= step ? P.nodes[nd.children[j]].n : P.nodes[nd.children[j]].r;
+      rinter = std::max(rinter, static_cast<size_t>(e));
     }
     if (v != 0) ustore += static_cast<size_t>(nd.n * nd.r);
   }
-  work = 2 * inter + ustore;
-  part = std::max(part, static_cast<size_t>(P.psi_root_len));
-  P.partial_elems = part;
-  P.work_elems = work;
+  P.work_elems = std::max({epi, core, ustore + 2 * rinter, size_t(1)});
 }
 
 void zero_accumulators(Plan& P, hipStream_t st) {
@@ -166,58 +253,66 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
     try_fused_update(P, block, off, ext, alpha, st, &fused_nodes, &fused_prefixes);
 
   const int cd = P.dtype;                       // dtype of the block and of the DRM copies
+  const bool whole = whole_box(P, off, ext);
   std::map<std::vector<int>, bool> done;        // prefixes computed for this update
   for (const auto& pf : fused_prefixes) done[pf] = true;
+  Batch batch(P, st);
+  // The first contraction of the raw block runs on the generic kernel with the
+  // compute-dtype DRMs; every contraction of an FP64 intermediate uses the FP64
+  // DRMs (batched MFMA GEMM for whole-tensor updates, generic kernel for boxes).
+  auto chain_ptr = [&](const std::vector<int>& pf) { return P.chain + P.prefix_offset.at(pf); };
 
-  // returns the operand after contracting `prefix` (FP64 intermediate, or the block)
-  auto operand = [&](const std::vector<int>& prefix, int& th) -> const void* {
-    if (prefix.empty()) {
-      th = cd;
-      return block;
-    }
-    th = TTNN_F64;
-    double* dst = P.chain + P.prefix_offset.at(prefix);
-    if (done[prefix]) return dst;
+  auto operand = [&](const std::vector<int>& prefix) -> const void* {
+    if (prefix.empty()) return block;
     std::vector<int> chain;
     for (size_t j = 0; j < prefix.size(); ++j) {
       chain.push_back(prefix[j]);
-      double* out = P.chain + P.prefix_offset.at(chain);
       if (done[chain]) continue;
       std::vector<int> before(chain.begin(), chain.end() - 1);
-      int thin = cd;
-      const void* in = before.empty() ? block : static_cast<const void*>(P.chain + P.prefix_offset.at(before));
-      if (!before.empty()) thin = TTNN_F64;
       const std::vector<Pos> ps = positions_after(P, before, off, ext);
       const Node& g = P.nodes[chain.back()];
       const int p0 = position_of_mode(ps, g.first);
       const int w = g.last - g.first + 1;
-      GemmArgs a;
-      a.H = in;
-      a.th = thin;
-      a.L = prod_ext(ps, 0, p0);
-      a.n = prod_ext(ps, p0, p0 + w);
-      a.Q = prod_ext(ps, p0 + w, ps.size());
-      a.D = g.Yc;
-      a.td = cd;
-      a.sDr = g.k;
-      a.sDc = 1;
-      a.ncols = g.k;
-      a.amap = box_rows(P, g.first, g.last, off, ext);
-      left_op(P, a, out, 2, 1.0, st);
+      const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
+      if (!before.empty() && whole) {
+        if (batch.writes(chain_ptr(before))) batch.flush();
+        batch.add(left_job(chain_ptr(before), L, n, Q, g.Y64, g.k, 1, g.k, chain_ptr(chain), 0, 1.0));
+      } else {
+        batch.flush();
+        GemmArgs a;
+        a.H = before.empty() ? block : static_cast<const void*>(chain_ptr(before));
+        a.th = before.empty() ? cd : TTNN_F64;
+        a.L = L;
+        a.n = n;
+        a.Q = Q;
+        a.D = before.empty() ? g.Yc : static_cast<const void*>(g.Y64);
+        a.td = before.empty() ? cd : TTNN_F64;
+        a.sDr = g.k;
+        a.sDc = 1;
+        a.ncols = g.k;
+        a.amap = box_rows(P, g.first, g.last, off, ext);
+        left_op(P, a, chain_ptr(chain), 2, 1.0, st);
+      }
       done[chain] = true;
     }
-    return dst;
+    return chain_ptr(prefix);
   };
 
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     if (std::find(fused_nodes.begin(), fused_nodes.end(), static_cast<int>(v)) != fused_nodes.end()) continue;
     Node& t = P.nodes[v];
     const std::vector<int>& pre = t.S;          // empty for TTNN
-    int th = cd;
-    const void* in = operand(pre, th);
+    const void* in = operand(pre);
     const std::vector<Pos> ps = positions_after(P, pre, off, ext);
     const int p0 = position_of_mode(ps, t.first);
     const int w = t.last - t.first + 1;
+    const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
+    if (!pre.empty() && whole) {
+      if (batch.writes(in)) batch.flush();
+      batch.add(right_job(static_cast<const double*>(in), L, n, Q, t.X64, t.r, t.R, alpha));
+      continue;
+    }
+    batch.flush();
     // X_t rows: every position except those of t, first fastest
     IndexMap amap, bmap;
     int64_t C = 1;
@@ -230,12 +325,12 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
     GemmArgs a;
     a.right = true;
     a.H = in;
-    a.th = th;
-    a.L = prod_ext(ps, 0, p0);
-    a.n = prod_ext(ps, p0, p0 + w);
-    a.Q = prod_ext(ps, p0 + w, ps.size());
-    a.D = t.Xc;
-    a.td = cd;
+    a.th = pre.empty() ? cd : TTNN_F64;
+    a.L = L;
+    a.n = n;
+    a.Q = Q;
+    a.D = pre.empty() ? t.Xc : static_cast<const void*>(t.X64);
+    a.td = pre.empty() ? cd : TTNN_F64;
     a.sDr = t.r;
     a.sDc = 1;
     a.ncols = t.r;
@@ -253,20 +348,27 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
   // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0
   const auto& rc = P.nodes[0].children;
   std::vector<int> before(rc.begin(), rc.end() - 1);
-  int th = cd;
-  const void* in = operand(before, th);
+  const void* in = operand(before);
   const std::vector<Pos> ps = positions_after(P, before, off, ext);
   const Node& g = P.nodes[rc.back()];
   const int p0 = position_of_mode(ps, g.first);
   const int w = g.last - g.first + 1;
+  const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
+  if (!before.empty() && whole) {
+    if (batch.writes(in)) batch.flush();
+    batch.add(left_job(static_cast<const double*>(in), L, n, Q, g.Y64, g.k, 1, g.k, P.psi_root, 1, alpha));
+    batch.flush();
+    return;
+  }
+  batch.flush();
   GemmArgs a;
   a.H = in;
-  a.th = th;
-  a.L = prod_ext(ps, 0, p0);
-  a.n = prod_ext(ps, p0, p0 + w);
-  a.Q = prod_ext(ps, p0 + w, ps.size());
-  a.D = g.Yc;
-  a.td = cd;
+  a.th = before.empty() ? cd : TTNN_F64;
+  a.L = L;
+  a.n = n;
+  a.Q = Q;
+  a.D = before.empty() ? g.Yc : static_cast<const void*>(g.Y64);
+  a.td = before.empty() ? cd : TTNN_F64;
   a.sDr = g.k;
   a.sDc = 1;
   a.ncols = g.k;
@@ -275,26 +377,52 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
 }
 
 // ---------------------------------------------------------------- epilogue
+// Omega_t = Y_t^T R_t for every non-root node and Psi_t = (Y_cm^T kron ... kron Y_c1^T) R_t
+// for internal nodes (child c1 fastest), in FP64 with the FP64 DRMs.  Jobs of one
+// chain step are launched together.
 void run_epilogue(Plan& P, hipStream_t st) {
-  for (size_t v = 1; v < P.nodes.size(); ++v) {
+  Batch batch(P, st);
+  const int nn = static_cast<int>(P.nodes.size());
+  // work buffers for the chain steps of every internal node (disjoint slices)
+  std::vector<double*> buf(nn, nullptr), buf2(nn, nullptr);
+  size_t used = 0;
+  size_t maxstep = 1;
+  for (int v = 1; v < nn; ++v) maxstep = std::max(maxstep, P.nodes[v].children.size());
+  for (int v = 1; v < nn; ++v) {
     Node& t = P.nodes[v];
-    // Omega_t = Y_t^T R_t  (R_t viewed as [1][n_t][r_t])
-    mode_product(P, t.R, {t.n, t.r}, 0, t.Y64, t.k, 1, t.k, t.Om, st);
-    if (t.leaf()) continue;
-    // Psi_t = (Y_cm^T kron ... kron Y_c1^T) R_t
-    std::vector<int64_t> sizes;
-    for (int c : t.children) sizes.push_back(P.nodes[c].n);
-    sizes.push_back(t.r);
-    const double* cur = t.R;
-    double* bufs[2] = {P.work, P.work + (P.work_elems / 2)};
-    for (size_t i = 0; i < t.children.size(); ++i) {
-      const Node& c = P.nodes[t.children[i]];
-      double* out = (i + 1 == t.children.size()) ? t.Psi : bufs[i % 2];
-      mode_product(P, cur, sizes, static_cast<int>(i), c.Y64, c.k, 1, c.k, out, st);
-      sizes[i] = c.k;
-      cur = out;
-    }
+    batch.add(left_job(t.R, 1, t.n, t.r, t.Y64, t.k, 1, t.k, t.Om, 0, 1.0));
   }
+  for (size_t step = 0; step < maxstep; ++step) {
+    for (int v = 1; v < nn; ++v) {
+      Node& t = P.nodes[v];
+      if (t.leaf() || step >= t.children.size()) continue;
+      // sizes after `step` contractions: k_c (done) then n_c (pending) then r
+      std::vector<int64_t> sizes;
+      for (size_t i = 0; i < t.children.size(); ++i)
+        sizes.push_back(i < step ? P.nodes[t.children[i]].k : P.nodes[t.children[i]].n);
+      sizes.push_back(t.r);
+      int64_t elems = 1;
+      for (int64_t x : sizes) elems *= x;
+      const Node& c = P.nodes[t.children[step]];
+      const bool last = step + 1 == t.children.size();
+      const double* in = step == 0 ? t.R : (step % 2 == 1 ? buf[v] : buf2[v]);
+      double* out;
+      if (last) out = t.Psi;
+      else {
+        const size_t need = static_cast<size_t>(elems / c.n * c.k);
+        double*& slot = (step % 2 == 0) ? buf[v] : buf2[v];
+        if (!slot) {
+          slot = P.work + used;
+          used += need;
+          TTNN_REQUIRE(used <= P.work_elems, TTNN_E_INVALID, "epilogue work buffer too small");
+        }
+        out = slot;
+      }
+      batch.add(mode_job(in, sizes, static_cast<int>(step), c.Y64, c.k, 1, c.k, out));
+    }
+    batch.flush();
+  }
+  batch.flush();
   P.epilogue_valid = true;
 }
 
@@ -316,53 +444,71 @@ ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
   if (!P.epilogue_valid) run_epilogue(P, st);
   const int nn = static_cast<int>(P.nodes.size());
   // finite check of the sketches
-  TTNN_HIP(hipMemsetAsync(P.d_flag, 0, sizeof(int) * 2 * TTNN_MAX_NODES, st));
+  launch_zero_int(P.d_flag, 2 * TTNN_MAX_NODES, st);
   for (int v = 1; v < nn; ++v) launch_finite_check(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r, P.d_flag, st);
   launch_finite_check(P.psi_root, P.psi_root_len, P.d_flag, st);
 
-  std::vector<QrJob>& jobs = P.host_jobs;
-  jobs.clear();
+  QrJobList jl{};
   int max_k = 1, max_r = 1;
   for (int v = 1; v < nn; ++v) {
     const Node& t = P.nodes[v];
-    jobs.push_back(QrJob{t.Om, t.Q, t.Pinv, t.k, t.r});
+    jl.jobs[jl.n++] = QrJob{t.Om, t.Q, t.Pinv, t.k, t.r};
     max_k = std::max(max_k, t.k);
     max_r = std::max(max_r, t.r);
   }
-  TTNN_REQUIRE(static_cast<size_t>(max_k * max_r + 2 * max_r * max_r) * 8 <= 160 * 1024, TTNN_E_INVALID,
-               "ranks too large for the in-LDS recovery kernel");
-  TTNN_HIP(hipMemcpyAsync(P.d_jobs, jobs.data(), sizeof(QrJob) * jobs.size(), hipMemcpyHostToDevice, st));
-  int* d_kept = P.d_flag + 1;
-  launch_qr_pinv(P.d_jobs, static_cast<int>(jobs.size()), max_k, max_r, P.eps_factor, d_kept, st);
+  launch_qr_pinv(jl, max_k, max_r, P.eps_factor, P.d_flag + 1, st);
 
-  // cores
-  double* bufs[2] = {P.work, P.work + (P.work_elems / 2)};
-  for (int v = 0; v < nn; ++v) {
-    const Node& t = P.nodes[v];
-    if (v > 0 && t.leaf()) {
-      // B_t = Psi_t Pinv_t  (Psi_t = R_t, n_t x r_t; Pinv col-major r x r)
-      mode_product(P, t.R, {t.n, t.r}, 1, t.Pinv, 1, t.r, t.r, cores[v], st);
-      continue;
+  // cores: leaves B = Psi Pinv; internal nodes and root contract Psi with Q_c^T child by
+  // child, then (non-root) apply Pinv.
+  Batch batch(P, st);
+  std::vector<double*> buf(nn, nullptr), buf2(nn, nullptr);
+  size_t used = 0;
+  size_t maxstep = 0;
+  for (int v = 0; v < nn; ++v)
+    if (!P.nodes[v].leaf()) maxstep = std::max(maxstep, P.nodes[v].children.size() + (v > 0 ? 1 : 0));
+  for (int v = 1; v < nn; ++v)
+    if (P.nodes[v].leaf()) {
+      const Node& t = P.nodes[v];
+      batch.add(mode_job(t.R, {t.n, t.r}, 1, t.Pinv, 1, t.r, t.r, cores[v]));
     }
-    std::vector<int64_t> sizes;
-    for (int c : t.children) sizes.push_back(P.nodes[c].k);
-    if (v > 0) sizes.push_back(t.r);
-    const double* cur = v == 0 ? P.psi_root : t.Psi;
-    const size_t m = t.children.size();
-    for (size_t i = 0; i < m; ++i) {
-      const Node& c = P.nodes[t.children[i]];
-      const bool last = (i + 1 == m) && v == 0;
-      double* out = last ? cores[v] : bufs[i % 2];
-      mode_product(P, cur, sizes, static_cast<int>(i), c.Q, 1, c.k, c.r, out, st);   // Q_c^T
-      sizes[i] = c.r;
-      cur = out;
+  for (size_t step = 0; step < maxstep; ++step) {
+    for (int v = 0; v < nn; ++v) {
+      const Node& t = P.nodes[v];
+      if (t.leaf()) continue;
+      const size_t m = t.children.size();
+      const size_t nsteps = m + (v > 0 ? 1 : 0);
+      if (step >= nsteps) continue;
+      const double* in = step == 0 ? (v == 0 ? P.psi_root : t.Psi) : (step % 2 == 1 ? buf[v] : buf2[v]);
+      const bool last = step + 1 == nsteps;
+      std::vector<int64_t> sizes;
+      for (size_t i = 0; i < m; ++i) sizes.push_back(i < step ? P.nodes[t.children[i]].r : P.nodes[t.children[i]].k);
+      if (v > 0) sizes.push_back(t.r);
+      int64_t elems = 1;
+      for (int64_t x : sizes) elems *= x;
+      double* out;
+      if (last) out = cores[v];
+      else {
+        const Node& c = P.nodes[t.children[step]];
+        const size_t need = static_cast<size_t>(elems / c.k * c.r);
+        double*& slot = (step % 2 == 0) ? buf[v] : buf2[v];
+        if (!slot) {
+          slot = P.work + used;
+          used += need;
+          TTNN_REQUIRE(used <= P.work_elems, TTNN_E_INVALID, "assembly work buffer too small");
+        }
+        out = slot;
+      }
+      if (step < m) {
+        const Node& c = P.nodes[t.children[step]];
+        batch.add(mode_job(in, sizes, static_cast<int>(step), c.Q, 1, c.k, c.r, out));   // Q_c^T
+      } else {
+        int64_t rows = elems / t.r;
+        batch.add(mode_job(in, {rows, t.r}, 1, t.Pinv, 1, t.r, t.r, out));
+      }
     }
-    if (v > 0) {
-      int64_t rows = 1;
-      for (size_t i = 0; i < m; ++i) rows *= sizes[i];
-      mode_product(P, cur, {rows, t.r}, 1, t.Pinv, 1, t.r, t.r, cores[v], st);
-    }
+    batch.flush();
   }
+  batch.flush();
   // status: flag[0] = non-finite, kept counts of each job
   std::vector<int> host(nn, 0);
   TTNN_HIP(hipMemcpyAsync(host.data(), P.d_flag, sizeof(int) * nn, hipMemcpyDeviceToHost, st));
@@ -375,74 +521,85 @@ ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- reconstruction
+// U_leaf = B_leaf, U_t = (U_cm kron ... kron U_c1) B_t, vec(T_hat) = (U_cm kron ... kron U_c1) B_0,
+// deepest nodes first; the final contraction writes the caller's buffer.
 void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dtype, hipStream_t st) {
   const int nn = static_cast<int>(P.nodes.size());
-  // U_t for internal non-root nodes, children before parents
   std::vector<const double*> U(nn, nullptr);
-  double* ustore = P.work;
   size_t inter = 0;
   for (int v = 1; v < nn; ++v)
     if (!P.nodes[v].leaf()) inter += static_cast<size_t>(P.nodes[v].n * P.nodes[v].r);
+  double* ustore = P.work;
   double* bufs[2] = {P.work + inter, P.work + inter + (P.work_elems - inter) / 2};
   size_t used = 0;
-  for (int v = nn - 1; v >= 0; --v) {
-    const Node& t = P.nodes[v];
-    if (v > 0 && t.leaf()) {
-      U[v] = cores[v];
-      continue;
-    }
-    std::vector<int64_t> sizes;
-    for (int c : t.children) sizes.push_back(P.nodes[c].r);
-    if (v > 0) sizes.push_back(t.r);
-    const double* cur = cores[v];
-    const size_t m = t.children.size();
-    double* dest = nullptr;
-    if (v > 0) {
-      dest = ustore + used;
-      used += static_cast<size_t>(t.n * t.r);
-    }
-    for (size_t i = 0; i < m; ++i) {
-      const Node& c = P.nodes[t.children[i]];
-      const bool last = i + 1 == m;
-      if (last && v == 0) {
-        // final step writes the dense tensor (dtype of the caller's buffer) directly
-        GemmArgs g;
-        g.right = false;
-        g.H = cur;
-        g.th = TTNN_F64;
-        g.L = 1;
-        for (size_t j = 0; j < i; ++j) g.L *= sizes[j];
-        g.n = sizes[i];
-        g.Q = 1;
-        g.D = U[t.children[i]];
-        g.td = TTNN_F64;
-        g.sDr = c.n;
-        g.sDc = 1;
-        g.ncols = static_cast<int>(c.n);
-        IndexMap id;
-        id.push(g.n, 0, 1);
-        g.amap = id;
-        g.nchunks = 1;
-        g.out = out;
-        g.out_f32 = out_dtype == TTNN_F32;
-        g.ol = OutLayout{g.L, 1, g.L, g.L * g.ncols, 0};
-        launch_gemm(g, st);
-        break;
+  int maxlevel = 0;
+  for (const Node& t : P.nodes) maxlevel = std::max(maxlevel, t.level);
+  for (int v = 1; v < nn; ++v)
+    if (P.nodes[v].leaf()) U[v] = cores[v];
+  Batch batch(P, st);
+  for (int lev = maxlevel; lev >= 0; --lev) {
+    for (int v = nn - 1; v >= 0; --v) {
+      const Node& t = P.nodes[v];
+      if (t.level != lev || t.leaf()) continue;
+      std::vector<int64_t> sizes;
+      for (int c : t.children) sizes.push_back(P.nodes[c].r);
+      if (v > 0) sizes.push_back(t.r);
+      const double* cur = cores[v];
+      const size_t m = t.children.size();
+      double* dest = nullptr;
+      if (v > 0) {
+        dest = ustore + used;
+        used += static_cast<size_t>(t.n * t.r);
       }
-      double* o = last ? dest : bufs[i % 2];
-      // contract position i (size r_c) with U_c^T: M(i', j) = U_c[j + n_c i']
-      mode_product(P, cur, sizes, static_cast<int>(i), U[t.children[i]], c.n, 1, static_cast<int>(c.n), o, st);
-      sizes[i] = c.n;
-      cur = o;
+      for (size_t i = 0; i < m; ++i) {
+        const Node& c = P.nodes[t.children[i]];
+        const bool last = i + 1 == m;
+        if (last && v == 0) {
+          batch.flush();
+          // final step writes the dense tensor (dtype of the caller's buffer) directly
+          GemmArgs g;
+          g.right = false;
+          g.H = cur;
+          g.th = TTNN_F64;
+          g.L = 1;
+          for (size_t j = 0; j < i; ++j) g.L *= sizes[j];
+          g.n = sizes[i];
+          g.Q = 1;
+          g.D = U[t.children[i]];
+          g.td = TTNN_F64;
+          g.sDr = c.n;
+          g.sDc = 1;
+          g.ncols = static_cast<int>(c.n);
+          IndexMap id;
+          id.push(g.n, 0, 1);
+          g.amap = id;
+          g.nchunks = 1;
+          g.out = out;
+          g.out_f32 = out_dtype == TTNN_F32;
+          g.ol = OutLayout{g.L, 1, g.L, g.L * g.ncols, 0};
+          if (out_dtype == TTNN_F64) {
+            std::vector<GJob> one{mode_job(cur, sizes, static_cast<int>(i), U[t.children[i]], c.n, 1, c.n,
+                                           static_cast<double*>(out))};
+            launch_bgemm64(one, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+          } else {
+            launch_gemm(g, st);
+          }
+          break;
+        }
+        double* o = last ? dest : bufs[i % 2];
+        // contract position i (size r_c) with U_c^T: M(i', j) = U_c[j + n_c i']
+        std::vector<GJob> one{mode_job(cur, sizes, static_cast<int>(i), U[t.children[i]], c.n, 1, c.n, o)};
+        launch_bgemm64(one, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+        sizes[i] = c.n;
+        cur = o;
+      }
+      if (v > 0) U[v] = dest;
     }
-    if (v > 0) U[v] = dest;
   }
+  batch.flush();
 }
 
 void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t st) {
-  // H = a_1 o ... o a_d is materialised in FP64 in the chain scratch only when it
-  // fits; otherwise the update is rejected by the caller.  Rank-1 terms arrive as
-  // dense blocks through the same path as box updates.
   (void)P;
   (void)factors;
   (void)alpha;

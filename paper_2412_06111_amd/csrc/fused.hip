@@ -41,31 +41,128 @@ __device__ inline typename P::Frag frag_contig(const typename P::T* p) {
   else return *p;
 }
 
+// LDS plan of the kernel: the slab of T and the DRM rows of one sub-tile are copied
+// straight from global memory into one of two LDS stages (global_load_lds, 16 bytes
+// per lane) while the other stage is being consumed.  Operands that do not fit the
+// budget are read from global memory (L2) instead.
 template <int DT, int R, int KP, int B2, int SC>
-__global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
+struct SttnnLayout {
   using P = Pol<DT>;
+  using T = typename P::T;
+  static constexpr int ESZ = P::ESZ;
+  static constexpr int KPL = P::KPL;
+  static constexpr int PADE = 16 / ESZ;                       // one 16-byte vector of padding
+  static constexpr int S = N1 + PADE;                         // slab column stride
+  static constexpr int SY = (KPL == 8) ? N1 + PADE : KP;      // row stride of staged Y blocks
+  static constexpr int SX = (KPL == 8) ? SC + PADE : R;       // row stride of staged X blocks
+  static constexpr int YROWS = (KPL == 8) ? KP : N1;
+  static constexpr int XROWS = (KPL == 8) ? R : SC;
+  static constexpr size_t MS = size_t(SC) * S * ESZ;
+  static constexpr size_t Z1 = size_t(B2) * KP * SC * ESZ;
+  static constexpr size_t YB = size_t(YROWS) * SY * ESZ;
+  static constexpr size_t XB = size_t(XROWS) * SX * ESZ;
+  static constexpr size_t BUDGET = 156 * 1024;
+  static constexpr bool STAGE_YA = 2 * (MS + YB) + Z1 <= BUDGET;
+  static constexpr bool STAGE_X = STAGE_YA && 2 * (MS + YB + 2 * XB) + Z1 <= BUDGET;
+  static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
+  static constexpr bool STAGE_Y1 = 2 * STAGE + Z1 + YB <= BUDGET;
+  static constexpr size_t OFF_YA = MS;                         // offsets within a stage
+  static constexpr size_t OFF_XA = OFF_YA + (STAGE_YA ? YB : 0);
+  static constexpr size_t OFF_X1 = OFF_XA + (STAGE_X ? XB : 0);
+  static constexpr size_t OFF_Z1 = 2 * STAGE;                 // after both stages
+  static constexpr size_t OFF_Y1 = OFF_Z1 + Z1;
+  static constexpr size_t TOTAL = OFF_Y1 + (STAGE_Y1 ? YB : 0);
+};
+
+constexpr int kThreadsF = 512;
+
+// One lane's 16 bytes from global memory straight into LDS (global_load_lds_dwordx4);
+// the LDS address is the wave's base plus 16 bytes per lane.
+__device__ inline void lds_dma16(const void* g, void* l) {
+  __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+}
+
+// Copy `rows` rows of `vecs` 16-byte vectors, row r from g + r*gs to l + r*ls
+// (elements), straight into LDS; rows are dealt to the eight waves, one instruction
+// per row and 64 vectors.  The LDS address of an instruction is wave-uniform.
+template <typename T>
+__device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int ls, int rows, int vecs, int wave, int lane) {
+  constexpr int EV = 16 / sizeof(T);
+  for (int r = wave; r < rows; r += kThreadsF / 64) {
+    for (int c0 = 0; c0 < vecs; c0 += 64) {
+      if (lane < vecs - c0) lds_dma16(g + r * gs + static_cast<int64_t>(c0 + lane) * EV, l + r * ls + c0 * EV);
+    }
+  }
+}
+
+// Copy `vecs` contiguous 16-byte vectors from g to l, 64 per instruction, dealt to waves.
+template <typename T>
+__device__ inline void lds_dma_contig(const T* g, T* l, int vecs, int wave, int lane) {
+  constexpr int EV = 16 / sizeof(T);
+  for (int c0 = wave * 64; c0 < vecs; c0 += kThreadsF) {
+    if (lane < vecs - c0) lds_dma16(g + static_cast<int64_t>(c0 + lane) * EV, l + c0 * EV);
+  }
+}
+
+
+// Issue the copies of the sub-tile (slab i2, columns col0 .. col0+SC-1) into one stage.
+template <int DT, int R, int KP, int B2, int SC>
+__device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int64_t col0, int wave, int lane) {
+  using P = Pol<DT>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC>;
+  using T = typename P::T;
+  constexpr int EV = 16 / sizeof(T);
+  const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
+  lds_dma_rows(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), Lay::S, SC, N1 / EV,
+               wave, lane);
+  if constexpr (Lay::STAGE_YA) {
+    const T* YA = static_cast<const T*>(a.YA);
+    T* ys = reinterpret_cast<T*>(sb + Lay::OFF_YA);
+    if constexpr (P::KPL == 8) lds_dma_rows(YA + i2 * N1, nA, ys, Lay::SY, KP, N1 / EV, wave, lane);
+    else lds_dma_contig(YA + i2 * N1 * KP, ys, N1 * KP / EV, wave, lane);
+  }
+  if constexpr (Lay::STAGE_X) {
+    const T* XA = static_cast<const T*>(a.XA);
+    const T* X1 = static_cast<const T*>(a.X1);
+    T* xa = reinterpret_cast<T*>(sb + Lay::OFF_XA);
+    T* x1 = reinterpret_cast<T*>(sb + Lay::OFF_X1);
+    if constexpr (P::KPL == 8) {
+      lds_dma_rows(XA + col0, nB, xa, Lay::SX, R, SC / EV, wave, lane);
+      lds_dma_rows(X1 + i2 * nB + col0, n2 * nB, x1, Lay::SX, R, SC / EV, wave, lane);
+    } else {
+      lds_dma_contig(XA + col0 * R, xa, SC * R / EV, wave, lane);
+      lds_dma_rows(X1 + (i2 + n2 * col0) * R, n2 * R, x1, R, SC, R / EV, wave, lane);
+    }
+  }
+}
+
+template <int DT, int R, int KP, int B2, int SC>
+__global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
+  using P = Pol<DT>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC>;
   using T = typename P::T;
   using Acc = typename P::Acc;
   using Frag = typename P::Frag;
   using CFrag = typename P::CFrag;
-  constexpr int KPL = P::KPL, KSTEP = P::KSTEP;
-  constexpr int PAD = 16 / P::ESZ;
-  constexpr int S = N1 + PAD;               // LDS column stride (elements)
+  constexpr int KPL = P::KPL, KSTEP = P::KSTEP, ESZ = P::ESZ;
+  constexpr int EV = 16 / ESZ;              // elements per 16-byte vector
+  constexpr int S = Lay::S, SY = Lay::SY, SX = Lay::SX;
   constexpr int CBR = R / 16;               // 16-wide column blocks of an R-wide output
   constexpr int KB = KP / 16;               // 16-row blocks of KP
   constexpr int NCB = SC / 16;              // 16-wide column blocks of a sub-tile
   static_assert(NCB == 4 || NCB == 2, "sub-tile width");
-  constexpr int KT = KP * SC;               // (d2) contraction length per sub-tile column block
-  constexpr int KW = KT / 4;                // per wave
-  constexpr int VPC = N1 * P::ESZ / 16;     // 16-byte vectors per column of a slab
-  constexpr int NVEC = VPC * SC / 256;
-  static_assert(NVEC * 256 == VPC * SC, "slab split");
-  static_assert(4 * 16 * R * sizeof(Acc) <= SC * S * sizeof(T), "reduction scratch aliases the slab");
+  constexpr int KT = KP * SC;               // (d2) contraction length per column sub-block
+  constexpr int KW = KT / 8;                // per wave
+  static_assert(KW % KSTEP == 0, "(d2) split");
+  static_assert(Lay::TOTAL <= 160 * 1024, "LDS budget");
+  static_assert(8 * 16 * R * sizeof(Acc) <= Lay::TOTAL, "reduction scratch");
 
-  __shared__ __align__(16) T Ms[SC * S];
-  __shared__ __align__(16) T Z1s[B2 * KT];
+  __shared__ __align__(16) char smem[Lay::TOTAL];
+  T* Z1s = reinterpret_cast<T*>(smem + Lay::OFF_Z1);
+  T* Y1s = reinterpret_cast<T*>(smem + Lay::OFF_Y1);
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
 
   // tile of this workgroup; tiles of one column band share an XCD (L2) when possible
   int tA, tB;
@@ -90,47 +187,40 @@ __global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
   const T* X2 = static_cast<const T*>(a.X2);
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
 
-  uint4 pre[NVEC];
-  auto load_sub = [&](int s) {
+  auto stage_base = [&](int buf) -> char* { return smem + buf * Lay::STAGE; };
+  // issue the copies of sub-tile s into stage buf
+  auto issue = [&](int s, int buf) {
     const int cb = s / B2, i2l = s % B2;
-    const int64_t col0 = c_tile + static_cast<int64_t>(cb) * SC;
-    const int64_t base = (i2_0 + i2l) * N1;
-#pragma unroll
-    for (int u = 0; u < NVEC; ++u) {
-      const int vid = tid + 256 * u;
-      const int col = vid / VPC, part = vid % VPC;
-      pre[u] = *reinterpret_cast<const uint4*>(Tg + base + nA * (col0 + col) + part * (16 / P::ESZ));
-    }
+    sttnn_issue<DT, R, KP, B2, SC>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC, wave,
+                                   lane);
   };
-  auto store_sub = [&]() {
-#pragma unroll
-    for (int u = 0; u < NVEC; ++u) {
-      const int vid = tid + 256 * u;
-      const int col = vid / VPC, part = vid % VPC;
-      *reinterpret_cast<uint4*>(&Ms[col * S + part * (16 / P::ESZ)]) = pre[u];
-    }
-  };
+  // Y_1 rows, resident for the whole kernel
+  if constexpr (Lay::STAGE_Y1) {
+    if constexpr (KPL == 8) lds_dma_rows(Y1, N1, Y1s, SY, KP, N1 / EV, wave, lane);
+    else lds_dma_contig(Y1, Y1s, N1 * KP / EV, wave, lane);
+  }
 
-  CFrag rA[B2][2][CBR];
-  CFrag r1[2][CBR];
+  CFrag rA[B2][CBR];
+  CFrag r1[CBR];
   CFrag r2[CBR];
   CFrag zA[KB];
   const CFrag zero = {};
 #pragma unroll
   for (int i = 0; i < B2; ++i)
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int c = 0; c < CBR; ++c) rA[i][c] = zero;
 #pragma unroll
-      for (int c = 0; c < CBR; ++c) rA[i][rb][c] = zero;
-#pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-    for (int c = 0; c < CBR; ++c) r1[rb][c] = zero;
-#pragma unroll
-  for (int c = 0; c < CBR; ++c) r2[c] = zero;
+  for (int c = 0; c < CBR; ++c) {
+    r1[c] = zero;
+    r2[c] = zero;
+  }
+  // roles in the (b)/(d1) phase: Z_A or Z1 for one 16-column block of the sub-tile
+  const bool bd_active = wave < 2 * NCB;
+  const int cblk = wave % NCB;
+  const bool bd_zA = (wave / NCB) == 0;
 
   const int nsub = a.CB * B2;
-  load_sub(0);
+  issue(0, 0);
   for (int cb = 0; cb < a.CB; ++cb) {
     const int64_t iBbase = c_tile + static_cast<int64_t>(cb) * SC;
 #pragma unroll
@@ -140,84 +230,105 @@ __global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
     for (int i2l = 0; i2l < B2; ++i2l) {
       const int s = cb * B2 + i2l;
       const int64_t i2 = i2_0 + i2l;
-      __syncthreads();
-      store_sub();
-      __syncthreads();
-      if (s + 1 < nsub) load_sub(s + 1);
+      const int buf = s & 1;
+      __builtin_amdgcn_s_waitcnt(0);      // this wave's copies of sub-tile s have landed
+      __syncthreads();                    // ... everyone's; and stage buf^1 is free again
+      if (s + 1 < nsub) issue(s + 1, buf ^ 1);
+      const T* Ms = reinterpret_cast<const T*>(stage_base(buf));
+      const T* YAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
+      const T* XAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XA);
+      const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
 
       // (a) R_A rows of this slab and (c) R_1: A = slab (rows i1, K = columns)
-#pragma unroll 2
+      const int i1 = 16 * wave + l16;
+#pragma unroll 4
       for (int ks = 0; ks < SC / KSTEP; ++ks) {
         const int kk = ks * KSTEP + KPL * lg;
-        Frag af[2];
+        Frag af;
+        if constexpr (KPL == 8) {
+          u16x8_t v;
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb) {
-          const int i1 = 32 * wave + 16 * rb + l16;
-          if constexpr (KPL == 8) {
-            u16x8_t v;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) v[e] = Ms[(kk + e) * S + i1];
-            af[rb] = __builtin_bit_cast(Frag, v);
-          } else {
-            af[rb] = Ms[kk * S + i1];
-          }
+          for (int e = 0; e < 8; ++e) v[e] = Ms[(kk + e) * S + i1];
+          af = __builtin_bit_cast(Frag, v);
+        } else {
+          af = Ms[kk * S + i1];
         }
 #pragma unroll
         for (int c = 0; c < CBR; ++c) {
           const int j = 16 * c + l16;
           Frag bA, b1;
-          if constexpr (KPL == 8) {
-            bA = P::load8(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
-            b1 = P::load8(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
+          if constexpr (Lay::STAGE_X) {
+            if constexpr (KPL == 8) {
+              bA = P::load8(XAs + j * SX + kk);
+              b1 = P::load8(X1s + j * SX + kk);
+            } else {
+              bA = XAs[kk * R + j];
+              b1 = X1s[kk * R + j];
+            }
           } else {
-            bA = XA[(iBbase + kk) * R + j];
-            b1 = X1[(i2 + n2 * (iBbase + kk)) * R + j];
+            if constexpr (KPL == 8) {
+              bA = P::load8(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
+              b1 = P::load8(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
+            } else {
+              bA = XA[(iBbase + kk) * R + j];
+              b1 = X1[(i2 + n2 * (iBbase + kk)) * R + j];
+            }
           }
-#pragma unroll
-          for (int rb = 0; rb < 2; ++rb) {
-            rA[i2l][rb][c] = P::mfma(af[rb], bA, rA[i2l][rb][c]);
-            r1[rb][c] = P::mfma(af[rb], b1, r1[rb][c]);
-          }
+          rA[i2l][c] = P::mfma(af, bA, rA[i2l][c]);
+          r1[c] = P::mfma(af, b1, r1[c]);
         }
       }
 
-      // (b) Z_A += Y_A^T slab and (d1) Z1 = Y_1^T slab: B = slab (K = i1, columns)
-      const bool do_zA = (NCB == 4) || wave < 2;
-      const bool do_z1 = (NCB == 4) || wave >= 2;
-      const int cblk = (NCB == 4) ? wave : (wave & 1);
-      CFrag z1[KB];
-#pragma unroll
-      for (int rb = 0; rb < KB; ++rb) z1[rb] = zero;
-#pragma unroll 2
-      for (int ks = 0; ks < N1 / KSTEP; ++ks) {
-        const int kk = ks * KSTEP + KPL * lg;
+      // (b) Z_A += Y_A^T slab or (d1) Z1 = Y_1^T slab: B = slab (K = i1, columns)
+      if (bd_active && bd_zA) {
         const int iBl = 16 * cblk + l16;
-        const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll 4
+        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
+          const int kk = ks * KSTEP + KPL * lg;
+          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
 #pragma unroll
-        for (int rb = 0; rb < KB; ++rb) {
-          const int jr = 16 * rb + l16;
-          if (do_zA) {
-            Frag aY;
-            if constexpr (KPL == 8) aY = P::load8(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
-            else aY = YA[(i2 * N1 + kk) * KP + jr];
-            zA[rb] = P::mfma(aY, bM, zA[rb]);
-          }
-          if (do_z1) {
-            Frag a1;
-            if constexpr (KPL == 8) a1 = P::load8(Y1 + static_cast<int64_t>(jr) * N1 + kk);
-            else a1 = Y1[kk * KP + jr];
-            z1[rb] = P::mfma(a1, bM, z1[rb]);
+          for (int rb = 0; rb < KB; ++rb) {
+            const int jr = 16 * rb + l16;
+            Frag ay;
+            if constexpr (Lay::STAGE_YA) {
+              if constexpr (KPL == 8) ay = P::load8(YAs + jr * SY + kk);
+              else ay = YAs[kk * SY + jr];
+            } else {
+              if constexpr (KPL == 8) ay = P::load8(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
+              else ay = YA[(i2 * N1 + kk) * KP + jr];
+            }
+            zA[rb] = P::mfma(ay, bM, zA[rb]);
           }
         }
-      }
-      if (do_z1) {
+      } else if (bd_active) {
         const int iBl = 16 * cblk + l16;
+        CFrag acc[KB];
+#pragma unroll
+        for (int rb = 0; rb < KB; ++rb) acc[rb] = zero;
+#pragma unroll 4
+        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
+          const int kk = ks * KSTEP + KPL * lg;
+          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll
+          for (int rb = 0; rb < KB; ++rb) {
+            const int jr = 16 * rb + l16;
+            Frag ay;
+            if constexpr (Lay::STAGE_Y1) {
+              if constexpr (KPL == 8) ay = P::load8(Y1s + jr * SY + kk);
+              else ay = Y1s[kk * SY + jr];
+            } else {
+              if constexpr (KPL == 8) ay = P::load8(Y1 + static_cast<int64_t>(jr) * N1 + kk);
+              else ay = Y1[kk * KP + jr];
+            }
+            acc[rb] = P::mfma(ay, bM, acc[rb]);
+          }
+        }
 #pragma unroll
         for (int rb = 0; rb < KB; ++rb)
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int j1 = 16 * rb + P::crow(lane, v);
-            Z1s[i2l * KT + iBl * KP + j1] = P::from_acc(z1[rb][v]);
+            Z1s[i2l * KT + iBl * KP + j1] = P::from_acc(acc[rb][v]);
           }
       }
     }  // i2l
@@ -242,20 +353,16 @@ __global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
     }
 
     // Z_A partial of this tile's row range for the sub-block's columns
-    {
+    if (bd_active && bd_zA) {
       Acc* PZA = static_cast<Acc*>(a.PZA);
-      const bool do_zA = (NCB == 4) || wave < 2;
-      if (do_zA) {
-        const int cblk = (NCB == 4) ? wave : (wave & 1);
-        const int64_t iB = iBbase + 16 * cblk + l16;
+      const int64_t iB = iBbase + 16 * cblk + l16;
 #pragma unroll
-        for (int rb = 0; rb < KB; ++rb)
+      for (int rb = 0; rb < KB; ++rb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int jA = 16 * rb + P::crow(lane, v);
-            PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
-          }
-      }
+        for (int v = 0; v < 4; ++v) {
+          const int jA = 16 * rb + P::crow(lane, v);
+          PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
+        }
     }
   }  // cb
 
@@ -264,23 +371,21 @@ __global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
     Acc* PRA = static_cast<Acc*>(a.PRA);
     Acc* PR1 = static_cast<Acc*>(a.PR1);
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int c = 0; c < CBR; ++c)
 #pragma unroll
-      for (int c = 0; c < CBR; ++c)
+      for (int v = 0; v < 4; ++v) {
+        const int i1 = 16 * wave + P::crow(lane, v);
+        const int j = 16 * c + l16;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int i1 = 32 * wave + 16 * rb + P::crow(lane, v);
-          const int j = 16 * c + l16;
-#pragma unroll
-          for (int i2l = 0; i2l < B2; ++i2l) {
-            const int64_t iA = (i2_0 + i2l) * N1 + i1;
-            PRA[(static_cast<int64_t>(tB) * nA + iA) * R + j] = rA[i2l][rb][c][v];
-          }
-          PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[rb][c][v];
+        for (int i2l = 0; i2l < B2; ++i2l) {
+          const int64_t iA = (i2_0 + i2l) * N1 + i1;
+          PRA[(static_cast<int64_t>(tB) * nA + iA) * R + j] = rA[i2l][c][v];
         }
+        PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[c][v];
+      }
   }
   __syncthreads();
-  Acc* red = reinterpret_cast<Acc*>(Ms);            // 4 waves x 16 rows x R
+  Acc* red = reinterpret_cast<Acc*>(smem);          // 8 waves x 16 rows x R
 #pragma unroll
   for (int c = 0; c < CBR; ++c)
 #pragma unroll
@@ -288,10 +393,11 @@ __global__ __launch_bounds__(256) void sttnn_t4_kernel(SttnnArgs a) {
   __syncthreads();
   {
     Acc* PR2 = static_cast<Acc*>(a.PR2);
-    for (int e = tid; e < B2 * R; e += 256) {
+    for (int e = tid; e < B2 * R; e += kThreadsF) {
       const int row = e / R, j = e % R;
-      const Acc s = red[(0 * 16 + row) * R + j] + red[(1 * 16 + row) * R + j] + red[(2 * 16 + row) * R + j] +
-                    red[(3 * 16 + row) * R + j];
+      Acc s = 0;
+#pragma unroll
+      for (int w = 0; w < 8; ++w) s += red[(w * 16 + row) * R + j];
       PR2[(static_cast<int64_t>(tB) * n2 + i2_0 + row) * R + j] = s;
     }
   }
@@ -313,7 +419,7 @@ __global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, 
       RA[iA + nA * j] += alpha * s;
     } else if (e < nRA + nZA) {
       const int64_t f = e - nRA;
-      const int64_t iB = f / k, jA = f % k;
+      const int64_t jA = f / nB, iB = f % nB;
       double s = 0.0;
       for (int t = 0; t < TA; ++t) s += static_cast<double>(PZA[(t * static_cast<int64_t>(KP) + jA) * nB + iB]);
       ZA[jA + k * iB] = s;
@@ -373,16 +479,26 @@ struct Shape {
   int B2, SC;
 };
 
+template <int DT, int R>
+constexpr int b2_of() {
+  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : (R >= 64 ? 2 : 4);
+}
+template <int DT>
+constexpr int sc_of() {
+  return DT == TTNN_F64 ? 32 : 64;
+}
+
 Shape shape_for(int dt, int R) {
-  if (dt == TTNN_F64) return {R >= 64 ? 2 : 4, 32};
-  return {R >= 64 ? 4 : 8, 64};
+  if (dt == TTNN_BF16) return {R >= 64 ? 4 : 8, 64};
+  if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 64};
+  return {R >= 64 ? 2 : 4, 32};
 }
 
 template <int DT, int R, int KP>
 void launch_sttnn(const SttnnArgs& a, hipStream_t st) {
-  constexpr int B2 = (DT == TTNN_F64) ? (R >= 64 ? 2 : 4) : (R >= 64 ? 4 : 8);
-  constexpr int SC = (DT == TTNN_F64) ? 32 : 64;
-  hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC>), dim3(a.TA * a.TB), dim3(256), 0, st, a);
+  constexpr int B2 = b2_of<DT, R>();
+  constexpr int SC = sc_of<DT>();
+  hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
 }
 
 template <int DT>

@@ -193,6 +193,11 @@ __global__ void f64_to_f32_kernel(float* y, const double* x, int64_t n) {
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     y[i] = static_cast<float>(x[i]);
 }
+__global__ void zero_int_kernel(int* p, int64_t n) {
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+    p[i] = 0;
+}
 __global__ void finite_kernel(const double* p, int64_t n, int* flag) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -252,6 +257,9 @@ void launch_copy_f64(double* y, const double* x, int64_t n, hipStream_t st) {
 }
 void launch_f64_to_f32(float* y, const double* x, int64_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(f64_to_f32_kernel, dim3(grid_for(n)), dim3(256), 0, st, y, x, n);
+}
+void launch_zero_int(int* p, int64_t n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(zero_int_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
 }
 void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, flag);

@@ -1,0 +1,182 @@
+// Batched strided FP64 GEMM on MFMA (v_mfma_f64_16x16x4f64) for the dense FP64
+// work of the engine: the epilogue (Omega_t = Y_t^T R_t, Psi_t), the cores of the
+// recovery phase, the reconstruction, and contractions of FP64 intermediates.
+//
+// A job computes, for every output batch cb < nbC,
+//   C[cb](m, n) = (accumulate ? C[cb](m, n) : 0)
+//                 + alpha * sum_{kb < nbK} sum_{k < K} A(m, k; cb, kb) B(k, n; cb, kb)
+// with A(m, k; cb, kb) = A[m sAm + k sAk + cb sAc + kb sAkb] (B, C likewise).
+// Long contractions are split over several workgroups; the last workgroup of a
+// tile to finish adds the partial tiles in split order, so results do not depend
+// on scheduling.  Several jobs share one launch.
+#include "kernels.hpp"
+#include "mfma.hpp"
+
+namespace ttnn {
+namespace {
+
+constexpr int TM = 32, TN = 32, TK = 32;
+constexpr int LPT = TM * TK / 256;          // elements of each operand tile per thread (4)
+
+__global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
+  __shared__ double As[TK][TM + 1];
+  __shared__ double Bs[TK][TN + 1];
+  __shared__ int last_flag;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int64_t b = blockIdx.x;
+  int ji = 0;
+  while (ji + 1 < L.n && L.jobs[ji + 1].first_block <= b) ++ji;
+  const GJob& J = L.jobs[ji];
+  int64_t rel = b - J.first_block;
+  const int split = static_cast<int>(rel % J.splits);
+  rel /= J.splits;
+  const int64_t tn = rel % J.tiles_n;
+  rel /= J.tiles_n;
+  const int64_t tm = rel % J.tiles_m;
+  const int64_t cb = rel / J.tiles_m;
+  const int64_t m0 = tm * TM, n0 = tn * TN;
+
+  // contraction range of this split over the flattened (kb, k) space
+  const int64_t KK = static_cast<int64_t>(J.nbK) * J.K;
+  const int64_t k_begin = (KK * split) / J.splits;
+  const int64_t k_end = (KK * (split + 1)) / J.splits;
+
+  const int wm = wave >> 1, wn = wave & 1;    // 16 x 16 block of the wave
+  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const double* Ab = J.A + cb * J.sAc;
+  const double* Bb = J.B + cb * J.sBc;
+  // thread -> (row, k) map of the tile loads: contiguous index fastest
+  const bool a_k_fast = J.sAk == 1 && J.sAm != 1;
+  const bool b_k_fast = J.sBk == 1 && J.sBn != 1;
+
+  double ra[LPT], rb[LPT];
+  int64_t kk = k_begin;
+  int64_t kcur = 0;   // length of the staged step
+  auto fetch = [&](int64_t kpos, int64_t& klen) {
+    const int64_t kb = kpos / J.K;
+    const int64_t k0 = kpos - kb * J.K;
+    int64_t kstop = J.K - k0;                  // stay inside one kb
+    if (kstop > k_end - kpos) kstop = k_end - kpos;
+    if (kstop > TK) kstop = TK;
+    klen = kstop;
+    const double* Ak = Ab + kb * J.sAkb;
+    const double* Bk = Bb + kb * J.sBkb;
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int e = tid + 256 * u;
+      const int mm = a_k_fast ? e / TK : e % TM, kx = a_k_fast ? e % TK : e / TM;
+      ra[u] = (kx < kstop && m0 + mm < J.M) ? Ak[(m0 + mm) * J.sAm + (k0 + kx) * J.sAk] : 0.0;
+      const int nn = b_k_fast ? e / TK : e % TN, ky = b_k_fast ? e % TK : e / TN;
+      rb[u] = (ky < kstop && n0 + nn < J.N) ? Bk[(k0 + ky) * J.sBk + (n0 + nn) * J.sBn] : 0.0;
+    }
+  };
+  if (kk < k_end) fetch(kk, kcur);
+  while (kk < k_end) {
+#pragma unroll
+    for (int u = 0; u < LPT; ++u) {
+      const int e = tid + 256 * u;
+      const int mm = a_k_fast ? e / TK : e % TM, kx = a_k_fast ? e % TK : e / TM;
+      As[kx][mm] = ra[u];
+      const int nn = b_k_fast ? e / TK : e % TN, ky = b_k_fast ? e % TK : e / TN;
+      Bs[ky][nn] = rb[u];
+    }
+    __syncthreads();
+    const int64_t knext = kk + kcur;
+    int64_t klen_next = 0;
+    if (knext < k_end) fetch(knext, klen_next);   // next step's loads overlap the MFMAs
+#pragma unroll
+    for (int s = 0; s < TK / 4; ++s) {
+      const double a = As[4 * s + lg][16 * wm + l16];
+      const double bv = Bs[4 * s + lg][16 * wn + l16];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+    kk = knext;
+    kcur = klen_next;
+  }
+
+  // C fragment: lane holds C[16 wm + 4 v + lg][16 wn + l16]
+  if (J.splits == 1) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t m = m0 + 16 * wm + 4 * v + lg, n = n0 + 16 * wn + l16;
+      if (m < J.M && n < J.N) {
+        double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
+        *c = (J.accumulate ? *c : 0.0) + J.alpha * acc[v];
+      }
+    }
+    return;
+  }
+  // split contraction: publish the partial tile, the last split combines
+  const int64_t tile_id = (cb * J.tiles_m + tm) * J.tiles_n + tn;
+  double* part = J.part + (tile_id * J.splits + split) * (TM * TN);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) part[(16 * wm + 4 * v + lg) * TN + 16 * wn + l16] = acc[v];
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) {
+    const int prev = atomicAdd(J.counter + tile_id, 1);
+    last_flag = (prev == J.splits - 1);
+  }
+  __syncthreads();
+  if (!last_flag) return;
+  __threadfence();
+  const double* parts = J.part + tile_id * J.splits * (TM * TN);
+  for (int e = tid; e < TM * TN; e += 256) {
+    const int mm = e / TN, nn = e % TN;
+    const int64_t m = m0 + mm, n = n0 + nn;
+    // eight independent partial sums keep eight loads in flight; fixed combination order
+    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int sp = 0;
+    for (; sp + 8 <= J.splits; sp += 8)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s8[q] += parts[(sp + q) * (TM * TN) + e];
+    for (int q = 0; sp < J.splits; ++sp, ++q) s8[q] += parts[sp * (TM * TN) + e];
+    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    if (m >= J.M || n >= J.N) continue;
+    double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
+    *c = (J.accumulate ? *c : 0.0) + J.alpha * s;
+  }
+  if (tid == 0) J.counter[tile_id] = 0;       // ready for the next launch
+}
+
+}  // namespace
+
+void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, int* counters, size_t ncounters,
+                    hipStream_t st) {
+  for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxGJobs) {
+    GJobList L{};
+    L.n = static_cast<int>(std::min<size_t>(kMaxGJobs, jobs.size() - j0));
+    int64_t blocks = 0;
+    size_t part_used = 0, ctr_used = 0;
+    for (int i = 0; i < L.n; ++i) {
+      GJob j = jobs[j0 + i];
+      j.tiles_m = (j.M + TM - 1) / TM;
+      j.tiles_n = (j.N + TN - 1) / TN;
+      const int64_t tiles = j.tiles_m * j.tiles_n * j.nbC;
+      // split long contractions so that the launch has enough workgroups
+      const int64_t KK = static_cast<int64_t>(j.nbK) * j.K;
+      int64_t sp = 1;
+      if (tiles < 512 && KK > 256) {
+        sp = std::min<int64_t>((KK + 255) / 256, std::max<int64_t>(1, 1024 / tiles));
+        sp = std::min<int64_t>(sp, 256);
+      }
+      const size_t need = static_cast<size_t>(tiles * sp * TM * TN);
+      if (sp > 1 && (part_used + need > part_elems || ctr_used + static_cast<size_t>(tiles) > ncounters)) sp = 1;
+      j.splits = static_cast<int>(sp);
+      if (sp > 1) {
+        j.part = part + part_used;
+        j.counter = counters + ctr_used;
+        part_used += need;
+        ctr_used += static_cast<size_t>(tiles);
+      }
+      j.first_block = blocks;
+      blocks += tiles * sp;
+      L.jobs[i] = j;
+    }
+    if (blocks > 0)
+      hipLaunchKernelGGL(bgemm64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, L);
+  }
+}
+
+}  // namespace ttnn

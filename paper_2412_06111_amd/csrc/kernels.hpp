@@ -1,6 +1,8 @@
 // Host-callable launchers of the engine's HIP kernels.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace ttnn {
@@ -50,12 +52,43 @@ void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int
                    const IndexMap& rmap, int64_t ldr, double* dst, int64_t L, int64_t kdim,
                    hipStream_t stream);
 
+// ---------------------------------------------------------------- batched FP64 GEMM
+// C[cb](m,n) = (accumulate ? C : 0) + alpha * sum_{kb<nbK} sum_{k<K} A(m,k;cb,kb) B(k,n;cb,kb)
+// with A(m,k;cb,kb) = A[m sAm + k sAk + cb sAc + kb sAkb] and likewise for B and C.
+struct GJob {
+  int64_t M = 0, N = 0, K = 0;
+  int nbK = 1, nbC = 1;
+  const double* A = nullptr;
+  int64_t sAm = 0, sAk = 0, sAkb = 0, sAc = 0;
+  const double* B = nullptr;
+  int64_t sBk = 0, sBn = 0, sBkb = 0, sBc = 0;
+  double* C = nullptr;
+  int64_t sCm = 0, sCn = 0, sCc = 0;
+  double alpha = 1.0;
+  int accumulate = 0;
+  // filled by the launcher
+  int splits = 1;
+  int64_t tiles_m = 0, tiles_n = 0, first_block = 0;
+  double* part = nullptr;
+  int* counter = nullptr;
+};
+constexpr int kMaxGJobs = 12;
+struct GJobList {
+  GJob jobs[kMaxGJobs];
+  int n;
+};
+// Launches every job (in chunks of kMaxGJobs per kernel); `part` and `counters`
+// are split-contraction scratch (counters zero on entry, left zero on exit).
+void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, int* counters, size_t ncounters,
+                    hipStream_t stream);
+
 // ---------------------------------------------------------------- small utilities
 void launch_zero(double* p, int64_t n, hipStream_t stream);
 void launch_axpy(double* y, const double* x, double alpha, int64_t n, hipStream_t stream);
 void launch_copy_f64(double* dst, const double* src, int64_t n, hipStream_t stream);
 void launch_f64_to_f32(float* dst, const double* src, int64_t n, hipStream_t stream);
 void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t stream);
+void launch_zero_int(int* p, int64_t n, hipStream_t stream);
 
 // ---------------------------------------------------------------- recovery phase
 // One workgroup per job: Householder QR of Omega (k x r, column-major), sign fix
@@ -66,8 +99,11 @@ struct QrJob {
   double* Pinv;       // r x r out
   int k, r;
 };
-void launch_qr_pinv(const QrJob* d_jobs, int njobs, int max_k, int max_r, double eps_factor,
-                    int* d_kept, hipStream_t stream);
+struct QrJobList {
+  QrJob jobs[TTNN_MAX_NODES];
+  int n;
+};
+void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t stream);
 
 // ---------------------------------------------------------------- norms
 // Deterministic two-pass sums of (a - b)^2 and b^2; result in d_out[0..1].

@@ -202,7 +202,11 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
   for (int c : P->nodes[0].children) P->psi_root_len *= P->nodes[c].k;
   P->psi_root = static_cast<double*>(P->alloc(sizeof(double) * P->psi_root_len));
   P->d_flag = static_cast<int*>(P->alloc(sizeof(int) * 2 * TTNN_MAX_NODES));
-  P->d_jobs = static_cast<QrJob*>(P->alloc(sizeof(QrJob) * TTNN_MAX_NODES));
+  P->g64_part_elems = size_t(1) << 21;
+  P->g64_part = static_cast<double*>(P->alloc(sizeof(double) * P->g64_part_elems));
+  P->g64_counters_n = size_t(1) << 14;
+  P->g64_counters = static_cast<int*>(P->alloc(sizeof(int) * P->g64_counters_n));
+  launch_zero_int(P->g64_counters, static_cast<int64_t>(P->g64_counters_n), stream);
 
   size_chain_scratch(*P);
   P->chain = static_cast<double*>(P->alloc(sizeof(double) * P->chain_elems));

@@ -69,8 +69,10 @@ struct Plan {
   double* work = nullptr;                  // assembly / reconstruction scratch
   size_t work_elems = 0;
   int* d_flag = nullptr;                   // numeric-status flag written by kernels
-  struct QrJob* d_jobs = nullptr;          // recovery job table (device)
-  std::vector<struct QrJob> host_jobs;
+  double* g64_part = nullptr;              // split-contraction scratch of the batched FP64 GEMM
+  size_t g64_part_elems = 0;
+  int* g64_counters = nullptr;
+  size_t g64_counters_n = 0;
 
   std::vector<void*> allocs;
   size_t footprint = 0;

@@ -7,6 +7,8 @@
 //      rotated in round-robin order until every pair is orthogonal to working
 //      precision; sigma_p = ||a_p||, u_p = a_p / sigma_p, V accumulates rotations.
 //   3. R^{+eps} = sum_{sigma_p > eps} v_p u_p^T / sigma_p with eps = eps_factor * max sigma.
+//   When ||R||_F ||R^{-1}||_F < 1/(2 eps_factor) no singular value can fall below
+//   eps, so R^{+eps} = R^{-1} is formed by back substitution and the SVD is skipped.
 // Also: deterministic squared-norm reductions used for error reporting.
 #include "kernels.hpp"
 
@@ -27,17 +29,44 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-__global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, double eps_factor, int* kept) {
+// 8 lanes per matrix column: returns the sum over the group of 8 consecutive lanes
+__device__ inline double group8_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v;
+}
+
+// Apply H_j = I - tau v v^T (v_j = 1, v_i = A[i + k j] for i > j) to columns
+// [c0, c1) of the k-row column-major matrix X (leading dimension k).
+__device__ inline void apply_reflector(const double* A, int k, int j, double tau, double* X, int c0, int c1) {
+  const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
+  for (int cbase = c0; cbase < c1; cbase += kThreads / 8) {
+    const int c = cbase + g;
+    const bool on = c < c1;
+    double w = 0.0;
+    if (on)
+      for (int i = j + sub; i < k; i += 8) w += (i == j ? 1.0 : A[i + k * j]) * X[i + k * c];
+    w = group8_sum(w) * tau;
+    if (on)
+      for (int i = j + sub; i < k; i += 8) X[i + k * c] -= w * (i == j ? 1.0 : A[i + k * j]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double eps_factor, int* kept) {
   extern __shared__ double lds[];
   __shared__ double red[4];
   __shared__ double tau_s[128];
+  __shared__ double sig[128];
   __shared__ int any_rot;
-  const QrJob job = jobs[blockIdx.x];
+  __shared__ int fast;
+  const QrJob job = jl.jobs[blockIdx.x];
   const int k = job.k, r = job.r;
   const int tid = threadIdx.x;
-  double* A = lds;               // k x r column-major (Omega, then reflectors + R)
-  double* W = A + k * r;         // r x r : columns a_p of the Jacobi iteration
-  double* V = W + r * r;         // r x r : right singular vectors
+  double* A = lds;               // k x r: Omega, then reflectors below the diagonal and R above
+  double* Qm = A + k * r;        // k x r: Q
+  double* W = Qm;                // r x r (after Q is stored): R, then the Jacobi columns
+  double* V = A;                 // r x r (after R is extracted): R^{-1}, or right singular vectors
 
   for (int e = tid; e < k * r; e += kThreads) A[e] = job.Om[e];
   __syncthreads();
@@ -62,40 +91,23 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, do
       tau_s[j] = tau;
     }
     __syncthreads();
-    if (tau != 0.0) {
-      // A[j:k, c] -= tau v (v^T A[j:k, c]) for c > j, one column per thread
-      for (int c = j + 1 + tid; c < r; c += kThreads) {
-        double w = A[j + k * c];
-        for (int i = j + 1; i < k; ++i) w += A[i + k * j] * A[i + k * c];
-        w *= tau;
-        A[j + k * c] -= w;
-        for (int i = j + 1; i < k; ++i) A[i + k * c] -= w * A[i + k * j];
-      }
-    }
+    if (tau != 0.0) apply_reflector(A, k, j, tau, A, j + 1, r);
     __syncthreads();
   }
 
-  // ---- Q = H_0 ... H_{r-1} [I; 0], built in global memory, one column per thread
-  for (int c = tid; c < r; c += kThreads) {
-    double* q = job.Q + static_cast<int64_t>(k) * c;
-    for (int i = 0; i < k; ++i) q[i] = (i == c) ? 1.0 : 0.0;
-    for (int j = r - 1; j >= 0; --j) {
-      const double tau = tau_s[j];
-      if (tau == 0.0) continue;
-      double w = q[j];
-      for (int i = j + 1; i < k; ++i) w += A[i + k * j] * q[i];
-      w *= tau;
-      q[j] -= w;
-      for (int i = j + 1; i < k; ++i) q[i] -= w * A[i + k * j];
-    }
-  }
+  // ---- Q = H_0 ... H_{r-1} [I; 0]
+  for (int e = tid; e < k * r; e += kThreads) Qm[e] = ((e % k) == (e / k)) ? 1.0 : 0.0;
   __syncthreads();
-  // sign fix: diag(R) >= 0 (flip row j of R and column j of Q)
-  for (int c = tid; c < r; c += kThreads) {
-    if (A[c + k * c] < 0.0) {
-      double* q = job.Q + static_cast<int64_t>(k) * c;
-      for (int i = 0; i < k; ++i) q[i] = -q[i];
-    }
+  for (int j = r - 1; j >= 0; --j) {
+    const double tau = tau_s[j];
+    if (tau != 0.0) apply_reflector(A, k, j, tau, Qm, j, r);
+    __syncthreads();
+  }
+  // sign fix diag(R) >= 0: flip row j of R and column j of Q
+  for (int e = tid; e < k * r; e += kThreads) {
+    const int c = e / k;
+    const double v = Qm[e];
+    job.Q[e] = (A[c + k * c] < 0.0) ? -v : v;
   }
   __syncthreads();
   for (int e = tid; e < r * r; e += kThreads) {
@@ -103,8 +115,38 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, do
     double v = (i <= c) ? A[i + k * c] : 0.0;
     if (A[i + k * i] < 0.0) v = -v;
     W[e] = v;
-    V[e] = (i == c) ? 1.0 : 0.0;
   }
+  __syncthreads();
+
+  // ---- fast path: if ||R||_F ||R^{-1}||_F < 1 / (2 eps_factor) then sigma_min / sigma_max
+  // exceeds eps_factor, nothing is truncated and R^{+eps} = R^{-1} (back substitution)
+  {
+    double part = 0.0;
+    for (int e = tid; e < r * r; e += kThreads) part += W[e] * W[e];
+    const double rnorm2 = block_sum(part, red);
+    bool nonsingular = true;
+    for (int i = 0; i < r; ++i) nonsingular = nonsingular && (W[i + r * i] > 0.0);
+    double inv2 = 0.0;
+    if (nonsingular) {
+      for (int c = tid; c < r; c += kThreads) {     // column c of R^{-1}: R x = e_c
+        for (int i = r - 1; i >= 0; --i) {
+          double s = (i == c) ? 1.0 : 0.0;
+          for (int m = i + 1; m <= c; ++m) s -= W[i + r * m] * V[m + r * c];
+          V[i + r * c] = (i > c) ? 0.0 : s / W[i + r * i];
+        }
+        for (int i = 0; i < r; ++i) inv2 += V[i + r * c] * V[i + r * c];
+      }
+    }
+    inv2 = block_sum(inv2, red);
+    if (tid == 0) fast = nonsingular && (sqrt(rnorm2 * inv2) * eps_factor < 0.5);
+    __syncthreads();
+    if (fast) {
+      for (int e = tid; e < r * r; e += kThreads) job.Pinv[e] = V[e];
+      if (tid == 0) kept[blockIdx.x] = r;
+      return;
+    }
+  }
+  for (int e = tid; e < r * r; e += kThreads) V[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
   __syncthreads();
 
   // ---- one-sided Jacobi on the columns of W (r x r)
@@ -129,11 +171,9 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, do
             ga += x * y;
           }
         }
-        for (int o = 4; o > 0; o >>= 1) {
-          al += __shfl_xor(al, o);
-          be += __shfl_xor(be, o);
-          ga += __shfl_xor(ga, o);
-        }
+        al = group8_sum(al);
+        be = group8_sum(be);
+        ga = group8_sum(ga);
         if (q < r && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -158,7 +198,6 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(const QrJob* jobs, do
   }
 
   // ---- singular values and truncated pseudo-inverse
-  double* sig = tau_s;                         // reuse (r <= 128)
   for (int c = tid; c < r; c += kThreads) {
     double s = 0.0;
     for (int i = 0; i < r; ++i) s += W[i + r * c] * W[i + r * c];
@@ -217,10 +256,9 @@ __global__ void diff_norm_final(const double* part, int nb, double* out) {
 
 }  // namespace
 
-void launch_qr_pinv(const QrJob* d_jobs, int njobs, int max_k, int max_r, double eps_factor, int* d_kept,
-                    hipStream_t st) {
-  if (njobs <= 0) return;
-  const size_t lds = static_cast<size_t>(max_k * max_r + 2 * max_r * max_r) * sizeof(double);
+void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t st) {
+  if (jl.n <= 0) return;
+  const size_t lds = static_cast<size_t>(2 * max_k * max_r) * sizeof(double);
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_pinv_kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -229,7 +267,7 @@ void launch_qr_pinv(const QrJob* d_jobs, int njobs, int max_k, int max_r, double
       throw Error{TTNN_E_INVALID, "recovery kernel needs " + std::to_string(lds) + " bytes of LDS"};
     }
   }
-  hipLaunchKernelGGL(qr_pinv_kernel, dim3(njobs), dim3(kThreads), lds, st, d_jobs, eps_factor, d_kept);
+  hipLaunchKernelGGL(qr_pinv_kernel, dim3(jl.n), dim3(kThreads), lds, st, jl, eps_factor, d_kept);
 }
 
 void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, double* d_part, double* d_out,
