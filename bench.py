@@ -93,6 +93,50 @@ def work_counts(tree, variant):
     return flops, drm_entries, N
 
 
+def sweep_counts(tree, variant, dtype):
+    """Algorithmic flops and bytes of the sweep kernel alone.
+
+    STTNN on ((1,2),(3,4)) runs a one-pass kernel that reads the tensor once and the
+    DRMs X_A, X_1, X_2, Y_A, Y_1 once, and writes R_A, Z_A = Y_A^T T^{A}, R_1, R_2 once
+    (FP32, FP64 for an FP64 plan); the remaining nodes are formed from Z_A afterwards.
+    Otherwise the sweep is the whole update and its counts are those of the pass."""
+    flops, drm, N = work_counts(tree, variant)
+    s = ESIZE[dtype]
+    if variant != "sttnn":
+        return flops, N * s + drm * s
+    A, B = tree[0].children
+    l1, l2 = tree[A].children
+    r, k = tree[A].rank, tree[A].k
+    nA, nB, n1 = tree.n_of(A), tree.n_of(B), tree.n_of(l1)
+    drm_k = (tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + tree.x_rows(l2, variant) * r
+             + nA * k + n1 * k)
+    out = nA * r + k * nB + n1 * r + tree.n_of(l2) * r
+    acc = 8 if dtype == "f64" else 4
+    kflops = 2 * N * (2 * r + 2 * k) + 2 * (N // n1) * k * r
+    return kflops, N * s + drm_k * s + out * acc
+
+
+def copy_rate(nbytes=1 << 30, reps=10):
+    """A plain device-to-device copy of known size: the calibration kernel for the
+    HBM byte counters and a measured streaming ceiling (read + write bytes / time)."""
+    import torch
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "ms": ms, "GBps_read_plus_write": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 # ---------------------------------------------------------------- GPU run
 def run_gpu(args, T_dev64, variant, dtype):
     import torch
@@ -116,6 +160,8 @@ def run_gpu(args, T_dev64, variant, dtype):
         X = T_dev64.to(torch.float32).to(torch.bfloat16)
     cores = plan.alloc_cores()
 
+    sweep_ms = []
+
     def step(ev=None):
         plan.reset()
         if ev is not None:
@@ -123,8 +169,11 @@ def run_gpu(args, T_dev64, variant, dtype):
         plan.update(X)
         if ev is not None:
             ev[1].record(stream)
-        plan.assemble(cores)
+        plan.assemble(cores)          # reads a status flag back: the stream is drained here
+        if ev is not None:
+            sweep_ms.append(plan.sweep_time_ms())
 
+    plan.set_timing(True)             # HIP events on the launch stream around the sweep kernel
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -137,7 +186,8 @@ def run_gpu(args, T_dev64, variant, dtype):
     ms_step = (toc - tic) * 1e3 / args.steps
     sketch_ms = [a.elapsed_time(b) for a, b in evs]
     res = {"ms_per_step": ms_step, "sketch_ms_avg": sum(sketch_ms) / len(sketch_ms),
-           "sketch_ms_min": min(sketch_ms), "drm_generation_ms": drm_ms, "footprint_bytes": plan.footprint()}
+           "sketch_ms_min": min(sketch_ms), "sweep_kernel_ms_avg": sum(sweep_ms) / len(sweep_ms),
+           "sweep_kernel_ms_min": min(sweep_ms), "drm_generation_ms": drm_ms, "footprint_bytes": plan.footprint()}
     if not args.no_error:
         That = plan.reconstruct(cores)
         e2, n2 = P.diff_norms(That, T_dev64)
@@ -149,7 +199,7 @@ def run_gpu(args, T_dev64, variant, dtype):
     return res
 
 
-def cpu_baseline(T, tree, variant, seed=1, box=64):
+def cpu_baseline(T, tree, variant, seed=1, box=112):
     """The FP64 oracle on a bounded sample of the same workload: the corner box of
     size box^4 as a streaming update (DRM rows generated before timing)."""
     import numpy as np
@@ -196,21 +246,34 @@ def main():
             r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
             r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
             r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
+            kf, kb = sweep_counts(tree_def, variant, dtype)
+            r["sweep_flops"] = kf
+            r["sweep_algorithmic_bytes"] = kb
+            r["sweep_GBps"] = kb / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9
+            r["sweep_TFLOPs"] = kf / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12
             results[f"{variant}:{dtype}"] = r
             print(f"# {variant} {dtype}: {json.dumps(r)}", file=sys.stderr, flush=True)
 
     key = args.headline if args.headline in results else next(iter(results))
     hv, hd = key.split(":")
     head = results[key]
-    t_hbm = head["algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
-    t_mfma = head["flops"] / (MFMA_PEAK_TFLOPS[hd] * 1e12)
-    if t_mfma > t_hbm:
-        roof = {"bound": "mfma", "achieved": head["sketch_TFLOPs"], "peak": MFMA_PEAK_TFLOPS[hd], "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": head["sketch_GBps_algorithmic"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    for k, r in results.items():
+        d = k.split(":")[1]
+        t_hbm = r["sweep_algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
+        t_mfma = r["sweep_flops"] / (MFMA_PEAK_TFLOPS[d] * 1e12)
+        if t_mfma > t_hbm:
+            r["roofline"] = {"bound": "mfma", "achieved": r["sweep_TFLOPs"], "peak": MFMA_PEAK_TFLOPS[d],
+                             "unit": "TFLOP/s"}
+        else:
+            r["roofline"] = {"bound": "hbm", "achieved": r["sweep_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        r["roofline"]["frac"] = r["roofline"]["achieved"] / r["roofline"]["peak"]
+    roof = dict(head["roofline"])
     roof["traffic"] = None
-    roof["kernel"] = "sketch phase of one whole-tensor update (event-timed on the launch stream)"
+    roof["kernel"] = (("sttnn_t4_kernel (one-pass STTNN sweep)" if hv == "sttnn" else "whole TTNN update")
+                      + f", {hd}, {args.n}^4, r={args.rank}, p={args.over}; HIP events on the launch stream")
+    roof["algorithmic_bytes_per_launch"] = head["sweep_algorithmic_bytes"]
+    roof["flops_per_launch"] = head["sweep_flops"]
+    copy = copy_rate()
 
     cpu = None
     if not args.no_cpu:
@@ -236,6 +299,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "results": results,
+        "copy_calibration": copy,
         "input_generation_s": t_gen,
     }
     print(json.dumps(line))

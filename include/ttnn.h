@@ -192,6 +192,15 @@ ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t 
 ttnn_status ttnn_level_id(ttnn_plan_t plan, int32_t node, int32_t* level_id);
 ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32_t* ids);
 
+/* Measurement hook.  With timing on, every update records two HIP events on its
+ * stream: before its first kernel and after its sweep, the kernel that streams the
+ * tensor (the one-pass fused kernel where it applies; otherwise the whole update).
+ * ttnn_sweep_time_ms waits for the second event of the last update and returns the
+ * elapsed milliseconds (TTNN_E_STATE if no update was timed).  Off by default; it
+ * adds no synchronisation to the update itself. */
+ttnn_status ttnn_set_timing(ttnn_plan_t plan, int32_t on);
+ttnn_status ttnn_sweep_time_ms(ttnn_plan_t plan, float* ms);
+
 /* Zero the accumulators and clear a sticky error. */
 ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream);
 

@@ -70,6 +70,8 @@ def _load():
         "ttnn_level_id": [vp, i32, C.POINTER(i32)],
         "ttnn_reuse_set": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
         "ttnn_reset": [vp, vp],
+        "ttnn_set_timing": [vp, i32],
+        "ttnn_sweep_time_ms": [vp, C.POINTER(C.c_float)],
     }
     for name, args in sigs.items():
         f = getattr(lib, name)
@@ -197,6 +199,15 @@ class Plan:
 
     def reset(self, stream=None):
         check(lib.ttnn_reset(self.handle, stream_ptr(stream)))
+
+    def set_timing(self, on=True):
+        check(lib.ttnn_set_timing(self.handle, 1 if on else 0))
+
+    def sweep_time_ms(self):
+        """Elapsed time of the last update's sweep kernel (waits for it)."""
+        ms = C.c_float()
+        check(lib.ttnn_sweep_time_ms(self.handle, C.byref(ms)))
+        return ms.value
 
     # ------------------------------------------------------------ readbacks
     def sketch_shape(self, node, kind):

@@ -320,6 +320,30 @@ ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream) {
   }
 }
 
+ttnn_status ttnn_set_timing(ttnn_plan_t plan, int32_t on) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
+    if (on && !P->sweep_ev[0]) {
+      for (hipEvent_t& e : P->sweep_ev) TTNN_HIP(hipEventCreate(&e));
+    }
+    P->timing = on != 0;
+    P->sweep_recorded = false;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sweep_time_ms(ttnn_plan_t plan, float* ms) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !ms) throw Error{TTNN_E_INVALID, "plan or ms is NULL"};
+    if (!P->timing || !P->sweep_recorded) throw Error{TTNN_E_STATE, "no timed update since ttnn_set_timing"};
+    TTNN_HIP(hipEventSynchronize(P->sweep_ev[1]));
+    TTNN_HIP(hipEventElapsedTime(ms, P->sweep_ev[0], P->sweep_ev[1]));
+    return TTNN_OK;
+  });
+}
+
 const char* ttnn_status_string(ttnn_status s) {
   switch (s) {
     case TTNN_OK: return "ok";

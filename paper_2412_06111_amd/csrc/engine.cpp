@@ -244,11 +244,16 @@ void zero_accumulators(Plan& P, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- sketch phase
-void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                hipStream_t st) {
+namespace {
+void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
+                     hipStream_t st) {
   P.epilogue_valid = false;
   std::vector<int> fused_nodes;
   std::vector<std::vector<int>> fused_prefixes;
+  if (P.timing) {
+    TTNN_HIP(hipEventRecord(P.sweep_ev[0], st));
+    P.sweep_recorded = false;
+  }
   if (P.allow_fused)
     try_fused_update(P, block, off, ext, alpha, st, &fused_nodes, &fused_prefixes);
 
@@ -374,6 +379,17 @@ void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
   a.ncols = g.k;
   a.amap = box_rows(P, g.first, g.last, off, ext);
   left_op(P, a, P.psi_root, 1, alpha, st);
+}
+}  // namespace
+
+void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
+                hipStream_t st) {
+  update_box_impl(P, block, off, ext, alpha, st);
+  // without a one-pass sweep kernel the whole update counts as the sweep
+  if (P.timing && !P.sweep_recorded) {
+    TTNN_HIP(hipEventRecord(P.sweep_ev[1], st));
+    P.sweep_recorded = true;
+  }
 }
 
 // ---------------------------------------------------------------- epilogue

@@ -618,6 +618,10 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
   if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, a, st);
   else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, a, st);
   else launch_sttnn_dt<TTNN_F64>(F.R, a, st);
+  if (P.timing) {
+    TTNN_HIP(hipEventRecord(P.sweep_ev[1], st));
+    P.sweep_recorded = true;
+  }
 
   const std::vector<int> pre{F.node_A};
   double* ZA = P.chain + P.prefix_offset.at(pre);

@@ -17,6 +17,8 @@ namespace ttnn {
 
 Plan::~Plan() {
   for (void* p : allocs) (void)hipFree(p);
+  for (hipEvent_t e : sweep_ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void* Plan::alloc(size_t bytes) {

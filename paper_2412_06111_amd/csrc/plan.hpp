@@ -81,6 +81,10 @@ struct Plan {
   bool has_cores = false;
   FusedT4 fused;
   bool allow_fused = true;                 // off: every update takes the generic path
+  // measurement hook: events around the sweep of the last update (see ttnn_set_timing)
+  bool timing = false;
+  hipEvent_t sweep_ev[2] = {nullptr, nullptr};
+  bool sweep_recorded = false;
 
   ~Plan();
   void* alloc(size_t bytes);
