@@ -125,6 +125,11 @@ ttnn_status ttnn_destroy(ttnn_plan_t plan);
  * accumulators, cores and scratch).  Used for admission by footprint. */
 size_t ttnn_footprint_bytes(ttnn_plan_t plan);
 
+/* The footprint ttnn_plan_create would allocate for `problem`, computed on the host
+ * without allocating or launching anything (admission before creation).  Validates
+ * the problem like ttnn_plan_create. */
+ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes);
+
 /* Streaming update (Sec. 4, linearity): add alpha * sketch(H) to the accumulators,
  * where H is zero outside the box [offset, offset + extent) and equals the packed
  * column-major block d_block (extent[0] fastest, plan dtype) inside it.  The whole
@@ -137,10 +142,15 @@ ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int6
 ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_factors,
                                      double alpha, void* stream);
 
-/* Several box updates, possibly for different plans, in one call.  Updates of plans
- * with the same tree shape, variant and dtype are batched into shared kernel
- * launches; for a given plan the result equals applying its updates one by one
- * (bitwise, the reduction order depends only on each update's own box). */
+/* Several box updates, possibly for different plans, in one call (continuous
+ * batching of streamed updates, Sec. 4 linearity).  The call works in rounds: a
+ * round takes the earliest remaining update of every plan; the box updates of a
+ * round whose plans share tree shape, variant and dtype (sizes and boxes may differ)
+ * run each step of the generic path as one launch over all of them (descriptor
+ * tables staged through pinned memory); whole-tensor updates run alone.  For every
+ * plan the result is bitwise the result of applying its updates one by one with
+ * ttnn_sketch_update: each update's arithmetic and reduction order depend only on its
+ * own box.  All descriptors are validated before anything is enqueued. */
 typedef struct {
   ttnn_plan_t plan;
   const void* d_block;

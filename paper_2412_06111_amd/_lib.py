@@ -71,6 +71,7 @@ def _load():
         "ttnn_reuse_set": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
         "ttnn_reset": [vp, vp],
         "ttnn_set_timing": [vp, i32],
+        "ttnn_footprint_estimate": [C.POINTER(Problem), C.POINTER(C.c_size_t)],
         "ttnn_sweep_time_ms": [vp, C.POINTER(C.c_float)],
     }
     for name, args in sigs.items():
@@ -131,6 +132,32 @@ def tree_arrays(spec):
     return parent, first, last, modes
 
 
+def _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor):
+    """Marshal a problem; returns (Problem, keep-alive arrays, node modes)."""
+    dims = tuple(int(n) for n in dims)
+    d = len(dims)
+    variant = VARIANT_OF_NAME[variant] if isinstance(variant, str) else int(variant)
+    dtype = DTYPE_OF_NAME[dtype] if isinstance(dtype, str) else int(dtype)
+    par, fst, lst, modes = tree_arrays(spec)
+    nn = len(par)
+    rk = [int(rank[m] if isinstance(rank, dict) else rank) if i else 0 for i, m in enumerate(modes)]
+    ov = [int(over[m] if isinstance(over, dict) else over) if i else 0 for i, m in enumerate(modes)]
+    arrays = ((C.c_int64 * d)(*dims), (C.c_int32 * nn)(*par), (C.c_int32 * nn)(*fst),
+              (C.c_int32 * nn)(*lst), (C.c_int32 * nn)(*rk), (C.c_int32 * nn)(*ov))
+    a = arrays
+    pr = Problem(d, a[0], nn, a[1], a[2], a[3], a[4], a[5], variant, dtype, C.c_uint64(int(seed)),
+                 float(eps_factor))
+    return pr, arrays, modes
+
+
+def footprint_estimate(spec, dims, rank, over, variant="ttnn", dtype="f64"):
+    """Device bytes a plan for this problem would own (host-side sizing, no allocation)."""
+    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0)
+    out = C.c_size_t()
+    check(lib.ttnn_footprint_estimate(C.byref(pr), C.byref(out)))
+    return int(out.value)
+
+
 class Plan:
     """A sketching plan: problem of Sec. 4 / Alg. 2 plus seed and precision."""
 
@@ -140,20 +167,10 @@ class Plan:
         self.d = len(self.dims)
         self.variant = VARIANT_OF_NAME[variant] if isinstance(variant, str) else int(variant)
         self.dtype = DTYPE_OF_NAME[dtype] if isinstance(dtype, str) else int(dtype)
-        par, fst, lst, modes = tree_arrays(spec)
+        self.problem, self._arrays, modes = _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor)
         self.node_modes = modes
         self.node_of_modes = {m: i for i, m in enumerate(modes)}
-        nn = len(par)
-        rk = [int(rank[m] if isinstance(rank, dict) else rank) if i else 0 for i, m in enumerate(modes)]
-        ov = [int(over[m] if isinstance(over, dict) else over) if i else 0 for i, m in enumerate(modes)]
-        self._arrays = (
-            (C.c_int64 * self.d)(*self.dims), (C.c_int32 * nn)(*par), (C.c_int32 * nn)(*fst),
-            (C.c_int32 * nn)(*lst), (C.c_int32 * nn)(*rk), (C.c_int32 * nn)(*ov),
-        )
-        a = self._arrays
-        self.problem = Problem(self.d, a[0], nn, a[1], a[2], a[3], a[4], a[5], self.variant, self.dtype,
-                               C.c_uint64(int(seed)), float(eps_factor))
-        self.num_nodes = nn
+        self.num_nodes = len(modes)
         self.handle = C.c_void_p()
         check(lib.ttnn_plan_create(C.byref(self.problem), stream_ptr(stream), C.byref(self.handle)))
 
@@ -290,7 +307,7 @@ def diff_norms(a, b, stream=None):
 
 
 def update_batched(items, stream=None):
-    """items: list of (plan, block, extent, offset, alpha)."""
+    """items: list of (plan, block, extent, offset, alpha); see ttnn_sketch_update_batched."""
     arr = (UpdateDesc * max(1, len(items)))()
     keep = []
     for i, (plan, block, extent, offset, alpha) in enumerate(items):

@@ -1,6 +1,9 @@
 // extern "C" entry points of libttnn.so.  Each wraps its body so that no C++
 // exception crosses the ABI; statuses and messages follow include/ttnn.h.
+#include <algorithm>
 #include <cstring>
+#include <map>
+#include <vector>
 #include <string>
 
 #include "engine.hpp"
@@ -125,20 +128,68 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
       check_box(*P, descs[i].offset, descs[i].extent, &empty);
       if (!empty && !descs[i].d_block) throw Error{TTNN_E_INVALID, "descriptor block is NULL"};
     }
+    std::vector<int32_t> pending;
     for (int32_t i = 0; i < n; ++i) {
-      Plan* P = get(descs[i].plan);
       bool empty = false;
-      check_box(*P, descs[i].offset, descs[i].extent, &empty);
-      if (empty) continue;
-      try {
-        ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha,
-                         as_stream(stream));
-        TTNN_HIP(hipGetLastError());
-      } catch (const Error& e) {
-        if (e.status == TTNN_E_HIP) P->sticky = TTNN_E_HIP;
-        throw;
-      }
+      check_box(*get(descs[i].plan), descs[i].offset, descs[i].extent, &empty);
+      if (!empty) pending.push_back(i);
     }
+    const hipStream_t st = as_stream(stream);
+    try {
+      // Rounds: each round takes the earliest pending update of every plan (so a plan's
+      // updates keep their order); the box updates of a round whose plans share a tree
+      // shape, variant and dtype run as one launch per step.
+      while (!pending.empty()) {
+        std::vector<int32_t> round, rest;
+        std::vector<Plan*> seen;
+        for (int32_t i : pending) {
+          Plan* P = get(descs[i].plan);
+          if (std::find(seen.begin(), seen.end(), P) != seen.end()) {
+            rest.push_back(i);
+            continue;
+          }
+          seen.push_back(P);
+          round.push_back(i);
+        }
+        std::map<std::string, std::vector<int32_t>> buckets;
+        for (int32_t i : round) {
+          Plan* P = get(descs[i].plan);
+          if (ttnn::whole_tensor(*P, descs[i].offset, descs[i].extent))
+            ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, st);
+          else
+            buckets[ttnn::batch_key(*P)].push_back(i);
+        }
+        for (auto& kv : buckets) {
+          std::vector<std::vector<ttnn::BoxOp>> recs(kv.second.size());
+          std::vector<const std::vector<ttnn::BoxOp>*> items;
+          for (size_t b = 0; b < kv.second.size(); ++b) {
+            const int32_t i = kv.second[b];
+            Plan* P = get(descs[i].plan);
+            P->epilogue_valid = false;
+            ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, recs[b]);
+            items.push_back(&recs[b]);
+          }
+          if (items.size() == 1) ttnn::run_box_ops(recs[0], st);
+          else ttnn::run_box_ops_batched(items, st);
+        }
+        TTNN_HIP(hipGetLastError());
+        pending.swap(rest);
+      }
+    } catch (const Error& e) {
+      if (e.status == TTNN_E_HIP)
+        for (int32_t i = 0; i < n; ++i) get(descs[i].plan)->sticky = TTNN_E_HIP;
+      throw;
+    }
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!bytes) throw Error{TTNN_E_INVALID, "bytes is NULL"};
+    *bytes = 0;
+    auto P = ttnn::build_plan(problem, nullptr, /*dry=*/true);
+    *bytes = P->footprint;
     return TTNN_OK;
   });
 }

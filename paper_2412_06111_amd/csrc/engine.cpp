@@ -244,10 +244,180 @@ void zero_accumulators(Plan& P, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------- sketch phase
+bool whole_tensor(const Plan& P, const int64_t* off, const int64_t* ext) { return whole_box(P, off, ext); }
+
+std::string batch_key(const Plan& P) {
+  std::string k = std::to_string(P.variant) + "/" + std::to_string(P.dtype) + "/" + std::to_string(P.d);
+  for (const Node& nd : P.nodes)
+    k += "/" + std::to_string(nd.parent) + ":" + std::to_string(nd.first) + "-" + std::to_string(nd.last);
+  return k;
+}
+
+void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
+                std::vector<BoxOp>& ops) {
+  const int cd = P.dtype;
+  std::map<std::vector<int>, bool> done;
+  auto chain_ptr = [&](const std::vector<int>& pf) { return P.chain + P.prefix_offset.at(pf); };
+
+  // LEFT contraction into dst: mode 2 stores, mode 1 accumulates a * result
+  auto left = [&](GemmArgs g, double* dst, int mode, double a) {
+    g.right = false;
+    const int64_t rows = g.L * g.Q;
+    g.nchunks = pick_chunks(rows, g.ncols, g.n, P.partial_elems);
+    g.out_f32 = false;
+    BoxOp op;
+    if (g.nchunks == 1 && mode == 2) {
+      g.out = dst;
+      g.ol = OutLayout{g.L, 1, g.L, g.L * g.ncols, 0};
+    } else {
+      g.out = P.partial;
+      g.ol = OutLayout{INT64_MAX, g.ncols, 1, 0, rows * g.ncols};
+      op.reduce = true;
+      op.r.part = P.partial;
+      op.r.rows = rows;
+      op.r.ncols = g.ncols;
+      op.r.mode = mode;
+      op.r.alpha = a;
+      op.r.dst = dst;
+      op.r.L = g.L;
+      op.r.kdim = g.ncols;
+    }
+    op.g = g;
+    ops.push_back(op);
+  };
+  // contraction of a group g of the operand `before` (raw block if empty) with Y_g
+  auto group_args = [&](const std::vector<int>& before, const Node& g) {
+    const std::vector<Pos> ps = positions_after(P, before, off, ext);
+    const int p0 = position_of_mode(ps, g.first);
+    const int w = g.last - g.first + 1;
+    GemmArgs a;
+    a.H = before.empty() ? block : static_cast<const void*>(chain_ptr(before));
+    a.th = before.empty() ? cd : TTNN_F64;
+    a.L = prod_ext(ps, 0, p0);
+    a.n = prod_ext(ps, p0, p0 + w);
+    a.Q = prod_ext(ps, p0 + w, ps.size());
+    a.D = before.empty() ? g.Yc : static_cast<const void*>(g.Y64);
+    a.td = before.empty() ? cd : TTNN_F64;
+    a.sDr = g.k;
+    a.sDc = 1;
+    a.ncols = g.k;
+    a.amap = box_rows(P, g.first, g.last, off, ext);
+    return a;
+  };
+  auto operand = [&](const std::vector<int>& prefix) -> const void* {
+    if (prefix.empty()) return block;
+    std::vector<int> chain;
+    for (size_t j = 0; j < prefix.size(); ++j) {
+      chain.push_back(prefix[j]);
+      if (done[chain]) continue;
+      std::vector<int> before(chain.begin(), chain.end() - 1);
+      left(group_args(before, P.nodes[chain.back()]), chain_ptr(chain), 2, 1.0);
+      done[chain] = true;
+    }
+    return chain_ptr(prefix);
+  };
+
+  for (size_t v = 1; v < P.nodes.size(); ++v) {
+    Node& t = P.nodes[v];
+    const std::vector<int>& pre = t.S;          // empty for TTNN
+    const void* in = operand(pre);
+    const std::vector<Pos> ps = positions_after(P, pre, off, ext);
+    const int p0 = position_of_mode(ps, t.first);
+    const int w = t.last - t.first + 1;
+    // X_t rows: every position except those of t, first fastest
+    IndexMap amap, bmap;
+    int64_t C = 1;
+    for (int i = 0; i < static_cast<int>(ps.size()); ++i) {
+      if (i >= p0 && i < p0 + w) continue;
+      if (i < p0) amap.push(ps[i].ext, ps[i].off, C);
+      else bmap.push(ps[i].ext, ps[i].off, C);
+      C *= ps[i].glob;
+    }
+    BoxOp op;
+    GemmArgs& a = op.g;
+    a.right = true;
+    a.H = in;
+    a.th = pre.empty() ? cd : TTNN_F64;
+    a.L = prod_ext(ps, 0, p0);
+    a.n = prod_ext(ps, p0, p0 + w);
+    a.Q = prod_ext(ps, p0 + w, ps.size());
+    a.D = pre.empty() ? t.Xc : static_cast<const void*>(t.X64);
+    a.td = pre.empty() ? cd : TTNN_F64;
+    a.sDr = t.r;
+    a.sDc = 1;
+    a.ncols = t.r;
+    a.amap = amap;
+    a.bmap = bmap;
+    a.nchunks = pick_chunks(a.n, a.ncols, a.L * a.Q, P.partial_elems);
+    a.out = P.partial;
+    a.ol = OutLayout{INT64_MAX, a.ncols, 1, 0, a.n * a.ncols};
+    op.reduce = true;
+    op.r.part = P.partial;
+    op.r.rows = a.n;
+    op.r.ncols = a.ncols;
+    op.r.mode = 0;
+    op.r.alpha = alpha;
+    op.r.rmap = box_rows(P, t.first, t.last, off, ext);
+    op.r.ldr = t.n;
+    op.r.dst = t.R;
+    ops.push_back(op);
+  }
+
+  // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0
+  const auto& rc = P.nodes[0].children;
+  std::vector<int> before(rc.begin(), rc.end() - 1);
+  operand(before);
+  left(group_args(before, P.nodes[rc.back()]), P.psi_root, 1, alpha);
+}
+
+void run_box_ops(const std::vector<BoxOp>& ops, hipStream_t st) {
+  for (const BoxOp& op : ops) {
+    const int nch = launch_gemm(op.g, st);
+    if (nch == 0 || !op.reduce) continue;
+    const ReduceTask& r = op.r;
+    launch_reduce(r.part, nch, r.rows, r.ncols, r.mode, r.alpha, r.rmap, r.ldr, r.dst, r.L, r.kdim, st);
+  }
+}
+
+void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hipStream_t st) {
+  if (items.empty()) return;
+  const size_t nops = items[0]->size();
+  for (const auto* it : items)
+    TTNN_REQUIRE(it->size() == nops, TTNN_E_INVALID, "batched updates of different tree shapes");
+  std::vector<GemmArgs> gs;
+  std::vector<ReduceTask> rs;
+  for (size_t k = 0; k < nops; ++k) {
+    gs.clear();
+    rs.clear();
+    for (const auto* it : items) {
+      const BoxOp& op = (*it)[k];
+      gs.push_back(op.g);
+      if (!op.reduce) continue;
+      const int nch = gemm_chunks(op.g, nullptr);
+      if (nch == 0) continue;
+      ReduceTask r = op.r;
+      r.nchunks = nch;
+      rs.push_back(r);
+    }
+    launch_gemm_batched(gs, st);
+    launch_reduce_batched(rs, st);
+  }
+}
+
 namespace {
 void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
                      hipStream_t st) {
   P.epilogue_valid = false;
+  if (!whole_box(P, off, ext)) {
+    if (P.timing) {
+      TTNN_HIP(hipEventRecord(P.sweep_ev[0], st));
+      P.sweep_recorded = false;
+    }
+    std::vector<BoxOp> ops;
+    record_box(P, block, off, ext, alpha, ops);
+    run_box_ops(ops, st);
+    return;
+  }
   std::vector<int> fused_nodes;
   std::vector<std::vector<int>> fused_prefixes;
   if (P.timing) {
@@ -615,12 +785,58 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
   batch.flush();
 }
 
+// Rank-1 update H = a_1 o ... o a_d (Sec. 4, streaming by linearity).  With u_I the
+// Kronecker vector of the factors of a mode group (first mode fastest):
+//   R_t += alpha * u_{I_t} (X_t^T v_t)^T,   v_t = kron over the rows of X_t,
+// where the rows run over the modes outside I_t (TTNN) or over the contracted groups
+// S_t, each contributing g_s = Y_s^T u_{I_s}, then the modes after t (STTNN); and
+//   Psi_0 += alpha * kron_c g_c over the root's children.
+// The maps are the ones a box update uses: the compute-dtype copy for a contraction
+// of the raw tensor (a chain's first group, or X_t when S_t is empty), the FP64
+// master for a contraction of an FP64 intermediate; products and sums are FP64.
+// Reads every row of every X_t once.
 void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t st) {
-  (void)P;
-  (void)factors;
-  (void)alpha;
-  (void)st;
-  throw Error{TTNN_E_INVALID, "rank-1 updates are not available in this build"};
+  P.epilogue_valid = false;
+  const int cd = P.dtype;
+  auto modes = [&](int first, int last) {
+    KronVec kv;
+    for (int mu = first; mu <= last; ++mu) kv.push(factors[mu], P.dims[mu]);
+    return kv;
+  };
+  // chains start at mode 0 (every S_t and the root's children cover a prefix of the
+  // modes), so a group is contracted from the raw tensor exactly when it starts at 0
+  std::vector<int64_t> goff(P.nodes.size(), -1);
+  int64_t used = 0;
+  auto g_of = [&](int s) -> const double* {
+    if (goff[s] < 0) {
+      const Node& g = P.nodes[s];
+      goff[s] = used;
+      used += g.k;
+      const bool raw = g.first == 0;
+      launch_kron_gemv(raw ? g.Yc : static_cast<const void*>(g.Y64), raw ? cd : TTNN_F64, g.n, g.k,
+                       modes(g.first, g.last), P.partial, P.partial_elems, P.r1 + goff[s], st);
+    }
+    return P.r1 + goff[s];
+  };
+  double* w = P.r1 + P.r1_w;
+  for (size_t v = 1; v < P.nodes.size(); ++v) {
+    const Node& t = P.nodes[v];
+    KronVec kx;
+    if (P.variant == TTNN_STTNN) {
+      for (int s : t.S) kx.push(g_of(s), P.nodes[s].k);
+      for (int mu = t.last + 1; mu < P.d; ++mu) kx.push(factors[mu], P.dims[mu]);
+    } else {
+      for (int mu = 0; mu < P.d; ++mu)
+        if (mu < t.first || mu > t.last) kx.push(factors[mu], P.dims[mu]);
+    }
+    const bool raw = t.S.empty();
+    launch_kron_gemv(raw ? t.Xc : static_cast<const void*>(t.X64), raw ? cd : TTNN_F64, t.m, t.r, kx, P.partial,
+                     P.partial_elems, w, st);
+    launch_outer_acc(t.R, t.n, t.r, modes(t.first, t.last), w, alpha, st);
+  }
+  KronVec kg;
+  for (int c : P.nodes[0].children) kg.push(g_of(c), P.nodes[c].k);
+  launch_outer_acc(P.psi_root, P.psi_root_len, 1, kg, nullptr, alpha, st);
 }
 
 }  // namespace ttnn

@@ -1,9 +1,21 @@
 // Host-side drivers of the TTNN engine (enqueue kernels on a stream).
 #pragma once
 
+#include <string>
+
+#include "kernels.hpp"
 #include "plan.hpp"
 
 namespace ttnn {
+
+// One step of a box update on the generic kernels: a contraction and, when it was
+// split or accumulates, the fixed-order reduction that delivers it (nchunks is
+// filled in at execution).
+struct BoxOp {
+  GemmArgs g;
+  bool reduce = false;
+  ReduceTask r;
+};
 
 void size_chain_scratch(Plan& P);
 void zero_accumulators(Plan& P, hipStream_t stream);
@@ -12,6 +24,16 @@ void zero_accumulators(Plan& P, hipStream_t stream);
 void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
                 hipStream_t stream);
 void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t stream);
+
+// The steps of a box update that is not the whole tensor, in order.  Plans with equal
+// batch_key() give step lists of equal length whose i-th steps have the same kind, so
+// the i-th steps of several such updates can share one launch.
+void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
+                std::vector<BoxOp>& ops);
+void run_box_ops(const std::vector<BoxOp>& ops, hipStream_t stream);
+void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hipStream_t stream);
+std::string batch_key(const Plan& P);
+bool whole_tensor(const Plan& P, const int64_t* off, const int64_t* ext);
 
 // Omega_t = Y_t^T R_t and Psi_t = (Y_cm^T kron ... kron Y_c1^T) R_t, FP64, from the accumulators.
 void run_epilogue(Plan& P, hipStream_t stream);

@@ -571,7 +571,9 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.X2 = P.alloc(es * nB * KP * R);
   const Node& NA = P.nodes[A];
   const int k = nA_.k;
-  if (k8) {
+  if (P.dry) {
+    // sizing only
+  } else if (k8) {
     copy_layout(NA.X64, F.XA, dt, nB, R, 1, R, 1, 0, 0, nB, st);                     // [j][iB]
     copy_layout(L1.X64, F.X1, dt, nB, n2, R, n2 * R, R, 1, 0, nB, st);               // [j][i2][iB]
     copy_layout(NA.Y64, F.YA, dt, nAs, KP, 1, k, 1, 0, 1, k, st);                    // [jA][iA]

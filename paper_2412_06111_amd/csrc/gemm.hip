@@ -21,11 +21,13 @@ constexpr int BK = 16;   // contraction step
 
 template <typename T> __device__ inline double ld(const T* p, int64_t i) { return to_f64(p[i]); }
 
+// One output tile (rows row0.., columns j0.., contraction chunk c) of a generic contraction.
 template <bool RIGHT, typename TH, typename TD, typename TO>
-__global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
-                                               const TD* __restrict__ D, int64_t sDr, int64_t sDc,
-                                               int ncols, IndexMap amap, IndexMap bmap, int64_t kchunk,
-                                               TO* __restrict__ out, OutLayout ol) {
+__device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+                                          const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
+                                          const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
+                                          TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
+                                          int j0) {
   __shared__ double As[BK][BR + 1];
   __shared__ double Bs[BK][BJ + 1];
   __shared__ int64_t drow[BK];
@@ -33,9 +35,6 @@ __global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t
   const int tid = threadIdx.x;
   const int64_t rows_total = RIGHT ? n : L * Q;
   const int64_t K = RIGHT ? L * Q : n;
-  const int64_t row0 = static_cast<int64_t>(blockIdx.x) * BR;
-  const int64_t c = blockIdx.y;
-  const int j0 = blockIdx.z * BJ;
   const int64_t k_begin = c * kchunk;
   const int64_t k_end = (k_begin + kchunk < K) ? k_begin + kchunk : K;
   const bool kk_contig = RIGHT ? (L > 1) : (L == 1);
@@ -122,6 +121,55 @@ __global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t
   }
 }
 
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+                                               const TD* __restrict__ D, int64_t sDr, int64_t sDc,
+                                               int ncols, IndexMap amap, IndexMap bmap, int64_t kchunk,
+                                               TO* __restrict__ out, OutLayout ol) {
+  gemm_tile<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol,
+                               static_cast<int64_t>(blockIdx.x) * BR, blockIdx.y, blockIdx.z * BJ);
+}
+
+// Copy a descriptor from global memory into LDS (8-byte words) after locating, by
+// binary search on first_block, the task that owns this workgroup.
+template <typename Task>
+__device__ inline int64_t load_task(const Task* __restrict__ tasks, int ntasks, Task* t) {
+  __shared__ int idx;
+  const int64_t b = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = ntasks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (tasks[mid].first_block <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    idx = lo;
+  }
+  __syncthreads();
+  static_assert(sizeof(Task) % 8 == 0, "task size");
+  const uint64_t* src = reinterpret_cast<const uint64_t*>(tasks + idx);
+  uint64_t* dst = reinterpret_cast<uint64_t*>(t);
+  for (int w = threadIdx.x; w < static_cast<int>(sizeof(Task) / 8); w += blockDim.x) dst[w] = src[w];
+  __syncthreads();
+  return b - t->first_block;
+}
+
+// Every workgroup serves one tile of one task; tasks of one launch may belong to
+// different updates (of different plans) and have different sizes.
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__global__ __launch_bounds__(256) void hm_gemm_batched(const GemmTask* __restrict__ tasks, int ntasks) {
+  __shared__ __align__(16) char tbuf[sizeof(GemmTask)];      // raw storage: IndexMap has initialisers
+  GemmTask& t = *reinterpret_cast<GemmTask*>(tbuf);
+  int64_t rel = load_task(tasks, ntasks, &t);
+  const int64_t rb = rel % t.row_blocks;
+  rel /= t.row_blocks;
+  const int64_t c = rel % t.nch;
+  const int cb = static_cast<int>(rel / t.nch);
+  gemm_tile<RIGHT, TH, TD, TO>(static_cast<const TH*>(t.H), t.L, t.n, t.Q, static_cast<const TD*>(t.D), t.sDr,
+                               t.sDc, t.ncols, t.amap, t.bmap, t.kchunk, static_cast<TO*>(t.out), t.ol, rb * BR,
+                               c, cb * BJ);
+}
+
 template <bool RIGHT, typename TH, typename TD>
 void gemm_dispatch_out(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t st) {
   if (a.out_f32)
@@ -152,13 +200,38 @@ void gemm_dispatch_h(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t s
   }
 }
 
-__global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
-                              double alpha, IndexMap rmap, int64_t ldr, double* __restrict__ dst, int64_t L,
-                              int64_t kdim) {
+template <bool RIGHT, typename TH, typename TD>
+void batched_dispatch_d(bool out_f32, const GemmTask* tasks, int nt, int64_t blocks, hipStream_t st) {
+  if (out_f32)
+    hipLaunchKernelGGL((hm_gemm_batched<RIGHT, TH, TD, float>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       st, tasks, nt);
+  else
+    hipLaunchKernelGGL((hm_gemm_batched<RIGHT, TH, TD, double>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                       st, tasks, nt);
+}
+template <bool RIGHT, typename TH>
+void batched_dispatch_h(int td, bool out_f32, const GemmTask* tasks, int nt, int64_t blocks, hipStream_t st) {
+  switch (td) {
+    case TTNN_F64: batched_dispatch_d<RIGHT, TH, double>(out_f32, tasks, nt, blocks, st); break;
+    case TTNN_F32: batched_dispatch_d<RIGHT, TH, float>(out_f32, tasks, nt, blocks, st); break;
+    default: batched_dispatch_d<RIGHT, TH, uint16_t>(out_f32, tasks, nt, blocks, st); break;
+  }
+}
+template <bool RIGHT>
+void batched_dispatch(int th, int td, bool out_f32, const GemmTask* tasks, int nt, int64_t blocks, hipStream_t st) {
+  switch (th) {
+    case TTNN_F64: batched_dispatch_h<RIGHT, double>(td, out_f32, tasks, nt, blocks, st); break;
+    case TTNN_F32: batched_dispatch_h<RIGHT, float>(td, out_f32, tasks, nt, blocks, st); break;
+    default: batched_dispatch_h<RIGHT, uint16_t>(td, out_f32, tasks, nt, blocks, st); break;
+  }
+}
+
+__device__ inline void reduce_range(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
+                                    double alpha, const IndexMap& rmap, int64_t ldr, double* __restrict__ dst,
+                                    int64_t L, int64_t kdim, int64_t start, int64_t step) {
   const int64_t total = rows * ncols;
   const int64_t stride = rows * ncols;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+  for (int64_t e = start; e < total; e += step) {
     const int64_t row = e / ncols;
     const int j = static_cast<int>(e - row * ncols);
     double s = 0.0;
@@ -171,6 +244,22 @@ __global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int6
       else dst[o] = s;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void reduce_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+  __shared__ __align__(16) char tbuf[sizeof(ReduceTask)];
+  ReduceTask& t = *reinterpret_cast<ReduceTask*>(tbuf);
+  const int64_t rel = load_task(tasks, ntasks, &t);
+  reduce_range(t.part, t.nchunks, t.rows, t.ncols, t.mode, t.alpha, t.rmap, t.ldr, t.dst, t.L, t.kdim,
+               rel * 256 + threadIdx.x, t.nblocks * 256);
+}
+
+__global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
+                              double alpha, IndexMap rmap, int64_t ldr, double* __restrict__ dst, int64_t L,
+                              int64_t kdim) {
+  reduce_range(part, nchunks, rows, ncols, mode, alpha, rmap, ldr, dst, L, kdim,
+               static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x,
+               static_cast<int64_t>(gridDim.x) * blockDim.x);
 }
 
 __global__ void zero_kernel(double* p, int64_t n) {
@@ -224,7 +313,7 @@ int pick_chunks(int64_t rows, int ncols, int64_t K, size_t partial_cap) {
   return static_cast<int>(want < 1 ? 1 : want);
 }
 
-int launch_gemm(const GemmArgs& a, hipStream_t st) {
+int gemm_chunks(const GemmArgs& a, int64_t* kchunk_out) {
   const int64_t rows = a.right ? a.n : a.L * a.Q;
   const int64_t K = a.right ? a.L * a.Q : a.n;
   if (rows <= 0 || a.ncols <= 0) return 0;
@@ -232,11 +321,81 @@ int launch_gemm(const GemmArgs& a, hipStream_t st) {
   kchunk = ((kchunk + BK - 1) / BK) * BK;
   if (kchunk < BK) kchunk = BK;
   const int nch = static_cast<int>((K + kchunk - 1) / kchunk);
-  dim3 grid(static_cast<unsigned>((rows + BR - 1) / BR), static_cast<unsigned>(nch > 0 ? nch : 1),
+  if (kchunk_out) *kchunk_out = kchunk;
+  return nch > 0 ? nch : 1;
+}
+
+int launch_gemm(const GemmArgs& a, hipStream_t st) {
+  int64_t kchunk = 0;
+  const int nch = gemm_chunks(a, &kchunk);
+  if (nch == 0) return 0;
+  const int64_t rows = a.right ? a.n : a.L * a.Q;
+  dim3 grid(static_cast<unsigned>((rows + BR - 1) / BR), static_cast<unsigned>(nch),
             static_cast<unsigned>((a.ncols + BJ - 1) / BJ));
   if (a.right) gemm_dispatch_h<true>(a, grid, kchunk, st);
   else gemm_dispatch_h<false>(a, grid, kchunk, st);
-  return static_cast<int>(grid.y);
+  return nch;
+}
+
+void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t st) {
+  std::vector<GemmTask> tasks;
+  tasks.reserve(args.size());
+  int64_t blocks = 0;
+  for (const GemmArgs& a : args) {
+    TTNN_REQUIRE(a.right == args[0].right && a.th == args[0].th && a.td == args[0].td &&
+                     a.out_f32 == args[0].out_f32,
+                 TTNN_E_INVALID, "batched contraction with mixed kinds");
+    GemmTask t{};
+    const int nch = gemm_chunks(a, &t.kchunk);
+    if (nch == 0) continue;
+    const int64_t rows = a.right ? a.n : a.L * a.Q;
+    t.H = a.H;
+    t.D = a.D;
+    t.out = a.out;
+    t.L = a.L;
+    t.n = a.n;
+    t.Q = a.Q;
+    t.sDr = a.sDr;
+    t.sDc = a.sDc;
+    t.ncols = a.ncols;
+    t.amap = a.amap;
+    t.bmap = a.bmap;
+    t.ol = a.ol;
+    t.row_blocks = (rows + BR - 1) / BR;
+    t.nch = nch;
+    t.col_blocks = (a.ncols + BJ - 1) / BJ;
+    t.first_block = blocks;
+    blocks += t.row_blocks * t.nch * t.col_blocks;
+    tasks.push_back(t);
+  }
+  if (tasks.empty()) return;
+  TTNN_REQUIRE(blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+  StagingLock lock;
+  const GemmTask* d = static_cast<const GemmTask*>(stage_descriptors(tasks.data(), tasks.size() * sizeof(GemmTask), st));
+  const int nt = static_cast<int>(tasks.size());
+  if (args[0].right) batched_dispatch<true>(args[0].th, args[0].td, args[0].out_f32, d, nt, blocks, st);
+  else batched_dispatch<false>(args[0].th, args[0].td, args[0].out_f32, d, nt, blocks, st);
+  fence_descriptors(st);
+}
+
+void launch_reduce_batched(const std::vector<ReduceTask>& in, hipStream_t st) {
+  std::vector<ReduceTask> tasks;
+  int64_t blocks = 0;
+  for (ReduceTask t : in) {
+    if (t.rows <= 0 || t.ncols <= 0 || t.nchunks <= 0) continue;
+    t.nblocks = grid_for(t.rows * t.ncols);
+    t.first_block = blocks;
+    blocks += t.nblocks;
+    tasks.push_back(t);
+  }
+  if (tasks.empty()) return;
+  TTNN_REQUIRE(blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+  StagingLock lock;
+  const ReduceTask* d =
+      static_cast<const ReduceTask*>(stage_descriptors(tasks.data(), tasks.size() * sizeof(ReduceTask), st));
+  hipLaunchKernelGGL(reduce_batched_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d,
+                     static_cast<int>(tasks.size()));
+  fence_descriptors(st);
 }
 
 void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,

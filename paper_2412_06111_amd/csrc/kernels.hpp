@@ -43,6 +43,49 @@ int launch_gemm(const GemmArgs& a, hipStream_t stream);
 
 // choose the split over the contraction index; returns the number of chunks
 int pick_chunks(int64_t rows, int ncols, int64_t K, size_t partial_cap);
+// The number of chunks launch_gemm writes for `a` (0 if nothing to do) and their length.
+int gemm_chunks(const GemmArgs& a, int64_t* kchunk);
+
+// ---------------------------------------------------------------- batched launches
+// Descriptors as the batched kernels read them (device memory, staged per launch).
+struct GemmTask {
+  const void* H;
+  const void* D;
+  void* out;
+  int64_t L, n, Q, sDr, sDc, kchunk;
+  int64_t row_blocks, nch, col_blocks, first_block;
+  IndexMap amap, bmap;
+  OutLayout ol;
+  int32_t ncols, pad_;
+};
+struct ReduceTask {
+  const double* part = nullptr;
+  double* dst = nullptr;
+  int64_t rows = 0, ldr = 0, L = 1, kdim = 1;
+  double alpha = 1.0;
+  IndexMap rmap;
+  int64_t first_block = 0, nblocks = 0;
+  int32_t nchunks = 0, ncols = 0, mode = 0, pad_ = 0;
+};
+// Launch the same kind of generic contraction (right/left, dtypes, output type) for
+// every element of `args` in one kernel: each workgroup serves one tile of one task.
+// Results are bitwise those of launch_gemm on each element.
+void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t stream);
+// Fixed-order partial sums of several contractions in one launch (see launch_reduce).
+void launch_reduce_batched(const std::vector<ReduceTask>& tasks, hipStream_t stream);
+// Copy `bytes` of host descriptors into device memory that stays valid for work
+// enqueued on `stream` after this call and before the next fence_descriptors on it
+// (pinned staging ring, reused once the fenced work has finished).
+void* stage_descriptors(const void* host, size_t bytes, hipStream_t stream);
+// Mark the end of the work that reads the descriptors staged so far on `stream`.
+void fence_descriptors(hipStream_t stream);
+// Held from staging to fence, so that another host thread cannot wrap the ring in between.
+struct StagingLock {
+  StagingLock();
+  ~StagingLock();
+  StagingLock(const StagingLock&) = delete;
+  StagingLock& operator=(const StagingLock&) = delete;
+};
 
 // Sum partial results over chunks in a fixed order (FP64) and deliver them.
 //   mode 0 (RIGHT accumulate): dst[rmap(row) + ldr*j] += alpha * s
@@ -81,6 +124,27 @@ struct GJobList {
 // are split-contraction scratch (counters zero on entry, left zero on exit).
 void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, int* counters, size_t ncounters,
                     hipStream_t stream);
+
+// ---------------------------------------------------------------- rank-1 updates
+// Kronecker vector over positions (first fastest): entry(row) = prod_p v[p][digit_p(row)].
+struct KronVec {
+  int n = 0;
+  const double* v[kMaxPos] = {};
+  int64_t len[kMaxPos] = {};
+  void push(const double* p, int64_t l) {
+    v[n] = p;
+    len[n] = l;
+    ++n;
+  }
+};
+// w[j] = sum_row D[row * ncols + j] * kv(row), D row-major rows x ncols of dtype dt
+// (products and sums in FP64); deterministic (fixed blocks, fixed summation order);
+// `partial` is scratch.
+void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronVec& kv, double* partial,
+                      size_t partial_elems, double* w, hipStream_t stream);
+// R[i + n j] += alpha * ku(i) * (w ? w[j] : 1), R column-major n x ncols.
+void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const double* w, double alpha,
+                      hipStream_t stream);
 
 // ---------------------------------------------------------------- small utilities
 void launch_zero(double* p, int64_t n, hipStream_t stream);

@@ -24,6 +24,10 @@ Plan::~Plan() {
 void* Plan::alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   bytes = (bytes + 255) & ~static_cast<size_t>(255);
+  if (dry) {
+    footprint += bytes;
+    return nullptr;
+  }
   void* p = nullptr;
   if (hipMalloc(&p, bytes) != hipSuccess || p == nullptr) {
     (void)hipGetLastError();
@@ -53,7 +57,7 @@ void check_mul(int64_t a, int64_t b, const char* what) {
 
 }  // namespace
 
-std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry) {
   TTNN_REQUIRE(pr != nullptr, TTNN_E_INVALID, "problem is NULL");
   TTNN_REQUIRE(pr->order >= 2 && pr->order <= TTNN_MAX_ORDER, TTNN_E_INVALID, "order must be in [2, 8]");
   TTNN_REQUIRE(pr->dims && pr->parent && pr->first_mode && pr->last_mode && pr->rank && pr->oversample,
@@ -66,6 +70,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
   TTNN_REQUIRE(pr->eps_factor >= 0.0, TTNN_E_INVALID, "eps_factor must be >= 0");
 
   auto P = std::make_unique<Plan>();
+  P->dry = dry;
   P->d = pr->order;
   P->variant = pr->variant;
   P->dtype = pr->dtype;
@@ -208,12 +213,29 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
   P->g64_part = static_cast<double*>(P->alloc(sizeof(double) * P->g64_part_elems));
   P->g64_counters_n = size_t(1) << 14;
   P->g64_counters = static_cast<int*>(P->alloc(sizeof(int) * P->g64_counters_n));
-  launch_zero_int(P->g64_counters, static_cast<int64_t>(P->g64_counters_n), stream);
+  if (!dry) launch_zero_int(P->g64_counters, static_cast<int64_t>(P->g64_counters_n), stream);
 
   size_chain_scratch(*P);
   P->chain = static_cast<double*>(P->alloc(sizeof(double) * P->chain_elems));
   P->partial = static_cast<double*>(P->alloc(sizeof(double) * P->partial_elems));
   P->work = static_cast<double*>(P->alloc(sizeof(double) * P->work_elems));
+  {
+    size_t ks = 0, rmax = 1;
+    for (int v = 1; v < nn; ++v) {
+      ks += static_cast<size_t>(P->nodes[v].k);
+      rmax = std::max(rmax, static_cast<size_t>(P->nodes[v].r));
+    }
+    P->r1_w = ks;
+    P->r1 = static_cast<double*>(P->alloc(sizeof(double) * (ks + rmax)));
+  }
+
+  // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
+  const char* nf = std::getenv("TTNN_DISABLE_FUSED");
+  P->allow_fused = !(nf && nf[0] == '1');
+  if (dry) {
+    if (P->allow_fused) fused_prepare(*P, stream);   // sizes its buffers only
+    return P;
+  }
 
   // ---- DRMs and zeroed accumulators
   for (int v = 1; v < nn; ++v) {
@@ -226,9 +248,6 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream) {
     launch_drm(nd.m, nd.r, P->seed, tx, nd.X64, x32, x16, stream);
     launch_drm(nd.n, nd.k, P->seed, ty, nd.Y64, y32, y16, stream);
   }
-  // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
-  const char* nf = std::getenv("TTNN_DISABLE_FUSED");
-  P->allow_fused = !(nf && nf[0] == '1');
   if (P->allow_fused) fused_prepare(*P, stream);
   zero_accumulators(*P, stream);
   TTNN_HIP(hipGetLastError());

@@ -66,6 +66,8 @@ struct Plan {
   size_t chain_elems = 0;
   double* partial = nullptr;               // split-K partials
   size_t partial_elems = 0;
+  double* r1 = nullptr;                    // rank-1 updates: g_s vectors, then w (max r)
+  size_t r1_w = 0;                         // offset of w in r1
   double* work = nullptr;                  // assembly / reconstruction scratch
   size_t work_elems = 0;
   int* d_flag = nullptr;                   // numeric-status flag written by kernels
@@ -76,6 +78,7 @@ struct Plan {
 
   std::vector<void*> allocs;
   size_t footprint = 0;
+  bool dry = false;                        // sizing only: alloc() counts and returns nullptr
   ttnn_status sticky = TTNN_OK;
   bool epilogue_valid = false;             // Om / Psi reflect the accumulators
   bool has_cores = false;
@@ -91,7 +94,9 @@ struct Plan {
 };
 
 // construction / validation (host); throws Error
-std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream);
+// dry: validate and size everything, allocate nothing and launch nothing (the
+// returned plan only reports its footprint).
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry = false);
 
 // IndexMap from a set of consecutive modes of a box to the column-major index of
 // the same modes in the full tensor

@@ -71,3 +71,22 @@ def test_bad_arguments_rejected():
     pr = _lib.Problem(2, arr[0], 3, arr[1], arr[2], arr[3], arr[4], arr[5], 0, 0, 1, 0.0)
     assert _create(pr)[0] == -2
     assert _lib.lib.ttnn_status_string(-7) == b"numerical failure"
+
+
+def test_footprint_estimate_without_device():
+    """Host-side sizing: no allocation or launch, so it runs without a GPU."""
+    import paper_2412_06111_amd as P
+    spec = ((1, 2), (3, 4))
+    small = P.footprint_estimate(spec, (16, 16, 16, 16), 6, 3, "ttnn", "f64")
+    big = P.footprint_estimate(spec, (64, 64, 64, 64), 6, 3, "ttnn", "f64")
+    bf = P.footprint_estimate(spec, (64, 64, 64, 64), 6, 3, "ttnn", "bf16")
+    assert 0 < small < big < bf
+    # the TTNN leaf X maps alone: 4 leaves x 64^3 rows x 6 columns, FP64 masters + BF16 copies
+    assert bf > 4 * 64 ** 3 * 6 * (8 + 2)
+
+
+def test_footprint_estimate_rejects_bad_tree():
+    import paper_2412_06111_amd as P
+    with pytest.raises(P.TTNNError) as e:
+        P.footprint_estimate(((1, 3), (2, 4)), (4, 4, 4, 4), 2, 1)
+    assert e.value.status == -2
