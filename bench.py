@@ -42,6 +42,11 @@ def parse():
     ap.add_argument("--headline", default="sttnn:f32")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--serve-streams", type=int, default=64)
+    ap.add_argument("--serve-nmax", type=int, default=160)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="Poisson rate as a fraction of the batched path's closed-loop rate")
     return ap.parse_args()
 
 
@@ -199,6 +204,103 @@ def run_gpu(args, T_dev64, variant, dtype):
     return res
 
 
+# ---------------------------------------------------------------- serving
+def serving_bench(args):
+    """Many streams of box updates (mode sizes U{32..nmax}, TTN ranks 8..32 + 1e-5
+    noise, r in {16, 32}, p = r/2, TTNN on ((1,2),(3,4))), admission at 50% of the
+    streams' total footprint.  Batched FP32 server vs the plain FP64 path with one
+    update per launch, each closed-loop (all updates at t=0: saturation rate) and
+    under Poisson arrivals at `serve_load` x the batched saturation rate.  Update
+    payloads are resident in HBM before the clock starts."""
+    import numpy as np
+    import torch
+    import paper_2412_06111_amd as P
+    from paper_2412_06111_amd import serve as S
+    from workloads import serving as WS
+
+    probs = [WS.stream_problem(s, nhi=args.serve_nmax) for s in range(args.serve_streams)]
+    tens, boxes = [], []
+    for pr in probs:
+        tens.append(WS.stream_tensor_device(pr))
+        boxes.append(WS.boxes(pr["dims"], WS.rng(pr["seed"] + 31)))
+    n_updates = sum(len(b) for b in boxes)
+
+    def make_updates(dtype):
+        tdt = {"f32": torch.float32, "f64": torch.float64}[dtype]
+        per = []
+        for s, (pr, T, bx) in enumerate(zip(probs, tens, boxes)):
+            n1, n2, n3, n4 = pr["dims"]
+            V = T.view(n4, n3, n2, n1)
+            ups = []
+            for off, ext in bx:
+                blk = V[off[3]:off[3] + ext[3], off[2]:off[2] + ext[2], off[1]:off[1] + ext[1],
+                        off[0]:off[0] + ext[0]].to(tdt).contiguous().reshape(-1)
+                ups.append(S.Update(s, "box", block=blk, offset=off, extent=ext, nbytes=blk.numel() * blk.element_size()))
+            per.append(ups)
+        return per
+
+    def specs(dtype):
+        return [S.StreamSpec(WS.T4, pr["dims"], pr["r"], pr["p"], variant="ttnn", dtype=dtype, seed=pr["seed"])
+                for pr in probs]
+
+    def one_run(dtype, max_batch, rate, per):
+        sp = specs(dtype)
+        fps = [P.footprint_estimate(x.spec, x.dims, x.rank, x.over, x.variant, x.dtype) for x in sp]
+        budget = max(max(fps), sum(fps) // 2)
+        errs = {}
+
+        def on_close(sid, plan, cores):
+            That = plan.reconstruct(cores)
+            e2, n2 = P.diff_norms(That, tens[sid])
+            errs[sid] = (e2 / n2) ** 0.5
+            del That
+
+        srv = S.Server(budget_bytes=budget, max_batch=max_batch, max_inflight=2, on_close=on_close)
+        for s in range(len(probs)):
+            srv.open_stream(s, sp[s])
+        # arrival order: a random interleaving of the streams (each stream's boxes in its own order)
+        g = WS.rng(7)
+        order = g.permutation(np.repeat(np.arange(len(probs)), [len(u) for u in per]))
+        nxt = [0] * len(probs)
+        arrivals = []
+        times = WS.poisson_arrivals(len(order), rate, seed=11) if rate else np.zeros(len(order))
+        for t, sid in zip(times, order):
+            u = per[sid][nxt[sid]]
+            nxt[sid] += 1
+            u.arrival, u.t_done = float(t), None
+            arrivals.append(u)
+        st = srv.run(arrivals)
+        st["budget_bytes"] = budget
+        st["total_footprint_bytes"] = sum(fps)
+        st["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else 0.0
+        st["approx_rel_error_median"] = float(np.median(list(errs.values())))
+        st["approx_rel_error_max"] = float(np.max(list(errs.values())))
+        return st
+
+    out = {"streams": len(probs), "updates": n_updates,
+           "workload": f"{len(probs)} streams, TTNN on ((1,2),(3,4)), n ~ U{{32..{args.serve_nmax}}}, "
+                       "TTN ranks 8..32 + 1e-5 noise, r in {16,32}, p=r/2, sub-blocks 4..48 per mode; "
+                       "admission at 50% of the total footprint"}
+    per32 = make_updates("f32")
+    closed = one_run("f32", 64, 0.0, per32)
+    out["batched_f32_closed_loop"] = closed
+    print(f"# serving batched f32 closed loop: {json.dumps(closed)}", file=sys.stderr, flush=True)
+    rate = args.serve_load * closed["updates_per_s"]
+    out["poisson_rate_per_s"] = rate
+    out["batched_f32_poisson"] = one_run("f32", 64, rate, per32)
+    print(f"# serving batched f32 poisson: {json.dumps(out['batched_f32_poisson'])}", file=sys.stderr, flush=True)
+    del per32
+    per64 = make_updates("f64")
+    out["fp64_one_per_launch_closed_loop"] = one_run("f64", 1, 0.0, per64)
+    print(f"# serving fp64 closed loop: {json.dumps(out['fp64_one_per_launch_closed_loop'])}", file=sys.stderr,
+          flush=True)
+    out["fp64_one_per_launch_poisson"] = one_run("f64", 1, rate, per64)
+    print(f"# serving fp64 poisson: {json.dumps(out['fp64_one_per_launch_poisson'])}", file=sys.stderr, flush=True)
+    del per64, tens
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(T, tree, variant, seed=1, box=112):
     """The FP64 oracle on a bounded sample of the same workload: the corner box of
     size box^4 as a streaming update (DRM rows generated before timing)."""
@@ -278,6 +380,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(T, tree_def, hv)
+    serving = None
+    if not args.no_serve:
+        del T_dev64
+        torch.cuda.empty_cache()
+        serving = serving_bench(args)
 
     line = {
         "metric": METRIC,
@@ -300,6 +407,7 @@ def main():
         "cpu_baseline": cpu,
         "results": results,
         "copy_calibration": copy,
+        "serving": serving,
         "input_generation_s": t_gen,
     }
     print(json.dumps(line))

@@ -64,6 +64,28 @@ def stream_tensor(prob, noise=1e-5):
     return add_relative_noise(T, noise, seed=prob["seed"] + 17, unit_rms=True)
 
 
+def stream_tensor_device(prob, noise=1e-5, device="cuda"):
+    """The same recipe as stream_tensor, contracted on the device (torch, FP64) for
+    large streams: cores drawn on the host (seeded), noise from a seeded device
+    generator.  Returns the flat column-major FP64 device tensor."""
+    import torch
+    dims = prob["dims"]
+    c = gaussian_ttn_cores(T4, dims, prob["ttn_ranks"], prob["seed"])
+    t = {m: torch.from_numpy(np.asarray(v, dtype=np.float64)).to(device) for m, v in c.items()}
+    U1, U2, U3, U4 = t[(1,)], t[(2,)], t[(3,)], t[(4,)]            # (n, r) each
+    A, B, root = t[(1, 2)], t[(3, 4)], t[(1, 2, 3, 4)]             # (r1, r2, rA), (r3, r4, rB), (rA, rB)
+    # UA[(i1, i2), a] and UB[(i3, i4), b], first index fastest, then T = UA root UB^T
+    UA = torch.einsum("ix,jy,xya->jia", U1, U2, A).reshape(dims[0] * dims[1], -1)
+    UB = torch.einsum("kz,lw,zwb->lkb", U3, U4, B).reshape(dims[2] * dims[3], -1)
+    Tm = UA @ root @ UB.T                       # (nA, nB): column-major flat = Tm.T row-major
+    flat = Tm.T.contiguous().reshape(-1)
+    flat *= (flat.numel() ** 0.5) / torch.linalg.vector_norm(flat)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(prob["seed"]) + 17)
+    flat += noise * torch.randn(flat.numel(), generator=g, device=device, dtype=torch.float64)
+    return flat
+
+
 def box_updates(T, prob, lo=4, hi=48):
     """(offset, extent, block) for the boxes of one tiling of T; block is the
     column-major flat FP64 copy of T over the box."""
