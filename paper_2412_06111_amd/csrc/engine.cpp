@@ -488,6 +488,11 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
       continue;
     }
     batch.flush();
+    if (pre.empty() && whole && t.Xt) {          // raw tensor, contiguous contraction: MFMA
+      const int nch = launch_right_mfma(block, cd, L, n, Q, t.Xt, t.m, t.r, P.partial, P.partial_elems, st);
+      launch_reduce(P.partial, nch, n, t.r, 0, alpha, box_rows(P, t.first, t.last, off, ext), t.n, t.R, 1, 1, st);
+      continue;
+    }
     // X_t rows: every position except those of t, first fastest
     IndexMap amap, bmap;
     int64_t C = 1;

@@ -9,6 +9,11 @@
 //   R_2 = (T x_1 Y_1^T)^{2} X_2  -- Z1 = Y_1^T slab kept on chip, then Z1 . X_2 rows
 // R_B and the right subtree (and the root sketch) follow from Z_A on the generic path.
 //
+// TTNN mode (template flag TT): R_A, Z_A and R_1 are the same sketches in TTNN (their
+// reuse sets are empty), and for a root with two children R_B = T^{(B)} X_B with X_B
+// rows over i_A, so R_B^T = X_B^T M is formed like Z_A, by the waves that STTNN spends
+// on Z1.  The leaves right of A ({2} and the subtree of B) follow on the other paths.
+//
 // Each workgroup streams a tile of M (B2 whole i1-slabs x BB columns) through LDS
 // once; every product is an MFMA chain on that LDS tile:
 //   (a)+(c) share the A fragments of the slab (rows i1, K = columns) against
@@ -31,8 +36,8 @@ struct SttnnArgs {
   const void* T;
   int64_t n2, nA, nB;
   int TA, TB, CB;
-  const void *XA, *X1, *YA, *Y1, *X2;
-  void *PRA, *PZA, *PR1, *PR2;
+  const void *XA, *X1, *YA, *Y1, *X2, *XB;
+  void *PRA, *PZA, *PR1, *PR2, *PRB;
 };
 
 template <typename P>
@@ -45,7 +50,7 @@ __device__ inline typename P::Frag frag_contig(const typename P::T* p) {
 // straight from global memory into one of two LDS stages (global_load_lds, 16 bytes
 // per lane) while the other stage is being consumed.  Operands that do not fit the
 // budget are read from global memory (L2) instead.
-template <int DT, int R, int KP, int B2, int SC>
+template <int DT, int R, int KP, int B2, int SC, bool TT>
 struct SttnnLayout {
   using P = Pol<DT>;
   using T = typename P::T;
@@ -53,20 +58,23 @@ struct SttnnLayout {
   static constexpr int KPL = P::KPL;
   static constexpr int PADE = 16 / ESZ;                       // one 16-byte vector of padding
   static constexpr int S = N1 + PADE;                         // slab column stride
-  static constexpr int SY = (KPL == 8) ? N1 + PADE : KP;      // row stride of staged Y blocks
+  static constexpr int SY = (KPL == 8) ? N1 + PADE : KP;      // row stride of staged Y_A blocks
+  static constexpr int SXB = (KPL == 8) ? N1 + PADE : R;      // row stride of staged X_B blocks (TT)
   static constexpr int SX = (KPL == 8) ? SC + PADE : R;       // row stride of staged X blocks
   static constexpr int YROWS = (KPL == 8) ? KP : N1;
+  static constexpr int XBROWS = (KPL == 8) ? R : N1;
   static constexpr int XROWS = (KPL == 8) ? R : SC;
   static constexpr size_t MS = size_t(SC) * S * ESZ;
-  static constexpr size_t Z1 = size_t(B2) * KP * SC * ESZ;
-  static constexpr size_t YB = size_t(YROWS) * SY * ESZ;
+  static constexpr size_t Z1 = TT ? 0 : size_t(B2) * KP * SC * ESZ;
+  static constexpr size_t YB = size_t(YROWS) * SY * ESZ + (TT ? size_t(XBROWS) * SXB * ESZ : 0);
   static constexpr size_t XB = size_t(XROWS) * SX * ESZ;
   static constexpr size_t BUDGET = 156 * 1024;
   static constexpr bool STAGE_YA = 2 * (MS + YB) + Z1 <= BUDGET;
   static constexpr bool STAGE_X = STAGE_YA && 2 * (MS + YB + 2 * XB) + Z1 <= BUDGET;
   static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
-  static constexpr bool STAGE_Y1 = 2 * STAGE + Z1 + YB <= BUDGET;
+  static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + YB <= BUDGET;
   static constexpr size_t OFF_YA = MS;                         // offsets within a stage
+  static constexpr size_t OFF_XB = OFF_YA + size_t(YROWS) * SY * ESZ;   // TT: X_B rows after Y_A rows
   static constexpr size_t OFF_XA = OFF_YA + (STAGE_YA ? YB : 0);
   static constexpr size_t OFF_X1 = OFF_XA + (STAGE_X ? XB : 0);
   static constexpr size_t OFF_Z1 = 2 * STAGE;                 // after both stages
@@ -106,10 +114,10 @@ __device__ inline void lds_dma_contig(const T* g, T* l, int vecs, int wave, int 
 
 
 // Issue the copies of the sub-tile (slab i2, columns col0 .. col0+SC-1) into one stage.
-template <int DT, int R, int KP, int B2, int SC>
+template <int DT, int R, int KP, int B2, int SC, bool TT>
 __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int64_t col0, int wave, int lane) {
   using P = Pol<DT>;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
   using T = typename P::T;
   constexpr int EV = 16 / sizeof(T);
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
@@ -120,6 +128,12 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
     T* ys = reinterpret_cast<T*>(sb + Lay::OFF_YA);
     if constexpr (P::KPL == 8) lds_dma_rows(YA + i2 * N1, nA, ys, Lay::SY, KP, N1 / EV, wave, lane);
     else lds_dma_contig(YA + i2 * N1 * KP, ys, N1 * KP / EV, wave, lane);
+    if constexpr (TT) {
+      const T* XB = static_cast<const T*>(a.XB);
+      T* xb = reinterpret_cast<T*>(sb + Lay::OFF_XB);
+      if constexpr (P::KPL == 8) lds_dma_rows(XB + i2 * N1, nA, xb, Lay::SXB, R, N1 / EV, wave, lane);
+      else lds_dma_contig(XB + i2 * N1 * R, xb, N1 * R / EV, wave, lane);
+    }
   }
   if constexpr (Lay::STAGE_X) {
     const T* XA = static_cast<const T*>(a.XA);
@@ -136,10 +150,10 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
   }
 }
 
-template <int DT, int R, int KP, int B2, int SC>
+template <int DT, int R, int KP, int B2, int SC, bool TT>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
   using T = typename P::T;
   using Acc = typename P::Acc;
   using Frag = typename P::Frag;
@@ -191,8 +205,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // issue the copies of sub-tile s into stage buf
   auto issue = [&](int s, int buf) {
     const int cb = s / B2, i2l = s % B2;
-    sttnn_issue<DT, R, KP, B2, SC>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC, wave,
-                                   lane);
+    sttnn_issue<DT, R, KP, B2, SC, TT>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC,
+                                       wave, lane);
   };
   // Y_1 rows, resident for the whole kernel
   if constexpr (Lay::STAGE_Y1) {
@@ -200,10 +214,13 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     else lds_dma_contig(Y1, Y1s, N1 * KP / EV, wave, lane);
   }
 
+  constexpr int KBB = R / 16;               // TT: 16-row blocks of R_B^T
+  const T* XB = static_cast<const T*>(a.XB);
   CFrag rA[B2][CBR];
   CFrag r1[CBR];
   CFrag r2[CBR];
   CFrag zA[KB];
+  CFrag zB[TT ? KBB : 1];
   const CFrag zero = {};
 #pragma unroll
   for (int i = 0; i < B2; ++i)
@@ -225,6 +242,10 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     const int64_t iBbase = c_tile + static_cast<int64_t>(cb) * SC;
 #pragma unroll
     for (int rb = 0; rb < KB; ++rb) zA[rb] = zero;
+    if constexpr (TT) {
+#pragma unroll
+      for (int rb = 0; rb < KBB; ++rb) zB[rb] = zero;
+    }
 
 #pragma unroll
     for (int i2l = 0; i2l < B2; ++i2l) {
@@ -238,6 +259,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       const T* YAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
       const T* XAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XA);
       const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
+      const T* XBs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
 
       // (a) R_A rows of this slab and (c) R_1: A = slab (rows i1, K = columns)
       const int i1 = 16 * wave + l16;
@@ -300,7 +322,28 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
             zA[rb] = P::mfma(ay, bM, zA[rb]);
           }
         }
-      } else if (bd_active) {
+      } else if (TT && bd_active) {
+        // (b') R_B^T += X_B^T slab
+        const int iBl = 16 * cblk + l16;
+#pragma unroll 4
+        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
+          const int kk = ks * KSTEP + KPL * lg;
+          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll
+          for (int rb = 0; rb < KBB; ++rb) {
+            const int jr = 16 * rb + l16;
+            Frag ax;
+            if constexpr (Lay::STAGE_YA) {
+              if constexpr (KPL == 8) ax = P::load8(XBs + jr * Lay::SXB + kk);
+              else ax = XBs[kk * Lay::SXB + jr];
+            } else {
+              if constexpr (KPL == 8) ax = P::load8(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
+              else ax = XB[(i2 * N1 + kk) * R + jr];
+            }
+            zB[rb] = P::mfma(ax, bM, zB[rb]);
+          }
+        }
+      } else if (!TT && bd_active) {
         const int iBl = 16 * cblk + l16;
         CFrag acc[KB];
 #pragma unroll
@@ -332,11 +375,11 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           }
       }
     }  // i2l
-    __syncthreads();
+    if constexpr (!TT) __syncthreads();
 
     // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (j1, column)) . X_2 rows (j1 + k column)
 #pragma unroll 2
-    for (int ks = 0; ks < KW / KSTEP; ++ks) {
+    for (int ks = 0; ks < (TT ? 0 : KW / KSTEP); ++ks) {
       const int K = wave * KW + ks * KSTEP + KPL * lg;
       Frag az;
       if (l16 < B2) az = frag_contig<P>(&Z1s[l16 * KT + K]);
@@ -364,6 +407,19 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
         }
     }
+    if constexpr (TT) {
+      if (bd_active && !bd_zA) {
+        Acc* PRB = static_cast<Acc*>(a.PRB);
+        const int64_t iB = iBbase + 16 * cblk + l16;
+#pragma unroll
+        for (int rb = 0; rb < KBB; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j = 16 * rb + P::crow(lane, v);
+            PRB[(static_cast<int64_t>(tA) * R + j) * nB + iB] = zB[rb][v];
+          }
+      }
+    }
   }  // cb
 
   // ---- partial results of the tile
@@ -384,6 +440,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
         PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[c][v];
       }
   }
+  if constexpr (TT) return;
   __syncthreads();
   Acc* red = reinterpret_cast<Acc*>(smem);          // 8 waves x 16 rows x R
 #pragma unroll
@@ -403,12 +460,14 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   }
 }
 
-// Sum the tile partials in a fixed order into the FP64 state.
+// Sum the tile partials in a fixed order into the FP64 state.  The last segment is
+// R_2 (STTNN; PR2 [tB][n2][R]) or, in TTNN mode, R_B (PRB [tA][R][nB]).
 template <typename Acc>
 __global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2, int TA, int TB,
                                 int64_t n2, int64_t nA, int64_t nB, int R, int KP, int k, double alpha, double* RA,
-                                double* ZA, double* R1, double* R2) {
-  const int64_t nRA = nA * R, nZA = static_cast<int64_t>(k) * nB, nR1 = static_cast<int64_t>(N1) * R, nR2 = n2 * R;
+                                double* ZA, double* R1, double* R2, int tt) {
+  const int64_t nRA = nA * R, nZA = static_cast<int64_t>(k) * nB, nR1 = static_cast<int64_t>(N1) * R;
+  const int64_t nR2 = tt ? nB * R : n2 * R;
   const int64_t total = nRA + nZA + nR1 + nR2;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
@@ -429,12 +488,18 @@ __global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, 
       double s = 0.0;
       for (int t = 0; t < TA * TB; ++t) s += static_cast<double>(PR1[(t * static_cast<int64_t>(N1) + i1) * R + j]);
       R1[i1 + N1 * j] += alpha * s;
-    } else {
+    } else if (!tt) {
       const int64_t f = e - nRA - nZA - nR1;
       const int64_t i2 = f / R, j = f % R;
       double s = 0.0;
       for (int t = 0; t < TB; ++t) s += static_cast<double>(PR2[(t * n2 + i2) * R + j]);
       R2[i2 + n2 * j] += alpha * s;
+    } else {
+      const int64_t f = e - nRA - nZA - nR1;
+      const int64_t j = f / nB, c = f % nB;
+      double s = 0.0;
+      for (int t = 0; t < TA; ++t) s += static_cast<double>(PR2[(t * static_cast<int64_t>(R) + j) * nB + c]);
+      R2[c + nB * j] += alpha * s;
     }
   }
 }
@@ -460,6 +525,8 @@ __global__ void gather_copy(const double* src, TO* out, int64_t d0, int64_t d1, 
   }
 }
 
+}  // namespace
+
 void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, int64_t d2, int64_t s0, int64_t s1,
                  int64_t s2, int cdim, int64_t lim, hipStream_t st) {
   const int64_t total = d0 * d1 * d2;
@@ -474,6 +541,8 @@ void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, i
     hipLaunchKernelGGL(gather_copy<double>, dim3(blocks), dim3(256), 0, st, src, static_cast<double*>(out), d0, d1,
                        d2, s0, s1, s2, cdim, lim);
 }
+
+namespace {
 
 struct Shape {
   int B2, SC;
@@ -495,17 +564,18 @@ Shape shape_for(int dt, int R) {
 }
 
 template <int DT, int R, int KP>
-void launch_sttnn(const SttnnArgs& a, hipStream_t st) {
+void launch_sttnn(bool tt, const SttnnArgs& a, hipStream_t st) {
   constexpr int B2 = b2_of<DT, R>();
   constexpr int SC = sc_of<DT>();
-  hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
+  if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC, true>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
+  else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC, false>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
 }
 
 template <int DT>
-void launch_sttnn_dt(int R, const SttnnArgs& a, hipStream_t st) {
-  if (R == 16) launch_sttnn<DT, 16, 32>(a, st);
-  else if (R == 32) launch_sttnn<DT, 32, 48>(a, st);
-  else launch_sttnn<DT, 64, 96>(a, st);
+void launch_sttnn_dt(int R, bool tt, const SttnnArgs& a, hipStream_t st) {
+  if (R == 16) launch_sttnn<DT, 16, 32>(tt, a, st);
+  else if (R == 32) launch_sttnn<DT, 32, 48>(tt, a, st);
+  else launch_sttnn<DT, 64, 96>(tt, a, st);
 }
 
 int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; }
@@ -516,9 +586,11 @@ int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; 
 void fused_prepare(Plan& P, hipStream_t st) {
   FusedT4& F = P.fused;
   F.enabled = false;
-  if (P.variant != TTNN_STTNN || P.d < 3) return;
+  const bool tt = P.variant == TTNN_TTNN;
+  if (P.d < 3) return;
   const Node& root = P.nodes[0];
   if (root.children.size() < 2) return;
+  if (tt && root.children.size() != 2) return;            // X_B rows must be exactly i_A
   const int A = root.children[0];
   const Node& nA_ = P.nodes[A];
   if (nA_.first != 0 || nA_.last != 1 || nA_.children.size() != 2) return;
@@ -559,6 +631,9 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.node_A = A;
   F.node_1 = c1;
   F.node_2 = c2;
+  F.tt = tt;
+  F.node_B = root.children[1];
+  if (tt && (P.nodes[F.node_B].r != R || P.nodes[F.node_B].m != nAs)) return;
 
   const int dt = P.dtype;
   const int64_t es = elem_size(dt);
@@ -567,9 +642,14 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.XA = P.alloc(es * nB * R);
   F.X1 = P.alloc(es * nAs / N1 * nB * R);
   F.YA = P.alloc(es * nAs * KP);
-  F.Y1 = P.alloc(es * N1 * KP);
-  F.X2 = P.alloc(es * nB * KP * R);
+  if (tt) {
+    F.XB = P.alloc(es * nAs * R);
+  } else {
+    F.Y1 = P.alloc(es * N1 * KP);
+    F.X2 = P.alloc(es * nB * KP * R);
+  }
   const Node& NA = P.nodes[A];
+  const double* XB64 = P.nodes[F.node_B].X64;
   const int k = nA_.k;
   if (P.dry) {
     // sizing only
@@ -577,20 +657,29 @@ void fused_prepare(Plan& P, hipStream_t st) {
     copy_layout(NA.X64, F.XA, dt, nB, R, 1, R, 1, 0, 0, nB, st);                     // [j][iB]
     copy_layout(L1.X64, F.X1, dt, nB, n2, R, n2 * R, R, 1, 0, nB, st);               // [j][i2][iB]
     copy_layout(NA.Y64, F.YA, dt, nAs, KP, 1, k, 1, 0, 1, k, st);                    // [jA][iA]
-    copy_layout(L1.Y64, F.Y1, dt, N1, KP, 1, k, 1, 0, 1, k, st);                     // [j1][i1]
-    copy_layout(L2.X64, F.X2, dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
+    if (tt) {
+      copy_layout(XB64, F.XB, dt, nAs, R, 1, R, 1, 0, 1, R, st);                     // [j][iA]
+    } else {
+      copy_layout(L1.Y64, F.Y1, dt, N1, KP, 1, k, 1, 0, 1, k, st);                   // [j1][i1]
+      copy_layout(L2.X64, F.X2, dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
+    }
   } else {
     copy_layout(NA.X64, F.XA, dt, R, nB, 1, 1, R, 0, 0, R, st);                      // [iB][j]
     copy_layout(L1.X64, F.X1, dt, R, nAs / N1 * nB, 1, 1, R, 0, 0, R, st);           // rows (i2 + n2 iB)
     copy_layout(NA.Y64, F.YA, dt, KP, nAs, 1, 1, k, 0, 0, k, st);                    // [iA][jA]
-    copy_layout(L1.Y64, F.Y1, dt, KP, N1, 1, 1, k, 0, 0, k, st);                     // [i1][j1]
-    copy_layout(L2.X64, F.X2, dt, R, KP, nB, 1, R, static_cast<int64_t>(k) * R, 1, k, st);  // [iB][j1][j]
+    if (tt) {
+      copy_layout(XB64, F.XB, dt, R, nAs, 1, 1, R, 0, 0, R, st);                     // [iA][j]
+    } else {
+      copy_layout(L1.Y64, F.Y1, dt, KP, N1, 1, 1, k, 0, 0, k, st);                   // [i1][j1]
+      copy_layout(L2.X64, F.X2, dt, R, KP, nB, 1, R, static_cast<int64_t>(k) * R, 1, k, st);  // [iB][j1][j]
+    }
   }
   const int64_t as = dt == TTNN_F64 ? 8 : 4;
   F.PRA = P.alloc(as * TB * nAs * R);
   F.PZA = P.alloc(as * TA * KP * nB);
   F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
-  F.PR2 = P.alloc(as * TB * n2 * R);
+  if (tt) F.PRB = P.alloc(as * TA * R * nB);
+  else F.PR2 = P.alloc(as * TB * n2 * R);
   F.enabled = true;
 }
 
@@ -613,13 +702,15 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
   a.YA = F.YA;
   a.Y1 = F.Y1;
   a.X2 = F.X2;
+  a.XB = F.XB;
   a.PRA = F.PRA;
   a.PZA = F.PZA;
   a.PR1 = F.PR1;
   a.PR2 = F.PR2;
-  if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, a, st);
-  else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, a, st);
-  else launch_sttnn_dt<TTNN_F64>(F.R, a, st);
+  a.PRB = F.PRB;
+  if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, F.tt, a, st);
+  else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, F.tt, a, st);
+  else launch_sttnn_dt<TTNN_F64>(F.R, F.tt, a, st);
   if (P.timing) {
     TTNN_HIP(hipEventRecord(P.sweep_ev[1], st));
     P.sweep_recorded = true;
@@ -627,19 +718,22 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
 
   const std::vector<int> pre{F.node_A};
   double* ZA = P.chain + P.prefix_offset.at(pre);
-  const int64_t total = F.nA * F.R + static_cast<int64_t>(F.k) * F.nB + static_cast<int64_t>(N1) * F.R + F.n2 * F.R;
+  const int64_t total = F.nA * F.R + static_cast<int64_t>(F.k) * F.nB + static_cast<int64_t>(N1) * F.R +
+                        (F.tt ? F.nB : F.n2) * F.R;
+  const int node_last = F.tt ? F.node_B : F.node_2;
+  const void* plast = F.tt ? F.PRB : F.PR2;
   const int blocks = static_cast<int>(std::min<int64_t>((total + 255) / 256, 8192));
   if (P.dtype == TTNN_F64)
     hipLaunchKernelGGL(sttnn_t4_reduce<double>, dim3(blocks), dim3(256), 0, st, static_cast<const double*>(F.PRA),
                        static_cast<const double*>(F.PZA), static_cast<const double*>(F.PR1),
-                       static_cast<const double*>(F.PR2), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[F.node_2].R);
+                       static_cast<const double*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0);
   else
     hipLaunchKernelGGL(sttnn_t4_reduce<float>, dim3(blocks), dim3(256), 0, st, static_cast<const float*>(F.PRA),
                        static_cast<const float*>(F.PZA), static_cast<const float*>(F.PR1),
-                       static_cast<const float*>(F.PR2), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[F.node_2].R);
-  done_nodes->assign({F.node_A, F.node_1, F.node_2});
+                       static_cast<const float*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0);
+  done_nodes->assign({F.node_A, F.node_1, node_last});
   done_prefixes->assign({pre});
   return true;
 }

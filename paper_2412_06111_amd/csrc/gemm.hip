@@ -228,9 +228,8 @@ void batched_dispatch(int th, int td, bool out_f32, const GemmTask* tasks, int n
 
 __device__ inline void reduce_range(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
                                     double alpha, const IndexMap& rmap, int64_t ldr, double* __restrict__ dst,
-                                    int64_t L, int64_t kdim, int64_t start, int64_t step) {
+                                    int64_t L, int64_t kdim, int64_t start, int64_t step, int64_t stride) {
   const int64_t total = rows * ncols;
-  const int64_t stride = rows * ncols;
   for (int64_t e = start; e < total; e += step) {
     const int64_t row = e / ncols;
     const int j = static_cast<int>(e - row * ncols);
@@ -251,15 +250,48 @@ __global__ __launch_bounds__(256) void reduce_batched_kernel(const ReduceTask* _
   ReduceTask& t = *reinterpret_cast<ReduceTask*>(tbuf);
   const int64_t rel = load_task(tasks, ntasks, &t);
   reduce_range(t.part, t.nchunks, t.rows, t.ncols, t.mode, t.alpha, t.rmap, t.ldr, t.dst, t.L, t.kdim,
-               rel * 256 + threadIdx.x, t.nblocks * 256);
+               rel * 256 + threadIdx.x, t.nblocks * 256, t.cstride ? t.cstride : t.rows * t.ncols);
+}
+
+constexpr int kFold = 32;
+
+// Fold groups of kFold consecutive chunks into each group's first slot (see
+// fold_chunks_kernel); workgroup -> (task, element block, group).
+__global__ __launch_bounds__(256) void fold_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+  __shared__ __align__(16) char tbuf[sizeof(ReduceTask)];
+  ReduceTask& t = *reinterpret_cast<ReduceTask*>(tbuf);
+  const int64_t rel = load_task(tasks, ntasks, &t);
+  const int64_t E = t.rows * t.ncols;
+  const int64_t eblocks = (E + 255) / 256;
+  const int64_t e = (rel % eblocks) * 256 + threadIdx.x;
+  const int g = static_cast<int>(rel / eblocks);
+  if (e >= E) return;
+  const int c0 = g * kFold, c1 = c0 + kFold < t.nchunks ? c0 + kFold : t.nchunks;
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += t.part[c * E + e];
+  t.part[c0 * E + e] = s;
 }
 
 __global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
                               double alpha, IndexMap rmap, int64_t ldr, double* __restrict__ dst, int64_t L,
-                              int64_t kdim) {
+                              int64_t kdim, int64_t stride) {
   reduce_range(part, nchunks, rows, ncols, mode, alpha, rmap, ldr, dst, L, kdim,
                static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x,
-               static_cast<int64_t>(gridDim.x) * blockDim.x);
+               static_cast<int64_t>(gridDim.x) * blockDim.x, stride);
+}
+
+// Many chunks, few elements: fold each group of kFold consecutive chunks into the
+// group's first chunk slot (in place, fixed order), so that the final pass sums
+// ceil(nchunks / kFold) values per element.  Element e of group g is read and
+// written by one thread only.
+__global__ void fold_chunks_kernel(double* __restrict__ part, int nchunks, int64_t E) {
+  const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int g = blockIdx.y;
+  if (e >= E) return;
+  const int c0 = g * kFold, c1 = c0 + kFold < nchunks ? c0 + kFold : nchunks;
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += part[c * E + e];
+  part[c0 * E + e] = s;
 }
 
 __global__ void zero_kernel(double* p, int64_t n) {
@@ -292,6 +324,8 @@ __global__ void finite_kernel(const double* p, int64_t n, int* flag) {
        i += static_cast<int64_t>(gridDim.x) * blockDim.x)
     if (!isfinite(p[i])) *flag = 1;
 }
+
+inline bool fold_pays(int nchunks, int64_t E) { return nchunks > 2 * kFold && E < (int64_t(1) << 20); }
 
 inline int grid_for(int64_t n) {
   const int64_t b = (n + 255) / 256;
@@ -379,16 +413,36 @@ void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t st) {
 }
 
 void launch_reduce_batched(const std::vector<ReduceTask>& in, hipStream_t st) {
-  std::vector<ReduceTask> tasks;
-  int64_t blocks = 0;
+  // the same two passes as launch_reduce, so batched and single results are bitwise equal
+  std::vector<ReduceTask> folds, tasks;
+  int64_t fblocks = 0, blocks = 0;
   for (ReduceTask t : in) {
     if (t.rows <= 0 || t.ncols <= 0 || t.nchunks <= 0) continue;
-    t.nblocks = grid_for(t.rows * t.ncols);
+    const int64_t E = t.rows * t.ncols;
+    if (fold_pays(t.nchunks, E)) {
+      ReduceTask f = t;
+      f.groups = (t.nchunks + kFold - 1) / kFold;
+      f.first_block = fblocks;
+      fblocks += (E + 255) / 256 * f.groups;
+      folds.push_back(f);
+      t.nchunks = f.groups;
+      t.cstride = E * kFold;
+    }
+    t.nblocks = grid_for(E);
     t.first_block = blocks;
     blocks += t.nblocks;
     tasks.push_back(t);
   }
   if (tasks.empty()) return;
+  if (!folds.empty()) {
+    TTNN_REQUIRE(fblocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+    StagingLock lock;
+    const ReduceTask* d =
+        static_cast<const ReduceTask*>(stage_descriptors(folds.data(), folds.size() * sizeof(ReduceTask), st));
+    hipLaunchKernelGGL(fold_batched_kernel, dim3(static_cast<unsigned>(fblocks)), dim3(256), 0, st, d,
+                       static_cast<int>(folds.size()));
+    fence_descriptors(st);
+  }
   TTNN_REQUIRE(blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
   StagingLock lock;
   const ReduceTask* d =
@@ -398,11 +452,20 @@ void launch_reduce_batched(const std::vector<ReduceTask>& in, hipStream_t st) {
   fence_descriptors(st);
 }
 
-void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
+void launch_reduce(double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
                    const IndexMap& rmap, int64_t ldr, double* dst, int64_t L, int64_t kdim, hipStream_t st) {
   if (rows <= 0 || ncols <= 0) return;
-  hipLaunchKernelGGL(reduce_kernel, dim3(grid_for(rows * ncols)), dim3(256), 0, st, part, nchunks, rows, ncols,
-                     mode, alpha, rmap, ldr, dst, L, kdim);
+  const int64_t E = rows * ncols;
+  int64_t stride = E;
+  if (fold_pays(nchunks, E)) {
+    const int groups = (nchunks + kFold - 1) / kFold;
+    hipLaunchKernelGGL(fold_chunks_kernel, dim3(static_cast<unsigned>((E + 255) / 256), groups), dim3(256), 0, st,
+                       part, nchunks, E);
+    nchunks = groups;
+    stride = E * kFold;
+  }
+  hipLaunchKernelGGL(reduce_kernel, dim3(grid_for(E)), dim3(256), 0, st, part, nchunks, rows, ncols, mode, alpha,
+                     rmap, ldr, dst, L, kdim, stride);
 }
 
 void launch_zero(double* p, int64_t n, hipStream_t st) {

@@ -59,13 +59,14 @@ struct GemmTask {
   int32_t ncols, pad_;
 };
 struct ReduceTask {
-  const double* part = nullptr;
+  double* part = nullptr;
   double* dst = nullptr;
   int64_t rows = 0, ldr = 0, L = 1, kdim = 1;
   double alpha = 1.0;
   IndexMap rmap;
   int64_t first_block = 0, nblocks = 0;
-  int32_t nchunks = 0, ncols = 0, mode = 0, pad_ = 0;
+  int64_t cstride = 0;                     // distance between chunk partials (0: rows * ncols)
+  int32_t nchunks = 0, ncols = 0, mode = 0, groups = 0;
 };
 // Launch the same kind of generic contraction (right/left, dtypes, output type) for
 // every element of `args` in one kernel: each workgroup serves one tile of one task.
@@ -91,7 +92,9 @@ struct StagingLock {
 //   mode 0 (RIGHT accumulate): dst[rmap(row) + ldr*j] += alpha * s
 //   mode 1 (LEFT  accumulate): dst[(row % L) + L*(j + kdim*(row / L))] += alpha * s
 //   mode 2 (LEFT  store)     : dst[(row % L) + L*(j + kdim*(row / L))]  = s
-void launch_reduce(const double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
+// With many chunks and few elements the partials are first folded in place (groups of
+// consecutive chunks, fixed order), so `part` is overwritten.
+void launch_reduce(double* part, int nchunks, int64_t rows, int ncols, int mode, double alpha,
                    const IndexMap& rmap, int64_t ldr, double* dst, int64_t L, int64_t kdim,
                    hipStream_t stream);
 
@@ -145,6 +148,19 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
 // R[i + n j] += alpha * ku(i) * (w ? w[j] : 1), R column-major n x ncols.
 void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const double* w, double alpha,
                       hipStream_t stream);
+
+// ---------------------------------------------------------------- whole-tensor right sketch on MFMA
+// H (dtype dt) viewed as [L][n][Q] (l fastest); Xt is the transposed DRM copy (r x m,
+// m = L Q, contraction index contiguous).  Writes FP64 chunk partials
+// part[(c n + i) r + j] and returns the number of chunks (sum them with launch_reduce).
+bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt);
+int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
+                      double* part, size_t part_elems, hipStream_t stream);
+
+// out[i0 + d0 (i1 + d1 i2)] = round_dt(src[i0 s0 + i1 s1 + i2 s2]) where the coordinate
+// `cdim` is below `lim`, else 0 (layout copies of the DRMs, rounded like the compute copies).
+void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, int64_t d2, int64_t s0, int64_t s1,
+                 int64_t s2, int cdim, int64_t lim, hipStream_t stream);
 
 // ---------------------------------------------------------------- small utilities
 void launch_zero(double* p, int64_t n, hipStream_t stream);

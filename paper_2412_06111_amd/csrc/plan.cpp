@@ -232,8 +232,26 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
   const char* nf = std::getenv("TTNN_DISABLE_FUSED");
   P->allow_fused = !(nf && nf[0] == '1');
+  // transposed DRM copies for whole-tensor right sketches on MFMA (large tensors only,
+  // nodes sketched on the raw tensor that the fused kernel does not cover)
+  auto plan_xt = [&](bool fill) {
+    if (P->N < (int64_t(1) << 22)) return;
+    const FusedT4& F = P->fused;
+    for (int v = 1; v < nn; ++v) {
+      Node& nd = P->nodes[v];
+      if (!nd.S.empty()) continue;
+      if (F.enabled && (v == F.node_A || v == F.node_1 || v == (F.tt ? F.node_B : F.node_2))) continue;
+      int64_t L = 1;
+      for (int mu = 0; mu < nd.first; ++mu) L *= P->dims[mu];
+      int64_t n = nd.n, Q = nd.m / (L > 0 ? L : 1);
+      if (!right_mfma_eligible(L, n, Q, nd.r, P->dtype)) continue;
+      nd.Xt = P->alloc(dtype_size(P->dtype) * nd.m * nd.r);
+      if (fill) copy_layout(nd.X64, nd.Xt, P->dtype, nd.m, nd.r, 1, nd.r, 1, 0, 0, nd.m, stream);
+    }
+  };
   if (dry) {
     if (P->allow_fused) fused_prepare(*P, stream);   // sizes its buffers only
+    plan_xt(false);
     return P;
   }
 
@@ -249,6 +267,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     launch_drm(nd.n, nd.k, P->seed, ty, nd.Y64, y32, y16, stream);
   }
   if (P->allow_fused) fused_prepare(*P, stream);
+  plan_xt(true);
   zero_accumulators(*P, stream);
   TTNN_HIP(hipGetLastError());
   return P;

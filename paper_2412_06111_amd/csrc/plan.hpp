@@ -27,6 +27,7 @@ struct Node {
   // device memory (views into the plan's allocations)
   double* X64 = nullptr;       // m x r row-major
   void* Xc = nullptr;          // compute-dtype copy (== X64 for FP64 plans)
+  void* Xt = nullptr;          // transposed compute-dtype copy (r x m) for whole-tensor MFMA sketches
   double* Y64 = nullptr;       // n x k row-major
   void* Yc = nullptr;
   double* R = nullptr;         // n x r column-major FP64 accumulator
@@ -41,9 +42,10 @@ struct FusedT4 {
   bool enabled = false;
   int R = 0, KP = 0, k = 0, B2 = 0, SC = 0, TA = 0, TB = 0, CB = 0;
   int64_t n2 = 0, nA = 0, nB = 0;
-  int node_A = -1, node_1 = -1, node_2 = -1;
-  void *XA = nullptr, *X1 = nullptr, *YA = nullptr, *Y1 = nullptr, *X2 = nullptr;
-  void *PRA = nullptr, *PZA = nullptr, *PR1 = nullptr, *PR2 = nullptr;
+  int node_A = -1, node_1 = -1, node_2 = -1, node_B = -1;
+  bool tt = false;                         // TTNN mode: R_B instead of the R_2 chain
+  void *XA = nullptr, *X1 = nullptr, *YA = nullptr, *Y1 = nullptr, *X2 = nullptr, *XB = nullptr;
+  void *PRA = nullptr, *PZA = nullptr, *PR1 = nullptr, *PR2 = nullptr, *PRB = nullptr;
 };
 
 struct Plan {
