@@ -40,46 +40,62 @@ struct SttnnArgs {
   void *PRA, *PZA, *PR1, *PR2, *PRB;
 };
 
+// Wide fragment: V = 16 / sizeof(T) consecutive contraction values of one lane (one
+// 16-byte load).  A 16 x 16 MFMA step takes KPL of them per lane group (BF16: all 8;
+// FP32 / FP64: one), so a wide load feeds SUB = V / KPL MFMAs; sub-step s of every
+// operand uses value s, and the SUB steps together cover the 4 V contraction values
+// of the lane groups.  Every operand is laid out with the contraction index
+// contiguous, in global memory and in LDS.
 template <typename P>
-__device__ inline typename P::Frag frag_contig(const typename P::T* p) {
-  if constexpr (P::KPL == 8) return P::load8(p);
-  else return *p;
-}
+struct Wide {
+  using T = typename P::T;
+  static constexpr int V = 16 / P::ESZ;
+  static constexpr int SUB = V / P::KPL;
+  static constexpr int KG = 4 * V;            // contraction values per wide step
+  typedef T vec __attribute__((ext_vector_type(V)));
+  __device__ static inline vec load(const T* p) { return *reinterpret_cast<const vec*>(p); }
+  __device__ static inline typename P::Frag frag(const vec& w, int s) {
+    if constexpr (P::KPL == 8) {
+      (void)s;
+      return __builtin_bit_cast(typename P::Frag, w);
+    } else {
+      return w[s];
+    }
+  }
+};
 
 // LDS plan of the kernel: the slab of T and the DRM rows of one sub-tile are copied
 // straight from global memory into one of two LDS stages (global_load_lds, 16 bytes
 // per lane) while the other stage is being consumed.  Operands that do not fit the
-// budget are read from global memory (L2) instead.
+// budget are read from global memory (L2) instead.  Rows are padded by 16 bytes.
 template <int DT, int R, int KP, int B2, int SC, bool TT>
 struct SttnnLayout {
   using P = Pol<DT>;
   using T = typename P::T;
   static constexpr int ESZ = P::ESZ;
-  static constexpr int KPL = P::KPL;
   static constexpr int PADE = 16 / ESZ;                       // one 16-byte vector of padding
   static constexpr int S = N1 + PADE;                         // slab column stride
-  static constexpr int SY = (KPL == 8) ? N1 + PADE : KP;      // row stride of staged Y_A blocks
-  static constexpr int SXB = (KPL == 8) ? N1 + PADE : R;      // row stride of staged X_B blocks (TT)
-  static constexpr int SX = (KPL == 8) ? SC + PADE : R;       // row stride of staged X blocks
-  static constexpr int YROWS = (KPL == 8) ? KP : N1;
-  static constexpr int XBROWS = (KPL == 8) ? R : N1;
-  static constexpr int XROWS = (KPL == 8) ? R : SC;
+  static constexpr int SY = N1 + PADE;                        // row stride of staged Y_A / Y_1 / X_B rows
+  static constexpr int SXB = SY;
+  static constexpr int SX = SC + PADE;                        // row stride of staged X_A / X_1 rows
   static constexpr size_t MS = size_t(SC) * S * ESZ;
   static constexpr size_t Z1 = TT ? 0 : size_t(B2) * KP * SC * ESZ;
-  static constexpr size_t YB = size_t(YROWS) * SY * ESZ + (TT ? size_t(XBROWS) * SXB * ESZ : 0);
-  static constexpr size_t XB = size_t(XROWS) * SX * ESZ;
+  static constexpr size_t YAB = size_t(KP) * SY * ESZ;
+  static constexpr size_t YB = YAB + (TT ? size_t(R) * SXB * ESZ : 0);
+  static constexpr size_t XB = size_t(R) * SX * ESZ;
   static constexpr size_t BUDGET = 156 * 1024;
   static constexpr bool STAGE_YA = 2 * (MS + YB) + Z1 <= BUDGET;
   static constexpr bool STAGE_X = STAGE_YA && 2 * (MS + YB + 2 * XB) + Z1 <= BUDGET;
   static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
-  static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + YB <= BUDGET;
+  static constexpr size_t Y1B = size_t(KP) * SY * ESZ;
+  static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + Y1B <= BUDGET;
   static constexpr size_t OFF_YA = MS;                         // offsets within a stage
-  static constexpr size_t OFF_XB = OFF_YA + size_t(YROWS) * SY * ESZ;   // TT: X_B rows after Y_A rows
+  static constexpr size_t OFF_XB = OFF_YA + YAB;               // TT: X_B rows after Y_A rows
   static constexpr size_t OFF_XA = OFF_YA + (STAGE_YA ? YB : 0);
   static constexpr size_t OFF_X1 = OFF_XA + (STAGE_X ? XB : 0);
   static constexpr size_t OFF_Z1 = 2 * STAGE;                 // after both stages
   static constexpr size_t OFF_Y1 = OFF_Z1 + Z1;
-  static constexpr size_t TOTAL = OFF_Y1 + (STAGE_Y1 ? YB : 0);
+  static constexpr size_t TOTAL = OFF_Y1 + (STAGE_Y1 ? Y1B : 0);
 };
 
 constexpr int kThreadsF = 512;
@@ -103,16 +119,6 @@ __device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int ls, int ro
   }
 }
 
-// Copy `vecs` contiguous 16-byte vectors from g to l, 64 per instruction, dealt to waves.
-template <typename T>
-__device__ inline void lds_dma_contig(const T* g, T* l, int vecs, int wave, int lane) {
-  constexpr int EV = 16 / sizeof(T);
-  for (int c0 = wave * 64; c0 < vecs; c0 += kThreadsF) {
-    if (lane < vecs - c0) lds_dma16(g + static_cast<int64_t>(c0 + lane) * EV, l + c0 * EV);
-  }
-}
-
-
 // Issue the copies of the sub-tile (slab i2, columns col0 .. col0+SC-1) into one stage.
 template <int DT, int R, int KP, int B2, int SC, bool TT>
 __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int64_t col0, int wave, int lane) {
@@ -124,50 +130,40 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
   lds_dma_rows(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), Lay::S, SC, N1 / EV,
                wave, lane);
   if constexpr (Lay::STAGE_YA) {
-    const T* YA = static_cast<const T*>(a.YA);
-    T* ys = reinterpret_cast<T*>(sb + Lay::OFF_YA);
-    if constexpr (P::KPL == 8) lds_dma_rows(YA + i2 * N1, nA, ys, Lay::SY, KP, N1 / EV, wave, lane);
-    else lds_dma_contig(YA + i2 * N1 * KP, ys, N1 * KP / EV, wave, lane);
-    if constexpr (TT) {
-      const T* XB = static_cast<const T*>(a.XB);
-      T* xb = reinterpret_cast<T*>(sb + Lay::OFF_XB);
-      if constexpr (P::KPL == 8) lds_dma_rows(XB + i2 * N1, nA, xb, Lay::SXB, R, N1 / EV, wave, lane);
-      else lds_dma_contig(XB + i2 * N1 * R, xb, N1 * R / EV, wave, lane);
-    }
+    lds_dma_rows(static_cast<const T*>(a.YA) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_YA), Lay::SY, KP,
+                 N1 / EV, wave, lane);
+    if constexpr (TT)
+      lds_dma_rows(static_cast<const T*>(a.XB) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_XB), Lay::SXB, R,
+                   N1 / EV, wave, lane);
   }
   if constexpr (Lay::STAGE_X) {
-    const T* XA = static_cast<const T*>(a.XA);
-    const T* X1 = static_cast<const T*>(a.X1);
-    T* xa = reinterpret_cast<T*>(sb + Lay::OFF_XA);
-    T* x1 = reinterpret_cast<T*>(sb + Lay::OFF_X1);
-    if constexpr (P::KPL == 8) {
-      lds_dma_rows(XA + col0, nB, xa, Lay::SX, R, SC / EV, wave, lane);
-      lds_dma_rows(X1 + i2 * nB + col0, n2 * nB, x1, Lay::SX, R, SC / EV, wave, lane);
-    } else {
-      lds_dma_contig(XA + col0 * R, xa, SC * R / EV, wave, lane);
-      lds_dma_rows(X1 + (i2 + n2 * col0) * R, n2 * R, x1, R, SC, R / EV, wave, lane);
-    }
+    lds_dma_rows(static_cast<const T*>(a.XA) + col0, nB, reinterpret_cast<T*>(sb + Lay::OFF_XA), Lay::SX, R, SC / EV,
+                 wave, lane);
+    lds_dma_rows(static_cast<const T*>(a.X1) + i2 * nB + col0, n2 * nB, reinterpret_cast<T*>(sb + Lay::OFF_X1),
+                 Lay::SX, R, SC / EV, wave, lane);
   }
 }
 
 template <int DT, int R, int KP, int B2, int SC, bool TT>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
+  using W = Wide<P>;
   using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
   using T = typename P::T;
   using Acc = typename P::Acc;
-  using Frag = typename P::Frag;
   using CFrag = typename P::CFrag;
-  constexpr int KPL = P::KPL, KSTEP = P::KSTEP, ESZ = P::ESZ;
-  constexpr int EV = 16 / ESZ;              // elements per 16-byte vector
+  using vec = typename W::vec;
+  constexpr int V = W::V, SUB = W::SUB, KG = W::KG;
+  constexpr int EV = 16 / P::ESZ;           // elements per 16-byte vector
   constexpr int S = Lay::S, SY = Lay::SY, SX = Lay::SX;
   constexpr int CBR = R / 16;               // 16-wide column blocks of an R-wide output
   constexpr int KB = KP / 16;               // 16-row blocks of KP
+  constexpr int KBB = R / 16;               // TT: 16-row blocks of R_B^T
   constexpr int NCB = SC / 16;              // 16-wide column blocks of a sub-tile
   static_assert(NCB == 4 || NCB == 2, "sub-tile width");
   constexpr int KT = KP * SC;               // (d2) contraction length per column sub-block
   constexpr int KW = KT / 8;                // per wave
-  static_assert(KW % KSTEP == 0, "(d2) split");
+  static_assert(KW % KG == 0 && SC % KG == 0 && N1 % KG == 0, "wide steps");
   static_assert(Lay::TOTAL <= 160 * 1024, "LDS budget");
   static_assert(8 * 16 * R * sizeof(Acc) <= Lay::TOTAL, "reduction scratch");
 
@@ -193,12 +189,12 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   }
   const int64_t i2_0 = static_cast<int64_t>(tA) * B2;
   const int64_t c_tile = static_cast<int64_t>(tB) * a.CB * SC;
-  const T* Tg = static_cast<const T*>(a.T);
   const T* XA = static_cast<const T*>(a.XA);
   const T* X1 = static_cast<const T*>(a.X1);
   const T* YA = static_cast<const T*>(a.YA);
   const T* Y1 = static_cast<const T*>(a.Y1);
   const T* X2 = static_cast<const T*>(a.X2);
+  const T* XB = static_cast<const T*>(a.XB);
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
 
   auto stage_base = [&](int buf) -> char* { return smem + buf * Lay::STAGE; };
@@ -209,13 +205,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
                                        wave, lane);
   };
   // Y_1 rows, resident for the whole kernel
-  if constexpr (Lay::STAGE_Y1) {
-    if constexpr (KPL == 8) lds_dma_rows(Y1, N1, Y1s, SY, KP, N1 / EV, wave, lane);
-    else lds_dma_contig(Y1, Y1s, N1 * KP / EV, wave, lane);
-  }
+  if constexpr (Lay::STAGE_Y1) lds_dma_rows(Y1, N1, Y1s, SY, KP, N1 / EV, wave, lane);
 
-  constexpr int KBB = R / 16;               // TT: 16-row blocks of R_B^T
-  const T* XB = static_cast<const T*>(a.XB);
   CFrag rA[B2][CBR];
   CFrag r1[CBR];
   CFrag r2[CBR];
@@ -231,10 +222,12 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     r1[c] = zero;
     r2[c] = zero;
   }
-  // roles in the (b)/(d1) phase: Z_A or Z1 for one 16-column block of the sub-tile
+  // roles in the (b)/(d1) phase: Z_A, or Z1 (STTNN) / R_B^T (TTNN), for one 16-column
+  // block of the sub-tile
   const bool bd_active = wave < 2 * NCB;
   const int cblk = wave % NCB;
   const bool bd_zA = (wave / NCB) == 0;
+  const int iBl = 16 * cblk + l16;         // column of the sub-tile in the (b)/(d1) phase
 
   const int nsub = a.CB * B2;
   issue(0, 0);
@@ -257,114 +250,96 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       if (s + 1 < nsub) issue(s + 1, buf ^ 1);
       const T* Ms = reinterpret_cast<const T*>(stage_base(buf));
       const T* YAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
+      const T* XBs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
       const T* XAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XA);
       const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
-      const T* XBs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
 
       // (a) R_A rows of this slab and (c) R_1: A = slab (rows i1, K = columns)
       const int i1 = 16 * wave + l16;
-#pragma unroll 4
-      for (int ks = 0; ks < SC / KSTEP; ++ks) {
-        const int kk = ks * KSTEP + KPL * lg;
-        Frag af;
-        if constexpr (KPL == 8) {
-          u16x8_t v;
 #pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = Ms[(kk + e) * S + i1];
-          af = __builtin_bit_cast(Frag, v);
-        } else {
-          af = Ms[kk * S + i1];
-        }
+      for (int kw = 0; kw < SC / KG; ++kw) {
+        const int kk = kw * KG + V * lg;
+        vec aw;
+#pragma unroll
+        for (int e = 0; e < V; ++e) aw[e] = Ms[(kk + e) * S + i1];
+        vec bA[CBR], b1[CBR];
 #pragma unroll
         for (int c = 0; c < CBR; ++c) {
           const int j = 16 * c + l16;
-          Frag bA, b1;
           if constexpr (Lay::STAGE_X) {
-            if constexpr (KPL == 8) {
-              bA = P::load8(XAs + j * SX + kk);
-              b1 = P::load8(X1s + j * SX + kk);
-            } else {
-              bA = XAs[kk * R + j];
-              b1 = X1s[kk * R + j];
-            }
+            bA[c] = W::load(XAs + j * SX + kk);
+            b1[c] = W::load(X1s + j * SX + kk);
           } else {
-            if constexpr (KPL == 8) {
-              bA = P::load8(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
-              b1 = P::load8(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
-            } else {
-              bA = XA[(iBbase + kk) * R + j];
-              b1 = X1[(i2 + n2 * (iBbase + kk)) * R + j];
-            }
+            bA[c] = W::load(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
+            b1[c] = W::load(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
           }
-          rA[i2l][c] = P::mfma(af, bA, rA[i2l][c]);
-          r1[c] = P::mfma(af, b1, r1[c]);
+        }
+#pragma unroll
+        for (int sb = 0; sb < SUB; ++sb) {
+          const auto af = W::frag(aw, sb);
+#pragma unroll
+          for (int c = 0; c < CBR; ++c) {
+            rA[i2l][c] = P::mfma(af, W::frag(bA[c], sb), rA[i2l][c]);
+            r1[c] = P::mfma(af, W::frag(b1[c], sb), r1[c]);
+          }
         }
       }
 
-      // (b) Z_A += Y_A^T slab or (d1) Z1 = Y_1^T slab: B = slab (K = i1, columns)
+      // (b) Z_A += Y_A^T slab; (b') TTNN: R_B^T += X_B^T slab; (d1) STTNN: Z1 = Y_1^T slab.
+      // B = slab (K = i1, columns)
       if (bd_active && bd_zA) {
-        const int iBl = 16 * cblk + l16;
-#pragma unroll 4
-        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
-          const int kk = ks * KSTEP + KPL * lg;
-          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll 2
+        for (int kw = 0; kw < N1 / KG; ++kw) {
+          const int kk = kw * KG + V * lg;
+          const vec bw = W::load(&Ms[iBl * S + kk]);
+          vec ay[KB];
 #pragma unroll
           for (int rb = 0; rb < KB; ++rb) {
             const int jr = 16 * rb + l16;
-            Frag ay;
-            if constexpr (Lay::STAGE_YA) {
-              if constexpr (KPL == 8) ay = P::load8(YAs + jr * SY + kk);
-              else ay = YAs[kk * SY + jr];
-            } else {
-              if constexpr (KPL == 8) ay = P::load8(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
-              else ay = YA[(i2 * N1 + kk) * KP + jr];
-            }
-            zA[rb] = P::mfma(ay, bM, zA[rb]);
+            if constexpr (Lay::STAGE_YA) ay[rb] = W::load(YAs + jr * SY + kk);
+            else ay[rb] = W::load(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
+#pragma unroll
+          for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+            for (int rb = 0; rb < KB; ++rb) zA[rb] = P::mfma(W::frag(ay[rb], sb), W::frag(bw, sb), zA[rb]);
         }
       } else if (TT && bd_active) {
-        // (b') R_B^T += X_B^T slab
-        const int iBl = 16 * cblk + l16;
-#pragma unroll 4
-        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
-          const int kk = ks * KSTEP + KPL * lg;
-          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll 2
+        for (int kw = 0; kw < N1 / KG; ++kw) {
+          const int kk = kw * KG + V * lg;
+          const vec bw = W::load(&Ms[iBl * S + kk]);
+          vec ax[KBB];
 #pragma unroll
           for (int rb = 0; rb < KBB; ++rb) {
             const int jr = 16 * rb + l16;
-            Frag ax;
-            if constexpr (Lay::STAGE_YA) {
-              if constexpr (KPL == 8) ax = P::load8(XBs + jr * Lay::SXB + kk);
-              else ax = XBs[kk * Lay::SXB + jr];
-            } else {
-              if constexpr (KPL == 8) ax = P::load8(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
-              else ax = XB[(i2 * N1 + kk) * R + jr];
-            }
-            zB[rb] = P::mfma(ax, bM, zB[rb]);
+            if constexpr (Lay::STAGE_YA) ax[rb] = W::load(XBs + jr * Lay::SXB + kk);
+            else ax[rb] = W::load(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
+#pragma unroll
+          for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+            for (int rb = 0; rb < KBB; ++rb) zB[rb] = P::mfma(W::frag(ax[rb], sb), W::frag(bw, sb), zB[rb]);
         }
       } else if (!TT && bd_active) {
-        const int iBl = 16 * cblk + l16;
         CFrag acc[KB];
 #pragma unroll
         for (int rb = 0; rb < KB; ++rb) acc[rb] = zero;
-#pragma unroll 4
-        for (int ks = 0; ks < N1 / KSTEP; ++ks) {
-          const int kk = ks * KSTEP + KPL * lg;
-          const Frag bM = frag_contig<P>(&Ms[iBl * S + kk]);
+#pragma unroll 2
+        for (int kw = 0; kw < N1 / KG; ++kw) {
+          const int kk = kw * KG + V * lg;
+          const vec bw = W::load(&Ms[iBl * S + kk]);
+          vec ay[KB];
 #pragma unroll
           for (int rb = 0; rb < KB; ++rb) {
             const int jr = 16 * rb + l16;
-            Frag ay;
-            if constexpr (Lay::STAGE_Y1) {
-              if constexpr (KPL == 8) ay = P::load8(Y1s + jr * SY + kk);
-              else ay = Y1s[kk * SY + jr];
-            } else {
-              if constexpr (KPL == 8) ay = P::load8(Y1 + static_cast<int64_t>(jr) * N1 + kk);
-              else ay = Y1[kk * KP + jr];
-            }
-            acc[rb] = P::mfma(ay, bM, acc[rb]);
+            if constexpr (Lay::STAGE_Y1) ay[rb] = W::load(Y1s + jr * SY + kk);
+            else ay[rb] = W::load(Y1 + static_cast<int64_t>(jr) * N1 + kk);
           }
+#pragma unroll
+          for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+            for (int rb = 0; rb < KB; ++rb) acc[rb] = P::mfma(W::frag(ay[rb], sb), W::frag(bw, sb), acc[rb]);
         }
 #pragma unroll
         for (int rb = 0; rb < KB; ++rb)
@@ -375,30 +350,32 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           }
       }
     }  // i2l
-    if constexpr (!TT) __syncthreads();
-
-    // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (j1, column)) . X_2 rows (j1 + k column)
-#pragma unroll 2
-    for (int ks = 0; ks < (TT ? 0 : KW / KSTEP); ++ks) {
-      const int K = wave * KW + ks * KSTEP + KPL * lg;
-      Frag az;
-      if (l16 < B2) az = frag_contig<P>(&Z1s[l16 * KT + K]);
-      else az = Frag{};
-      const int iBl = K / KP, j1 = K % KP;
+    if constexpr (!TT) {
+      __syncthreads();
+      // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1)
+#pragma unroll 4
+      for (int kw = 0; kw < KW / KG; ++kw) {
+        const int K = wave * KW + kw * KG + V * lg;
+        vec azw;
+        if (l16 < B2) azw = W::load(&Z1s[l16 * KT + K]);
+        else azw = vec{};
+        vec bx[CBR];
 #pragma unroll
-      for (int c = 0; c < CBR; ++c) {
-        const int j = 16 * c + l16;
-        Frag bx;
-        if constexpr (KPL == 8) bx = P::load8(X2 + (static_cast<int64_t>(j) * nB + iBbase + iBl) * KP + j1);
-        else bx = X2[((iBbase + iBl) * KP + j1) * R + j];
-        r2[c] = P::mfma(az, bx, r2[c]);
+        for (int c = 0; c < CBR; ++c) {
+          const int j = 16 * c + l16;
+          bx[c] = W::load(X2 + (static_cast<int64_t>(j) * nB + iBbase) * KP + K);
+        }
+#pragma unroll
+        for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+          for (int c = 0; c < CBR; ++c) r2[c] = P::mfma(W::frag(azw, sb), W::frag(bx[c], sb), r2[c]);
       }
     }
 
-    // Z_A partial of this tile's row range for the sub-block's columns
+    // Z_A (and TTNN R_B^T) partials of this tile's row range for the sub-block's columns
     if (bd_active && bd_zA) {
       Acc* PZA = static_cast<Acc*>(a.PZA);
-      const int64_t iB = iBbase + 16 * cblk + l16;
+      const int64_t iB = iBbase + iBl;
 #pragma unroll
       for (int rb = 0; rb < KB; ++rb)
 #pragma unroll
@@ -410,7 +387,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     if constexpr (TT) {
       if (bd_active && !bd_zA) {
         Acc* PRB = static_cast<Acc*>(a.PRB);
-        const int64_t iB = iBbase + 16 * cblk + l16;
+        const int64_t iB = iBbase + iBl;
 #pragma unroll
         for (int rb = 0; rb < KBB; ++rb)
 #pragma unroll
@@ -548,19 +525,21 @@ struct Shape {
   int B2, SC;
 };
 
+// Tile shape per dtype: B2 slabs of i_2 per tile, SC columns per sub-tile (sized so
+// that the slab, the DRM rows of a sub-tile and the Z1 stash fit the LDS budget).
 template <int DT, int R>
 constexpr int b2_of() {
-  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : (R >= 64 ? 2 : 4);
+  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : 2;
 }
 template <int DT>
 constexpr int sc_of() {
-  return DT == TTNN_F64 ? 32 : 64;
+  return DT == TTNN_BF16 ? 64 : 32;
 }
 
 Shape shape_for(int dt, int R) {
   if (dt == TTNN_BF16) return {R >= 64 ? 4 : 8, 64};
-  if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 64};
-  return {R >= 64 ? 2 : 4, 32};
+  if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 32};
+  return {2, 32};
 }
 
 template <int DT, int R, int KP>
@@ -637,7 +616,6 @@ void fused_prepare(Plan& P, hipStream_t st) {
 
   const int dt = P.dtype;
   const int64_t es = elem_size(dt);
-  const bool k8 = dt == TTNN_BF16;
   // DRM copies in the fragment layouts of the kernel (values rounded like the compute copies)
   F.XA = P.alloc(es * nB * R);
   F.X1 = P.alloc(es * nAs / N1 * nB * R);
@@ -651,9 +629,8 @@ void fused_prepare(Plan& P, hipStream_t st) {
   const Node& NA = P.nodes[A];
   const double* XB64 = P.nodes[F.node_B].X64;
   const int k = nA_.k;
-  if (P.dry) {
-    // sizing only
-  } else if (k8) {
+  // contraction index contiguous for every dtype
+  if (!P.dry) {
     copy_layout(NA.X64, F.XA, dt, nB, R, 1, R, 1, 0, 0, nB, st);                     // [j][iB]
     copy_layout(L1.X64, F.X1, dt, nB, n2, R, n2 * R, R, 1, 0, nB, st);               // [j][i2][iB]
     copy_layout(NA.Y64, F.YA, dt, nAs, KP, 1, k, 1, 0, 1, k, st);                    // [jA][iA]
@@ -662,16 +639,6 @@ void fused_prepare(Plan& P, hipStream_t st) {
     } else {
       copy_layout(L1.Y64, F.Y1, dt, N1, KP, 1, k, 1, 0, 1, k, st);                   // [j1][i1]
       copy_layout(L2.X64, F.X2, dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
-    }
-  } else {
-    copy_layout(NA.X64, F.XA, dt, R, nB, 1, 1, R, 0, 0, R, st);                      // [iB][j]
-    copy_layout(L1.X64, F.X1, dt, R, nAs / N1 * nB, 1, 1, R, 0, 0, R, st);           // rows (i2 + n2 iB)
-    copy_layout(NA.Y64, F.YA, dt, KP, nAs, 1, 1, k, 0, 0, k, st);                    // [iA][jA]
-    if (tt) {
-      copy_layout(XB64, F.XB, dt, R, nAs, 1, 1, R, 0, 0, R, st);                     // [iA][j]
-    } else {
-      copy_layout(L1.Y64, F.Y1, dt, KP, N1, 1, 1, k, 0, 0, k, st);                   // [i1][j1]
-      copy_layout(L2.X64, F.X2, dt, R, KP, nB, 1, R, static_cast<int64_t>(k) * R, 1, k, st);  // [iB][j1][j]
     }
   }
   const int64_t as = dt == TTNN_F64 ? 8 : 4;
