@@ -121,6 +121,25 @@ def sweep_counts(tree, variant, dtype):
     return kflops, N * s + drm_k * s + out * acc
 
 
+def measured_traffic(key):
+    """HBM bytes per launch of the fused sweep kernel, from the rocprofv3 FETCH_SIZE /
+    WRITE_SIZE runs summarised under profiles/ (scaled by a plain 1 GiB copy), if the
+    kernel sources still hash to what was measured; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sttnn_t4_kernel_traffic.json")
+    if not key.startswith("sttnn:") or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for name in rec["sources"]:
+        with open(os.path.join(ROOT, "paper_2412_06111_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != rec["hash"] or key not in rec["traffic"]:
+        return None
+    return rec["traffic"][key]["bytes"]
+
+
 def copy_rate(nbytes=1 << 30, reps=10):
     """A plain device-to-device copy of known size: the calibration kernel for the
     HBM byte counters and a measured streaming ceiling (read + write bytes / time)."""
@@ -370,7 +389,7 @@ def main():
             r["roofline"] = {"bound": "hbm", "achieved": r["sweep_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         r["roofline"]["frac"] = r["roofline"]["achieved"] / r["roofline"]["peak"]
     roof = dict(head["roofline"])
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(key)
     roof["kernel"] = (("sttnn_t4_kernel (one-pass STTNN sweep)" if hv == "sttnn" else "whole TTNN update")
                       + f", {hd}, {args.n}^4, r={args.rank}, p={args.over}; HIP events on the launch stream")
     roof["algorithmic_bytes_per_launch"] = head["sweep_algorithmic_bytes"]
