@@ -123,3 +123,27 @@ def test_sketch_box_equals_zero_padded(spec, dims, variant):
     for t in full["R"]:
         assert rel(box["R"][t], full["R"][t]) < 1e-13
     assert rel(box["Psi_root"], full["Psi"][0]) < 1e-13
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("spec,dims", [(O.T4, (5, 4, 3, 6)), (O.T5, (3, 4, 2, 3, 4)), (O.TOY, (2, 3, 2, 3, 2, 2))])
+def test_sampled_entries_match_full_sketch(spec, dims, variant):
+    """The one-entry evaluator used for full-size GPU checks equals the full oracle sketch."""
+    from oracle.sampled import right_entry, root_entry
+    T = np.random.default_rng(3).standard_normal(dims)
+    tree = O.Tree(spec, dims, 3, 2)
+    sk = O.sketch(T, tree, O.DRMs(tree, 9, variant), variant)
+    g = np.random.default_rng(4)
+    for n in tree.nodes[1:]:
+        ext = [dims[m - 1] for m in n.modes]
+        for _ in range(3):
+            im = [int(g.integers(e)) for e in ext]
+            j = int(g.integers(n.rank))
+            i = int(np.ravel_multi_index(im, ext, order="F"))
+            want = sk["R"][n.id][i, j]
+            assert abs(right_entry(T, tree, 9, variant, n.id, im, j) - want) <= 1e-12 * (1 + abs(want))
+    kk = [tree[c].k for c in tree[0].children]
+    for _ in range(3):
+        km = [int(g.integers(k)) for k in kk]
+        want = sk["Psi"][0][int(np.ravel_multi_index(km, kk, order="F"))]
+        assert abs(root_entry(T, tree, 9, km) - want) <= 1e-12 * (1 + abs(want))
