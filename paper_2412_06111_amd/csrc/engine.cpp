@@ -238,8 +238,10 @@ void size_chain_scratch(Plan& P) {
 }
 
 void zero_accumulators(Plan& P, hipStream_t st) {
-  for (size_t v = 1; v < P.nodes.size(); ++v) launch_zero(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r, st);
-  launch_zero(P.psi_root, P.psi_root_len, st);
+  SegList s;
+  for (size_t v = 1; v < P.nodes.size(); ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+  s.push(P.psi_root, P.psi_root_len);
+  launch_zero_list(s, st);
   P.epilogue_valid = false;
 }
 
@@ -636,8 +638,12 @@ ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
   const int nn = static_cast<int>(P.nodes.size());
   // finite check of the sketches
   launch_zero_int(P.d_flag, 2 * TTNN_MAX_NODES, st);
-  for (int v = 1; v < nn; ++v) launch_finite_check(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r, P.d_flag, st);
-  launch_finite_check(P.psi_root, P.psi_root_len, P.d_flag, st);
+  {
+    SegList s;
+    for (int v = 1; v < nn; ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+    s.push(P.psi_root, P.psi_root_len);
+    launch_finite_list(s, P.d_flag, st);
+  }
 
   QrJobList jl{};
   int max_k = 1, max_r = 1;

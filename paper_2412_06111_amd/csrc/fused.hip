@@ -437,6 +437,23 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   }
 }
 
+// sum_{t < n} p[t * stride] in FP64 with four interleaved partial sums (t mod 4),
+// combined in a fixed order: four loads in flight per thread.
+template <typename Acc>
+__device__ inline double sum_strided(const Acc* p, int n, int64_t stride) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int t = 0;
+  for (; t + 4 <= n; t += 4) {
+    const Acc v0 = p[(t + 0) * stride], v1 = p[(t + 1) * stride], v2 = p[(t + 2) * stride], v3 = p[(t + 3) * stride];
+    s[0] += static_cast<double>(v0);
+    s[1] += static_cast<double>(v1);
+    s[2] += static_cast<double>(v2);
+    s[3] += static_cast<double>(v3);
+  }
+  for (int q = 0; t < n; ++t, ++q) s[q] += static_cast<double>(p[t * stride]);
+  return (s[0] + s[1]) + (s[2] + s[3]);
+}
+
 // Sum the tile partials in a fixed order into the FP64 state.  The last segment is
 // R_2 (STTNN; PR2 [tB][n2][R]) or, in TTNN mode, R_B (PRB [tA][R][nB]).
 template <typename Acc>
@@ -450,33 +467,23 @@ __global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, 
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     if (e < nRA) {
       const int64_t iA = e / R, j = e % R;
-      double s = 0.0;
-      for (int t = 0; t < TB; ++t) s += static_cast<double>(PRA[(t * nA + iA) * R + j]);
-      RA[iA + nA * j] += alpha * s;
+      RA[iA + nA * j] += alpha * sum_strided(PRA + iA * R + j, TB, nA * R);
     } else if (e < nRA + nZA) {
       const int64_t f = e - nRA;
       const int64_t jA = f / nB, iB = f % nB;
-      double s = 0.0;
-      for (int t = 0; t < TA; ++t) s += static_cast<double>(PZA[(t * static_cast<int64_t>(KP) + jA) * nB + iB]);
-      ZA[jA + k * iB] = s;
+      ZA[jA + k * iB] = sum_strided(PZA + jA * nB + iB, TA, static_cast<int64_t>(KP) * nB);
     } else if (e < nRA + nZA + nR1) {
       const int64_t f = e - nRA - nZA;
       const int64_t i1 = f / R, j = f % R;
-      double s = 0.0;
-      for (int t = 0; t < TA * TB; ++t) s += static_cast<double>(PR1[(t * static_cast<int64_t>(N1) + i1) * R + j]);
-      R1[i1 + N1 * j] += alpha * s;
+      R1[i1 + N1 * j] += alpha * sum_strided(PR1 + i1 * R + j, TA * TB, static_cast<int64_t>(N1) * R);
     } else if (!tt) {
       const int64_t f = e - nRA - nZA - nR1;
       const int64_t i2 = f / R, j = f % R;
-      double s = 0.0;
-      for (int t = 0; t < TB; ++t) s += static_cast<double>(PR2[(t * n2 + i2) * R + j]);
-      R2[i2 + n2 * j] += alpha * s;
+      R2[i2 + n2 * j] += alpha * sum_strided(PR2 + i2 * R + j, TB, n2 * R);
     } else {
       const int64_t f = e - nRA - nZA - nR1;
       const int64_t j = f / nB, c = f % nB;
-      double s = 0.0;
-      for (int t = 0; t < TA; ++t) s += static_cast<double>(PR2[(t * static_cast<int64_t>(R) + j) * nB + c]);
-      R2[c + nB * j] += alpha * s;
+      R2[c + nB * j] += alpha * sum_strided(PR2 + j * nB + c, TA, static_cast<int64_t>(R) * nB);
     }
   }
 }

@@ -325,6 +325,43 @@ __global__ void finite_kernel(const double* p, int64_t n, int* flag) {
     if (!isfinite(p[i])) *flag = 1;
 }
 
+// Block b of a list launch serves segment `seg` (blocks are dealt to segments in
+// proportion to their length, at most kSegBlocks each).
+constexpr int kSegBlocks = 512;
+__device__ inline int seg_of(const SegList& s, int b, int* first) {
+  int acc = 0;
+  for (int i = 0; i < s.count; ++i) {
+    int64_t nb = (s.n[i] + 255) / 256;
+    if (nb > kSegBlocks) nb = kSegBlocks;
+    if (nb < 1) nb = 1;
+    if (b < acc + nb) {
+      *first = acc;
+      return i;
+    }
+    acc += static_cast<int>(nb);
+  }
+  *first = acc;
+  return -1;
+}
+__global__ void zero_list_kernel(SegList s) {
+  int first = 0;
+  const int i = seg_of(s, blockIdx.x, &first);
+  if (i < 0) return;
+  int64_t nb = (s.n[i] + 255) / 256;
+  nb = nb > kSegBlocks ? kSegBlocks : (nb < 1 ? 1 : nb);
+  for (int64_t e = static_cast<int64_t>(blockIdx.x - first) * 256 + threadIdx.x; e < s.n[i]; e += nb * 256)
+    s.p[i][e] = 0.0;
+}
+__global__ void finite_list_kernel(SegList s, int* flag) {
+  int first = 0;
+  const int i = seg_of(s, blockIdx.x, &first);
+  if (i < 0) return;
+  int64_t nb = (s.n[i] + 255) / 256;
+  nb = nb > kSegBlocks ? kSegBlocks : (nb < 1 ? 1 : nb);
+  for (int64_t e = static_cast<int64_t>(blockIdx.x - first) * 256 + threadIdx.x; e < s.n[i]; e += nb * 256)
+    if (!isfinite(s.p[i][e])) *flag = 1;
+}
+
 inline bool fold_pays(int nchunks, int64_t E) { return nchunks > 2 * kFold && E < (int64_t(1) << 20); }
 
 inline int grid_for(int64_t n) {
@@ -483,6 +520,21 @@ void launch_f64_to_f32(float* y, const double* x, int64_t n, hipStream_t st) {
 void launch_zero_int(int* p, int64_t n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(zero_int_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
 }
+static int list_blocks(const SegList& s) {
+  int64_t b = 0;
+  for (int i = 0; i < s.count; ++i) {
+    int64_t nb = (s.n[i] + 255) / 256;
+    b += nb > kSegBlocks ? kSegBlocks : (nb < 1 ? 1 : nb);
+  }
+  return static_cast<int>(b);
+}
+void launch_zero_list(const SegList& s, hipStream_t st) {
+  if (s.count > 0) hipLaunchKernelGGL(zero_list_kernel, dim3(list_blocks(s)), dim3(256), 0, st, s);
+}
+void launch_finite_list(const SegList& s, int* flag, hipStream_t st) {
+  if (s.count > 0) hipLaunchKernelGGL(finite_list_kernel, dim3(list_blocks(s)), dim3(256), 0, st, s, flag);
+}
+
 void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, flag);
 }

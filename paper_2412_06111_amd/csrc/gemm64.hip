@@ -122,17 +122,35 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
   if (!last_flag) return;
   __threadfence();
   const double* parts = J.part + tile_id * J.splits * (TM * TN);
-  for (int e = tid; e < TM * TN; e += 256) {
+  // each thread combines 4 elements; 8 independent partial sums per element keep 32
+  // loads in flight; fixed combination order
+  constexpr int EPT = TM * TN / 256;
+  double s8[EPT][8];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s8[u][q] = 0.0;
+  int sp = 0;
+  for (; sp + 8 <= J.splits; sp += 8) {
+    double v[EPT][8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int u = 0; u < EPT; ++u) v[u][q] = parts[(sp + q) * (TM * TN) + tid + 256 * u];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s8[u][q] += v[u][q];
+  }
+  for (int q = 0; sp < J.splits; ++sp, ++q)
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) s8[u][q] += parts[sp * (TM * TN) + tid + 256 * u];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = tid + 256 * u;
     const int mm = e / TN, nn = e % TN;
     const int64_t m = m0 + mm, n = n0 + nn;
-    // eight independent partial sums keep eight loads in flight; fixed combination order
-    double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int sp = 0;
-    for (; sp + 8 <= J.splits; sp += 8)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s8[q] += parts[(sp + q) * (TM * TN) + e];
-    for (int q = 0; sp < J.splits; ++sp, ++q) s8[q] += parts[sp * (TM * TN) + e];
-    const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
+    const double s = ((s8[u][0] + s8[u][1]) + (s8[u][2] + s8[u][3])) + ((s8[u][4] + s8[u][5]) + (s8[u][6] + s8[u][7]));
     if (m >= J.M || n >= J.N) continue;
     double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
     *c = (J.accumulate ? *c : 0.0) + J.alpha * s;

@@ -164,6 +164,19 @@ void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, i
 
 // ---------------------------------------------------------------- small utilities
 void launch_zero(double* p, int64_t n, hipStream_t stream);
+// Several FP64 arrays in one launch: zero them, or set *flag when one holds a non-finite value.
+struct SegList {
+  double* p[TTNN_MAX_NODES + 1];
+  int64_t n[TTNN_MAX_NODES + 1];
+  int count = 0;
+  void push(double* ptr, int64_t len) {
+    p[count] = ptr;
+    n[count] = len;
+    ++count;
+  }
+};
+void launch_zero_list(const SegList& s, hipStream_t stream);
+void launch_finite_list(const SegList& s, int* flag, hipStream_t stream);
 void launch_axpy(double* y, const double* x, double alpha, int64_t n, hipStream_t stream);
 void launch_copy_f64(double* dst, const double* src, int64_t n, hipStream_t stream);
 void launch_f64_to_f32(float* dst, const double* src, int64_t n, hipStream_t stream);

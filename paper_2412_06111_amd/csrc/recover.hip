@@ -71,26 +71,30 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   for (int e = tid; e < k * r; e += kThreads) A[e] = job.Om[e];
   __syncthreads();
 
-  // ---- Householder QR (LAPACK dlarfg convention, v_0 = 1)
+  // ---- Householder QR (LAPACK dlarfg convention, v_0 = 1).  Wave 0 forms each
+  // reflector with shuffles (rows strided over its 64 lanes, fixed order); all
+  // threads apply it to the remaining columns; two barriers per column.
   for (int j = 0; j < r; ++j) {
-    double part = 0.0;
-    for (int i = j + 1 + tid; i < k; i += kThreads) part += A[i + k * j] * A[i + k * j];
-    const double xnorm2 = block_sum(part, red);
-    const double alpha = A[j + k * j];
-    double tau = 0.0, beta = alpha, scale = 0.0;
-    if (xnorm2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
-      tau = (beta - alpha) / beta;
-      scale = 1.0 / (alpha - beta);
+    if (tid < 64) {
+      double part = 0.0;
+      for (int i = j + 1 + tid; i < k; i += 64) part += A[i + k * j] * A[i + k * j];
+      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+      const double xnorm2 = part;
+      const double alpha = A[j + k * j];
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+        for (int i = j + 1 + tid; i < k; i += 64) A[i + k * j] *= scale;
+      }
+      if (tid == 0) {
+        A[j + k * j] = beta;
+        tau_s[j] = tau;
+      }
     }
     __syncthreads();
-    if (xnorm2 > 0.0)
-      for (int i = j + 1 + tid; i < k; i += kThreads) A[i + k * j] *= scale;
-    if (tid == 0) {
-      A[j + k * j] = beta;
-      tau_s[j] = tau;
-    }
-    __syncthreads();
+    const double tau = tau_s[j];
     if (tau != 0.0) apply_reflector(A, k, j, tau, A, j + 1, r);
     __syncthreads();
   }
@@ -128,14 +132,23 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
     for (int i = 0; i < r; ++i) nonsingular = nonsingular && (W[i + r * i] > 0.0);
     double inv2 = 0.0;
     if (nonsingular) {
-      for (int c = tid; c < r; c += kThreads) {     // column c of R^{-1}: R x = e_c
-        for (int i = r - 1; i >= 0; --i) {
-          double s = (i == c) ? 1.0 : 0.0;
-          for (int m = i + 1; m <= c; ++m) s -= W[i + r * m] * V[m + r * c];
-          V[i + r * c] = (i > c) ? 0.0 : s / W[i + r * i];
+      // R^{-1} by back substitution, row i = r-1 .. 0 for all columns at once:
+      // V[i][c] = (delta_ic - sum_{i<m<=c} R[i][m] V[m][c]) / R[i][i], 8 lanes per column
+      for (int e = tid; e < r * r; e += kThreads) V[e] = 0.0;
+      __syncthreads();
+      const int g = tid >> 3, sub = tid & 7;
+      for (int i = r - 1; i >= 0; --i) {
+        for (int cbase = i; cbase < r; cbase += kThreads / 8) {
+          const int c = cbase + g;
+          double sacc = 0.0;
+          if (c < r)
+            for (int m = i + 1 + sub; m <= c; m += 8) sacc += W[i + r * m] * V[m + r * c];
+          sacc = group8_sum(sacc);
+          if (c < r && sub == 0) V[i + r * c] = ((i == c ? 1.0 : 0.0) - sacc) / W[i + r * i];
         }
-        for (int i = 0; i < r; ++i) inv2 += V[i + r * c] * V[i + r * c];
+        __syncthreads();
       }
+      for (int e = tid; e < r * r; e += kThreads) inv2 += V[e] * V[e];
     }
     inv2 = block_sum(inv2, red);
     if (tid == 0) fast = nonsingular && (sqrt(rnorm2 * inv2) * eps_factor < 0.5);
