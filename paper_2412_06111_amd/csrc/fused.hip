@@ -66,18 +66,20 @@ struct Wide {
 
 // LDS plan of the kernel: the slab of T and the DRM rows of one sub-tile are copied
 // straight from global memory into one of two LDS stages (global_load_lds, 16 bytes
-// per lane) while the other stage is being consumed.  Operands that do not fit the
-// budget are read from global memory (L2) instead.  Rows are padded by 16 bytes.
+// per lane, 64 lanes = whole rows per instruction) while the other stage is being
+// consumed.  Operands that do not fit the budget are read from global memory (L2)
+// instead.  Staged rows are not padded: the 16-byte chunks of row r are stored in
+// XOR-swizzled order (chunk c at position c ^ (r mod 16, or mod the chunk count)),
+// so reads along a row and gathers down a column spread over the LDS banks.
 template <int DT, int R, int KP, int B2, int SC, bool TT>
 struct SttnnLayout {
   using P = Pol<DT>;
   using T = typename P::T;
   static constexpr int ESZ = P::ESZ;
-  static constexpr int PADE = 16 / ESZ;                       // one 16-byte vector of padding
-  static constexpr int S = N1 + PADE;                         // slab column stride
-  static constexpr int SY = N1 + PADE;                        // row stride of staged Y_A / Y_1 / X_B rows
+  static constexpr int S = N1;                                // slab column stride
+  static constexpr int SY = N1;                               // row stride of staged Y_A / Y_1 / X_B rows
   static constexpr int SXB = SY;
-  static constexpr int SX = SC + PADE;                        // row stride of staged X_A / X_1 rows
+  static constexpr int SX = SC;                               // row stride of staged X_A / X_1 rows
   static constexpr size_t MS = size_t(SC) * S * ESZ;
   static constexpr size_t Z1 = TT ? 0 : size_t(B2) * KP * SC * ESZ;
   static constexpr size_t YAB = size_t(KP) * SY * ESZ;
@@ -106,16 +108,31 @@ __device__ inline void lds_dma16(const void* g, void* l) {
   __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
 }
 
-// Copy `rows` rows of `vecs` 16-byte vectors, row r from g + r*gs to l + r*ls
-// (elements), straight into LDS; rows are dealt to the eight waves, one instruction
-// per row and 64 vectors.  The LDS address of an instruction is wave-uniform.
-template <typename T>
-__device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int ls, int rows, int vecs, int wave, int lane) {
-  constexpr int EV = 16 / sizeof(T);
-  for (int r = wave; r < rows; r += kThreadsF / 64) {
-    for (int c0 = 0; c0 < vecs; c0 += 64) {
-      if (lane < vecs - c0) lds_dma16(g + r * gs + static_cast<int64_t>(c0 + lane) * EV, l + r * ls + c0 * EV);
-    }
+// XOR swizzle of the 16-byte chunks of a staged row of RL elements: element k of
+// row r lives at r*RL + swz_off<T, RL>(r, k).
+template <typename T, int RL>
+struct Swz {
+  static constexpr int EV = 16 / sizeof(T);
+  static constexpr int CPR = RL / EV;                 // chunks per row
+  static constexpr int MASK = (CPR < 16 ? CPR : 16) - 1;
+  static_assert(CPR >= 1 && CPR <= 64 && (CPR & (CPR - 1)) == 0, "chunks per row");
+  __device__ static inline int off(int r, int k) { return r * RL + ((((k / EV) ^ (r & MASK))) * EV) + (k % EV); }
+};
+
+// Copy `rows` rows of RL elements (row r from g + r*gs) into LDS at l, swizzled:
+// each instruction fills 64 / CPR whole rows (64 lanes x 16 bytes, one contiguous
+// kilobyte of LDS); lane L fetches the chunk that belongs at its position.
+// Instructions are dealt to the eight waves; the LDS address is wave-uniform.
+template <typename T, int RL>
+__device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int rows, int wave, int lane) {
+  using Z = Swz<T, RL>;
+  constexpr int RPI = 64 / Z::CPR;                    // rows per instruction
+  const int ninstr = rows / RPI;
+  const int rl = lane / Z::CPR, p = lane % Z::CPR;
+  for (int q = wave; q < ninstr; q += kThreadsF / 64) {
+    const int r = q * RPI + rl;
+    const int c = p ^ (r & Z::MASK);
+    lds_dma16(g + r * gs + static_cast<int64_t>(c) * Z::EV, l + q * RPI * RL);
   }
 }
 
@@ -125,22 +142,21 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
   using P = Pol<DT>;
   using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
   using T = typename P::T;
-  constexpr int EV = 16 / sizeof(T);
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
-  lds_dma_rows(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), Lay::S, SC, N1 / EV,
-               wave, lane);
+  lds_dma_rows<T, N1>(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), SC, wave,
+                      lane);
   if constexpr (Lay::STAGE_YA) {
-    lds_dma_rows(static_cast<const T*>(a.YA) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_YA), Lay::SY, KP,
-                 N1 / EV, wave, lane);
+    lds_dma_rows<T, N1>(static_cast<const T*>(a.YA) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_YA), KP, wave,
+                        lane);
     if constexpr (TT)
-      lds_dma_rows(static_cast<const T*>(a.XB) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_XB), Lay::SXB, R,
-                   N1 / EV, wave, lane);
+      lds_dma_rows<T, N1>(static_cast<const T*>(a.XB) + i2 * N1, nA, reinterpret_cast<T*>(sb + Lay::OFF_XB), R, wave,
+                          lane);
   }
   if constexpr (Lay::STAGE_X) {
-    lds_dma_rows(static_cast<const T*>(a.XA) + col0, nB, reinterpret_cast<T*>(sb + Lay::OFF_XA), Lay::SX, R, SC / EV,
-                 wave, lane);
-    lds_dma_rows(static_cast<const T*>(a.X1) + i2 * nB + col0, n2 * nB, reinterpret_cast<T*>(sb + Lay::OFF_X1),
-                 Lay::SX, R, SC / EV, wave, lane);
+    lds_dma_rows<T, SC>(static_cast<const T*>(a.XA) + col0, nB, reinterpret_cast<T*>(sb + Lay::OFF_XA), R, wave,
+                        lane);
+    lds_dma_rows<T, SC>(static_cast<const T*>(a.X1) + i2 * nB + col0, n2 * nB, reinterpret_cast<T*>(sb + Lay::OFF_X1),
+                        R, wave, lane);
   }
 }
 
@@ -154,8 +170,6 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using CFrag = typename P::CFrag;
   using vec = typename W::vec;
   constexpr int V = W::V, SUB = W::SUB, KG = W::KG;
-  constexpr int EV = 16 / P::ESZ;           // elements per 16-byte vector
-  constexpr int S = Lay::S, SY = Lay::SY, SX = Lay::SX;
   constexpr int CBR = R / 16;               // 16-wide column blocks of an R-wide output
   constexpr int KB = KP / 16;               // 16-row blocks of KP
   constexpr int KBB = R / 16;               // TT: 16-row blocks of R_B^T
@@ -205,7 +219,9 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
                                        wave, lane);
   };
   // Y_1 rows, resident for the whole kernel
-  if constexpr (Lay::STAGE_Y1) lds_dma_rows(Y1, N1, Y1s, SY, KP, N1 / EV, wave, lane);
+  if constexpr (Lay::STAGE_Y1) lds_dma_rows<T, N1>(Y1, N1, Y1s, KP, wave, lane);
+  using ZN = Swz<T, N1>;                    // staged rows of N1 elements (slab columns, Y rows)
+  using ZX = Swz<T, SC>;                    // staged rows of SC elements (X_A, X_1 rows)
 
   CFrag rA[B2][CBR];
   CFrag r1[CBR];
@@ -261,14 +277,14 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
         const int kk = kw * KG + V * lg;
         vec aw;
 #pragma unroll
-        for (int e = 0; e < V; ++e) aw[e] = Ms[(kk + e) * S + i1];
+        for (int e = 0; e < V; ++e) aw[e] = Ms[ZN::off(kk + e, i1)];
         vec bA[CBR], b1[CBR];
 #pragma unroll
         for (int c = 0; c < CBR; ++c) {
           const int j = 16 * c + l16;
           if constexpr (Lay::STAGE_X) {
-            bA[c] = W::load(XAs + j * SX + kk);
-            b1[c] = W::load(X1s + j * SX + kk);
+            bA[c] = W::load(XAs + ZX::off(j, kk));
+            b1[c] = W::load(X1s + ZX::off(j, kk));
           } else {
             bA[c] = W::load(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
             b1[c] = W::load(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
@@ -291,12 +307,12 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll 2
         for (int kw = 0; kw < N1 / KG; ++kw) {
           const int kk = kw * KG + V * lg;
-          const vec bw = W::load(&Ms[iBl * S + kk]);
+          const vec bw = W::load(&Ms[ZN::off(iBl, kk)]);
           vec ay[KB];
 #pragma unroll
           for (int rb = 0; rb < KB; ++rb) {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) ay[rb] = W::load(YAs + jr * SY + kk);
+            if constexpr (Lay::STAGE_YA) ay[rb] = W::load(YAs + ZN::off(jr, kk));
             else ay[rb] = W::load(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
 #pragma unroll
@@ -308,12 +324,12 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll 2
         for (int kw = 0; kw < N1 / KG; ++kw) {
           const int kk = kw * KG + V * lg;
-          const vec bw = W::load(&Ms[iBl * S + kk]);
+          const vec bw = W::load(&Ms[ZN::off(iBl, kk)]);
           vec ax[KBB];
 #pragma unroll
           for (int rb = 0; rb < KBB; ++rb) {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) ax[rb] = W::load(XBs + jr * Lay::SXB + kk);
+            if constexpr (Lay::STAGE_YA) ax[rb] = W::load(XBs + ZN::off(jr, kk));
             else ax[rb] = W::load(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
 #pragma unroll
@@ -328,12 +344,12 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll 2
         for (int kw = 0; kw < N1 / KG; ++kw) {
           const int kk = kw * KG + V * lg;
-          const vec bw = W::load(&Ms[iBl * S + kk]);
+          const vec bw = W::load(&Ms[ZN::off(iBl, kk)]);
           vec ay[KB];
 #pragma unroll
           for (int rb = 0; rb < KB; ++rb) {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_Y1) ay[rb] = W::load(Y1s + jr * SY + kk);
+            if constexpr (Lay::STAGE_Y1) ay[rb] = W::load(Y1s + ZN::off(jr, kk));
             else ay[rb] = W::load(Y1 + static_cast<int64_t>(jr) * N1 + kk);
           }
 #pragma unroll
