@@ -366,10 +366,24 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           }
       }
     }  // i2l
+    // Z_A partials of this tile's row range for the sub-block's columns (before (d2),
+    // so that the stores overlap it and zA's registers are free)
+    if (bd_active && bd_zA) {
+      Acc* PZA = static_cast<Acc*>(a.PZA);
+      const int64_t iB = iBbase + iBl;
+#pragma unroll
+      for (int rb = 0; rb < KB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int jA = 16 * rb + P::crow(lane, v);
+          PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
+        }
+    }
     if constexpr (!TT) {
       __syncthreads();
-      // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1)
-#pragma unroll 4
+      // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1);
+      // fully unrolled so that every X_2 load of the wave is in flight at once
+#pragma unroll
       for (int kw = 0; kw < KW / KG; ++kw) {
         const int K = wave * KW + kw * KG + V * lg;
         vec azw;
@@ -388,18 +402,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       }
     }
 
-    // Z_A (and TTNN R_B^T) partials of this tile's row range for the sub-block's columns
-    if (bd_active && bd_zA) {
-      Acc* PZA = static_cast<Acc*>(a.PZA);
-      const int64_t iB = iBbase + iBl;
-#pragma unroll
-      for (int rb = 0; rb < KB; ++rb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int jA = 16 * rb + P::crow(lane, v);
-          PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
-        }
-    }
+    // TTNN R_B^T partials of this tile's row range for the sub-block's columns
     if constexpr (TT) {
       if (bd_active && !bd_zA) {
         Acc* PRB = static_cast<Acc*>(a.PRB);
