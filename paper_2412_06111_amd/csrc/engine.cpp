@@ -475,6 +475,40 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
     return chain_ptr(prefix);
   };
 
+  // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0.  For a whole tensor
+  // its last step is an FP64 job that depends only on the chain, so it joins the
+  // first batch of node jobs (it runs first; the accumulators are independent).
+  auto do_root = [&]() {
+    const auto& rc = P.nodes[0].children;
+    std::vector<int> before(rc.begin(), rc.end() - 1);
+    const void* in = operand(before);
+    const std::vector<Pos> ps = positions_after(P, before, off, ext);
+    const Node& g = P.nodes[rc.back()];
+    const int p0 = position_of_mode(ps, g.first);
+    const int w = g.last - g.first + 1;
+    const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
+    if (!before.empty() && whole) {
+      if (batch.writes(in)) batch.flush();
+      batch.add(left_job(static_cast<const double*>(in), L, n, Q, g.Y64, g.k, 1, g.k, P.psi_root, 1, alpha));
+      return;
+    }
+    batch.flush();
+    GemmArgs a;
+    a.H = in;
+    a.th = before.empty() ? cd : TTNN_F64;
+    a.L = L;
+    a.n = n;
+    a.Q = Q;
+    a.D = before.empty() ? g.Yc : static_cast<const void*>(g.Y64);
+    a.td = before.empty() ? cd : TTNN_F64;
+    a.sDr = g.k;
+    a.sDc = 1;
+    a.ncols = g.k;
+    a.amap = box_rows(P, g.first, g.last, off, ext);
+    left_op(P, a, P.psi_root, 1, alpha, st);
+  };
+  do_root();
+
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     if (std::find(fused_nodes.begin(), fused_nodes.end(), static_cast<int>(v)) != fused_nodes.end()) continue;
     Node& t = P.nodes[v];
@@ -527,35 +561,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
                   t.R, 1, 1, st);
   }
 
-  // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0
-  const auto& rc = P.nodes[0].children;
-  std::vector<int> before(rc.begin(), rc.end() - 1);
-  const void* in = operand(before);
-  const std::vector<Pos> ps = positions_after(P, before, off, ext);
-  const Node& g = P.nodes[rc.back()];
-  const int p0 = position_of_mode(ps, g.first);
-  const int w = g.last - g.first + 1;
-  const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
-  if (!before.empty() && whole) {
-    if (batch.writes(in)) batch.flush();
-    batch.add(left_job(static_cast<const double*>(in), L, n, Q, g.Y64, g.k, 1, g.k, P.psi_root, 1, alpha));
-    batch.flush();
-    return;
-  }
   batch.flush();
-  GemmArgs a;
-  a.H = in;
-  a.th = before.empty() ? cd : TTNN_F64;
-  a.L = L;
-  a.n = n;
-  a.Q = Q;
-  a.D = before.empty() ? g.Yc : static_cast<const void*>(g.Y64);
-  a.td = before.empty() ? cd : TTNN_F64;
-  a.sDr = g.k;
-  a.sDc = 1;
-  a.ncols = g.k;
-  a.amap = box_rows(P, g.first, g.last, off, ext);
-  left_op(P, a, P.psi_root, 1, alpha, st);
 }
 }  // namespace
 

@@ -553,27 +553,27 @@ struct Shape {
 
 // Tile shape per dtype: B2 slabs of i_2 per tile, SC columns per sub-tile (sized so
 // that the slab, the DRM rows of a sub-tile and the Z1 stash fit the LDS budget).
-template <int DT, int R>
+template <int DT, int R, bool TT>
 constexpr int b2_of() {
-  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : 2;
+  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : (R >= 64 || TT ? 2 : 4);
 }
 template <int DT>
 constexpr int sc_of() {
   return DT == TTNN_BF16 ? 64 : 32;
 }
 
-Shape shape_for(int dt, int R) {
+Shape shape_for(int dt, int R, bool tt) {
   if (dt == TTNN_BF16) return {R >= 64 ? 4 : 8, 64};
   if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 32};
-  return {2, 32};
+  return {R >= 64 || tt ? 2 : 4, 32};
 }
 
 template <int DT, int R, int KP>
 void launch_sttnn(bool tt, const SttnnArgs& a, hipStream_t st) {
-  constexpr int B2 = b2_of<DT, R>();
   constexpr int SC = sc_of<DT>();
-  if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC, true>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
-  else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2, SC, false>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
+  constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>();
+  if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
+  else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
 }
 
 template <int DT>
@@ -610,7 +610,7 @@ void fused_prepare(Plan& P, hipStream_t st) {
   else if (R == 64 && nA_.k <= 96) KP = 96;
   if (KP == 0) return;
   if (P.dims[0] != N1) return;
-  const Shape sh = shape_for(P.dtype, R);
+  const Shape sh = shape_for(P.dtype, R, tt);
   const int64_t n2 = P.dims[1], nAs = N1 * n2, nB = P.N / nAs;
   if (n2 % sh.B2 != 0 || nB % sh.SC != 0) return;
   const int TA = static_cast<int>(n2 / sh.B2);
