@@ -174,6 +174,19 @@ ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64
  * synchronously, so this call synchronises `stream`. */
 ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream);
 
+/* The same recovery phase, enqueued on `stream` without waiting: returns TTNN_OK
+ * once the work is enqueued (TTNN_E_INVALID for bad arguments).  The cores are valid
+ * when `stream` reaches the end of this work.  The numerical status (non-finite
+ * sketch, or a node whose Omega has numerical rank 0) is or-ed into the plan's
+ * sticky status, which ttnn_assemble_status reports.  For serving loops that
+ * assemble on demand without draining the stream. */
+ttnn_status ttnn_assemble_async(ttnn_plan_t plan, double* const* d_cores, void* stream);
+
+/* TTNN_E_NUMERIC if any ttnn_assemble / ttnn_assemble_async of this plan since the
+ * previous call found a non-finite sketch or a rank-0 node, else TTNN_OK; clears the
+ * sticky status.  Synchronises `stream` (use the stream the assemblies ran on). */
+ttnn_status ttnn_assemble_status(ttnn_plan_t plan, void* stream);
+
 /* Dense reconstruction (Def. 5, matricised form) from cores laid out as written by
  * ttnn_assemble: d_out receives prod(dims) values of dtype out_dtype, column-major. */
 ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, void* d_out,

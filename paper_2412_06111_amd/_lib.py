@@ -61,6 +61,8 @@ def _load():
         "ttnn_sketch_update_batched": [i32, C.POINTER(UpdateDesc), vp],
         "ttnn_core_shape": [vp, i32, C.POINTER(i32), P64],
         "ttnn_assemble": [vp, C.POINTER(vp), vp],
+        "ttnn_assemble_async": [vp, C.POINTER(vp), vp],
+        "ttnn_assemble_status": [vp, vp],
         "ttnn_reconstruct": [vp, C.POINTER(vp), vp, i32, vp],
         "ttnn_diff_norms": [vp, i32, vp, i64, C.POINTER(dbl), vp],
         "ttnn_sketch_shape": [vp, i32, i32, P64, P64],
@@ -284,6 +286,21 @@ class Plan:
         if check_status:
             check(st)
         return cores if check_status else (cores, st)
+
+    def assemble_async(self, cores=None, stream=None):
+        """Enqueue the recovery phase without waiting; the numerical status is kept
+        (sticky) until assemble_status()."""
+        cores = self.alloc_cores() if cores is None else cores
+        ptrs = (C.c_void_p * self.num_nodes)(*[C.c_void_p(c.data_ptr()) for c in cores])
+        check(lib.ttnn_assemble_async(self.handle, ptrs, stream_ptr(stream)))
+        return cores
+
+    def assemble_status(self, stream=None, check_status=True):
+        """Status of every assembly since the last query (waits for the stream)."""
+        st = lib.ttnn_assemble_status(self.handle, stream_ptr(stream))
+        if check_status:
+            check(st)
+        return st
 
     def reconstruct(self, cores, out=None, out_dtype=F64, stream=None):
         n = 1

@@ -221,6 +221,32 @@ ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream
   });
 }
 
+ttnn_status ttnn_assemble_async(ttnn_plan_t plan, double* const* d_cores, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_cores) throw Error{TTNN_E_INVALID, "NULL argument"};
+    std::vector<double*> by_level(P->nodes.size());
+    for (size_t c = 0; c < P->nodes.size(); ++c) {
+      if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
+      by_level[P->level_of_caller[c]] = d_cores[c];
+    }
+    ttnn::enqueue_assemble(*P, by_level.data(), as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_assemble_status(ttnn_plan_t plan, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const ttnn_status s = ttnn::assemble_status(*P, as_stream(stream));
+    if (s != TTNN_OK) ttnn::set_error("an assembly since the last status query met a non-finite sketch, or a node "
+                                      "whose Omega has numerical rank 0");
+    return s;
+  });
+}
+
 ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, void* d_out, int32_t out_dtype,
                              void* stream) {
   Plan* P = get(plan);

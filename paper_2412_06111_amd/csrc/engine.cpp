@@ -639,11 +639,15 @@ std::vector<int64_t> core_shape(const Plan& P, int v) {
 }
 
 // ---------------------------------------------------------------- recovery phase
-ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
+// d_flag: [0] non-finite count, [1, nn) kept singular values per node, then the call
+// and sticky status words at the end of the array
+constexpr int kCallWord = 2 * TTNN_MAX_NODES - 2, kStickyWord = 2 * TTNN_MAX_NODES - 1;
+
+void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   if (!P.epilogue_valid) run_epilogue(P, st);
   const int nn = static_cast<int>(P.nodes.size());
   // finite check of the sketches
-  launch_zero_int(P.d_flag, 2 * TTNN_MAX_NODES, st);
+  launch_zero_int(P.d_flag, kCallWord, st);
   {
     SegList s;
     for (int v = 1; v < nn; ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
@@ -712,15 +716,24 @@ ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
     batch.flush();
   }
   batch.flush();
-  // status: flag[0] = non-finite, kept counts of each job
-  std::vector<int> host(nn, 0);
-  TTNN_HIP(hipMemcpyAsync(host.data(), P.d_flag, sizeof(int) * nn, hipMemcpyDeviceToHost, st));
-  TTNN_HIP(hipStreamSynchronize(st));
+  launch_status_fold(P.d_flag, nn, P.d_flag + kCallWord, P.d_flag + kStickyWord, st);
   P.has_cores = true;
-  if (host[0] != 0) return TTNN_E_NUMERIC;
-  for (int v = 1; v < nn; ++v)
-    if (host[v] == 0) return TTNN_E_NUMERIC;
-  return TTNN_OK;
+}
+
+ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
+  enqueue_assemble(P, cores, st);
+  int bad = 0;
+  TTNN_HIP(hipMemcpyAsync(&bad, P.d_flag + kCallWord, sizeof(int), hipMemcpyDeviceToHost, st));
+  TTNN_HIP(hipStreamSynchronize(st));
+  return bad ? TTNN_E_NUMERIC : TTNN_OK;
+}
+
+ttnn_status assemble_status(Plan& P, hipStream_t st) {
+  int bad = 0;
+  TTNN_HIP(hipMemcpyAsync(&bad, P.d_flag + kStickyWord, sizeof(int), hipMemcpyDeviceToHost, st));
+  TTNN_HIP(hipStreamSynchronize(st));
+  launch_zero_int(P.d_flag + kStickyWord, 1, st);
+  return bad ? TTNN_E_NUMERIC : TTNN_OK;
 }
 
 // ---------------------------------------------------------------- reconstruction

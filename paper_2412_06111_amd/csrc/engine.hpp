@@ -38,7 +38,13 @@ bool whole_tensor(const Plan& P, const int64_t* off, const int64_t* ext);
 // Omega_t = Y_t^T R_t and Psi_t = (Y_cm^T kron ... kron Y_c1^T) R_t, FP64, from the accumulators.
 void run_epilogue(Plan& P, hipStream_t stream);
 // Recovery phase; cores[v] indexed by level-order id.  Returns the numeric status.
+// Enqueues the recovery phase; its status lands in the plan's call word and is
+// or-ed into the sticky word (no host synchronisation).
+void enqueue_assemble(Plan& P, double* const* cores, hipStream_t stream);
+// Enqueues and reads this assembly's status back (synchronises `stream`).
 ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t stream);
+// Status of every assembly since the last query (synchronises `stream`), then clears it.
+ttnn_status assemble_status(Plan& P, hipStream_t stream);
 void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dtype, hipStream_t stream);
 
 // Core shape of level-order node v.

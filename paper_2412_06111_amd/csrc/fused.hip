@@ -81,7 +81,11 @@ struct SttnnLayout {
   static constexpr int SXB = SY;
   static constexpr int SX = SC;                               // row stride of staged X_A / X_1 rows
   static constexpr size_t MS = size_t(SC) * S * ESZ;
-  static constexpr size_t Z1 = TT ? 0 : size_t(B2) * KP * SC * ESZ;
+  // Z1 stash rows (one per slab): FP32 rows are padded by 16 elements so that the four
+  // rows read together by the 4 x 4 block products of (d2) fall on distinct banks
+  static constexpr int ZPAD = DT == TTNN_F32 ? 16 : 0;
+  static constexpr int ZS = KP * SC + ZPAD;
+  static constexpr size_t Z1 = TT ? 0 : size_t(B2) * ZS * ESZ;
   static constexpr size_t YAB = size_t(KP) * SY * ESZ;
   static constexpr size_t YB = YAB + (TT ? size_t(R) * SXB * ESZ : 0);
   static constexpr size_t XB = size_t(R) * SX * ESZ;
@@ -178,6 +182,10 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   constexpr int KT = KP * SC;               // (d2) contraction length per column sub-block
   constexpr int KW = KT / 8;                // per wave
   static_assert(KW % KG == 0 && SC % KG == 0 && N1 % KG == 0, "wide steps");
+  // FP32 R_2 stage on 4 x 4 blocks (R <= 32; wider R keeps the 16 x 16 tiles, whose
+  // accumulators are 4x smaller)
+  constexpr bool D2Q = DT == TTNN_F32 && R <= 32;
+  static_assert(!D2Q || KW % 64 == 0, "4 x 4 block steps");
   static_assert(Lay::TOTAL <= 160 * 1024, "LDS budget");
   static_assert(8 * 16 * R * sizeof(Acc) <= Lay::TOTAL, "reduction scratch");
 
@@ -226,6 +234,9 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   CFrag rA[B2][CBR];
   CFrag r1[CBR];
   CFrag r2[CBR];
+  // FP32 (d2): 16 blocks of 4 x 4 per column group (block = lane / 4, row i2l = register
+  // index, column 4 g + lane % 4); summed over blocks and waves at the end of the tile
+  f32x4_t r2q[D2Q ? R / 4 : 1];
   CFrag zA[KB];
   CFrag zB[TT ? KBB : 1];
   const CFrag zero = {};
@@ -238,6 +249,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     r1[c] = zero;
     r2[c] = zero;
   }
+#pragma unroll
+  for (int g = 0; g < (D2Q ? R / 4 : 1); ++g) r2q[g] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   // roles in the (b)/(d1) phase: Z_A, or Z1 (STTNN) / R_B^T (TTNN), for one 16-column
   // block of the sub-tile
   const bool bd_active = wave < 2 * NCB;
@@ -362,7 +375,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int j1 = 16 * rb + P::crow(lane, v);
-            Z1s[i2l * KT + iBl * KP + j1] = P::from_acc(acc[rb][v]);
+            Z1s[i2l * Lay::ZS + iBl * KP + j1] = P::from_acc(acc[rb][v]);
           }
       }
     }  // i2l
@@ -379,7 +392,30 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
         }
     }
-    if constexpr (!TT) {
+    if constexpr (!TT && D2Q) {
+      __syncthreads();
+      // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1) on
+      // the 16-block 4 x 4 x 1 MFMA: only B2 <= 4 rows are live, so 16 x 16 tiles would
+      // idle three quarters of the unit.  Block q = lane / 4 takes its own contraction
+      // values (4 consecutive per wide load), lane % 4 is the row i2l for A and the
+      // column within a group of 4 for B; group g covers columns 4 g .. 4 g + 3.
+      const int q = lane >> 2, iq = lane & 3;
+#pragma unroll
+      for (int kw = 0; kw < KW / 64; ++kw) {
+        const int K = wave * KW + kw * 64 + 4 * q;
+        f32x4_t az;
+        if (iq < B2) az = *reinterpret_cast<const f32x4_t*>(&Z1s[iq * Lay::ZS + K]);
+        else az = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        f32x4_t bx[R / 4];
+#pragma unroll
+        for (int g = 0; g < R / 4; ++g)
+          bx[g] = *reinterpret_cast<const f32x4_t*>(X2 + (static_cast<int64_t>(4 * g + iq) * nB + iBbase) * KP + K);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int g = 0; g < R / 4; ++g) r2q[g] = __builtin_amdgcn_mfma_f32_4x4x1f32(az[s], bx[g][s], r2q[g], 0, 0, 0);
+      }
+    } else if constexpr (!TT) {
       __syncthreads();
       // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1);
       // fully unrolled so that every X_2 load of the wave is in flight at once
@@ -387,7 +423,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       for (int kw = 0; kw < KW / KG; ++kw) {
         const int K = wave * KW + kw * KG + V * lg;
         vec azw;
-        if (l16 < B2) azw = W::load(&Z1s[l16 * KT + K]);
+        if (l16 < B2) azw = W::load(&Z1s[l16 * Lay::ZS + K]);
         else azw = vec{};
         vec bx[CBR];
 #pragma unroll
@@ -439,10 +475,26 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   if constexpr (TT) return;
   __syncthreads();
   Acc* red = reinterpret_cast<Acc*>(smem);          // 8 waves x 16 rows x R
+  if constexpr (D2Q) {
+    // sum the 16 blocks (lanes 4 q + jj, q = 0..15) by a fixed butterfly; lanes 0..3 of
+    // each wave then hold rows i2l = v, columns 4 g + lane
 #pragma unroll
-  for (int c = 0; c < CBR; ++c)
+    for (int g = 0; g < R / 4; ++g)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) red[(wave * 16 + P::crow(lane, v)) * R + 16 * c + l16] = r2[c][v];
+      for (int v = 0; v < 4; ++v) {
+        float x = r2q[g][v];
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 8);
+        x += __shfl_xor(x, 16);
+        x += __shfl_xor(x, 32);
+        if (lane < 4) red[(wave * 16 + v) * R + 4 * g + lane] = x;
+      }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CBR; ++c)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) red[(wave * 16 + P::crow(lane, v)) * R + 16 * c + l16] = r2[c][v];
+  }
   __syncthreads();
   {
     Acc* PR2 = static_cast<Acc*>(a.PR2);

@@ -130,21 +130,20 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
   for (int u = 0; u < EPT; ++u)
 #pragma unroll
     for (int q = 0; q < 8; ++q) s8[u][q] = 0.0;
-  int sp = 0;
-  for (; sp + 8 <= J.splits; sp += 8) {
+  // split sp + q goes to sum q; splits past the end add nothing (every index of s8
+  // stays static, so it lives in registers)
+  for (int sp = 0; sp < J.splits; sp += 8) {
     double v[EPT][8];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
 #pragma unroll
-      for (int u = 0; u < EPT; ++u) v[u][q] = parts[(sp + q) * (TM * TN) + tid + 256 * u];
+      for (int u = 0; u < EPT; ++u)
+        v[u][q] = sp + q < J.splits ? parts[(sp + q) * (TM * TN) + tid + 256 * u] : 0.0;
 #pragma unroll
     for (int u = 0; u < EPT; ++u)
 #pragma unroll
       for (int q = 0; q < 8; ++q) s8[u][q] += v[u][q];
   }
-  for (int q = 0; sp < J.splits; ++sp, ++q)
-#pragma unroll
-    for (int u = 0; u < EPT; ++u) s8[u][q] += parts[sp * (TM * TN) + tid + 256 * u];
 #pragma unroll
   for (int u = 0; u < EPT; ++u) {
     const int e = tid + 256 * u;

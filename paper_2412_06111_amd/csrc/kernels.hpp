@@ -197,6 +197,9 @@ struct QrJobList {
   int n;
 };
 void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t stream);
+// Status of one assembly from its flags (flags[0] non-finite count, flags[1..nn-1] kept
+// singular values per node): *call = 1 if bad else 0, and *sticky |= *call.
+void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t stream);
 
 // ---------------------------------------------------------------- norms
 // Deterministic two-pass sums of (a - b)^2 and b^2; result in d_out[0..1].

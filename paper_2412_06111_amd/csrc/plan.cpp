@@ -209,6 +209,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   for (int c : P->nodes[0].children) P->psi_root_len *= P->nodes[c].k;
   P->psi_root = static_cast<double*>(P->alloc(sizeof(double) * P->psi_root_len));
   P->d_flag = static_cast<int*>(P->alloc(sizeof(int) * 2 * TTNN_MAX_NODES));
+  if (!dry) launch_zero_int(P->d_flag, 2 * TTNN_MAX_NODES, stream);     // status words start clear
   P->g64_part_elems = size_t(1) << 21;
   P->g64_part = static_cast<double*>(P->alloc(sizeof(double) * P->g64_part_elems));
   P->g64_counters_n = size_t(1) << 14;

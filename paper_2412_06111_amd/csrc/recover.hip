@@ -234,6 +234,16 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   }
 }
 
+// one thread: an assembly is bad if a sketch was not finite or a node kept nothing
+__global__ void status_fold_kernel(const int* __restrict__ flags, int nn, int* __restrict__ call,
+                                   int* __restrict__ sticky) {
+  if (threadIdx.x != 0) return;
+  int bad = flags[0] != 0 ? 1 : 0;
+  for (int v = 1; v < nn; ++v) bad |= flags[v] == 0 ? 1 : 0;
+  *call = bad;
+  *sticky = *sticky | bad;
+}
+
 __global__ void diff_norm_part(const void* a, int a_dtype, const double* b, int64_t n, double* part) {
   double s0 = 0.0, s1 = 0.0;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
@@ -281,6 +291,10 @@ void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor
     }
   }
   hipLaunchKernelGGL(qr_pinv_kernel, dim3(jl.n), dim3(kThreads), lds, st, jl, eps_factor, d_kept);
+}
+
+void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t st) {
+  hipLaunchKernelGGL(status_fold_kernel, dim3(1), dim3(64), 0, st, flags, nn, call, sticky);
 }
 
 void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, double* d_part, double* d_out,

@@ -15,8 +15,9 @@ stream's plan (DRMs + FP64 sketch accumulators) resident on the device and
 * launches each batch through ttnn_sketch_update_batched, which runs every step of
   the box updates of same-shaped plans as one launch, so a stream's result is bitwise
   the same alone and in the mix (fixed reduction orders);
-* assembles cores on demand (every `assemble_every` updates of a stream, and when a
-  stream closes);
+* assembles cores on demand (every `assemble_every` updates of a stream, enqueued
+  without draining the GPU; and when a stream closes, where the numerical status of
+  every assembly of the stream is checked);
 * records a HIP event per batch and reports per-update latency (arrival to the end
   of its batch on the GPU) as p50/p99, beside throughput.
 
@@ -81,7 +82,15 @@ class LibEngine:
                 p.update_rank1(u.factors, u.alpha, stream=self.stream)
 
     def assemble(self, plan):
-        return plan.assemble(stream=self.stream)
+        """Cores of the plan; reads back the status of every assembly since the last
+        query (synchronises the stream)."""
+        cores = plan.assemble_async(stream=self.stream)
+        plan.assemble_status(stream=self.stream)
+        return cores
+
+    def assemble_async(self, plan):
+        """On-demand cores without draining the stream (status checked at close)."""
+        return plan.assemble_async(stream=self.stream)
 
     def destroy(self, plan):
         plan.close()
@@ -228,7 +237,7 @@ class Server:
         for st in chosen:
             st.n_done += 1
             if self.assemble_every and st.n_done % self.assemble_every == 0:
-                st.cores = self.engine.assemble(st.plan)
+                st.cores = self.engine.assemble_async(st.plan)
         ev = self.engine.event()
         self.inflight.append((ev, ups, [st.sid for st in chosen]))
         self.batches.append(len(ups))

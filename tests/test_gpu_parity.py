@@ -186,3 +186,33 @@ def test_error_paths(P):
     cores = plan.assemble()
     e2, n2 = P.diff_norms(plan.reconstruct(cores), dev)
     assert np.sqrt(e2 / n2) < 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["f64", "bf16"])
+def test_assemble_async(P, dtype):
+    """Enqueued assembly writes the same cores as the synchronous call, bitwise; its
+    numerical status is sticky until queried."""
+    dims = (16, 12, 10, 14)
+    T = W.small_random_ttn(O.T4, dims, 3, seed=5)
+    dev, _ = to_device(T, dtype)
+    plan = P.Plan(O.T4, dims, 4, 2, variant="sttnn", dtype=dtype, seed=3)
+    plan.update(dev)
+    sync = plan.assemble()
+    asyn = plan.assemble_async()
+    assert plan.assemble_status() == 0
+    for a, b in zip(sync, asyn):
+        assert torch.equal(a, b)
+    # a non-finite update: the enqueue succeeds, the status query reports it once
+    bad = torch.full_like(dev, float("nan"))
+    plan.update(bad)
+    plan.assemble_async()
+    assert plan.assemble_status(check_status=False) == -7
+    assert plan.assemble_status() == 0
+    # back to a clean state; several enqueued assemblies, one query
+    plan.reset()
+    plan.update(dev)
+    for _ in range(3):
+        cores = plan.assemble_async()
+    assert plan.assemble_status() == 0
+    for a, b in zip(sync, cores):
+        assert torch.equal(a, b)

@@ -39,6 +39,8 @@ class FakeEngine:
         self.assembled.append(plan[1])
         return ("cores", plan[1])
 
+    assemble_async = assemble
+
     def destroy(self, plan):
         self.live.remove(plan)
 
