@@ -153,7 +153,7 @@ struct Batch {
   bool writes(const void* p) const { return std::find(outs.begin(), outs.end(), p) != outs.end(); }
   void flush() {
     if (jobs.empty()) return;
-    launch_bgemm64(jobs, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+    launch_bgemm64(jobs, P.g64_part, P.g64_part_elems, st);
     jobs.clear();
     outs.clear();
   }
@@ -796,7 +796,7 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
           if (out_dtype == TTNN_F64) {
             std::vector<GJob> one{mode_job(cur, sizes, static_cast<int>(i), U[t.children[i]], c.n, 1, c.n,
                                            static_cast<double*>(out))};
-            launch_bgemm64(one, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+            launch_bgemm64(one, P.g64_part, P.g64_part_elems, st);
           } else {
             launch_gemm(g, st);
           }
@@ -805,7 +805,7 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
         double* o = last ? dest : bufs[i % 2];
         // contract position i (size r_c) with U_c^T: M(i', j) = U_c[j + n_c i']
         std::vector<GJob> one{mode_job(cur, sizes, static_cast<int>(i), U[t.children[i]], c.n, 1, c.n, o)};
-        launch_bgemm64(one, P.g64_part, P.g64_part_elems, P.g64_counters, P.g64_counters_n, st);
+        launch_bgemm64(one, P.g64_part, P.g64_part_elems, st);
         sizes[i] = c.n;
         cur = o;
       }

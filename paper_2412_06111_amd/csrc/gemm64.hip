@@ -6,22 +6,25 @@
 //   C[cb](m, n) = (accumulate ? C[cb](m, n) : 0)
 //                 + alpha * sum_{kb < nbK} sum_{k < K} A(m, k; cb, kb) B(k, n; cb, kb)
 // with A(m, k; cb, kb) = A[m sAm + k sAk + cb sAc + kb sAkb] (B, C likewise).
-// Long contractions are split over several workgroups; the last workgroup of a
-// tile to finish adds the partial tiles in split order, so results do not depend
-// on scheduling.  Several jobs share one launch.
+// Long contractions are split over several workgroups whose partial tiles a second
+// launch adds in split order, so results do not depend on scheduling.  (A last-block
+// combine would need a device-scope fence, which on this chip writes back and
+// invalidates the whole L2 of the XCD for every workgroup.)  Several jobs share one
+// launch.
 #include "kernels.hpp"
 #include "mfma.hpp"
 
 namespace ttnn {
 namespace {
 
-constexpr int TM = 32, TN = 32, TK = 32;
-constexpr int LPT = TM * TK / 256;          // elements of each operand tile per thread (4)
+// A K-step of 64 keeps 16 loads a thread in flight: these products are short, so
+// their time is the number of dependent memory round trips, not arithmetic.
+constexpr int TM = 32, TN = 32, TK = 64;
+constexpr int LPT = TM * TK / 256;          // elements of each operand tile per thread (8)
 
 __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
   __shared__ double As[TK][TM + 1];
   __shared__ double Bs[TK][TN + 1];
-  __shared__ int last_flag;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int64_t b = blockIdx.x;
   int ji = 0;
@@ -84,8 +87,10 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
     const int64_t knext = kk + kcur;
     int64_t klen_next = 0;
     if (knext < k_end) fetch(knext, klen_next);   // next step's loads overlap the MFMAs
-#pragma unroll
-    for (int s = 0; s < TK / 4; ++s) {
+    // rows past the staged length are zero; skip whole groups of 4 beyond it
+    const int nmf = static_cast<int>((kcur + 3) / 4);
+#pragma unroll 8
+    for (int s = 0; s < nmf; ++s) {
       const double a = As[4 * s + lg][16 * wm + l16];
       const double bv = Bs[4 * s + lg][16 * wn + l16];
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
@@ -107,23 +112,31 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
     }
     return;
   }
-  // split contraction: publish the partial tile, the last split combines
+  // split contraction: store the partial tile; bgemm64_combine_kernel adds them
   const int64_t tile_id = (cb * J.tiles_m + tm) * J.tiles_n + tn;
   double* part = J.part + (tile_id * J.splits + split) * (TM * TN);
 #pragma unroll
   for (int v = 0; v < 4; ++v) part[(16 * wm + 4 * v + lg) * TN + 16 * wn + l16] = acc[v];
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const int prev = atomicAdd(J.counter + tile_id, 1);
-    last_flag = (prev == J.splits - 1);
-  }
-  __syncthreads();
-  if (!last_flag) return;
-  __threadfence();
+}
+
+// One workgroup per tile of a split job: C = (accumulate ? C : 0) + alpha * sum of the
+// partial tiles in split order (8 interleaved sums per element, fixed combination), so
+// results do not depend on scheduling.  A launch of its own: the kernel boundary makes
+// the partials visible without a device-wide fence.
+__global__ __launch_bounds__(256) void bgemm64_combine_kernel(GJobList L) {
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  int ji = 0;
+  while (ji + 1 < L.n && L.jobs[ji + 1].first_tile <= b) ++ji;
+  const GJob& J = L.jobs[ji];
+  const int64_t tile_id = b - J.first_tile;
+  int64_t rel = tile_id;
+  const int64_t tn = rel % J.tiles_n;
+  rel /= J.tiles_n;
+  const int64_t tm = rel % J.tiles_m;
+  const int64_t cb = rel / J.tiles_m;
+  const int64_t m0 = tm * TM, n0 = tn * TN;
   const double* parts = J.part + tile_id * J.splits * (TM * TN);
-  // each thread combines 4 elements; 8 independent partial sums per element keep 32
-  // loads in flight; fixed combination order
   constexpr int EPT = TM * TN / 256;
   double s8[EPT][8];
 #pragma unroll
@@ -154,18 +167,17 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
     double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
     *c = (J.accumulate ? *c : 0.0) + J.alpha * s;
   }
-  if (tid == 0) J.counter[tile_id] = 0;       // ready for the next launch
 }
 
 }  // namespace
 
-void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, int* counters, size_t ncounters,
-                    hipStream_t st) {
+void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, hipStream_t st) {
   for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxGJobs) {
     GJobList L{};
+    GJobList LC{};                              // split jobs, for the combine launch
     L.n = static_cast<int>(std::min<size_t>(kMaxGJobs, jobs.size() - j0));
-    int64_t blocks = 0;
-    size_t part_used = 0, ctr_used = 0;
+    int64_t blocks = 0, ctiles = 0;
+    size_t part_used = 0;
     for (int i = 0; i < L.n; ++i) {
       GJob j = jobs[j0 + i];
       j.tiles_m = (j.M + TM - 1) / TM;
@@ -179,20 +191,23 @@ void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, in
         sp = std::min<int64_t>(sp, 256);
       }
       const size_t need = static_cast<size_t>(tiles * sp * TM * TN);
-      if (sp > 1 && (part_used + need > part_elems || ctr_used + static_cast<size_t>(tiles) > ncounters)) sp = 1;
+      if (sp > 1 && part_used + need > part_elems) sp = 1;
       j.splits = static_cast<int>(sp);
       if (sp > 1) {
         j.part = part + part_used;
-        j.counter = counters + ctr_used;
         part_used += need;
-        ctr_used += static_cast<size_t>(tiles);
+        j.first_tile = ctiles;
+        ctiles += tiles;
       }
       j.first_block = blocks;
       blocks += tiles * sp;
       L.jobs[i] = j;
+      if (sp > 1) LC.jobs[LC.n++] = j;
     }
     if (blocks > 0)
       hipLaunchKernelGGL(bgemm64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, L);
+    if (ctiles > 0)
+      hipLaunchKernelGGL(bgemm64_combine_kernel, dim3(static_cast<unsigned>(ctiles)), dim3(256), 0, st, LC);
   }
 }
 

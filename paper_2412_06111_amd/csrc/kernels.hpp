@@ -114,19 +114,17 @@ struct GJob {
   int accumulate = 0;
   // filled by the launcher
   int splits = 1;
-  int64_t tiles_m = 0, tiles_n = 0, first_block = 0;
+  int64_t tiles_m = 0, tiles_n = 0, first_block = 0, first_tile = 0;
   double* part = nullptr;
-  int* counter = nullptr;
 };
 constexpr int kMaxGJobs = 12;
 struct GJobList {
   GJob jobs[kMaxGJobs];
   int n;
 };
-// Launches every job (in chunks of kMaxGJobs per kernel); `part` and `counters`
-// are split-contraction scratch (counters zero on entry, left zero on exit).
-void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, int* counters, size_t ncounters,
-                    hipStream_t stream);
+// Launches every job (in chunks of kMaxGJobs per kernel, plus one combine launch for
+// the chunk's split contractions); `part` is split-contraction scratch.
+void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, hipStream_t stream);
 
 // ---------------------------------------------------------------- rank-1 updates
 // Kronecker vector over positions (first fastest): entry(row) = prod_p v[p][digit_p(row)].

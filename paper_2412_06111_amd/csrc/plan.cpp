@@ -212,9 +212,6 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   if (!dry) launch_zero_int(P->d_flag, 2 * TTNN_MAX_NODES, stream);     // status words start clear
   P->g64_part_elems = size_t(1) << 21;
   P->g64_part = static_cast<double*>(P->alloc(sizeof(double) * P->g64_part_elems));
-  P->g64_counters_n = size_t(1) << 14;
-  P->g64_counters = static_cast<int*>(P->alloc(sizeof(int) * P->g64_counters_n));
-  if (!dry) launch_zero_int(P->g64_counters, static_cast<int64_t>(P->g64_counters_n), stream);
 
   size_chain_scratch(*P);
   P->chain = static_cast<double*>(P->alloc(sizeof(double) * P->chain_elems));

@@ -75,8 +75,6 @@ struct Plan {
   int* d_flag = nullptr;                   // numeric-status flag written by kernels
   double* g64_part = nullptr;              // split-contraction scratch of the batched FP64 GEMM
   size_t g64_part_elems = 0;
-  int* g64_counters = nullptr;
-  size_t g64_counters_n = 0;
 
   std::vector<void*> allocs;
   size_t footprint = 0;
