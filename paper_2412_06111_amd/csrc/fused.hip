@@ -525,35 +525,78 @@ __device__ inline double sum_strided(const Acc* p, int n, int64_t stride) {
   return (s[0] + s[1]) + (s[2] + s[3]);
 }
 
-// Sum the tile partials in a fixed order into the FP64 state.  The last segment is
-// R_2 (STTNN; PR2 [tB][n2][R]) or, in TTNN mode, R_B (PRB [tA][R][nB]).
+// Tile of the transposing reductions: 16 output-fast x 32 input-fast entries per
+// 256-thread block, two per thread.
+constexpr int kRTX = 16, kRTY = 32;
+
+// O[x + ldo y] (+)= alpha * sum_t P[t * tstride + x * ldx + y] for the tile (x0, y0):
+// the partials are read along y (their contiguous index) and, through an LDS
+// transpose, the output is written along x (its contiguous index).
 template <typename Acc>
-__global__ void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2, int TA, int TB,
-                                int64_t n2, int64_t nA, int64_t nB, int R, int KP, int k, double alpha, double* RA,
-                                double* ZA, double* R1, double* R2, int tt) {
-  const int64_t nRA = nA * R, nZA = static_cast<int64_t>(k) * nB, nR1 = static_cast<int64_t>(N1) * R;
+__device__ inline void reduce_transpose_tile(const Acc* P, int nt, int64_t tstride, int64_t ldx, int64_t X, int64_t Y,
+                                             int64_t x0, int64_t y0, double* O, int64_t ldo, double alpha, bool acc,
+                                             double (*tile)[kRTX + 1]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kRTX * kRTY / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int xl = e / kRTY, yl = e % kRTY;
+    const int64_t x = x0 + xl, y = y0 + yl;
+    double v = 0.0;
+    if (x < X && y < Y) v = sum_strided(P + x * ldx + y, nt, tstride);
+    tile[yl][xl] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kRTX * kRTY / 256; ++u) {
+    const int e = tid + 256 * u;
+    const int xl = e % kRTX, yl = e / kRTX;
+    const int64_t x = x0 + xl, y = y0 + yl;
+    if (x < X && y < Y) {
+      double* o = O + x + ldo * y;
+      *o = acc ? *o + alpha * tile[yl][xl] : tile[yl][xl];
+    }
+  }
+}
+
+// Sum the tile partials in a fixed order into the FP64 state.  Blocks [0, nbA) do R_A
+// (PRA [tB][iA][R] -> RA[iA + nA j]) and [nbA, nbA + nbZ) Z_A (PZA [tA][jA][iB] ->
+// ZA[jA + k iB]) tile by tile; the remaining blocks do R_1 and the last segment, R_2
+// (STTNN; PR2 [tB][n2][R]) or, in TTNN mode, R_B (PRB [tA][R][nB]), entry by entry.
+template <typename Acc>
+__global__ __launch_bounds__(256) void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2,
+                                                       int TA, int TB, int64_t n2, int64_t nA, int64_t nB, int R,
+                                                       int KP, int k, double alpha, double* RA, double* ZA, double* R1,
+                                                       double* R2, int tt, int nbA, int nbZ) {
+  __shared__ double tile[kRTY][kRTX + 1];
+  const int64_t b = blockIdx.x;
+  if (b < nbA) {
+    const int64_t ty = (R + kRTY - 1) / kRTY;
+    reduce_transpose_tile(PRA, TB, nA * R, R, nA, R, (b / ty) * kRTX, (b % ty) * kRTY, RA, nA, alpha, true, tile);
+    return;
+  }
+  if (b < nbA + nbZ) {
+    const int64_t bz = b - nbA;
+    const int64_t tx = (k + kRTX - 1) / kRTX;
+    reduce_transpose_tile(PZA, TA, static_cast<int64_t>(KP) * nB, nB, k, nB, (bz % tx) * kRTX, (bz / tx) * kRTY, ZA,
+                          k, 1.0, false, tile);
+    return;
+  }
+  const int64_t nR1 = static_cast<int64_t>(N1) * R;
   const int64_t nR2 = tt ? nB * R : n2 * R;
-  const int64_t total = nRA + nZA + nR1 + nR2;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    if (e < nRA) {
-      const int64_t iA = e / R, j = e % R;
-      RA[iA + nA * j] += alpha * sum_strided(PRA + iA * R + j, TB, nA * R);
-    } else if (e < nRA + nZA) {
-      const int64_t f = e - nRA;
-      const int64_t jA = f / nB, iB = f % nB;
-      ZA[jA + k * iB] = sum_strided(PZA + jA * nB + iB, TA, static_cast<int64_t>(KP) * nB);
-    } else if (e < nRA + nZA + nR1) {
-      const int64_t f = e - nRA - nZA;
+  const int64_t total = nR1 + nR2;
+  const int64_t nb = gridDim.x - nbA - nbZ;
+  for (int64_t f = (b - nbA - nbZ) * blockDim.x + threadIdx.x; f < total; f += nb * blockDim.x) {
+    if (f < nR1) {
       const int64_t i1 = f / R, j = f % R;
       R1[i1 + N1 * j] += alpha * sum_strided(PR1 + i1 * R + j, TA * TB, static_cast<int64_t>(N1) * R);
     } else if (!tt) {
-      const int64_t f = e - nRA - nZA - nR1;
-      const int64_t i2 = f / R, j = f % R;
+      const int64_t g = f - nR1;
+      const int64_t i2 = g / R, j = g % R;
       R2[i2 + n2 * j] += alpha * sum_strided(PR2 + i2 * R + j, TB, n2 * R);
     } else {
-      const int64_t f = e - nRA - nZA - nR1;
-      const int64_t j = f / nB, c = f % nB;
+      const int64_t g = f - nR1;
+      const int64_t j = g / nB, c = g % nB;
       R2[c + nB * j] += alpha * sum_strided(PR2 + j * nB + c, TA, static_cast<int64_t>(R) * nB);
     }
   }
@@ -763,21 +806,25 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
 
   const std::vector<int> pre{F.node_A};
   double* ZA = P.chain + P.prefix_offset.at(pre);
-  const int64_t total = F.nA * F.R + static_cast<int64_t>(F.k) * F.nB + static_cast<int64_t>(N1) * F.R +
-                        (F.tt ? F.nB : F.n2) * F.R;
   const int node_last = F.tt ? F.node_B : F.node_2;
   const void* plast = F.tt ? F.PRB : F.PR2;
-  const int blocks = static_cast<int>(std::min<int64_t>((total + 255) / 256, 8192));
+  const int64_t nbA = ((F.nA + kRTX - 1) / kRTX) * ((F.R + kRTY - 1) / kRTY);
+  const int64_t nbZ = ((F.k + kRTX - 1) / kRTX) * ((F.nB + kRTY - 1) / kRTY);
+  const int64_t rest = static_cast<int64_t>(N1) * F.R + (F.tt ? F.nB : F.n2) * F.R;
+  const int64_t nbE = std::min<int64_t>((rest + 255) / 256, 2048);
+  const dim3 grid(static_cast<unsigned>(nbA + nbZ + nbE));
   if (P.dtype == TTNN_F64)
-    hipLaunchKernelGGL(sttnn_t4_reduce<double>, dim3(blocks), dim3(256), 0, st, static_cast<const double*>(F.PRA),
+    hipLaunchKernelGGL(sttnn_t4_reduce<double>, grid, dim3(256), 0, st, static_cast<const double*>(F.PRA),
                        static_cast<const double*>(F.PZA), static_cast<const double*>(F.PR1),
                        static_cast<const double*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0);
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0,
+                       static_cast<int>(nbA), static_cast<int>(nbZ));
   else
-    hipLaunchKernelGGL(sttnn_t4_reduce<float>, dim3(blocks), dim3(256), 0, st, static_cast<const float*>(F.PRA),
+    hipLaunchKernelGGL(sttnn_t4_reduce<float>, grid, dim3(256), 0, st, static_cast<const float*>(F.PRA),
                        static_cast<const float*>(F.PZA), static_cast<const float*>(F.PR1),
                        static_cast<const float*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0);
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0,
+                       static_cast<int>(nbA), static_cast<int>(nbZ));
   done_nodes->assign({F.node_A, F.node_1, node_last});
   done_prefixes->assign({pre});
   return true;

@@ -17,9 +17,44 @@ namespace {
 
 constexpr int kThreads = 256;
 
+
+// DPP move of a double (both halves); lanes whose source is out of the row pattern or
+// outside row_mask read 0
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp64(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const int lo2 = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROW_MASK, 0xF, false);
+  const int hi2 = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROW_MASK, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+
+// 8 lanes per matrix column: the sum over the group of 8 consecutive lanes, in every
+// lane of the group (quad sums, then the mirrored quad of the half row; a + b = b + a
+// exactly, so all lanes agree)
+__device__ inline double group8_sum(double v) {
+  v += dpp64<0xB1>(v);            // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);            // quad_perm [2,3,0,1]
+  v += dpp64<0x141>(v);           // row_half_mirror: lane i <-> 7 - i
+  return v;
+}
+
+// Sum over the 64 lanes of a wave in a fixed order, returned to every lane: row sums
+// by DPP, rows combined by row broadcasts into lane 63, then read from lane 63.
+__device__ inline double wave_sum64(double v) {
+  v += dpp64<0xB1>(v);
+  v += dpp64<0x4E>(v);
+  v += dpp64<0x141>(v);           // half-row sums
+  v += dpp64<0x140>(v);           // row_mirror: row sums in every lane of the row
+  v += dpp64<0x142, 0xA>(v);      // row_bcast:15 into rows 1 and 3
+  v += dpp64<0x143, 0xC>(v);      // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
 __device__ inline double block_sum(double v, double* red) {
   // 256 threads: wave reduction then across the 4 waves
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  v = wave_sum64(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __syncthreads();
   if (lane == 0) red[wave] = v;
@@ -29,27 +64,19 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
-// 8 lanes per matrix column: returns the sum over the group of 8 consecutive lanes
-__device__ inline double group8_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  return v;
-}
-
-// Apply H_j = I - tau v v^T (v_j = 1, v_i = A[i + k j] for i > j) to columns
-// [c0, c1) of the k-row column-major matrix X (leading dimension k).
-__device__ inline void apply_reflector(const double* A, int k, int j, double tau, double* X, int c0, int c1) {
+// Apply H_j = I - tau v v^T (v_j = 1, v_i = A[i + ld j] for i > j) to columns
+// [c0, c1) of the k-row column-major matrix X (leading dimension ld).
+__device__ inline void apply_reflector(const double* A, int ld, int k, int j, double tau, double* X, int c0, int c1) {
   const int g = threadIdx.x >> 3, sub = threadIdx.x & 7;
   for (int cbase = c0; cbase < c1; cbase += kThreads / 8) {
     const int c = cbase + g;
     const bool on = c < c1;
     double w = 0.0;
     if (on)
-      for (int i = j + sub; i < k; i += 8) w += (i == j ? 1.0 : A[i + k * j]) * X[i + k * c];
+      for (int i = j + sub; i < k; i += 8) w += (i == j ? 1.0 : A[i + ld * j]) * X[i + ld * c];
     w = group8_sum(w) * tau;
     if (on)
-      for (int i = j + sub; i < k; i += 8) X[i + k * c] -= w * (i == j ? 1.0 : A[i + k * j]);
+      for (int i = j + sub; i < k; i += 8) X[i + ld * c] -= w * (i == j ? 1.0 : A[i + ld * j]);
   }
 }
 
@@ -63,12 +90,13 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   const QrJob job = jl.jobs[blockIdx.x];
   const int k = job.k, r = job.r;
   const int tid = threadIdx.x;
-  double* A = lds;               // k x r: Omega, then reflectors below the diagonal and R above
-  double* Qm = A + k * r;        // k x r: Q
+  const int ld = k | 1;          // odd leading dimension: the 8 columns a wave touches at once spread over the banks
+  double* A = lds;               // ld x r: Omega, then reflectors below the diagonal and R above
+  double* Qm = A + ld * r;       // ld x r: Q
   double* W = Qm;                // r x r (after Q is stored): R, then the Jacobi columns
   double* V = A;                 // r x r (after R is extracted): R^{-1}, or right singular vectors
 
-  for (int e = tid; e < k * r; e += kThreads) A[e] = job.Om[e];
+  for (int e = tid; e < k * r; e += kThreads) A[e % k + ld * (e / k)] = job.Om[e];
   __syncthreads();
 
   // ---- Householder QR (LAPACK dlarfg convention, v_0 = 1).  Wave 0 forms each
@@ -77,47 +105,46 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   for (int j = 0; j < r; ++j) {
     if (tid < 64) {
       double part = 0.0;
-      for (int i = j + 1 + tid; i < k; i += 64) part += A[i + k * j] * A[i + k * j];
-      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-      const double xnorm2 = part;
-      const double alpha = A[j + k * j];
+      for (int i = j + 1 + tid; i < k; i += 64) part += A[i + ld * j] * A[i + ld * j];
+      const double xnorm2 = wave_sum64(part);
+      const double alpha = A[j + ld * j];
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (xnorm2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
         tau = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
-        for (int i = j + 1 + tid; i < k; i += 64) A[i + k * j] *= scale;
+        for (int i = j + 1 + tid; i < k; i += 64) A[i + ld * j] *= scale;
       }
       if (tid == 0) {
-        A[j + k * j] = beta;
+        A[j + ld * j] = beta;
         tau_s[j] = tau;
       }
     }
     __syncthreads();
     const double tau = tau_s[j];
-    if (tau != 0.0) apply_reflector(A, k, j, tau, A, j + 1, r);
+    if (tau != 0.0) apply_reflector(A, ld, k, j, tau, A, j + 1, r);
     __syncthreads();
   }
 
   // ---- Q = H_0 ... H_{r-1} [I; 0]
-  for (int e = tid; e < k * r; e += kThreads) Qm[e] = ((e % k) == (e / k)) ? 1.0 : 0.0;
+  for (int e = tid; e < k * r; e += kThreads) Qm[e % k + ld * (e / k)] = ((e % k) == (e / k)) ? 1.0 : 0.0;
   __syncthreads();
   for (int j = r - 1; j >= 0; --j) {
     const double tau = tau_s[j];
-    if (tau != 0.0) apply_reflector(A, k, j, tau, Qm, j, r);
+    if (tau != 0.0) apply_reflector(A, ld, k, j, tau, Qm, j, r);
     __syncthreads();
   }
   // sign fix diag(R) >= 0: flip row j of R and column j of Q
   for (int e = tid; e < k * r; e += kThreads) {
     const int c = e / k;
-    const double v = Qm[e];
-    job.Q[e] = (A[c + k * c] < 0.0) ? -v : v;
+    const double v = Qm[e % k + ld * c];
+    job.Q[e] = (A[c + ld * c] < 0.0) ? -v : v;
   }
   __syncthreads();
   for (int e = tid; e < r * r; e += kThreads) {
     const int i = e % r, c = e / r;
-    double v = (i <= c) ? A[i + k * c] : 0.0;
-    if (A[i + k * i] < 0.0) v = -v;
+    double v = (i <= c) ? A[i + ld * c] : 0.0;
+    if (A[i + ld * i] < 0.0) v = -v;
     W[e] = v;
   }
   __syncthreads();
@@ -281,7 +308,7 @@ __global__ void diff_norm_final(const double* part, int nb, double* out) {
 
 void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t st) {
   if (jl.n <= 0) return;
-  const size_t lds = static_cast<size_t>(2 * max_k * max_r) * sizeof(double);
+  const size_t lds = static_cast<size_t>(2 * (max_k | 1) * max_r) * sizeof(double);
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_pinv_kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
