@@ -376,7 +376,7 @@ int pick_chunks(int64_t rows, int ncols, int64_t K, size_t partial_cap) {
   const int64_t col_blocks = (ncols + BJ - 1) / BJ;
   const int64_t blocks = row_blocks * col_blocks;
   int64_t want = 2048 / (blocks > 0 ? blocks : 1);
-  const int64_t by_len = (K + 511) / 512;              // at least ~512 terms per chunk
+  const int64_t by_len = (K + 127) / 128;              // at least ~128 terms per chunk
   if (want > by_len) want = by_len;
   const int64_t cap = static_cast<int64_t>(partial_cap / static_cast<size_t>(rows * ncols));
   if (want > cap) want = cap;
