@@ -36,8 +36,10 @@
  *    that plan return it until ttnn_reset.  Input buffers must stay valid until
  *    the stream has passed the call.
  *  - Ownership: the caller owns every buffer it passes.  A plan owns its device
- *    memory (DRMs, FP64 accumulators, scratch), allocated in ttnn_plan_create and
- *    released by ttnn_destroy.  ttnn_footprint_bytes reports its size.
+ *    memory (DRMs, FP64 accumulators, scratch), allocated in ttnn_plan_create
+ *    (stream ordered on its stream: use the plan on other streams only after that
+ *    stream has passed the call) and released by ttnn_destroy or
+ *    ttnn_destroy_async.  ttnn_footprint_bytes reports its size.
  *  - Threads: one host thread per plan at a time; distinct plans are independent.
  *  - Errors: no exception or abort crosses the ABI.  ttnn_last_error() returns a
  *    thread-local message describing the last non-OK status.
@@ -121,6 +123,13 @@ typedef struct {
 ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_plan_t* out);
 ttnn_status ttnn_destroy(ttnn_plan_t plan);
 
+/* Releases the plan without waiting: its device memory (stream-ordered allocations)
+ * returns to the device pool when `stream` reaches this call, and the handle is
+ * invalid on return.  Every piece of work on the plan must be enqueued on `stream`
+ * (or ordered before this point on it).  For serving loops that retire streams
+ * while other work is in flight. */
+ttnn_status ttnn_destroy_async(ttnn_plan_t plan, void* stream);
+
 /* Device bytes owned by the plan (DRMs in FP64 and in the compute dtype, FP64
  * accumulators, cores and scratch).  Used for admission by footprint. */
 size_t ttnn_footprint_bytes(ttnn_plan_t plan);
@@ -186,6 +195,12 @@ ttnn_status ttnn_assemble_async(ttnn_plan_t plan, double* const* d_cores, void* 
  * previous call found a non-finite sketch or a rank-0 node, else TTNN_OK; clears the
  * sticky status.  Synchronises `stream` (use the stream the assemblies ran on). */
 ttnn_status ttnn_assemble_status(ttnn_plan_t plan, void* stream);
+
+/* The same query without waiting: enqueues on `stream` a copy of the sticky status
+ * (0 = sound, 1 = TTNN_E_NUMERIC) into *h_status, which must be pinned host memory
+ * (hipHostMalloc) that the caller owns, and clears it.  *h_status is valid once
+ * `stream` has passed the call (e.g. an event recorded after it has completed). */
+ttnn_status ttnn_assemble_status_async(ttnn_plan_t plan, int32_t* h_status, void* stream);
 
 /* Dense reconstruction (Def. 5, matricised form) from cores laid out as written by
  * ttnn_assemble: d_out receives prod(dims) values of dtype out_dtype, column-major. */

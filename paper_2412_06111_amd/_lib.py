@@ -56,6 +56,7 @@ def _load():
     sigs = {
         "ttnn_plan_create": [C.POINTER(Problem), vp, C.POINTER(vp)],
         "ttnn_destroy": [vp],
+        "ttnn_destroy_async": [vp, vp],
         "ttnn_sketch_update": [vp, vp, P64, P64, dbl, vp],
         "ttnn_sketch_update_rank1": [vp, C.POINTER(vp), dbl, vp],
         "ttnn_sketch_update_batched": [i32, C.POINTER(UpdateDesc), vp],
@@ -63,6 +64,7 @@ def _load():
         "ttnn_assemble": [vp, C.POINTER(vp), vp],
         "ttnn_assemble_async": [vp, C.POINTER(vp), vp],
         "ttnn_assemble_status": [vp, vp],
+        "ttnn_assemble_status_async": [vp, vp, vp],
         "ttnn_reconstruct": [vp, C.POINTER(vp), vp, i32, vp],
         "ttnn_diff_norms": [vp, i32, vp, i64, C.POINTER(dbl), vp],
         "ttnn_sketch_shape": [vp, i32, i32, P64, P64],
@@ -180,6 +182,13 @@ class Plan:
     def close(self):
         if self.handle:
             lib.ttnn_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def close_async(self, stream=None):
+        """Release without waiting: the memory returns to the pool when `stream` (on
+        which all of this plan's work ran) reaches this point."""
+        if self.handle:
+            lib.ttnn_destroy_async(self.handle, stream_ptr(stream))
             self.handle = C.c_void_p()
 
     def __del__(self):
@@ -301,6 +310,12 @@ class Plan:
         if check_status:
             check(st)
         return st
+
+    def assemble_status_async(self, h_status, stream=None):
+        """Enqueue the status query into `h_status`, a pinned int32 CPU tensor of one
+        element (0 = sound); read it after the stream has passed this call."""
+        assert h_status.dtype == torch.int32 and h_status.is_pinned() and h_status.numel() >= 1
+        check(lib.ttnn_assemble_status_async(self.handle, C.c_void_p(h_status.data_ptr()), stream_ptr(stream)))
 
     def reconstruct(self, cores, out=None, out_dtype=F64, stream=None):
         n = 1

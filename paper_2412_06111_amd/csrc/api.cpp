@@ -87,6 +87,13 @@ ttnn_status ttnn_destroy(ttnn_plan_t plan) {
   return TTNN_OK;
 }
 
+ttnn_status ttnn_destroy_async(ttnn_plan_t plan, void* stream) {
+  if (!plan) return TTNN_OK;
+  plan->p->free_stream = as_stream(stream);
+  delete plan;
+  return TTNN_OK;
+}
+
 size_t ttnn_footprint_bytes(ttnn_plan_t plan) { return plan ? plan->p->footprint : 0; }
 
 ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset, const int64_t* extent,
@@ -244,6 +251,16 @@ ttnn_status ttnn_assemble_status(ttnn_plan_t plan, void* stream) {
     if (s != TTNN_OK) ttnn::set_error("an assembly since the last status query met a non-finite sketch, or a node "
                                       "whose Omega has numerical rank 0");
     return s;
+  });
+}
+
+ttnn_status ttnn_assemble_status_async(ttnn_plan_t plan, int32_t* h_status, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !h_status) throw Error{TTNN_E_INVALID, "NULL argument"};
+    ttnn::assemble_status_async(*P, h_status, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
   });
 }
 

@@ -728,6 +728,11 @@ ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t st) {
   return bad ? TTNN_E_NUMERIC : TTNN_OK;
 }
 
+void assemble_status_async(Plan& P, int32_t* h_status, hipStream_t st) {
+  TTNN_HIP(hipMemcpyAsync(h_status, P.d_flag + kStickyWord, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  launch_zero_int(P.d_flag + kStickyWord, 1, st);
+}
+
 ttnn_status assemble_status(Plan& P, hipStream_t st) {
   int bad = 0;
   TTNN_HIP(hipMemcpyAsync(&bad, P.d_flag + kStickyWord, sizeof(int), hipMemcpyDeviceToHost, st));

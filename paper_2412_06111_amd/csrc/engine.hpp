@@ -45,6 +45,8 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t stream);
 ttnn_status run_assemble(Plan& P, double* const* cores, hipStream_t stream);
 // Status of every assembly since the last query (synchronises `stream`), then clears it.
 ttnn_status assemble_status(Plan& P, hipStream_t stream);
+// The same status copied to pinned host memory in stream order (no synchronisation).
+void assemble_status_async(Plan& P, int32_t* h_status, hipStream_t stream);
 void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dtype, hipStream_t stream);
 
 // Core shape of level-order node v.

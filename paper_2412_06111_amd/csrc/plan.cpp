@@ -5,6 +5,7 @@
 // shapes (Sec. 4, eq. "sketch"; Sec. 5 for the reduced X_t of STTNN) and the
 // device memory of a plan.
 #include <algorithm>
+#include <cstdint>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -15,8 +16,11 @@
 
 namespace ttnn {
 
+// Device memory of a plan is stream ordered (hipMallocAsync on the creation stream),
+// so releasing it does not synchronise the device: the blocks return to the pool
+// when the release stream reaches them.
 Plan::~Plan() {
-  for (void* p : allocs) (void)hipFree(p);
+  for (void* p : allocs) (void)hipFreeAsync(p, free_stream);
   for (hipEvent_t e : sweep_ev)
     if (e) (void)hipEventDestroy(e);
 }
@@ -29,9 +33,13 @@ void* Plan::alloc(size_t bytes) {
     return nullptr;
   }
   void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess || p == nullptr) {
+  if (hipMallocAsync(&p, bytes, stream) != hipSuccess || p == nullptr) {
     (void)hipGetLastError();
-    throw Error{TTNN_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    throw Error{TTNN_E_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
+  }
+  if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {       // the kernels assume 256-byte aligned arrays
+    (void)hipFreeAsync(p, stream);
+    throw Error{TTNN_E_NOMEM, "device allocation not 256-byte aligned"};
   }
   allocs.push_back(p);
   footprint += bytes;
@@ -71,6 +79,8 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
 
   auto P = std::make_unique<Plan>();
   P->dry = dry;
+  P->stream = stream;
+  P->free_stream = stream;
   P->d = pr->order;
   P->variant = pr->variant;
   P->dtype = pr->dtype;

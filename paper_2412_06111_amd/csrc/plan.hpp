@@ -77,6 +77,8 @@ struct Plan {
   size_t g64_part_elems = 0;
 
   std::vector<void*> allocs;
+  hipStream_t stream = nullptr;            // creation stream: allocations are ordered on it
+  hipStream_t free_stream = nullptr;       // release stream (ttnn_destroy_async may change it)
   size_t footprint = 0;
   bool dry = false;                        // sizing only: alloc() counts and returns nullptr
   ttnn_status sticky = TTNN_OK;

@@ -15,9 +15,11 @@ stream's plan (DRMs + FP64 sketch accumulators) resident on the device and
 * launches each batch through ttnn_sketch_update_batched, which runs every step of
   the box updates of same-shaped plans as one launch, so a stream's result is bitwise
   the same alone and in the mix (fixed reduction orders);
-* assembles cores on demand (every `assemble_every` updates of a stream, enqueued
-  without draining the GPU; and when a stream closes, where the numerical status of
-  every assembly of the stream is checked);
+* assembles cores on demand (every `assemble_every` updates of a stream, and when a
+  stream closes), enqueued without draining the GPU; a closing stream is retired
+  once an event after its final assembly has completed: the numerical status of all
+  its assemblies (copied to pinned memory in stream order) is checked, `on_close`
+  runs and the plan's memory is released in stream order;
 * records a HIP event per batch and reports per-update latency (arrival to the end
   of its batch on the GPU) as p50/p99, beside throughput.
 
@@ -92,8 +94,19 @@ class LibEngine:
         """On-demand cores without draining the stream (status checked at close)."""
         return plan.assemble_async(stream=self.stream)
 
+    def status_async(self, plan):
+        """Enqueue the plan's sticky numerical status into pinned host memory; read it
+        with status_value once an event recorded after this call has completed."""
+        h = self.torch.zeros(1, dtype=self.torch.int32, pin_memory=True)
+        plan.assemble_status_async(h, stream=self.stream)
+        return h
+
+    def status_value(self, h):
+        return int(h[0])
+
     def destroy(self, plan):
-        plan.close()
+        """Release in stream order (no device synchronisation)."""
+        plan.close_async(stream=self.stream)
 
     def event(self):
         e = self.torch.cuda.Event(enable_timing=True)
@@ -115,7 +128,7 @@ class LibEngine:
 
 class _Stream:
     __slots__ = ("sid", "spec", "plan", "queue", "footprint", "closing", "n_done", "n_total", "cores",
-                 "inflight", "admitted_at")
+                 "inflight", "admitted_at", "close_ev", "close_status")
 
     def __init__(self, sid, spec, footprint):
         self.sid, self.spec, self.footprint = sid, spec, footprint
@@ -127,6 +140,8 @@ class _Stream:
         self.cores = None
         self.inflight = 0
         self.admitted_at = None
+        self.close_ev = None                    # event after the final assembly
+        self.close_status = None
 
 
 class Server:
@@ -192,12 +207,23 @@ class Server:
             st.admitted_at = self.now() if self._ref is not None else 0.0
             self.admit_order.append(sid)
 
-    def _retire(self):
+    def _retire(self, block=False):
         for sid in list(self.streams):
             st = self.streams[sid]
             if st.plan is None or not st.closing or st.queue or st.inflight:
                 continue
-            st.cores = self.engine.assemble(st.plan)
+            if st.close_ev is None:             # enqueue the final assembly, retire later
+                st.cores = self.engine.assemble_async(st.plan)
+                st.close_status = self.engine.status_async(st.plan)
+                st.close_ev = self.engine.event()
+                if not block:
+                    continue
+            if block:
+                self.engine.wait(st.close_ev)
+            elif not self.engine.done(st.close_ev):
+                continue
+            if self.engine.status_value(st.close_status) != 0:
+                raise RuntimeError(f"stream {sid}: an assembly met a non-finite sketch or a rank-0 node")
             self.closed[sid] = st.cores
             if self.on_close is not None:
                 self.on_close(sid, st.plan, st.cores)
@@ -268,7 +294,7 @@ class Server:
             if self.inflight:
                 self.poll(block=True)
                 continue
-            self._retire()
+            self._retire(block=True)
             self._admit()
             if any(st.plan is not None and st.queue for st in self.streams.values()):
                 continue

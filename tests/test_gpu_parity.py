@@ -216,3 +216,30 @@ def test_assemble_async(P, dtype):
     assert plan.assemble_status() == 0
     for a, b in zip(sync, cores):
         assert torch.equal(a, b)
+
+
+def test_status_async_and_destroy_async(P):
+    """The status copied to pinned memory in stream order matches the synchronous
+    query; a plan released in stream order leaves later plans correct."""
+    dims = (12, 10, 9, 11)
+    T = W.small_random_ttn(O.T4, dims, 3, seed=9)
+    dev, _ = to_device(T, "f64")
+    stream = torch.cuda.current_stream()
+    h = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+    for round_ in range(3):
+        plan = P.Plan(O.T4, dims, 4, 2, variant="ttnn", dtype="f64", seed=4)
+        plan.update(dev)
+        if round_ == 1:
+            plan.update(torch.full_like(dev, float("nan")))
+        cores = plan.assemble_async()
+        h.fill_(-1)
+        plan.assemble_status_async(h)
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        ev.synchronize()
+        assert int(h[0]) == (1 if round_ == 1 else 0)
+        if round_ != 1:
+            e2, n2 = P.diff_norms(plan.reconstruct(cores), dev)
+            assert np.sqrt(e2 / n2) < 1e-10
+        plan.close_async()                 # no synchronisation; the next plan reuses the pool
+    torch.cuda.synchronize()

@@ -41,6 +41,12 @@ class FakeEngine:
 
     assemble_async = assemble
 
+    def status_async(self, plan):
+        return 0
+
+    def status_value(self, h):
+        return h
+
     def destroy(self, plan):
         self.live.remove(plan)
 
