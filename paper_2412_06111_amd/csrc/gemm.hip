@@ -10,7 +10,10 @@
 // second kernel sums in a fixed order, so the result does not depend on timing.
 // This path is the reference engine for arbitrary shapes; the fused kernels for
 // the large dense trees live in separate files.
+#include <type_traits>
+
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace ttnn {
 namespace {
@@ -20,10 +23,109 @@ constexpr int BJ = 32;   // output columns per block
 constexpr int BK = 16;   // contraction step
 
 template <typename T> __device__ inline double ld(const T* p, int64_t i) { return to_f64(p[i]); }
+__device__ inline float ldf(const float* p, int64_t i) { return p[i]; }
+__device__ inline float ldf(const uint16_t* p, int64_t i) { return bf16_bits_to_f32(p[i]); }
+
+// FP32 / BF16 operands: the tile's inner product runs on the FP32 MFMA (16x16x4,
+// FP32 accumulation within the chunk; the chunk partial is written in the output
+// type and chunks are summed in FP64 by the reduction).  Each of the 4 waves owns 16
+// rows and both 16-column blocks.  The VALU form below reads six LDS words per eight
+// FMAs and is bound by LDS bandwidth; an MFMA reads one word a lane per 1024 FMAs.
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+                                               const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
+                                               const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
+                                               TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
+                                               int j0) {
+  __shared__ float As[BK][BR + 4];
+  __shared__ float Bs[BK][BJ + 4];
+  __shared__ int64_t drow[BK];
+
+  const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wave = tid >> 6;
+  const int64_t rows_total = RIGHT ? n : L * Q;
+  const int64_t K = RIGHT ? L * Q : n;
+  const int64_t k_begin = c * kchunk;
+  const int64_t k_end = (k_begin + kchunk < K) ? k_begin + kchunk : K;
+  const bool kk_contig = RIGHT ? (L > 1) : (L == 1);
+  f32x4_t acc[BJ / 16];
+#pragma unroll
+  for (int cb = 0; cb < BJ / 16; ++cb) acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
+    if (tid < BK) {
+      const int64_t kk = kb + tid;
+      int64_t r = -1;
+      if (kk < k_end) {
+        if (RIGHT) r = amap(kk % L) + bmap(kk / L);
+        else r = amap(kk);
+      }
+      drow[tid] = r;
+    }
+#pragma unroll
+    for (int s = 0; s < (BR * BK) / 256; ++s) {
+      const int e = tid + 256 * s;
+      int kk, rr;
+      if (kk_contig) {
+        kk = e % BK;
+        rr = e / BK;
+      } else {
+        rr = e % BR;
+        kk = e / BR;
+      }
+      const int64_t kg = kb + kk;
+      const int64_t rg = row0 + rr;
+      float v = 0.f;
+      if (kg < k_end && rg < rows_total) {
+        const int64_t m = RIGHT ? kg : rg;
+        const int64_t i = RIGHT ? rg : kg;
+        const int64_t l = m % L;
+        const int64_t q = m / L;
+        v = ldf(H, l + L * (i + n * q));
+      }
+      As[kk][rr] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < (BK * BJ) / 256; ++s) {
+      const int e = tid + 256 * s;
+      const int jj = e % BJ;
+      const int kk = e / BJ;
+      const int64_t r = drow[kk];
+      float v = 0.f;
+      if (r >= 0 && j0 + jj < ncols) v = ldf(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc);
+      Bs[kk][jj] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < BK / 4; ++s) {
+      const float a = As[4 * s + lg][16 * wave + l16];
+#pragma unroll
+      for (int cb = 0; cb < BJ / 16; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[4 * s + lg][16 * cb + l16], acc[cb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+  // lane holds C[16 wave + 4 lg + v][16 cb + l16]
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t row = row0 + 16 * wave + 4 * lg + v;
+    if (row >= rows_total) continue;
+#pragma unroll
+    for (int cb = 0; cb < BJ / 16; ++cb) {
+      const int j = j0 + 16 * cb + l16;
+      if (j >= ncols) continue;
+      const int64_t o = c * ol.cs + (row % ol.Lo) * ol.s0 + static_cast<int64_t>(j) * ol.s1 +
+                        (row / ol.Lo) * ol.s2;
+      out[o] = static_cast<TO>(acc[cb][v]);
+    }
+  }
+}
 
 // One output tile (rows row0.., columns j0.., contraction chunk c) of a generic contraction.
 template <bool RIGHT, typename TH, typename TD, typename TO>
-__device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+__device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                           const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
                                           const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
                                           TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
@@ -119,6 +221,19 @@ __device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, i
       out[o] = static_cast<TO>(acc[u][v]);
     }
   }
+}
+
+// FP32 / BF16 operands take the MFMA tile, anything with FP64 the VALU tile.
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
+                                          const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
+                                          const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
+                                          TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
+                                          int j0) {
+  if constexpr (!std::is_same_v<TH, double> && !std::is_same_v<TD, double>)
+    gemm_tile_mfma<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol, row0, c, j0);
+  else
+    gemm_tile_valu<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol, row0, c, j0);
 }
 
 template <bool RIGHT, typename TH, typename TD, typename TO>

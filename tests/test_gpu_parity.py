@@ -132,7 +132,11 @@ def test_config1_noisy_matches_oracle(P, variant, dtype):
     ocores, _ = O.assemble(sk, tree)
     e_gpu = rel(plan.reconstruct(cores).cpu().numpy(), W.flat_colmajor(T))
     e_or = rel(W.flat_colmajor(O.reconstruct(ocores, tree)), W.flat_colmajor(T))
-    assert e_gpu < 1e-4 and abs(e_gpu - e_or) <= 0.05 * e_or + 1e-9
+    # FP32 sketches (FP32 products, FP32 accumulation within a chunk) sit within 1e-5 of
+    # the oracle's; the reconstruction error of this noisy tensor is itself of order
+    # 1e-5, so the two errors agree to the same order, not to a few percent
+    rtol = 0.05 if dtype == "f64" else 0.5
+    assert e_gpu < 1e-4 and abs(e_gpu - e_or) <= rtol * e_or + 1e-9
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
