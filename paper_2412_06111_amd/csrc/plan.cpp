@@ -6,6 +6,8 @@
 // device memory of a plan.
 #include <algorithm>
 #include <cstdint>
+#include <map>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
@@ -16,15 +18,42 @@
 
 namespace ttnn {
 
-// Device memory of a plan is stream ordered (hipMallocAsync on the creation stream),
-// so releasing it does not synchronise the device: the blocks return to the pool
-// when the release stream reaches them.
+namespace {
+// Plans allocate from a pool of their own per device that keeps released memory
+// (release threshold: never), so a plan created after another was released reuses its
+// pages instead of mapping new ones.  The pool lives until the process ends.
+hipMemPool_t plan_pool() {
+  static std::mutex mu;
+  static std::map<int, hipMemPool_t> pools;
+  int dev = 0;
+  TTNN_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = pools.find(dev);
+  if (it != pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  TTNN_HIP(hipMemPoolCreate(&pool, &props));
+  uint64_t keep = UINT64_MAX;
+  TTNN_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
+  pools[dev] = pool;
+  return pool;
+}
+}  // namespace
+
+// Device memory of a plan is stream ordered (allocated on the creation stream), so
+// releasing it does not synchronise the device: the blocks return to the pool when
+// the release stream reaches them.
 Plan::~Plan() {
-  for (void* p : allocs) (void)hipFreeAsync(p, free_stream);
+  if (arena) (void)hipFreeAsync(arena, free_stream);
   for (hipEvent_t e : sweep_ev)
     if (e) (void)hipEventDestroy(e);
 }
 
+// One stream-ordered block per plan, sized by a dry build, handed out in order (every
+// request rounded to 256 bytes, so every array is 256-byte aligned).
 void* Plan::alloc(size_t bytes) {
   if (bytes == 0) bytes = 8;
   bytes = (bytes + 255) & ~static_cast<size_t>(255);
@@ -32,16 +61,10 @@ void* Plan::alloc(size_t bytes) {
     footprint += bytes;
     return nullptr;
   }
-  void* p = nullptr;
-  if (hipMallocAsync(&p, bytes, stream) != hipSuccess || p == nullptr) {
-    (void)hipGetLastError();
-    throw Error{TTNN_E_NOMEM, "hipMallocAsync of " + std::to_string(bytes) + " bytes failed"};
-  }
-  if (reinterpret_cast<uintptr_t>(p) % 256 != 0) {       // the kernels assume 256-byte aligned arrays
-    (void)hipFreeAsync(p, stream);
-    throw Error{TTNN_E_NOMEM, "device allocation not 256-byte aligned"};
-  }
-  allocs.push_back(p);
+  TTNN_REQUIRE(arena != nullptr && arena_used + bytes <= arena_size, TTNN_E_INVALID,
+               "plan memory exceeds its sized footprint");
+  void* p = arena + arena_used;
+  arena_used += bytes;
   footprint += bytes;
   return p;
 }
@@ -77,10 +100,23 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
                "bad dtype");
   TTNN_REQUIRE(pr->eps_factor >= 0.0, TTNN_E_INVALID, "eps_factor must be >= 0");
 
+  size_t need = 0;                        // the real build first sizes itself with a dry one
+  if (!dry) need = build_plan(pr, stream, true)->footprint;
   auto P = std::make_unique<Plan>();
   P->dry = dry;
   P->stream = stream;
   P->free_stream = stream;
+  if (!dry) {
+    void* a = nullptr;
+    if (hipMallocFromPoolAsync(&a, need, plan_pool(), stream) != hipSuccess || a == nullptr) {
+      (void)hipGetLastError();
+      throw Error{TTNN_E_NOMEM, "stream-ordered allocation of " + std::to_string(need) + " bytes failed"};
+    }
+    P->arena = static_cast<char*>(a);
+    P->arena_size = need;
+    if (reinterpret_cast<uintptr_t>(a) % 256 != 0)         // the kernels assume 256-byte aligned arrays
+      throw Error{TTNN_E_NOMEM, "device allocation not 256-byte aligned"};
+  }
   P->d = pr->order;
   P->variant = pr->variant;
   P->dtype = pr->dtype;

@@ -76,7 +76,8 @@ struct Plan {
   double* g64_part = nullptr;              // split-contraction scratch of the batched FP64 GEMM
   size_t g64_part_elems = 0;
 
-  std::vector<void*> allocs;
+  char* arena = nullptr;                   // the plan's one device block
+  size_t arena_size = 0, arena_used = 0;
   hipStream_t stream = nullptr;            // creation stream: allocations are ordered on it
   hipStream_t free_stream = nullptr;       // release stream (ttnn_destroy_async may change it)
   size_t footprint = 0;

@@ -66,6 +66,8 @@ class LibEngine:
         from . import _lib as L
         self.torch, self.L = torch, L
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        # pinned status words, reused (a pinned allocation costs milliseconds)
+        self._pinned = [torch.zeros(1, dtype=torch.int32, pin_memory=True) for _ in range(16)]
 
     def footprint(self, s):
         return self.L.footprint_estimate(s.spec, s.dims, s.rank, s.over, s.variant, s.dtype)
@@ -97,12 +99,14 @@ class LibEngine:
     def status_async(self, plan):
         """Enqueue the plan's sticky numerical status into pinned host memory; read it
         with status_value once an event recorded after this call has completed."""
-        h = self.torch.zeros(1, dtype=self.torch.int32, pin_memory=True)
+        h = self._pinned.pop() if self._pinned else self.torch.zeros(1, dtype=self.torch.int32, pin_memory=True)
         plan.assemble_status_async(h, stream=self.stream)
         return h
 
     def status_value(self, h):
-        return int(h[0])
+        v = int(h[0])
+        self._pinned.append(h)
+        return v
 
     def destroy(self, plan):
         """Release in stream order (no device synchronisation)."""
