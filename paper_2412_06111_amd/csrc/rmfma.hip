@@ -2,16 +2,18 @@
 // modes before t are contiguous and long, i.e. with T viewed as H[L][n][Q]
 // (l fastest) and X_t rows indexed by l + L q:
 //   out(i, j) = sum_{l, q} H[l + L (i + n q)] Xt[j][l + L q].
-// The contraction index runs along memory, so the tensor feeds MFMA A fragments
-// straight from global memory (16 bytes a lane) and the transposed DRM copy Xt
-// (r x m, contraction index contiguous) feeds B fragments the same way; no LDS.
-// A workgroup (4 waves) owns 128 output rows and one contiguous chunk of the
-// contraction; chunk partials are summed in a fixed order by the generic reduce.
+// The contraction index runs along memory in both the tensor and the transposed DRM
+// copy Xt (r x m).  A workgroup (4 waves) owns 128 output rows and one contiguous
+// chunk of the contraction, taken in steps of 128 bytes of every row: the step's
+// rows are loaded with eight lanes per row (full cache lines, 16 bytes a lane) into a
+// padded LDS tile, from which the waves read their MFMA fragments while the next
+// step's loads are in flight.  Chunk partials are summed in a fixed order by the
+// generic reduce.
 //
-// Each lane loads V = 16 / sizeof(T) consecutive contraction values; a 16 x 16 x K
-// MFMA step takes KPL of them per lane group, so one load feeds V / KPL MFMAs.  The
-// pairing of A and B values is the same in every MFMA, so the sum runs over the
-// whole K range whatever the order.
+// A fragment load gives a lane V = 16 / sizeof(T) consecutive contraction values; a
+// 16 x 16 x K MFMA step takes KPL of them per lane group, so one load feeds V / KPL
+// MFMAs.  The pairing of A and B values is the same in every MFMA, so the sum runs
+// over the whole K range whatever the order.
 #include <algorithm>
 
 #include "kernels.hpp"
@@ -33,9 +35,18 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   using CFrag = typename P::CFrag;
   constexpr int V = 16 / P::ESZ;            // values per 16-byte load
   constexpr int KPL = P::KPL;
-  constexpr int SUB = V / KPL;              // MFMAs per load
-  constexpr int KG = 4 * V;                 // contraction values per step (4 lane groups)
+  constexpr int SUB = V / KPL;              // MFMAs per fragment load
+  constexpr int KG = 4 * V;                 // contraction values per fragment step (4 lane groups)
+  constexpr int KS = 2 * KG;                // contraction values per staged step: 128 bytes of a row
+  constexpr int CPR = KS / V;               // 16-byte chunks of a row per step (8)
+  constexpr int PITCH = KS + V;             // LDS row pitch: one 16-byte pad (rows on distinct banks)
+  constexpr int NJ = 16 * NCB;              // DRM rows staged (output columns, padded)
+  constexpr int RPR = 256 / CPR;            // rows per staging round (32)
+  constexpr int AR = kRows / RPR;           // staging rounds of the tensor tile
+  constexpr int BRN = (NJ + RPR - 1) / RPR; // staging rounds of the DRM tile
   typedef T vec_t __attribute__((ext_vector_type(V)));
+  __shared__ __align__(16) T As[2][kRows * PITCH];
+  __shared__ __align__(16) T Bs[2][NJ * PITCH];
 
   const T* H = static_cast<const T*>(Hv);
   const T* Xt = static_cast<const T*>(Xtv);
@@ -47,21 +58,31 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   const int64_t k_begin = c * kchunk;
   const int64_t k_end = k_begin + kchunk < K ? k_begin + kchunk : K;
 
-  // rows of this lane's A loads (two row blocks per wave), clamped for loading
-  int64_t irow[2];
-  bool rvalid[2];
+  // staging map: thread -> row tid / CPR (+ RPR per round), chunk tid % CPR
+  const int sr = tid / CPR, sc = (tid % CPR) * V;
+  vec_t ra[AR], rb[BRN];
+  auto gload = [&](int64_t k) {
+    const bool live = k < k_end;
+    const int64_t kk = k + sc;
+    const int64_t q = kk / L, l = kk - q * L;
 #pragma unroll
-  for (int b = 0; b < 2; ++b) {
-    irow[b] = row0 + 32 * wave + 16 * b + l16;
-    rvalid[b] = irow[b] < n;
-  }
-  int jcol[NCB];
-  bool cvalid[NCB];
+    for (int u = 0; u < AR; ++u) {
+      const int64_t row = row0 + sr + RPR * u;
+      ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
+    }
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) {
-    jcol[cb] = 16 * cb + l16;
-    cvalid[cb] = jcol[cb] < r;
-  }
+    for (int u = 0; u < BRN; ++u) {
+      const int j = sr + RPR * u;
+      rb[u] = (live && j < r) ? *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(j) * m + kk) : vec_t{};
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < AR; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPR * u) * PITCH + sc]) = ra[u];
+#pragma unroll
+    for (int u = 0; u < BRN; ++u)
+      if (sr + RPR * u < NJ) *reinterpret_cast<vec_t*>(&Bs[buf][(sr + RPR * u) * PITCH + sc]) = rb[u];
+  };
 
   CFrag acc[2][NCB];
   const CFrag zero = {};
@@ -70,37 +91,41 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[b][cb] = zero;
 
-#pragma unroll 2
-  for (int64_t k = k_begin; k < k_end; k += KG) {
-    const int64_t kk = k + V * lg;          // this lane group's first value
-    const int64_t q = kk / L, l = kk - q * L;
-    vec_t a[2], bx[NCB];
+  gload(k_begin);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k = k_begin; k < k_end; k += KS) {
+    gload(k + KS);                          // the next step's rows in flight
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      if (rvalid[b]) a[b] = *reinterpret_cast<const vec_t*>(H + l + L * (irow[b] + n * q));
-      else a[b] = vec_t{};
-    }
+    for (int h = 0; h < KS / KG; ++h) {
+      const int kl = h * KG + V * lg;
+      vec_t a[2], bx[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-      if (cvalid[cb]) bx[cb] = *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(jcol[cb]) * m + kk);
-      else bx[cb] = vec_t{};
-    }
+      for (int b = 0; b < 2; ++b)
+        a[b] = *reinterpret_cast<const vec_t*>(&As[buf][(32 * wave + 16 * b + l16) * PITCH + kl]);
 #pragma unroll
-    for (int s = 0; s < SUB; ++s) {
+      for (int cb = 0; cb < NCB; ++cb) bx[cb] = *reinterpret_cast<const vec_t*>(&Bs[buf][(16 * cb + l16) * PITCH + kl]);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        Frag af;
-        if constexpr (KPL == 8) af = __builtin_bit_cast(Frag, a[b]);
-        else af = a[b][s];
+      for (int s = 0; s < SUB; ++s) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          Frag bf;
-          if constexpr (KPL == 8) bf = __builtin_bit_cast(Frag, bx[cb]);
-          else bf = bx[cb][s];
-          acc[b][cb] = P::mfma(af, bf, acc[b][cb]);
+        for (int b = 0; b < 2; ++b) {
+          Frag af;
+          if constexpr (KPL == 8) af = __builtin_bit_cast(Frag, a[b]);
+          else af = a[b][s];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) {
+            Frag bf;
+            if constexpr (KPL == 8) bf = __builtin_bit_cast(Frag, bx[cb]);
+            else bf = bx[cb][s];
+            acc[b][cb] = P::mfma(af, bf, acc[b][cb]);
+          }
         }
       }
     }
+    lstore(buf ^ 1);                        // its previous contents were read before the last barrier
+    __syncthreads();
+    buf ^= 1;
   }
 
   // partial of chunk c: part[(c n + i) r + j]
@@ -136,14 +161,14 @@ void launch_dt(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, i
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
   (void)n;
   (void)Q;
-  const int64_t kg = dt == TTNN_BF16 ? 32 : dt == TTNN_F32 ? 16 : 8;
-  return L % kg == 0 && L >= 64 && r >= 1 && r <= 64;
+  const int64_t ks = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;   // staged step: 128 bytes of a row
+  return L % ks == 0 && L >= 64 && r >= 1 && r <= 64;
 }
 
 int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
                       double* part, size_t part_elems, hipStream_t st) {
   const int64_t K = L * Q;
-  const int64_t kg = dt == TTNN_BF16 ? 32 : dt == TTNN_F32 ? 16 : 8;
+  const int64_t kg = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;    // staged step
   const int64_t row_blocks = (n + kRows - 1) / kRows;
   // enough workgroups to fill the chip twice, chunks of at least 1024 values, and
   // partials within the scratch
