@@ -80,6 +80,174 @@ __device__ inline void apply_reflector(const double* A, int ld, int k, int j, do
   }
 }
 
+// ---------------------------------------------------------------- register path
+// r <= 32 and k <= 8 TM: column c of Omega lives in the registers of the 8 lanes
+// tid = 8 c .. 8 c + 7 (lane sub holds rows sub + 8 t, t < TM).  A factorization step
+// forms the reflector in its column's lanes, broadcasts it through LDS (double
+// buffered) and takes one barrier; every other column applies it in registers.  Q and
+// R^{-1} are then formed column by column from reflectors and R in LDS, with no
+// barrier.  Returns true on the fast path (Q, Pinv = R^{-1}, kept written); otherwise
+// leaves R in W and the identity in V (leading dimension r) for the Jacobi path.
+template <int TM>
+__device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, double* W, double* V,
+                        double* vb, double* tau_s, double* red, int* kept) {
+  const int k = job.k, r = job.r;
+  const int tid = threadIdx.x, c = tid >> 3, sub = tid & 7;
+  const bool own = c < r;
+  double a[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const int i = sub + 8 * t;
+    a[t] = (own && i < k) ? job.Om[i + static_cast<int64_t>(k) * c] : 0.0;
+  }
+  // ---- factorization (LAPACK dlarfg convention, v_j = 1)
+  for (int j = 0; j < r; ++j) {
+    double* vj = vb + (j & 1) * 8 * TM;
+    if (c == j) {
+      double n0 = 0.0, n1 = 0.0, al = 0.0;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = sub + 8 * t;
+        const double x = i > j ? a[t] : 0.0;
+        if (t & 1) n1 = fma(x, x, n1);
+        else n0 = fma(x, x, n0);
+        al += i == j ? a[t] : 0.0;
+      }
+      const double xnorm2 = group8_sum(n0 + n1);
+      const double alpha = group8_sum(al);
+      double tau = 0.0, beta = alpha, scale = 0.0;
+      if (xnorm2 > 0.0) {
+        beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = sub + 8 * t;
+        const double v = i > j ? a[t] * scale : (i == j ? 1.0 : 0.0);
+        vj[i] = v;
+        a[t] = i > j ? v : (i == j ? beta : a[t]);
+      }
+      if (sub == 0) tau_s[j] = tau;
+    }
+    __syncthreads();
+    if (own && c > j) {
+      const double tau = tau_s[j];
+      if (tau != 0.0) {
+        double v[TM];
+        double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) {
+          v[t] = vj[sub + 8 * t];
+          if (t & 1) w1 = fma(v[t], a[t], w1);
+          else w0 = fma(v[t], a[t], w0);
+        }
+        const double w = group8_sum(w0 + w1) * tau;
+#pragma unroll
+        for (int t = 0; t < TM; ++t) a[t] = fma(-w, v[t], a[t]);
+      }
+    }
+  }
+  // reflectors and R to LDS (column c: R on and above the diagonal, v below)
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int i = sub + 8 * t;
+      if (i < k) A[i + ld * c] = a[t];
+    }
+  }
+  __syncthreads();
+  // ---- Q = H_0 ... H_{r-1} [I; 0], column by column (H_j e_c = e_c for j > c exactly)
+  const double rcc = own ? A[c + ld * c] : 1.0;
+  const double sgn = rcc < 0.0 ? -1.0 : 1.0;
+  {
+    double q[TM];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) q[t] = (sub + 8 * t) == c ? 1.0 : 0.0;
+    for (int j = r - 1; j >= 0; --j) {
+      const double tau = tau_s[j];
+      if (tau == 0.0) continue;
+      double v[TM];
+      double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = sub + 8 * t;
+        v[t] = i > j ? (i < k ? A[i + ld * j] : 0.0) : (i == j ? 1.0 : 0.0);
+        if (t & 1) w1 = fma(v[t], q[t], w1);
+        else w0 = fma(v[t], q[t], w0);
+      }
+      const double w = group8_sum(w0 + w1) * tau;
+#pragma unroll
+      for (int t = 0; t < TM; ++t) q[t] = fma(-w, v[t], q[t]);
+    }
+    if (own) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = sub + 8 * t;
+        if (i < k) job.Q[i + static_cast<int64_t>(k) * c] = sgn * q[t];
+      }
+    }
+  }
+  // ---- W = diag(sign R(i, i)) R, upper triangular (leading dimension r) in registers and LDS
+  double w[TM];
+  double wn = 0.0;
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const int i = sub + 8 * t;
+    double x = 0.0;
+    if (own && i <= c) x = A[i + ld * i] < 0.0 ? -a[t] : a[t];
+    w[t] = x;
+    wn = fma(x, x, wn);
+  }
+  __syncthreads();                        // A (the reflectors) is read; W and V may overwrite it
+  if (own) {
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int i = sub + 8 * t;
+      if (i < r) W[i + r * c] = w[t];
+    }
+  }
+  const double rnorm2 = block_sum(wn, red);   // its barriers also publish W
+  // ---- V = W^{-1} column by column: x = W^{-1} e_c, m = r-1 .. 0
+  double x[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) x[t] = (sub + 8 * t) == c ? 1.0 : 0.0;
+  bool nonsingular = true;
+  for (int m = r - 1; m >= 0; --m) {
+    const double dm = W[m + r * m];
+    nonsingular = nonsingular && dm > 0.0;
+    double xl = 0.0;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) xl += (sub + 8 * t) == m ? x[t] : 0.0;
+    const double xm = group8_sum(xl) / dm;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+      const int i = sub + 8 * t;
+      const double wim = i < m ? W[i + r * m] : 0.0;
+      x[t] = i == m ? xm : (i < m ? fma(-xm, wim, x[t]) : x[t]);
+    }
+  }
+  double vn = 0.0;
+#pragma unroll
+  for (int t = 0; t < TM; ++t) vn += (own && (sub + 8 * t) < r) ? x[t] * x[t] : 0.0;
+  const double inv2 = block_sum(vn, red);
+  const bool fast = nonsingular && (sqrt(rnorm2 * inv2) * eps_factor < 0.5);
+  if (fast) {
+    if (own) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        const int i = sub + 8 * t;
+        if (i < r) job.Pinv[i + r * c] = x[t];
+      }
+    }
+    if (tid == 0) kept[blockIdx.x] = r;
+    return true;
+  }
+  for (int e = tid; e < r * r; e += kThreads) V[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
+  __syncthreads();
+  return false;
+}
+
 __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double eps_factor, int* kept) {
   extern __shared__ double lds[];
   __shared__ double red[4];
@@ -96,6 +264,15 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   double* W = Qm;                // r x r (after Q is stored): R, then the Jacobi columns
   double* V = A;                 // r x r (after R is extracted): R^{-1}, or right singular vectors
 
+  __shared__ double vb[2 * 8 * 16];
+  const int tm = r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
+  if (tm != 0) {
+    const bool f = tm == 4    ? qr_regs<4>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                   : tm == 6 ? qr_regs<6>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                   : tm == 8 ? qr_regs<8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                             : qr_regs<16>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept);
+    if (f) return;
+  } else {
   for (int e = tid; e < k * r; e += kThreads) A[e % k + ld * (e / k)] = job.Om[e];
   __syncthreads();
 
@@ -188,6 +365,7 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   }
   for (int e = tid; e < r * r; e += kThreads) V[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
   __syncthreads();
+  }
 
   // ---- one-sided Jacobi on the columns of W (r x r)
   const int R2 = r + (r & 1);                 // pad to even with a virtual zero column
