@@ -119,13 +119,17 @@ __global__ __launch_bounds__(256) void bgemm64_kernel(GJobList L) {
   for (int v = 0; v < 4; ++v) part[(16 * wm + 4 * v + lg) * TN + 16 * wn + l16] = acc[v];
 }
 
-// One workgroup per tile of a split job: C = (accumulate ? C : 0) + alpha * sum of the
-// partial tiles in split order (8 interleaved sums per element, fixed combination), so
-// results do not depend on scheduling.  A launch of its own: the kernel boundary makes
-// the partials visible without a device-wide fence.
+// Four workgroups per tile of a split job, one element a thread: C = (accumulate ? C :
+// 0) + alpha * sum of the partial tiles in split order (32 interleaved sums, combined
+// pairwise in a fixed tree), so results do not depend on scheduling and a thread keeps
+// 32 loads in flight.  A launch of its own: the kernel boundary makes the partials
+// visible without a device-wide fence.
+constexpr int kCombineParts = 4;          // workgroups per 32 x 32 tile
+static_assert(kCombineParts * 256 == TM * TN, "one tile element per thread");
 __global__ __launch_bounds__(256) void bgemm64_combine_kernel(GJobList L) {
   const int tid = threadIdx.x;
-  const int64_t b = blockIdx.x;
+  const int64_t b = blockIdx.x / kCombineParts;
+  const int part_of = static_cast<int>(blockIdx.x % kCombineParts);
   int ji = 0;
   while (ji + 1 < L.n && L.jobs[ji + 1].first_tile <= b) ++ji;
   const GJob& J = L.jobs[ji];
@@ -137,36 +141,28 @@ __global__ __launch_bounds__(256) void bgemm64_combine_kernel(GJobList L) {
   const int64_t cb = rel / J.tiles_m;
   const int64_t m0 = tm * TM, n0 = tn * TN;
   const double* parts = J.part + tile_id * J.splits * (TM * TN);
-  constexpr int EPT = TM * TN / 256;
-  double s8[EPT][8];
+  const int e = part_of * 256 + tid;        // element of the tile
+  constexpr int NS = 32;
+  double s[NS];
 #pragma unroll
-  for (int u = 0; u < EPT; ++u)
+  for (int q = 0; q < NS; ++q) s[q] = 0.0;
+  // split sp + q goes to sum q; splits past the end add nothing (static indices only)
+  for (int sp = 0; sp < J.splits; sp += NS) {
+    double v[NS];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) s8[u][q] = 0.0;
-  // split sp + q goes to sum q; splits past the end add nothing (every index of s8
-  // stays static, so it lives in registers)
-  for (int sp = 0; sp < J.splits; sp += 8) {
-    double v[EPT][8];
+    for (int q = 0; q < NS; ++q) v[q] = sp + q < J.splits ? parts[(sp + q) * (TM * TN) + e] : 0.0;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-#pragma unroll
-      for (int u = 0; u < EPT; ++u)
-        v[u][q] = sp + q < J.splits ? parts[(sp + q) * (TM * TN) + tid + 256 * u] : 0.0;
-#pragma unroll
-    for (int u = 0; u < EPT; ++u)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) s8[u][q] += v[u][q];
+    for (int q = 0; q < NS; ++q) s[q] += v[q];
   }
 #pragma unroll
-  for (int u = 0; u < EPT; ++u) {
-    const int e = tid + 256 * u;
-    const int mm = e / TN, nn = e % TN;
-    const int64_t m = m0 + mm, n = n0 + nn;
-    const double s = ((s8[u][0] + s8[u][1]) + (s8[u][2] + s8[u][3])) + ((s8[u][4] + s8[u][5]) + (s8[u][6] + s8[u][7]));
-    if (m >= J.M || n >= J.N) continue;
-    double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
-    *c = (J.accumulate ? *c : 0.0) + J.alpha * s;
-  }
+  for (int w = NS / 2; w > 0; w /= 2)
+#pragma unroll
+    for (int q = 0; q < w; ++q) s[q] += s[q + w];
+  const int mm = e / TN, nn = e % TN;
+  const int64_t m = m0 + mm, n = n0 + nn;
+  if (m >= J.M || n >= J.N) return;
+  double* c = J.C + cb * J.sCc + m * J.sCm + n * J.sCn;
+  *c = (J.accumulate ? *c : 0.0) + J.alpha * s[0];
 }
 
 }  // namespace
@@ -207,7 +203,8 @@ void launch_bgemm64(std::vector<GJob>& jobs, double* part, size_t part_elems, hi
     if (blocks > 0)
       hipLaunchKernelGGL(bgemm64_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, L);
     if (ctiles > 0)
-      hipLaunchKernelGGL(bgemm64_combine_kernel, dim3(static_cast<unsigned>(ctiles)), dim3(256), 0, st, LC);
+      hipLaunchKernelGGL(bgemm64_combine_kernel, dim3(static_cast<unsigned>(ctiles * kCombineParts)), dim3(256), 0,
+                         st, LC);
   }
 }
 
