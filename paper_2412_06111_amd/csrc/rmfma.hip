@@ -22,8 +22,7 @@
 namespace ttnn {
 namespace {
 
-constexpr int kRows = 128;     // output rows per workgroup
-constexpr int kWaves = 4;      // each wave: 2 row blocks of 16
+constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
 
 template <int DT, int NCB>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
