@@ -37,9 +37,12 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
                                                const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
                                                TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
                                                int j0) {
+  // operand and DRM entries of step s + 1 are loaded into registers (and the DRM rows
+  // of step s + 2 computed) while step s is multiplied out of LDS
+  constexpr int NA = BR * BK / 256, NB = BK * BJ / 256;
   __shared__ float As[BK][BR + 4];
   __shared__ float Bs[BK][BJ + 4];
-  __shared__ int64_t drow[BK];
+  __shared__ int64_t drow[2][BK];
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wave = tid >> 6;
@@ -52,27 +55,25 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
 #pragma unroll
   for (int cb = 0; cb < BJ / 16; ++cb) acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
 
-  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
-    if (tid < BK) {
-      const int64_t kk = kb + tid;
-      int64_t r = -1;
-      if (kk < k_end) {
-        if (RIGHT) r = amap(kk % L) + bmap(kk / L);
-        else r = amap(kk);
-      }
-      drow[tid] = r;
+  auto drm_row = [&](int64_t kk) -> int64_t {
+    if (kk >= k_end) return -1;
+    return RIGHT ? amap(kk % L) + bmap(kk / L) : amap(kk);
+  };
+  auto a_pos = [&](int e, int& kk, int& rr) {
+    if (kk_contig) {
+      kk = e % BK;
+      rr = e / BK;
+    } else {
+      rr = e % BR;
+      kk = e / BR;
     }
+  };
+  float ra[NA], rb[NB];
+  auto fetch = [&](int64_t kb, int buf) {
 #pragma unroll
-    for (int s = 0; s < (BR * BK) / 256; ++s) {
-      const int e = tid + 256 * s;
+    for (int s = 0; s < NA; ++s) {
       int kk, rr;
-      if (kk_contig) {
-        kk = e % BK;
-        rr = e / BK;
-      } else {
-        rr = e % BR;
-        kk = e / BR;
-      }
+      a_pos(tid + 256 * s, kk, rr);
       const int64_t kg = kb + kk;
       const int64_t rg = row0 + rr;
       float v = 0.f;
@@ -83,20 +84,41 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
         const int64_t q = m / L;
         v = ldf(H, l + L * (i + n * q));
       }
-      As[kk][rr] = v;
+      ra[s] = v;
     }
-    __syncthreads();
 #pragma unroll
-    for (int s = 0; s < (BK * BJ) / 256; ++s) {
+    for (int s = 0; s < NB; ++s) {
       const int e = tid + 256 * s;
       const int jj = e % BJ;
       const int kk = e / BJ;
-      const int64_t r = drow[kk];
-      float v = 0.f;
-      if (r >= 0 && j0 + jj < ncols) v = ldf(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc);
-      Bs[kk][jj] = v;
+      const int64_t r = drow[buf][kk];
+      rb[s] = (r >= 0 && j0 + jj < ncols) ? ldf(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc) : 0.f;
+    }
+  };
+
+  if (tid < BK) {
+    drow[0][tid] = drm_row(k_begin + tid);
+    drow[1][tid] = drm_row(k_begin + BK + tid);
+  }
+  __syncthreads();
+  if (k_begin < k_end) fetch(k_begin, 0);
+  int buf = 0;
+  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+      int kk, rr;
+      a_pos(tid + 256 * s, kk, rr);
+      As[kk][rr] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int e = tid + 256 * s;
+      Bs[e / BJ][e % BJ] = rb[s];
     }
     __syncthreads();
+    // drow[buf] is free again (its step is staged): it takes the rows of step s + 2
+    if (kb + BK < k_end) fetch(kb + BK, buf ^ 1);
+    if (tid < BK) drow[buf][tid] = drm_row(kb + 2 * BK + tid);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
       const float a = As[4 * s + lg][16 * wave + l16];
@@ -105,6 +127,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
         acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[4 * s + lg][16 * cb + l16], acc[cb], 0, 0, 0);
     }
     __syncthreads();
+    buf ^= 1;
   }
 
   // lane holds C[16 wave + 4 lg + v][16 cb + l16]
