@@ -7,6 +7,7 @@
 //   Psi_0 at the root               (T contracted with Y_c^T over every child c)
 // Omega_t = Y_t^T R_t and Psi_t = (kron_c Y_c^T) R_t are formed on demand.
 #include <algorithm>
+#include <cstring>
 #include <map>
 
 #include "engine.hpp"
@@ -386,6 +387,10 @@ void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hi
   const size_t nops = items[0]->size();
   for (const auto* it : items)
     TTNN_REQUIRE(it->size() == nops, TTNN_E_INVALID, "batched updates of different tree shapes");
+  // every step's descriptor tables are built first and staged in one copy, then the
+  // steps are launched in order from the staged tables
+  std::vector<BatchedGemm> gp(nops);
+  std::vector<BatchedReduce> rp(nops);
   std::vector<GemmArgs> gs;
   std::vector<ReduceTask> rs;
   for (size_t k = 0; k < nops; ++k) {
@@ -401,9 +406,38 @@ void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hi
       r.nchunks = nch;
       rs.push_back(r);
     }
-    launch_gemm_batched(gs, st);
-    launch_reduce_batched(rs, st);
+    gp[k] = plan_gemm_batched(gs);
+    rp[k] = plan_reduce_batched(rs);
   }
+  constexpr size_t kAlignD = 64;
+  auto aligned = [](size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; };
+  std::vector<size_t> og(nops), of(nops), orr(nops);
+  size_t total = 0;
+  for (size_t k = 0; k < nops; ++k) {
+    og[k] = total;
+    total = aligned(total + gp[k].tasks.size() * sizeof(GemmTask));
+    of[k] = total;
+    total = aligned(total + rp[k].folds.size() * sizeof(ReduceTask));
+    orr[k] = total;
+    total = aligned(total + rp[k].tasks.size() * sizeof(ReduceTask));
+  }
+  if (total == 0) return;
+  std::vector<char> host(total, 0);
+  for (size_t k = 0; k < nops; ++k) {
+    if (!gp[k].tasks.empty()) std::memcpy(host.data() + og[k], gp[k].tasks.data(), gp[k].tasks.size() * sizeof(GemmTask));
+    if (!rp[k].folds.empty())
+      std::memcpy(host.data() + of[k], rp[k].folds.data(), rp[k].folds.size() * sizeof(ReduceTask));
+    if (!rp[k].tasks.empty())
+      std::memcpy(host.data() + orr[k], rp[k].tasks.data(), rp[k].tasks.size() * sizeof(ReduceTask));
+  }
+  StagingLock lock;
+  char* d = static_cast<char*>(stage_descriptors(host.data(), total, st));
+  for (size_t k = 0; k < nops; ++k) {
+    launch_gemm_staged(gp[k], reinterpret_cast<const GemmTask*>(d + og[k]), st);
+    launch_reduce_staged(rp[k], reinterpret_cast<const ReduceTask*>(d + of[k]),
+                         reinterpret_cast<const ReduceTask*>(d + orr[k]), st);
+  }
+  fence_descriptors(st);
 }
 
 namespace {

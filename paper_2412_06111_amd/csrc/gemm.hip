@@ -546,14 +546,17 @@ int launch_gemm(const GemmArgs& a, hipStream_t st) {
   return nch;
 }
 
-void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t st) {
-  std::vector<GemmTask> tasks;
-  tasks.reserve(args.size());
-  int64_t blocks = 0;
+BatchedGemm plan_gemm_batched(const std::vector<GemmArgs>& args) {
+  BatchedGemm b;
+  if (args.empty()) return b;
+  b.right = args[0].right;
+  b.th = args[0].th;
+  b.td = args[0].td;
+  b.out_f32 = args[0].out_f32;
+  b.tasks.reserve(args.size());
   for (const GemmArgs& a : args) {
-    TTNN_REQUIRE(a.right == args[0].right && a.th == args[0].th && a.td == args[0].td &&
-                     a.out_f32 == args[0].out_f32,
-                 TTNN_E_INVALID, "batched contraction with mixed kinds");
+    TTNN_REQUIRE(a.right == b.right && a.th == b.th && a.td == b.td && a.out_f32 == b.out_f32, TTNN_E_INVALID,
+                 "batched contraction with mixed kinds");
     GemmTask t{};
     const int nch = gemm_chunks(a, &t.kchunk);
     if (nch == 0) continue;
@@ -573,57 +576,76 @@ void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t st) {
     t.row_blocks = (rows + BR - 1) / BR;
     t.nch = nch;
     t.col_blocks = (a.ncols + BJ - 1) / BJ;
-    t.first_block = blocks;
-    blocks += t.row_blocks * t.nch * t.col_blocks;
-    tasks.push_back(t);
+    t.first_block = b.blocks;
+    b.blocks += t.row_blocks * t.nch * t.col_blocks;
+    b.tasks.push_back(t);
   }
-  if (tasks.empty()) return;
-  TTNN_REQUIRE(blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+  TTNN_REQUIRE(b.blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+  return b;
+}
+
+void launch_gemm_staged(const BatchedGemm& b, const GemmTask* d, hipStream_t st) {
+  if (b.tasks.empty()) return;
+  const int nt = static_cast<int>(b.tasks.size());
+  if (b.right) batched_dispatch<true>(b.th, b.td, b.out_f32, d, nt, b.blocks, st);
+  else batched_dispatch<false>(b.th, b.td, b.out_f32, d, nt, b.blocks, st);
+}
+
+void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t st) {
+  const BatchedGemm b = plan_gemm_batched(args);
+  if (b.tasks.empty()) return;
   StagingLock lock;
-  const GemmTask* d = static_cast<const GemmTask*>(stage_descriptors(tasks.data(), tasks.size() * sizeof(GemmTask), st));
-  const int nt = static_cast<int>(tasks.size());
-  if (args[0].right) batched_dispatch<true>(args[0].th, args[0].td, args[0].out_f32, d, nt, blocks, st);
-  else batched_dispatch<false>(args[0].th, args[0].td, args[0].out_f32, d, nt, blocks, st);
+  const GemmTask* d =
+      static_cast<const GemmTask*>(stage_descriptors(b.tasks.data(), b.tasks.size() * sizeof(GemmTask), st));
+  launch_gemm_staged(b, d, st);
   fence_descriptors(st);
 }
 
-void launch_reduce_batched(const std::vector<ReduceTask>& in, hipStream_t st) {
+BatchedReduce plan_reduce_batched(const std::vector<ReduceTask>& in) {
   // the same two passes as launch_reduce, so batched and single results are bitwise equal
-  std::vector<ReduceTask> folds, tasks;
-  int64_t fblocks = 0, blocks = 0;
+  BatchedReduce b;
   for (ReduceTask t : in) {
     if (t.rows <= 0 || t.ncols <= 0 || t.nchunks <= 0) continue;
     const int64_t E = t.rows * t.ncols;
     if (fold_pays(t.nchunks, E)) {
       ReduceTask f = t;
       f.groups = (t.nchunks + kFold - 1) / kFold;
-      f.first_block = fblocks;
-      fblocks += (E + 255) / 256 * f.groups;
-      folds.push_back(f);
+      f.first_block = b.fblocks;
+      b.fblocks += (E + 255) / 256 * f.groups;
+      b.folds.push_back(f);
       t.nchunks = f.groups;
       t.cstride = E * kFold;
     }
     t.nblocks = grid_for(E);
-    t.first_block = blocks;
-    blocks += t.nblocks;
-    tasks.push_back(t);
+    t.first_block = b.blocks;
+    b.blocks += t.nblocks;
+    b.tasks.push_back(t);
   }
-  if (tasks.empty()) return;
-  if (!folds.empty()) {
-    TTNN_REQUIRE(fblocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
-    StagingLock lock;
-    const ReduceTask* d =
-        static_cast<const ReduceTask*>(stage_descriptors(folds.data(), folds.size() * sizeof(ReduceTask), st));
-    hipLaunchKernelGGL(fold_batched_kernel, dim3(static_cast<unsigned>(fblocks)), dim3(256), 0, st, d,
-                       static_cast<int>(folds.size()));
-    fence_descriptors(st);
-  }
-  TTNN_REQUIRE(blocks < (int64_t(1) << 31), TTNN_E_INVALID, "batched launch too large");
+  TTNN_REQUIRE(b.fblocks < (int64_t(1) << 31) && b.blocks < (int64_t(1) << 31), TTNN_E_INVALID,
+               "batched launch too large");
+  return b;
+}
+
+void launch_reduce_staged(const BatchedReduce& b, const ReduceTask* dfolds, const ReduceTask* dtasks,
+                          hipStream_t st) {
+  if (b.tasks.empty()) return;
+  if (!b.folds.empty())
+    hipLaunchKernelGGL(fold_batched_kernel, dim3(static_cast<unsigned>(b.fblocks)), dim3(256), 0, st, dfolds,
+                       static_cast<int>(b.folds.size()));
+  hipLaunchKernelGGL(reduce_batched_kernel, dim3(static_cast<unsigned>(b.blocks)), dim3(256), 0, st, dtasks,
+                     static_cast<int>(b.tasks.size()));
+}
+
+void launch_reduce_batched(const std::vector<ReduceTask>& in, hipStream_t st) {
+  const BatchedReduce b = plan_reduce_batched(in);
+  if (b.tasks.empty()) return;
   StagingLock lock;
-  const ReduceTask* d =
-      static_cast<const ReduceTask*>(stage_descriptors(tasks.data(), tasks.size() * sizeof(ReduceTask), st));
-  hipLaunchKernelGGL(reduce_batched_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, d,
-                     static_cast<int>(tasks.size()));
+  const ReduceTask* df = nullptr;
+  if (!b.folds.empty())
+    df = static_cast<const ReduceTask*>(stage_descriptors(b.folds.data(), b.folds.size() * sizeof(ReduceTask), st));
+  const ReduceTask* dt =
+      static_cast<const ReduceTask*>(stage_descriptors(b.tasks.data(), b.tasks.size() * sizeof(ReduceTask), st));
+  launch_reduce_staged(b, df, dt, st);
   fence_descriptors(st);
 }
 

@@ -74,6 +74,24 @@ struct ReduceTask {
 void launch_gemm_batched(const std::vector<GemmArgs>& args, hipStream_t stream);
 // Fixed-order partial sums of several contractions in one launch (see launch_reduce).
 void launch_reduce_batched(const std::vector<ReduceTask>& tasks, hipStream_t stream);
+// The same two launches split into building the descriptor tables on the host and
+// launching from tables already staged on the device, so that a caller can stage the
+// tables of many launches in one copy.
+struct BatchedGemm {
+  std::vector<GemmTask> tasks;
+  int64_t blocks = 0;
+  bool right = true, out_f32 = false;
+  int th = TTNN_F64, td = TTNN_F64;
+};
+BatchedGemm plan_gemm_batched(const std::vector<GemmArgs>& args);
+void launch_gemm_staged(const BatchedGemm& b, const GemmTask* d_tasks, hipStream_t stream);
+struct BatchedReduce {
+  std::vector<ReduceTask> folds, tasks;
+  int64_t fblocks = 0, blocks = 0;
+};
+BatchedReduce plan_reduce_batched(const std::vector<ReduceTask>& tasks);
+void launch_reduce_staged(const BatchedReduce& b, const ReduceTask* d_folds, const ReduceTask* d_tasks,
+                          hipStream_t stream);
 // Copy `bytes` of host descriptors into device memory that stays valid for work
 // enqueued on `stream` after this call and before the next fence_descriptors on it
 // (pinned staging ring, reused once the fenced work has finished).
