@@ -59,8 +59,8 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
 
   // staging map: thread -> row tid / CPR (+ RPR per round), chunk tid % CPR
   const int sr = tid / CPR, sc = (tid % CPR) * V;
-  vec_t ra[AR], rb[BRN];
-  auto gload = [&](int64_t k) {
+  vec_t ra0[AR], rb0[BRN], ra1[AR], rb1[BRN];   // two steps of loads in flight
+  auto gload = [&](int64_t k, vec_t* ra, vec_t* rb) {
     const bool live = k < k_end;
     const int64_t kk = k + sc;
     const int64_t q = kk / L, l = kk - q * L;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
       rb[u] = (live && j < r) ? *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(j) * m + kk) : vec_t{};
     }
   };
-  auto lstore = [&](int buf) {
+  auto lstore = [&](int buf, const vec_t* ra, const vec_t* rb) {
 #pragma unroll
     for (int u = 0; u < AR; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPR * u) * PITCH + sc]) = ra[u];
 #pragma unroll
@@ -90,12 +90,7 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[b][cb] = zero;
 
-  gload(k_begin);
-  lstore(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k = k_begin; k < k_end; k += KS) {
-    gload(k + KS);                          // the next step's rows in flight
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < KS / KG; ++h) {
       const int kl = h * KG + V * lg;
@@ -122,9 +117,23 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
         }
       }
     }
-    lstore(buf ^ 1);                        // its previous contents were read before the last barrier
+  };
+
+  // step s is staged in LDS buffer s % 2 and its loads were issued two steps earlier
+  gload(k_begin, ra0, rb0);
+  gload(k_begin + KS, ra1, rb1);
+  lstore(0, ra0, rb0);
+  __syncthreads();
+  for (int64_t k = k_begin; k < k_end; k += 2 * KS) {
+    gload(k + 2 * KS, ra0, rb0);             // step s + 2
+    compute(0);                              // step s
+    lstore(1, ra1, rb1);                     // step s + 1 (buffer 1 was read before the last barrier)
     __syncthreads();
-    buf ^= 1;
+    if (k + KS >= k_end) break;
+    gload(k + 3 * KS, ra1, rb1);             // step s + 3
+    compute(1);                              // step s + 1
+    lstore(0, ra0, rb0);                     // step s + 2
+    __syncthreads();
   }
 
   // partial of chunk c: part[(c n + i) r + j]
