@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--variants", default="ttnn,sttnn")
     ap.add_argument("--dtypes", default="f32,f64,bf16")
     ap.add_argument("--headline", default="sttnn:f32")
+    ap.add_argument("--precision-ranks", default="16,64",
+                    help="extra STTNN BF16 and FP64 runs at these sketch ranks (p = r/2)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
@@ -162,17 +164,43 @@ def copy_rate(nbytes=1 << 30, reps=10):
 
 
 # ---------------------------------------------------------------- GPU run
-def run_gpu(args, T_dev64, variant, dtype):
+def read_sketches(plan, tree):
+    """Every node sketch of the plan's last update (R, Omega, Psi; Psi only at the root),
+    as FP64 host arrays keyed by (node modes, kind)."""
+    import paper_2412_06111_amd as P
+    out = {}
+    for nd in tree.nodes:
+        cid = plan.node(nd.modes)
+        for kind in ((P.SK_PSI,) if nd.id == 0 else (P.SK_R, P.SK_OMEGA, P.SK_PSI)):
+            out[(tuple(nd.modes), kind)] = plan.read_sketch(cid, kind).cpu().numpy()
+    return out
+
+
+def sketch_rel_errors(sk, ref):
+    """Per node, the largest relative Frobenius error of its sketches against `ref`."""
+    import numpy as np
+    per = {}
+    for (modes, kind), a in sk.items():
+        b = ref[(modes, kind)]
+        e = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        key = ",".join(str(m) for m in modes)
+        per[key] = max(per.get(key, 0.0), e)
+    return per
+
+
+def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
     import torch
     import paper_2412_06111_amd as P
     from oracle.tree import T4
 
+    rank = args.rank if rank is None else rank
+    over = args.over if over is None else over
     dims = (args.n,) * 4
     stream = torch.cuda.current_stream()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record()
-    plan = P.Plan(T4, dims, args.rank, args.over, variant=variant, dtype=dtype, seed=1)
+    plan = P.Plan(T4, dims, rank, over, variant=variant, dtype=dtype, seed=1)
     t1.record()
     torch.cuda.synchronize()
     drm_ms = t0.elapsed_time(t1)
@@ -219,6 +247,8 @@ def run_gpu(args, T_dev64, variant, dtype):
         e2, n2 = P.diff_norms(That, T_dev64)
         res["approx_rel_error"] = (e2 / n2) ** 0.5
         del That
+    if tree is not None:
+        res["_sketches"] = read_sketches(plan, tree)
     del X
     plan.close()
     torch.cuda.empty_cache()
@@ -369,22 +399,48 @@ def main():
     tree_def = O.Tree(O.T4, T.shape, args.rank, args.over)
 
     results = {}
+
+    def measure(variant, dtype, rank, over, key, ref=None):
+        """One configuration; keeps its sketches when it is the FP64 reference (ref is
+        None and dtype f64), else reports their errors against `ref`."""
+        tree = O.Tree(O.T4, T.shape, rank, over)
+        r = run_gpu(args, T_dev64, variant, dtype, rank, over, tree=tree)
+        sk = r.pop("_sketches")
+        if ref is not None:
+            per = sketch_rel_errors(sk, ref)
+            r["sketch_rel_error_vs_fp64_path"] = per
+            r["sketch_rel_error_vs_fp64_path_max"] = max(per.values())
+        flops, drm_entries, N = work_counts(tree, variant)
+        r["rank"], r["oversample"] = rank, over
+        r["flops"] = flops
+        r["algorithmic_bytes"] = N * ESIZE[dtype] + drm_entries * ESIZE[dtype]
+        r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
+        r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
+        r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
+        kf, kb = sweep_counts(tree, variant, dtype)
+        r["sweep_flops"] = kf
+        r["sweep_algorithmic_bytes"] = kb
+        r["sweep_GBps"] = kb / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9
+        r["sweep_TFLOPs"] = kf / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12
+        results[key] = r
+        print(f"# {key}: {json.dumps(r)}", file=sys.stderr, flush=True)
+        return sk
+
+    # FP64 first in each variant: its sketches are the reference the other dtypes'
+    # sketch errors are reported against (the FP64 path is itself held to 1e-10 of the
+    # FP64 oracle by the GPU parity tests; the oracle is too slow at this size)
+    dtypes = args.dtypes.split(",")
+    dtypes = (["f64"] if "f64" in dtypes else []) + [d for d in dtypes if d != "f64"]
     for variant in args.variants.split(","):
-        for dtype in args.dtypes.split(","):
-            r = run_gpu(args, T_dev64, variant, dtype)
-            flops, drm_entries, N = work_counts(tree_def, variant)
-            r["flops"] = flops
-            r["algorithmic_bytes"] = N * ESIZE[dtype] + drm_entries * ESIZE[dtype]
-            r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
-            r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
-            r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
-            kf, kb = sweep_counts(tree_def, variant, dtype)
-            r["sweep_flops"] = kf
-            r["sweep_algorithmic_bytes"] = kb
-            r["sweep_GBps"] = kb / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9
-            r["sweep_TFLOPs"] = kf / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12
-            results[f"{variant}:{dtype}"] = r
-            print(f"# {variant} {dtype}: {json.dumps(r)}", file=sys.stderr, flush=True)
+        ref = None
+        for dtype in dtypes:
+            sk = measure(variant, dtype, args.rank, args.over, f"{variant}:{dtype}", ref)
+            if dtype == "f64":
+                ref = sk
+    # the precision workload's other sketch ranks: STTNN BF16 against FP64, p = r/2
+    for rr in [int(x) for x in args.precision_ranks.split(",") if x]:
+        ref = measure("sttnn", "f64", rr, rr // 2, f"sttnn:f64:r{rr}")
+        measure("sttnn", "bf16", rr, rr // 2, f"sttnn:bf16:r{rr}", ref)
 
     key = args.headline if args.headline in results else next(iter(results))
     hv, hd = key.split(":")
