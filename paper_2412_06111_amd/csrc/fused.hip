@@ -38,6 +38,7 @@ struct SttnnArgs {
   int TA, TB, CB;
   const void *XA, *X1, *YA, *Y1, *X2, *XB;
   void *PRA, *PZA, *PR1, *PR2, *PRB;
+  void* Z1;            // Z1-out mode: Y_1^T slab for every (i_2, column), [i_2][i_B][j1]
 };
 
 // Wide fragment: V = 16 / sizeof(T) consecutive contraction values of one lane (one
@@ -164,7 +165,10 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
   }
 }
 
-template <int DT, int R, int KP, int B2, int SC, bool TT>
+// ZO (STTNN only): instead of contracting Z1 with X_2 in the tile (which re-reads the
+// X_2 rows of the column band in every row tile), write Z1 out; R_2 is then one
+// streaming contraction that reads X_2 once (used where X_2 is large, r = 64).
+template <int DT, int R, int KP, int B2, int SC, bool TT, bool ZO>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
   using W = Wide<P>;
@@ -392,7 +396,19 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           PZA[(static_cast<int64_t>(tA) * KP + jA) * nB + iB] = zA[rb][v];
         }
     }
-    if constexpr (!TT && D2Q) {
+    if constexpr (ZO) {
+      // the tile's Z1 rows for this column block: B2 runs of SC * KP contiguous values
+      __syncthreads();
+      typedef T zvec __attribute__((ext_vector_type(16 / sizeof(T))));
+      constexpr int ZV = 16 / sizeof(T);
+      constexpr int NZ = SC * KP / ZV;
+      T* Z1g = static_cast<T*>(a.Z1);
+      for (int e = tid; e < B2 * NZ; e += kThreadsF) {
+        const int i2l = e / NZ, q = e % NZ;
+        const zvec v = *reinterpret_cast<const zvec*>(&Z1s[i2l * Lay::ZS + q * ZV]);
+        *reinterpret_cast<zvec*>(&Z1g[((i2_0 + i2l) * nB + iBbase) * KP + q * ZV]) = v;
+      }
+    } else if constexpr (!TT && D2Q) {
       __syncthreads();
       // (d2) R_2[i2 rows] += Z1 (rows i2l, K = (column, j1)) . X_2 rows (column, j1) on
       // the 16-block 4 x 4 x 1 MFMA: only B2 <= 4 rows are live, so 16 x 16 tiles would
@@ -472,7 +488,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
         PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[c][v];
       }
   }
-  if constexpr (TT) return;
+  if constexpr (TT || ZO) return;
   __syncthreads();
   Acc* red = reinterpret_cast<Acc*>(smem);          // 8 waves x 16 rows x R
   if constexpr (D2Q) {
@@ -561,8 +577,9 @@ __device__ inline void reduce_transpose_tile(const Acc* P, int nt, int64_t tstri
 
 // Sum the tile partials in a fixed order into the FP64 state.  Blocks [0, nbA) do R_A
 // (PRA [tB][iA][R] -> RA[iA + nA j]) and [nbA, nbA + nbZ) Z_A (PZA [tA][jA][iB] ->
-// ZA[jA + k iB]) tile by tile; the remaining blocks do R_1 and the last segment, R_2
-// (STTNN; PR2 [tB][n2][R]) or, in TTNN mode, R_B (PRB [tA][R][nB]), entry by entry.
+// ZA[jA + k iB]) tile by tile; the remaining blocks do R_1 and the last segment, entry
+// by entry: R_2 (mode 0, STTNN; PR2 [tB][n2][R]), R_B (mode 1, TTNN; PRB [tA][R][nB]) or
+// nothing (mode 2, STTNN with Z1 written out).
 template <typename Acc>
 __global__ __launch_bounds__(256) void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2,
                                                        int TA, int TB, int64_t n2, int64_t nA, int64_t nB, int R,
@@ -583,14 +600,14 @@ __global__ __launch_bounds__(256) void sttnn_t4_reduce(const Acc* PRA, const Acc
     return;
   }
   const int64_t nR1 = static_cast<int64_t>(N1) * R;
-  const int64_t nR2 = tt ? nB * R : n2 * R;
+  const int64_t nR2 = tt == 1 ? nB * R : tt == 0 ? n2 * R : 0;
   const int64_t total = nR1 + nR2;
   const int64_t nb = gridDim.x - nbA - nbZ;
   for (int64_t f = (b - nbA - nbZ) * blockDim.x + threadIdx.x; f < total; f += nb * blockDim.x) {
     if (f < nR1) {
       const int64_t i1 = f / R, j = f % R;
       R1[i1 + N1 * j] += alpha * sum_strided(PR1 + i1 * R + j, TA * TB, static_cast<int64_t>(N1) * R);
-    } else if (!tt) {
+    } else if (tt == 0) {
       const int64_t g = f - nR1;
       const int64_t i2 = g / R, j = g % R;
       R2[i2 + n2 * j] += alpha * sum_strided(PR2 + i2 * R + j, TB, n2 * R);
@@ -650,7 +667,7 @@ struct Shape {
 // that the slab, the DRM rows of a sub-tile and the Z1 stash fit the LDS budget).
 template <int DT, int R, bool TT>
 constexpr int b2_of() {
-  return DT == TTNN_BF16 ? (R >= 64 ? 4 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : (R >= 64 || TT ? 2 : 4);
+  return DT == TTNN_BF16 ? (R >= 64 ? 2 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : (R >= 64 || TT ? 2 : 4);
 }
 template <int DT>
 constexpr int sc_of() {
@@ -658,24 +675,30 @@ constexpr int sc_of() {
 }
 
 Shape shape_for(int dt, int R, bool tt) {
-  if (dt == TTNN_BF16) return {R >= 64 ? 4 : 8, 64};
+  if (dt == TTNN_BF16) return {R >= 64 ? 2 : 8, 64};
   if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 32};
   return {R >= 64 || tt ? 2 : 4, 32};
 }
 
 template <int DT, int R, int KP>
-void launch_sttnn(bool tt, const SttnnArgs& a, hipStream_t st) {
+void launch_sttnn(bool tt, bool zout, const SttnnArgs& a, hipStream_t st) {
   constexpr int SC = sc_of<DT>();
   constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>();
-  if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
-  else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false>), dim3(a.TA * a.TB), dim3(kThreadsF), 0, st, a);
+  const dim3 grid(a.TA * a.TB);
+  if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true, false>), grid, dim3(kThreadsF), 0, st, a);
+  else if constexpr (R == 64) {
+    if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
+    else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
+  } else {
+    hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
+  }
 }
 
 template <int DT>
-void launch_sttnn_dt(int R, bool tt, const SttnnArgs& a, hipStream_t st) {
-  if (R == 16) launch_sttnn<DT, 16, 32>(tt, a, st);
-  else if (R == 32) launch_sttnn<DT, 32, 48>(tt, a, st);
-  else launch_sttnn<DT, 64, 96>(tt, a, st);
+void launch_sttnn_dt(int R, bool tt, bool zout, const SttnnArgs& a, hipStream_t st) {
+  if (R == 16) launch_sttnn<DT, 16, 32>(tt, zout, a, st);
+  else if (R == 32) launch_sttnn<DT, 32, 48>(tt, zout, a, st);
+  else launch_sttnn<DT, 64, 96>(tt, zout, a, st);
 }
 
 int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; }
@@ -766,7 +789,10 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.PRA = P.alloc(as * TB * nAs * R);
   F.PZA = P.alloc(as * TA * KP * nB);
   F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
+  // Z1-out mode where X_2 re-reads dominate (r = 64) and the streaming R_2 applies
+  F.zout = !tt && R == 64 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, dt);
   if (tt) F.PRB = P.alloc(as * TA * R * nB);
+  else if (F.zout) F.Z1 = P.alloc(es * KP * n2 * nB);
   else F.PR2 = P.alloc(as * TB * n2 * R);
   F.enabled = true;
 }
@@ -796,9 +822,10 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
   a.PR1 = F.PR1;
   a.PR2 = F.PR2;
   a.PRB = F.PRB;
-  if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, F.tt, a, st);
-  else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, F.tt, a, st);
-  else launch_sttnn_dt<TTNN_F64>(F.R, F.tt, a, st);
+  a.Z1 = F.Z1;
+  if (P.dtype == TTNN_BF16) launch_sttnn_dt<TTNN_BF16>(F.R, F.tt, F.zout, a, st);
+  else if (P.dtype == TTNN_F32) launch_sttnn_dt<TTNN_F32>(F.R, F.tt, F.zout, a, st);
+  else launch_sttnn_dt<TTNN_F64>(F.R, F.tt, F.zout, a, st);
   if (P.timing) {
     TTNN_HIP(hipEventRecord(P.sweep_ev[1], st));
     P.sweep_recorded = true;
@@ -810,21 +837,30 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
   const void* plast = F.tt ? F.PRB : F.PR2;
   const int64_t nbA = ((F.nA + kRTX - 1) / kRTX) * ((F.R + kRTY - 1) / kRTY);
   const int64_t nbZ = ((F.k + kRTX - 1) / kRTX) * ((F.nB + kRTY - 1) / kRTY);
-  const int64_t rest = static_cast<int64_t>(N1) * F.R + (F.tt ? F.nB : F.n2) * F.R;
+  const int mode = F.tt ? 1 : F.zout ? 2 : 0;
+  const int64_t rest = static_cast<int64_t>(N1) * F.R + (F.tt ? F.nB : F.zout ? 0 : F.n2) * F.R;
   const int64_t nbE = std::min<int64_t>((rest + 255) / 256, 2048);
   const dim3 grid(static_cast<unsigned>(nbA + nbZ + nbE));
   if (P.dtype == TTNN_F64)
     hipLaunchKernelGGL(sttnn_t4_reduce<double>, grid, dim3(256), 0, st, static_cast<const double*>(F.PRA),
                        static_cast<const double*>(F.PZA), static_cast<const double*>(F.PR1),
                        static_cast<const double*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, mode,
                        static_cast<int>(nbA), static_cast<int>(nbZ));
   else
     hipLaunchKernelGGL(sttnn_t4_reduce<float>, grid, dim3(256), 0, st, static_cast<const float*>(F.PRA),
                        static_cast<const float*>(F.PZA), static_cast<const float*>(F.PR1),
                        static_cast<const float*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
-                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, F.tt ? 1 : 0,
+                       P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, mode,
                        static_cast<int>(nbA), static_cast<int>(nbZ));
+  if (F.zout) {
+    // R_2 += alpha Z1 X_2: Z1 [i_2][(i_B, j1)] against X_2 [j][(i_B, j1)], one pass over both
+    const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
+    const int nch = launch_right_mfma(F.Z1, P.dtype, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, st);
+    const Node& n2d = P.nodes[F.node_2];
+    launch_reduce(P.partial, nch, F.n2, F.R, 0, alpha, box_rows(P, n2d.first, n2d.last, off, ext), n2d.n, n2d.R, 1, 1,
+                  st);
+  }
   done_nodes->assign({F.node_A, F.node_1, node_last});
   done_prefixes->assign({pre});
   return true;

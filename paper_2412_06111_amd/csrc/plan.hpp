@@ -44,6 +44,8 @@ struct FusedT4 {
   int64_t n2 = 0, nA = 0, nB = 0;
   int node_A = -1, node_1 = -1, node_2 = -1, node_B = -1;
   bool tt = false;                         // TTNN mode: R_B instead of the R_2 chain
+  bool zout = false;                       // STTNN: Z1 written out, R_2 by a streaming contraction
+  void* Z1 = nullptr;
   void *XA = nullptr, *X1 = nullptr, *YA = nullptr, *Y1 = nullptr, *X2 = nullptr, *XB = nullptr;
   void *PRA = nullptr, *PZA = nullptr, *PR1 = nullptr, *PR2 = nullptr, *PRB = nullptr;
 };
