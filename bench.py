@@ -100,27 +100,39 @@ def work_counts(tree, variant):
     return flops, drm_entries, N
 
 
-def sweep_counts(tree, variant, dtype):
-    """Algorithmic flops and bytes of the sweep kernel alone.
+def sweep_counts(tree, variant, dtype, kind):
+    """Algorithmic flops and bytes of the timed sweep kernel alone (`kind` as reported
+    by the library, ttnn_sweep_kind).
 
-    STTNN on ((1,2),(3,4)) runs a one-pass kernel that reads the tensor once and the
-    DRMs X_A, X_1, X_2, Y_A, Y_1 once, and writes R_A, Z_A = Y_A^T T^{A}, R_1, R_2 once
-    (FP32, FP64 for an FP64 plan); the remaining nodes are formed from Z_A afterwards.
-    Otherwise the sweep is the whole update and its counts are those of the pass."""
+    1: the one-pass STTNN kernel reads the tensor once and the DRMs X_A, X_1, X_2, Y_A,
+       Y_1 once, and writes R_A, Z_A = Y_A^T T^{A}, R_1, R_2 once (FP32; FP64 for an
+       FP64 plan); the remaining nodes are formed from Z_A afterwards.
+    2: the same kernel without R_2: it writes Z1 = Y_1^T T^{(1)} (k x N / n_1 in the
+       plan dtype) and reads no X_2; R_2 is a separate streaming contraction.
+    3: the TTNN-mode kernel: tensor once, X_A, X_1, Y_A, X_B once; R_A, Z_A, R_1, R_B out.
+    0: the sweep is the whole update and its counts are those of the pass."""
     flops, drm, N = work_counts(tree, variant)
     s = ESIZE[dtype]
-    if variant != "sttnn":
+    if kind == 0:
         return flops, N * s + drm * s
     A, B = tree[0].children
     l1, l2 = tree[A].children
     r, k = tree[A].rank, tree[A].k
     nA, nB, n1 = tree.n_of(A), tree.n_of(B), tree.n_of(l1)
-    drm_k = (tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + tree.x_rows(l2, variant) * r
-             + nA * k + n1 * k)
-    out = nA * r + k * nB + n1 * r + tree.n_of(l2) * r
     acc = 8 if dtype == "f64" else 4
-    kflops = 2 * N * (2 * r + 2 * k) + 2 * (N // n1) * k * r
-    return kflops, N * s + drm_k * s + out * acc
+    if kind == 3:
+        drm_k = tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + nA * k + tree.x_rows(B, variant) * r
+        out = nA * r + k * nB + n1 * r + nB * r
+        return 2 * N * (3 * r + k), N * s + drm_k * s + out * acc
+    drm_k = tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + nA * k + n1 * k
+    out = nA * r + k * nB + n1 * r
+    kflops = 2 * N * (2 * r + 2 * k)
+    if kind == 1:
+        drm_k += tree.x_rows(l2, variant) * r
+        out += tree.n_of(l2) * r
+        kflops += 2 * (N // n1) * k * r
+        return kflops, N * s + drm_k * s + out * acc
+    return kflops, N * s + drm_k * s + out * acc + k * (N // n1) * s
 
 
 def measured_traffic(key):
@@ -241,7 +253,8 @@ def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
     sketch_ms = [a.elapsed_time(b) for a, b in evs]
     res = {"ms_per_step": ms_step, "sketch_ms_avg": sum(sketch_ms) / len(sketch_ms),
            "sketch_ms_min": min(sketch_ms), "sweep_kernel_ms_avg": sum(sweep_ms) / len(sweep_ms),
-           "sweep_kernel_ms_min": min(sweep_ms), "drm_generation_ms": drm_ms, "footprint_bytes": plan.footprint()}
+           "sweep_kernel_ms_min": min(sweep_ms), "drm_generation_ms": drm_ms, "footprint_bytes": plan.footprint(),
+           "sweep_kind": plan.sweep_kind()}
     if not args.no_error:
         That = plan.reconstruct(cores)
         e2, n2 = P.diff_norms(That, T_dev64)
@@ -417,7 +430,7 @@ def main():
         r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
         r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
         r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
-        kf, kb = sweep_counts(tree, variant, dtype)
+        kf, kb = sweep_counts(tree, variant, dtype, r["sweep_kind"])
         r["sweep_flops"] = kf
         r["sweep_algorithmic_bytes"] = kb
         r["sweep_GBps"] = kb / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9
@@ -457,8 +470,10 @@ def main():
         r["roofline"]["frac"] = r["roofline"]["achieved"] / r["roofline"]["peak"]
     roof = dict(head["roofline"])
     roof["traffic"] = measured_traffic(key)
-    roof["kernel"] = (("sttnn_t4_kernel (one-pass STTNN sweep)" if hv == "sttnn" else "whole TTNN update")
-                      + f", {hd}, {args.n}^4, r={args.rank}, p={args.over}; HIP events on the launch stream")
+    kind_name = {0: "whole update", 1: "sttnn_t4_kernel (one-pass STTNN sweep)",
+                 2: "sttnn_t4_kernel (one-pass STTNN sweep writing Z1; R_2 by a separate streaming kernel)",
+                 3: "sttnn_t4_kernel in TTNN mode (R_A, Z_A, R_1, R_B)"}[head["sweep_kind"]]
+    roof["kernel"] = kind_name + f", {hd}, {args.n}^4, r={args.rank}, p={args.over}; HIP events on the launch stream"
     roof["algorithmic_bytes_per_launch"] = head["sweep_algorithmic_bytes"]
     roof["flops_per_launch"] = head["sweep_flops"]
     copy = copy_rate()

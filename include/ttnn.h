@@ -238,6 +238,12 @@ ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32
  * adds no synchronisation to the update itself. */
 ttnn_status ttnn_set_timing(ttnn_plan_t plan, int32_t on);
 ttnn_status ttnn_sweep_time_ms(ttnn_plan_t plan, float* ms);
+/* What the timed sweep of a whole-tensor update computes, for accounting its work:
+ * 0 the whole update (no one-pass kernel applies); 1 one-pass STTNN kernel (R_A, Z_A,
+ * R_1, R_2 = Z1 X_2 in the kernel); 2 one-pass STTNN kernel writing Z1 out (R_2 formed
+ * after it by a streaming contraction); 3 one-pass TTNN-mode kernel (R_A, Z_A, R_1,
+ * R_B). */
+ttnn_status ttnn_sweep_kind(ttnn_plan_t plan, int32_t* kind);
 
 /* Zero the accumulators and clear a sticky error. */
 ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream);

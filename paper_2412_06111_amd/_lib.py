@@ -65,6 +65,7 @@ def _load():
         "ttnn_assemble_async": [vp, C.POINTER(vp), vp],
         "ttnn_assemble_status": [vp, vp],
         "ttnn_assemble_status_async": [vp, vp, vp],
+        "ttnn_sweep_kind": [vp, C.POINTER(i32)],
         "ttnn_reconstruct": [vp, C.POINTER(vp), vp, i32, vp],
         "ttnn_diff_norms": [vp, i32, vp, i64, C.POINTER(dbl), vp],
         "ttnn_sketch_shape": [vp, i32, i32, P64, P64],
@@ -230,6 +231,13 @@ class Plan:
 
     def set_timing(self, on=True):
         check(lib.ttnn_set_timing(self.handle, 1 if on else 0))
+
+    def sweep_kind(self):
+        """0 whole update, 1 STTNN one-pass kernel, 2 STTNN one-pass kernel writing Z1
+        out, 3 TTNN-mode one-pass kernel (see ttnn_sweep_kind)."""
+        k = C.c_int32()
+        check(lib.ttnn_sweep_kind(self.handle, C.byref(k)))
+        return k.value
 
     def sweep_time_ms(self):
         """Elapsed time of the last update's sweep kernel (waits for it)."""

@@ -438,6 +438,16 @@ ttnn_status ttnn_sweep_time_ms(ttnn_plan_t plan, float* ms) {
   });
 }
 
+ttnn_status ttnn_sweep_kind(ttnn_plan_t plan, int32_t* kind) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !kind) throw Error{TTNN_E_INVALID, "plan or kind is NULL"};
+    const auto& F = P->fused;
+    *kind = !F.enabled ? 0 : F.tt ? 3 : F.zout ? 2 : 1;
+    return TTNN_OK;
+  });
+}
+
 const char* ttnn_status_string(ttnn_status s) {
   switch (s) {
     case TTNN_OK: return "ok";

@@ -686,12 +686,8 @@ void launch_sttnn(bool tt, bool zout, const SttnnArgs& a, hipStream_t st) {
   constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>();
   const dim3 grid(a.TA * a.TB);
   if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true, false>), grid, dim3(kThreadsF), 0, st, a);
-  else if constexpr (R == 64) {
-    if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
-    else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
-  } else {
-    hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
-  }
+  else if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
+  else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
 }
 
 template <int DT>
@@ -790,7 +786,7 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.PZA = P.alloc(as * TA * KP * nB);
   F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
   // Z1-out mode where X_2 re-reads dominate (r = 64) and the streaming R_2 applies
-  F.zout = !tt && R == 64 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, dt);
+  F.zout = !tt && R >= 32 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, dt);
   if (tt) F.PRB = P.alloc(as * TA * R * nB);
   else if (F.zout) F.Z1 = P.alloc(es * KP * n2 * nB);
   else F.PR2 = P.alloc(as * TB * n2 * R);
