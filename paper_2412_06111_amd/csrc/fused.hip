@@ -165,6 +165,56 @@ __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int
   }
 }
 
+// Wait for every outstanding LDS read of the wave (s_waitcnt lgkmcnt(0)).  While a
+// global-to-LDS copy is in flight the compiler's own waits before an LDS operand
+// cover all reads issued so far, including prefetches; waiting here, before the next
+// step's reads are issued, lets those reads run under the current step's products.
+__device__ inline void lds_wait_all() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+// acc[rb] += A[rb rows, K = i1] . slab[i1, column iBl] over the whole slab (K = N1),
+// A rows delivered by loadA(rb, kk) (wide fragment at contraction offset kk).  The
+// operands of step kw + 1 are loaded before the MFMAs of step kw are issued, so the
+// LDS latency of one step is hidden behind the products of the previous one.
+template <typename P, int NB, typename LoadA>
+__device__ inline void bd_chain(const typename P::T* Ms, int iBl, int lg, LoadA&& loadA,
+                                typename P::CFrag (&acc)[NB]) {
+  using W = Wide<P>;
+  using vec = typename W::vec;
+  using ZN = Swz<typename P::T, N1>;
+  constexpr int V = W::V, SUB = W::SUB, KG = W::KG, NK = N1 / KG;
+  static_assert(NK % 2 == 0, "steps in pairs");
+  auto load = [&](int kw, vec& bw, vec (&ay)[NB]) {
+    const int kk = kw * KG + V * lg;
+    bw = W::load(&Ms[ZN::off(iBl, kk)]);
+#pragma unroll
+    for (int rb = 0; rb < NB; ++rb) ay[rb] = loadA(rb, kk);
+  };
+  auto mma = [&](const vec& bw, const vec (&ay)[NB]) {
+#pragma unroll
+    for (int sb = 0; sb < SUB; ++sb)
+#pragma unroll
+      for (int rb = 0; rb < NB; ++rb) acc[rb] = P::mfma(W::frag(ay[rb], sb), W::frag(bw, sb), acc[rb]);
+  };
+  {
+    vec bw0, ay0[NB], bw1, ay1[NB];
+    load(0, bw0, ay0);
+#pragma unroll
+    // each wait, its loads and the products that follow stay in this order
+    for (int kw = 0; kw < NK; kw += 2) {
+      lds_wait_all();
+      load(kw + 1, bw1, ay1);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bw0, ay0);
+      __builtin_amdgcn_sched_barrier(0);
+      lds_wait_all();
+      if (kw + 2 < NK) load(kw + 2, bw0, ay0);
+      __builtin_amdgcn_sched_barrier(0);
+      mma(bw1, ay1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+}
+
 // ZO (STTNN only): instead of contracting Z1 with X_2 in the tile (which re-reads the
 // X_2 rows of the column band in every row tile), write Z1 out; R_2 is then one
 // streaming contraction that reads X_2 once (used where X_2 is large, r = 64).
@@ -192,6 +242,16 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   static_assert(!D2Q || KW % 64 == 0, "4 x 4 block steps");
   static_assert(Lay::TOTAL <= 160 * 1024, "LDS budget");
   static_assert(8 * 16 * R * sizeof(Acc) <= Lay::TOTAL, "reduction scratch");
+  // With 32-column sub-tiles the (b)/(d1) products occupy waves 0-3 only; then (a)/(c)
+  // go to waves 4-7 (two 16-row blocks of i1 each), so that each SIMD runs one wave of
+  // either phase side by side instead of one wave alone through (b)/(d1).  Not where
+  // the doubled accumulators would crowd the register file: FP64 at r >= 32, r = 64,
+  // and, at r = 32, the forms that keep R_2 or R_B accumulators as well.
+  constexpr bool SPLIT =
+      NCB == 2 && (ZO || R <= 16) && 2 * (B2 + 1) * CBR * int(sizeof(CFrag) / 4) <= 80;
+  constexpr int RB1 = SPLIT ? 2 : 1;        // 16-row blocks of i1 per wave in (a)/(c)
+  // (b)/(d1) chains software-pipelined where the second register set fits
+  constexpr bool PIPE = DT != TTNN_F64 && (R <= 16 || (R == 32 && (ZO || (TT && DT == TTNN_F32))));
 
   __shared__ __align__(16) char smem[Lay::TOTAL];
   T* Z1s = reinterpret_cast<T*>(smem + Lay::OFF_Z1);
@@ -200,11 +260,18 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
 
-  // tile of this workgroup; tiles of one column band share an XCD (L2) when possible
+  // tile of this workgroup.  Workgroups are dealt to the eight XCDs round robin; each
+  // XCD takes a range of slab groups across every column band when TA allows, so the
+  // tiles that share an L2 run through the same slabs in step and fetch each Y_A row
+  // once between them (X_A, the smaller operand, is then shared by fewer tiles).
   int tA, tB;
   {
     const int w = blockIdx.x;
-    if (a.TB % 8 == 0) {
+    if (a.TA % 8 == 0) {
+      const int x = w % 8, j = w / 8, gpx = a.TA / 8;
+      tA = x * gpx + j % gpx;
+      tB = j / gpx;
+    } else if (a.TB % 8 == 0) {
       const int x = w % 8, j = w / 8, bpx = a.TB / 8;
       tB = x * bpx + j / a.TA;
       tA = j % a.TA;
@@ -235,8 +302,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using ZN = Swz<T, N1>;                    // staged rows of N1 elements (slab columns, Y rows)
   using ZX = Swz<T, SC>;                    // staged rows of SC elements (X_A, X_1 rows)
 
-  CFrag rA[B2][CBR];
-  CFrag r1[CBR];
+  CFrag rA[RB1][B2][CBR];
+  CFrag r1[RB1][CBR];
   CFrag r2[CBR];
   // FP32 (d2): 16 blocks of 4 x 4 per column group (block = lane / 4, row i2l = register
   // index, column 4 g + lane % 4); summed over blocks and waves at the end of the tile
@@ -245,14 +312,15 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   CFrag zB[TT ? KBB : 1];
   const CFrag zero = {};
 #pragma unroll
-  for (int i = 0; i < B2; ++i)
+  for (int h = 0; h < RB1; ++h)
 #pragma unroll
-    for (int c = 0; c < CBR; ++c) rA[i][c] = zero;
+    for (int c = 0; c < CBR; ++c) {
+      r1[h][c] = zero;
 #pragma unroll
-  for (int c = 0; c < CBR; ++c) {
-    r1[c] = zero;
-    r2[c] = zero;
-  }
+      for (int i = 0; i < B2; ++i) rA[h][i][c] = zero;
+    }
+#pragma unroll
+  for (int c = 0; c < CBR; ++c) r2[c] = zero;
 #pragma unroll
   for (int g = 0; g < (D2Q ? R / 4 : 1); ++g) r2q[g] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   // roles in the (b)/(d1) phase: Z_A, or Z1 (STTNN) / R_B^T (TTNN), for one 16-column
@@ -261,6 +329,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   const int cblk = wave % NCB;
   const bool bd_zA = (wave / NCB) == 0;
   const int iBl = 16 * cblk + l16;         // column of the sub-tile in the (b)/(d1) phase
+  const bool ac_active = !SPLIT || wave >= 2 * NCB;
+  const int i1base = SPLIT ? 32 * (wave - 2 * NCB) : 16 * wave;   // first i1 row of (a)/(c)
 
   const int nsub = a.CB * B2;
   issue(0, 0);
@@ -288,13 +358,45 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
 
       // (a) R_A rows of this slab and (c) R_1: A = slab (rows i1, K = columns)
-      const int i1 = 16 * wave + l16;
+      if constexpr (!SPLIT) {
+        const int i1 = 16 * wave + l16;
+#pragma unroll
+        for (int kw = 0; kw < SC / KG; ++kw) {
+          const int kk = kw * KG + V * lg;
+          vec aw;
+#pragma unroll
+          for (int e = 0; e < V; ++e) aw[e] = Ms[ZN::off(kk + e, i1)];
+          vec bA[CBR], b1[CBR];
+#pragma unroll
+          for (int c = 0; c < CBR; ++c) {
+            const int j = 16 * c + l16;
+            if constexpr (Lay::STAGE_X) {
+              bA[c] = W::load(XAs + ZX::off(j, kk));
+              b1[c] = W::load(X1s + ZX::off(j, kk));
+            } else {
+              bA[c] = W::load(XA + static_cast<int64_t>(j) * nB + iBbase + kk);
+              b1[c] = W::load(X1 + (static_cast<int64_t>(j) * n2 + i2) * nB + iBbase + kk);
+            }
+          }
+#pragma unroll
+          for (int sb = 0; sb < SUB; ++sb) {
+            const auto af = W::frag(aw, sb);
+#pragma unroll
+            for (int c = 0; c < CBR; ++c) {
+              rA[0][i2l][c] = P::mfma(af, W::frag(bA[c], sb), rA[0][i2l][c]);
+              r1[0][c] = P::mfma(af, W::frag(b1[c], sb), r1[0][c]);
+            }
+          }
+        }
+      } else if (ac_active) {
 #pragma unroll
       for (int kw = 0; kw < SC / KG; ++kw) {
         const int kk = kw * KG + V * lg;
-        vec aw;
+        vec aw[RB1];
 #pragma unroll
-        for (int e = 0; e < V; ++e) aw[e] = Ms[ZN::off(kk + e, i1)];
+        for (int h = 0; h < RB1; ++h)
+#pragma unroll
+          for (int e = 0; e < V; ++e) aw[h][e] = Ms[ZN::off(kk + e, i1base + 16 * h + l16)];
         vec bA[CBR], b1[CBR];
 #pragma unroll
         for (int c = 0; c < CBR; ++c) {
@@ -308,19 +410,56 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
           }
         }
 #pragma unroll
-        for (int sb = 0; sb < SUB; ++sb) {
-          const auto af = W::frag(aw, sb);
+        for (int sb = 0; sb < SUB; ++sb)
 #pragma unroll
-          for (int c = 0; c < CBR; ++c) {
-            rA[i2l][c] = P::mfma(af, W::frag(bA[c], sb), rA[i2l][c]);
-            r1[c] = P::mfma(af, W::frag(b1[c], sb), r1[c]);
+          for (int h = 0; h < RB1; ++h) {
+            const auto af = W::frag(aw[h], sb);
+#pragma unroll
+            for (int c = 0; c < CBR; ++c) {
+              rA[h][i2l][c] = P::mfma(af, W::frag(bA[c], sb), rA[h][i2l][c]);
+              r1[h][c] = P::mfma(af, W::frag(b1[c], sb), r1[h][c]);
+            }
           }
-        }
       }
+      }  // ac_active
 
       // (b) Z_A += Y_A^T slab; (b') TTNN: R_B^T += X_B^T slab; (d1) STTNN: Z1 = Y_1^T slab.
       // B = slab (K = i1, columns)
-      if (bd_active && bd_zA) {
+      // (d1) result: the Z1 rows of this slab go to the LDS stash
+      auto stash_z1 = [&](const CFrag (&acc)[KB]) {
+#pragma unroll
+        for (int rb = 0; rb < KB; ++rb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int j1 = 16 * rb + P::crow(lane, v);
+            Z1s[i2l * Lay::ZS + iBl * KP + j1] = P::from_acc(acc[rb][v]);
+          }
+      };
+      if constexpr (PIPE) {
+        if (bd_active && bd_zA) {
+          bd_chain<P, KB>(Ms, iBl, lg, [&](int rb, int kk) -> vec {
+            const int jr = 16 * rb + l16;
+            if constexpr (Lay::STAGE_YA) return W::load(YAs + ZN::off(jr, kk));
+            else return W::load(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
+          }, zA);
+        } else if (TT && bd_active) {
+          bd_chain<P, (TT ? KBB : 1)>(Ms, iBl, lg, [&](int rb, int kk) -> vec {
+            const int jr = 16 * rb + l16;
+            if constexpr (Lay::STAGE_YA) return W::load(XBs + ZN::off(jr, kk));
+            else return W::load(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
+          }, zB);
+        } else if (!TT && bd_active) {
+          CFrag acc[KB];
+#pragma unroll
+          for (int rb = 0; rb < KB; ++rb) acc[rb] = zero;
+          bd_chain<P, KB>(Ms, iBl, lg, [&](int rb, int kk) -> vec {
+            const int jr = 16 * rb + l16;
+            if constexpr (Lay::STAGE_Y1) return W::load(Y1s + ZN::off(jr, kk));
+            else return W::load(Y1 + static_cast<int64_t>(jr) * N1 + kk);
+          }, acc);
+          stash_z1(acc);
+        }
+      } else if (bd_active && bd_zA) {
 #pragma unroll 2
         for (int kw = 0; kw < N1 / KG; ++kw) {
           const int kk = kw * KG + V * lg;
@@ -471,22 +610,24 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   }  // cb
 
   // ---- partial results of the tile
-  {
+  if (ac_active) {
     Acc* PRA = static_cast<Acc*>(a.PRA);
     Acc* PR1 = static_cast<Acc*>(a.PR1);
 #pragma unroll
-    for (int c = 0; c < CBR; ++c)
+    for (int h = 0; h < RB1; ++h)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int i1 = 16 * wave + P::crow(lane, v);
-        const int j = 16 * c + l16;
+      for (int c = 0; c < CBR; ++c)
 #pragma unroll
-        for (int i2l = 0; i2l < B2; ++i2l) {
-          const int64_t iA = (i2_0 + i2l) * N1 + i1;
-          PRA[(static_cast<int64_t>(tB) * nA + iA) * R + j] = rA[i2l][c][v];
+        for (int v = 0; v < 4; ++v) {
+          const int i1 = i1base + 16 * h + P::crow(lane, v);
+          const int j = 16 * c + l16;
+#pragma unroll
+          for (int i2l = 0; i2l < B2; ++i2l) {
+            const int64_t iA = (i2_0 + i2l) * N1 + i1;
+            PRA[(static_cast<int64_t>(tB) * nA + iA) * R + j] = rA[h][i2l][c][v];
+          }
+          PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[h][c][v];
         }
-        PR1[((static_cast<int64_t>(tA) * a.TB + tB) * N1 + i1) * R + j] = r1[c][v];
-      }
   }
   if constexpr (TT || ZO) return;
   __syncthreads();
