@@ -8,7 +8,9 @@ sketched in one pass and the TTN cores are assembled in FP64.
 
 One step = sketch update of the whole tensor (fused one-pass kernel + deterministic
 reduction) + FP64 epilogue + recovery phase (QR, Jacobi SVD, eps-pseudoinverse,
-cores).  DRM generation happens once per plan, before timing.
+cores).  DRM generation happens once per plan, before timing.  The default warm-up
+(40 steps, about 50 ms of FP32 work) brings the GPU to its sustained clock before the
+timed steps; after a few steps from idle the sweep still runs about 10% slower.
 
     python bench.py [--steps K] [--warmup W] [--variants ttnn,sttnn] [--dtypes f32,f64,bf16]
 
@@ -32,8 +34,8 @@ ESIZE = {"f64": 8, "f32": 4, "bf16": 2}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--rank", type=int, default=32)
     ap.add_argument("--over", type=int, default=16)

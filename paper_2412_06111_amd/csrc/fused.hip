@@ -718,14 +718,15 @@ __device__ inline void reduce_transpose_tile(const Acc* P, int nt, int64_t tstri
 
 // Sum the tile partials in a fixed order into the FP64 state.  Blocks [0, nbA) do R_A
 // (PRA [tB][iA][R] -> RA[iA + nA j]) and [nbA, nbA + nbZ) Z_A (PZA [tA][jA][iB] ->
-// ZA[jA + k iB]) tile by tile; the remaining blocks do R_1 and the last segment, entry
-// by entry: R_2 (mode 0, STTNN; PR2 [tB][n2][R]), R_B (mode 1, TTNN; PRB [tA][R][nB]) or
-// nothing (mode 2, STTNN with Z1 written out).
+// ZA[jA + k iB]) tile by tile, [nbA + nbZ, + nb1) R_1 (16 lanes per entry), and the
+// remaining blocks the last segment, entry by entry: R_2 (mode 0, STTNN; PR2
+// [tB][n2][R]), R_B (mode 1, TTNN; PRB [tA][R][nB]) or nothing (mode 2, STTNN with Z1
+// written out).
 template <typename Acc>
 __global__ __launch_bounds__(256) void sttnn_t4_reduce(const Acc* PRA, const Acc* PZA, const Acc* PR1, const Acc* PR2,
                                                        int TA, int TB, int64_t n2, int64_t nA, int64_t nB, int R,
                                                        int KP, int k, double alpha, double* RA, double* ZA, double* R1,
-                                                       double* R2, int tt, int nbA, int nbZ) {
+                                                       double* R2, int tt, int nbA, int nbZ, int nb1) {
   __shared__ double tile[kRTY][kRTX + 1];
   const int64_t b = blockIdx.x;
   if (b < nbA) {
@@ -741,20 +742,31 @@ __global__ __launch_bounds__(256) void sttnn_t4_reduce(const Acc* PRA, const Acc
     return;
   }
   const int64_t nR1 = static_cast<int64_t>(N1) * R;
+  if (b < nbA + nbZ + nb1) {
+    // R_1: TA * TB partials per entry, 16 lanes per entry (lane g sums partials
+    // t = g mod 16), the 16 sums combined by a fixed butterfly
+    const int g = threadIdx.x & 15;
+    const int64_t f = ((b - nbA - nbZ) * blockDim.x + threadIdx.x) >> 4;
+    if (f >= nR1) return;                       // whole 16-lane groups leave together
+    const int64_t i1 = f / R, j = f % R;
+    const int nt = TA * TB;
+    const int64_t st = static_cast<int64_t>(N1) * R;
+    double x = g < nt ? sum_strided(PR1 + i1 * R + j + g * st, (nt - g + 15) / 16, 16 * st) : 0.0;
+    x += __shfl_xor(x, 8);
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 1);
+    if (g == 0) R1[i1 + N1 * j] += alpha * x;
+    return;
+  }
   const int64_t nR2 = tt == 1 ? nB * R : tt == 0 ? n2 * R : 0;
-  const int64_t total = nR1 + nR2;
-  const int64_t nb = gridDim.x - nbA - nbZ;
-  for (int64_t f = (b - nbA - nbZ) * blockDim.x + threadIdx.x; f < total; f += nb * blockDim.x) {
-    if (f < nR1) {
-      const int64_t i1 = f / R, j = f % R;
-      R1[i1 + N1 * j] += alpha * sum_strided(PR1 + i1 * R + j, TA * TB, static_cast<int64_t>(N1) * R);
-    } else if (tt == 0) {
-      const int64_t g = f - nR1;
-      const int64_t i2 = g / R, j = g % R;
+  const int64_t nb = gridDim.x - nbA - nbZ - nb1;
+  for (int64_t f = (b - nbA - nbZ - nb1) * blockDim.x + threadIdx.x; f < nR2; f += nb * blockDim.x) {
+    if (tt == 0) {
+      const int64_t i2 = f / R, j = f % R;
       R2[i2 + n2 * j] += alpha * sum_strided(PR2 + i2 * R + j, TB, n2 * R);
     } else {
-      const int64_t g = f - nR1;
-      const int64_t j = g / nB, c = g % nB;
+      const int64_t j = f / nB, c = f % nB;
       R2[c + nB * j] += alpha * sum_strided(PR2 + j * nB + c, TA, static_cast<int64_t>(R) * nB);
     }
   }
@@ -975,21 +987,22 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
   const int64_t nbA = ((F.nA + kRTX - 1) / kRTX) * ((F.R + kRTY - 1) / kRTY);
   const int64_t nbZ = ((F.k + kRTX - 1) / kRTX) * ((F.nB + kRTY - 1) / kRTY);
   const int mode = F.tt ? 1 : F.zout ? 2 : 0;
-  const int64_t rest = static_cast<int64_t>(N1) * F.R + (F.tt ? F.nB : F.zout ? 0 : F.n2) * F.R;
+  const int64_t nb1 = (static_cast<int64_t>(N1) * F.R * 16 + 255) / 256;
+  const int64_t rest = (F.tt ? F.nB : F.zout ? 0 : F.n2) * F.R;
   const int64_t nbE = std::min<int64_t>((rest + 255) / 256, 2048);
-  const dim3 grid(static_cast<unsigned>(nbA + nbZ + nbE));
+  const dim3 grid(static_cast<unsigned>(nbA + nbZ + nb1 + nbE));
   if (P.dtype == TTNN_F64)
     hipLaunchKernelGGL(sttnn_t4_reduce<double>, grid, dim3(256), 0, st, static_cast<const double*>(F.PRA),
                        static_cast<const double*>(F.PZA), static_cast<const double*>(F.PR1),
                        static_cast<const double*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
                        P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, mode,
-                       static_cast<int>(nbA), static_cast<int>(nbZ));
+                       static_cast<int>(nbA), static_cast<int>(nbZ), static_cast<int>(nb1));
   else
     hipLaunchKernelGGL(sttnn_t4_reduce<float>, grid, dim3(256), 0, st, static_cast<const float*>(F.PRA),
                        static_cast<const float*>(F.PZA), static_cast<const float*>(F.PR1),
                        static_cast<const float*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
                        P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, mode,
-                       static_cast<int>(nbA), static_cast<int>(nbZ));
+                       static_cast<int>(nbA), static_cast<int>(nbZ), static_cast<int>(nb1));
   if (F.zout) {
     // R_2 += alpha Z1 X_2: Z1 [i_2][(i_B, j1)] against X_2 [j][(i_B, j1)], one pass over both
     const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
