@@ -72,7 +72,7 @@ struct Wide {
 // instead.  Staged rows are not padded: the 16-byte chunks of row r are stored in
 // XOR-swizzled order (chunk c at position c ^ (r mod 16, or mod the chunk count)),
 // so reads along a row and gathers down a column spread over the LDS banks.
-template <int DT, int R, int KP, int B2, int SC, bool TT>
+template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR = false>
 struct SttnnLayout {
   using P = Pol<DT>;
   using T = typename P::T;
@@ -91,17 +91,21 @@ struct SttnnLayout {
   static constexpr size_t YB = YAB + (TT ? size_t(R) * SXB * ESZ : 0);
   static constexpr size_t XB = size_t(R) * SX * ESZ;
   static constexpr size_t BUDGET = 156 * 1024;
-  static constexpr bool STAGE_YA = 2 * (MS + YB) + Z1 <= BUDGET;
-  static constexpr bool STAGE_X = STAGE_YA && 2 * (MS + YB + 2 * XB) + Z1 <= BUDGET;
+  // YR: the Y_A rows of the tile's B2 slabs stay in LDS for the whole tile (one copy per
+  // tile instead of one per sub-tile), after both stages
+  static constexpr size_t YRB = YR ? size_t(B2) * YAB : 0;
+  static constexpr bool STAGE_YA = !YR && 2 * (MS + YB) + Z1 <= BUDGET;
+  static constexpr bool STAGE_X = (STAGE_YA || YR) && 2 * (MS + (STAGE_YA ? YB : 0) + 2 * XB) + Z1 + YRB <= BUDGET;
   static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
   static constexpr size_t Y1B = size_t(KP) * SY * ESZ;
-  static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + Y1B <= BUDGET;
+  static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + YRB + Y1B <= BUDGET;
   static constexpr size_t OFF_YA = MS;                         // offsets within a stage
   static constexpr size_t OFF_XB = OFF_YA + YAB;               // TT: X_B rows after Y_A rows
   static constexpr size_t OFF_XA = OFF_YA + (STAGE_YA ? YB : 0);
   static constexpr size_t OFF_X1 = OFF_XA + (STAGE_X ? XB : 0);
   static constexpr size_t OFF_Z1 = 2 * STAGE;                 // after both stages
-  static constexpr size_t OFF_Y1 = OFF_Z1 + Z1;
+  static constexpr size_t OFF_YR = OFF_Z1 + Z1;
+  static constexpr size_t OFF_Y1 = OFF_YR + YRB;
   static constexpr size_t TOTAL = OFF_Y1 + (STAGE_Y1 ? Y1B : 0);
 };
 
@@ -142,10 +146,10 @@ __device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int rows, int 
 }
 
 // Issue the copies of the sub-tile (slab i2, columns col0 .. col0+SC-1) into one stage.
-template <int DT, int R, int KP, int B2, int SC, bool TT>
+template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR>
 __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int64_t col0, int wave, int lane) {
   using P = Pol<DT>;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
   using T = typename P::T;
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
   lds_dma_rows<T, N1>(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), SC, wave,
@@ -222,7 +226,9 @@ template <int DT, int R, int KP, int B2, int SC, bool TT, bool ZO>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
   using W = Wide<P>;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT>;
+  // FP32 Z1-out form at r = 32 (two slabs per tile): the tile's Y_A rows stay resident
+  static constexpr bool YR = ZO && DT == TTNN_F32 && R == 32;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
   using T = typename P::T;
   using Acc = typename P::Acc;
   using CFrag = typename P::CFrag;
@@ -294,11 +300,17 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // issue the copies of sub-tile s into stage buf
   auto issue = [&](int s, int buf) {
     const int cb = s / B2, i2l = s % B2;
-    sttnn_issue<DT, R, KP, B2, SC, TT>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC,
-                                       wave, lane);
+    sttnn_issue<DT, R, KP, B2, SC, TT, YR>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC,
+                                           wave, lane);
   };
-  // Y_1 rows, resident for the whole kernel
+  // Y_1 rows, resident for the whole kernel; YR: the Y_A rows of the tile's slabs
   if constexpr (Lay::STAGE_Y1) lds_dma_rows<T, N1>(Y1, N1, Y1s, KP, wave, lane);
+  T* YRs = reinterpret_cast<T*>(smem + Lay::OFF_YR);
+  if constexpr (YR) {
+#pragma unroll
+    for (int i2l = 0; i2l < B2; ++i2l)
+      lds_dma_rows<T, N1>(YA + (i2_0 + i2l) * N1, nA, YRs + i2l * KP * N1, KP, wave, lane);
+  }
   using ZN = Swz<T, N1>;                    // staged rows of N1 elements (slab columns, Y rows)
   using ZX = Swz<T, SC>;                    // staged rows of SC elements (X_A, X_1 rows)
 
@@ -352,7 +364,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       __syncthreads();                    // ... everyone's; and stage buf^1 is free again
       if (s + 1 < nsub) issue(s + 1, buf ^ 1);
       const T* Ms = reinterpret_cast<const T*>(stage_base(buf));
-      const T* YAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
+      const T* YAs = YR ? YRs + i2l * KP * N1 : reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
       const T* XBs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
       const T* XAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XA);
       const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
@@ -439,7 +451,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
         if (bd_active && bd_zA) {
           bd_chain<P, KB>(Ms, iBl, lg, [&](int rb, int kk) -> vec {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) return W::load(YAs + ZN::off(jr, kk));
+            if constexpr (Lay::STAGE_YA || YR) return W::load(YAs + ZN::off(jr, kk));
             else return W::load(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }, zA);
         } else if (TT && bd_active) {
@@ -468,7 +480,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
           for (int rb = 0; rb < KB; ++rb) {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) ay[rb] = W::load(YAs + ZN::off(jr, kk));
+            if constexpr (Lay::STAGE_YA || YR) ay[rb] = W::load(YAs + ZN::off(jr, kk));
             else ay[rb] = W::load(YA + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
 #pragma unroll
@@ -665,21 +677,21 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   }
 }
 
-// sum_{t < n} p[t * stride] in FP64 with four interleaved partial sums (t mod 4),
-// combined in a fixed order: four loads in flight per thread.
+// sum_{t < n} p[t * stride] in FP64 with eight interleaved partial sums (t mod 8),
+// combined in a fixed order: eight loads in flight per thread.
 template <typename Acc>
 __device__ inline double sum_strided(const Acc* p, int n, int64_t stride) {
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int t = 0;
-  for (; t + 4 <= n; t += 4) {
-    const Acc v0 = p[(t + 0) * stride], v1 = p[(t + 1) * stride], v2 = p[(t + 2) * stride], v3 = p[(t + 3) * stride];
-    s[0] += static_cast<double>(v0);
-    s[1] += static_cast<double>(v1);
-    s[2] += static_cast<double>(v2);
-    s[3] += static_cast<double>(v3);
+  for (; t + 8 <= n; t += 8) {
+    Acc v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(t + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += static_cast<double>(v[u]);
   }
   for (int q = 0; t < n; ++t, ++q) s[q] += static_cast<double>(p[t * stride]);
-  return (s[0] + s[1]) + (s[2] + s[3]);
+  return ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
 }
 
 // Tile of the transposing reductions: 16 output-fast x 32 input-fast entries per
@@ -818,28 +830,31 @@ struct Shape {
 
 // Tile shape per dtype: B2 slabs of i_2 per tile, SC columns per sub-tile (sized so
 // that the slab, the DRM rows of a sub-tile and the Z1 stash fit the LDS budget).
-template <int DT, int R, bool TT>
+// The FP32 Z1-out form at r = 32 takes two slabs, so that their Y_A rows stay in LDS.
+template <int DT, int R, bool TT, bool ZO = false>
 constexpr int b2_of() {
-  return DT == TTNN_BF16 ? (R >= 64 ? 2 : 8) : DT == TTNN_F32 ? (R >= 64 ? 2 : 4) : (R >= 64 || TT ? 2 : 4);
+  return DT == TTNN_BF16 ? (R >= 64 ? 2 : 8)
+         : DT == TTNN_F32 ? (R >= 64 || (ZO && R == 32) ? 2 : 4)
+                          : (R >= 64 || TT ? 2 : 4);
 }
 template <int DT>
 constexpr int sc_of() {
   return DT == TTNN_BF16 ? 64 : 32;
 }
 
-Shape shape_for(int dt, int R, bool tt) {
+Shape shape_for(int dt, int R, bool tt, bool zout) {
   if (dt == TTNN_BF16) return {R >= 64 ? 2 : 8, 64};
-  if (dt == TTNN_F32) return {R >= 64 ? 2 : 4, 32};
+  if (dt == TTNN_F32) return {R >= 64 || (zout && R == 32) ? 2 : 4, 32};
   return {R >= 64 || tt ? 2 : 4, 32};
 }
 
 template <int DT, int R, int KP>
 void launch_sttnn(bool tt, bool zout, const SttnnArgs& a, hipStream_t st) {
   constexpr int SC = sc_of<DT>();
-  constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>();
+  constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>(), B2Z = b2_of<DT, R, false, true>();
   const dim3 grid(a.TA * a.TB);
   if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true, false>), grid, dim3(kThreadsF), 0, st, a);
-  else if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
+  else if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2Z, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
   else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
 }
 
@@ -877,8 +892,11 @@ void fused_prepare(Plan& P, hipStream_t st) {
   else if (R == 64 && nA_.k <= 96) KP = 96;
   if (KP == 0) return;
   if (P.dims[0] != N1) return;
-  const Shape sh = shape_for(P.dtype, R, tt);
   const int64_t n2 = P.dims[1], nAs = N1 * n2, nB = P.N / nAs;
+  // Z1-out form (STTNN, r >= 32): Z1 is written out and R_2 formed by one streaming
+  // contraction that reads X_2 once, instead of re-reading X_2 in every row tile
+  const bool zout = !tt && R >= 32 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, P.dtype);
+  const Shape sh = shape_for(P.dtype, R, tt, zout);
   if (n2 % sh.B2 != 0 || nB % sh.SC != 0) return;
   const int TA = static_cast<int>(n2 / sh.B2);
   // column tiles: the fewest that give every compute unit a tile (else as many as divide)
@@ -938,8 +956,7 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.PRA = P.alloc(as * TB * nAs * R);
   F.PZA = P.alloc(as * TA * KP * nB);
   F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
-  // Z1-out mode where X_2 re-reads dominate (r = 64) and the streaming R_2 applies
-  F.zout = !tt && R >= 32 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, dt);
+  F.zout = zout;
   if (tt) F.PRB = P.alloc(as * TA * R * nB);
   else if (F.zout) F.Z1 = P.alloc(es * KP * n2 * nB);
   else F.PR2 = P.alloc(as * TB * n2 * R);
