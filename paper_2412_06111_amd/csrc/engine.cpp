@@ -502,6 +502,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
         a.sDc = 1;
         a.ncols = g.k;
         a.amap = box_rows(P, g.first, g.last, off, ext);
+        join_side(P, st);                       // shares the partial scratch
         left_op(P, a, chain_ptr(chain), 2, 1.0, st);
       }
       done[chain] = true;
@@ -539,6 +540,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
     a.sDc = 1;
     a.ncols = g.k;
     a.amap = box_rows(P, g.first, g.last, off, ext);
+    join_side(P, st);
     left_op(P, a, P.psi_root, 1, alpha, st);
   };
   do_root();
@@ -558,6 +560,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
       continue;
     }
     batch.flush();
+    join_side(P, st);
     if (pre.empty() && whole && t.Xt) {          // raw tensor, contiguous contraction: MFMA
       const int nch = launch_right_mfma(block, cd, L, n, Q, t.Xt, t.m, t.r, P.partial, P.partial_elems, st);
       launch_reduce(P.partial, nch, n, t.r, 0, alpha, box_rows(P, t.first, t.last, off, ext), t.n, t.R, 1, 1, st);
@@ -596,6 +599,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
   }
 
   batch.flush();
+  join_side(P, st);
 }
 }  // namespace
 

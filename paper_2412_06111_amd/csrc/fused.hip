@@ -869,6 +869,22 @@ int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; 
 
 }  // namespace
 
+// ---------------------------------------------------------------- side stream
+void fork_side(Plan& P, hipStream_t st) {
+  if (!P.side) {
+    TTNN_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+    for (hipEvent_t& e : P.side_ev) TTNN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  TTNN_HIP(hipEventRecord(P.side_ev[0], st));
+  TTNN_HIP(hipStreamWaitEvent(P.side, P.side_ev[0], 0));
+}
+
+void join_side(Plan& P, hipStream_t st) {
+  if (!P.side_pending) return;
+  TTNN_HIP(hipStreamWaitEvent(st, P.side_ev[1], 0));
+  P.side_pending = false;
+}
+
 // ---------------------------------------------------------------- plan-time setup
 void fused_prepare(Plan& P, hipStream_t st) {
   FusedT4& F = P.fused;
@@ -997,6 +1013,25 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
     P.sweep_recorded = true;
   }
 
+  if (F.zout) {
+    // R_2 += alpha Z1 X_2: Z1 [i_2][(i_B, j1)] against X_2 [j][(i_B, j1)], one pass over
+    // both.  It needs only Z1 and X_2, so it runs on the plan's side stream beside the
+    // partial reduction and the FP64 jobs that follow on the caller's stream (it uses the
+    // partial scratch; the update joins it before any other user of that scratch).
+    // Every kernel of this stretch streams from HBM or waits on it, so the overlap gains
+    // little at FP32 (the kernels slow each other down); at BF16, where Z1 is half the
+    // size, it does.
+    fork_side(P, st);
+    const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
+    const int nch =
+        launch_right_mfma(F.Z1, P.dtype, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, P.side);
+    const Node& n2d = P.nodes[F.node_2];
+    launch_reduce(P.partial, nch, F.n2, F.R, 0, alpha, box_rows(P, n2d.first, n2d.last, off, ext), n2d.n, n2d.R, 1, 1,
+                  P.side);
+    TTNN_HIP(hipEventRecord(P.side_ev[1], P.side));
+    P.side_pending = true;
+  }
+
   const std::vector<int> pre{F.node_A};
   double* ZA = P.chain + P.prefix_offset.at(pre);
   const int node_last = F.tt ? F.node_B : F.node_2;
@@ -1020,14 +1055,6 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
                        static_cast<const float*>(plast), F.TA, F.TB, F.n2, F.nA, F.nB, F.R, F.KP, F.k, alpha,
                        P.nodes[F.node_A].R, ZA, P.nodes[F.node_1].R, P.nodes[node_last].R, mode,
                        static_cast<int>(nbA), static_cast<int>(nbZ), static_cast<int>(nb1));
-  if (F.zout) {
-    // R_2 += alpha Z1 X_2: Z1 [i_2][(i_B, j1)] against X_2 [j][(i_B, j1)], one pass over both
-    const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
-    const int nch = launch_right_mfma(F.Z1, P.dtype, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, st);
-    const Node& n2d = P.nodes[F.node_2];
-    launch_reduce(P.partial, nch, F.n2, F.R, 0, alpha, box_rows(P, n2d.first, n2d.last, off, ext), n2d.n, n2d.R, 1, 1,
-                  st);
-  }
   done_nodes->assign({F.node_A, F.node_1, node_last});
   done_prefixes->assign({pre});
   return true;

@@ -17,4 +17,11 @@ void fused_prepare(Plan& P, hipStream_t stream);
 bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
                       hipStream_t stream, std::vector<int>* done_nodes, std::vector<std::vector<int>>* done_prefixes);
 
+// Work forked onto the plan's side stream (created on first use) after everything
+// enqueued so far on `stream`; join_side makes `stream` wait for it (no-op when none
+// is pending).  A fused update leaves its side work pending; the update joins it
+// before returning and before any other launch that shares the partial scratch.
+void fork_side(Plan& P, hipStream_t stream);
+void join_side(Plan& P, hipStream_t stream);
+
 }  // namespace ttnn

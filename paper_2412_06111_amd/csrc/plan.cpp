@@ -50,6 +50,9 @@ Plan::~Plan() {
   if (arena) (void)hipFreeAsync(arena, free_stream);
   for (hipEvent_t e : sweep_ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : side_ev)
+    if (e) (void)hipEventDestroy(e);
+  if (side) (void)hipStreamDestroy(side);
 }
 
 // One stream-ordered block per plan, sized by a dry build, handed out in order (every

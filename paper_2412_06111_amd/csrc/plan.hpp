@@ -93,6 +93,11 @@ struct Plan {
   bool timing = false;
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};
   bool sweep_recorded = false;
+  // side stream (default priority) for work that may run beside the caller's stream:
+  // side_ev[0] forks it, side_ev[1] marks its end
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
+  bool side_pending = false;
 
   ~Plan();
   void* alloc(size_t bytes);

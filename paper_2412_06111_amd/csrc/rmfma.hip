@@ -60,36 +60,20 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   // staging map: thread -> row tid / CPR (+ RPR per round), chunk tid % CPR
   const int sr = tid / CPR, sc = (tid % CPR) * V;
   vec_t ra0[AR], rb0[BRN], ra1[AR], rb1[BRN];   // two steps of loads in flight
-  // Steps are loaded in order, KS values apart; the position (q, l) of the next step
-  // (k = l + L q, a step never crosses a multiple of L since L % KS == 0) advances
-  // without a division, and stops at the chunk's last step.  Every lane loads from an
-  // in-bounds address (a step past the chunk re-reads its last step, rows past the end
-  // re-read the last row) and masks the value, so the loads are unconditional and stay
-  // in flight across steps.
-  int64_t pk = k_begin, pq = k_begin / L, pl = k_begin - pq * L;
-  auto gload = [&](vec_t* ra, vec_t* rb) {
-    const bool live = pk < k_end;
-    const int64_t l = pl + sc, kk = pl + L * pq + sc;
+  auto gload = [&](int64_t k, vec_t* ra, vec_t* rb) {
+    const bool live = k < k_end;
+    const int64_t kk = k + sc;
+    const int64_t q = kk / L, l = kk - q * L;
 #pragma unroll
     for (int u = 0; u < AR; ++u) {
       const int64_t row = row0 + sr + RPR * u;
-      const vec_t v = *reinterpret_cast<const vec_t*>(H + l + L * ((row < n ? row : n - 1) + n * pq));
-      ra[u] = (live && row < n) ? v : vec_t{};
+      ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
     }
 #pragma unroll
     for (int u = 0; u < BRN; ++u) {
       const int j = sr + RPR * u;
-      const vec_t v = *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(j < r ? j : r - 1) * m + kk);
-      rb[u] = (live && j < r) ? v : vec_t{};
+      rb[u] = (live && j < r) ? *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(j) * m + kk) : vec_t{};
     }
-    if (pk + KS < k_end) {
-      pl += KS;
-      if (pl >= L) {
-        pl -= L;
-        ++pq;
-      }
-    }
-    pk += KS;
   };
   auto lstore = [&](int buf, const vec_t* ra, const vec_t* rb) {
 #pragma unroll
@@ -136,17 +120,17 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   };
 
   // step s is staged in LDS buffer s % 2 and its loads were issued two steps earlier
-  gload(ra0, rb0);
-  gload(ra1, rb1);
+  gload(k_begin, ra0, rb0);
+  gload(k_begin + KS, ra1, rb1);
   lstore(0, ra0, rb0);
   __syncthreads();
   for (int64_t k = k_begin; k < k_end; k += 2 * KS) {
-    gload(ra0, rb0);                         // step s + 2
+    gload(k + 2 * KS, ra0, rb0);             // step s + 2
     compute(0);                              // step s
     lstore(1, ra1, rb1);                     // step s + 1 (buffer 1 was read before the last barrier)
     __syncthreads();
     if (k + KS >= k_end) break;
-    gload(ra1, rb1);                         // step s + 3
+    gload(k + 3 * KS, ra1, rb1);             // step s + 3
     compute(1);                              // step s + 1
     lstore(0, ra0, rb0);                     // step s + 2
     __syncthreads();
