@@ -34,7 +34,11 @@
  *    done on the host before anything is enqueued and are reported synchronously.
  *    A failed HIP call makes the plan's status sticky (TTNN_E_HIP): later calls on
  *    that plan return it until ttnn_reset.  Input buffers must stay valid until
- *    the stream has passed the call.
+ *    the stream has passed the call.  A whole-tensor update may run part of its
+ *    work on a side stream that the plan owns (default priority); that work starts
+ *    after everything enqueued before the call on `stream` and is joined back into
+ *    `stream` before the call returns, so ordering on `stream` is as if all of it
+ *    ran there.
  *  - Ownership: the caller owns every buffer it passes.  A plan owns its device
  *    memory (DRMs, FP64 accumulators, scratch), allocated in ttnn_plan_create
  *    (stream ordered on its stream: use the plan on other streams only after that
