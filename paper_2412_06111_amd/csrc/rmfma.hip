@@ -15,6 +15,7 @@
 // MFMAs.  The pairing of A and B values is the same in every MFMA, so the sum runs
 // over the whole K range whatever the order.
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -164,6 +165,23 @@ void launch_dt(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, i
   else hipLaunchKernelGGL((right_mfma_kernel<DT, 4>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
 }
 
+// compute units of the current device (queried once per device; threads that race
+// on the first query store the same value)
+int compute_units() {
+  static std::atomic<int> cus[64];
+  int dev = 0;
+  TTNN_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return 256;
+  int c = cus[dev].load(std::memory_order_relaxed);
+  if (c == 0) {
+    int n = 0;
+    TTNN_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+    c = n > 0 ? n : 256;
+    cus[dev].store(c, std::memory_order_relaxed);
+  }
+  return c;
+}
+
 }  // namespace
 
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
@@ -183,6 +201,9 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   int64_t nch = (2048 + row_blocks - 1) / row_blocks;
   nch = std::min<int64_t>(nch, (K + 1023) / 1024);
   nch = std::min<int64_t>(nch, static_cast<int64_t>(part_elems / static_cast<size_t>(n * r)));
+  // and at most one round of resident workgroups (three a compute unit, by LDS): a
+  // second, partial round would stream with a fraction of the machine
+  nch = std::min<int64_t>(nch, std::max<int64_t>(1, 3 * compute_units() / row_blocks));
   nch = std::max<int64_t>(nch, 1);
   int64_t kchunk = (K + nch - 1) / nch;
   kchunk = (kchunk + kg - 1) / kg * kg;
