@@ -91,9 +91,9 @@ struct SttnnLayout {
   static constexpr size_t YB = YAB + (TT ? size_t(R) * SXB * ESZ : 0);
   static constexpr size_t XB = size_t(R) * SX * ESZ;
   static constexpr size_t BUDGET = 156 * 1024;
-  // YR: the Y_A rows of the tile's B2 slabs stay in LDS for the whole tile (one copy per
-  // tile instead of one per sub-tile), after both stages
-  static constexpr size_t YRB = YR ? size_t(B2) * YAB : 0;
+  // YR: the Y_A rows (TTNN: and the X_B rows) of the tile's B2 slabs stay in LDS for
+  // the whole tile (one copy per tile instead of one per sub-tile), after both stages
+  static constexpr size_t YRB = YR ? size_t(B2) * YB : 0;
   static constexpr bool STAGE_YA = !YR && 2 * (MS + YB) + Z1 <= BUDGET;
   static constexpr bool STAGE_X = (STAGE_YA || YR) && 2 * (MS + (STAGE_YA ? YB : 0) + 2 * XB) + Z1 + YRB <= BUDGET;
   static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
@@ -226,8 +226,9 @@ template <int DT, int R, int KP, int B2, int SC, bool TT, bool ZO>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
   using W = Wide<P>;
-  // FP32 Z1-out form at r = 32 (two slabs per tile): the tile's Y_A rows stay resident
-  static constexpr bool YR = ZO && DT == TTNN_F32 && R == 32;
+  // FP32 Z1-out and TTNN forms at r = 32 (two slabs per tile): the tile's Y_A rows (and
+  // X_B rows) stay resident
+  static constexpr bool YR = (ZO || TT) && DT == TTNN_F32 && R == 32;
   using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
   using T = typename P::T;
   using Acc = typename P::Acc;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // the doubled accumulators would crowd the register file: FP64 at r >= 32, r = 64,
   // and, at r = 32, the forms that keep R_2 or R_B accumulators as well.
   constexpr bool SPLIT =
-      NCB == 2 && (ZO || R <= 16) && 2 * (B2 + 1) * CBR * int(sizeof(CFrag) / 4) <= 80;
+      NCB == 2 && (ZO || YR || R <= 16) && 2 * (B2 + 1) * CBR * int(sizeof(CFrag) / 4) <= 80;
   constexpr int RB1 = SPLIT ? 2 : 1;        // 16-row blocks of i1 per wave in (a)/(c)
   // (b)/(d1) chains software-pipelined where the second register set fits
   constexpr bool PIPE = DT != TTNN_F64 && (R <= 16 || (R == 32 && (ZO || (TT && DT == TTNN_F32))));
@@ -306,10 +307,13 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // Y_1 rows, resident for the whole kernel; YR: the Y_A rows of the tile's slabs
   if constexpr (Lay::STAGE_Y1) lds_dma_rows<T, N1>(Y1, N1, Y1s, KP, wave, lane);
   T* YRs = reinterpret_cast<T*>(smem + Lay::OFF_YR);
+  constexpr int YRN = KP + (TT ? R : 0);      // resident rows per slab: Y_A, then X_B
   if constexpr (YR) {
 #pragma unroll
-    for (int i2l = 0; i2l < B2; ++i2l)
-      lds_dma_rows<T, N1>(YA + (i2_0 + i2l) * N1, nA, YRs + i2l * KP * N1, KP, wave, lane);
+    for (int i2l = 0; i2l < B2; ++i2l) {
+      lds_dma_rows<T, N1>(YA + (i2_0 + i2l) * N1, nA, YRs + i2l * YRN * N1, KP, wave, lane);
+      if constexpr (TT) lds_dma_rows<T, N1>(XB + (i2_0 + i2l) * N1, nA, YRs + (i2l * YRN + KP) * N1, R, wave, lane);
+    }
   }
   using ZN = Swz<T, N1>;                    // staged rows of N1 elements (slab columns, Y rows)
   using ZX = Swz<T, SC>;                    // staged rows of SC elements (X_A, X_1 rows)
@@ -364,8 +368,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
       __syncthreads();                    // ... everyone's; and stage buf^1 is free again
       if (s + 1 < nsub) issue(s + 1, buf ^ 1);
       const T* Ms = reinterpret_cast<const T*>(stage_base(buf));
-      const T* YAs = YR ? YRs + i2l * KP * N1 : reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
-      const T* XBs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
+      const T* YAs = YR ? YRs + i2l * YRN * N1 : reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_YA);
+      const T* XBs = YR ? YRs + (i2l * YRN + KP) * N1 : reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XB);
       const T* XAs = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_XA);
       const T* X1s = reinterpret_cast<const T*>(stage_base(buf) + Lay::OFF_X1);
 
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
         } else if (TT && bd_active) {
           bd_chain<P, (TT ? KBB : 1)>(Ms, iBl, lg, [&](int rb, int kk) -> vec {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) return W::load(XBs + ZN::off(jr, kk));
+            if constexpr (Lay::STAGE_YA || YR) return W::load(XBs + ZN::off(jr, kk));
             else return W::load(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }, zB);
         } else if (!TT && bd_active) {
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
           for (int rb = 0; rb < KBB; ++rb) {
             const int jr = 16 * rb + l16;
-            if constexpr (Lay::STAGE_YA) ax[rb] = W::load(XBs + ZN::off(jr, kk));
+            if constexpr (Lay::STAGE_YA || YR) ax[rb] = W::load(XBs + ZN::off(jr, kk));
             else ax[rb] = W::load(XB + static_cast<int64_t>(jr) * nA + i2 * N1 + kk);
           }
 #pragma unroll
@@ -830,11 +834,12 @@ struct Shape {
 
 // Tile shape per dtype: B2 slabs of i_2 per tile, SC columns per sub-tile (sized so
 // that the slab, the DRM rows of a sub-tile and the Z1 stash fit the LDS budget).
-// The FP32 Z1-out form at r = 32 takes two slabs, so that their Y_A rows stay in LDS.
+// The FP32 Z1-out and TTNN forms at r = 32 take two slabs, so that their Y_A (and X_B)
+// rows stay in LDS.
 template <int DT, int R, bool TT, bool ZO = false>
 constexpr int b2_of() {
   return DT == TTNN_BF16 ? (R >= 64 ? 2 : 8)
-         : DT == TTNN_F32 ? (R >= 64 || (ZO && R == 32) ? 2 : 4)
+         : DT == TTNN_F32 ? (R >= 64 || ((ZO || TT) && R == 32) ? 2 : 4)
                           : (R >= 64 || TT ? 2 : 4);
 }
 template <int DT>
@@ -844,7 +849,7 @@ constexpr int sc_of() {
 
 Shape shape_for(int dt, int R, bool tt, bool zout) {
   if (dt == TTNN_BF16) return {R >= 64 ? 2 : 8, 64};
-  if (dt == TTNN_F32) return {R >= 64 || (zout && R == 32) ? 2 : 4, 32};
+  if (dt == TTNN_F32) return {R >= 64 || ((zout || tt) && R == 32) ? 2 : 4, 32};
   return {R >= 64 || tt ? 2 : 4, 32};
 }
 
