@@ -228,7 +228,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using W = Wide<P>;
   // FP32 Z1-out and TTNN forms at r = 32 (two slabs per tile): the tile's Y_A rows (and
   // X_B rows) stay resident
-  static constexpr bool YR = (ZO || TT) && DT == TTNN_F32 && R == 32;
+  static constexpr bool YR = (ZO || TT) && DT != TTNN_F64 && R == 32;
   using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
   using T = typename P::T;
   using Acc = typename P::Acc;
@@ -838,7 +838,7 @@ struct Shape {
 // rows stay in LDS.
 template <int DT, int R, bool TT, bool ZO = false>
 constexpr int b2_of() {
-  return DT == TTNN_BF16 ? (R >= 64 ? 2 : 8)
+  return DT == TTNN_BF16 ? (R >= 64 ? 2 : (ZO || TT) && R == 32 ? 4 : 8)
          : DT == TTNN_F32 ? (R >= 64 || ((ZO || TT) && R == 32) ? 2 : 4)
                           : (R >= 64 || TT ? 2 : 4);
 }
@@ -848,7 +848,7 @@ constexpr int sc_of() {
 }
 
 Shape shape_for(int dt, int R, bool tt, bool zout) {
-  if (dt == TTNN_BF16) return {R >= 64 ? 2 : 8, 64};
+  if (dt == TTNN_BF16) return {R >= 64 ? 2 : (zout || tt) && R == 32 ? 4 : 8, 64};
   if (dt == TTNN_F32) return {R >= 64 || ((zout || tt) && R == 32) ? 2 : 4, 32};
   return {R >= 64 || tt ? 2 : 4, 32};
 }
