@@ -14,13 +14,14 @@
 // rows over i_A, so R_B^T = X_B^T M is formed like Z_A, by the waves that STTNN spends
 // on Z1.  The leaves right of A ({2} and the subtree of B) follow on the other paths.
 //
-// Each workgroup streams a tile of M (B2 whole i1-slabs x BB columns) through LDS
-// once; every product is an MFMA chain on that LDS tile:
+// Each workgroup streams a tile of M (B2 slabs, one i2 and all of i1 each, by a range
+// of columns) through LDS once; every product is an MFMA chain on that LDS tile:
 //   (a)+(c) share the A fragments of the slab (rows i1, K = columns) against
 //           [X_A | X_1] rows;  (b)+(d1) share its B fragments (K = i1) against
-//           [Y_A | Y_1] rows;  (d2) contracts the LDS-staged Z1 over (j1, column).
+//           [Y_A | Y_1] rows;  (d2) contracts the LDS-staged Z1 over (j1, column)
+//           (r = 16), or Z1 is written out for a streaming R_2 (r >= 32).
 // Partial sums are written per tile in the accumulation precision and summed in a
-// fixed order into the FP64 accumulators by fused_reduce.
+// fixed order into the FP64 accumulators by sttnn_t4_reduce.
 #include "fused.hpp"
 
 #include "engine.hpp"
@@ -221,7 +222,7 @@ __device__ inline void bd_chain(const typename P::T* Ms, int iBl, int lg, LoadA&
 
 // ZO (STTNN only): instead of contracting Z1 with X_2 in the tile (which re-reads the
 // X_2 rows of the column band in every row tile), write Z1 out; R_2 is then one
-// streaming contraction that reads X_2 once (used where X_2 is large, r = 64).
+// streaming contraction that reads X_2 once (used for r >= 32).
 template <int DT, int R, int KP, int B2, int SC, bool TT, bool ZO>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
