@@ -223,6 +223,12 @@ class Plan:
                                      (C.c_int64 * self.d)(*extent), float(alpha), stream_ptr(stream)))
 
     def update_rank1(self, factors, alpha=1.0, stream=None):
+        """factors: d CUDA float64 vectors, factor mu of length n_mu (the library reads
+        exactly that many doubles from each)."""
+        assert len(factors) == self.d, (len(factors), self.d)
+        for f, n in zip(factors, self.dims):
+            assert f.is_cuda and f.dtype == torch.float64 and f.is_contiguous() and f.numel() == n, \
+                (f.device, f.dtype, f.numel(), n)
         ptrs = (C.c_void_p * self.d)(*[C.c_void_p(f.data_ptr()) for f in factors])
         check(lib.ttnn_sketch_update_rank1(self.handle, ptrs, float(alpha), stream_ptr(stream)))
 
