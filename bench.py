@@ -46,7 +46,8 @@ def parse():
                     help="extra STTNN BF16 and FP64 runs at these sketch ranks (p = r/2)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-error", action="store_true")
-    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
+    ap.add_argument("--single-n", type=int, default=64, help="mode size of the single-stream serving run")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-nmax", type=int, default=160)
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -376,6 +377,72 @@ def serving_bench(args):
     return out
 
 
+def serving_single(args):
+    """Single stream of the order-5 serving shape: n^5 (n = 64) on (((1,2),3),(4,5)), a
+    random TTN with edge ranks 16 + 1e-5 noise, TTNN, r = 24, p = 12, FP32.  The tensor
+    arrives as the boxes of a random tiling (segments of 8..16 per mode) plus 8 cancelling
+    pairs of rank-1 terms, in a random order, and the cores are assembled (enqueued) every
+    256 updates; payloads are resident in HBM before the clock starts.  Per-update time
+    on the stream from HIP events before and after each update (p50 / p99), wall time and
+    ingest rate (payload bytes / wall), approximation error of the final cores."""
+    import numpy as np
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads import serving as WS
+
+    n = args.single_n
+    dims = (n,) * 5
+    T64 = WS.order5_tensor_device(n=n, rank=16, seed=2024, noise=1e-5)
+    X = T64.to(torch.float32)
+    V = X.view(*dims[::-1])                                   # [i5, .., i1]
+    g = WS.rng(41)
+    ups = []
+    for off, ext in WS.boxes(dims, g, lo=8, hi=16):
+        sl = tuple(slice(o, o + e) for o, e in zip(off[::-1], ext[::-1]))
+        ups.append(("box", V[sl].contiguous().reshape(-1), off, ext, 1.0))
+    for fac, a in WS.rank1_pairs(dims, 8, seed=43):
+        ups.append(("rank1", [torch.from_numpy(v).cuda() for v in fac], None, None, a))
+    ups = [ups[i] for i in g.permutation(len(ups))]
+    del X, V
+    payload = sum(u[1].numel() * 4 if u[0] == "box" else sum(f.numel() * 8 for f in u[1]) for u in ups)
+    plan = P.Plan(WS.T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=7)
+    cores = plan.alloc_cores()
+    st = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ups]
+    every = 256
+    torch.cuda.synchronize()
+    tic = time.perf_counter()
+    for i, u in enumerate(ups):
+        ev[i][0].record(st)
+        if u[0] == "box":
+            plan.update(u[1], extent=u[3], offset=u[2])
+        else:
+            plan.update_rank1(u[1], alpha=u[4])
+        ev[i][1].record(st)
+        if (i + 1) % every == 0:
+            plan.assemble_async(cores)
+    plan.assemble_async(cores)
+    plan.assemble_status()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tic
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    That = plan.reconstruct(cores)
+    e2, n2 = P.diff_norms(That, T64)
+    del That
+    plan.close()
+    boxes = sum(1 for u in ups if u[0] == "box")
+    out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTN ranks 16 + 1e-5 noise, TTNN, r=24, p=12, FP32; "
+                       f"{boxes} tiling boxes (8..16 per mode) + {len(ups) - boxes} rank-1 terms in random order, "
+                       f"cores every {every} updates",
+           "updates": len(ups), "wall_s": wall, "updates_per_s": len(ups) / wall,
+           "ingest_GBps": payload / wall / 1e9, "update_p50_ms": float(np.percentile(ms, 50)),
+           "update_p99_ms": float(np.percentile(ms, 99)), "assemblies": (len(ups) + every - 1) // every,
+           "approx_rel_error": (e2 / n2) ** 0.5}
+    del ups, T64
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(T, tree, variant, seed=1, box=112):
     """The FP64 oracle on a bounded sample of the same workload: the corner box of
     size box^4 as a streaming update (DRM rows generated before timing)."""
@@ -488,6 +555,8 @@ def main():
         del T_dev64
         torch.cuda.empty_cache()
         serving = serving_bench(args)
+        serving["single_stream_f32"] = serving_single(args)
+        print(f"# serving single stream: {json.dumps(serving['single_stream_f32'])}", file=sys.stderr, flush=True)
 
     line = {
         "metric": METRIC,

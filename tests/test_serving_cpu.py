@@ -163,3 +163,17 @@ def test_rank1_pairs_cancel():
     assert len(pairs) == 4
     for (f1, a1), (f2, a2) in zip(pairs[0::2], pairs[1::2]):
         assert a1 == -a2 and all(np.array_equal(x, y) for x, y in zip(f1, f2))
+
+
+def test_order5_tensor_matches_dense_ttn():
+    """The order-5 serving tensor built by the device contraction (run here on the
+    CPU) equals the einsum contraction of the same seeded cores, scaled to unit RMS."""
+    from workloads import synth as W
+    n, rank, seed = 5, 3, 11
+    flat = WS.order5_tensor_device(n=n, rank=rank, seed=seed, noise=0.0, device="cpu").numpy()
+    dims = (n,) * 5
+    T = W.ttn_dense(WS.T5, dims, W.gaussian_ttn_cores(WS.T5, dims, rank, seed))
+    ref = np.asarray(W.flat_colmajor(T), dtype=np.float64)
+    ref = ref * np.sqrt(ref.size) / np.linalg.norm(ref)
+    assert flat.shape == ref.shape
+    assert np.allclose(flat, ref, rtol=1e-12, atol=1e-12)

@@ -86,6 +86,34 @@ def stream_tensor_device(prob, noise=1e-5, device="cuda"):
     return flat
 
 
+T5 = (((1, 2), 3), (4, 5))
+
+
+def order5_tensor_device(n=64, rank=16, seed=2024, noise=1e-5, device="cuda"):
+    """Single-stream serving tensor: a random TTN on (((1,2),3),(4,5)) with every edge
+    rank `rank` (N(0,1) cores drawn on the host, seeded), contracted on the device in
+    FP64, scaled to unit RMS, plus seeded N(0, noise^2) entries.  Returns the flat
+    column-major FP64 device tensor of n^5 entries."""
+    import torch
+    dims = (n,) * 5
+    c = gaussian_ttn_cores(T5, dims, rank, seed)
+    t = {m: torch.from_numpy(np.asarray(v, dtype=np.float64)).to(device) for m, v in c.items()}
+    U1, U2, U3, U4, U5 = (t[(m,)] for m in range(1, 6))               # (n, r) each
+    A, Cc, E, root = t[(1, 2)], t[(1, 2, 3)], t[(4, 5)], t[(1, 2, 3, 4, 5)]
+    # UA[(i1, i2), a], UC[(i1, i2, i3), c], UE[(i4, i5), e], first index fastest
+    UA = torch.einsum("ix,jy,xya->jia", U1, U2, A).reshape(n * n, -1)
+    UC = torch.einsum("pa,kz,azc->kpc", UA, U3, Cc).reshape(n ** 3, -1)
+    UE = torch.einsum("ix,jy,xye->jie", U4, U5, E).reshape(n * n, -1)
+    Tm = UC @ root @ UE.T                       # (n^3, n^2): column-major flat = Tm.T row-major
+    flat = Tm.T.contiguous().reshape(-1)
+    del Tm
+    flat *= (flat.numel() ** 0.5) / torch.linalg.vector_norm(flat)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed) + 17)
+    flat += noise * torch.randn(flat.numel(), generator=g, device=device, dtype=torch.float64)
+    return flat
+
+
 def box_updates(T, prob, lo=4, hi=48):
     """(offset, extent, block) for the boxes of one tiling of T; block is the
     column-major flat FP64 copy of T over the box."""
