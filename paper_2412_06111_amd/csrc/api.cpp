@@ -176,7 +176,7 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
             ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, recs[b]);
             items.push_back(&recs[b]);
           }
-          if (items.size() == 1) ttnn::run_box_ops(recs[0], st);
+          if (items.size() == 1) ttnn::run_box_ops(*get(descs[kv.second[0]].plan), recs[0], st);
           else ttnn::run_box_ops_batched(items, st);
         }
         TTNN_HIP(hipGetLastError());

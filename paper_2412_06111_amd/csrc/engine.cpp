@@ -373,12 +373,55 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
   left(group_args(before, P.nodes[rc.back()]), P.psi_root, 1, alpha);
 }
 
-void run_box_ops(const std::vector<BoxOp>& ops, hipStream_t st) {
-  for (const BoxOp& op : ops) {
-    const int nch = launch_gemm(op.g, st);
-    if (nch == 0 || !op.reduce) continue;
-    const ReduceTask& r = op.r;
-    launch_reduce(r.part, nch, r.rows, r.ncols, r.mode, r.alpha, r.rmap, r.ldr, r.dst, r.L, r.kdim, st);
+void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
+  // The steps of one update are grouped, in order, into levels: a step joins the
+  // current level unless it reads a buffer that a step of the level writes, or its
+  // partial sums no longer fit the scratch next to those of the level.  A level runs as
+  // one batched contraction launch per kind of step and one batched reduction launch,
+  // each step with its own slice of the scratch.  Every step keeps its chunking and
+  // summation order, so the results are bitwise those of running the steps one by one;
+  // the update takes a few launches instead of two per node.
+  std::vector<BoxOp> ops(ops_in);
+  size_t i = 0;
+  while (i < ops.size()) {
+    std::vector<const void*> written;
+    std::vector<GemmArgs> gemms;
+    std::vector<ReduceTask> reds;
+    size_t used = 0, j = i;
+    for (; j < ops.size(); ++j) {
+      BoxOp& op = ops[j];
+      if (std::find(written.begin(), written.end(), op.g.H) != written.end()) break;
+      const int nch = gemm_chunks(op.g, nullptr);
+      const size_t need = op.reduce && nch > 0 ? static_cast<size_t>(nch) * op.r.rows * op.r.ncols : 0;
+      if (j > i && used + need > P.partial_elems) break;
+      if (op.reduce) {
+        op.g.out = P.partial + used;
+        op.r.part = P.partial + used;
+        used += need;
+      }
+      written.push_back(op.reduce ? static_cast<const void*>(op.r.dst) : op.g.out);
+      if (nch == 0) continue;
+      gemms.push_back(op.g);
+      if (!op.reduce) continue;
+      ReduceTask r = op.r;
+      r.nchunks = nch;
+      reds.push_back(r);
+    }
+    // one launch per kind of contraction (right / left, operand and output types)
+    std::vector<bool> taken(gemms.size(), false);
+    for (size_t a = 0; a < gemms.size(); ++a) {
+      if (taken[a]) continue;
+      std::vector<GemmArgs> kind;
+      for (size_t b = a; b < gemms.size(); ++b) {
+        const GemmArgs &x = gemms[a], &y = gemms[b];
+        if (taken[b] || x.right != y.right || x.th != y.th || x.td != y.td || x.out_f32 != y.out_f32) continue;
+        kind.push_back(y);
+        taken[b] = true;
+      }
+      launch_gemm_batched(kind, st);
+    }
+    launch_reduce_batched(reds, st);
+    i = j;
   }
 }
 
@@ -451,7 +494,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
     }
     std::vector<BoxOp> ops;
     record_box(P, block, off, ext, alpha, ops);
-    run_box_ops(ops, st);
+    run_box_ops(P, ops, st);
     return;
   }
   std::vector<int> fused_nodes;
