@@ -380,8 +380,12 @@ void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
   // one batched contraction launch per kind of step and one batched reduction launch,
   // each step with its own slice of the scratch.  Every step keeps its chunking and
   // summation order, so the results are bitwise those of running the steps one by one;
-  // the update takes a few launches instead of two per node.
+  // the update takes a few launches instead of two per node.  All descriptor tables
+  // are built first and staged in one copy.
   std::vector<BoxOp> ops(ops_in);
+  std::vector<BatchedGemm> gl;               // launch order: a level's kinds, then ...
+  std::vector<BatchedReduce> rl;             // ... its reduction (one per level)
+  std::vector<size_t> level_end;             // gl index where each level's kinds end
   size_t i = 0;
   while (i < ops.size()) {
     std::vector<const void*> written;
@@ -418,11 +422,46 @@ void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
         kind.push_back(y);
         taken[b] = true;
       }
-      launch_gemm_batched(kind, st);
+      gl.push_back(plan_gemm_batched(kind));
     }
-    launch_reduce_batched(reds, st);
+    level_end.push_back(gl.size());
+    rl.push_back(plan_reduce_batched(reds));
     i = j;
   }
+  constexpr size_t kAlignD = 64;
+  auto aligned = [](size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; };
+  std::vector<size_t> og(gl.size()), of(rl.size()), orr(rl.size());
+  size_t total = 0;
+  for (size_t k = 0; k < gl.size(); ++k) {
+    og[k] = total;
+    total = aligned(total + gl[k].tasks.size() * sizeof(GemmTask));
+  }
+  for (size_t k = 0; k < rl.size(); ++k) {
+    of[k] = total;
+    total = aligned(total + rl[k].folds.size() * sizeof(ReduceTask));
+    orr[k] = total;
+    total = aligned(total + rl[k].tasks.size() * sizeof(ReduceTask));
+  }
+  if (total == 0) return;
+  std::vector<char> host(total, 0);
+  for (size_t k = 0; k < gl.size(); ++k)
+    if (!gl[k].tasks.empty()) std::memcpy(host.data() + og[k], gl[k].tasks.data(), gl[k].tasks.size() * sizeof(GemmTask));
+  for (size_t k = 0; k < rl.size(); ++k) {
+    if (!rl[k].folds.empty())
+      std::memcpy(host.data() + of[k], rl[k].folds.data(), rl[k].folds.size() * sizeof(ReduceTask));
+    if (!rl[k].tasks.empty())
+      std::memcpy(host.data() + orr[k], rl[k].tasks.data(), rl[k].tasks.size() * sizeof(ReduceTask));
+  }
+  StagingLock lock;
+  char* d = static_cast<char*>(stage_descriptors(host.data(), total, st));
+  size_t g0 = 0;
+  for (size_t lv = 0; lv < rl.size(); ++lv) {
+    for (size_t k = g0; k < level_end[lv]; ++k) launch_gemm_staged(gl[k], reinterpret_cast<const GemmTask*>(d + og[k]), st);
+    g0 = level_end[lv];
+    launch_reduce_staged(rl[lv], reinterpret_cast<const ReduceTask*>(d + of[lv]),
+                         reinterpret_cast<const ReduceTask*>(d + orr[lv]), st);
+  }
+  fence_descriptors(st);
 }
 
 void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hipStream_t st) {
