@@ -169,15 +169,16 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
         for (auto& kv : buckets) {
           std::vector<std::vector<ttnn::BoxOp>> recs(kv.second.size());
           std::vector<const std::vector<ttnn::BoxOp>*> items;
+          std::vector<Plan*> plans;
           for (size_t b = 0; b < kv.second.size(); ++b) {
             const int32_t i = kv.second[b];
             Plan* P = get(descs[i].plan);
             P->epilogue_valid = false;
             ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, recs[b]);
             items.push_back(&recs[b]);
+            plans.push_back(P);
           }
-          if (items.size() == 1) ttnn::run_box_ops(*get(descs[kv.second[0]].plan), recs[0], st);
-          else ttnn::run_box_ops_batched(items, st);
+          ttnn::run_box_ops_batched(plans, items, st);
         }
         TTNN_HIP(hipGetLastError());
         pending.swap(rest);

@@ -373,44 +373,65 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
   left(group_args(before, P.nodes[rc.back()]), P.psi_root, 1, alpha);
 }
 
-void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
-  // The steps of one update are grouped, in order, into levels: a step joins the
+void run_box_ops_batched(const std::vector<Plan*>& plans, const std::vector<const std::vector<BoxOp>*>& items,
+                         hipStream_t st) {
+  // The steps of each update are grouped, in order, into levels: a step joins the
   // current level unless it reads a buffer that a step of the level writes, or its
-  // partial sums no longer fit the scratch next to those of the level.  A level runs as
-  // one batched contraction launch per kind of step and one batched reduction launch,
-  // each step with its own slice of the scratch.  Every step keeps its chunking and
-  // summation order, so the results are bitwise those of running the steps one by one;
-  // the update takes a few launches instead of two per node.  All descriptor tables
-  // are built first and staged in one copy.
-  std::vector<BoxOp> ops(ops_in);
-  std::vector<BatchedGemm> gl;               // launch order: a level's kinds, then ...
-  std::vector<BatchedReduce> rl;             // ... its reduction (one per level)
-  std::vector<size_t> level_end;             // gl index where each level's kinds end
-  size_t i = 0;
-  while (i < ops.size()) {
+  // partial sums no longer fit its plan's scratch next to those of the level (every step
+  // gets its own slice).  Level l of every update in the call runs as one batched
+  // contraction launch per kind of step and one batched reduction launch; updates
+  // depend only on their own earlier levels.  Every step keeps its chunking and
+  // summation order, so the results are bitwise those of running the steps one by one,
+  // update by update.  All descriptor tables are built first and staged in one copy.
+  TTNN_REQUIRE(plans.size() == items.size(), TTNN_E_INVALID, "one plan per batched update");
+  std::vector<std::vector<BoxOp>> ops(items.size());
+  std::vector<std::vector<int>> level(items.size());
+  int nlev = 0;
+  for (size_t u = 0; u < items.size(); ++u) {
+    ops[u] = *items[u];
+    Plan& P = *plans[u];
+    level[u].assign(ops[u].size(), 0);
     std::vector<const void*> written;
-    std::vector<GemmArgs> gemms;
-    std::vector<ReduceTask> reds;
-    size_t used = 0, j = i;
-    for (; j < ops.size(); ++j) {
-      BoxOp& op = ops[j];
-      if (std::find(written.begin(), written.end(), op.g.H) != written.end()) break;
+    size_t used = 0;
+    int lv = 0;
+    for (size_t k = 0; k < ops[u].size(); ++k) {
+      BoxOp& op = ops[u][k];
       const int nch = gemm_chunks(op.g, nullptr);
       const size_t need = op.reduce && nch > 0 ? static_cast<size_t>(nch) * op.r.rows * op.r.ncols : 0;
-      if (j > i && used + need > P.partial_elems) break;
+      const bool reads_level = std::find(written.begin(), written.end(), op.g.H) != written.end();
+      if (!written.empty() && (reads_level || used + need > P.partial_elems)) {
+        ++lv;
+        written.clear();
+        used = 0;
+      }
       if (op.reduce) {
         op.g.out = P.partial + used;
         op.r.part = P.partial + used;
         used += need;
       }
       written.push_back(op.reduce ? static_cast<const void*>(op.r.dst) : op.g.out);
-      if (nch == 0) continue;
-      gemms.push_back(op.g);
-      if (!op.reduce) continue;
-      ReduceTask r = op.r;
-      r.nchunks = nch;
-      reds.push_back(r);
+      level[u][k] = lv;
     }
+    nlev = std::max(nlev, lv + 1);
+  }
+  std::vector<BatchedGemm> gl;               // launch order: a level's kinds, then ...
+  std::vector<BatchedReduce> rl;             // ... its reduction (one per level)
+  std::vector<size_t> level_end;             // gl index where each level's kinds end
+  for (int lv = 0; lv < nlev; ++lv) {
+    std::vector<GemmArgs> gemms;
+    std::vector<ReduceTask> reds;
+    for (size_t u = 0; u < ops.size(); ++u)
+      for (size_t k = 0; k < ops[u].size(); ++k) {
+        if (level[u][k] != lv) continue;
+        const BoxOp& op = ops[u][k];
+        const int nch = gemm_chunks(op.g, nullptr);
+        if (nch == 0) continue;
+        gemms.push_back(op.g);
+        if (!op.reduce) continue;
+        ReduceTask r = op.r;
+        r.nchunks = nch;
+        reds.push_back(r);
+      }
     // one launch per kind of contraction (right / left, operand and output types)
     std::vector<bool> taken(gemms.size(), false);
     for (size_t a = 0; a < gemms.size(); ++a) {
@@ -426,7 +447,6 @@ void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
     }
     level_end.push_back(gl.size());
     rl.push_back(plan_reduce_batched(reds));
-    i = j;
   }
   constexpr size_t kAlignD = 64;
   auto aligned = [](size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; };
@@ -464,62 +484,8 @@ void run_box_ops(Plan& P, const std::vector<BoxOp>& ops_in, hipStream_t st) {
   fence_descriptors(st);
 }
 
-void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hipStream_t st) {
-  if (items.empty()) return;
-  const size_t nops = items[0]->size();
-  for (const auto* it : items)
-    TTNN_REQUIRE(it->size() == nops, TTNN_E_INVALID, "batched updates of different tree shapes");
-  // every step's descriptor tables are built first and staged in one copy, then the
-  // steps are launched in order from the staged tables
-  std::vector<BatchedGemm> gp(nops);
-  std::vector<BatchedReduce> rp(nops);
-  std::vector<GemmArgs> gs;
-  std::vector<ReduceTask> rs;
-  for (size_t k = 0; k < nops; ++k) {
-    gs.clear();
-    rs.clear();
-    for (const auto* it : items) {
-      const BoxOp& op = (*it)[k];
-      gs.push_back(op.g);
-      if (!op.reduce) continue;
-      const int nch = gemm_chunks(op.g, nullptr);
-      if (nch == 0) continue;
-      ReduceTask r = op.r;
-      r.nchunks = nch;
-      rs.push_back(r);
-    }
-    gp[k] = plan_gemm_batched(gs);
-    rp[k] = plan_reduce_batched(rs);
-  }
-  constexpr size_t kAlignD = 64;
-  auto aligned = [](size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; };
-  std::vector<size_t> og(nops), of(nops), orr(nops);
-  size_t total = 0;
-  for (size_t k = 0; k < nops; ++k) {
-    og[k] = total;
-    total = aligned(total + gp[k].tasks.size() * sizeof(GemmTask));
-    of[k] = total;
-    total = aligned(total + rp[k].folds.size() * sizeof(ReduceTask));
-    orr[k] = total;
-    total = aligned(total + rp[k].tasks.size() * sizeof(ReduceTask));
-  }
-  if (total == 0) return;
-  std::vector<char> host(total, 0);
-  for (size_t k = 0; k < nops; ++k) {
-    if (!gp[k].tasks.empty()) std::memcpy(host.data() + og[k], gp[k].tasks.data(), gp[k].tasks.size() * sizeof(GemmTask));
-    if (!rp[k].folds.empty())
-      std::memcpy(host.data() + of[k], rp[k].folds.data(), rp[k].folds.size() * sizeof(ReduceTask));
-    if (!rp[k].tasks.empty())
-      std::memcpy(host.data() + orr[k], rp[k].tasks.data(), rp[k].tasks.size() * sizeof(ReduceTask));
-  }
-  StagingLock lock;
-  char* d = static_cast<char*>(stage_descriptors(host.data(), total, st));
-  for (size_t k = 0; k < nops; ++k) {
-    launch_gemm_staged(gp[k], reinterpret_cast<const GemmTask*>(d + og[k]), st);
-    launch_reduce_staged(rp[k], reinterpret_cast<const ReduceTask*>(d + of[k]),
-                         reinterpret_cast<const ReduceTask*>(d + orr[k]), st);
-  }
-  fence_descriptors(st);
+void run_box_ops(Plan& P, const std::vector<BoxOp>& ops, hipStream_t st) {
+  run_box_ops_batched({&P}, {&ops}, st);
 }
 
 namespace {

@@ -31,7 +31,8 @@ void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream
 void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
                 std::vector<BoxOp>& ops);
 void run_box_ops(Plan& P, const std::vector<BoxOp>& ops, hipStream_t stream);
-void run_box_ops_batched(const std::vector<const std::vector<BoxOp>*>& items, hipStream_t stream);
+void run_box_ops_batched(const std::vector<Plan*>& plans, const std::vector<const std::vector<BoxOp>*>& items,
+                         hipStream_t stream);
 std::string batch_key(const Plan& P);
 bool whole_tensor(const Plan& P, const int64_t* off, const int64_t* ext);
 
