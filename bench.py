@@ -50,6 +50,13 @@ def parse():
     ap.add_argument("--single-n", type=int, default=64, help="mode size of the single-stream serving run")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-nmax", type=int, default=160)
+    ap.add_argument("--no-hilbert", action="store_true", help="skip the 6-D Hilbert accuracy curves")
+    ap.add_argument("--hilbert-only", action="store_true",
+                    help="run only the Hilbert curves and print them as one JSON line")
+    ap.add_argument("--hilbert-n", type=int, default=20)
+    ap.add_argument("--hilbert-trials", type=int, default=3, help="DRM seeds per rank (the paper averages 30)")
+    ap.add_argument("--hilbert-ranks", default="2,3,4,5,6,7,8,9,10,11,12,13")
+    ap.add_argument("--hilbert-dtypes", default="f64,f32")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson rate as a fraction of the batched path's closed-loop rate")
     return ap.parse_args()
@@ -271,6 +278,66 @@ def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
     return res
 
 
+# ---------------------------------------------------------------- 6-D Hilbert curves
+def hilbert_bench(args):
+    """The first accuracy experiment of Sec. 8: the 6-D Hilbert tensor
+    1 / (1 + i_1 + .. + i_6) (mode size 20, 64M entries, resident in HBM) on the index
+    tree of Fig. 1, equal ranks r, p = 3, TTNN and STTNN.  Per rank: the mean relative
+    Frobenius error over `--hilbert-trials` DRM seeds (the paper averages 30) and the
+    time of one approximation (reset + sketch update of the whole tensor + assembly of
+    the cores), from events on the stream, averaged over 5 timed repeats with the first
+    seed's plan after 2 untimed ones.  The FP32 rows sketch the FP32 rounding of the
+    tensor; their errors are against the FP64 tensor."""
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads import hilbert as H
+
+    n = args.hilbert_n
+    dims = (n,) * 6
+    T64 = H.hilbert_device(n)
+    ranks = [int(x) for x in args.hilbert_ranks.split(",") if x]
+    out = {"workload": f"6-D Hilbert tensor, {n}^6 on the Fig. 1 tree (((1,2),3),4,(5,6)), p = {H.P_PAPER}",
+           "trials": args.hilbert_trials, "curves": {}}
+    stream = torch.cuda.current_stream()
+    for dtype in args.hilbert_dtypes.split(","):
+        X = T64 if dtype == "f64" else T64.to(torch.float32)
+        for variant in ("ttnn", "sttnn"):
+            rows = []
+            for r in ranks:
+                errs, ms = [], None
+                for trial in range(args.hilbert_trials):
+                    plan = P.Plan(H.TOY, dims, r, H.P_PAPER, variant=variant, dtype=dtype, seed=100 + trial)
+                    cores = plan.alloc_cores()
+                    if trial == 0:
+                        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                               for _ in range(7)]
+                        for a, b in evs:
+                            a.record(stream)
+                            plan.reset()
+                            plan.update(X)
+                            plan.assemble_async(cores)
+                            b.record(stream)
+                        plan.assemble_status()
+                        torch.cuda.synchronize()
+                        t = [a.elapsed_time(b) for a, b in evs[2:]]
+                        ms = sum(t) / len(t)
+                    else:
+                        plan.update(X)
+                        plan.assemble(cores)
+                    e2, n2 = P.diff_norms(plan.reconstruct(cores), T64)
+                    errs.append((e2 / n2) ** 0.5)
+                    plan.close()
+                rows.append({"rank": r, "mean_rel_error": sum(errs) / len(errs), "max_rel_error": max(errs),
+                             "ms_per_approximation": ms,
+                             "ingest_GBps": X.numel() * X.element_size() / (ms * 1e-3) / 1e9})
+            out["curves"][f"{variant}:{dtype}"] = rows
+            print(f"# hilbert {variant}:{dtype}: {json.dumps(rows)}", file=sys.stderr, flush=True)
+        del X
+    del T64
+    torch.cuda.empty_cache()
+    return out
+
+
 # ---------------------------------------------------------------- serving
 def serving_bench(args):
     """Many streams of box updates (mode sizes U{32..nmax}, TTN ranks 8..32 + 1e-5
@@ -469,6 +536,10 @@ def main():
               "the sketch path has no multi-GPU mode in this build", file=sys.stderr)
         sys.exit(2)
 
+    if args.hilbert_only:
+        print(json.dumps(hilbert_bench(args)))
+        return
+
     import numpy as np
     import torch
     import oracle as O
@@ -550,6 +621,9 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(T, tree_def, hv)
+    hilbert = None
+    if not args.no_hilbert:
+        hilbert = hilbert_bench(args)
     serving = None
     if not args.no_serve:
         del T_dev64
@@ -580,6 +654,7 @@ def main():
         "results": results,
         "copy_calibration": copy,
         "serving": serving,
+        "hilbert_6d": hilbert,
         "input_generation_s": t_gen,
     }
     print(json.dumps(line))
