@@ -14,6 +14,13 @@
 // 16 x 16 x K MFMA step takes KPL of them per lane group, so one load feeds V / KPL
 // MFMAs.  The pairing of A and B values is the same in every MFMA, so the sum runs
 // over the whole K range whatever the order.
+//
+// Row-contiguous form (IF, L = 1: nodes that start at mode 1, FP32 / FP64): there the
+// contraction index q is the slow one and the rows i run along memory, so a step
+// stages, for each of its KS contraction values, the workgroup's 128 rows as 16-byte
+// row vectors into an LDS tile laid out [k][row]; a lane then gathers its V
+// contraction values of one row from V tile rows.  Row blocks wholly past n skip
+// their MFMAs.
 #include <algorithm>
 #include <atomic>
 
@@ -25,7 +32,7 @@ namespace {
 
 constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
 
-template <int DT, int NCB>
+template <int DT, int NCB, bool IF = false>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
                                                          const void* __restrict__ Xtv, int64_t m, int r,
                                                          int64_t kchunk, double* __restrict__ part) {
@@ -44,8 +51,12 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   constexpr int RPR = 256 / CPR;            // rows per staging round (32)
   constexpr int AR = kRows / RPR;           // staging rounds of the tensor tile
   constexpr int BRN = (NJ + RPR - 1) / RPR; // staging rounds of the DRM tile
+  constexpr int RV = kRows / V;             // IF: row vectors per contraction value
+  constexpr int PITCHT = kRows + V;         // IF: LDS pitch of a contraction value's rows
+  constexpr int ASZ = IF ? KS * PITCHT : kRows * PITCH;
+  static_assert(!IF || (KPL == 1 && KS * RV == 256 * AR), "row-contiguous form: FP32 / FP64 tiles");
   typedef T vec_t __attribute__((ext_vector_type(V)));
-  __shared__ __align__(16) T As[2][kRows * PITCH];
+  __shared__ __align__(16) T As[2][ASZ];
   __shared__ __align__(16) T Bs[2][NJ * PITCH];
 
   const T* H = static_cast<const T*>(Hv);
@@ -65,10 +76,20 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     const bool live = k < k_end;
     const int64_t kk = k + sc;
     const int64_t q = kk / L, l = kk - q * L;
+    if constexpr (IF) {
+      // H[i + n q]: thread -> row vector tid % RV of contraction values tid / RV (+ 256 / RV a round)
 #pragma unroll
-    for (int u = 0; u < AR; ++u) {
-      const int64_t row = row0 + sr + RPR * u;
-      ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
+      for (int u = 0; u < AR; ++u) {
+        const int e = tid + 256 * u;
+        const int64_t qq = k + e / RV, row = row0 + static_cast<int64_t>(e % RV) * V;
+        ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + row + n * qq) : vec_t{};
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < AR; ++u) {
+        const int64_t row = row0 + sr + RPR * u;
+        ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
+      }
     }
 #pragma unroll
     for (int u = 0; u < BRN; ++u) {
@@ -77,8 +98,16 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
   };
   auto lstore = [&](int buf, const vec_t* ra, const vec_t* rb) {
+    if constexpr (IF) {
 #pragma unroll
-    for (int u = 0; u < AR; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPR * u) * PITCH + sc]) = ra[u];
+      for (int u = 0; u < AR; ++u) {
+        const int e = tid + 256 * u;
+        *reinterpret_cast<vec_t*>(&As[buf][(e / RV) * PITCHT + (e % RV) * V]) = ra[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < AR; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPR * u) * PITCH + sc]) = ra[u];
+    }
 #pragma unroll
     for (int u = 0; u < BRN; ++u)
       if (sr + RPR * u < NJ) *reinterpret_cast<vec_t*>(&Bs[buf][(sr + RPR * u) * PITCH + sc]) = rb[u];
@@ -96,15 +125,25 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     for (int h = 0; h < KS / KG; ++h) {
       const int kl = h * KG + V * lg;
       vec_t a[2], bx[NCB];
+      if constexpr (IF) {
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
-        a[b] = *reinterpret_cast<const vec_t*>(&As[buf][(32 * wave + 16 * b + l16) * PITCH + kl]);
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int s = 0; s < V; ++s) a[b][s] = As[buf][(kl + s) * PITCHT + 32 * wave + 16 * b + l16];
+      } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          a[b] = *reinterpret_cast<const vec_t*>(&As[buf][(32 * wave + 16 * b + l16) * PITCH + kl]);
+      }
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) bx[cb] = *reinterpret_cast<const vec_t*>(&Bs[buf][(16 * cb + l16) * PITCH + kl]);
 #pragma unroll
       for (int s = 0; s < SUB; ++s) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
+          if constexpr (IF) {
+            if (row0 + 32 * wave + 16 * b >= n) continue;   // wave-uniform: rows past n
+          }
           Frag af;
           if constexpr (KPL == 8) af = __builtin_bit_cast(Frag, a[b]);
           else af = a[b][s];
@@ -152,17 +191,19 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
 }
 
-template <int DT>
+template <int DT, bool IF = false>
 void launch_dt(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
                int64_t nch, double* part, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n + kRows - 1) / kRows), static_cast<unsigned>(nch));
   const int ncb = (r + 15) / 16;
-  if (ncb <= 1) hipLaunchKernelGGL((right_mfma_kernel<DT, 1>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+  if (ncb <= 1)
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
   else if (ncb == 2)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 2>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
   else if (ncb == 3)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 3>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
-  else hipLaunchKernelGGL((right_mfma_kernel<DT, 4>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+  else
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
 }
 
 // compute units of the current device (queried once per device; threads that race
@@ -188,7 +229,11 @@ bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
   (void)n;
   (void)Q;
   const int64_t ks = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;   // staged step: 128 bytes of a row
-  return L % ks == 0 && L >= 64 && r >= 1 && r <= 64;
+  if (r < 1 || r > 64) return false;
+  if (L % ks == 0 && L >= 64) return true;
+  // row-contiguous form: whole 16-byte row vectors, whole steps
+  const int64_t v = dt == TTNN_F32 ? 4 : 2;
+  return L == 1 && dt != TTNN_BF16 && n % v == 0 && Q % ks == 0 && Q >= 64;
 }
 
 int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
@@ -208,8 +253,12 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   int64_t kchunk = (K + nch - 1) / nch;
   kchunk = (kchunk + kg - 1) / kg * kg;
   nch = (K + kchunk - 1) / kchunk;
+  TTNN_REQUIRE(right_mfma_eligible(L, n, Q, r, dt), TTNN_E_INVALID, "right sketch shape not covered by the MFMA form");
+  const bool rowc = !(L % kg == 0 && L >= 64);
   if (dt == TTNN_BF16) launch_dt<TTNN_BF16>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else if (dt == TTNN_F32 && rowc) launch_dt<TTNN_F32, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   else if (dt == TTNN_F32) launch_dt<TTNN_F32>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else if (rowc) launch_dt<TTNN_F64, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   else launch_dt<TTNN_F64>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   return static_cast<int>(nch);
 }

@@ -1,0 +1,44 @@
+"""GPU parity of the row-contiguous MFMA form of the whole-tensor right sketch: nodes
+that start at mode 1 (no modes before them, so the contraction index is the slow one
+and the rows run along memory).  Order-3 tensor 20 x 8 x 32768 (5.2M entries, large
+enough for the MFMA form) on ((1,2),3): node {1} (20 rows: one row block, three of
+its four waves past n), node {1,2} (160 rows: a second, ragged row block), both in
+the row-contiguous form, and node {3} in the long-leading-mode form; r = 6 (one
+column block) and 17 (two), FP64 and FP32, against the FP64 oracle on the consumed
+values, elementwise within the dtype tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from gpu_util import TOL, sketch_errors, to_device
+
+pytestmark = pytest.mark.gpu
+
+DIMS, SPEC = (20, 8, 32768), ((1, 2), 3)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2412_06111_amd as P
+    assert torch.cuda.is_available()
+    return P
+
+
+@pytest.fixture(scope="module")
+def tensor():
+    return np.random.default_rng(19).standard_normal(DIMS)
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("dtype,r", [("f64", 6), ("f64", 17), ("f32", 17)])
+def test_row_contiguous_right_sketch(P, tensor, variant, dtype, r):
+    dev, consumed = to_device(tensor, dtype)
+    plan = P.Plan(SPEC, DIMS, r, 3, variant=variant, dtype=dtype, seed=13)
+    plan.update(dev)
+    tree = O.Tree(SPEC, DIMS, r, 3)
+    sk = O.sketch(consumed, tree, O.DRMs(tree, 13, variant), variant)
+    errs = sketch_errors(plan, tree, sk)
+    plan.close()
+    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    assert not bad, (bad, errs)
