@@ -517,7 +517,8 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
   for (const auto& pf : fused_prefixes) done[pf] = true;
   Batch batch(P, st);
   // The first contraction of the raw block runs on the generic kernel with the
-  // compute-dtype DRMs; every contraction of an FP64 intermediate uses the FP64
+  // compute-dtype DRMs (on the MFMA right form when the whole tensor is contracted
+  // with Y^T of a group at mode 1); every contraction of an FP64 intermediate uses the FP64
   // DRMs (batched MFMA GEMM for whole-tensor updates, generic kernel for boxes).
   auto chain_ptr = [&](const std::vector<int>& pf) { return P.chain + P.prefix_offset.at(pf); };
 
@@ -551,7 +552,15 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
         a.ncols = g.k;
         a.amap = box_rows(P, g.first, g.last, off, ext);
         join_side(P, st);                       // shares the partial scratch
-        left_op(P, a, chain_ptr(chain), 2, 1.0, st);
+        if (before.empty() && whole && L == 1 && g.Yt) {
+          // raw tensor, group at mode 1: Z[j + k q] = sum_i T[i + n q] Y[i][j] is the
+          // MFMA right form with the contraction (i) contiguous and q as the row
+          const int nch = launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, P.partial, P.partial_elems, st);
+          IndexMap none;
+          launch_reduce(P.partial, nch, Q, g.k, 2, 1.0, none, 0, chain_ptr(chain), 1, g.k, st);
+        } else {
+          left_op(P, a, chain_ptr(chain), 2, 1.0, st);
+        }
       }
       done[chain] = true;
     }

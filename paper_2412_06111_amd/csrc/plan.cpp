@@ -286,6 +286,12 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     const FusedT4& F = P->fused;
     for (int v = 1; v < nn; ++v) {
       Node& nd = P->nodes[v];
+      // Y_t^T applied to the raw tensor when t starts at mode 1 (the first contraction
+      // of a chain): T viewed as [n_t][N / n_t] with the contraction index contiguous
+      if (nd.first == 0 && right_mfma_eligible(nd.n, P->N / nd.n, 1, nd.k, P->dtype)) {
+        nd.Yt = P->alloc(dtype_size(P->dtype) * nd.n * nd.k);
+        if (fill) copy_layout(nd.Y64, nd.Yt, P->dtype, nd.n, nd.k, 1, nd.k, 1, 0, 0, nd.n, stream);
+      }
       if (!nd.S.empty()) continue;
       if (F.enabled && (v == F.node_A || v == F.node_1 || v == (F.tt ? F.node_B : F.node_2))) continue;
       int64_t L = 1;

@@ -19,8 +19,13 @@
 // contraction index q is the slow one and the rows i run along memory, so a step
 // stages, for each of its KS contraction values, the workgroup's 128 rows as 16-byte
 // row vectors into an LDS tile laid out [k][row]; a lane then gathers its V
-// contraction values of one row from V tile rows.  Row blocks wholly past n skip
-// their MFMAs.
+// contraction values of one row from V tile rows.  In both forms, when n is not a
+// multiple of the 128 rows of a workgroup (SK), row blocks wholly past n skip their
+// MFMAs (a wave-uniform test).
+//
+// The contiguous form needs whole 16-byte vectors inside one l-run (L a multiple of
+// V) and whole steps (L Q a multiple of the step); the row-contiguous form needs whole
+// row vectors (n a multiple of V) and whole steps (Q a multiple of the step).
 #include <algorithm>
 #include <atomic>
 
@@ -32,7 +37,7 @@ namespace {
 
 constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
 
-template <int DT, int NCB, bool IF = false>
+template <int DT, int NCB, bool IF = false, bool SK = false>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
                                                          const void* __restrict__ Xtv, int64_t m, int r,
                                                          int64_t kchunk, double* __restrict__ part) {
@@ -141,7 +146,7 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
       for (int s = 0; s < SUB; ++s) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          if constexpr (IF) {
+          if constexpr (IF || SK) {
             if (row0 + 32 * wave + 16 * b >= n) continue;   // wave-uniform: rows past n
           }
           Frag af;
@@ -191,19 +196,33 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
 }
 
-template <int DT, bool IF = false>
-void launch_dt(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
-               int64_t nch, double* part, hipStream_t st) {
+template <int DT, bool IF, bool SK>
+void launch_form(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
+                 int64_t nch, double* part, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n + kRows - 1) / kRows), static_cast<unsigned>(nch));
   const int ncb = (r + 15) / 16;
   if (ncb <= 1)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
   else if (ncb == 2)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
   else if (ncb == 3)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
   else
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+}
+
+template <int DT>
+void launch_dt(bool rowc, const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
+               int64_t kchunk, int64_t nch, double* part, hipStream_t st) {
+  const bool sk = n % kRows != 0;
+  if constexpr (DT != TTNN_BF16) {
+    if (rowc) {
+      launch_form<DT, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+      return;
+    }
+  }
+  if (sk) launch_form<DT, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else launch_form<DT, false, false>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
 }
 
 // compute units of the current device (queried once per device; threads that race
@@ -226,13 +245,12 @@ int compute_units() {
 }  // namespace
 
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
-  (void)n;
-  (void)Q;
   const int64_t ks = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;   // staged step: 128 bytes of a row
-  if (r < 1 || r > 64) return false;
-  if (L % ks == 0 && L >= 64) return true;
-  // row-contiguous form: whole 16-byte row vectors, whole steps
-  const int64_t v = dt == TTNN_F32 ? 4 : 2;
+  const int64_t v = 16 / (dt == TTNN_BF16 ? 2 : dt == TTNN_F32 ? 4 : 8);   // values per 16-byte vector
+  if (r < 1 || r > 64 || n < 1 || Q < 1) return false;
+  // contiguous form: whole vectors inside one l-run, whole steps
+  if (L >= v && L % v == 0 && (L * Q) % ks == 0 && L * Q >= 64) return true;
+  // row-contiguous form: whole row vectors, whole steps
   return L == 1 && dt != TTNN_BF16 && n % v == 0 && Q % ks == 0 && Q >= 64;
 }
 
@@ -254,12 +272,10 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   kchunk = (kchunk + kg - 1) / kg * kg;
   nch = (K + kchunk - 1) / kchunk;
   TTNN_REQUIRE(right_mfma_eligible(L, n, Q, r, dt), TTNN_E_INVALID, "right sketch shape not covered by the MFMA form");
-  const bool rowc = !(L % kg == 0 && L >= 64);
-  if (dt == TTNN_BF16) launch_dt<TTNN_BF16>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else if (dt == TTNN_F32 && rowc) launch_dt<TTNN_F32, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else if (dt == TTNN_F32) launch_dt<TTNN_F32>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else if (rowc) launch_dt<TTNN_F64, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else launch_dt<TTNN_F64>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  const bool rowc = L == 1;
+  if (dt == TTNN_BF16) launch_dt<TTNN_BF16>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else if (dt == TTNN_F32) launch_dt<TTNN_F32>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else launch_dt<TTNN_F64>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   return static_cast<int>(nch);
 }
 

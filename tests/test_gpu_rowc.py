@@ -1,11 +1,19 @@
-"""GPU parity of the row-contiguous MFMA form of the whole-tensor right sketch: nodes
-that start at mode 1 (no modes before them, so the contraction index is the slow one
-and the rows run along memory).  Order-3 tensor 20 x 8 x 32768 (5.2M entries, large
-enough for the MFMA form) on ((1,2),3): node {1} (20 rows: one row block, three of
-its four waves past n), node {1,2} (160 rows: a second, ragged row block), both in
-the row-contiguous form, and node {3} in the long-leading-mode form; r = 6 (one
-column block) and 17 (two), FP64 and FP32, against the FP64 oracle on the consumed
-values, elementwise within the dtype tolerance."""
+"""GPU parity of the MFMA forms of the whole-tensor contractions on shapes beyond the
+order-4 sweep, through the C ABI.  Order-3 tensor 20 x 8 x 32768 (5.2M entries, large
+enough for the MFMA forms) on ((1,2),3):
+
+* row-contiguous right sketches (nodes that start at mode 1, where the contraction
+  index is the slow one): node {1} (20 rows: one row block, three of its four waves
+  past n), node {1,2} (160 rows: a second, ragged row block); FP64 / FP32;
+* contiguous right sketches with short l-runs: node {2} (L = 20, 8 rows), and node
+  {3} (L = 160, full row blocks);
+* Y^T of a group at mode 1 applied to the raw tensor (the root sketch's first
+  contraction, and STTNN's reuse prefixes), as the contiguous form with the
+  contraction along the group's modes;
+
+r = 6 (one column block) and 17 (two), against the FP64 oracle on the consumed
+values, elementwise within the dtype tolerance (BF16 takes the forms its 16-byte
+vectors allow)."""
 import numpy as np
 import pytest
 import torch
@@ -31,7 +39,7 @@ def tensor():
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
-@pytest.mark.parametrize("dtype,r", [("f64", 6), ("f64", 17), ("f32", 17)])
+@pytest.mark.parametrize("dtype,r", [("f64", 6), ("f64", 17), ("f32", 17), ("bf16", 17)])
 def test_row_contiguous_right_sketch(P, tensor, variant, dtype, r):
     dev, consumed = to_device(tensor, dtype)
     plan = P.Plan(SPEC, DIMS, r, 3, variant=variant, dtype=dtype, seed=13)
