@@ -554,10 +554,17 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
         join_side(P, st);                       // shares the partial scratch
         if (before.empty() && whole && L == 1 && g.Yt) {
           // raw tensor, group at mode 1: Z[j + k q] = sum_i T[i + n q] Y[i][j] is the
-          // MFMA right form with the contraction (i) contiguous and q as the row
-          const int nch = launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, P.partial, P.partial_elems, st);
-          IndexMap none;
-          launch_reduce(P.partial, nch, Q, g.k, 2, 1.0, none, 0, chain_ptr(chain), 1, g.k, st);
+          // MFMA right form with the contraction (i) contiguous and q as the row.  Its
+          // one-chunk partial layout is Z's, so when the scratch cannot hold two chunks
+          // the kernel writes Z directly (one chunk: the rows alone fill the machine)
+          const size_t out = static_cast<size_t>(Q) * static_cast<size_t>(g.k);
+          if (2 * out <= P.partial_elems) {
+            const int nch = launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, P.partial, P.partial_elems, st);
+            IndexMap none;
+            launch_reduce(P.partial, nch, Q, g.k, 2, 1.0, none, 0, chain_ptr(chain), 1, g.k, st);
+          } else {
+            launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, chain_ptr(chain), out, st);
+          }
         } else {
           left_op(P, a, chain_ptr(chain), 2, 1.0, st);
         }
@@ -611,6 +618,14 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
     const int p0 = position_of_mode(ps, t.first);
     const int w = t.last - t.first + 1;
     const int64_t L = prod_ext(ps, 0, p0), n = prod_ext(ps, p0, p0 + w), Q = prod_ext(ps, p0 + w, ps.size());
+    if (!pre.empty() && whole && t.Xt64 && right_mfma_eligible(L, n, Q, t.r, TTNN_F64)) {
+      // FP64 intermediate, contraction contiguous: MFMA right form
+      batch.flush();
+      join_side(P, st);
+      const int nch = launch_right_mfma(in, TTNN_F64, L, n, Q, t.Xt64, t.m, t.r, P.partial, P.partial_elems, st);
+      launch_reduce(P.partial, nch, n, t.r, 0, alpha, box_rows(P, t.first, t.last, off, ext), t.n, t.R, 1, 1, st);
+      continue;
+    }
     if (!pre.empty() && whole) {
       if (batch.writes(in)) batch.flush();
       batch.add(right_job(static_cast<const double*>(in), L, n, Q, t.X64, t.r, t.R, alpha));

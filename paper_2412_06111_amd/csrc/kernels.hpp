@@ -168,7 +168,9 @@ void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const 
 // ---------------------------------------------------------------- whole-tensor right sketch on MFMA
 // H (dtype dt) viewed as [L][n][Q] (l fastest); Xt is the transposed DRM copy (r x m,
 // m = L Q, contraction index contiguous).  Writes FP64 chunk partials
-// part[(c n + i) r + j] and returns the number of chunks (sum them with launch_reduce).
+// part[(c n + i) r + j] and returns the number of chunks (sum them with launch_reduce);
+// the chunks are as many as part_elems holds, so with part_elems = n r the single
+// chunk is the result itself.  Throws if part_elems < n r.
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt);
 int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
                       double* part, size_t part_elems, hipStream_t stream);

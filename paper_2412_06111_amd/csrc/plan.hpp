@@ -28,6 +28,8 @@ struct Node {
   double* X64 = nullptr;       // m x r row-major
   void* Xc = nullptr;          // compute-dtype copy (== X64 for FP64 plans)
   void* Xt = nullptr;          // transposed compute-dtype copy (r x m) for whole-tensor MFMA sketches
+  double* Xt64 = nullptr;      // transposed FP64 copy (r x m) for MFMA right sketches of the
+                               // FP64 intermediates (STTNN nodes with a reuse set)
   void* Yt = nullptr;          // transposed compute-dtype copy (k x n) for whole-tensor MFMA
                                // contractions with Y^T of a node that starts at mode 1
   double* Y64 = nullptr;       // n x k row-major

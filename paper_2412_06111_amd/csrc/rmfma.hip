@@ -24,8 +24,9 @@
 // MFMAs (a wave-uniform test).
 //
 // The contiguous form needs whole 16-byte vectors inside one l-run (L a multiple of
-// V) and whole steps (L Q a multiple of the step); the row-contiguous form needs whole
-// row vectors (n a multiple of V) and whole steps (Q a multiple of the step).
+// V); when L Q is not a multiple of the step (KT) the last step is masked vector by
+// vector.  The row-contiguous form needs whole row vectors (n a multiple of V) and
+// whole steps (Q a multiple of the step).
 #include <algorithm>
 #include <atomic>
 
@@ -37,7 +38,7 @@ namespace {
 
 constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
 
-template <int DT, int NCB, bool IF = false, bool SK = false>
+template <int DT, int NCB, bool IF = false, bool SK = false, bool KT = false>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
                                                          const void* __restrict__ Xtv, int64_t m, int r,
                                                          int64_t kchunk, double* __restrict__ part) {
@@ -78,8 +79,8 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   const int sr = tid / CPR, sc = (tid % CPR) * V;
   vec_t ra0[AR], rb0[BRN], ra1[AR], rb1[BRN];   // two steps of loads in flight
   auto gload = [&](int64_t k, vec_t* ra, vec_t* rb) {
-    const bool live = k < k_end;
     const int64_t kk = k + sc;
+    const bool live = (KT ? kk : k) < k_end;
     const int64_t q = kk / L, l = kk - q * L;
     if constexpr (IF) {
       // H[i + n q]: thread -> row vector tid % RV of contraction values tid / RV (+ 256 / RV a round)
@@ -196,19 +197,23 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
 }
 
-template <int DT, bool IF, bool SK>
+template <int DT, bool IF, bool SK, bool KT = false>
 void launch_form(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
                  int64_t nch, double* part, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n + kRows - 1) / kRows), static_cast<unsigned>(nch));
   const int ncb = (r + 15) / 16;
   if (ncb <= 1)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+                       part);
   else if (ncb == 2)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+                       part);
   else if (ncb == 3)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+                       part);
   else
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk, part);
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+                       part);
 }
 
 template <int DT>
@@ -221,7 +226,9 @@ void launch_dt(bool rowc, const void* H, int64_t L, int64_t n, int64_t Q, const 
       return;
     }
   }
-  if (sk) launch_form<DT, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  constexpr int64_t KS = 2 * 4 * (16 / Pol<DT>::ESZ);   // the kernel's staged step
+  if ((L * Q) % KS != 0) launch_form<DT, false, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  else if (sk) launch_form<DT, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   else launch_form<DT, false, false>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
 }
 
@@ -248,14 +255,17 @@ bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
   const int64_t ks = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;   // staged step: 128 bytes of a row
   const int64_t v = 16 / (dt == TTNN_BF16 ? 2 : dt == TTNN_F32 ? 4 : 8);   // values per 16-byte vector
   if (r < 1 || r > 64 || n < 1 || Q < 1) return false;
-  // contiguous form: whole vectors inside one l-run, whole steps
-  if (L >= v && L % v == 0 && (L * Q) % ks == 0 && L * Q >= 64) return true;
+  // contiguous form: whole vectors inside one l-run
+  if (L >= v && L % v == 0 && L * Q >= 16) return true;
   // row-contiguous form: whole row vectors, whole steps
   return L == 1 && dt != TTNN_BF16 && n % v == 0 && Q % ks == 0 && Q >= 64;
 }
 
 int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
                       double* part, size_t part_elems, hipStream_t st) {
+  TTNN_REQUIRE(right_mfma_eligible(L, n, Q, r, dt), TTNN_E_INVALID, "right sketch shape not covered by the MFMA form");
+  TTNN_REQUIRE(part_elems >= static_cast<size_t>(n) * static_cast<size_t>(r), TTNN_E_INVALID,
+               "partial buffer smaller than one chunk of the right sketch");
   const int64_t K = L * Q;
   const int64_t kg = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;    // staged step
   const int64_t row_blocks = (n + kRows - 1) / kRows;
@@ -271,7 +281,6 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   int64_t kchunk = (K + nch - 1) / nch;
   kchunk = (kchunk + kg - 1) / kg * kg;
   nch = (K + kchunk - 1) / kchunk;
-  TTNN_REQUIRE(right_mfma_eligible(L, n, Q, r, dt), TTNN_E_INVALID, "right sketch shape not covered by the MFMA form");
   const bool rowc = L == 1;
   if (dt == TTNN_BF16) launch_dt<TTNN_BF16>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   else if (dt == TTNN_F32) launch_dt<TTNN_F32>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
