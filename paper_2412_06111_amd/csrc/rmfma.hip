@@ -23,6 +23,12 @@
 // multiple of the 128 rows of a workgroup (SK), row blocks wholly past n skip their
 // MFMAs (a wave-uniform test).
 //
+// Few rows (SN, n <= 32, contiguous form): a 128-row tile would hold a quarter of real
+// rows or less, so each step would move a fraction of the bytes it is sized for and the
+// pass would be bound by the bytes in flight.  The tile is then 32 rows by four steps'
+// worth of contraction values; each wave takes one quarter of every staged step for
+// both row blocks, and the four waves' sums are added in wave order through LDS.
+//
 // The contiguous form needs whole 16-byte vectors inside one l-run (L a multiple of
 // V); when L Q is not a multiple of the step (KT) the last step is masked vector by
 // vector.  The row-contiguous form needs whole row vectors (n a multiple of V) and
@@ -37,8 +43,9 @@ namespace ttnn {
 namespace {
 
 constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
+constexpr int kRowsFew = 32;   // at most this many rows: the few-rows tile (one row block pair)
 
-template <int DT, int NCB, bool IF = false, bool SK = false, bool KT = false>
+template <int DT, int NCB, bool IF = false, bool SK = false, bool KT = false, bool SN = false>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
                                                          const void* __restrict__ Xtv, int64_t m, int r,
                                                          int64_t kchunk, double* __restrict__ part) {
@@ -57,13 +64,21 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   constexpr int RPR = 256 / CPR;            // rows per staging round (32)
   constexpr int AR = kRows / RPR;           // staging rounds of the tensor tile
   constexpr int BRN = (NJ + RPR - 1) / RPR; // staging rounds of the DRM tile
+  constexpr int ROWS = SN ? 32 : kRows;     // output rows per workgroup
+  constexpr int KSX = SN ? 4 * KS : KS;     // contraction values per staged step
+  constexpr int CPRX = KSX / V;
+  constexpr int PITCHX = KSX + V;
+  constexpr int RPRX = 256 / CPRX;
+  constexpr int ARX = ROWS / RPRX;
+  constexpr int BRNX = (NJ + RPRX - 1) / RPRX;
+  static_assert(!(IF && SN), "one tile form at a time");
   constexpr int RV = kRows / V;             // IF: row vectors per contraction value
   constexpr int PITCHT = kRows + V;         // IF: LDS pitch of a contraction value's rows
-  constexpr int ASZ = IF ? KS * PITCHT : kRows * PITCH;
+  constexpr int ASZ = IF ? KS * PITCHT : ROWS * PITCHX;
   static_assert(!IF || (KPL == 1 && KS * RV == 256 * AR), "row-contiguous form: FP32 / FP64 tiles");
   typedef T vec_t __attribute__((ext_vector_type(V)));
   __shared__ __align__(16) T As[2][ASZ];
-  __shared__ __align__(16) T Bs[2][NJ * PITCH];
+  __shared__ __align__(16) T Bs[2][NJ * PITCHX];
 
   const T* H = static_cast<const T*>(Hv);
   const T* Xt = static_cast<const T*>(Xtv);
@@ -76,8 +91,8 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   const int64_t k_end = k_begin + kchunk < K ? k_begin + kchunk : K;
 
   // staging map: thread -> row tid / CPR (+ RPR per round), chunk tid % CPR
-  const int sr = tid / CPR, sc = (tid % CPR) * V;
-  vec_t ra0[AR], rb0[BRN], ra1[AR], rb1[BRN];   // two steps of loads in flight
+  const int sr = tid / CPRX, sc = (tid % CPRX) * V;
+  vec_t ra0[ARX], rb0[BRNX], ra1[ARX], rb1[BRNX];   // two steps of loads in flight
   auto gload = [&](int64_t k, vec_t* ra, vec_t* rb) {
     const int64_t kk = k + sc;
     const bool live = (KT ? kk : k) < k_end;
@@ -92,14 +107,14 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < AR; ++u) {
-        const int64_t row = row0 + sr + RPR * u;
+      for (int u = 0; u < ARX; ++u) {
+        const int64_t row = row0 + sr + RPRX * u;
         ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
       }
     }
 #pragma unroll
-    for (int u = 0; u < BRN; ++u) {
-      const int j = sr + RPR * u;
+    for (int u = 0; u < BRNX; ++u) {
+      const int j = sr + RPRX * u;
       rb[u] = (live && j < r) ? *reinterpret_cast<const vec_t*>(Xt + static_cast<int64_t>(j) * m + kk) : vec_t{};
     }
   };
@@ -112,11 +127,11 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
       }
     } else {
 #pragma unroll
-      for (int u = 0; u < AR; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPR * u) * PITCH + sc]) = ra[u];
+      for (int u = 0; u < ARX; ++u) *reinterpret_cast<vec_t*>(&As[buf][(sr + RPRX * u) * PITCHX + sc]) = ra[u];
     }
 #pragma unroll
-    for (int u = 0; u < BRN; ++u)
-      if (sr + RPR * u < NJ) *reinterpret_cast<vec_t*>(&Bs[buf][(sr + RPR * u) * PITCH + sc]) = rb[u];
+    for (int u = 0; u < BRNX; ++u)
+      if (sr + RPRX * u < NJ) *reinterpret_cast<vec_t*>(&Bs[buf][(sr + RPRX * u) * PITCHX + sc]) = rb[u];
   };
 
   CFrag acc[2][NCB];
@@ -129,7 +144,8 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   auto compute = [&](int buf) {
 #pragma unroll
     for (int h = 0; h < KS / KG; ++h) {
-      const int kl = h * KG + V * lg;
+      const int kl = (SN ? KS * wave : 0) + h * KG + V * lg;
+      constexpr int WROWS = SN ? 0 : 32;      // rows a wave owns (SN: all 32, every wave)
       vec_t a[2], bx[NCB];
       if constexpr (IF) {
 #pragma unroll
@@ -139,16 +155,17 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
       } else {
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          a[b] = *reinterpret_cast<const vec_t*>(&As[buf][(32 * wave + 16 * b + l16) * PITCH + kl]);
+          a[b] = *reinterpret_cast<const vec_t*>(&As[buf][(WROWS * wave + 16 * b + l16) * PITCHX + kl]);
       }
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) bx[cb] = *reinterpret_cast<const vec_t*>(&Bs[buf][(16 * cb + l16) * PITCH + kl]);
+      for (int cb = 0; cb < NCB; ++cb)
+        bx[cb] = *reinterpret_cast<const vec_t*>(&Bs[buf][(16 * cb + l16) * PITCHX + kl]);
 #pragma unroll
       for (int s = 0; s < SUB; ++s) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           if constexpr (IF || SK) {
-            if (row0 + 32 * wave + 16 * b >= n) continue;   // wave-uniform: rows past n
+            if (row0 + WROWS * wave + 16 * b >= n) continue;   // wave-uniform: rows past n
           }
           Frag af;
           if constexpr (KPL == 8) af = __builtin_bit_cast(Frag, a[b]);
@@ -167,22 +184,49 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
 
   // step s is staged in LDS buffer s % 2 and its loads were issued two steps earlier
   gload(k_begin, ra0, rb0);
-  gload(k_begin + KS, ra1, rb1);
+  gload(k_begin + KSX, ra1, rb1);
   lstore(0, ra0, rb0);
   __syncthreads();
-  for (int64_t k = k_begin; k < k_end; k += 2 * KS) {
-    gload(k + 2 * KS, ra0, rb0);             // step s + 2
+  for (int64_t k = k_begin; k < k_end; k += 2 * KSX) {
+    gload(k + 2 * KSX, ra0, rb0);            // step s + 2
     compute(0);                              // step s
     lstore(1, ra1, rb1);                     // step s + 1 (buffer 1 was read before the last barrier)
     __syncthreads();
-    if (k + KS >= k_end) break;
-    gload(k + 3 * KS, ra1, rb1);             // step s + 3
+    if (k + KSX >= k_end) break;
+    gload(k + 3 * KSX, ra1, rb1);            // step s + 3
     compute(1);                              // step s + 1
     lstore(0, ra0, rb0);                     // step s + 2
     __syncthreads();
   }
 
   // partial of chunk c: part[(c n + i) r + j]
+  if constexpr (SN) {
+    // every wave holds its quarters' sums for all 32 rows: add them in wave order
+    // through LDS (the A tile is free after the loop's last barrier), one column block
+    // at a time; thread t delivers entries t and t + 256 of the block's 2 x 4 x 64
+    double* red = reinterpret_cast<double*>(&As[0][0]);
+    static_assert(2 * ASZ * sizeof(T) >= 4 * 512 * sizeof(double), "reduction fits the A tile");
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 8 + b * 4 + v) * 64 + lane] = static_cast<double>(acc[b][cb][v]);
+      __syncthreads();
+#pragma unroll
+      for (int e0 = 0; e0 < 512; e0 += 256) {
+        const int e = e0 + tid, b = e >> 8, v = (e >> 6) & 3, ln = e & 63;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) sum += red[(w * 8 + b * 4 + v) * 64 + ln];
+        const int64_t i = row0 + 16 * b + P::crow(ln, v);
+        const int j = 16 * cb + (ln & 15);
+        if (i < n && j < r) part[(c * n + i) * r + j] = sum;
+      }
+      __syncthreads();
+    }
+    return;
+  }
 #pragma unroll
   for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -197,22 +241,22 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
 }
 
-template <int DT, bool IF, bool SK, bool KT = false>
+template <int DT, bool IF, bool SK, bool KT = false, bool SN = false>
 void launch_form(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
                  int64_t nch, double* part, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n + kRows - 1) / kRows), static_cast<unsigned>(nch));
   const int ncb = (r + 15) / 16;
   if (ncb <= 1)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else if (ncb == 2)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else if (ncb == 3)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK, KT>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
 }
 
@@ -227,9 +271,16 @@ void launch_dt(bool rowc, const void* H, int64_t L, int64_t n, int64_t Q, const 
     }
   }
   constexpr int64_t KS = 2 * 4 * (16 / Pol<DT>::ESZ);   // the kernel's staged step
-  if ((L * Q) % KS != 0) launch_form<DT, false, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else if (sk) launch_form<DT, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
-  else launch_form<DT, false, false>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  if (n <= kRowsFew) {                                 // few rows: 32-row tiles of 4 steps
+    if ((L * Q) % (4 * KS) != 0) launch_form<DT, false, true, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+    else launch_form<DT, false, true, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  } else if ((L * Q) % KS != 0) {
+    launch_form<DT, false, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  } else if (sk) {
+    launch_form<DT, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  } else {
+    launch_form<DT, false, false>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+  }
 }
 
 // compute units of the current device (queried once per device; threads that race
@@ -267,7 +318,8 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   TTNN_REQUIRE(part_elems >= static_cast<size_t>(n) * static_cast<size_t>(r), TTNN_E_INVALID,
                "partial buffer smaller than one chunk of the right sketch");
   const int64_t K = L * Q;
-  const int64_t kg = dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16;    // staged step
+  const bool few = L != 1 && n <= kRowsFew;
+  const int64_t kg = (dt == TTNN_BF16 ? 64 : dt == TTNN_F32 ? 32 : 16) * (few ? 4 : 1);   // staged step
   const int64_t row_blocks = (n + kRows - 1) / kRows;
   // enough workgroups to fill the chip twice, chunks of at least 1024 values, and
   // partials within the scratch

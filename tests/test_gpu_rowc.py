@@ -50,3 +50,26 @@ def test_row_contiguous_right_sketch(P, tensor, variant, dtype, r):
     plan.close()
     bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
     assert not bad, (bad, errs)
+
+
+# Few rows (node {2} with n_t <= 32): the 32-row tile that takes four steps a stage and
+# splits each over the waves.  (18, 8, 30030): L = 18, K = 540540, not a multiple of the
+# four-step stage, so the last stage is masked vector by vector (FP64; FP32 / BF16 vectors
+# do not fit an l-run of 18).  (16, 24, 11000): L = 16, 24 rows (the second row block
+# ragged); whole stages in FP64 / FP32, a masked last stage in BF16.
+FEW = [((18, 8, 30030), "f64"), ((16, 24, 11000), "f64"), ((16, 24, 11000), "f32"), ((16, 24, 11000), "bf16")]
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("dims,dtype", FEW, ids=[f"{d[0]}x{d[1]}x{d[2]}-{t}" for d, t in FEW])
+def test_few_rows_right_sketch(P, variant, dims, dtype):
+    T = np.random.default_rng(23).standard_normal(dims)
+    dev, consumed = to_device(T, dtype)
+    plan = P.Plan(SPEC, dims, 6, 3, variant=variant, dtype=dtype, seed=29)
+    plan.update(dev)
+    tree = O.Tree(SPEC, dims, 6, 3)
+    sk = O.sketch(consumed, tree, O.DRMs(tree, 29, variant), variant)
+    errs = sketch_errors(plan, tree, sk)
+    plan.close()
+    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    assert not bad, (bad, errs)
