@@ -29,6 +29,10 @@
 // worth of contraction values; each wave takes one quarter of every staged step for
 // both row blocks, and the four waves' sums are added in wave order through LDS.
 //
+// Odd l-runs (S1, FP64, L odd): a lane's two consecutive contraction values may lie in
+// two l-runs, so the tensor operand is loaded as two 8-byte values, the second one
+// stepping to the next run when the first ends one.
+//
 // The contiguous form needs whole 16-byte vectors inside one l-run (L a multiple of
 // V); when L Q is not a multiple of the step (KT) the last step is masked vector by
 // vector.  The row-contiguous form needs whole row vectors (n a multiple of V) and
@@ -45,7 +49,7 @@ namespace {
 constexpr int kRows = 128;     // output rows per workgroup (4 waves x 2 row blocks of 16)
 constexpr int kRowsFew = 32;   // at most this many rows: the few-rows tile (one row block pair)
 
-template <int DT, int NCB, bool IF = false, bool SK = false, bool KT = false, bool SN = false>
+template <int DT, int NCB, bool IF = false, bool SK = false, bool KT = false, bool SN = false, bool S1 = false>
 __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict__ Hv, int64_t L, int64_t n, int64_t Q,
                                                          const void* __restrict__ Xtv, int64_t m, int r,
                                                          int64_t kchunk, double* __restrict__ part) {
@@ -72,6 +76,7 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
   constexpr int ARX = ROWS / RPRX;
   constexpr int BRNX = (NJ + RPRX - 1) / RPRX;
   static_assert(!(IF && SN), "one tile form at a time");
+  static_assert(!S1 || (DT == TTNN_F64 && !IF), "odd l-runs: FP64 contiguous form");
   constexpr int RV = kRows / V;             // IF: row vectors per contraction value
   constexpr int PITCHT = kRows + V;         // IF: LDS pitch of a contraction value's rows
   constexpr int ASZ = IF ? KS * PITCHT : ROWS * PITCHX;
@@ -106,10 +111,25 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
         ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + row + n * qq) : vec_t{};
       }
     } else {
+      if constexpr (S1) {
+        // value kk at (l, q), value kk + 1 at (l + 1, q) or at (0, q + 1)
+        const int64_t l1 = l + 1 == L ? 0 : l + 1, q1 = l + 1 == L ? q + 1 : q;
 #pragma unroll
-      for (int u = 0; u < ARX; ++u) {
-        const int64_t row = row0 + sr + RPRX * u;
-        ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
+        for (int u = 0; u < ARX; ++u) {
+          const int64_t row = row0 + sr + RPRX * u;
+          vec_t v{};
+          if (live && row < n) {
+            v[0] = H[l + L * (row + n * q)];
+            v[1] = H[l1 + L * (row + n * q1)];
+          }
+          ra[u] = v;
+        }
+      } else {
+#pragma unroll
+        for (int u = 0; u < ARX; ++u) {
+          const int64_t row = row0 + sr + RPRX * u;
+          ra[u] = (live && row < n) ? *reinterpret_cast<const vec_t*>(H + l + L * (row + n * q)) : vec_t{};
+        }
       }
     }
 #pragma unroll
@@ -241,22 +261,22 @@ __global__ __launch_bounds__(256) void right_mfma_kernel(const void* __restrict_
     }
 }
 
-template <int DT, bool IF, bool SK, bool KT = false, bool SN = false>
+template <int DT, bool IF, bool SK, bool KT = false, bool SN = false, bool S1 = false>
 void launch_form(const void* H, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r, int64_t kchunk,
                  int64_t nch, double* part, hipStream_t st) {
   const dim3 grid(static_cast<unsigned>((n + kRows - 1) / kRows), static_cast<unsigned>(nch));
   const int ncb = (r + 15) / 16;
   if (ncb <= 1)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 1, IF, SK, KT, SN, S1>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else if (ncb == 2)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 2, IF, SK, KT, SN, S1>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else if (ncb == 3)
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 3, IF, SK, KT, SN, S1>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
   else
-    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK, KT, SN>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
+    hipLaunchKernelGGL((right_mfma_kernel<DT, 4, IF, SK, KT, SN, S1>), grid, dim3(256), 0, st, H, L, n, Q, Xt, m, r, kchunk,
                        part);
 }
 
@@ -271,6 +291,15 @@ void launch_dt(bool rowc, const void* H, int64_t L, int64_t n, int64_t Q, const 
     }
   }
   constexpr int64_t KS = 2 * 4 * (16 / Pol<DT>::ESZ);   // the kernel's staged step
+  if constexpr (DT == TTNN_F64) {
+    if (L % 2 != 0) {                                  // odd l-runs: 8-byte tensor loads
+      const bool kt = (L * Q) % (n <= kRowsFew ? 4 * KS : KS) != 0;
+      if (n <= kRowsFew && kt) launch_form<DT, false, true, true, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+      else if (n <= kRowsFew) launch_form<DT, false, true, false, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+      else launch_form<DT, false, true, true, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
+      return;
+    }
+  }
   if (n <= kRowsFew) {                                 // few rows: 32-row tiles of 4 steps
     if ((L * Q) % (4 * KS) != 0) launch_form<DT, false, true, true, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
     else launch_form<DT, false, true, false, true>(H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
@@ -308,6 +337,8 @@ bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
   if (r < 1 || r > 64 || n < 1 || Q < 1) return false;
   // contiguous form: whole vectors inside one l-run
   if (L >= v && L % v == 0 && L * Q >= 16) return true;
+  // FP64 with odd l-runs: two 8-byte tensor loads a vector, whole DRM vectors
+  if (dt == TTNN_F64 && L > 1 && L % 2 == 1 && (L * Q) % 2 == 0 && L * Q >= 16) return true;
   // row-contiguous form: whole row vectors, whole steps
   return L == 1 && dt != TTNN_BF16 && n % v == 0 && Q % ks == 0 && Q >= 64;
 }

@@ -57,7 +57,11 @@ def test_row_contiguous_right_sketch(P, tensor, variant, dtype, r):
 # four-step stage, so the last stage is masked vector by vector (FP64; FP32 / BF16 vectors
 # do not fit an l-run of 18).  (16, 24, 11000): L = 16, 24 rows (the second row block
 # ragged); whole stages in FP64 / FP32, a masked last stage in BF16.
-FEW = [((18, 8, 30030), "f64"), ((16, 24, 11000), "f64"), ((16, 24, 11000), "f32"), ((16, 24, 11000), "bf16")]
+# STTNN on (20, 16, 32770) and (20, 40, 16384): node {2} is sketched on T x_1 Y_1^T, an
+# FP64 intermediate whose l-run is k_1 = 9 (odd), so FP64 vectors straddle runs and the
+# tensor operand is loaded value by value (few rows with a masked last stage; 40 rows).
+FEW = [((18, 8, 30030), "f64"), ((16, 24, 11000), "f64"), ((16, 24, 11000), "f32"), ((16, 24, 11000), "bf16"),
+       ((20, 16, 32770), "f64"), ((20, 40, 16384), "f64")]
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
