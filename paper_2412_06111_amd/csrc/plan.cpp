@@ -295,11 +295,12 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       if (F.enabled && (v == F.node_A || v == F.node_1 || v == (F.tt ? F.node_B : F.node_2))) continue;
       if (!nd.S.empty()) {
         // the intermediate T x_{s in S_t} Y_s^T: [prod k_s][n_t][modes after t]; only
-        // large ones (the small ones share batched FP64 launches)
+        // large ones (the small ones share batched FP64 launches), and only while the
+        // copy stays modest (it doubles the FP64 DRM of the node)
         int64_t Q = 1;
         for (int mu = nd.last + 1; mu < P->d; ++mu) Q *= P->dims[mu];
         const int64_t L = nd.m / Q;
-        if (L * Q == nd.m && L * nd.n * Q >= (int64_t(1) << 22) &&
+        if (L * Q == nd.m && L * nd.n * Q >= (int64_t(1) << 22) && nd.m * nd.r <= (int64_t(1) << 26) &&
             right_mfma_eligible(L, nd.n, Q, nd.r, TTNN_F64)) {
           nd.Xt64 = static_cast<double*>(P->alloc(sizeof(double) * nd.m * nd.r));
           if (fill) copy_layout(nd.X64, nd.Xt64, TTNN_F64, nd.m, nd.r, 1, nd.r, 1, 0, 0, nd.m, stream);
