@@ -279,6 +279,9 @@ def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
 
 
 # ---------------------------------------------------------------- 6-D Hilbert curves
+# pseudo-inverse thresholds: the library default (10 * 2^-52) for FP64 sketches, the FP32
+# noise level for FP32 sketches (a threshold set for FP64 keeps noise directions there)
+EPS_HILBERT = {"f64": 0.0, "f32": 10.0 * 2.0 ** -23, "bf16": 0.0}
 def hilbert_bench(args):
     """The first accuracy experiment of Sec. 8: the 6-D Hilbert tensor
     1 / (1 + i_1 + .. + i_6) (mode size 20, 64M entries, resident in HBM) on the index
@@ -287,7 +290,8 @@ def hilbert_bench(args):
     time of one approximation (reset + sketch update of the whole tensor + assembly of
     the cores), from events on the stream, averaged over 5 timed repeats with the first
     seed's plan after 2 untimed ones.  The FP32 rows sketch the FP32 rounding of the
-    tensor; their errors are against the FP64 tensor."""
+    tensor, with the pseudo-inverse threshold at the FP32 noise level; their errors are
+    against the FP64 tensor."""
     import torch
     import paper_2412_06111_amd as P
     from workloads import hilbert as H
@@ -297,7 +301,7 @@ def hilbert_bench(args):
     T64 = H.hilbert_device(n)
     ranks = [int(x) for x in args.hilbert_ranks.split(",") if x]
     out = {"workload": f"6-D Hilbert tensor, {n}^6 on the Fig. 1 tree (((1,2),3),4,(5,6)), p = {H.P_PAPER}",
-           "trials": args.hilbert_trials, "curves": {}}
+           "trials": args.hilbert_trials, "eps_factor": EPS_HILBERT, "curves": {}}
     stream = torch.cuda.current_stream()
     for dtype in args.hilbert_dtypes.split(","):
         X = T64 if dtype == "f64" else T64.to(torch.float32)
@@ -306,7 +310,8 @@ def hilbert_bench(args):
             for r in ranks:
                 errs, ms = [], None
                 for trial in range(args.hilbert_trials):
-                    plan = P.Plan(H.TOY, dims, r, H.P_PAPER, variant=variant, dtype=dtype, seed=100 + trial)
+                    plan = P.Plan(H.TOY, dims, r, H.P_PAPER, variant=variant, dtype=dtype, seed=100 + trial,
+                                  eps_factor=EPS_HILBERT[dtype])
                     cores = plan.alloc_cores()
                     if trial == 0:
                         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))

@@ -96,7 +96,10 @@ typedef enum { TTNN_SK_R = 0, TTNN_SK_OMEGA = 1, TTNN_SK_PSI = 2 } ttnn_sketch_k
  * (Def. 3 with equality).  Children of a node are ordered by first mode.
  * rank[i] = r_t >= 1 and oversample[i] = p_t >= 0 for non-root nodes (ignored at
  * the root).  eps_factor: the pseudo-inverse keeps singular values of R_t above
- * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52. */
+ * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52, which suits FP64 sketches.  With FP32
+ * sketches a threshold at the FP32 noise level (about 10 * 2^-23) drops the directions
+ * that noise creates and gives markedly smaller errors at ranks where the tensor's
+ * spectrum has fallen below it. */
 typedef struct {
   int32_t order;
   const int64_t* dims;
