@@ -538,7 +538,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the sketch path has no multi-GPU mode in this build", file=sys.stderr)
+              "the sketch path runs on a single GPU", file=sys.stderr)
         sys.exit(2)
 
     if args.hilbert_only:
