@@ -14,7 +14,7 @@ timed steps; after a few steps from idle the sweep still runs about 10% slower.
 
     python bench.py [--steps K] [--warmup W] [--variants ttnn,sttnn] [--dtypes f32,f64,bf16]
 
-Prints one JSON line.
+Prints one compact JSON line last on stdout; the full results go to --detail.
 """
 import argparse
 import json
@@ -57,62 +57,55 @@ def parse():
     ap.add_argument("--hilbert-trials", type=int, default=3, help="DRM seeds per rank (the paper averages 30)")
     ap.add_argument("--hilbert-ranks", default="2,3,4,5,6,7,8,9,10,11,12,13")
     ap.add_argument("--hilbert-dtypes", default="f64,f32")
+    ap.add_argument("--detail", default="bench_detail.json",
+                    help="file for the full per-configuration, serving and Hilbert results ('' = none)")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="Poisson rate as a fraction of the batched path's closed-loop rate")
     return ap.parse_args()
 
 
 # ---------------------------------------------------------------- work counts
-def work_counts(tree, variant):
-    """Leading-order flops and algorithmic bytes (entries) of one sketch pass.
+# Node list of ((1,2),(3,4)) in level order (root, A, B, {1}, {2}, {3}, {4}) and the
+# STTNN reuse sets of Sec. 5 / Fig. 5 on it: S_A = S_1 = {} , S_B = {A}, S_2 = {{1}},
+# S_3 = {A}, S_4 = {A, {3}}.
+T4_MODES = [(1, 2, 3, 4), (1, 2), (3, 4), (1,), (2,), (3,), (4,)]
+
+
+def work_counts(dims, r, p, variant):
+    """Leading-order flops and DRM entries of one sketch pass over the whole tensor on
+    ((1,2),(3,4)), every node with rank r and oversampling p (k = r + p).
 
     Flops: every contraction of the sketch phase, 2 * (entries of its input) * (columns
-    of its DRM).  DRM entries: every DRM the pass reads, once."""
-    N = 1
-    for n in tree.dims:
-        N *= n
-    sizes = {}
-
-    def size_after(prefix):
-        if not prefix:
-            return N
-        e = 1
-        for s in prefix:
-            e *= tree[s].k
-        for m in range(tree[prefix[-1]].last + 1, tree.d + 1):
-            e *= tree.dims[m - 1]
-        return e
-
-    flops = 0
-    done = set()
-    drm_entries = 0
-    used_y = set()
-
-    def chain_cost(prefix):
-        nonlocal flops
-        for j in range(1, len(prefix) + 1):
-            pf = tuple(prefix[:j])
-            if pf in done:
-                continue
-            done.add(pf)
-            flops += 2 * size_after(list(pf[:-1])) * tree[pf[-1]].k
-            used_y.add(pf[-1])
-
-    for n in tree.nodes[1:]:
-        S = tree.S(n.id) if variant == "sttnn" else []
-        chain_cost(S)
-        flops += 2 * size_after(S) * n.rank
-        drm_entries += tree.x_rows(n.id, variant) * n.rank
-    rc = tree[0].children
-    chain_cost(rc)
-    for s in used_y:
-        drm_entries += tree.n_of(s) * tree[s].k
-    return flops, drm_entries, N
+    of its DRM), including the root chain T x_A Y_A^T x_B Y_B^T.  DRM entries: every
+    X_t, and every Y_s that some contraction of the tensor (or of an intermediate) uses,
+    once.  Returns (flops, drm_entries, N)."""
+    n1, n2, n3, n4 = dims
+    N = n1 * n2 * n3 * n4
+    nA, nB = n1 * n2, n3 * n4
+    k = r + p
+    if variant == "ttnn":
+        flops = 2 * N * (6 * r + k) + 2 * k * nB * k           # six R_t, root chain
+        x_rows = nB + nA + N // n1 + N // n2 + N // n3 + N // n4
+        y_used = nA + nB                                       # Y_A, Y_B (root)
+    else:
+        flops = (2 * N * k                      # T x_A Y_A^T (S_B, S_3, S_4, root)
+                 + 2 * N * k                    # T x_1 Y_1^T (S_2)
+                 + 2 * (k * n3 * n4) * k        # (T x_A Y_A^T) x_3 Y_3^T (S_4)
+                 + 2 * (k * nB) * k             # root: x_B Y_B^T
+                 + 2 * N * r                    # R_A
+                 + 2 * (k * nB) * r             # R_B
+                 + 2 * N * r                    # R_1
+                 + 2 * (k * n2 * n3 * n4) * r   # R_2
+                 + 2 * (k * n3 * n4) * r        # R_3
+                 + 2 * (k * k * n4) * r)        # R_4
+        x_rows = nB + k + N // n1 + k * n3 * n4 + k * n4 + k * k
+        y_used = nA + nB + n1 + n3                             # Y_A, Y_B, Y_1, Y_3
+    return flops, x_rows * r + y_used * k, N
 
 
-def sweep_counts(tree, variant, dtype, kind):
+def sweep_counts(dims, r, p, variant, dtype, kind):
     """Algorithmic flops and bytes of the timed sweep kernel alone (`kind` as reported
-    by the library, ttnn_sweep_kind).
+    by the library, ttnn_sweep_kind), on ((1,2),(3,4)).
 
     1: the one-pass STTNN kernel reads the tensor once and the DRMs X_A, X_1, X_2, Y_A,
        Y_1 once, and writes R_A, Z_A = Y_A^T T^{A}, R_1, R_2 once (FP32; FP64 for an
@@ -121,25 +114,24 @@ def sweep_counts(tree, variant, dtype, kind):
        plan dtype) and reads no X_2; R_2 is a separate streaming contraction.
     3: the TTNN-mode kernel: tensor once, X_A, X_1, Y_A, X_B once; R_A, Z_A, R_1, R_B out.
     0: the sweep is the whole update and its counts are those of the pass."""
-    flops, drm, N = work_counts(tree, variant)
+    flops, drm, N = work_counts(dims, r, p, variant)
     s = ESIZE[dtype]
     if kind == 0:
         return flops, N * s + drm * s
-    A, B = tree[0].children
-    l1, l2 = tree[A].children
-    r, k = tree[A].rank, tree[A].k
-    nA, nB, n1 = tree.n_of(A), tree.n_of(B), tree.n_of(l1)
+    n1, n2, n3, n4 = dims
+    nA, nB = n1 * n2, n3 * n4
+    k = r + p
     acc = 8 if dtype == "f64" else 4
     if kind == 3:
-        drm_k = tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + nA * k + tree.x_rows(B, variant) * r
+        drm_k = nB * r + (N // n1) * r + nA * k + nA * r        # X_A, X_1, Y_A, X_B
         out = nA * r + k * nB + n1 * r + nB * r
         return 2 * N * (3 * r + k), N * s + drm_k * s + out * acc
-    drm_k = tree.x_rows(A, variant) * r + tree.x_rows(l1, variant) * r + nA * k + n1 * k
+    drm_k = nB * r + (N // n1) * r + nA * k + n1 * k              # X_A, X_1, Y_A, Y_1
     out = nA * r + k * nB + n1 * r
     kflops = 2 * N * (2 * r + 2 * k)
     if kind == 1:
-        drm_k += tree.x_rows(l2, variant) * r
-        out += tree.n_of(l2) * r
+        drm_k += k * n3 * n4 * r                                 # X_2
+        out += n2 * r
         kflops += 2 * (N // n1) * k * r
         return kflops, N * s + drm_k * s + out * acc
     return kflops, N * s + drm_k * s + out * acc + k * (N // n1) * s
@@ -186,15 +178,15 @@ def copy_rate(nbytes=1 << 30, reps=10):
 
 
 # ---------------------------------------------------------------- GPU run
-def read_sketches(plan, tree):
+def read_sketches(plan):
     """Every node sketch of the plan's last update (R, Omega, Psi; Psi only at the root),
     as FP64 host arrays keyed by (node modes, kind)."""
     import paper_2412_06111_amd as P
     out = {}
-    for nd in tree.nodes:
-        cid = plan.node(nd.modes)
-        for kind in ((P.SK_PSI,) if nd.id == 0 else (P.SK_R, P.SK_OMEGA, P.SK_PSI)):
-            out[(tuple(nd.modes), kind)] = plan.read_sketch(cid, kind).cpu().numpy()
+    for i, modes in enumerate(T4_MODES):
+        cid = plan.node(modes)
+        for kind in ((P.SK_PSI,) if i == 0 else (P.SK_R, P.SK_OMEGA, P.SK_PSI)):
+            out[(modes, kind)] = plan.read_sketch(cid, kind).cpu().numpy()
     return out
 
 
@@ -210,10 +202,10 @@ def sketch_rel_errors(sk, ref):
     return per
 
 
-def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
+def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, keep_sketches=False):
     import torch
     import paper_2412_06111_amd as P
-    from oracle.tree import T4
+    from workloads.serving import T4
 
     rank = args.rank if rank is None else rank
     over = args.over if over is None else over
@@ -270,8 +262,8 @@ def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, tree=None):
         e2, n2 = P.diff_norms(That, T_dev64)
         res["approx_rel_error"] = (e2 / n2) ** 0.5
         del That
-    if tree is not None:
-        res["_sketches"] = read_sketches(plan, tree)
+    if keep_sketches:
+        res["_sketches"] = read_sketches(plan)
     del X
     plan.close()
     torch.cuda.empty_cache()
@@ -336,7 +328,8 @@ def hilbert_bench(args):
                              "ms_per_approximation": ms,
                              "ingest_GBps": X.numel() * X.element_size() / (ms * 1e-3) / 1e9})
             out["curves"][f"{variant}:{dtype}"] = rows
-            print(f"# hilbert {variant}:{dtype}: {json.dumps(rows)}", file=sys.stderr, flush=True)
+            print(f"# hilbert {variant}:{dtype}: r={rows[-1]['rank']} error {rows[-1]['mean_rel_error']:.2e}",
+                  file=sys.stderr, flush=True)
         del X
     del T64
     torch.cuda.empty_cache()
@@ -344,6 +337,11 @@ def hilbert_bench(args):
 
 
 # ---------------------------------------------------------------- serving
+def _brief(name, st):
+    print(f"# serving {name}: {st['updates_per_s']:.0f} updates/s, p50 {st['p50_ms']:.3f} ms, "
+          f"p99 {st['p99_ms']:.3f} ms", file=sys.stderr, flush=True)
+
+
 def serving_bench(args):
     """Many streams of box updates (mode sizes U{32..nmax}, TTN ranks 8..32 + 1e-5
     noise, r in {16, 32}, p = r/2, TTNN on ((1,2),(3,4))).  Batched FP32 server vs the
@@ -432,18 +430,17 @@ def serving_bench(args):
     per32 = make_updates("f32")
     closed = one_run("f32", 64, 0.0, per32)
     out["batched_f32_closed_loop"] = closed
-    print(f"# serving batched f32 closed loop: {json.dumps(closed)}", file=sys.stderr, flush=True)
+    _brief("batched f32 closed loop", closed)
     rate = args.serve_load * closed["updates_per_s"]
     out["poisson_rate_per_s"] = rate
     out["batched_f32_poisson"] = one_run("f32", 64, rate, per32)
-    print(f"# serving batched f32 poisson: {json.dumps(out['batched_f32_poisson'])}", file=sys.stderr, flush=True)
+    _brief("batched f32 poisson", out['batched_f32_poisson'])
     del per32
     per64 = make_updates("f64")
     out["fp64_one_per_launch_closed_loop"] = one_run("f64", 1, 0.0, per64)
-    print(f"# serving fp64 closed loop: {json.dumps(out['fp64_one_per_launch_closed_loop'])}", file=sys.stderr,
-          flush=True)
+    _brief("fp64 closed loop", out['fp64_one_per_launch_closed_loop'])
     out["fp64_one_per_launch_poisson"] = one_run("f64", 1, rate, per64)
-    print(f"# serving fp64 poisson: {json.dumps(out['fp64_one_per_launch_poisson'])}", file=sys.stderr, flush=True)
+    _brief("fp64 poisson", out['fp64_one_per_launch_poisson'])
     del per64, tens
     torch.cuda.empty_cache()
     return out
@@ -515,22 +512,147 @@ def serving_single(args):
     return out
 
 
-def cpu_baseline(T, tree, variant, seed=1, box=112):
-    """The FP64 oracle on a bounded sample of the same workload: the corner box of
-    size box^4 as a streaming update (DRM rows generated before timing)."""
+def host_info():
+    """CPU model, usable cores and the BLAS libraries NumPy runs on (with their threads)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        for p in threadpool_info():
+            if p.get("user_api") == "blas":
+                blas.append(f"{p.get('internal_api')} {p.get('version')} x{p.get('num_threads')}")
+    except Exception:                      # threadpoolctl missing or failing: report nothing
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas": ", ".join(blas) or "unknown"}
+
+
+def cpu_baseline(T, variant, rank, over, seed=1, box=80):
+    """The FP64 oracle, as it stands, on a bounded sample of the same workload: the
+    corner box of size box^4 of the 128^4 tensor as one streaming update.  Phases timed
+    separately: generation of the DRM rows the box touches (and of every Y_t), the
+    sketch of the box, the epilogue plus recovery phase on those sketches, and the
+    dense reconstruction of the full-size tensor from the cores.  `value` is the box's
+    FP64 bytes over the sketch time."""
     import numpy as np
-    from oracle.sketch import box_drms, sketch_box
+    import oracle as O
+    from oracle.sketch import box_drms, psi_internal, sketch_box
+    tree = O.Tree(O.T4, T.shape, rank, over)
     blk = np.ascontiguousarray(T[:box, :box, :box, :box])
     off = (0, 0, 0, 0)
-    drms = box_drms(tree, seed, variant, off, blk.shape)
+    ph = {}
     tic = time.perf_counter()
-    sketch_box(blk, off, tree, seed, variant, drms=drms)
-    dt = time.perf_counter() - tic
-    return {"value": blk.size * 8 / dt / 1e9, "unit": "GB/s", "cores": len(os.sched_getaffinity(0)),
+    drms = box_drms(tree, seed, variant, off, blk.shape)
+    Y = {n.id: O.drm_matrix(seed, n.id, 1, tree.n_of(n.id), n.k) for n in tree.nodes[1:]}
+    ph["drm_s"] = time.perf_counter() - tic
+    tic = time.perf_counter()
+    sk = sketch_box(blk, off, tree, seed, variant, drms=drms)
+    ph["sketch_s"] = time.perf_counter() - tic
+
+    class _Maps:                           # the Y maps the epilogue needs
+        pass
+    _Maps.Y = Y
+    tic = time.perf_counter()
+    R = sk["R"]
+    full = {"R": R, "Omega": {i: Y[i].T @ R[i] for i in R},
+            "Psi": {n.id: R[n.id] if n.is_leaf else psi_internal(tree, _Maps, n.id, R[n.id])
+                    for n in tree.nodes[1:]}}
+    full["Psi"][0] = sk["Psi_root"]
+    cores, _ = O.assemble(full, tree)
+    ph["assemble_s"] = time.perf_counter() - tic
+    tic = time.perf_counter()
+    O.reconstruct(cores, tree)
+    ph["reconstruct_s"] = time.perf_counter() - tic
+    info = host_info()
+    return {"value": blk.size * 8 / ph["sketch_s"] / 1e9, "unit": "GB/s", "cores": info["cores"],
             "kind": "oracle",
-            "sample": f"{variant} sketch of the {box}^4 corner box of the 128^4 workload as one streaming "
-                      f"update, FP64 NumPy; DRM rows generated before timing; {dt:.2f} s",
-            "seconds": dt}
+            "sample": f"{variant} r={rank} p={over}: the {box}^4 corner box of the 128^4 tensor as one streaming "
+                      f"update (FP64 NumPy); value = box bytes / sketch time; reconstruct is full 128^4",
+            "phases_s": {k[:-2]: round(v, 3) for k, v in ph.items()},
+            "cpu_model": info["cpu_model"], "blas": info["blas"]}
+
+
+# per-configuration summary in the final record: one list per configuration, in this order
+SUMMARY_FIELDS = ("ms_per_step", "sweep_kernel_ms_avg", "sweep_roofline_frac", "approx_rel_error",
+                  "sketch_rel_error_vs_fp64_path_max")
+
+
+def roofline_of(flops, nbytes, ms, dtype):
+    """Bound (the larger of the HBM and MFMA times at peak), achieved rate and fraction."""
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    t_mfma = flops / (MFMA_PEAK_TFLOPS[dtype] * 1e12)
+    if t_mfma > t_hbm:
+        ach = flops / (ms * 1e-3) / 1e12
+        return {"bound": "mfma", "achieved": ach, "peak": MFMA_PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+                "frac": ach / MFMA_PEAK_TFLOPS[dtype]}
+    ach = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+
+
+def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=None, traffic=None):
+    """The one JSON record the benchmark prints last (kept well under 4 KB): headline
+    value, the sweep kernel's roofline and a step-level one, the CPU baseline and a
+    short summary of every other measured configuration."""
+    hv, hd = key.split(":")[:2]
+    head = results[key]
+    kind_name = {0: "whole update", 1: "sttnn_t4_kernel (one-pass STTNN sweep)",
+                 2: "sttnn_t4_kernel (one-pass STTNN sweep writing Z1; R_2 by a streaming kernel)",
+                 3: "sttnn_t4_kernel in TTNN mode (R_A, Z_A, R_1, R_B)"}[head["sweep_kind"]]
+    roof = roofline_of(head["sweep_flops"], head["sweep_algorithmic_bytes"], head["sweep_kernel_ms_avg"], hd)
+    roof["traffic"] = traffic
+    roof["kernel"] = f"{kind_name}; HIP events on the launch stream"
+    roof["algorithmic_bytes_per_launch"] = head["sweep_algorithmic_bytes"]
+    roof["flops_per_launch"] = head["sweep_flops"]
+    step = roofline_of(head["flops"], head["algorithmic_bytes"], head["ms_per_step"], hd)
+    step["what"] = "whole step (sketch update + FP64 epilogue + assembly) vs all sketch-phase flops and compulsory bytes"
+    roof["step"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in step.items()}
+    for k in ("achieved", "frac"):
+        roof[k] = round(roof[k], 4)
+    summary = {"fields": list(SUMMARY_FIELDS)}
+    for k, r in results.items():
+        summary[k] = [float(f"{r[s]:.3g}") if r.get(s) is not None else None for s in SUMMARY_FIELDS]
+    line = {
+        "metric": METRIC,
+        "value": round(head["ingest_GBps"], 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": hd,
+        "data": "synthetic",
+        "config": {"workload": f"{hv.upper()} one-pass sketch + FP64 assembly, {args.n}^4 on ((1,2),(3,4)), "
+                               f"TTN ranks 24, 0.8^k spectra, 1e-4 noise, r={args.rank}, p={args.over}",
+                   "variant": hv, "n": args.n, "rank": args.rank, "oversample": args.over},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "results": summary,
+    }
+    if copy is not None:
+        line["copy_GBps_read_plus_write"] = round(copy["GBps_read_plus_write"], 1)
+    if serving is not None:
+        sv = {}
+        for name in ("batched_f32_closed_loop", "batched_f32_poisson", "fp64_one_per_launch_closed_loop",
+                     "fp64_one_per_launch_poisson", "single_stream_f32"):
+            s = serving.get(name)
+            if s:
+                sv[name] = {f: float(f"{s[f]:.4g}") for f in ("updates_per_s", "ingest_GBps", "p50_ms", "p99_ms",
+                                                               "update_p50_ms", "update_p99_ms") if f in s}
+        line["serving"] = sv
+    if hilbert is not None:
+        line["hilbert_6d"] = {c: f"r{rows[-1]['rank']} err {rows[-1]['mean_rel_error']:.2g}"
+                              for c, rows in hilbert["curves"].items()}
+    return line
 
 
 def main():
@@ -547,41 +669,41 @@ def main():
 
     import numpy as np
     import torch
-    import oracle as O
     from workloads import synth as W
 
     t_gen = time.perf_counter()
     T = W.config2_tensor(n=args.n)
     T_dev64 = torch.from_numpy(np.ascontiguousarray(W.flat_colmajor(T))).cuda()
     t_gen = time.perf_counter() - t_gen
-    tree_def = O.Tree(O.T4, T.shape, args.rank, args.over)
-
+    dims = T.shape
     results = {}
 
     def measure(variant, dtype, rank, over, key, ref=None):
         """One configuration; keeps its sketches when it is the FP64 reference (ref is
         None and dtype f64), else reports their errors against `ref`."""
-        tree = O.Tree(O.T4, T.shape, rank, over)
-        r = run_gpu(args, T_dev64, variant, dtype, rank, over, tree=tree)
+        r = run_gpu(args, T_dev64, variant, dtype, rank, over, keep_sketches=True)
         sk = r.pop("_sketches")
         if ref is not None:
             per = sketch_rel_errors(sk, ref)
             r["sketch_rel_error_vs_fp64_path"] = per
             r["sketch_rel_error_vs_fp64_path_max"] = max(per.values())
-        flops, drm_entries, N = work_counts(tree, variant)
+        flops, drm_entries, N = work_counts(dims, rank, over, variant)
         r["rank"], r["oversample"] = rank, over
         r["flops"] = flops
         r["algorithmic_bytes"] = N * ESIZE[dtype] + drm_entries * ESIZE[dtype]
         r["ingest_GBps"] = N * ESIZE[dtype] / (r["ms_per_step"] * 1e-3) / 1e9
         r["sketch_GBps_algorithmic"] = r["algorithmic_bytes"] / (r["sketch_ms_avg"] * 1e-3) / 1e9
         r["sketch_TFLOPs"] = flops / (r["sketch_ms_avg"] * 1e-3) / 1e12
-        kf, kb = sweep_counts(tree, variant, dtype, r["sweep_kind"])
+        kf, kb = sweep_counts(dims, rank, over, variant, dtype, r["sweep_kind"])
         r["sweep_flops"] = kf
         r["sweep_algorithmic_bytes"] = kb
         r["sweep_GBps"] = kb / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e9
         r["sweep_TFLOPs"] = kf / (r["sweep_kernel_ms_avg"] * 1e-3) / 1e12
+        rf = roofline_of(kf, kb, r["sweep_kernel_ms_avg"], dtype)
+        r["sweep_roofline_frac"] = rf["frac"]
         results[key] = r
-        print(f"# {key}: {json.dumps(r)}", file=sys.stderr, flush=True)
+        print(f"# {key}: {r['ms_per_step']:.3f} ms/step, sweep {r['sweep_kernel_ms_avg']:.3f} ms "
+              f"({rf['bound']} frac {rf['frac']:.3f})", file=sys.stderr, flush=True)
         return sk
 
     # FP64 first in each variant: its sketches are the reference the other dtypes'
@@ -601,31 +723,8 @@ def main():
         measure("sttnn", "bf16", rr, rr // 2, f"sttnn:bf16:r{rr}", ref)
 
     key = args.headline if args.headline in results else next(iter(results))
-    hv, hd = key.split(":")
-    head = results[key]
-    for k, r in results.items():
-        d = k.split(":")[1]
-        t_hbm = r["sweep_algorithmic_bytes"] / (HBM_PEAK_GBS * 1e9)
-        t_mfma = r["sweep_flops"] / (MFMA_PEAK_TFLOPS[d] * 1e12)
-        if t_mfma > t_hbm:
-            r["roofline"] = {"bound": "mfma", "achieved": r["sweep_TFLOPs"], "peak": MFMA_PEAK_TFLOPS[d],
-                             "unit": "TFLOP/s"}
-        else:
-            r["roofline"] = {"bound": "hbm", "achieved": r["sweep_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-        r["roofline"]["frac"] = r["roofline"]["achieved"] / r["roofline"]["peak"]
-    roof = dict(head["roofline"])
-    roof["traffic"] = measured_traffic(key)
-    kind_name = {0: "whole update", 1: "sttnn_t4_kernel (one-pass STTNN sweep)",
-                 2: "sttnn_t4_kernel (one-pass STTNN sweep writing Z1; R_2 by a separate streaming kernel)",
-                 3: "sttnn_t4_kernel in TTNN mode (R_A, Z_A, R_1, R_B)"}[head["sweep_kind"]]
-    roof["kernel"] = kind_name + f", {hd}, {args.n}^4, r={args.rank}, p={args.over}; HIP events on the launch stream"
-    roof["algorithmic_bytes_per_launch"] = head["sweep_algorithmic_bytes"]
-    roof["flops_per_launch"] = head["sweep_flops"]
     copy = copy_rate()
 
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(T, tree_def, hv)
     hilbert = None
     if not args.no_hilbert:
         hilbert = hilbert_bench(args)
@@ -635,34 +734,25 @@ def main():
         torch.cuda.empty_cache()
         serving = serving_bench(args)
         serving["single_stream_f32"] = serving_single(args)
-        print(f"# serving single stream: {json.dumps(serving['single_stream_f32'])}", file=sys.stderr, flush=True)
+        print(f"# serving single stream: {serving['single_stream_f32']['updates_per_s']:.0f} updates/s",
+              file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu:
+        hv = key.split(":")[0]
+        cpu = cpu_baseline(T, hv, args.rank, args.over)
+        print(f"# cpu baseline: {json.dumps(cpu['phases_s'])}", file=sys.stderr, flush=True)
 
-    line = {
-        "metric": METRIC,
-        "value": head["ingest_GBps"],
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": hd,
-        "data": "synthetic",
-        "config": {"workload": f"{hv.upper()} one-pass sketch + FP64 assembly, {args.n}^4 tensor on ((1,2),(3,4)), "
-                               f"TTN ranks 24 with 0.8^k spectra + 1e-4 noise, r={args.rank}, p={args.over}",
-                   "variant": hv, "n": args.n, "rank": args.rank, "oversample": args.over,
-                   "tensor_bytes": head["algorithmic_bytes"] and (args.n ** 4) * ESIZE[hd]},
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "results": results,
-        "copy_calibration": copy,
-        "serving": serving,
-        "hilbert_6d": hilbert,
-        "input_generation_s": t_gen,
-    }
-    print(json.dumps(line))
+    line = compact_line(args, key, results, cpu=cpu, serving=serving, hilbert=hilbert, copy=copy,
+                        traffic=measured_traffic(key))
+    detail = {"line": line, "results": results, "copy_calibration": copy, "serving": serving,
+              "hilbert_6d": hilbert, "input_generation_s": t_gen}
+    if args.detail:
+        d = os.path.dirname(os.path.abspath(args.detail))
+        os.makedirs(d, exist_ok=True)
+        with open(args.detail, "w") as f:
+            json.dump(detail, f, indent=1, default=float)
+    sys.stdout.flush()
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":
