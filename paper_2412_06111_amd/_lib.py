@@ -100,6 +100,40 @@ def check(status):
         raise TTNNError(status, (lib.ttnn_last_error() or b"").decode())
 
 
+def check_block(block, dtype, extent, d, strides=None):
+    """Argument checks of a box update's block (raised, not asserted, so they hold under
+    python -O).  `dtype` is the plan's torch dtype, `extent` the box, `d` the tensor
+    order.  Without strides the block must be contiguous with exactly prod(extent)
+    entries; with strides (elements, one per mode) it must hold every addressed entry."""
+    if not isinstance(block, torch.Tensor):
+        raise TypeError(f"block must be a torch.Tensor, got {type(block).__name__}")
+    if block.dtype != dtype:
+        raise TypeError(f"block dtype {block.dtype} differs from the plan dtype {dtype}")
+    if len(extent) != d:
+        raise ValueError(f"extent has {len(extent)} modes, the tensor has {d}")
+    n = 1
+    for e in extent:
+        if int(e) < 0:
+            raise ValueError(f"negative extent {tuple(extent)}")
+        n *= int(e)
+    if strides is None:
+        if not block.is_contiguous():
+            raise ValueError("block must be contiguous (column-major box, extent[0] fastest); pass strides "
+                             "for a strided view")
+        if block.numel() != n:
+            raise ValueError(f"block has {block.numel()} entries, the box {tuple(extent)} has {n}")
+    else:
+        if len(strides) != d:
+            raise ValueError(f"strides has {len(strides)} modes, the tensor has {d}")
+        if n > 0:
+            last = sum((int(e) - 1) * int(s) for e, s in zip(extent, strides))
+            room = block.untyped_storage().nbytes() // block.element_size() - block.storage_offset()
+            if any(int(s) < 0 for s in strides) or last >= room:
+                raise ValueError(f"strides {tuple(strides)} address entries outside the block's storage")
+    if not block.is_cuda:
+        raise TypeError("block must be a CUDA (HIP) tensor")
+
+
 def stream_ptr(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
@@ -214,21 +248,19 @@ class Plan:
         order (numel == prod(extent))."""
         extent = self.dims if extent is None else tuple(int(e) for e in extent)
         offset = (0,) * self.d if offset is None else tuple(int(o) for o in offset)
-        assert block.is_cuda and block.dtype == self.torch_dtype and block.is_contiguous()
-        n = 1
-        for e in extent:
-            n *= e
-        assert block.numel() == n, (block.numel(), extent)
+        check_block(block, self.torch_dtype, extent, self.d)
+        if len(offset) != self.d:
+            raise ValueError(f"offset has {len(offset)} modes, the tensor has {self.d}")
         check(lib.ttnn_sketch_update(self.handle, C.c_void_p(block.data_ptr()), (C.c_int64 * self.d)(*offset),
                                      (C.c_int64 * self.d)(*extent), float(alpha), stream_ptr(stream)))
 
     def update_rank1(self, factors, alpha=1.0, stream=None):
         """factors: d CUDA float64 vectors, factor mu of length n_mu (the library reads
         exactly that many doubles from each)."""
-        assert len(factors) == self.d, (len(factors), self.d)
+        if len(factors) != self.d:
+            raise ValueError(f"{len(factors)} factors for a tensor of order {self.d}")
         for f, n in zip(factors, self.dims):
-            assert f.is_cuda and f.dtype == torch.float64 and f.is_contiguous() and f.numel() == n, \
-                (f.device, f.dtype, f.numel(), n)
+            check_block(f, torch.float64, (n,), 1)
         ptrs = (C.c_void_p * self.d)(*[C.c_void_p(f.data_ptr()) for f in factors])
         check(lib.ttnn_sketch_update_rank1(self.handle, ptrs, float(alpha), stream_ptr(stream)))
 
@@ -328,7 +360,9 @@ class Plan:
     def assemble_status_async(self, h_status, stream=None):
         """Enqueue the status query into `h_status`, a pinned int32 CPU tensor of one
         element (0 = sound); read it after the stream has passed this call."""
-        assert h_status.dtype == torch.int32 and h_status.is_pinned() and h_status.numel() >= 1
+        if not (isinstance(h_status, torch.Tensor) and h_status.dtype == torch.int32 and h_status.numel() >= 1
+                and h_status.is_pinned()):
+            raise TypeError("h_status must be a pinned int32 CPU tensor with at least one element")
         check(lib.ttnn_assemble_status_async(self.handle, C.c_void_p(h_status.data_ptr()), stream_ptr(stream)))
 
     def reconstruct(self, cores, out=None, out_dtype=F64, stream=None):
@@ -345,8 +379,11 @@ class Plan:
 def diff_norms(a, b, stream=None):
     """(||a - b||^2, ||b||^2) computed on the GPU; a any plan dtype, b float64."""
     out = (C.c_double * 2)()
+    if a.dtype not in (torch.float64, torch.float32, torch.bfloat16):
+        raise TypeError(f"a has dtype {a.dtype}; expected float64, float32 or bfloat16")
     dt = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[a.dtype]
-    assert a.numel() == b.numel() and b.dtype == torch.float64
+    check_block(b, torch.float64, (a.numel(),), 1)
+    check_block(a, a.dtype, (b.numel(),), 1)
     check(lib.ttnn_diff_norms(C.c_void_p(a.data_ptr()), dt, C.c_void_p(b.data_ptr()), a.numel(), out,
                               stream_ptr(stream)))
     return out[0], out[1]
@@ -357,6 +394,9 @@ def update_batched(items, stream=None):
     arr = (UpdateDesc * max(1, len(items)))()
     keep = []
     for i, (plan, block, extent, offset, alpha) in enumerate(items):
+        check_block(block, plan.torch_dtype, extent, plan.d)
+        if len(offset) != plan.d:
+            raise ValueError(f"item {i}: offset has {len(offset)} modes, the tensor has {plan.d}")
         arr[i].plan = plan.handle
         arr[i].d_block = C.c_void_p(block.data_ptr())
         for mu in range(plan.d):

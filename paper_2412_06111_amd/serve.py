@@ -183,7 +183,8 @@ class Server:
 
     # ---------------------------------------------------------------- streams
     def open_stream(self, sid, spec):
-        assert sid not in self.streams
+        if sid in self.streams:
+            raise ValueError(f"stream {sid} is already open")
         fp = self.engine.footprint(spec)
         if fp > self.budget:
             raise ValueError(f"stream {sid} needs {fp} bytes, more than the whole budget {self.budget}")
@@ -192,7 +193,8 @@ class Server:
 
     def submit(self, u):
         st = self.streams[u.sid]
-        assert not st.closing, "stream already closed"
+        if st.closing:
+            raise ValueError(f"stream {u.sid} is already closed")
         st.queue.append(u)
         st.n_total += 1
 
