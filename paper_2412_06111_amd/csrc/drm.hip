@@ -132,15 +132,21 @@ __global__ void drm_kernel(int64_t rows, int cols, uint64_t seed, uint32_t tag, 
     const uint64_t row = static_cast<uint64_t>(idx / cols);
     const uint32_t col = static_cast<uint32_t>(idx - static_cast<int64_t>(row) * cols);
     const double z = gaussian(seed, tag, row, col);
-    o64[idx] = z;
+    // a plan of lower precision uses one matrix everywhere: the rounded copy, whose
+    // values the FP64 array then holds exactly
+    double m = z;
     if (o32 || o16) {
       const float f = static_cast<float>(z);
+      m = static_cast<double>(f);
       if (o32) o32[idx] = f;
       if (o16) {
         const uint32_t b = __float_as_uint(f);
-        o16[idx] = static_cast<uint16_t>((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+        const uint16_t h = static_cast<uint16_t>((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+        o16[idx] = h;
+        m = static_cast<double>(bf16_bits_to_f32(h));
       }
     }
+    o64[idx] = m;
   }
 }
 

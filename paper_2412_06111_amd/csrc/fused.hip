@@ -24,6 +24,8 @@
 // fixed order into the FP64 accumulators by sttnn_t4_reduce.
 #include "fused.hpp"
 
+#include <type_traits>
+
 #include "engine.hpp"
 #include "kernels.hpp"
 #include "mfma.hpp"
@@ -73,7 +75,7 @@ struct Wide {
 // instead.  Staged rows are not padded: the 16-byte chunks of row r are stored in
 // XOR-swizzled order (chunk c at position c ^ (r mod 16, or mod the chunk count)),
 // so reads along a row and gathers down a column spread over the LDS banks.
-template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR = false>
+template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR = false, bool ZO = false>
 struct SttnnLayout {
   using P = Pol<DT>;
   using T = typename P::T;
@@ -87,7 +89,15 @@ struct SttnnLayout {
   // rows read together by the 4 x 4 block products of (d2) fall on distinct banks
   static constexpr int ZPAD = DT == TTNN_F32 ? 16 : 0;
   static constexpr int ZS = KP * SC + ZPAD;
-  static constexpr size_t Z1 = TT ? 0 : size_t(B2) * ZS * ESZ;
+  // STTNN keeps Z1 = Y_1^T slab at FP32 accuracy whatever the plan dtype (the chained
+  // intermediate of the sequential variant): a BF16 plan stashes FP32 values where Z1
+  // is written out (ZF), and a high and a low BF16 half (hi = RNE(z), lo = RNE(z - hi),
+  // |z - hi - lo| <= 2^-18 |z|) where it contracts Z1 with X_2 in the tile (ZH), so
+  // that the BF16 MFMA takes both halves.
+  static constexpr bool ZF = DT == TTNN_BF16 && ZO && !TT;
+  static constexpr bool ZH = DT == TTNN_BF16 && !ZO && !TT;
+  static constexpr int ZESZ = ZF ? 4 : ESZ;
+  static constexpr size_t Z1 = TT ? 0 : size_t(ZH ? 2 : 1) * B2 * ZS * ZESZ;
   static constexpr size_t YAB = size_t(KP) * SY * ESZ;
   static constexpr size_t YB = YAB + (TT ? size_t(R) * SXB * ESZ : 0);
   static constexpr size_t XB = size_t(R) * SX * ESZ;
@@ -147,10 +157,10 @@ __device__ inline void lds_dma_rows(const T* g, int64_t gs, T* l, int rows, int 
 }
 
 // Issue the copies of the sub-tile (slab i2, columns col0 .. col0+SC-1) into one stage.
-template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR>
+template <int DT, int R, int KP, int B2, int SC, bool TT, bool YR, bool ZO>
 __device__ inline void sttnn_issue(const SttnnArgs& a, char* sb, int64_t i2, int64_t col0, int wave, int lane) {
   using P = Pol<DT>;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR, ZO>;
   using T = typename P::T;
   const int64_t nA = a.nA, nB = a.nB, n2 = a.n2;
   lds_dma_rows<T, N1>(static_cast<const T*>(a.T) + i2 * N1 + nA * col0, nA, reinterpret_cast<T*>(sb), SC, wave,
@@ -230,7 +240,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // FP32 Z1-out and TTNN forms at r = 32 (two slabs per tile): the tile's Y_A rows (and
   // X_B rows) stay resident
   static constexpr bool YR = (ZO || TT) && DT != TTNN_F64 && R == 32;
-  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR>;
+  using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR, ZO>;
   using T = typename P::T;
   using Acc = typename P::Acc;
   using CFrag = typename P::CFrag;
@@ -262,7 +272,9 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   constexpr bool PIPE = DT != TTNN_F64 && (R <= 16 || (R == 32 && (ZO || (TT && DT == TTNN_F32))));
 
   __shared__ __align__(16) char smem[Lay::TOTAL];
-  T* Z1s = reinterpret_cast<T*>(smem + Lay::OFF_Z1);
+  using ZT = typename std::conditional<Lay::ZF, float, T>::type;   // Z1 stash element
+  ZT* Z1s = reinterpret_cast<ZT*>(smem + Lay::OFF_Z1);
+  T* Z1lo = reinterpret_cast<T*>(smem + Lay::OFF_Z1) + B2 * Lay::ZS;   // ZH: the low halves
   T* Y1s = reinterpret_cast<T*>(smem + Lay::OFF_Y1);
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
@@ -302,8 +314,8 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   // issue the copies of sub-tile s into stage buf
   auto issue = [&](int s, int buf) {
     const int cb = s / B2, i2l = s % B2;
-    sttnn_issue<DT, R, KP, B2, SC, TT, YR>(a, stage_base(buf), i2_0 + i2l, c_tile + static_cast<int64_t>(cb) * SC,
-                                           wave, lane);
+    sttnn_issue<DT, R, KP, B2, SC, TT, YR, ZO>(a, stage_base(buf), i2_0 + i2l,
+                                               c_tile + static_cast<int64_t>(cb) * SC, wave, lane);
   };
   // Y_1 rows, resident for the whole kernel; YR: the Y_A rows of the tile's slabs
   if constexpr (Lay::STAGE_Y1) lds_dma_rows<T, N1>(Y1, N1, Y1s, KP, wave, lane);
@@ -449,7 +461,16 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int j1 = 16 * rb + P::crow(lane, v);
-            Z1s[i2l * Lay::ZS + iBl * KP + j1] = P::from_acc(acc[rb][v]);
+            const int at = i2l * Lay::ZS + iBl * KP + j1;
+            if constexpr (Lay::ZF) {
+              Z1s[at] = acc[rb][v];
+            } else if constexpr (Lay::ZH) {
+              const T hi = P::from_acc(acc[rb][v]);
+              Z1s[at] = hi;
+              Z1lo[at] = P::from_acc(acc[rb][v] - bf16_bits_to_f32(hi));
+            } else {
+              Z1s[at] = P::from_acc(acc[rb][v]);
+            }
           }
       };
       if constexpr (PIPE) {
@@ -530,13 +551,7 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
             for (int rb = 0; rb < KB; ++rb) acc[rb] = P::mfma(W::frag(ay[rb], sb), W::frag(bw, sb), acc[rb]);
         }
-#pragma unroll
-        for (int rb = 0; rb < KB; ++rb)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int j1 = 16 * rb + P::crow(lane, v);
-            Z1s[i2l * Lay::ZS + iBl * KP + j1] = P::from_acc(acc[rb][v]);
-          }
+        stash_z1(acc);
       }
     }  // i2l
     // Z_A partials of this tile's row range for the sub-block's columns (before (d2),
@@ -555,10 +570,10 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
     if constexpr (ZO) {
       // the tile's Z1 rows for this column block: B2 runs of SC * KP contiguous values
       __syncthreads();
-      typedef T zvec __attribute__((ext_vector_type(16 / sizeof(T))));
-      constexpr int ZV = 16 / sizeof(T);
+      typedef ZT zvec __attribute__((ext_vector_type(16 / sizeof(ZT))));
+      constexpr int ZV = 16 / sizeof(ZT);
       constexpr int NZ = SC * KP / ZV;
-      T* Z1g = static_cast<T*>(a.Z1);
+      ZT* Z1g = static_cast<ZT*>(a.Z1);
       for (int e = tid; e < B2 * NZ; e += kThreadsF) {
         const int i2l = e / NZ, q = e % NZ;
         const zvec v = *reinterpret_cast<const zvec*>(&Z1s[i2l * Lay::ZS + q * ZV]);
@@ -594,9 +609,13 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
       for (int kw = 0; kw < KW / KG; ++kw) {
         const int K = wave * KW + kw * KG + V * lg;
-        vec azw;
-        if (l16 < B2) azw = W::load(&Z1s[l16 * Lay::ZS + K]);
+        vec azw, azl;
+        if (l16 < B2) azw = W::load(reinterpret_cast<const T*>(&Z1s[l16 * Lay::ZS + K]));
         else azw = vec{};
+        if constexpr (Lay::ZH) {
+          if (l16 < B2) azl = W::load(&Z1lo[l16 * Lay::ZS + K]);
+          else azl = vec{};
+        }
         vec bx[CBR];
 #pragma unroll
         for (int c = 0; c < CBR; ++c) {
@@ -606,7 +625,10 @@ __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
 #pragma unroll
         for (int sb = 0; sb < SUB; ++sb)
 #pragma unroll
-          for (int c = 0; c < CBR; ++c) r2[c] = P::mfma(W::frag(azw, sb), W::frag(bx[c], sb), r2[c]);
+          for (int c = 0; c < CBR; ++c) {
+            r2[c] = P::mfma(W::frag(azw, sb), W::frag(bx[c], sb), r2[c]);
+            if constexpr (Lay::ZH) r2[c] = P::mfma(W::frag(azl, sb), W::frag(bx[c], sb), r2[c]);
+          }
       }
     }
 
@@ -917,7 +939,9 @@ void fused_prepare(Plan& P, hipStream_t st) {
   const int64_t n2 = P.dims[1], nAs = N1 * n2, nB = P.N / nAs;
   // Z1-out form (STTNN, r >= 32): Z1 is written out and R_2 formed by one streaming
   // contraction that reads X_2 once, instead of re-reading X_2 in every row tile
-  const bool zout = !tt && R >= 32 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, P.dtype);
+  // (a BF16 plan writes Z1 in FP32 and contracts it with an FP32 copy of X_2)
+  const int zdt = P.dtype == TTNN_BF16 ? TTNN_F32 : P.dtype;
+  const bool zout = !tt && R >= 32 && right_mfma_eligible(static_cast<int64_t>(KP) * nB, n2, 1, R, zdt);
   const Shape sh = shape_for(P.dtype, R, tt, zout);
   if (n2 % sh.B2 != 0 || nB % sh.SC != 0) return;
   const int TA = static_cast<int>(n2 / sh.B2);
@@ -949,15 +973,17 @@ void fused_prepare(Plan& P, hipStream_t st) {
 
   const int dt = P.dtype;
   const int64_t es = elem_size(dt);
-  // DRM copies in the fragment layouts of the kernel (values rounded like the compute copies)
+  // DRM copies in the fragment layouts of the kernel (the FP64 arrays of a lower-precision
+  // plan hold the rounded values already, so these copies are exact)
   F.XA = P.alloc(es * nB * R);
   F.X1 = P.alloc(es * nAs / N1 * nB * R);
   F.YA = P.alloc(es * nAs * KP);
+  const int x2dt = zout ? zdt : dt;
   if (tt) {
     F.XB = P.alloc(es * nAs * R);
   } else {
     F.Y1 = P.alloc(es * N1 * KP);
-    F.X2 = P.alloc(es * nB * KP * R);
+    F.X2 = P.alloc(elem_size(x2dt) * nB * KP * R);
   }
   const Node& NA = P.nodes[A];
   const double* XB64 = P.nodes[F.node_B].X64;
@@ -971,7 +997,7 @@ void fused_prepare(Plan& P, hipStream_t st) {
       copy_layout(XB64, F.XB, dt, nAs, R, 1, R, 1, 0, 1, R, st);                     // [j][iA]
     } else {
       copy_layout(L1.Y64, F.Y1, dt, N1, KP, 1, k, 1, 0, 1, k, st);                   // [j1][i1]
-      copy_layout(L2.X64, F.X2, dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
+      copy_layout(L2.X64, F.X2, x2dt, KP, nB, R, R, static_cast<int64_t>(k) * R, 1, 0, k, st);  // [j][iB][j1]
     }
   }
   const int64_t as = dt == TTNN_F64 ? 8 : 4;
@@ -980,7 +1006,7 @@ void fused_prepare(Plan& P, hipStream_t st) {
   F.PR1 = P.alloc(as * static_cast<int64_t>(TA) * TB * N1 * R);
   F.zout = zout;
   if (tt) F.PRB = P.alloc(as * TA * R * nB);
-  else if (F.zout) F.Z1 = P.alloc(es * KP * n2 * nB);
+  else if (F.zout) F.Z1 = P.alloc(elem_size(zdt) * KP * n2 * nB);
   else F.PR2 = P.alloc(as * TB * n2 * R);
   F.enabled = true;
 }
@@ -1029,8 +1055,8 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
     // size, it does.
     fork_side(P, st);
     const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
-    const int nch =
-        launch_right_mfma(F.Z1, P.dtype, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, P.side);
+    const int zdt = P.dtype == TTNN_BF16 ? TTNN_F32 : P.dtype;      // Z1 and this X_2 copy
+    const int nch = launch_right_mfma(F.Z1, zdt, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, P.side);
     const Node& n2d = P.nodes[F.node_2];
     launch_reduce(P.partial, nch, F.n2, F.R, 0, alpha, box_rows(P, n2d.first, n2d.last, off, ext), n2d.n, n2d.R, 1, 1,
                   P.side);
