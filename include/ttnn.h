@@ -39,11 +39,15 @@
  *    after everything enqueued before the call on `stream` and is joined back into
  *    `stream` before the call returns, so ordering on `stream` is as if all of it
  *    ran there.
- *  - Ownership: the caller owns every buffer it passes.  A plan owns its device
- *    memory (DRMs, FP64 accumulators, scratch), allocated in ttnn_plan_create
- *    (stream ordered on its stream: use the plan on other streams only after that
- *    stream has passed the call) and released by ttnn_destroy or
- *    ttnn_destroy_async.  ttnn_footprint_bytes reports its size.
+ *  - Ownership: the caller owns every buffer it passes.  A plan made by ttnn_plan
+ *    lives in a device workspace the caller owns (ttnn_workspace_bytes gives its
+ *    size): every device array of the plan (DRMs, FP64 accumulators, scratch) is a
+ *    view into it, and the plan never frees it.  ttnn_plan_create instead takes one
+ *    block from the library's per-device pool (stream ordered on its stream: use the
+ *    plan on other streams only after that stream has passed the call), released by
+ *    ttnn_destroy or ttnn_destroy_async.  ttnn_footprint_bytes reports the size.
+ *    Besides plans the library keeps, per process, a small pinned/device ring that
+ *    stages the descriptor tables of batched launches.
  *  - Threads: one host thread per plan at a time; distinct plans are independent.
  *  - Errors: no exception or abort crosses the ABI.  ttnn_last_error() returns a
  *    thread-local message describing the last non-OK status.
@@ -124,15 +128,33 @@ typedef struct {
  * half as u1 = (a + 1) 2^-53 and u2 = b 2^-53, and fixed-order binary64 series for
  * ln and cos(2 pi .) so that the FP64 value is reproducible bit for bit; the FP32
  * copy is its round-to-nearest value and the BF16 copy the round-to-nearest-even of
- * the FP32 bits.  Rows of X_t run column-major over the modes outside I_t (TTNN) or
- * over the indices of the contracted tensor outside I_t (STTNN, contracted groups
- * kept in place); rows of Y_t run column-major over I_t.  Accumulators start at 0. */
+ * the FP32 bits.  An F32 / BF16 plan uses its rounded copy for every use of a map
+ * (the sweeps, the FP64 intermediates and epilogue, rank-1 updates): its FP64 array
+ * holds the rounded values exactly, so that each node has one X_t and one Y_t and the
+ * projector identities of Sec. 4 / Sec. 5 hold for the sketches it computes.  Rows of
+ * X_t run column-major over the modes outside I_t (TTNN) or over the indices of the
+ * contracted tensor outside I_t (STTNN, contracted groups kept in place); rows of Y_t
+ * run column-major over I_t.  Accumulators start at 0. */
 ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_plan_t* out);
+
+/* Device bytes a plan for `problem` needs (its DRMs in FP64 and in the compute dtype,
+ * FP64 accumulators, cores' scratch and partial sums), computed on the host without
+ * allocating or launching anything; 0 if the problem is invalid (ttnn_last_error says
+ * why). */
+size_t ttnn_workspace_bytes(const ttnn_problem* problem);
+
+/* The plan of ttnn_plan_create, built inside a device workspace the caller owns:
+ * d_ws (256-byte aligned) of ws_bytes >= ttnn_workspace_bytes(problem).  Every device
+ * array of the plan is a view into d_ws; the DRMs are generated and the accumulators
+ * zeroed on `stream`.  The workspace must stay allocated, and be used by nothing else,
+ * until ttnn_destroy / ttnn_destroy_async, which never free it.  TTNN_E_INVALID if the
+ * workspace is missing, misaligned or too small. */
+ttnn_status ttnn_plan(const ttnn_problem* problem, void* d_ws, size_t ws_bytes, void* stream, ttnn_plan_t* out);
 ttnn_status ttnn_destroy(ttnn_plan_t plan);
 
-/* Releases the plan without waiting: its device memory (stream-ordered allocations)
- * returns to the device pool when `stream` reaches this call, and the handle is
- * invalid on return.  Every piece of work on the plan must be enqueued on `stream`
+/* Releases the plan without waiting: the device memory of a ttnn_plan_create plan
+ * (stream ordered) returns to the device pool when `stream` reaches this call (a
+ * caller's workspace stays the caller's), and the handle is invalid on return.  Every piece of work on the plan must be enqueued on `stream`
  * (or ordered before this point on it).  For serving loops that retire streams
  * while other work is in flight. */
 ttnn_status ttnn_destroy_async(ttnn_plan_t plan, void* stream);
@@ -147,11 +169,16 @@ size_t ttnn_footprint_bytes(ttnn_plan_t plan);
 ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes);
 
 /* Streaming update (Sec. 4, linearity): add alpha * sketch(H) to the accumulators,
- * where H is zero outside the box [offset, offset + extent) and equals the packed
- * column-major block d_block (extent[0] fastest, plan dtype) inside it.  The whole
- * tensor is offset = 0, extent = dims.  Empty boxes are a no-op. */
+ * where H is zero outside the box [offset, offset + extent) and equals the block
+ * d_block (plan dtype) inside it.  strides: NULL for a packed column-major block
+ * (extent[0] fastest), else the element stride of each mode (>= 1 on modes of extent
+ * > 1), so that box entry (i_1, .., i_d) is d_block[sum_mu i_mu strides[mu]]: a slice
+ * of a larger resident array is read in place (e.g. strides = the array's packed
+ * strides).  A strided block takes the generic contraction kernels; packed whole
+ * tensors take the one-pass kernels.  The whole tensor is offset = 0, extent = dims.
+ * Empty boxes are a no-op. */
 ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset,
-                               const int64_t* extent, double alpha, void* stream);
+                               const int64_t* extent, const int64_t* strides, double alpha, void* stream);
 
 /* Rank-1 update H = a_1 o a_2 o ... o a_d: d_factors is a host array of `order`
  * device pointers to FP64 vectors of length n_mu. */
@@ -172,6 +199,7 @@ typedef struct {
   const void* d_block;
   int64_t offset[TTNN_MAX_ORDER];
   int64_t extent[TTNN_MAX_ORDER];
+  int64_t strides[TTNN_MAX_ORDER];   /* strides[0] == 0: packed; else as in ttnn_sketch_update */
   double alpha;
 } ttnn_update_desc;
 ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs, void* stream);
@@ -225,8 +253,9 @@ ttnn_status ttnn_sketch_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int6
                               int64_t* cols);
 ttnn_status ttnn_read_sketch(ttnn_plan_t plan, int32_t node, int32_t kind, double* d_out,
                              void* stream);
-/* DRM of node `node` (kind 0 = X, 1 = Y) as stored for `dtype` (FP64 master, or the
- * FP32 / BF16 copy of an F32 / BF16 plan), row-major rows x cols; BF16 as uint16. */
+/* DRM of node `node` (kind 0 = X, 1 = Y) as stored for `dtype` (the FP64 array, or the
+ * FP32 / BF16 copy of an F32 / BF16 plan, whose values the FP64 array then holds),
+ * row-major rows x cols; BF16 as uint16. */
 ttnn_status ttnn_drm_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows,
                            int64_t* cols);
 ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t dtype,
@@ -251,6 +280,23 @@ ttnn_status ttnn_sweep_time_ms(ttnn_plan_t plan, float* ms);
  * after it by a streaming contraction); 3 one-pass TTNN-mode kernel (R_A, Z_A, R_1,
  * R_B). */
 ttnn_status ttnn_sweep_kind(ttnn_plan_t plan, int32_t* kind);
+
+/* Host-side sizing hooks (pure arithmetic, no device; for tests and tools).
+ * ttnn_right_sketch_split: how a whole-tensor right sketch R = T^{t} X_t on the MFMA
+ * form is split over its contraction: the operand is [contraction_run][rows][runs]
+ * (the contraction runs over contraction_run x runs values, rows = n_t), r columns;
+ * nchunks chunks of kchunk values, each writing a rows x r FP64 partial into scratch of
+ * scratch_elems doubles (nchunks * rows * r <= scratch_elems).  TTNN_E_INVALID if the
+ * shape is not covered or the scratch cannot hold one chunk.
+ * ttnn_chain_head_split: the first contraction of an STTNN / root chain, Y_g^T applied
+ * to the raw tensor for a group g at mode 1 (group_rows = n_g contracted values per
+ * row, `rows` output rows of k values): *in_place = 1 when the partial scratch cannot
+ * hold two chunks, the single chunk then being written straight into the chain buffer
+ * of rows * k values; otherwise the split through the scratch. */
+ttnn_status ttnn_right_sketch_split(int64_t contraction_run, int64_t rows, int64_t runs, int32_t r, int32_t dtype,
+                                    size_t scratch_elems, int32_t compute_units, int64_t* nchunks, int64_t* kchunk);
+ttnn_status ttnn_chain_head_split(int64_t group_rows, int64_t rows, int32_t k, int32_t dtype, size_t scratch_elems,
+                                  int32_t compute_units, int32_t* in_place, int64_t* nchunks, int64_t* kchunk);
 
 /* Zero the accumulators and clear a sticky error. */
 ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream);

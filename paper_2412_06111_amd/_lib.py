@@ -43,7 +43,8 @@ class Problem(C.Structure):
 class UpdateDesc(C.Structure):
     _fields_ = [
         ("plan", C.c_void_p), ("d_block", C.c_void_p),
-        ("offset", C.c_int64 * MAX_ORDER), ("extent", C.c_int64 * MAX_ORDER), ("alpha", C.c_double),
+        ("offset", C.c_int64 * MAX_ORDER), ("extent", C.c_int64 * MAX_ORDER), ("strides", C.c_int64 * MAX_ORDER),
+        ("alpha", C.c_double),
     ]
 
 
@@ -55,9 +56,10 @@ def _load():
     P64 = C.POINTER(i64)
     sigs = {
         "ttnn_plan_create": [C.POINTER(Problem), vp, C.POINTER(vp)],
+        "ttnn_plan": [C.POINTER(Problem), vp, C.c_size_t, vp, C.POINTER(vp)],
         "ttnn_destroy": [vp],
         "ttnn_destroy_async": [vp, vp],
-        "ttnn_sketch_update": [vp, vp, P64, P64, dbl, vp],
+        "ttnn_sketch_update": [vp, vp, P64, P64, P64, dbl, vp],
         "ttnn_sketch_update_rank1": [vp, C.POINTER(vp), dbl, vp],
         "ttnn_sketch_update_batched": [i32, C.POINTER(UpdateDesc), vp],
         "ttnn_core_shape": [vp, i32, C.POINTER(i32), P64],
@@ -85,6 +87,8 @@ def _load():
         f.restype = C.c_int
     lib.ttnn_footprint_bytes.argtypes = [vp]
     lib.ttnn_footprint_bytes.restype = C.c_size_t
+    lib.ttnn_workspace_bytes.argtypes = [C.POINTER(Problem)]
+    lib.ttnn_workspace_bytes.restype = C.c_size_t
     lib.ttnn_status_string.argtypes = [C.c_int]
     lib.ttnn_status_string.restype = C.c_char_p
     lib.ttnn_last_error.argtypes = []
@@ -132,6 +136,14 @@ def check_block(block, dtype, extent, d, strides=None):
                 raise ValueError(f"strides {tuple(strides)} address entries outside the block's storage")
     if not block.is_cuda:
         raise TypeError("block must be a CUDA (HIP) tensor")
+
+
+class _nullctx:
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        return False
 
 
 def stream_ptr(stream=None):
@@ -197,11 +209,35 @@ def footprint_estimate(spec, dims, rank, over, variant="ttnn", dtype="f64"):
     return int(out.value)
 
 
+def workspace_bytes(spec, dims, rank, over, variant="ttnn", dtype="f64"):
+    """Size of the device workspace ttnn_plan needs for this problem."""
+    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0)
+    n = int(lib.ttnn_workspace_bytes(C.byref(pr)))
+    if n == 0:
+        raise TTNNError(-1, (lib.ttnn_last_error() or b"").decode())
+    return n
+
+
+def view_strides(block, extent, d):
+    """Column-major element strides of a block given as a torch view of shape
+    (e_d, .., e_1) (the layout of a C-contiguous (n_d, .., n_1) tensor), or None when
+    it is packed (contiguous) or flat."""
+    if block.dim() == d and tuple(block.shape) == tuple(int(e) for e in reversed(extent)) \
+            and not block.is_contiguous():
+        return tuple(int(block.stride(d - 1 - mu)) for mu in range(d))
+    return None
+
+
 class Plan:
-    """A sketching plan: problem of Sec. 4 / Alg. 2 plus seed and precision."""
+    """A sketching plan: problem of Sec. 4 / Alg. 2 plus seed and precision.
+
+    Device memory: by default a workspace tensor allocated with torch (ttnn_plan; the
+    plan's arrays are views into it); `workspace` passes one of the caller's (a CUDA
+    uint8 tensor of at least workspace_bytes(...)); pool=True lets the library take a
+    block from its own per-device pool (ttnn_plan_create)."""
 
     def __init__(self, spec, dims, rank, over, variant="ttnn", dtype="f64", seed=1, eps_factor=0.0,
-                 stream=None):
+                 stream=None, workspace=None, pool=False):
         self.spec, self.dims = spec, tuple(int(n) for n in dims)
         self.d = len(self.dims)
         self.variant = VARIANT_OF_NAME[variant] if isinstance(variant, str) else int(variant)
@@ -211,20 +247,42 @@ class Plan:
         self.node_of_modes = {m: i for i, m in enumerate(modes)}
         self.num_nodes = len(modes)
         self.handle = C.c_void_p()
-        check(lib.ttnn_plan_create(C.byref(self.problem), stream_ptr(stream), C.byref(self.handle)))
+        self.workspace = None
+        if pool:
+            check(lib.ttnn_plan_create(C.byref(self.problem), stream_ptr(stream), C.byref(self.handle)))
+            return
+        need = int(lib.ttnn_workspace_bytes(C.byref(self.problem)))
+        if need == 0:
+            raise TTNNError(-1, (lib.ttnn_last_error() or b"").decode())
+        if workspace is None:
+            with torch.cuda.stream(stream) if stream is not None else _nullctx():
+                workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+        if not (isinstance(workspace, torch.Tensor) and workspace.is_cuda and workspace.is_contiguous()):
+            raise TypeError("workspace must be a contiguous CUDA tensor")
+        if workspace.numel() * workspace.element_size() < need:
+            raise ValueError(f"workspace of {workspace.numel() * workspace.element_size()} bytes; the plan needs {need}")
+        check(lib.ttnn_plan(C.byref(self.problem), C.c_void_p(workspace.data_ptr()),
+                            workspace.numel() * workspace.element_size(), stream_ptr(stream), C.byref(self.handle)))
+        self.workspace = workspace
 
     # ------------------------------------------------------------ lifetime
     def close(self):
         if self.handle:
             lib.ttnn_destroy(self.handle)
             self.handle = C.c_void_p()
+        self.workspace = None
 
     def close_async(self, stream=None):
-        """Release without waiting: the memory returns to the pool when `stream` (on
-        which all of this plan's work ran) reaches this point."""
+        """Release without waiting: the memory returns to its pool (the library's, or
+        torch's for a workspace tensor) when `stream` (on which all of this plan's work
+        ran) reaches this point."""
         if self.handle:
             lib.ttnn_destroy_async(self.handle, stream_ptr(stream))
             self.handle = C.c_void_p()
+        if self.workspace is not None:
+            if stream is not None:
+                self.workspace.record_stream(stream)
+            self.workspace = None
 
     def __del__(self):
         try:
@@ -243,16 +301,20 @@ class Plan:
         return self.node_of_modes[tuple(modes)]
 
     # ------------------------------------------------------------ sketch phase
-    def update(self, block, extent=None, offset=None, alpha=1.0, stream=None):
-        """block: CUDA tensor of the plan dtype whose memory is the box in column-major
-        order (numel == prod(extent))."""
+    def update(self, block, extent=None, offset=None, alpha=1.0, stream=None, strides=None):
+        """block: CUDA tensor of the plan dtype holding the box: packed column-major
+        (numel == prod(extent)), or a view of shape (e_d, .., e_1) into a larger tensor,
+        read in place with its strides; `strides` (elements, mode 1 first) overrides."""
         extent = self.dims if extent is None else tuple(int(e) for e in extent)
         offset = (0,) * self.d if offset is None else tuple(int(o) for o in offset)
-        check_block(block, self.torch_dtype, extent, self.d)
+        if strides is None:
+            strides = view_strides(block, extent, self.d)
+        check_block(block, self.torch_dtype, extent, self.d, strides)
         if len(offset) != self.d:
             raise ValueError(f"offset has {len(offset)} modes, the tensor has {self.d}")
+        st = None if strides is None else (C.c_int64 * self.d)(*strides)
         check(lib.ttnn_sketch_update(self.handle, C.c_void_p(block.data_ptr()), (C.c_int64 * self.d)(*offset),
-                                     (C.c_int64 * self.d)(*extent), float(alpha), stream_ptr(stream)))
+                                     (C.c_int64 * self.d)(*extent), st, float(alpha), stream_ptr(stream)))
 
     def update_rank1(self, factors, alpha=1.0, stream=None):
         """factors: d CUDA float64 vectors, factor mu of length n_mu (the library reads
@@ -394,7 +456,8 @@ def update_batched(items, stream=None):
     arr = (UpdateDesc * max(1, len(items)))()
     keep = []
     for i, (plan, block, extent, offset, alpha) in enumerate(items):
-        check_block(block, plan.torch_dtype, extent, plan.d)
+        strides = view_strides(block, extent, plan.d)
+        check_block(block, plan.torch_dtype, extent, plan.d, strides)
         if len(offset) != plan.d:
             raise ValueError(f"item {i}: offset has {len(offset)} modes, the tensor has {plan.d}")
         arr[i].plan = plan.handle
@@ -402,6 +465,7 @@ def update_batched(items, stream=None):
         for mu in range(plan.d):
             arr[i].offset[mu] = int(offset[mu])
             arr[i].extent[mu] = int(extent[mu])
+            arr[i].strides[mu] = 0 if strides is None else int(strides[mu])
         arr[i].alpha = float(alpha)
         keep.append(block)
     check(lib.ttnn_sketch_update_batched(len(items), arr, stream_ptr(stream)))

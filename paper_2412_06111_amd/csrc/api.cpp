@@ -64,6 +64,22 @@ void check_box(const Plan& P, const int64_t* off, const int64_t* ext, bool* empt
   }
 }
 
+// Validated strides of a block, or nullptr when the block is packed (strides equal to
+// the packed column-major ones on every mode of extent > 1, or strides absent).
+const int64_t* block_strides(const Plan& P, const int64_t* ext, const int64_t* strides) {
+  if (!strides) return nullptr;
+  bool packed = true;
+  int64_t pk = 1;
+  for (int mu = 0; mu < P.d; ++mu) {
+    if (ext[mu] > 1) {
+      if (strides[mu] < 1) throw Error{TTNN_E_INVALID, "strides must be >= 1 on modes of extent > 1"};
+      if (strides[mu] != pk) packed = false;
+    }
+    pk *= ext[mu];
+  }
+  return packed ? nullptr : strides;
+}
+
 }  // namespace
 
 extern "C" {
@@ -73,6 +89,31 @@ ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_pla
     if (!out) throw Error{TTNN_E_INVALID, "out is NULL"};
     *out = nullptr;
     auto P = ttnn::build_plan(problem, as_stream(stream));
+    auto* h = new ttnn_plan_s;
+    h->p = std::move(P);
+    *out = h;
+    return TTNN_OK;
+  });
+}
+
+size_t ttnn_workspace_bytes(const ttnn_problem* problem) {
+  try {
+    return ttnn::build_plan(problem, nullptr, /*dry=*/true)->footprint;
+  } catch (const Error& e) {
+    ttnn::set_error(e.msg);
+  } catch (const std::exception& e) {
+    ttnn::set_error(e.what());
+  }
+  return 0;
+}
+
+ttnn_status ttnn_plan(const ttnn_problem* problem, void* d_ws, size_t ws_bytes, void* stream, ttnn_plan_t* out) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!out) throw Error{TTNN_E_INVALID, "out is NULL"};
+    *out = nullptr;
+    if (!d_ws) throw Error{TTNN_E_INVALID, "workspace is NULL"};
+    if (reinterpret_cast<uintptr_t>(d_ws) % 256 != 0) throw Error{TTNN_E_INVALID, "workspace not 256-byte aligned"};
+    auto P = ttnn::build_plan(problem, as_stream(stream), false, d_ws, ws_bytes);
     auto* h = new ttnn_plan_s;
     h->p = std::move(P);
     *out = h;
@@ -97,7 +138,7 @@ ttnn_status ttnn_destroy_async(ttnn_plan_t plan, void* stream) {
 size_t ttnn_footprint_bytes(ttnn_plan_t plan) { return plan ? plan->p->footprint : 0; }
 
 ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset, const int64_t* extent,
-                               double alpha, void* stream) {
+                               const int64_t* strides, double alpha, void* stream) {
   Plan* P = get(plan);
   return guard(P, [&]() -> ttnn_status {
     if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
@@ -105,7 +146,8 @@ ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int6
     check_box(*P, offset, extent, &empty);
     if (empty) return TTNN_OK;
     if (!d_block) throw Error{TTNN_E_INVALID, "block is NULL"};
-    ttnn::update_box(*P, d_block, offset, extent, alpha, as_stream(stream));
+    const int64_t* st = block_strides(*P, extent, strides);
+    ttnn::update_box(*P, d_block, offset, extent, st, alpha, as_stream(stream));
     TTNN_HIP(hipGetLastError());
     return TTNN_OK;
   });
@@ -134,6 +176,7 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
       bool empty = false;
       check_box(*P, descs[i].offset, descs[i].extent, &empty);
       if (!empty && !descs[i].d_block) throw Error{TTNN_E_INVALID, "descriptor block is NULL"};
+      if (!empty && descs[i].strides[0] != 0) block_strides(*P, descs[i].extent, descs[i].strides);
     }
     std::vector<int32_t> pending;
     for (int32_t i = 0; i < n; ++i) {
@@ -159,10 +202,14 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
           round.push_back(i);
         }
         std::map<std::string, std::vector<int32_t>> buckets;
+        auto strides_of = [&](int32_t i) {
+          const ttnn_update_desc& u = descs[i];
+          return u.strides[0] != 0 ? block_strides(*get(u.plan), u.extent, u.strides) : nullptr;
+        };
         for (int32_t i : round) {
           Plan* P = get(descs[i].plan);
-          if (ttnn::whole_tensor(*P, descs[i].offset, descs[i].extent))
-            ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, st);
+          if (ttnn::whole_tensor(*P, descs[i].offset, descs[i].extent) && !strides_of(i))
+            ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, nullptr, descs[i].alpha, st);
           else
             buckets[ttnn::batch_key(*P)].push_back(i);
         }
@@ -174,7 +221,8 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
             const int32_t i = kv.second[b];
             Plan* P = get(descs[i].plan);
             P->epilogue_valid = false;
-            ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, descs[i].alpha, recs[b]);
+            ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, strides_of(i), descs[i].alpha,
+                             recs[b]);
             items.push_back(&recs[b]);
             plans.push_back(P);
           }
@@ -445,6 +493,34 @@ ttnn_status ttnn_sweep_kind(ttnn_plan_t plan, int32_t* kind) {
     if (!P || !kind) throw Error{TTNN_E_INVALID, "plan or kind is NULL"};
     const auto& F = P->fused;
     *kind = !F.enabled ? 0 : F.tt ? 3 : F.zout ? 2 : 1;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_right_sketch_split(int64_t contraction_run, int64_t rows, int64_t runs, int32_t r, int32_t dtype,
+                                    size_t scratch_elems, int32_t compute_units, int64_t* nchunks, int64_t* kchunk) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!nchunks || !kchunk || compute_units < 1) throw Error{TTNN_E_INVALID, "bad argument"};
+    if (dtype != TTNN_F64 && dtype != TTNN_F32 && dtype != TTNN_BF16) throw Error{TTNN_E_INVALID, "bad dtype"};
+    const ttnn::RightMfmaSplit sp =
+        ttnn::right_mfma_split(contraction_run, rows, runs, r, dtype, scratch_elems, compute_units);
+    *nchunks = sp.nch;
+    *kchunk = sp.kchunk;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_chain_head_split(int64_t group_rows, int64_t rows, int32_t k, int32_t dtype, size_t scratch_elems,
+                                  int32_t compute_units, int32_t* in_place, int64_t* nchunks, int64_t* kchunk) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!in_place || !nchunks || !kchunk || compute_units < 1 || k < 1) throw Error{TTNN_E_INVALID, "bad argument"};
+    if (dtype != TTNN_F64 && dtype != TTNN_F32 && dtype != TTNN_BF16) throw Error{TTNN_E_INVALID, "bad dtype"};
+    const bool inpl = ttnn::chain_head_in_place(rows, k, scratch_elems);
+    const size_t room = inpl ? static_cast<size_t>(rows) * static_cast<size_t>(k) : scratch_elems;
+    const ttnn::RightMfmaSplit sp = ttnn::right_mfma_split(group_rows, rows, 1, k, dtype, room, compute_units);
+    *in_place = inpl ? 1 : 0;
+    *nchunks = sp.nch;
+    *kchunk = sp.kchunk;
     return TTNN_OK;
   });
 }

@@ -170,6 +170,19 @@ GJob mode_job(const double* in, const std::vector<int64_t>& sizes, int p, const 
   return left_job(in, L, sizes[p], Q, M, sMi, sMj, ncols, out, 0, 1.0);
 }
 
+// Operand addressing of a contraction that reads the raw block, whose contracted
+// positions are the modes [p0, p0 + w): packed, or in place with the caller's strides.
+HMap raw_hmap(const Plan& P, const int64_t* ext, const int64_t* strides, int p0, int w) {
+  HMap h;
+  if (!strides) return h;
+  h.strided = 1;
+  for (int mu = 0; mu < P.d; ++mu) {
+    IndexMap& m = mu < p0 ? h.ml : mu < p0 + w ? h.mi : h.mq;
+    m.push(ext[mu], 0, strides[mu]);
+  }
+  return h;
+}
+
 bool whole_box(const Plan& P, const int64_t* off, const int64_t* ext) {
   for (int mu = 0; mu < P.d; ++mu)
     if (off[mu] != 0 || ext[mu] != P.dims[mu]) return false;
@@ -256,8 +269,8 @@ std::string batch_key(const Plan& P) {
   return k;
 }
 
-void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                std::vector<BoxOp>& ops) {
+void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
+                double alpha, std::vector<BoxOp>& ops) {
   const int cd = P.dtype;
   std::map<std::vector<int>, bool> done;
   auto chain_ptr = [&](const std::vector<int>& pf) { return P.chain + P.prefix_offset.at(pf); };
@@ -305,6 +318,7 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
     a.sDc = 1;
     a.ncols = g.k;
     a.amap = box_rows(P, g.first, g.last, off, ext);
+    if (before.empty()) a.hm = raw_hmap(P, ext, strides, p0, w);
     return a;
   };
   auto operand = [&](const std::vector<int>& prefix) -> const void* {
@@ -351,6 +365,7 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
     a.ncols = t.r;
     a.amap = amap;
     a.bmap = bmap;
+    if (pre.empty()) a.hm = raw_hmap(P, ext, strides, p0, w);
     a.nchunks = pick_chunks(a.n, a.ncols, a.L * a.Q, P.partial_elems);
     a.out = P.partial;
     a.ol = OutLayout{INT64_MAX, a.ncols, 1, 0, a.n * a.ncols};
@@ -489,16 +504,18 @@ void run_box_ops(Plan& P, const std::vector<BoxOp>& ops, hipStream_t st) {
 }
 
 namespace {
-void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                     hipStream_t st) {
+void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
+                     double alpha, hipStream_t st) {
   P.epilogue_valid = false;
-  if (!whole_box(P, off, ext)) {
+  // boxes, and any block read in place with strides, take the generic kernels (the
+  // one-pass and MFMA right-sketch kernels stream a packed whole tensor)
+  if (!whole_box(P, off, ext) || strides) {
     if (P.timing) {
       TTNN_HIP(hipEventRecord(P.sweep_ev[0], st));
       P.sweep_recorded = false;
     }
     std::vector<BoxOp> ops;
-    record_box(P, block, off, ext, alpha, ops);
+    record_box(P, block, off, ext, strides, alpha, ops);
     run_box_ops(P, ops, st);
     return;
   }
@@ -558,7 +575,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
           // one-chunk partial layout is Z's, so when the scratch cannot hold two chunks
           // the kernel writes Z directly (one chunk: the rows alone fill the machine)
           const size_t out = static_cast<size_t>(Q) * static_cast<size_t>(g.k);
-          if (2 * out <= P.partial_elems) {
+          if (!chain_head_in_place(Q, g.k, P.partial_elems)) {
             const int nch = launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, P.partial, P.partial_elems, st);
             IndexMap none;
             launch_reduce(P.partial, nch, Q, g.k, 2, 1.0, none, 0, chain_ptr(chain), 1, g.k, st);
@@ -675,9 +692,9 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
 }
 }  // namespace
 
-void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                hipStream_t st) {
-  update_box_impl(P, block, off, ext, alpha, st);
+void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
+                double alpha, hipStream_t st) {
+  update_box_impl(P, block, off, ext, strides, alpha, st);
   // without a one-pass sweep kernel the whole update counts as the sweep
   if (P.timing && !P.sweep_recorded) {
     TTNN_HIP(hipEventRecord(P.sweep_ev[1], st));

@@ -21,15 +21,16 @@ void size_chain_scratch(Plan& P);
 void zero_accumulators(Plan& P, hipStream_t stream);
 
 // Sketch phase on a box update (Sec. 4; Sec. 5 for STTNN): accumulators += alpha * sketch(H).
-void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                hipStream_t stream);
+// strides: element strides of the block per mode (read in place), or nullptr = packed.
+void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
+                double alpha, hipStream_t stream);
 void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t stream);
 
 // The steps of a box update that is not the whole tensor, in order.  Plans with equal
 // batch_key() give step lists of equal length whose i-th steps have the same kind, so
 // the i-th steps of several such updates can share one launch.
-void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, double alpha,
-                std::vector<BoxOp>& ops);
+void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
+                double alpha, std::vector<BoxOp>& ops);
 void run_box_ops(Plan& P, const std::vector<BoxOp>& ops, hipStream_t stream);
 void run_box_ops_batched(const std::vector<Plan*>& plans, const std::vector<const std::vector<BoxOp>*>& items,
                          hipStream_t stream);

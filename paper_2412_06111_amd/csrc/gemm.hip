@@ -34,9 +34,9 @@ __device__ inline float ldf(const uint16_t* p, int64_t i) { return bf16_bits_to_
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                                const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
-                                               const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
-                                               TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
-                                               int j0) {
+                                               const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
+                                               int64_t kchunk, TO* __restrict__ out, const OutLayout& ol,
+                                               int64_t row0, int64_t c, int j0) {
   // operand and DRM entries of step s + 1 are loaded into registers (and the DRM rows
   // of step s + 2 computed) while step s is multiplied out of LDS
   constexpr int NA = BR * BK / 256, NB = BK * BJ / 256;
@@ -82,7 +82,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
         const int64_t i = RIGHT ? rg : kg;
         const int64_t l = m % L;
         const int64_t q = m / L;
-        v = ldf(H, l + L * (i + n * q));
+        v = ldf(H, hm(l, i, q, L, n));
       }
       ra[s] = v;
     }
@@ -150,9 +150,9 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                           const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
-                                          const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
-                                          TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
-                                          int j0) {
+                                          const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
+                                          int64_t kchunk, TO* __restrict__ out, const OutLayout& ol, int64_t row0,
+                                          int64_t c, int j0) {
   __shared__ double As[BK][BR + 1];
   __shared__ double Bs[BK][BJ + 1];
   __shared__ int64_t drow[BK];
@@ -199,7 +199,7 @@ __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t
         const int64_t i = RIGHT ? rg : kg;
         const int64_t l = m % L;
         const int64_t q = m / L;
-        v = ld(H, l + L * (i + n * q));
+        v = ld(H, hm(l, i, q, L, n));
       }
       As[kk][rr] = v;
     }
@@ -250,21 +250,23 @@ __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                           const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
-                                          const IndexMap& amap, const IndexMap& bmap, int64_t kchunk,
-                                          TO* __restrict__ out, const OutLayout& ol, int64_t row0, int64_t c,
-                                          int j0) {
+                                          const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
+                                          int64_t kchunk, TO* __restrict__ out, const OutLayout& ol, int64_t row0,
+                                          int64_t c, int j0) {
   if constexpr (!std::is_same_v<TH, double> && !std::is_same_v<TD, double>)
-    gemm_tile_mfma<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol, row0, c, j0);
+    gemm_tile_mfma<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0, c,
+                                      j0);
   else
-    gemm_tile_valu<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol, row0, c, j0);
+    gemm_tile_valu<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0, c,
+                                      j0);
 }
 
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                                const TD* __restrict__ D, int64_t sDr, int64_t sDc,
-                                               int ncols, IndexMap amap, IndexMap bmap, int64_t kchunk,
+                                               int ncols, IndexMap amap, IndexMap bmap, HMap hm, int64_t kchunk,
                                                TO* __restrict__ out, OutLayout ol) {
-  gemm_tile<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, kchunk, out, ol,
+  gemm_tile<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol,
                                static_cast<int64_t>(blockIdx.x) * BR, blockIdx.y, blockIdx.z * BJ);
 }
 
@@ -304,8 +306,8 @@ __global__ __launch_bounds__(256) void hm_gemm_batched(const GemmTask* __restric
   const int64_t c = rel % t.nch;
   const int cb = static_cast<int>(rel / t.nch);
   gemm_tile<RIGHT, TH, TD, TO>(static_cast<const TH*>(t.H), t.L, t.n, t.Q, static_cast<const TD*>(t.D), t.sDr,
-                               t.sDc, t.ncols, t.amap, t.bmap, t.kchunk, static_cast<TO*>(t.out), t.ol, rb * BR,
-                               c, cb * BJ);
+                               t.sDc, t.ncols, t.amap, t.bmap, t.hm, t.kchunk, static_cast<TO*>(t.out), t.ol,
+                               rb * BR, c, cb * BJ);
 }
 
 template <bool RIGHT, typename TH, typename TD>
@@ -313,11 +315,11 @@ void gemm_dispatch_out(const GemmArgs& a, dim3 grid, int64_t kchunk, hipStream_t
   if (a.out_f32)
     hipLaunchKernelGGL((hm_gemm<RIGHT, TH, TD, float>), grid, dim3(256), 0, st,
                        static_cast<const TH*>(a.H), a.L, a.n, a.Q, static_cast<const TD*>(a.D), a.sDr,
-                       a.sDc, a.ncols, a.amap, a.bmap, kchunk, static_cast<float*>(a.out), a.ol);
+                       a.sDc, a.ncols, a.amap, a.bmap, a.hm, kchunk, static_cast<float*>(a.out), a.ol);
   else
     hipLaunchKernelGGL((hm_gemm<RIGHT, TH, TD, double>), grid, dim3(256), 0, st,
                        static_cast<const TH*>(a.H), a.L, a.n, a.Q, static_cast<const TD*>(a.D), a.sDr,
-                       a.sDc, a.ncols, a.amap, a.bmap, kchunk, static_cast<double*>(a.out), a.ol);
+                       a.sDc, a.ncols, a.amap, a.bmap, a.hm, kchunk, static_cast<double*>(a.out), a.ol);
 }
 
 template <bool RIGHT, typename TH>
@@ -572,6 +574,7 @@ BatchedGemm plan_gemm_batched(const std::vector<GemmArgs>& args) {
     t.ncols = a.ncols;
     t.amap = a.amap;
     t.bmap = a.bmap;
+    t.hm = a.hm;
     t.ol = a.ol;
     t.row_blocks = (rows + BR - 1) / BR;
     t.nch = nch;

@@ -23,6 +23,18 @@ struct OutLayout {
   int64_t Lo, s0, s1, s2, cs;
 };
 
+// Address of entry (l, i, q) of the operand H[L][n][Q]: packed, l + L (i + n q); or,
+// for a box read in place from a strided array (the caller's tensor), the sum of three
+// position maps over the box positions before the contracted group (ml), the group
+// (mi) and the positions after it (mq), each with the caller's element strides.
+struct HMap {
+  int32_t strided = 0, pad_ = 0;
+  IndexMap ml, mi, mq;
+  __host__ __device__ inline int64_t operator()(int64_t l, int64_t i, int64_t q, int64_t L, int64_t n) const {
+    return strided ? ml(l) + mi(i) + mq(q) : l + L * (i + n * q);
+  }
+};
+
 struct GemmArgs {
   bool right = true;
   const void* H = nullptr;
@@ -33,6 +45,7 @@ struct GemmArgs {
   int64_t sDr = 1, sDc = 1;
   int ncols = 1;
   IndexMap amap, bmap;
+  HMap hm;                     // operand addressing (packed unless a strided raw box)
   int nchunks = 1;
   void* out = nullptr;
   bool out_f32 = false;
@@ -55,6 +68,7 @@ struct GemmTask {
   int64_t L, n, Q, sDr, sDc, kchunk;
   int64_t row_blocks, nch, col_blocks, first_block;
   IndexMap amap, bmap;
+  HMap hm;
   OutLayout ol;
   int32_t ncols, pad_;
 };
@@ -172,6 +186,20 @@ void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const 
 // the chunks are as many as part_elems holds, so with part_elems = n r the single
 // chunk is the result itself.  Throws if part_elems < n r.
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt);
+// Split of such a right sketch over its contraction (pure host arithmetic): nch chunks
+// of kchunk values, each writing an n x r FP64 partial, nch * n * r <= part_elems.
+// Throws TTNN_E_INVALID when the shape is not covered or part_elems cannot hold one
+// chunk.  cus: compute units of the device.
+struct RightMfmaSplit {
+  int64_t nch, kchunk;
+};
+RightMfmaSplit right_mfma_split(int64_t L, int64_t n, int64_t Q, int r, int dt, size_t part_elems, int cus);
+// Where the head of a contraction chain (Y_g^T on the raw tensor, group g at mode 1,
+// Q rows of k values) writes: through the partial scratch and a reduction while two
+// chunks fit it, else as one chunk straight into the chain buffer of Q * k values.
+inline bool chain_head_in_place(int64_t Q, int k, size_t partial_elems) {
+  return 2 * static_cast<size_t>(Q) * static_cast<size_t>(k) > partial_elems;
+}
 int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
                       double* part, size_t part_elems, hipStream_t stream);
 

@@ -47,7 +47,7 @@ hipMemPool_t plan_pool() {
 // releasing it does not synchronise the device: the blocks return to the pool when
 // the release stream reaches them.
 Plan::~Plan() {
-  if (arena) (void)hipFreeAsync(arena, free_stream);
+  if (arena && owns_arena) (void)hipFreeAsync(arena, free_stream);
   for (hipEvent_t e : sweep_ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : side_ev)
@@ -91,7 +91,7 @@ void check_mul(int64_t a, int64_t b, const char* what) {
 
 }  // namespace
 
-std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry) {
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry, void* ws, size_t ws_bytes) {
   TTNN_REQUIRE(pr != nullptr, TTNN_E_INVALID, "problem is NULL");
   TTNN_REQUIRE(pr->order >= 2 && pr->order <= TTNN_MAX_ORDER, TTNN_E_INVALID, "order must be in [2, 8]");
   TTNN_REQUIRE(pr->dims && pr->parent && pr->first_mode && pr->last_mode && pr->rank && pr->oversample,
@@ -109,7 +109,13 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   P->dry = dry;
   P->stream = stream;
   P->free_stream = stream;
-  if (!dry) {
+  if (!dry && ws) {                      // the caller's workspace: views only, never freed here
+    TTNN_REQUIRE(ws_bytes >= need, TTNN_E_INVALID,
+                 "workspace of " + std::to_string(ws_bytes) + " bytes; the plan needs " + std::to_string(need));
+    P->arena = static_cast<char*>(ws);
+    P->arena_size = need;
+    P->owns_arena = false;
+  } else if (!dry) {
     void* a = nullptr;
     if (hipMallocFromPoolAsync(&a, need, plan_pool(), stream) != hipSuccess || a == nullptr) {
       (void)hipGetLastError();

@@ -84,6 +84,7 @@ struct Plan {
 
   char* arena = nullptr;                   // the plan's one device block
   size_t arena_size = 0, arena_used = 0;
+  bool owns_arena = true;                  // false: a caller-owned workspace (ttnn_plan)
   hipStream_t stream = nullptr;            // creation stream: allocations are ordered on it
   hipStream_t free_stream = nullptr;       // release stream (ttnn_destroy_async may change it)
   size_t footprint = 0;
@@ -109,8 +110,11 @@ struct Plan {
 
 // construction / validation (host); throws Error
 // dry: validate and size everything, allocate nothing and launch nothing (the
-// returned plan only reports its footprint).
-std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry = false);
+// returned plan only reports its footprint).  ws: a caller-owned device workspace of
+// ws_bytes (256-byte aligned) that holds every array of the plan; without it the plan
+// allocates one block from the library's per-device pool.
+std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry = false, void* ws = nullptr,
+                                 size_t ws_bytes = 0);
 
 // IndexMap from a set of consecutive modes of a box to the column-major index of
 // the same modes in the full tensor

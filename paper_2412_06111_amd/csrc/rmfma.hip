@@ -343,9 +343,9 @@ bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt) {
   return L == 1 && dt != TTNN_BF16 && n % v == 0 && Q % ks == 0 && Q >= 64;
 }
 
-int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
-                      double* part, size_t part_elems, hipStream_t st) {
+RightMfmaSplit right_mfma_split(int64_t L, int64_t n, int64_t Q, int r, int dt, size_t part_elems, int cus) {
   TTNN_REQUIRE(right_mfma_eligible(L, n, Q, r, dt), TTNN_E_INVALID, "right sketch shape not covered by the MFMA form");
+  // every chunk writes an n x r partial: the scratch must hold at least one
   TTNN_REQUIRE(part_elems >= static_cast<size_t>(n) * static_cast<size_t>(r), TTNN_E_INVALID,
                "partial buffer smaller than one chunk of the right sketch");
   const int64_t K = L * Q;
@@ -359,11 +359,18 @@ int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, co
   nch = std::min<int64_t>(nch, static_cast<int64_t>(part_elems / static_cast<size_t>(n * r)));
   // and at most one round of resident workgroups (three a compute unit, by LDS): a
   // second, partial round would stream with a fraction of the machine
-  nch = std::min<int64_t>(nch, std::max<int64_t>(1, 3 * compute_units() / row_blocks));
+  nch = std::min<int64_t>(nch, std::max<int64_t>(1, 3 * static_cast<int64_t>(cus) / row_blocks));
   nch = std::max<int64_t>(nch, 1);
   int64_t kchunk = (K + nch - 1) / nch;
   kchunk = (kchunk + kg - 1) / kg * kg;
   nch = (K + kchunk - 1) / kchunk;
+  return RightMfmaSplit{nch, kchunk};
+}
+
+int launch_right_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Xt, int64_t m, int r,
+                      double* part, size_t part_elems, hipStream_t st) {
+  const RightMfmaSplit sp = right_mfma_split(L, n, Q, r, dt, part_elems, compute_units());
+  const int64_t nch = sp.nch, kchunk = sp.kchunk;
   const bool rowc = L == 1;
   if (dt == TTNN_BF16) launch_dt<TTNN_BF16>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);
   else if (dt == TTNN_F32) launch_dt<TTNN_F32>(rowc, H, L, n, Q, Xt, m, r, kchunk, nch, part, st);

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -91,3 +92,65 @@ def test_footprint_estimate_rejects_bad_tree():
     with pytest.raises(P.TTNNError) as e:
         P.footprint_estimate(((1, 3), (2, 4)), (4, 4, 4, 4), 2, 1)
     assert e.value.status == -2
+
+
+def test_workspace_sizing_and_refusals_without_device():
+    """ttnn_workspace_bytes is host-only sizing (equal to the footprint estimate, 0 for
+    an invalid problem); ttnn_plan refuses a missing, misaligned or short workspace on
+    the host, before the device is touched."""
+    import paper_2412_06111_amd as P
+    from paper_2412_06111_amd import _lib
+    spec, dims = ((1, 2), (3, 4)), (16, 12, 10, 14)
+    for v in ("ttnn", "sttnn"):
+        for dt in ("f64", "f32", "bf16"):
+            assert P.workspace_bytes(spec, dims, 5, 3, v, dt) == P.footprint_estimate(spec, dims, 5, 3, v, dt)
+    pr, keep = _problem(((1, 3), (2, 4)), (2, 2, 2, 2))
+    assert _lib.lib.ttnn_workspace_bytes(C.byref(pr)) == 0
+    pr, keep = _problem(spec, dims)
+    need = _lib.lib.ttnn_workspace_bytes(C.byref(pr))
+    h = C.c_void_p()
+    assert _lib.lib.ttnn_plan(C.byref(pr), None, need, None, C.byref(h)) == -1 and not h.value
+    assert _lib.lib.ttnn_plan(C.byref(pr), C.c_void_p(0x1000 + 8), need, None, C.byref(h)) == -1
+    assert b"aligned" in _lib.lib.ttnn_last_error()
+    assert _lib.lib.ttnn_plan(C.byref(pr), C.c_void_p(0x1000), need - 256, None, C.byref(h)) == -1
+    assert b"needs" in _lib.lib.ttnn_last_error() and not h.value
+
+
+def test_chain_head_and_right_sketch_split_without_device():
+    """The chunking of the MFMA right sketch and the chain-head choice, as pure host
+    arithmetic.  The geometry of an out-of-bounds write once seen (the Y^T chain head
+    of a 20-wide group at mode 1 of the 20^6 tensor: 3.2M rows of k = 9 values against a
+    4,194,304-value partial scratch) goes in place as one chunk that exactly fills the
+    chain buffer; a scratch that cannot hold one chunk is refused; every split keeps
+    its partials inside the scratch and covers the contraction."""
+    from paper_2412_06111_amd import _lib
+    L = _lib.lib
+    L.ttnn_chain_head_split.argtypes = [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_size_t, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.ttnn_right_sketch_split.argtypes = [C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_size_t,
+                                          C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    inp, nch, kch = C.c_int32(), C.c_int64(), C.c_int64()
+    rows, k, scratch = 20 ** 5, 9, 1 << 22
+    for dt in (0, 1):
+        assert L.ttnn_chain_head_split(20, rows, k, dt, scratch, 256, C.byref(inp), C.byref(nch), C.byref(kch)) == 0
+        assert inp.value == 1 and nch.value == 1 and kch.value >= 20
+    # the same chain head sent through the partial scratch is refused on the host
+    assert L.ttnn_right_sketch_split(20, rows, 1, k, 0, scratch, 256, C.byref(nch), C.byref(kch)) == -1
+    assert b"partial buffer" in L.ttnn_last_error()
+    # small enough: through the scratch, two or more chunks' room
+    assert L.ttnn_chain_head_split(20, 1000, k, 0, scratch, 256, C.byref(inp), C.byref(nch), C.byref(kch)) == 0
+    assert inp.value == 0 and nch.value * 1000 * k <= scratch
+    g = np.random.default_rng(3)
+    for _ in range(300):
+        dt = int(g.integers(0, 3))
+        v = 16 // (8, 4, 2)[dt]
+        Lr = int(v * g.integers(1, 64))
+        n = int(g.integers(1, 600))
+        Q = int(g.integers(1, 4000))
+        r = int(g.integers(1, 65))
+        cap = int(g.integers(n * r, 40 * n * r + 1))
+        cus = int(g.integers(1, 300))
+        assert L.ttnn_right_sketch_split(Lr, n, Q, r, dt, cap, cus, C.byref(nch), C.byref(kch)) == 0
+        assert nch.value >= 1 and nch.value * n * r <= cap, (Lr, n, Q, r, cap)
+        assert nch.value * kch.value >= Lr * Q > (nch.value - 1) * kch.value
+        assert L.ttnn_right_sketch_split(Lr, n, Q, r, dt, n * r - 1, cus, C.byref(nch), C.byref(kch)) == -1

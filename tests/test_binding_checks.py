@@ -10,9 +10,18 @@ from paper_2412_06111_amd._lib import check_block
 
 
 def test_refuses_non_contiguous_block():
-    blk = torch.zeros(6, 4, dtype=torch.float32).t()          # a transposed view
+    blk = torch.zeros(6, 4, dtype=torch.float32).t()          # a transposed view, no strides given
     with pytest.raises(ValueError, match="contiguous"):
         check_block(blk, torch.float32, (6, 4), 2)
+
+
+def test_views_of_the_box_shape_are_read_with_their_strides():
+    from paper_2412_06111_amd._lib import view_strides
+    base = torch.zeros(5, 7, 9, dtype=torch.float32)            # (n3, n2, n1): column-major 9 x 7 x 5
+    view = base[1:4, 2:6, 3:8]                                  # box extents (5, 4, 3) at offset (3, 2, 1)
+    assert view_strides(view, (5, 4, 3), 3) == (1, 9, 63)
+    assert view_strides(base, (9, 7, 5), 3) is None             # contiguous: packed
+    assert view_strides(view.reshape(-1) if view.is_contiguous() else torch.zeros(60), (5, 4, 3), 3) is None
 
 
 def test_refuses_mis_sized_block():
@@ -49,6 +58,6 @@ def test_update_batched_checks_before_marshalling():
     class FakePlan:                                            # only the fields the checks read
         torch_dtype, d, handle = torch.float32, 2, None
     with pytest.raises(ValueError, match="contiguous"):
-        P.update_batched([(FakePlan(), torch.zeros(6, 4).t(), (6, 4), (0, 0), 1.0)])
+        P.update_batched([(FakePlan(), torch.zeros(48)[::2], (6, 4), (0, 0), 1.0)])
     with pytest.raises(ValueError, match="entries"):
         P.update_batched([(FakePlan(), torch.zeros(5), (6, 4), (0, 0), 1.0)])
