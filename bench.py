@@ -110,8 +110,9 @@ def sweep_counts(dims, r, p, variant, dtype, kind):
     1: the one-pass STTNN kernel reads the tensor once and the DRMs X_A, X_1, X_2, Y_A,
        Y_1 once, and writes R_A, Z_A = Y_A^T T^{A}, R_1, R_2 once (FP32; FP64 for an
        FP64 plan); the remaining nodes are formed from Z_A afterwards.
-    2: the same kernel without R_2: it writes Z1 = Y_1^T T^{(1)} (k x N / n_1 in the
-       plan dtype) and reads no X_2; R_2 is a separate streaming contraction.
+    2: the same kernel without R_2: it writes Z1 = Y_1^T T^{(1)} (k x N / n_1, in the
+       plan dtype, FP32 for a BF16 plan) and reads no X_2; R_2 is a separate streaming
+       contraction.
     3: the TTNN-mode kernel: tensor once, X_A, X_1, Y_A, X_B once; R_A, Z_A, R_1, R_B out.
     0: the sweep is the whole update and its counts are those of the pass."""
     flops, drm, N = work_counts(dims, r, p, variant)
@@ -134,7 +135,8 @@ def sweep_counts(dims, r, p, variant, dtype, kind):
         out += n2 * r
         kflops += 2 * (N // n1) * k * r
         return kflops, N * s + drm_k * s + out * acc
-    return kflops, N * s + drm_k * s + out * acc + k * (N // n1) * s
+    zs = 4 if dtype == "bf16" else s               # a BF16 plan writes Z1 in FP32
+    return kflops, N * s + drm_k * s + out * acc + k * (N // n1) * zs
 
 
 def measured_traffic(key):

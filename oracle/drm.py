@@ -123,7 +123,20 @@ def cos2pi_fixed(v):
 
 
 def gaussian(seed, node, kind, rows, cols):
-    """G(seed, node, kind, row, col) as float64 for broadcastable index arrays."""
+    """G(seed, node, kind, row, col) as float64 for broadcastable index arrays.  Uses
+    the plain-C evaluation of the same definition (oracle/cdrm.c, bit-identical) when
+    it is built, else gaussian_numpy."""
+    from . import cdrm
+    if cdrm.lib() is not None:
+        rows, cols = np.broadcast_arrays(np.asarray(rows, dtype=np.uint64), np.asarray(cols, dtype=np.uint64))
+        out = cdrm.gaussian(seed, 2 * node + kind, rows.ravel(), cols.ravel().astype(np.uint32))
+        return out.reshape(rows.shape)
+    return gaussian_numpy(seed, node, kind, rows, cols)
+
+
+def gaussian_numpy(seed, node, kind, rows, cols):
+    """The definition of G in NumPy float64 operations (the reference the C
+    evaluation is pinned to)."""
     rows = np.asarray(rows, dtype=np.uint64)
     cols = np.asarray(cols, dtype=np.uint64)
     rows, cols = np.broadcast_arrays(rows, cols)
@@ -139,6 +152,9 @@ def gaussian(seed, node, kind, rows, cols):
 
 def drm(seed, node, kind, nrows, ncols, chunk=1 << 22):
     """Dense DRM of shape (nrows, ncols), float64, generated in row chunks."""
+    from . import cdrm
+    if cdrm.lib() is not None:
+        return cdrm.drm_rows(seed, 2 * node + kind, 0, nrows, ncols)
     out = np.empty((nrows, ncols), dtype=np.float64)
     step = max(1, chunk // max(1, ncols))
     cols = np.arange(ncols, dtype=np.uint64)[None, :]

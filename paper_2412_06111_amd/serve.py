@@ -40,13 +40,14 @@ class Update:
     `extent`; kind 'rank1': `factors` (one FP64 device vector per mode)."""
 
     __slots__ = ("sid", "kind", "block", "offset", "extent", "factors", "alpha", "arrival", "nbytes",
-                 "t_done", "batch")
+                 "t_done", "t_launch", "batch")
 
     def __init__(self, sid, kind="box", block=None, offset=None, extent=None, factors=None, alpha=1.0,
                  arrival=0.0, nbytes=0):
         self.sid, self.kind, self.block, self.offset, self.extent = sid, kind, block, offset, extent
         self.factors, self.alpha, self.arrival, self.nbytes = factors, alpha, arrival, nbytes
         self.t_done = None
+        self.t_launch = None                    # host time its batch was launched
         self.batch = None
 
 
@@ -159,6 +160,8 @@ class Server:
         self.on_close = on_close                # on_close(sid, plan, cores) before the plan is released
         self.engine = engine if engine is not None else LibEngine()
         self.used = 0
+        self.peak_used = 0                      # largest admitted footprint at any time
+        self.create_s = []                      # host time of each plan creation (admission)
         self.streams = {}
         self.waiting = collections.deque()      # sids not yet admitted, arrival order
         self.admit_order = []
@@ -208,8 +211,11 @@ class Server:
             if self.used + st.footprint > self.budget:
                 break
             self.waiting.popleft()
+            t0 = time.perf_counter()
             st.plan = self.engine.create(st.spec)
+            self.create_s.append(time.perf_counter() - t0)
             self.used += st.footprint
+            self.peak_used = max(self.peak_used, self.used)
             st.admitted_at = self.now() if self._ref is not None else 0.0
             self.admit_order.append(sid)
 
@@ -265,6 +271,9 @@ class Server:
             items.append((st.plan, u))
             ups.append(u)
             st.inflight += 1
+        t_launch = self.now()
+        for u in ups:
+            u.t_launch = t_launch
         self.engine.launch(items)
         for st in chosen:
             st.n_done += 1
@@ -334,7 +343,11 @@ class Server:
                 elif not self.inflight and i < n:
                     time.sleep(min(50e-6, max(0.0, arrivals[i].arrival - self.now())))
         self.drain()
-        return stats(self.completed, self.now())
+        out = stats(self.completed, self.now())
+        out["peak_used_bytes"] = self.peak_used
+        out["plan_create_ms_max"] = max(self.create_s) * 1e3 if self.create_s else 0.0
+        out["plan_create_ms_total"] = sum(self.create_s) * 1e3
+        return out
 
 
 def stats(completed, wall_s):
@@ -348,6 +361,15 @@ def stats(completed, wall_s):
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
     }
+    # latency = waiting (arrival to the launch of its batch: admission of its stream,
+    # earlier updates of the stream, batches in flight) + on the GPU (launch to the end
+    # of its batch)
+    timed = [u for u in completed if u.t_launch is not None]
+    if timed:
+        wait = [(u.t_launch - u.arrival) * 1e3 for u in timed]
+        gpu = [(u.t_done - u.t_launch) * 1e3 for u in timed]
+        out["wait_p50_ms"], out["wait_p99_ms"] = float(np.percentile(wait, 50)), float(np.percentile(wait, 99))
+        out["gpu_p50_ms"], out["gpu_p99_ms"] = float(np.percentile(gpu, 50)), float(np.percentile(gpu, 99))
     for kind in ("box", "rank1"):
         lk = [(u.t_done - u.arrival) * 1e3 for u in completed if u.kind == kind]
         if lk:

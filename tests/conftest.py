@@ -7,6 +7,13 @@ if ROOT not in sys.path:
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
 
+# the oracle's plain-C DRM evaluation (pinned to its NumPy definition); built here when
+# missing so that a bare checkout runs the suite
+from oracle import cdrm as _cdrm  # noqa: E402
+
+if not os.path.exists(_cdrm.LIB):
+    _cdrm.build()
+
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")

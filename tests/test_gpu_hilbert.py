@@ -14,7 +14,7 @@ import torch
 
 import oracle as O
 from oracle.sampled import right_entry
-from gpu_util import TOL, rel, sketch_errors, to_device
+from gpu_util import TOL, rel, failures, sketch_errors, to_device
 from workloads import hilbert as H
 from workloads import synth as W
 
@@ -47,7 +47,7 @@ def test_hilbert_parity(P, variant, dtype, r):
     tree = O.Tree(H.TOY, T.shape, r, H.P_PAPER)
     sk = O.sketch(consumed, tree, O.DRMs(tree, 21, variant), variant)
     errs = sketch_errors(plan, tree, sk)
-    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    bad = failures(errs, TOL[dtype])
     assert not bad, bad
     if dtype != "f64":
         plan.close()

@@ -1,9 +1,12 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
-* DRMs: bit-exact for FP64 masters and their FP32 / BF16 copies;
-* sketches R_t, Omega_t, Psi_t (and the root Psi) within 1e-10 (FP64), 1e-5
-  (FP32), 1e-2 (BF16) relative Frobenius error, the oracle running on exactly the
-  values the GPU consumed with FP64 DRMs;
+* DRMs: bit-exact for FP64 masters and their FP32 / BF16 copies (a lower-precision
+  plan uses its rounded copy everywhere, so its FP64 array holds the rounded values);
+* sketches R_t, Omega_t, Psi_t (and the root Psi), element by element (relative
+  Frobenius error, and largest entry error over the RMS entry): within 1e-10 (FP64),
+  1e-5 (FP32), 1e-2 (BF16) of the oracle run on exactly the values the GPU consumed
+  with FP64 DRMs, and within 1e-5 (FP32 and BF16) of the oracle fed the same rounded
+  DRMs (arithmetic error alone);
 * recovery phase: cores (full-rank cases) and the reconstruction within 1e-10;
 * streaming: box updates add up to the one-shot sketch.
 Sizes span several 64 x 32 tiles with ragged tails.
@@ -14,7 +17,7 @@ import torch
 
 import oracle as O
 from workloads import synth as W
-from gpu_util import TOL, rel, sketch_errors, to_device
+from gpu_util import TOL, TOL_ARITH, rel, failures, sketch_errors, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -49,7 +52,8 @@ def test_drm_bit_exact(P, variant, dtype):
             want = O.drm_matrix(0x1234_5678_9abc, n.id, kind, rows, cols)
             got = plan.read_drm(cid, kind, P.F64).cpu().numpy()
             assert got.shape == want.shape
-            assert np.array_equal(got.view(np.uint64), want.view(np.uint64)), (n.modes, kind)
+            used = O.rounded(want, dtype)          # the one matrix every use of the map sees
+            assert np.array_equal(got.view(np.uint64), used.view(np.uint64)), (n.modes, kind)
             if dtype == "f32":
                 g32 = plan.read_drm(cid, kind, P.F32).cpu().numpy()
                 assert np.array_equal(g32.view(np.uint32), want.astype(np.float32).view(np.uint32))
@@ -79,8 +83,47 @@ def test_sketch_parity(P, case, variant, dtype):
     tree = O.Tree(spec, dims, r, p)
     sk = O.sketch(consumed, tree, O.DRMs(tree, 3, variant), variant)
     errs = sketch_errors(plan, tree, sk)
-    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    bad = failures(errs, TOL[dtype])
     assert not bad, bad
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_sketch_parity_rounded_drms(P, case, variant, dtype):
+    """Against the oracle fed the rounded DRMs the plan uses: what is left is the
+    arithmetic of the GPU path (exact products of FP32 / BF16 values, FP32 sums within a
+    chunk, FP64 across chunks and in every FP64 intermediate)."""
+    name, spec, dims, r, p = case
+    T = np.random.default_rng(5).standard_normal(dims)
+    dev, consumed = to_device(T, dtype)
+    plan = P.Plan(spec, dims, r, p, variant=variant, dtype=dtype, seed=3)
+    plan.update(dev)
+    tree = O.Tree(spec, dims, r, p)
+    sk = O.sketch(consumed, tree, O.DRMs(tree, 3, variant, dtype), variant)
+    bad = failures(sketch_errors(plan, tree, sk), TOL_ARITH[dtype])
+    assert not bad, bad
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+def test_bf16_exact_recovery(P, variant):
+    """Lemma 1 / exact recovery in BF16: a tensor of TTN rank <= 3 < r whose entries are
+    small integers (a sum of three outer products of {-1, 0, 1} vectors) is stored
+    exactly in BF16; with sketches accurate to FP32 accumulation and the pseudo-inverse
+    threshold at FP32 resolution, the cores reproduce it to that accuracy."""
+    dims = (40, 24, 20, 28)
+    g = np.random.default_rng(17)
+    T = np.zeros(dims)
+    for _ in range(3):
+        f = [g.integers(-1, 2, size=n).astype(np.float64) for n in dims]
+        T += np.einsum("a,b,c,d->abcd", *f)
+    dev, consumed = to_device(T, "bf16")
+    assert np.array_equal(consumed, T)
+    plan = P.Plan(O.T4, dims, 6, 3, variant=variant, dtype="bf16", seed=1, eps_factor=10 * 2.0 ** -23)
+    plan.update(dev)
+    cores = plan.assemble()
+    e2, n2 = P.diff_norms(plan.reconstruct(cores), torch.from_numpy(np.ascontiguousarray(W.flat_colmajor(T))).cuda())
+    assert np.sqrt(e2 / n2) < 1e-5, np.sqrt(e2 / n2)
 
 
 @pytest.mark.parametrize("case", CASES[:4], ids=[c[0] for c in CASES[:4]])
@@ -127,16 +170,36 @@ def test_config1_noisy_matches_oracle(P, variant, dtype):
     tree = O.Tree(O.T4, T.shape, 6, 3)
     sk = O.sketch(consumed, tree, O.DRMs(tree, 1, variant), variant)
     errs = sketch_errors(plan, tree, sk)
-    assert max(errs.values()) <= TOL[dtype], errs
+    assert not failures(errs, TOL[dtype]), errs
     cores = plan.assemble()
     ocores, _ = O.assemble(sk, tree)
     e_gpu = rel(plan.reconstruct(cores).cpu().numpy(), W.flat_colmajor(T))
     e_or = rel(W.flat_colmajor(O.reconstruct(ocores, tree)), W.flat_colmajor(T))
-    # FP32 sketches (FP32 products, FP32 accumulation within a chunk) sit within 1e-5 of
-    # the oracle's; the reconstruction error of this noisy tensor is itself of order
-    # 1e-5, so the two errors agree to the same order, not to a few percent
+    # FP32: the singular values of R~_t kept beyond the TTN rank (4 < r = 6) sit near
+    # 3e-7 sigma_1, a few units of FP32 resolution (2^-23), so FP32 sketch rounding moves
+    # them by O(1) and the error (set by those directions) by up to ~40% (relative
+    # perturbations of 1e-7..3e-7 of the oracle's own sketches move it by 8-42%).  The
+    # 1e-3-noise case below holds FP32 to 10%.
     rtol = 0.05 if dtype == "f64" else 0.5
     assert e_gpu < 1e-4 and abs(e_gpu - e_or) <= rtol * e_or + 1e-9
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+def test_f32_error_matches_f64_at_resolved_noise(P, variant):
+    """FP32 path vs FP64 oracle at equal final approximation error, within 10%, where the
+    directions that set the error lie far above FP32 resolution: the 16^4 TTN of rank 4
+    with relative noise 1e-3 (tail singular values ~1e-4 sigma_1, 10^3 x 2^-23)."""
+    T0 = W.config1_tensor(noise=False)
+    T = W.add_relative_noise(T0, 1e-3, seed=3)
+    dev, consumed = to_device(T, "f32")
+    plan = P.Plan(O.T4, T.shape, 6, 3, variant=variant, dtype="f32", seed=1)
+    plan.update(dev)
+    cores = plan.assemble()
+    tree = O.Tree(O.T4, T.shape, 6, 3)
+    ocores, _ = O.assemble(O.sketch(T, tree, O.DRMs(tree, 1, variant), variant), tree)
+    e_gpu = rel(plan.reconstruct(cores).cpu().numpy(), W.flat_colmajor(T))
+    e_or = rel(W.flat_colmajor(O.reconstruct(ocores, tree)), W.flat_colmajor(T))
+    assert abs(e_gpu - e_or) <= 0.1 * e_or, (e_gpu, e_or)
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])

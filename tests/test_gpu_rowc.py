@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import oracle as O
-from gpu_util import TOL, sketch_errors, to_device
+from gpu_util import TOL, failures, sketch_errors, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def test_row_contiguous_right_sketch(P, tensor, variant, dtype, r):
     sk = O.sketch(consumed, tree, O.DRMs(tree, 13, variant), variant)
     errs = sketch_errors(plan, tree, sk)
     plan.close()
-    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    bad = failures(errs, TOL[dtype])
     assert not bad, (bad, errs)
 
 
@@ -75,5 +75,5 @@ def test_few_rows_right_sketch(P, variant, dims, dtype):
     sk = O.sketch(consumed, tree, O.DRMs(tree, 29, variant), variant)
     errs = sketch_errors(plan, tree, sk)
     plan.close()
-    bad = {k: v for k, v in errs.items() if not v <= TOL[dtype]}
+    bad = failures(errs, TOL[dtype])
     assert not bad, (bad, errs)

@@ -1,7 +1,10 @@
 """GPU tests of the streaming / serving path, through the C ABI.
 
 * rank-1 updates: the sketches of a_1 o ... o a_d match the oracle's sketches of the
-  dense outer product (tolerances of the dtype);
+  dense outer product, the oracle fed the plan's (rounded) DRMs: the factors are FP64
+  and every product and sum is FP64, so FP64 accuracy is asked of every dtype (the
+  quantization of the maps themselves is not an error of the path; on these 2..9-wide
+  modes it alone moves BF16 sketches by a few percent from FP64-map sketches);
 * batched updates (ttnn_sketch_update_batched): bitwise equal to the same updates
   applied one by one, for plans of different sizes and boxes, with several updates
   of one plan in the same call;
@@ -16,7 +19,7 @@ import torch
 import oracle as O
 from workloads import serving as WS
 from workloads import synth as W
-from gpu_util import TOL, rel, sketch_errors, to_device
+from gpu_util import rel, failures, sketch_errors, to_device
 
 pytestmark = pytest.mark.gpu
 
@@ -62,9 +65,9 @@ def test_rank1_matches_oracle(P, case, variant, dtype):
     torch.cuda.synchronize()
     T = 0.75 * np.einsum(",".join("abcdefgh"[i] for i in range(len(dims))) + "->" + "abcdefgh"[:len(dims)], *f)
     tree = O.Tree(spec, dims, r, p)
-    sk = O.sketch(T, tree, O.DRMs(tree, 3, variant), variant)
+    sk = O.sketch(T, tree, O.DRMs(tree, 3, variant, dtype), variant)
     errs = sketch_errors(plan, tree, sk)
-    bad = {k: v for k, v in errs.items() if v > TOL[dtype]}
+    bad = failures(errs, 1e-10)
     assert not bad, bad
     plan.close()
 
@@ -86,7 +89,7 @@ def test_rank1_pairs_cancel_and_mix_with_boxes(P):
     tree = O.Tree(spec, dims, r, p)
     sk = O.sketch(T, tree, O.DRMs(tree, 2, "sttnn"), "sttnn")
     errs = sketch_errors(plan, tree, sk)
-    assert max(errs.values()) < 1e-10, errs
+    assert not failures(errs, 1e-10), errs
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
@@ -188,8 +191,9 @@ def test_serving_budget_admission_and_parity(P):
     assert st["p99_ms"] >= st["p50_ms"] > 0
     assert srv.used == 0 and not srv.streams
     assert len(srv.closed) == 5
-    # admission never exceeded the budget: at most the streams whose footprints fit
+    # admission in arrival order, and the admitted footprint never exceeded the budget
     assert srv.admit_order == list(range(5))
+    assert 0 < st["peak_used_bytes"] <= budget and srv.peak_used <= budget
     # final cores of every stream reconstruct its tensor like the oracle's cores do
     for s, (pr, T) in enumerate(zip(probs, tens)):
         tree = O.Tree(O.T4, pr["dims"], pr["r"], pr["p"])

@@ -1,19 +1,16 @@
 """Streamed updates at full size on the order-5 serving shape: 64^5 on
 (((1,2),3),(4,5)), r = 24, p = 12, FP32, delivered as the boxes of a random tiling of
 the tensor plus a cancelling pair of rank-1 terms (the sketches are linear, Sec. 4,
-so the sum of the update sketches is the sketch of the tensor).  Sampled entries of
-the node sketches are checked against the oracle's one-entry evaluator of the tensor
-(oracle.sampled) within the FP32 tolerance relative to the RMS entry of the GPU
-sketch.  The oracle regenerates a whole DRM column per sampled entry (16.7M rows for
-a leaf), so the samples are few: every internal node, and two leaves (TTNN) or one
-(STTNN)."""
+so the sum of the update sketches is the sketch of the tensor).  Every sketch the plan
+holds (R_t, Omega_t, Psi_t, root Psi) is compared element by element with the full
+oracle sketch of the tensor, the oracle fed the same FP32-rounded DRMs, at the
+arithmetic tolerance (FP32 tensor values, FP32 sums within a chunk, FP64 beyond)."""
 import numpy as np
 import pytest
 import torch
 
 import oracle as O
-from oracle.sampled import right_entry
-from gpu_util import TOL
+from gpu_util import TOL_ARITH, failures, sketch_errors
 from workloads import serving as WS
 from workloads import synth as W
 
@@ -47,9 +44,10 @@ def boxes_of(dev, offs_exts):
         yield off, ext, V[sl].contiguous().reshape(-1)
 
 
-@pytest.mark.parametrize("variant,leaves", [("ttnn", 2), ("sttnn", 1)])
-def test_stream64_sampled_parity(P, tensor, variant, leaves):
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+def test_stream64_parity(P, tensor, variant):
     dev, host = tensor
+    print(f"order-5 streamed parity {variant}", flush=True)
     tree = O.Tree(O.T5, DIMS, R, P_OVER)
     plan = P.Plan(O.T5, DIMS, R, P_OVER, variant=variant, dtype="f32", seed=SEED)
     g = W.rng(31)
@@ -59,20 +57,8 @@ def test_stream64_sampled_parity(P, tensor, variant, leaves):
     for fac, a in WS.rank1_pairs(DIMS, 1, seed=17):
         plan.update_rank1([torch.from_numpy(v).cuda() for v in fac], alpha=a)
     torch.cuda.synchronize()
-
-    internal = [n for n in tree.nodes[1:] if n.children]
-    leaf = [n for n in tree.nodes[1:] if not n.children]
-    picked = internal + [leaf[int(i)] for i in g.choice(len(leaf), leaves, replace=False)]
-    worst = {}
-    for n in picked:
-        Rg = plan.read_sketch(plan.node(n.modes), P.SK_R).cpu().numpy()
-        scale = np.sqrt(np.mean(Rg ** 2))
-        ext = [DIMS[m - 1] for m in n.modes]
-        j = int(g.integers(R))
-        im = [int(g.integers(e)) for e in ext]
-        i = int(np.ravel_multi_index(im, ext, order="F"))
-        want = right_entry(host, tree, SEED, variant, n.id, im, j)
-        worst[n.modes] = abs(Rg[i, j] - want) / scale
+    sk = O.sketch(host, tree, O.DRMs(tree, SEED, variant, "f32"), variant)
+    errs = sketch_errors(plan, tree, sk)
     plan.close()
-    bad = {k: v for k, v in worst.items() if not v <= TOL["f32"]}
-    assert not bad, (bad, worst)
+    bad = failures(errs, TOL_ARITH["f32"])
+    assert not bad, bad

@@ -135,3 +135,23 @@ def test_gaussian_counter_layout_and_transform_from_kat():
         z = float(R.gaussian(seed, node, kind, np.array([r], dtype=np.uint64), c2)[0])
         want = _box_muller_libm(v[6:10])
         assert abs(z - want) <= 4e-15 * max(1.0, abs(want)), (z, want)
+
+
+def test_c_evaluation_matches_numpy_definition_bitwise():
+    """oracle/cdrm.c (the fast path of oracle.drm.gaussian / drm) against the NumPy
+    definition, bit for bit: random indices including rows past 2^32, extreme seeds,
+    both map kinds, and a dense block."""
+    from oracle import cdrm
+    from oracle import drm as D
+    assert cdrm.lib() is not None, "oracle/_cdrm.so is built by tests/conftest.py"
+    g = np.random.default_rng(123)
+    rows = np.concatenate([g.integers(0, 2 ** 48, size=50000, dtype=np.uint64),
+                           np.array([0, 1, 2 ** 32 - 1, 2 ** 32, 2 ** 63], dtype=np.uint64)])
+    cols = g.integers(0, 2 ** 31, size=rows.size, dtype=np.uint64)
+    for seed, node, kind in [(0, 0, 0), (1, 5, 1), (0xFFFFFFFFFFFFFFFF, 63, 1), (0x1234_5678_9abc, 12, 0)]:
+        a = D.gaussian(seed, node, kind, rows, cols)
+        b = D.gaussian_numpy(seed, node, kind, rows, cols)
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64)), (seed, node, kind)
+    dense = D.drm(7, 3, 0, 300, 17)
+    ref = D.gaussian_numpy(7, 3, 0, np.arange(300, dtype=np.uint64)[:, None], np.arange(17, dtype=np.uint64)[None, :])
+    assert np.array_equal(dense.view(np.uint64), ref.view(np.uint64))

@@ -163,7 +163,7 @@ def test_theorem2_expected_bound():
     T = W.add_relative_noise(base, 0.05, seed=22)
     tree = O.Tree(spec, dims, 5, 3)
     errs = []
-    for s in range(40):
+    for s in range(200):
         D = O.DRMs(tree, 100 + s, "ttnn")
         cores, _ = O.assemble(O.sketch(T, tree, D, "ttnn"), tree)
         errs.append(np.linalg.norm(O.reconstruct(cores, tree) - T))

@@ -82,9 +82,11 @@ def test_admission_respects_budget_and_frees_memory():
     for s in range(4):
         for k in range(3):
             arr.append(S.Update(s, arrival=0.0, nbytes=10))
-    srv.run(arr)
+    st = srv.run(arr)
     assert eng.peak_live <= 100
+    assert st["peak_used_bytes"] == srv.peak_used <= 100 and srv.peak_used >= 60
     assert srv.admit_order == [0, 1, 2, 3]          # FIFO admission
+    assert st["wait_p99_ms"] >= 0 and st["gpu_p99_ms"] >= 0
     assert sorted(eng.assembled) == [0, 1, 2, 3]
     assert srv.used == 0 and not eng.live
     assert len(srv.completed) == 12
