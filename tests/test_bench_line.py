@@ -46,8 +46,8 @@ def _recorded():
              "ingest_GBps": 300.0} for r in range(2, 14)]
     hilbert = {"curves": {f"{v}:{d}": rows for v in ("ttnn", "sttnn") for d in ("f64", "f32")}}
     cpu = {"value": 0.0761234567, "unit": "GB/s", "cores": 16, "kind": "oracle",
-           "sample": "sttnn r=32 p=16: the 80^4 corner box of the 128^4 tensor as one streaming update (FP64 "
-                     "NumPy); value = box bytes / sketch time; reconstruct is full 128^4",
+           "sample": "whole workload: sttnn r=32 p=16 on the 128^4 tensor, FP64 NumPy (DRM entries in C); "
+                     "value = tensor bytes / sketch time; approximation error 0.00103",
            "phases_s": {"drm": 12.345, "sketch": 6.789, "assemble": 0.012, "reconstruct": 0.345},
            "cpu_model": "AMD EPYC 9575F 64-Core Processor with a long marketing name",
            "blas": "openblas 0.3.27 x16, openblas 0.3.27 x16"}

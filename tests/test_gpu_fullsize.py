@@ -64,3 +64,36 @@ def test_fullsize_parity(P, T, variant, dtype, r):
         bad = failures(errs, TOL_ARITH[dtype])
         assert not bad, bad
     plan.close()
+
+
+@pytest.fixture(scope="module")
+def T2():
+    """The 128^4 benchmark tensor: a TTN with edge ranks 24 and 0.8^k spectra, unit RMS
+    plus N(0, 1e-4^2) noise."""
+    from workloads import synth as W
+    return W.config2_tensor(n=128)
+
+
+@pytest.mark.parametrize("variant", ["sttnn", "ttnn"])
+@pytest.mark.parametrize("dtype", ["bf16", "f32"])
+def test_fullsize_error_matches_oracle_on_consumed_values(P, T2, variant, dtype):
+    """Approximation error of the benchmark tensor: the GPU path against the oracle run
+    on the same consumed (rounded) values with the same rounded DRMs, within 1%.  In
+    BF16 both sit near 1.4e-2: the storage rounding (1.7e-3 relative) acts as input
+    noise, which the method amplifies about ninefold on this tensor, as it does the
+    1e-4 noise of the FP64 workload (error 1.0e-3)."""
+    from workloads import synth as W
+    dev, consumed = to_device(T2, dtype)
+    plan = P.Plan(O.T4, DIMS, 32, 16, variant=variant, dtype=dtype, seed=SEED)
+    plan.update(dev)
+    cores = plan.assemble()
+    ref = torch.from_numpy(np.ascontiguousarray(W.flat_colmajor(T2))).cuda()
+    e2, n2 = P.diff_norms(plan.reconstruct(cores), ref)
+    e_gpu = float(np.sqrt(e2 / n2))
+    del ref, dev
+    _DEV.clear()
+    tree = O.Tree(O.T4, DIMS, 32, 16)
+    oc, _ = O.assemble(O.sketch(consumed, tree, O.DRMs(tree, SEED, variant, dtype), variant), tree)
+    e_or = float(np.linalg.norm(O.reconstruct(oc, tree) - T2) / np.linalg.norm(T2))
+    plan.close()
+    assert abs(e_gpu - e_or) <= 0.01 * e_or, (e_gpu, e_or)
