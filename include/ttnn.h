@@ -248,6 +248,16 @@ ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, voi
 ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n,
                             double* h_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): ttnn_diff_norms with its partial
+ * sums in a library-static device array (2 x 1024 doubles per device, 16 KB, the same
+ * for every n >= 0) instead of a fresh allocation, and without a host
+ * synchronisation: the two sums ||a - b||^2 and ||b||^2 go to d_out[0..1] (device
+ * memory) in stream order, bitwise equal to ttnn_diff_norms's.  Calls that overlap on
+ * one device (other streams or threads) share that array and race. */
+ttnn_status ttnn_diff_norms_noalloc(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n, double* d_out,
+                                    void* stream);
+
 /* Parity hooks. */
 ttnn_status ttnn_sketch_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows,
                               int64_t* cols);

@@ -348,6 +348,17 @@ ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b,
   });
 }
 
+ttnn_status ttnn_diff_norms_noalloc(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n, double* d_out,
+                                    void* stream) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!d_a || !d_b || !d_out || n < 0) throw Error{TTNN_E_INVALID, "bad argument"};
+    if (a_dtype != TTNN_F64 && a_dtype != TTNN_F32 && a_dtype != TTNN_BF16) throw Error{TTNN_E_INVALID, "bad dtype"};
+    ttnn::launch_diff_norms_static(d_a, a_dtype, d_b, n, d_out, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
 ttnn_status ttnn_sketch_shape(ttnn_plan_t plan, int32_t node, int32_t kind, int64_t* rows, int64_t* cols) {
   Plan* P = get(plan);
   return guard(nullptr, [&]() -> ttnn_status {

@@ -252,5 +252,9 @@ void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStr
 void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, double* d_part,
                        double* d_out, hipStream_t stream);
 constexpr int kNormBlocks = 1024;
+// The same two kernels with their 2 x kNormBlocks partials in a static device array
+// (no allocation); d_out: two doubles of device memory, written in stream order.
+void launch_diff_norms_static(const void* a, int a_dtype, const double* b, int64_t n, double* d_out,
+                              hipStream_t stream);
 
 }  // namespace ttnn

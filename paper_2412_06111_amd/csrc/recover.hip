@@ -10,6 +10,8 @@
 //   When ||R||_F ||R^{-1}||_F < 1/(2 eps_factor) no singular value can fall below
 //   eps, so R^{+eps} = R^{-1} is formed by back substitution and the SVD is skipped.
 // Also: deterministic squared-norm reductions used for error reporting.
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace ttnn {
@@ -506,6 +508,42 @@ void launch_diff_norms(const void* a, int a_dtype, const double* b, int64_t n, d
                        hipStream_t st) {
   hipLaunchKernelGGL(diff_norm_part, dim3(kNormBlocks), dim3(256), 0, st, a, a_dtype, b, n, d_part);
   hipLaunchKernelGGL(diff_norm_final, dim3(1), dim3(64), 0, st, d_part, kNormBlocks, d_out);
+}
+
+// ---------------------------------------------------------------- allocation-free form
+// The partial sums of the norms in a static device array, for callers that cannot
+// allocate.  Its size does not depend on n: every one of the kNormBlocks workgroups
+// writes its two partials before the final kernel reads them (nothing has to start
+// at zero).  Each device holds its own copy; calls that overlap on one device (other
+// streams, other threads) share it and race.
+namespace {
+constexpr int kStaticNormElems = 2 * kNormBlocks;
+__device__ __align__(256) double scratch[kStaticNormElems];
+
+// Device address of `scratch` on each device, looked up once per device with that
+// device current (host code must not use the symbol itself as a device pointer).
+double* static_norm_scratch() {
+  static std::mutex mu;
+  static double* addr[64] = {};
+  int dev = 0;
+  TTNN_HIP(hipGetDevice(&dev));
+  TTNN_REQUIRE(dev >= 0 && dev < 64, TTNN_E_INVALID, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    TTNN_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    TTNN_REQUIRE(p != nullptr, TTNN_E_HIP, "no device address for the static scratch");
+    addr[dev] = static_cast<double*>(p);
+  }
+  return addr[dev];
+}
+}  // namespace
+
+void launch_diff_norms_static(const void* a, int a_dtype, const double* b, int64_t n, double* d_out,
+                              hipStream_t st) {
+  static_assert(kStaticNormElems >= 2 * kNormBlocks, "the static scratch holds every partial");
+  double* part = static_norm_scratch();
+  launch_diff_norms(a, a_dtype, b, n, part, d_out, st);
 }
 
 }  // namespace ttnn
