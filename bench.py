@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--no-error", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--single-n", type=int, default=64, help="mode size of the single-stream serving run")
+    ap.add_argument("--config4-tilings", type=int, default=1,
+                    help="two-piece tilings of the single-stream run (32 boxes each); 112 in the full recipe")
+    ap.add_argument("--config4-pairs", type=int, default=256, help="cancelling rank-1 pairs of the single-stream run")
     ap.add_argument("--serve-streams", type=int, default=64)
     ap.add_argument("--serve-nmax", type=int, default=160)
     ap.add_argument("--no-hilbert", action="store_true", help="skip the 6-D Hilbert accuracy curves")
@@ -60,7 +63,8 @@ def parse():
     ap.add_argument("--detail", default="bench_detail.json",
                     help="file for the full per-configuration, serving and Hilbert results ('' = none)")
     ap.add_argument("--serve-load", type=float, default=0.8,
-                    help="Poisson rate as a fraction of the batched path's closed-loop rate")
+                    help="the Poisson load (a fraction of the batched path's closed-loop rate) summarised in the record")
+    ap.add_argument("--serve-loads", default="0.25,0.5,0.8", help="Poisson loads run (fractions of the closed-loop rate)")
     return ap.parse_args()
 
 
@@ -423,6 +427,15 @@ def serving_bench(args):
         st["mean_batch"] = float(np.mean(srv.batches)) if srv.batches else 0.0
         st["approx_rel_error_median"] = float(np.median(list(errs.values())))
         st["approx_rel_error_max"] = float(np.max(list(errs.values())))
+        # streams whose sketch rank is below a TTN edge rank cannot capture their tensor:
+        # their errors are reported apart
+        low = [s for s in errs if probs[s]["r"] < max(probs[s]["ttn_ranks"].values())]
+        ok = [s for s in errs if s not in low]
+        st["streams_r_below_ttn_rank"] = len(low)
+        if ok:
+            st["approx_rel_error_max_r_at_least_ttn_rank"] = float(max(errs[s] for s in ok))
+        if low:
+            st["approx_rel_error_median_r_below_ttn_rank"] = float(np.median([errs[s] for s in low]))
         return st
 
     out = {"streams": len(probs), "updates": n_updates,
@@ -433,83 +446,86 @@ def serving_bench(args):
     closed = one_run("f32", 64, 0.0, per32)
     out["batched_f32_closed_loop"] = closed
     _brief("batched f32 closed loop", closed)
-    rate = args.serve_load * closed["updates_per_s"]
-    out["poisson_rate_per_s"] = rate
-    out["batched_f32_poisson"] = one_run("f32", 64, rate, per32)
-    _brief("batched f32 poisson", out['batched_f32_poisson'])
-    del per32
     per64 = make_updates("f64")
     out["fp64_one_per_launch_closed_loop"] = one_run("f64", 1, 0.0, per64)
-    _brief("fp64 closed loop", out['fp64_one_per_launch_closed_loop'])
-    out["fp64_one_per_launch_poisson"] = one_run("f64", 1, rate, per64)
-    _brief("fp64 poisson", out['fp64_one_per_launch_poisson'])
+    _brief("fp64 closed loop", out["fp64_one_per_launch_closed_loop"])
+    # Poisson arrivals at fractions of the batched path's closed-loop rate, both paths on
+    # the same arrival trace
+    out["poisson"] = {}
+    for load in [float(x) for x in args.serve_loads.split(",") if x]:
+        rate = load * closed["updates_per_s"]
+        b = one_run("f32", 64, rate, per32)
+        f = one_run("f64", 1, rate, per64)
+        out["poisson"][f"{load:g}"] = {"rate_per_s": rate, "batched_f32": b, "fp64_one_per_launch": f}
+        _brief(f"batched f32 poisson {load:g}", b)
+        _brief(f"fp64 poisson {load:g}", f)
+    hi = out["poisson"].get(f"{args.serve_load:g}")
+    if hi:
+        out["poisson_rate_per_s"] = hi["rate_per_s"]
+        out["batched_f32_poisson"] = hi["batched_f32"]
+        out["fp64_one_per_launch_poisson"] = hi["fp64_one_per_launch"]
     del per64, tens
     torch.cuda.empty_cache()
     return out
 
 
 def serving_single(args):
-    """Single stream of the order-5 serving shape: n^5 (n = 64) on (((1,2),3),(4,5)), a
-    random TTN with edge ranks 16 + 1e-5 noise, TTNN, r = 24, p = 12, FP32.  The tensor
-    arrives as the boxes of a random tiling (segments of 8..16 per mode) plus 8 cancelling
-    pairs of rank-1 terms, in a random order, and the cores are assembled (enqueued) every
-    256 updates; payloads are resident in HBM before the clock starts.  Per-update time
-    on the stream from HIP events before and after each update (p50 / p99), wall time and
-    ingest rate (payload bytes / wall), approximation error of the final cores."""
+    """Single stream of the order-5 serving workload through the batching server: the
+    64^5 FP32 TTN on (((1,2),3),(4,5)) with every edge rank 16 (N(0,1) cores, seeded,
+    unit RMS), r = 24, p = 12, TTNN.  Updates: the 32 boxes of each of `config4_tilings`
+    two-piece tilings (one cut per mode at U{8..56}), each the resident tensor over the
+    box read in place (strided) with alpha = 1 / tilings, plus `config4_pairs` cancelling
+    pairs of rank-1 terms with N(0,1) factors; all in a random order, submitted at once
+    (closed loop); cores enqueued every 256 updates.  Per update: the device time of its
+    launch (p50 / p99, overall and by kind); ingest rate (payload bytes: box entries
+    read and rank-1 factor bytes, over wall time); approximation error of the final
+    cores against the tensor (the pairs cancel, the tilings sum to it)."""
     import numpy as np
     import torch
     import paper_2412_06111_amd as P
+    from paper_2412_06111_amd import serve as S
     from workloads import serving as WS
 
     n = args.single_n
     dims = (n,) * 5
-    T64 = WS.order5_tensor_device(n=n, rank=16, seed=2024, noise=1e-5)
+    T64 = WS.order5_tensor_device(n=n, rank=16, seed=0, noise=0.0)
     X = T64.to(torch.float32)
     V = X.view(*dims[::-1])                                   # [i5, .., i1]
-    g = WS.rng(41)
+    k = args.config4_tilings
     ups = []
-    for off, ext in WS.boxes(dims, g, lo=8, hi=16):
-        sl = tuple(slice(o, o + e) for o, e in zip(off[::-1], ext[::-1]))
-        ups.append(("box", V[sl].contiguous().reshape(-1), off, ext, 1.0))
-    for fac, a in WS.rank1_pairs(dims, 8, seed=43):
-        ups.append(("rank1", [torch.from_numpy(v).cuda() for v in fac], None, None, a))
-    ups = [ups[i] for i in g.permutation(len(ups))]
-    del X, V
-    payload = sum(u[1].numel() * 4 if u[0] == "box" else sum(f.numel() * 8 for f in u[1]) for u in ups)
-    plan = P.Plan(WS.T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=7)
-    cores = plan.alloc_cores()
-    st = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in ups]
-    every = 256
-    torch.cuda.synchronize()
-    tic = time.perf_counter()
-    for i, u in enumerate(ups):
-        ev[i][0].record(st)
-        if u[0] == "box":
-            plan.update(u[1], extent=u[3], offset=u[2])
-        else:
-            plan.update_rank1(u[1], alpha=u[4])
-        ev[i][1].record(st)
-        if (i + 1) % every == 0:
-            plan.assemble_async(cores)
-    plan.assemble_async(cores)
-    plan.assemble_status()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - tic
-    ms = np.array([a.elapsed_time(b) for a, b in ev])
-    That = plan.reconstruct(cores)
-    e2, n2 = P.diff_norms(That, T64)
-    del That
-    plan.close()
-    boxes = sum(1 for u in ups if u[0] == "box")
-    out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTN ranks 16 + 1e-5 noise, TTNN, r=24, p=12, FP32; "
-                       f"{boxes} tiling boxes (8..16 per mode) + {len(ups) - boxes} rank-1 terms in random order, "
-                       f"cores every {every} updates",
-           "updates": len(ups), "wall_s": wall, "updates_per_s": len(ups) / wall,
-           "ingest_GBps": payload / wall / 1e9, "update_p50_ms": float(np.percentile(ms, 50)),
-           "update_p99_ms": float(np.percentile(ms, 99)), "assemblies": (len(ups) + every - 1) // every,
-           "approx_rel_error": (e2 / n2) ** 0.5}
-    del ups, T64
+    for off, ext in WS.cut_tilings(dims, k, seed=3, lo=8, hi=56):
+        view = V[tuple(slice(o, o + e) for o, e in zip(off[::-1], ext[::-1]))]
+        nb = int(np.prod(ext)) * 4
+        ups.append(S.Update(0, "box", block=view, offset=off, extent=ext, alpha=1.0 / k, nbytes=nb))
+    for fac, a in WS.rank1_pairs(dims, args.config4_pairs, seed=43):
+        f = [torch.from_numpy(v).cuda() for v in fac]
+        ups.append(S.Update(0, "rank1", factors=f, alpha=a, nbytes=sum(v.size * 8 for v in fac)))
+    order = WS.rng(1).permutation(len(ups))
+    ups = [ups[i] for i in order]
+    for u in ups:
+        u.arrival = 0.0
+    spec = S.StreamSpec(WS.T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=7)
+    final = {}
+
+    def on_close(sid, plan, cores):
+        That = plan.reconstruct(cores)
+        final["err"] = P.diff_norms(That, T64)
+        del That
+
+    srv = S.Server(budget_bytes=1 << 40, max_batch=1, max_inflight=2, assemble_every=256, on_close=on_close)
+    srv.open_stream(0, spec)
+    st = srv.run(ups)
+    e2, n2 = final["err"]
+    boxes = sum(1 for u in ups if u.kind == "box")
+    keep = ("updates", "wall_s", "updates_per_s", "ingest_GBps", "device_p50_ms", "device_p99_ms",
+            "box_device_p50_ms", "box_device_p99_ms", "rank1_device_p50_ms", "rank1_device_p99_ms",
+            "plan_create_ms_max")
+    out = {"workload": f"{n}^5 FP32 TTN (edge ranks 16) on (((1,2),3),(4,5)), TTNN, r=24, p=12; {boxes} boxes of "
+                       f"{k} two-piece tilings (8..56 per mode, read in place, alpha 1/{k}) + {len(ups) - boxes} "
+                       "rank-1 terms (cancelling pairs), random order, cores every 256 updates, via the server",
+           **{f: st[f] for f in keep if f in st}, "approx_rel_error": (e2 / n2) ** 0.5}
+    out["update_p50_ms"], out["update_p99_ms"] = out.get("device_p50_ms"), out.get("device_p99_ms")
+    del ups, X, V, T64
     torch.cuda.empty_cache()
     return out
 
@@ -636,7 +652,8 @@ def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=
             s = serving.get(name)
             if s:
                 sv[name] = {f: float(f"{s[f]:.4g}") for f in ("updates_per_s", "ingest_GBps", "p50_ms", "p99_ms",
-                                                               "update_p50_ms", "update_p99_ms") if f in s}
+                                                               "box_device_p99_ms", "rank1_device_p99_ms",
+                                                               "approx_rel_error") if f in s}
         line["serving"] = sv
     if hilbert is not None:
         line["hilbert_6d"] = {c: f"r{rows[-1]['rank']} err {rows[-1]['mean_rel_error']:.2g}"

@@ -13,7 +13,6 @@ namespace ttnn {
 namespace {
 
 constexpr int kThreadsR = 256;
-constexpr int kColsPerPass = 64;
 
 __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   double w = 1.0;
@@ -26,42 +25,121 @@ __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   return w;
 }
 
-// partial[b][j] = sum over rows of block b of D[row * ncols + j] * weight(row)
-template <typename TD>
+// the same with 32-bit index arithmetic (rows below 2^32)
+__device__ inline double kron_weight32(const KronVec& kv, uint32_t row) {
+  double w = 1.0;
+  for (int p = 0; p < kv.n; ++p) {
+    const uint32_t e = static_cast<uint32_t>(kv.len[p]);
+    const uint32_t q = row / e;
+    w *= kv.v[p][row - q * e];
+    row = q;
+  }
+  return w;
+}
+
+// partial[b][j] = sum over the rows of block b of D[row * ncols + j] * weight(row).  The
+// block's rows are contiguous in D: each step copies RB of them into LDS with coalesced
+// loads (consecutive threads, consecutive elements; rows padded by one element against
+// bank conflicts), then one lane per row forms the row's weight once and accumulates
+// its ncols products in FP64 (NC >= ncols accumulators a lane); a fixed-order reduction
+// over the lanes (shuffles, then the waves in order) ends the block.
+template <typename TD, int NC>
 __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restrict__ D, int64_t rows, int ncols,
-                                                              KronVec kv, int64_t rows_per_block,
+                                                              KronVec kv, int64_t rows_per_block, bool small,
                                                               double* __restrict__ partial) {
-  __shared__ double red[kThreadsR];
-  const int tid = threadIdx.x;
-  const int jl = tid % kColsPerPass, rl = tid / kColsPerPass;       // 4 row lanes x 64 columns
-  constexpr int RL = kThreadsR / kColsPerPass;
+  constexpr int RB = sizeof(TD) == 8 ? kThreadsR / 2 : kThreadsR;     // rows a step (LDS <= 66 KB)
+  __shared__ TD tile[RB * (NC + 1)];
+  __shared__ double red[kThreadsR / 64][NC];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
-  for (int j0 = 0; j0 < ncols; j0 += kColsPerPass) {
-    const int j = j0 + jl;
-    double acc = 0.0;
-    if (j < ncols)
-      for (int64_t row = r0 + rl; row < r1; row += RL)
-        acc = fma(to_f64(D[row * ncols + j]), kron_weight(kv, row), acc);
-    red[tid] = acc;
-    __syncthreads();
-    if (rl == 0 && j < ncols) {
-      double s = red[jl];
+  const int ld = ncols + 1;
+  const int dr = kThreadsR / ncols, dc = kThreadsR % ncols;            // a thread's stride in (row, col)
+  double acc[NC];
 #pragma unroll
-      for (int q = 1; q < RL; ++q) s += red[q * kColsPerPass + jl];
-      partial[static_cast<int64_t>(blockIdx.x) * ncols + j] = s;
+  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  // a step's elements: at most RB * NC, i.e. NC * (RB / kThreadsR) per thread
+  constexpr int PER = NC * RB / kThreadsR;
+  TD v[PER];
+  auto fetch = [&](int64_t b) {            // the step's loads, all in flight together
+    const int64_t nr = r1 - b < RB ? r1 - b : RB;
+    const int total = static_cast<int>(nr) * ncols;
+    const TD* src = D + b * ncols;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = tid + k * kThreadsR;
+      v[k] = e < total ? src[e] : TD(0);
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (int64_t base = r0; base < r1; base += RB) {
+    const int nr = static_cast<int>(r1 - base < RB ? r1 - base : RB);
+    const int total = nr * ncols;
+    int rr = tid / ncols, cc = tid % ncols;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      if (tid + k * kThreadsR < total) tile[rr * ld + cc] = v[k];
+      rr += dr;
+      cc += dc;
+      if (cc >= ncols) {
+        cc -= ncols;
+        ++rr;
+      }
+    }
+    __syncthreads();
+    if (base + RB < r1) fetch(base + RB);  // next step's loads overlap this step's products
+    if (tid < nr) {
+      const int64_t row = base + tid;
+      const double w = small ? kron_weight32(kv, static_cast<uint32_t>(row)) : kron_weight(kv, row);
+      const TD* p = tile + tid * ld;
+#pragma unroll
+      for (int j = 0; j < NC; ++j)
+        if (j < ncols) acc[j] += to_f64(p[j]) * w;
     }
     __syncthreads();
   }
+#pragma unroll
+  for (int j = 0; j < NC; ++j) {
+    double x = acc[j];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == 0) red[wave][j] = x;
+  }
+  __syncthreads();
+  if (tid < ncols) {
+    double s = red[0][tid];
+#pragma unroll
+    for (int q = 1; q < kThreadsR / 64; ++q) s += red[q][tid];
+    partial[static_cast<int64_t>(blockIdx.x) * ncols + tid] = s;
+  }
 }
 
-// w[j] = sum_b partial[b][j], blocks in order
-__global__ void sum_blocks_kernel(const double* __restrict__ partial, int nb, int ncols, double* __restrict__ w) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= ncols) return;
+template <typename TD>
+void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, bool small, dim3 grid,
+                    double* partial, hipStream_t st) {
+  if (ncols <= 8)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 8>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small, partial);
+  else if (ncols <= 16)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 16>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
+                       partial);
+  else if (ncols <= 32)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 32>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
+                       partial);
+  else
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 64>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
+                       partial);
+}
+
+// w[j] = sum_b partial[b][j]: one wave per column, lane l summing blocks l, l + 64, ..
+// in order, the 64 sums combined by a fixed butterfly
+__global__ __launch_bounds__(64) void sum_blocks_kernel(const double* __restrict__ partial, int nb, int ncols,
+                                                        double* __restrict__ w) {
+  const int j = blockIdx.x, l = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += partial[static_cast<int64_t>(b) * ncols + j];
-  w[j] = s;
+  for (int b = l; b < nb; b += 64) s += partial[static_cast<int64_t>(b) * ncols + j];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (l == 0) w[j] = s;
 }
 
 // R[i + n j] += alpha * weight(i) * (w ? w[j] : 1)
@@ -82,7 +160,8 @@ __global__ void outer_acc_kernel(double* __restrict__ R, int64_t n, int ncols, K
 void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronVec& kv, double* partial,
                       size_t partial_elems, double* w, hipStream_t st) {
   if (ncols <= 0) return;
-  int64_t nb = (rows + 4095) / 4096;                   // ~4096 rows per block
+  TTNN_REQUIRE(ncols <= 64, TTNN_E_INVALID, "rank-1 update with more than 64 map columns");
+  int64_t nb = (rows + 511) / 512;                     // >= 512 rows a block, at most 2048 blocks
   if (nb < 1) nb = 1;
   if (nb > 2048) nb = 2048;
   const int64_t cap = static_cast<int64_t>(partial_elems / static_cast<size_t>(ncols));
@@ -92,17 +171,15 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
   nb = rows > 0 ? (rows + per - 1) / per : 1;
   const dim3 grid(static_cast<unsigned>(nb));
   const int64_t pr = per > 0 ? per : 1;
+  bool small = rows < (int64_t(1) << 32);
+  for (int p = 0; p < kv.n; ++p) small = small && kv.len[p] < (int64_t(1) << 32);
   if (dt == TTNN_F64)
-    hipLaunchKernelGGL(kron_gemv_kernel<double>, grid, dim3(kThreadsR), 0, st, static_cast<const double*>(D), rows,
-                       ncols, kv, pr, partial);
+    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kv, pr, small, grid, partial, st);
   else if (dt == TTNN_F32)
-    hipLaunchKernelGGL(kron_gemv_kernel<float>, grid, dim3(kThreadsR), 0, st, static_cast<const float*>(D), rows,
-                       ncols, kv, pr, partial);
+    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kv, pr, small, grid, partial, st);
   else
-    hipLaunchKernelGGL(kron_gemv_kernel<uint16_t>, grid, dim3(kThreadsR), 0, st, static_cast<const uint16_t*>(D),
-                       rows, ncols, kv, pr, partial);
-  hipLaunchKernelGGL(sum_blocks_kernel, dim3((ncols + 63) / 64), dim3(64), 0, st, partial, static_cast<int>(nb), ncols,
-                     w);
+    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kv, pr, small, grid, partial, st);
+  hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols), dim3(64), 0, st, partial, static_cast<int>(nb), ncols, w);
 }
 
 void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const double* w, double alpha,

@@ -40,7 +40,7 @@ class Update:
     `extent`; kind 'rank1': `factors` (one FP64 device vector per mode)."""
 
     __slots__ = ("sid", "kind", "block", "offset", "extent", "factors", "alpha", "arrival", "nbytes",
-                 "t_done", "t_launch", "batch")
+                 "t_done", "t_launch", "t_gpu", "batch")
 
     def __init__(self, sid, kind="box", block=None, offset=None, extent=None, factors=None, alpha=1.0,
                  arrival=0.0, nbytes=0):
@@ -48,6 +48,7 @@ class Update:
         self.factors, self.alpha, self.arrival, self.nbytes = factors, alpha, arrival, nbytes
         self.t_done = None
         self.t_launch = None                    # host time its batch was launched
+        self.t_gpu = None                       # device time of its batch (s)
         self.batch = None
 
 
@@ -165,7 +166,7 @@ class Server:
         self.streams = {}
         self.waiting = collections.deque()      # sids not yet admitted, arrival order
         self.admit_order = []
-        self.inflight = collections.deque()     # (event, [updates], [sids])
+        self.inflight = collections.deque()     # (event, [updates], [sids], event before launch)
         self.completed = []
         self.batches = []                       # sizes of launched batches
         self.closed = {}                        # sid -> cores of finished streams
@@ -274,27 +275,30 @@ class Server:
         t_launch = self.now()
         for u in ups:
             u.t_launch = t_launch
+        ev0 = self.engine.event()               # the batch's device span: ev0 .. ev
         self.engine.launch(items)
         for st in chosen:
             st.n_done += 1
             if self.assemble_every and st.n_done % self.assemble_every == 0:
                 st.cores = self.engine.assemble_async(st.plan)
         ev = self.engine.event()
-        self.inflight.append((ev, ups, [st.sid for st in chosen]))
+        self.inflight.append((ev, ups, [st.sid for st in chosen], ev0))
         self.batches.append(len(ups))
         return len(ups)
 
     def poll(self, block=False):
         while self.inflight:
-            ev, ups, sids = self.inflight[0]
+            ev, ups, sids, ev0 = self.inflight[0]
             if block:
                 self.engine.wait(ev)
             elif not self.engine.done(ev):
                 break
             self.inflight.popleft()
             t = self.engine.elapsed_ms(self._ref, ev) * 1e-3      # seconds on the server clock
+            t_gpu = self.engine.elapsed_ms(ev0, ev) * 1e-3
             for u in ups:
                 u.t_done = t
+                u.t_gpu = t_gpu
                 self.completed.append(u)
             for sid in sids:
                 if sid in self.streams:
@@ -370,9 +374,19 @@ def stats(completed, wall_s):
         gpu = [(u.t_done - u.t_launch) * 1e3 for u in timed]
         out["wait_p50_ms"], out["wait_p99_ms"] = float(np.percentile(wait, 50)), float(np.percentile(wait, 99))
         out["gpu_p50_ms"], out["gpu_p99_ms"] = float(np.percentile(gpu, 50)), float(np.percentile(gpu, 99))
+    # device time of the batch that carried each update (from an event before its launch
+    # to one after it: the batch's own span on the stream)
+    dev = [u.t_gpu * 1e3 for u in completed if u.t_gpu is not None]
+    if dev:
+        out["device_p50_ms"], out["device_p99_ms"] = float(np.percentile(dev, 50)), float(np.percentile(dev, 99))
     for kind in ("box", "rank1"):
         lk = [(u.t_done - u.arrival) * 1e3 for u in completed if u.kind == kind]
         if lk:
             out[f"{kind}_p50_ms"] = float(np.percentile(lk, 50))
             out[f"{kind}_p99_ms"] = float(np.percentile(lk, 99))
+        dk = [u.t_gpu * 1e3 for u in completed if u.kind == kind and u.t_gpu is not None]
+        if dk:
+            out[f"{kind}_device_p50_ms"] = float(np.percentile(dk, 50))
+            out[f"{kind}_device_p99_ms"] = float(np.percentile(dk, 99))
+            out[f"{kind}_updates"] = len(dk)
     return out

@@ -126,6 +126,21 @@ def box_updates(T, prob, lo=4, hi=48):
     return out
 
 
+def cut_tilings(dims, ntilings, seed, lo=8, hi=56):
+    """The boxes of `ntilings` independent two-piece tilings: in each tiling every mode
+    is cut once at c ~ U{lo..hi} (pieces [0, c) and [c, n)), which gives 2^d boxes with
+    extents in [lo, hi] when n - hi >= lo.  Returns (offset, extent) per box."""
+    g = rng(seed)
+    out = []
+    for _ in range(ntilings):
+        cuts = [int(g.integers(lo, hi + 1)) for _ in dims]
+        segs = [((0, c), (c, n - c)) for c, n in zip(cuts, dims)]
+        for idx in np.ndindex(*([2] * len(dims))):
+            out.append((tuple(segs[m][i][0] for m, i in enumerate(idx)),
+                        tuple(segs[m][i][1] for m, i in enumerate(idx))))
+    return out
+
+
 def rank1_pairs(dims, npairs, seed):
     """npairs cancelling pairs (factors, +1) and (factors, -1), factors N(0,1)."""
     g = rng(seed)
