@@ -7,6 +7,7 @@
 //   Psi_0 at the root               (T contracted with Y_c^T over every child c)
 // Omega_t = Y_t^T R_t and Psi_t = (kron_c Y_c^T) R_t are formed on demand.
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -15,6 +16,11 @@
 #include "kernels.hpp"
 
 namespace ttnn {
+
+// d_flag: [0] non-finite count, [1, nn) kept singular values per node, then the call
+// and sticky status words at the end of the array
+constexpr int kCallWord = 2 * TTNN_MAX_NODES - 2, kStickyWord = 2 * TTNN_MAX_NODES - 1;
+
 namespace {
 
 // one index position of an operand during a contraction chain
@@ -463,6 +469,18 @@ void run_box_ops_batched(const std::vector<Plan*>& plans, const std::vector<cons
     level_end.push_back(gl.size());
     rl.push_back(plan_reduce_batched(reds));
   }
+  // TTNN_PERSISTENT=1: the whole round as one persistent cooperative launch.  Measured
+  // slower than one launch per level and kind (a grid barrier's device-scope fences,
+  // one a workgroup, write back and invalidate each XCD's L2: ~0.1 ms a barrier), so it
+  // is not the default; the results are bitwise the same either way.
+  const char* pe = std::getenv("TTNN_PERSISTENT");
+  if (pe && pe[0] == '1' && !plans.empty()) {
+    std::vector<int*> sticky;
+    for (Plan* P : plans)
+      if (std::find(sticky.begin(), sticky.end(), P->d_flag + kStickyWord) == sticky.end())
+        sticky.push_back(P->d_flag + kStickyWord);
+    if (launch_ingest(plans[0]->dtype, gl, level_end, rl, sticky, st)) return;
+  }
   constexpr size_t kAlignD = 64;
   auto aligned = [](size_t x) { return (x + kAlignD - 1) / kAlignD * kAlignD; };
   std::vector<size_t> og(gl.size()), of(rl.size()), orr(rl.size());
@@ -766,9 +784,6 @@ std::vector<int64_t> core_shape(const Plan& P, int v) {
 }
 
 // ---------------------------------------------------------------- recovery phase
-// d_flag: [0] non-finite count, [1, nn) kept singular values per node, then the call
-// and sticky status words at the end of the array
-constexpr int kCallWord = 2 * TTNN_MAX_NODES - 2, kStickyWord = 2 * TTNN_MAX_NODES - 1;
 
 void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   if (!P.epilogue_valid) run_epilogue(P, st);

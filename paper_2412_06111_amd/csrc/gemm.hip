@@ -10,6 +10,10 @@
 // second kernel sums in a fixed order, so the result does not depend on timing.
 // This path is the reference engine for arbitrary shapes; the fused kernels for
 // the large dense trees live in separate files.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -273,9 +277,8 @@ __global__ __launch_bounds__(256) void hm_gemm(const TH* __restrict__ H, int64_t
 // Copy a descriptor from global memory into LDS (8-byte words) after locating, by
 // binary search on first_block, the task that owns this workgroup.
 template <typename Task>
-__device__ inline int64_t load_task(const Task* __restrict__ tasks, int ntasks, Task* t) {
+__device__ inline int64_t load_task(const Task* __restrict__ tasks, int ntasks, Task* t, int64_t b) {
   __shared__ int idx;
-  const int64_t b = blockIdx.x;
   if (threadIdx.x == 0) {
     int lo = 0, hi = ntasks - 1;
     while (lo < hi) {
@@ -296,11 +299,12 @@ __device__ inline int64_t load_task(const Task* __restrict__ tasks, int ntasks, 
 
 // Every workgroup serves one tile of one task; tasks of one launch may belong to
 // different updates (of different plans) and have different sizes.
+// Tile b of a batched contraction launch (its task found by binary search).
 template <bool RIGHT, typename TH, typename TD, typename TO>
-__global__ __launch_bounds__(256) void hm_gemm_batched(const GemmTask* __restrict__ tasks, int ntasks) {
+__device__ __forceinline__ void gemm_task_tile(const GemmTask* __restrict__ tasks, int ntasks, int64_t b) {
   __shared__ __align__(16) char tbuf[sizeof(GemmTask)];      // raw storage: IndexMap has initialisers
   GemmTask& t = *reinterpret_cast<GemmTask*>(tbuf);
-  int64_t rel = load_task(tasks, ntasks, &t);
+  int64_t rel = load_task(tasks, ntasks, &t, b);
   const int64_t rb = rel % t.row_blocks;
   rel /= t.row_blocks;
   const int64_t c = rel % t.nch;
@@ -308,6 +312,11 @@ __global__ __launch_bounds__(256) void hm_gemm_batched(const GemmTask* __restric
   gemm_tile<RIGHT, TH, TD, TO>(static_cast<const TH*>(t.H), t.L, t.n, t.Q, static_cast<const TD*>(t.D), t.sDr,
                                t.sDc, t.ncols, t.amap, t.bmap, t.hm, t.kchunk, static_cast<TO*>(t.out), t.ol,
                                rb * BR, c, cb * BJ);
+}
+
+template <bool RIGHT, typename TH, typename TD, typename TO>
+__global__ __launch_bounds__(256) void hm_gemm_batched(const GemmTask* __restrict__ tasks, int ntasks) {
+  gemm_task_tile<RIGHT, TH, TD, TO>(tasks, ntasks, static_cast<int64_t>(blockIdx.x));
 }
 
 template <bool RIGHT, typename TH, typename TD>
@@ -385,22 +394,26 @@ __device__ inline void reduce_range(const double* __restrict__ part, int nchunks
   }
 }
 
-__global__ __launch_bounds__(256) void reduce_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+__device__ __forceinline__ void reduce_task_tile(const ReduceTask* __restrict__ tasks, int ntasks, int64_t b) {
   __shared__ __align__(16) char tbuf[sizeof(ReduceTask)];
   ReduceTask& t = *reinterpret_cast<ReduceTask*>(tbuf);
-  const int64_t rel = load_task(tasks, ntasks, &t);
+  const int64_t rel = load_task(tasks, ntasks, &t, b);
   reduce_range(t.part, t.nchunks, t.rows, t.ncols, t.mode, t.alpha, t.rmap, t.ldr, t.dst, t.L, t.kdim,
                rel * 256 + threadIdx.x, t.nblocks * 256, t.cstride ? t.cstride : t.rows * t.ncols);
+}
+
+__global__ __launch_bounds__(256) void reduce_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+  reduce_task_tile(tasks, ntasks, static_cast<int64_t>(blockIdx.x));
 }
 
 constexpr int kFold = 32;
 
 // Fold groups of kFold consecutive chunks into each group's first slot (see
 // fold_chunks_kernel); workgroup -> (task, element block, group).
-__global__ __launch_bounds__(256) void fold_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+__device__ __forceinline__ void fold_task_tile(const ReduceTask* __restrict__ tasks, int ntasks, int64_t b) {
   __shared__ __align__(16) char tbuf[sizeof(ReduceTask)];
   ReduceTask& t = *reinterpret_cast<ReduceTask*>(tbuf);
-  const int64_t rel = load_task(tasks, ntasks, &t);
+  const int64_t rel = load_task(tasks, ntasks, &t, b);
   const int64_t E = t.rows * t.ncols;
   const int64_t eblocks = (E + 255) / 256;
   const int64_t e = (rel % eblocks) * 256 + threadIdx.x;
@@ -410,6 +423,99 @@ __global__ __launch_bounds__(256) void fold_batched_kernel(const ReduceTask* __r
   double s = 0.0;
   for (int c = c0; c < c1; ++c) s += t.part[c * E + e];
   t.part[c0 * E + e] = s;
+}
+
+__global__ __launch_bounds__(256) void fold_batched_kernel(const ReduceTask* __restrict__ tasks, int ntasks) {
+  fold_task_tile(tasks, ntasks, static_cast<int64_t>(blockIdx.x));
+}
+
+// ---------------------------------------------------------------- persistent ingest
+// One launch for a whole batched round of box updates: the workgroups sweep, phase by
+// phase, every tile of every task list of the round (a level's contractions of all
+// kinds, then its chunk folds, then its reductions, level after level) and meet at a
+// grid-wide barrier between phases.  The tiles are those of the per-level launches, so
+// results are bitwise the same.  Launched cooperatively (every workgroup resident), so
+// each barrier ends; the wait is still bounded, and a wait that ran out marks the
+// round's plans (their sticky numerical status).
+struct IngestSeg {
+  int64_t tasks;        // byte offset of the task table from the program
+  int64_t blocks;
+  int32_t kind, ntasks;
+};
+struct IngestPhase {
+  IngestSeg seg[kIngestSegs];
+  int32_t nseg, pad_;
+};
+struct IngestProgram {
+  uint32_t counter;     // barrier arrivals (zero as staged)
+  int32_t nphases, nsticky, pad_;
+  int* sticky[kIngestPlans];
+  IngestPhase ph[kIngestPhases];
+};
+
+__device__ inline bool grid_barrier(uint32_t* counter, uint32_t target) {
+  __shared__ int ok;
+  __syncthreads();                                     // the workgroup's writes are done
+  if (threadIdx.x == 0) {
+    __threadfence();                                   // ... and visible device-wide
+    __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t spins = 0;
+    ok = 1;
+    while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > (1u << 24)) {                      // ~1 s: cannot happen with resident workgroups
+        ok = 0;
+        break;
+      }
+    }
+    __threadfence();                                   // later reads see the other workgroups' writes
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void ingest_kernel(char* base) {
+  IngestProgram* prog = reinterpret_cast<IngestProgram*>(base);
+  uint32_t* counter = &prog->counter;
+  const int nph = prog->nphases;
+  for (int p = 0; p < nph; ++p) {
+    const IngestPhase& P = prog->ph[p];
+    int64_t total = 0;
+    for (int s = 0; s < P.nseg; ++s) total += P.seg[s].blocks;
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+      int s = 0;
+      int64_t rel = b;
+      while (rel >= P.seg[s].blocks) rel -= P.seg[s++].blocks;
+      const IngestSeg& g = P.seg[s];
+      const void* tasks = base + g.tasks;
+      switch (g.kind) {
+        case kSegRightRaw:
+          gemm_task_tile<true, TC, TC, double>(static_cast<const GemmTask*>(tasks), g.ntasks, rel);
+          break;
+        case kSegLeftRaw:
+          gemm_task_tile<false, TC, TC, double>(static_cast<const GemmTask*>(tasks), g.ntasks, rel);
+          break;
+        case kSegRightF64:
+          gemm_task_tile<true, double, double, double>(static_cast<const GemmTask*>(tasks), g.ntasks, rel);
+          break;
+        case kSegLeftF64:
+          gemm_task_tile<false, double, double, double>(static_cast<const GemmTask*>(tasks), g.ntasks, rel);
+          break;
+        case kSegFold:
+          fold_task_tile(static_cast<const ReduceTask*>(tasks), g.ntasks, rel);
+          break;
+        default:
+          reduce_task_tile(static_cast<const ReduceTask*>(tasks), g.ntasks, rel);
+          break;
+      }
+    }
+    if (p + 1 < nph && !grid_barrier(counter, static_cast<uint32_t>(p + 1) * gridDim.x)) {
+      if (threadIdx.x == 0)
+        for (int i = 0; i < prog->nsticky; ++i) atomicOr(prog->sticky[i], 1);
+      return;
+    }
+  }
 }
 
 __global__ void reduce_kernel(const double* __restrict__ part, int nchunks, int64_t rows, int ncols, int mode,
@@ -700,6 +806,122 @@ void launch_finite_list(const SegList& s, int* flag, hipStream_t st) {
 
 void launch_finite_check(const double* p, int64_t n, int* flag, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(finite_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n, flag);
+}
+
+// ---------------------------------------------------------------- persistent ingest (host)
+namespace {
+template <typename TC>
+int ingest_grid(int64_t want) {
+  static std::mutex mu;
+  static std::map<int, int> slots;              // device -> resident workgroups of the kernel
+  int dev = 0;
+  TTNN_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = slots.find(dev);
+  if (it == slots.end()) {
+    int coop = 0, cus = 0, per = 0;
+    TTNN_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+    TTNN_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    TTNN_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(ingest_kernel<TC>),
+                                                            256, 0));
+    it = slots.emplace(dev, coop ? per * cus : 0).first;
+  }
+  if (it->second <= 0) return 0;
+  return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(want, it->second)));
+}
+}  // namespace
+
+bool launch_ingest(int cd, const std::vector<BatchedGemm>& gl, const std::vector<size_t>& level_end,
+                   const std::vector<BatchedReduce>& rl, const std::vector<int*>& sticky, hipStream_t st) {
+  if (sticky.size() > static_cast<size_t>(kIngestPlans)) return false;
+  std::vector<IngestPhase> phases;
+  // task tables follow the program, each 64-byte aligned
+  const size_t head = (sizeof(IngestProgram) + 63) / 64 * 64;
+  std::vector<std::pair<const void*, size_t>> tables;     // (host data, bytes)
+  size_t off = head;
+  auto add_table = [&](const void* data, size_t bytes) {
+    const size_t at = off;
+    tables.emplace_back(data, bytes);
+    off = (off + bytes + 63) / 64 * 64;
+    return static_cast<int64_t>(at);
+  };
+  int64_t most = 0;
+  size_t g0 = 0;
+  for (size_t lv = 0; lv < rl.size(); ++lv) {
+    IngestPhase ph{};
+    for (size_t k = g0; k < level_end[lv]; ++k) {
+      const BatchedGemm& b = gl[k];
+      if (b.tasks.empty()) continue;
+      if (b.out_f32 || ph.nseg == kIngestSegs) return false;
+      int kind;
+      if (b.th == cd && b.td == cd) kind = b.right ? kSegRightRaw : kSegLeftRaw;
+      else if (b.th == TTNN_F64 && b.td == TTNN_F64) kind = b.right ? kSegRightF64 : kSegLeftF64;
+      else return false;
+      IngestSeg& g = ph.seg[ph.nseg++];
+      g.kind = kind;
+      g.ntasks = static_cast<int32_t>(b.tasks.size());
+      g.blocks = b.blocks;
+      g.tasks = add_table(b.tasks.data(), b.tasks.size() * sizeof(GemmTask));
+    }
+    g0 = level_end[lv];
+    auto push = [&](IngestPhase& q) {
+      if (q.nseg == 0) return;
+      int64_t t = 0;
+      for (int i = 0; i < q.nseg; ++i) t += q.seg[i].blocks;
+      most = std::max(most, t);
+      phases.push_back(q);
+    };
+    push(ph);
+    const BatchedReduce& r = rl[lv];
+    if (!r.folds.empty()) {
+      IngestPhase f{};
+      f.nseg = 1;
+      f.seg[0] = IngestSeg{add_table(r.folds.data(), r.folds.size() * sizeof(ReduceTask)), r.fblocks, kSegFold,
+                           static_cast<int32_t>(r.folds.size())};
+      push(f);
+    }
+    if (!r.tasks.empty()) {
+      IngestPhase q{};
+      q.nseg = 1;
+      q.seg[0] = IngestSeg{add_table(r.tasks.data(), r.tasks.size() * sizeof(ReduceTask)), r.blocks, kSegReduce,
+                           static_cast<int32_t>(r.tasks.size())};
+      push(q);
+    }
+  }
+  if (phases.empty()) return true;
+  if (phases.size() > static_cast<size_t>(kIngestPhases)) return false;
+  const int grid = cd == TTNN_BF16 ? ingest_grid<uint16_t>(most)
+                   : cd == TTNN_F32 ? ingest_grid<float>(most)
+                                    : ingest_grid<double>(most);
+  if (grid <= 0) return false;
+  std::vector<char> host(off, 0);
+  IngestProgram* prog = reinterpret_cast<IngestProgram*>(host.data());
+  prog->counter = 0;
+  prog->nphases = static_cast<int32_t>(phases.size());
+  prog->nsticky = static_cast<int32_t>(sticky.size());
+  for (size_t i = 0; i < sticky.size(); ++i) prog->sticky[i] = sticky[i];
+  for (size_t i = 0; i < phases.size(); ++i) prog->ph[i] = phases[i];
+  size_t at = head;
+  for (auto& t : tables) {
+    std::memcpy(host.data() + at, t.first, t.second);
+    at = (at + t.second + 63) / 64 * 64;
+  }
+  StagingLock lock;
+  char* d = static_cast<char*>(stage_descriptors(host.data(), host.size(), st));
+  void* args[] = {&d};
+  hipError_t e;
+  if (cd == TTNN_BF16)
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(ingest_kernel<uint16_t>), dim3(grid), dim3(256),
+                                   args, 0, st);
+  else if (cd == TTNN_F32)
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(ingest_kernel<float>), dim3(grid), dim3(256), args,
+                                   0, st);
+  else
+    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(ingest_kernel<double>), dim3(grid), dim3(256),
+                                   args, 0, st);
+  TTNN_HIP(e);
+  fence_descriptors(st);
+  return true;
 }
 
 }  // namespace ttnn

@@ -106,6 +106,17 @@ struct BatchedReduce {
 BatchedReduce plan_reduce_batched(const std::vector<ReduceTask>& tasks);
 void launch_reduce_staged(const BatchedReduce& b, const ReduceTask* d_folds, const ReduceTask* d_tasks,
                           hipStream_t stream);
+// Persistent ingest: every phase of a batched round of box updates in one cooperative
+// launch (level by level: the contractions of all kinds, the chunk folds, the
+// reductions; grid-wide barriers between phases), bitwise the same results as the
+// per-level launches.  gl / level_end / rl as built for those launches (all plans of
+// compute dtype cd); sticky: each plan's sticky status word (set if a barrier wait ran
+// out).  Returns false, launching nothing, when the round does not fit the program
+// (too many phases, segments or plans, FP32 outputs) or the device cannot launch it.
+constexpr int kIngestSegs = 4, kIngestPlans = 128, kIngestPhases = 48;
+enum : int32_t { kSegRightRaw = 0, kSegLeftRaw = 1, kSegRightF64 = 2, kSegLeftF64 = 3, kSegFold = 4, kSegReduce = 5 };
+bool launch_ingest(int cd, const std::vector<BatchedGemm>& gl, const std::vector<size_t>& level_end,
+                   const std::vector<BatchedReduce>& rl, const std::vector<int*>& sticky, hipStream_t stream);
 // Copy `bytes` of host descriptors into device memory that stays valid for work
 // enqueued on `stream` after this call and before the next fence_descriptors on it
 // (pinned staging ring, reused once the fenced work has finished).

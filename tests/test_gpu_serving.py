@@ -203,3 +203,36 @@ def test_serving_budget_admission_and_parity(P):
         e_gpu = rel(recon[s], W.flat_colmajor(T))
         e_orc = rel(W.flat_colmajor(want), W.flat_colmajor(T))
         assert abs(e_gpu - e_orc) <= 0.1 * e_orc + 1e-6, (s, e_gpu, e_orc)
+
+
+@pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+def test_persistent_round_equals_per_level_launches(P, variant, dtype):
+    """With TTNN_PERSISTENT=1 a batched round runs as one persistent cooperative launch
+    (every level's contractions, folds and reductions, grid-wide barriers between them);
+    by default the same tiles run as one launch per level and kind.  The two must agree
+    bit for bit, for plans of different sizes and several rounds per call."""
+    import os
+    spec = O.T5 if variant == "sttnn" else O.T4
+    dims_list = [(9, 8, 7, 6, 5), (6, 9, 5, 8, 7)] if variant == "sttnn" else [(17, 9, 12, 10), (9, 14, 8, 13)]
+    tensors = [W.small_random_ttn(spec, d, 3, seed=40 + i) for i, d in enumerate(dims_list)]
+    g = W.rng(19)
+    work = []
+    for i, d in enumerate(dims_list):
+        for off, ext in WS.boxes(d, g, lo=2, hi=5)[:12]:
+            blk, _ = to_device(tensors[i][tuple(slice(o, o + e) for o, e in zip(off, ext))], dtype)
+            work.append((i, off, ext, blk))
+    results = []
+    for persistent in ("1", "0"):
+        os.environ["TTNN_PERSISTENT"] = persistent
+        try:
+            plans = [P.Plan(spec, d, 4, 2, variant=variant, dtype=dtype, seed=3) for d in dims_list]
+            P.update_batched([(plans[i], blk, ext, off, 0.5 + i) for i, off, ext, blk in work])
+            torch.cuda.synchronize()
+            results.append([read_all(P, pl) for pl in plans])
+            for pl in plans:
+                pl.close()
+        finally:
+            del os.environ["TTNN_PERSISTENT"]
+    for a, b in zip(*results):
+        assert same_bits(a, b)
