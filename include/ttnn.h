@@ -78,7 +78,14 @@ typedef enum {
   TTNN_E_NUMERIC = -7   /* non-finite sketch, or a node whose Omega has rank 0     */
 } ttnn_status;
 
-typedef enum { TTNN_TTNN = 0, TTNN_STTNN = 1 } ttnn_variant;
+/* TTNN_KR: the TTNN sketches of Sec. 4 with the Khatri-Rao structured maps of Sec. 7,
+ * for tensors given in TTN format (rounding / recompression, e.g. of sums of TTNs): see
+ * ttnn_sketch_update_ttn. */
+typedef enum { TTNN_TTNN = 0, TTNN_STTNN = 1, TTNN_KR = 2 } ttnn_variant;
+
+/* Per-mode factors of TTNN_KR plans are seeded with map tags 2 (TTNN_KR_TAG_BASE + mu)
+ * + kind (mu 0-based), after the per-node tags 2 v + kind of the dense maps. */
+#define TTNN_KR_TAG_BASE 64
 
 /* Storage / multiply precision of the tensor, of the DRM copies read by the hot
  * kernels and of the MFMA inputs.  Accumulators and the whole recovery phase are
@@ -136,6 +143,16 @@ typedef struct {
  * contracted tensor outside I_t (STTNN, contracted groups kept in place); rows of Y_t
  * run column-major over I_t.  Accumulators start at 0. */
 ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_plan_t* out);
+/* A TTNN_KR plan (dtype F64, one rank r and one oversample p for every node) draws
+ * instead, for every mode mu, the factors X_mu (n_mu x r) and Y_mu (n_mu x (r + p)) of
+ * Sec. 7 with tags 2 (TTNN_KR_TAG_BASE + mu) + kind, row-major, by the same generator.
+ * Its maps are X_t = khatri-rao of X_mu over the modes outside I_t and Y_t =
+ * khatri-rao of Y_mu over I_t, never formed: column j of each is the Kronecker product
+ * of the factors' columns j, entry (i_1, .., i_d) of it prod_mu X_mu(i_mu, j), rows
+ * column-major as for the dense maps.  It keeps Omega_t, Psi_t (R_t for leaves) and the
+ * root Psi as accumulators, takes TTN-format updates only (ttnn_sketch_update_ttn), and
+ * its recovery is that of every plan.  It sizes the dense reconstruction only when its
+ * intermediates stay below 2^27 doubles (else ttnn_reconstruct returns TTNN_E_STATE). */
 
 /* Device bytes a plan for `problem` needs (its DRMs in FP64 and in the compute dtype,
  * FP64 accumulators, cores' scratch and partial sums), computed on the host without
@@ -203,6 +220,40 @@ typedef struct {
   double alpha;
 } ttnn_update_desc;
 ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs, void* stream);
+
+/* TTN-format update of a TTNN_KR plan (Sec. 7; Sec. 4 linearity): add alpha * the
+ * sketches of the tensor with TTN cores d_cores[c] (device pointers by caller node id,
+ * the core layout of ttnn_assemble: leaf (n_t, s_t), internal (s_c1, .., s_cm, s_t),
+ * root (s_c1, .., s_cm), column-major FP64) and ranks s_t = ranks[c] in [1, 4096] (the
+ * root's ignored).  Computed by contracting the tree, at a cost linear in the mode
+ * sizes and without forming the tensor:
+ *   dx_t, dy_t = the subtree of t contracted with the X (Y) columns j of its modes,
+ *   u_t = everything outside the subtree of t contracted with the X columns j,
+ *   Omega_t += alpha dy_t^T u_t,  leaf R_t = Psi_t += alpha U_t u_t,
+ *   internal Psi_t += alpha B_t x_c dy_c^T (each child) x_t u_t^T,
+ *   root Psi_0 += alpha B_0 x_c dy_c^T (each child).
+ * d_work: device scratch of ttnn_update_ttn_work_bytes bytes (256-byte aligned), or
+ * NULL to take it from the library's per-device pool for the call (stream ordered).
+ * TTNN_E_STATE on other plans; ttnn_sketch_update / _rank1 / _batched return
+ * TTNN_E_STATE on TTNN_KR plans. */
+ttnn_status ttnn_update_ttn_work_bytes(ttnn_plan_t plan, const int32_t* ranks, size_t* bytes);
+ttnn_status ttnn_sketch_update_ttn(ttnn_plan_t plan, const double* const* d_cores, const int32_t* ranks,
+                                   double alpha, void* d_work, size_t work_bytes, void* stream);
+
+/* Inner product <A, B> of two tensors in TTN format on the plan's tree (any plan;
+ * cores and ranks as for ttnn_sketch_update_ttn), by Gram matrices of the subtrees,
+ * deepest first: G_leaf = U_a^T U_b, G_t = B_a x_c G_c (each child) contracted with
+ * B_b.  The result goes to d_out[0] (device memory) in stream order.  Errors of a
+ * rounding follow as ||A - B||^2 = <A,A> - 2 <A,B> + <B,B>, which resolves relative
+ * errors down to about 1e-7 in FP64.  d_work as for ttnn_sketch_update_ttn, sized by
+ * ttnn_ttn_dot_work_bytes. */
+ttnn_status ttnn_ttn_dot_work_bytes(ttnn_plan_t plan, const int32_t* ranks_a, const int32_t* ranks_b, size_t* bytes);
+ttnn_status ttnn_ttn_dot(ttnn_plan_t plan, const double* const* d_a, const int32_t* ranks_a, const double* const* d_b,
+                         const int32_t* ranks_b, double* d_out, void* d_work, size_t work_bytes, void* stream);
+
+/* Per-mode factor of a TTNN_KR plan: kind 0 = X_mu (n_mu x r), 1 = Y_mu (n_mu x (r + p)),
+ * row-major FP64, copied to d_out. */
+ttnn_status ttnn_read_factor(ttnn_plan_t plan, int32_t mode, int32_t kind, double* d_out, void* stream);
 
 /* Shape of node `node`'s core (column-major, parent rank index last):
  *   leaf (n_t, r_t); internal (r_c1, ..., r_cm, r_t); root (r_c1, ..., r_cm). */

@@ -4,5 +4,5 @@ C ABI (include/ttnn.h), and a thin Python binding."""
 
 from ._lib import (  # noqa: F401
     Plan, TTNNError, diff_norms, update_batched, tree_arrays, footprint_estimate, workspace_bytes, lib,
-    F64, F32, BF16, TTNN, STTNN, SK_R, SK_OMEGA, SK_PSI, TORCH_DTYPE, DTYPE_NAME,
+    F64, F32, BF16, TTNN, STTNN, KR, SK_R, SK_OMEGA, SK_PSI, TORCH_DTYPE, DTYPE_NAME,
 )

@@ -14,14 +14,14 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libttnn.so")
 
 F64, F32, BF16 = 0, 1, 2
-TTNN, STTNN = 0, 1
+TTNN, STTNN, KR = 0, 1, 2
 SK_R, SK_OMEGA, SK_PSI = 0, 1, 2
 MAX_ORDER = 8
 
 TORCH_DTYPE = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}
 DTYPE_NAME = {F64: "f64", F32: "f32", BF16: "bf16"}
 DTYPE_OF_NAME = {"f64": F64, "f32": F32, "bf16": BF16}
-VARIANT_OF_NAME = {"ttnn": TTNN, "sttnn": STTNN}
+VARIANT_OF_NAME = {"ttnn": TTNN, "sttnn": STTNN, "kr": KR}
 
 
 class TTNNError(RuntimeError):
@@ -54,7 +54,14 @@ def _load():
     lib = C.CDLL(LIB_PATH)
     vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     P64 = C.POINTER(i64)
+    P32 = C.POINTER(i32)
+    PSZ = C.POINTER(C.c_size_t)
     sigs = {
+        "ttnn_update_ttn_work_bytes": [vp, P32, PSZ],
+        "ttnn_sketch_update_ttn": [vp, C.POINTER(vp), P32, dbl, vp, C.c_size_t, vp],
+        "ttnn_ttn_dot_work_bytes": [vp, P32, P32, PSZ],
+        "ttnn_ttn_dot": [vp, C.POINTER(vp), P32, C.POINTER(vp), P32, vp, vp, C.c_size_t, vp],
+        "ttnn_read_factor": [vp, i32, i32, vp, vp],
         "ttnn_plan_create": [C.POINTER(Problem), vp, C.POINTER(vp)],
         "ttnn_plan": [C.POINTER(Problem), vp, C.c_size_t, vp, C.POINTER(vp)],
         "ttnn_destroy": [vp],
@@ -325,6 +332,80 @@ class Plan:
             check_block(f, torch.float64, (n,), 1)
         ptrs = (C.c_void_p * self.d)(*[C.c_void_p(f.data_ptr()) for f in factors])
         check(lib.ttnn_sketch_update_rank1(self.handle, ptrs, float(alpha), stream_ptr(stream)))
+
+    # ------------------------------------------------------------ TTN-format inputs
+    def _ranks_list(self, ranks):
+        if isinstance(ranks, dict):
+            return [int(ranks[m]) if i else 0 for i, m in enumerate(self.node_modes)]
+        if isinstance(ranks, int):
+            return [int(ranks) if i else 0 for i in range(self.num_nodes)]
+        return [int(x) for x in ranks]
+
+    def _ttn_args(self, cores, ranks):
+        """Core pointers and ranks of a TTN on this plan's tree, in caller node order.
+        cores: a list by caller node id or a dict keyed by node modes (CUDA float64,
+        contiguous, the layout of assembled cores); ranks: an int (every non-root node),
+        a list by caller node id, or a dict keyed by node modes."""
+        nn = self.num_nodes
+        if isinstance(cores, dict):
+            cores = [cores[m] for m in self.node_modes]
+        rk = self._ranks_list(ranks)
+        if len(cores) != nn or len(rk) != nn:
+            raise ValueError(f"a TTN on this tree has {nn} cores and ranks")
+        parent = list(self._arrays[1])
+        kids = [[] for _ in range(nn)]
+        for i in range(1, nn):
+            kids[parent[i]].append(i)
+        for i in range(nn):
+            if i and rk[i] < 1:
+                raise ValueError(f"node {i}: TTN rank {rk[i]} < 1")
+            if kids[i]:
+                want = 1
+                for c in kids[i]:
+                    want *= rk[c]
+                want *= rk[i] if i else 1
+            else:
+                want = rk[i]
+                for m in self.node_modes[i]:
+                    want *= self.dims[m - 1]
+            check_block(cores[i], torch.float64, (want,), 1)
+        ptrs = (C.c_void_p * nn)(*[C.c_void_p(c.data_ptr()) for c in cores])
+        return ptrs, (C.c_int32 * nn)(*rk)
+
+    def core_ranks(self):
+        """Ranks r_t of the cores this plan assembles, by caller node id (root 0)."""
+        return [int(x) if i else 0 for i, x in enumerate(self._arrays[4])]
+
+    def update_ttn(self, cores, ranks, alpha=1.0, stream=None, work=None):
+        """Khatri-Rao plans: accumulators += alpha * sketches of the TTN (cores, ranks);
+        work: optional CUDA uint8 scratch tensor (else the library's pool serves the call)."""
+        ptrs, rk = self._ttn_args(cores, ranks)
+        wp, wb = (None, 0) if work is None else (C.c_void_p(work.data_ptr()), work.numel() * work.element_size())
+        check(lib.ttnn_sketch_update_ttn(self.handle, ptrs, rk, float(alpha), wp, wb, stream_ptr(stream)))
+
+    def update_ttn_work_bytes(self, ranks):
+        """Device scratch (bytes) of one update_ttn with TTN ranks `ranks`."""
+        rk = self._ranks_list(ranks)
+        out = C.c_size_t()
+        check(lib.ttnn_update_ttn_work_bytes(self.handle, (C.c_int32 * self.num_nodes)(*rk), C.byref(out)))
+        return int(out.value)
+
+    def ttn_dot(self, a, ranks_a, b, ranks_b, stream=None):
+        """<A, B> of two TTNs on this plan's tree, computed on the GPU (waits for it)."""
+        pa, ra = self._ttn_args(a, ranks_a)
+        pb, rb = self._ttn_args(b, ranks_b)
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        check(lib.ttnn_ttn_dot(self.handle, pa, ra, pb, rb, C.c_void_p(out.data_ptr()), None, 0, stream_ptr(stream)))
+        if stream is not None:
+            stream.synchronize()
+        return float(out.cpu()[0])
+
+    def read_factor(self, mode, kind, stream=None):
+        """Per-mode factor of a Khatri-Rao plan: kind 0 = X (n x r), 1 = Y (n x (r + p)), row-major."""
+        cols = self.core_ranks()[1] + (0 if kind == 0 else int(self._arrays[5][1]))
+        out = torch.empty((self.dims[mode], cols), dtype=torch.float64, device="cuda")
+        check(lib.ttnn_read_factor(self.handle, int(mode), int(kind), C.c_void_p(out.data_ptr()), stream_ptr(stream)))
+        return out
 
     def reset(self, stream=None):
         check(lib.ttnn_reset(self.handle, stream_ptr(stream)))

@@ -8,6 +8,7 @@
 
 #include "engine.hpp"
 #include "kernels.hpp"
+#include "kr.hpp"
 
 struct ttnn_plan_s {
   std::unique_ptr<ttnn::Plan> p;
@@ -80,6 +81,54 @@ const int64_t* block_strides(const Plan& P, const int64_t* ext, const int64_t* s
   return packed ? nullptr : strides;
 }
 
+void dense_updates(const Plan& P) {
+  if (P.variant == TTNN_KR)
+    throw Error{TTNN_E_STATE, "a Khatri-Rao plan takes TTN-format updates only (ttnn_sketch_update_ttn)"};
+}
+
+// Level-order ranks of a TTN from the caller's array (root entry ignored).
+std::vector<int64_t> ttn_ranks(const Plan& P, const int32_t* ranks) {
+  if (!ranks) throw Error{TTNN_E_INVALID, "ranks is NULL"};
+  std::vector<int64_t> s(P.nodes.size(), 1);
+  for (size_t c = 0; c < P.nodes.size(); ++c) {
+    const int v = P.level_of_caller[c];
+    if (v > 0) s[v] = ranks[c];
+  }
+  return s;
+}
+
+std::vector<const double*> ttn_cores(const Plan& P, const double* const* cores) {
+  if (!cores) throw Error{TTNN_E_INVALID, "cores is NULL"};
+  std::vector<const double*> by_level(P.nodes.size());
+  for (size_t c = 0; c < P.nodes.size(); ++c) {
+    if (!cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
+    by_level[P.level_of_caller[c]] = cores[c];
+  }
+  return by_level;
+}
+
+// Scratch for one call: the caller's (checked), else from the pool for the call.
+struct CallWork {
+  void* p = nullptr;
+  bool owned = false;
+  hipStream_t st = nullptr;
+  CallWork(void* d_work, size_t have, size_t need, hipStream_t s) : st(s) {
+    if (d_work) {
+      if (have < need)
+        throw Error{TTNN_E_INVALID, "work buffer of " + std::to_string(have) + " bytes; the call needs " +
+                                        std::to_string(need)};
+      if (reinterpret_cast<uintptr_t>(d_work) % 256 != 0) throw Error{TTNN_E_INVALID, "work buffer not 256-byte aligned"};
+      p = d_work;
+    } else {
+      p = ttnn::pool_alloc(need, s);
+      owned = true;
+    }
+  }
+  ~CallWork() {
+    if (owned) ttnn::pool_free(p, st);
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -142,6 +191,7 @@ ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int6
   Plan* P = get(plan);
   return guard(P, [&]() -> ttnn_status {
     if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
+    dense_updates(*P);
     bool empty = false;
     check_box(*P, offset, extent, &empty);
     if (empty) return TTNN_OK;
@@ -157,6 +207,7 @@ ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_fa
   Plan* P = get(plan);
   return guard(P, [&]() -> ttnn_status {
     if (!P || !d_factors) throw Error{TTNN_E_INVALID, "plan or factors is NULL"};
+    dense_updates(*P);
     for (int mu = 0; mu < P->d; ++mu)
       if (!d_factors[mu]) throw Error{TTNN_E_INVALID, "factor pointer is NULL"};
     ttnn::update_rank1(*P, d_factors, alpha, as_stream(stream));
@@ -173,6 +224,7 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
       Plan* P = get(descs[i].plan);
       if (!P) throw Error{TTNN_E_INVALID, "descriptor " + std::to_string(i) + " has no plan"};
       if (P->sticky != TTNN_OK) throw Error{P->sticky, "descriptor plan has a sticky error"};
+      dense_updates(*P);
       bool empty = false;
       check_box(*P, descs[i].offset, descs[i].extent, &empty);
       if (!empty && !descs[i].d_block) throw Error{TTNN_E_INVALID, "descriptor block is NULL"};
@@ -250,6 +302,72 @@ ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes) 
   });
 }
 
+ttnn_status ttnn_update_ttn_work_bytes(ttnn_plan_t plan, const int32_t* ranks, size_t* bytes) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !bytes) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (P->variant != TTNN_KR) throw Error{TTNN_E_STATE, "TTN-format updates need a Khatri-Rao plan"};
+    *bytes = ttnn::kr_update_work_bytes(*P, ttn_ranks(*P, ranks));
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sketch_update_ttn(ttnn_plan_t plan, const double* const* d_cores, const int32_t* ranks, double alpha,
+                                   void* d_work, size_t work_bytes, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
+    if (P->variant != TTNN_KR) throw Error{TTNN_E_STATE, "TTN-format updates need a Khatri-Rao plan"};
+    const auto s = ttn_ranks(*P, ranks);
+    const auto cores = ttn_cores(*P, d_cores);
+    const size_t need = ttnn::kr_update_work_bytes(*P, s);
+    const hipStream_t st = as_stream(stream);
+    CallWork w(d_work, work_bytes, need, st);
+    ttnn::update_ttn(*P, cores.data(), s, alpha, w.p, st);
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_ttn_dot_work_bytes(ttnn_plan_t plan, const int32_t* ranks_a, const int32_t* ranks_b, size_t* bytes) {
+  Plan* P = get(plan);
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!P || !bytes) throw Error{TTNN_E_INVALID, "NULL argument"};
+    *bytes = ttnn::ttn_dot_work_bytes(*P, ttn_ranks(*P, ranks_a), ttn_ranks(*P, ranks_b));
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_ttn_dot(ttnn_plan_t plan, const double* const* d_a, const int32_t* ranks_a, const double* const* d_b,
+                         const int32_t* ranks_b, double* d_out, void* d_work, size_t work_bytes, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    const auto sa = ttn_ranks(*P, ranks_a), sb = ttn_ranks(*P, ranks_b);
+    const auto a = ttn_cores(*P, d_a), b = ttn_cores(*P, d_b);
+    const size_t need = ttnn::ttn_dot_work_bytes(*P, sa, sb);
+    const hipStream_t st = as_stream(stream);
+    CallWork w(d_work, work_bytes, need, st);
+    ttnn::ttn_dot(*P, a.data(), sa, b.data(), sb, d_out, w.p, st);
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_read_factor(ttnn_plan_t plan, int32_t mode, int32_t kind, double* d_out, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (P->variant != TTNN_KR) throw Error{TTNN_E_STATE, "only Khatri-Rao plans have per-mode factors"};
+    if (mode < 0 || mode >= P->d) throw Error{TTNN_E_RANGE, "mode out of range"};
+    if (kind != 0 && kind != 1) throw Error{TTNN_E_INVALID, "bad factor kind"};
+    const int cols = kind == 0 ? P->nodes[1].r : P->nodes[1].k;
+    ttnn::launch_copy_f64(d_out, kind == 0 ? P->kr_x[mode] : P->kr_y[mode], P->dims[mode] * cols, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
 ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64_t* shape) {
   Plan* P = get(plan);
   return guard(nullptr, [&]() -> ttnn_status {
@@ -319,6 +437,7 @@ ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, voi
   return guard(P, [&]() -> ttnn_status {
     if (!P || !d_cores || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
     if (out_dtype != TTNN_F64 && out_dtype != TTNN_F32) throw Error{TTNN_E_INVALID, "out_dtype must be F64 or F32"};
+    if (!P->recon_ok) throw Error{TTNN_E_STATE, "this Khatri-Rao plan sized no dense reconstruction (tensor too large)"};
     std::vector<const double*> by_level(P->nodes.size());
     for (size_t c = 0; c < P->nodes.size(); ++c) {
       if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
@@ -395,7 +514,10 @@ ttnn_status ttnn_read_sketch(ttnn_plan_t plan, int32_t node, int32_t kind, doubl
     const ttnn::Node& t = P->nodes[v];
     const double* src = nullptr;
     if (v == 0) src = P->psi_root;
-    else if (kind == TTNN_SK_R || (kind == TTNN_SK_PSI && t.leaf())) src = t.R;
+    else if (kind == TTNN_SK_R || (kind == TTNN_SK_PSI && t.leaf())) {
+      if (!t.R) throw Error{TTNN_E_STATE, "a Khatri-Rao plan keeps no R_t of internal nodes"};
+      src = t.R;
+    }
     else {
       if (!P->epilogue_valid) ttnn::run_epilogue(*P, st);
       src = kind == TTNN_SK_OMEGA ? t.Om : t.Psi;
@@ -428,6 +550,7 @@ ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t 
     const ttnn_status s = ttnn_drm_shape(plan, node, kind, &rows, &cols);
     if (s != TTNN_OK) return s;
     const ttnn::Node& t = P->nodes[level_id(*P, node)];
+    if (P->variant == TTNN_KR) throw Error{TTNN_E_STATE, "a Khatri-Rao plan forms no dense maps (ttnn_read_factor)"};
     const void* src;
     if (dtype == TTNN_F64) src = kind == 0 ? t.X64 : t.Y64;
     else if (dtype == P->dtype) src = kind == 0 ? t.Xc : t.Yc;

@@ -80,6 +80,8 @@ void left_op(Plan& P, GemmArgs g, double* dst, int mode, double alpha, hipStream
   launch_reduce(P.partial, nch, rows, g.ncols, mode, alpha, none, 0, dst, g.L, g.ncols, st);
 }
 
+}  // namespace
+
 // Dense FP64 mode product as a batched-GEMM job: the operand H is [L][n][Q]
 // (L fastest); out[l][j][q] = (acc ? out : 0) + alpha * sum_i H[l][i][q] M(i, j),
 // M(i, j) = M[i sMi + j sMj], j < c.
@@ -113,6 +115,8 @@ GJob left_job(const double* H, int64_t L, int64_t n, int64_t Q, const double* M,
   }
   return j;
 }
+
+namespace {
 
 // Dense FP64 right sketch as a job: R(i, j) += alpha * sum_{l,q} H[l][i][q] X[(l + L q) r + j]
 // with R column-major n x r.
@@ -166,6 +170,8 @@ struct Batch {
   }
 };
 
+}  // namespace
+
 // FP64 dense mode product on an operand with positions `sizes` (first fastest):
 // contract position p with M (rows = sizes[p]; M(i, j) at M[i*sMi + j*sMj]), j < ncols.
 GJob mode_job(const double* in, const std::vector<int64_t>& sizes, int p, const double* M, int64_t sMi,
@@ -175,6 +181,8 @@ GJob mode_job(const double* in, const std::vector<int64_t>& sizes, int p, const 
   for (size_t i = p + 1; i < sizes.size(); ++i) Q *= sizes[i];
   return left_job(in, L, sizes[p], Q, M, sMi, sMj, ncols, out, 0, 1.0);
 }
+
+namespace {
 
 // Operand addressing of a contraction that reads the raw block, whose contracted
 // positions are the modes [p0, p0 + w): packed, or in place with the caller's strides.
@@ -199,14 +207,19 @@ bool whole_box(const Plan& P, const int64_t* off, const int64_t* ext) {
 
 // ---------------------------------------------------------------- sizing
 void size_chain_scratch(Plan& P) {
+  // Khatri-Rao plans take no box updates (no chains, no split partials) and keep no
+  // R_t of internal nodes; they size the reconstruction only for tensors that fit
+  const bool kr = P.variant == TTNN_KR;
   std::vector<std::vector<int>> prefixes;
   auto add_prefixes = [&](const std::vector<int>& chain, size_t upto) {
     for (size_t j = 1; j <= upto && j <= chain.size(); ++j)
       prefixes.emplace_back(chain.begin(), chain.begin() + j);
   };
-  for (size_t v = 1; v < P.nodes.size(); ++v) add_prefixes(P.nodes[v].S, P.nodes[v].S.size());
-  const auto& rc = P.nodes[0].children;
-  add_prefixes(rc, rc.size() - 1);      // the last root step accumulates into Psi_0
+  if (!kr) {
+    for (size_t v = 1; v < P.nodes.size(); ++v) add_prefixes(P.nodes[v].S, P.nodes[v].S.size());
+    const auto& rc = P.nodes[0].children;
+    add_prefixes(rc, rc.size() - 1);      // the last root step accumulates into Psi_0
+  }
   size_t total = 0;
   for (auto& pf : prefixes) {
     if (P.prefix_offset.count(pf)) continue;
@@ -218,13 +231,13 @@ void size_chain_scratch(Plan& P) {
   }
   P.chain_elems = std::max<size_t>(total, 1);
 
-  size_t part = size_t(1) << 22;
-  for (size_t v = 1; v < P.nodes.size(); ++v) {
+  size_t part = kr ? 1 : size_t(1) << 22;
+  for (size_t v = 1; v < P.nodes.size() && !kr; ++v) {
     const Node& nd = P.nodes[v];
     part = std::max(part, static_cast<size_t>(nd.n * nd.r));
     part = std::max(part, static_cast<size_t>(nd.k * nd.r));
   }
-  part = std::max(part, static_cast<size_t>(P.psi_root_len));
+  if (!kr) part = std::max(part, static_cast<size_t>(P.psi_root_len));
   P.partial_elems = part;
 
   // work buffer: every intermediate of the epilogue chains, of the core chains, and
@@ -236,7 +249,7 @@ void size_chain_scratch(Plan& P) {
     const size_t m = nd.children.size();
     const int64_t rt = v == 0 ? 1 : nd.r;
     for (size_t step = 0; step + 1 < m; ++step) {          // epilogue: after step s, k for <= s, n after
-      if (v == 0) break;
+      if (v == 0 || kr) break;
       int64_t e = rt;
       for (size_t j = 0; j < m; ++j) e *= j <= step ? P.nodes[nd.children[j]].k : P.nodes[nd.children[j]].n;
       epi += static_cast<size_t>(e);
@@ -254,15 +267,31 @@ void size_chain_scratch(Plan& P) {
     }
     if (v != 0) ustore += static_cast<size_t>(nd.n * nd.r);
   }
-  P.work_elems = std::max({epi, core, ustore + 2 * rinter, size_t(1)});
+  P.recon_ok = !kr || ustore + 2 * rinter <= (size_t(1) << 27);
+  P.work_elems = std::max({epi, core, P.recon_ok ? ustore + 2 * rinter : size_t(1), size_t(1)});
 }
 
 void zero_accumulators(Plan& P, hipStream_t st) {
   SegList s;
-  for (size_t v = 1; v < P.nodes.size(); ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+  if (P.variant == TTNN_KR) {               // structured plans accumulate Omega_t and Psi_t directly
+    for (size_t v = 1; v < P.nodes.size(); ++v) {
+      const Node& t = P.nodes[v];
+      s.push(t.Om, t.k * t.r);
+      if (t.leaf()) s.push(t.R, t.n * t.r);
+      else s.push(t.Psi, psi_rows(P, static_cast<int>(v)) * t.r);
+    }
+  } else {
+    for (size_t v = 1; v < P.nodes.size(); ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+  }
   s.push(P.psi_root, P.psi_root_len);
   launch_zero_list(s, st);
-  P.epilogue_valid = false;
+  P.epilogue_valid = P.variant == TTNN_KR;
+}
+
+int64_t psi_rows(const Plan& P, int v) {
+  int64_t kk = 1;
+  for (int c : P.nodes[v].children) kk *= P.nodes[c].k;
+  return kk;
 }
 
 // ---------------------------------------------------------------- sketch phase
@@ -792,7 +821,14 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   launch_zero_int(P.d_flag, kCallWord, st);
   {
     SegList s;
-    for (int v = 1; v < nn; ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+    for (int v = 1; v < nn; ++v) {
+      const Node& t = P.nodes[v];
+      if (P.variant != TTNN_KR) s.push(t.R, t.n * t.r);
+      else {                                   // the structured accumulators themselves
+        s.push(t.Om, t.k * t.r);
+        s.push(t.leaf() ? t.R : t.Psi, (t.leaf() ? t.n : psi_rows(P, v)) * t.r);
+      }
+    }
     s.push(P.psi_root, P.psi_root_len);
     launch_finite_list(s, P.d_flag, st);
   }

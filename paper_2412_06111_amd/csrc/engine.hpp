@@ -51,6 +51,18 @@ ttnn_status assemble_status(Plan& P, hipStream_t stream);
 void assemble_status_async(Plan& P, int32_t* h_status, hipStream_t stream);
 void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dtype, hipStream_t stream);
 
+// Rows of Psi_t of internal node v: prod of the children's r_c + p_c.
+int64_t psi_rows(const Plan& P, int v);
+// FP64 mode products on the batched GEMM (see launch_bgemm64):
+//   left_job: out(l, j, q) (+)= alpha sum_i H[l + L (i + n q)] M(i, j), M(i, j) = M[i sMi + j sMj],
+//             out column-major [L][c][Q]
+//   mode_job: position p of an operand with positions `sizes` (first fastest) contracted
+//             with M (rows sizes[p], ncols columns), stored.
+GJob left_job(const double* H, int64_t L, int64_t n, int64_t Q, const double* M, int64_t sMi, int64_t sMj,
+              int64_t c, double* out, int acc, double alpha);
+GJob mode_job(const double* in, const std::vector<int64_t>& sizes, int p, const double* M, int64_t sMi,
+              int64_t sMj, int64_t ncols, double* out);
+
 // Core shape of level-order node v.
 std::vector<int64_t> core_shape(const Plan& P, int v);
 

@@ -223,10 +223,12 @@ void copy_layout(const double* src, void* out, int dt, int64_t d0, int64_t d1, i
 void launch_zero(double* p, int64_t n, hipStream_t stream);
 // Several FP64 arrays in one launch: zero them, or set *flag when one holds a non-finite value.
 struct SegList {
-  double* p[TTNN_MAX_NODES + 1];
-  int64_t n[TTNN_MAX_NODES + 1];
+  static constexpr int kMax = 2 * TTNN_MAX_NODES + 1;    // two arrays per node plus the root's
+  double* p[kMax];
+  int64_t n[kMax];
   int count = 0;
   void push(double* ptr, int64_t len) {
+    TTNN_REQUIRE(count < kMax, TTNN_E_INVALID, "too many arrays in one list launch");
     p[count] = ptr;
     n[count] = len;
     ++count;

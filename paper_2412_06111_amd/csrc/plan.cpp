@@ -43,6 +43,23 @@ hipMemPool_t plan_pool() {
 }
 }  // namespace
 
+void* pool_alloc(size_t bytes, hipStream_t stream) {
+  void* a = nullptr;
+  if (hipMallocFromPoolAsync(&a, bytes, plan_pool(), stream) != hipSuccess || a == nullptr) {
+    (void)hipGetLastError();
+    throw Error{TTNN_E_NOMEM, "stream-ordered allocation of " + std::to_string(bytes) + " bytes failed"};
+  }
+  if (reinterpret_cast<uintptr_t>(a) % 256 != 0) {        // the kernels assume 256-byte aligned arrays
+    (void)hipFreeAsync(a, stream);
+    throw Error{TTNN_E_NOMEM, "device allocation not 256-byte aligned"};
+  }
+  return a;
+}
+
+void pool_free(void* p, hipStream_t stream) {
+  if (p) (void)hipFreeAsync(p, stream);
+}
+
 // Device memory of a plan is stream ordered (allocated on the creation stream), so
 // releasing it does not synchronise the device: the blocks return to the pool when
 // the release stream reaches them.
@@ -98,7 +115,10 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
                TTNN_E_INVALID, "problem has a NULL array");
   TTNN_REQUIRE(pr->num_nodes >= 2 && pr->num_nodes <= TTNN_MAX_NODES, TTNN_E_TREE,
                "num_nodes must be in [2, 64]");
-  TTNN_REQUIRE(pr->variant == TTNN_TTNN || pr->variant == TTNN_STTNN, TTNN_E_INVALID, "bad variant");
+  TTNN_REQUIRE(pr->variant == TTNN_TTNN || pr->variant == TTNN_STTNN || pr->variant == TTNN_KR, TTNN_E_INVALID,
+               "bad variant");
+  TTNN_REQUIRE(pr->variant != TTNN_KR || pr->dtype == TTNN_F64, TTNN_E_INVALID,
+               "Khatri-Rao plans sketch FP64 TTN cores (dtype F64)");
   TTNN_REQUIRE(pr->dtype == TTNN_F64 || pr->dtype == TTNN_F32 || pr->dtype == TTNN_BF16, TTNN_E_INVALID,
                "bad dtype");
   TTNN_REQUIRE(pr->eps_factor >= 0.0, TTNN_E_INVALID, "eps_factor must be >= 0");
@@ -116,15 +136,8 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     P->arena_size = need;
     P->owns_arena = false;
   } else if (!dry) {
-    void* a = nullptr;
-    if (hipMallocFromPoolAsync(&a, need, plan_pool(), stream) != hipSuccess || a == nullptr) {
-      (void)hipGetLastError();
-      throw Error{TTNN_E_NOMEM, "stream-ordered allocation of " + std::to_string(need) + " bytes failed"};
-    }
-    P->arena = static_cast<char*>(a);
+    P->arena = static_cast<char*>(pool_alloc(need, stream));
     P->arena_size = need;
-    if (reinterpret_cast<uintptr_t>(a) % 256 != 0)         // the kernels assume 256-byte aligned arrays
-      throw Error{TTNN_E_NOMEM, "device allocation not 256-byte aligned"};
   }
   P->d = pr->order;
   P->variant = pr->variant;
@@ -212,6 +225,11 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     }
   }
 
+  if (P->variant == TTNN_KR)                 // X_t, Y_t are Khatri-Rao products of shared per-mode factors
+    for (int v = 2; v < nn; ++v)
+      TTNN_REQUIRE(P->nodes[v].r == P->nodes[1].r && P->nodes[v].p == P->nodes[1].p, TTNN_E_INVALID,
+                   "Khatri-Rao plans need one rank and one oversample for every node");
+
   // ---- STTNN reuse sets and X_t row positions
   for (int v = 1; v < nn; ++v) {
     Node& nd = P->nodes[v];
@@ -243,7 +261,30 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   // ---- device memory
   const bool copy = P->dtype != TTNN_F64;
   const size_t cs = dtype_size(P->dtype);
-  for (int v = 1; v < nn; ++v) {
+  const bool kr = P->variant == TTNN_KR;
+  for (int v = 1; v < nn && kr; ++v) {     // structured: no dense maps, no R_t of internal nodes
+    Node& nd = P->nodes[v];
+    nd.Om = static_cast<double*>(P->alloc(sizeof(double) * nd.k * nd.r));
+    nd.Q = static_cast<double*>(P->alloc(sizeof(double) * nd.k * nd.r));
+    nd.Pinv = static_cast<double*>(P->alloc(sizeof(double) * nd.r * nd.r));
+    if (nd.leaf()) {
+      check_mul(nd.n, nd.r, "R_t size");
+      nd.R = static_cast<double*>(P->alloc(sizeof(double) * nd.n * nd.r));
+    } else {
+      int64_t kk = 1;
+      for (int c : nd.children) {
+        check_mul(kk, P->nodes[c].k, "Psi_t size");
+        kk *= P->nodes[c].k;
+      }
+      check_mul(kk, nd.r, "Psi_t size");
+      nd.Psi = static_cast<double*>(P->alloc(sizeof(double) * kk * nd.r));
+    }
+  }
+  for (int mu = 0; mu < P->d && kr; ++mu) {
+    P->kr_x[mu] = static_cast<double*>(P->alloc(sizeof(double) * P->dims[mu] * P->nodes[1].r));
+    P->kr_y[mu] = static_cast<double*>(P->alloc(sizeof(double) * P->dims[mu] * P->nodes[1].k));
+  }
+  for (int v = 1; v < nn && !kr; ++v) {
     Node& nd = P->nodes[v];
     check_mul(nd.m, nd.r, "X_t size");
     nd.X64 = static_cast<double*>(P->alloc(sizeof(double) * nd.m * nd.r));
@@ -261,7 +302,10 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     }
   }
   P->psi_root_len = 1;
-  for (int c : P->nodes[0].children) P->psi_root_len *= P->nodes[c].k;
+  for (int c : P->nodes[0].children) {
+    check_mul(P->psi_root_len, P->nodes[c].k, "root Psi size");
+    P->psi_root_len *= P->nodes[c].k;
+  }
   P->psi_root = static_cast<double*>(P->alloc(sizeof(double) * P->psi_root_len));
   P->d_flag = static_cast<int*>(P->alloc(sizeof(int) * 2 * TTNN_MAX_NODES));
   if (!dry) launch_zero_int(P->d_flag, 2 * TTNN_MAX_NODES, stream);     // status words start clear
@@ -284,11 +328,11 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
 
   // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
   const char* nf = std::getenv("TTNN_DISABLE_FUSED");
-  P->allow_fused = !(nf && nf[0] == '1');
+  P->allow_fused = !(nf && nf[0] == '1') && !kr;
   // transposed DRM copies for whole-tensor right sketches on MFMA (large tensors only,
   // nodes sketched on the raw tensor that the fused kernel does not cover)
   auto plan_xt = [&](bool fill) {
-    if (P->N < (int64_t(1) << 22)) return;
+    if (P->N < (int64_t(1) << 22) || kr) return;
     const FusedT4& F = P->fused;
     for (int v = 1; v < nn; ++v) {
       Node& nd = P->nodes[v];
@@ -328,7 +372,12 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   }
 
   // ---- DRMs and zeroed accumulators
-  for (int v = 1; v < nn; ++v) {
+  for (int mu = 0; mu < P->d && kr; ++mu) {          // per-mode factors: tags 2 (64 + mu) + kind
+    const uint32_t tx = static_cast<uint32_t>(2 * (TTNN_KR_TAG_BASE + mu)), ty = tx + 1;
+    launch_drm(P->dims[mu], P->nodes[1].r, P->seed, tx, P->kr_x[mu], nullptr, nullptr, stream);
+    launch_drm(P->dims[mu], P->nodes[1].k, P->seed, ty, P->kr_y[mu], nullptr, nullptr, stream);
+  }
+  for (int v = 1; v < nn && !kr; ++v) {
     Node& nd = P->nodes[v];
     const uint32_t tx = static_cast<uint32_t>(2 * v + 0), ty = static_cast<uint32_t>(2 * v + 1);
     float* x32 = P->dtype == TTNN_F32 ? static_cast<float*>(nd.Xc) : nullptr;

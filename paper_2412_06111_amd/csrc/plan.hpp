@@ -68,6 +68,12 @@ struct Plan {
   double* psi_root = nullptr;              // prod(k_c) FP64 accumulator
   int64_t psi_root_len = 0;
 
+  // Khatri-Rao plans (Sec. 7): per-mode factors X_mu (n_mu x r) and Y_mu (n_mu x k),
+  // row-major FP64; the nodes hold Omega_t, Psi_t (internal) and R_t (leaves) only
+  double* kr_x[TTNN_MAX_ORDER] = {};
+  double* kr_y[TTNN_MAX_ORDER] = {};
+  bool recon_ok = true;                    // reconstruction scratch sized (not for large structured plans)
+
   // chain intermediates of the generic update path, keyed by contraction prefix
   std::map<std::vector<int>, size_t> prefix_offset;   // element offset into chain scratch
   double* chain = nullptr;
@@ -115,6 +121,11 @@ struct Plan {
 // allocates one block from the library's per-device pool.
 std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry = false, void* ws = nullptr,
                                  size_t ws_bytes = 0);
+
+// Stream-ordered device memory from the library's per-device pool (plans and per-call
+// scratch); throws TTNN_E_NOMEM.
+void* pool_alloc(size_t bytes, hipStream_t stream);
+void pool_free(void* p, hipStream_t stream);
 
 // IndexMap from a set of consecutive modes of a box to the column-major index of
 // the same modes in the full tensor

@@ -56,14 +56,15 @@ def failures(errs, tol):
 def sketch_errors(plan, tree, sk):
     """Per GPU sketch (R_t, Omega_t, Psi_t, root Psi) against the oracle sketches `sk`,
     element by element: (relative Frobenius error, max |difference| / RMS entry)."""
-    from paper_2412_06111_amd import SK_R, SK_OMEGA, SK_PSI
+    from paper_2412_06111_amd import KR, SK_R, SK_OMEGA, SK_PSI
     out = {}
     for n in tree.nodes:
         cid = plan.node(n.modes)
         if n.id == 0:
             out[("psi", n.modes)] = errs2(plan.read_sketch(cid, SK_PSI).cpu().numpy(), sk["Psi"][0])
             continue
-        out[("R", n.modes)] = errs2(plan.read_sketch(cid, SK_R).cpu().numpy(), sk["R"][n.id])
+        if plan.variant != KR or n.is_leaf:          # structured plans keep R_t of leaves only
+            out[("R", n.modes)] = errs2(plan.read_sketch(cid, SK_R).cpu().numpy(), sk["R"][n.id])
         out[("omega", n.modes)] = errs2(plan.read_sketch(cid, SK_OMEGA).cpu().numpy(), sk["Omega"][n.id])
         out[("psi", n.modes)] = errs2(plan.read_sketch(cid, SK_PSI).cpu().numpy(), sk["Psi"][n.id])
     return out

@@ -154,3 +154,24 @@ def test_chain_head_and_right_sketch_split_without_device():
         assert nch.value >= 1 and nch.value * n * r <= cap, (Lr, n, Q, r, cap)
         assert nch.value * kch.value >= Lr * Q > (nch.value - 1) * kch.value
         assert L.ttnn_right_sketch_split(Lr, n, Q, r, dt, n * r - 1, cus, C.byref(nch), C.byref(kch)) == -1
+
+
+def test_khatri_rao_plan_sizing_without_device():
+    """A Khatri-Rao plan forms no dense map and no R_t of an internal node: the order-6
+    rounding workload (mode size 500, 1.6e16 entries) sizes to the per-mode factors,
+    the Omega / Psi accumulators, the leaf R_t and fixed scratch, tens of MB; it needs
+    FP64 and one rank and oversample for every node."""
+    import oracle as O
+    import paper_2412_06111_amd as P
+    toy = O.TOY
+    b48 = P.footprint_estimate(toy, (500,) * 6, 48, 10, "kr", "f64")
+    b16 = P.footprint_estimate(toy, (500,) * 6, 16, 10, "kr", "f64")
+    assert 0 < b16 < b48 < 64 << 20
+    # at least the factors (6 x 500 x (r + r + p)) and the root Psi ((r + p)^3)
+    assert b48 > 8 * (6 * 500 * (48 + 58) + 58 ** 3)
+    with pytest.raises(P.TTNNError, match="F64"):
+        P.footprint_estimate(toy, (500,) * 6, 16, 10, "kr", "f32")
+    ranks = {m: 16 for m in [(1, 2, 3), (4,), (5, 6), (1, 2), (3,), (5,), (6,), (1,), (2,)]}
+    ranks[(4,)] = 12
+    with pytest.raises(P.TTNNError, match="one rank"):
+        P.footprint_estimate(toy, (500,) * 6, ranks, 10, "kr", "f64")
