@@ -65,6 +65,12 @@ def parse():
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="the Poisson load (a fraction of the batched path's closed-loop rate) summarised in the record")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.8", help="Poisson loads run (fractions of the closed-loop rate)")
+    ap.add_argument("--no-rounding", action="store_true", help="skip the TTN rounding runs (Khatri-Rao maps)")
+    ap.add_argument("--rounding-only", action="store_true",
+                    help="run only the TTN rounding runs and print them as one JSON line")
+    ap.add_argument("--round-n", type=int, default=500)
+    ap.add_argument("--round-ranks", default="16,32,48")
+    ap.add_argument("--round-trials", type=int, default=3, help="map seeds per rank (the paper averages 30)")
     return ap.parse_args()
 
 
@@ -342,6 +348,138 @@ def hilbert_bench(args):
     return out
 
 
+# ---------------------------------------------------------------- TTN rounding
+ROUND_TTN_RANK, ROUND_P = 70, 10
+ROUND_DECAYS = {"quadratic": lambda i: 1.0 / i ** 2, "cubic": lambda i: 1.0 / i ** 3, "exponential": lambda i: 0.5 ** i}
+
+
+def rounding_counts(spec, dims, r, p, s):
+    """Flops of one structured sketch (Khatri-Rao maps) of a TTN with ranks s on `spec`,
+    every node with rank r and oversampling p (k = r + p), as the path computes it: down
+    vectors (each core entry times r + k columns), up vectors (r columns per child),
+    Omega_t = dy^T u, leaf R_t = U u, and the Psi chains (parent index with u, then each
+    child with dy; the root's children only).  2 flops per multiply-add."""
+    from workloads import synth as W
+    k = r + p
+    fma = 0
+    for i, (sp, modes, par, kids) in enumerate(W.tree_spec_nodes(spec)):
+        root = i == 0
+        if not kids:
+            nt = 1
+            for m in modes:
+                nt *= dims[m - 1]
+            core = nt * s
+            fma += core * (r + k) + s * k * r + nt * s * r
+            continue
+        m = len(kids)
+        core = s ** m * (1 if root else s)
+        if not root:
+            fma += core * (r + k) + s * k * r
+        fma += core * r * m                                   # up vectors of the children
+        sizes = [s] * m + ([] if root else [s])
+        if not root:                                          # parent index with u
+            fma += core * r
+            sizes[-1] = r
+        for q in range(m):                                    # each child index with dy
+            cur = 1
+            for x in sizes:
+                cur *= x
+            fma += cur * k
+            sizes[q] = k
+    return 2 * fma
+
+
+def rounding_bench(args):
+    """The second experiment of Sec. 8: rounding of order-6 tensors given in TTN format
+    on the tree of Fig. 1, mode size 500, TTN ranks 70, internal cores superdiagonal with
+    entries sigma_i (quadratic, cubic, exponential decay) rotated by Haar matrices, Haar
+    leaves; TTNN with Khatri-Rao maps (Sec. 7), equal ranks r, p = 10.  Per decay and
+    rank: the mean relative error ||T - T_r|| / ||T|| over `--round-trials` map seeds,
+    from TTN inner products on the GPU, and the time of one rounding (reset + structured
+    sketch of the TTN + FP64 assembly of the cores), from events on the stream,
+    averaged over 10 timed repeats after 3 untimed ones."""
+    import numpy as np
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads import synth as W
+
+    spec = ((((1, 2), 3), 4, (5, 6)))
+    n = args.round_n
+    dims = (n,) * 6
+    s = ROUND_TTN_RANK
+    ranks = [int(x) for x in args.round_ranks.split(",") if x]
+    out = {"workload": f"TTN rounding, order 6, n={n}, TTN ranks {s}, Fig. 1 tree, Khatri-Rao maps, p={ROUND_P}",
+           "trials": args.round_trials, "rows": {}}
+    stream = torch.cuda.current_stream()
+    for name, f in ROUND_DECAYS.items():
+        sigma = np.array([f(i) for i in range(1, s + 1)])
+        host = W.decaying_ttn_cores(spec, dims, s, sigma, seed=7)
+        dc = {m: torch.from_numpy(np.ascontiguousarray(c.reshape(-1, order="F"))).cuda() for m, c in host.items()}
+        for r in ranks:
+            errs, ms = [], None
+            for trial in range(args.round_trials):
+                plan = P.Plan(spec, dims, r, ROUND_P, variant="kr", seed=300 + trial)
+                cores = plan.alloc_cores()
+                work = torch.empty(plan.update_ttn_work_bytes(s), dtype=torch.uint8, device="cuda")
+                if trial == 0:
+                    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                           for _ in range(13)]
+                    for a, b in evs:
+                        a.record(stream)
+                        plan.reset()
+                        plan.update_ttn(dc, s, work=work)
+                        plan.assemble_async(cores)
+                        b.record(stream)
+                    plan.assemble_status()
+                    torch.cuda.synchronize()
+                    t = [a.elapsed_time(b) for a, b in evs[3:]]
+                    ms = sum(t) / len(t)
+                else:
+                    plan.update_ttn(dc, s, work=work)
+                    plan.assemble(cores)
+                rr = plan.core_ranks()
+                tt = plan.ttn_dot(dc, s, dc, s)
+                e2 = tt - 2 * plan.ttn_dot(dc, s, cores, rr) + plan.ttn_dot(cores, rr, cores, rr)
+                errs.append(float(np.sqrt(max(e2, 0.0) / tt)))
+                plan.close()
+            flops = rounding_counts(spec, dims, r, ROUND_P, s)
+            out["rows"][f"{name}:r{r}"] = {"rank": r, "mean_rel_error": sum(errs) / len(errs),
+                                          "max_rel_error": max(errs), "ms_per_rounding": ms,
+                                          "sketch_flops": flops,
+                                          "TFLOPs_whole_rounding": flops / (ms * 1e-3) / 1e12}
+            print(f"# rounding {name} r={r}: {ms:.3f} ms, error {sum(errs) / len(errs):.3e}",
+                  file=sys.stderr, flush=True)
+        del dc
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline_rounding(args, r=48):
+    """The oracle (plain NumPy FP64 tree contractions and recovery) on one rounding of
+    the quadratic-decay TTN of the rounding runs, same sizes: the CPU reference time."""
+    import numpy as np
+    import oracle as O
+    from oracle import structured as S
+    from workloads import synth as W
+
+    spec = ((((1, 2), 3), 4, (5, 6)))
+    dims = (args.round_n,) * 6
+    s = ROUND_TTN_RANK
+    sigma = np.array([ROUND_DECAYS["quadratic"](i) for i in range(1, s + 1)])
+    cores = W.decaying_ttn_cores(spec, dims, s, sigma, seed=7)
+    tree = O.Tree(spec, dims, r, ROUND_P)
+    X, Y = S.factors(300, dims, r, ROUND_P)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.assemble(S.ttn_sketch(cores, tree, X, Y), tree)
+        reps += 1
+        if time.perf_counter() - t0 > 3.0 or reps >= 50:
+            break
+    sec = (time.perf_counter() - t0) / reps
+    return {"value": sec * 1e3, "unit": "ms per rounding", "kind": "oracle", "rank": r,
+            "sample": f"{reps} roundings (structured sketch + assembly, maps drawn once)"}
+
+
 # ---------------------------------------------------------------- serving
 def _brief(name, st):
     print(f"# serving {name}: {st['updates_per_s']:.0f} updates/s, p50 {st['p50_ms']:.3f} ms, "
@@ -601,7 +739,7 @@ def roofline_of(flops, nbytes, ms, dtype):
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
 
 
-def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=None, traffic=None):
+def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=None, traffic=None, rounding=None):
     """The one JSON record the benchmark prints last (kept well under 4 KB): headline
     value, the sweep kernel's roofline and a step-level one, the CPU baseline and a
     short summary of every other measured configuration."""
@@ -658,6 +796,13 @@ def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=
     if hilbert is not None:
         line["hilbert_6d"] = {c: f"r{rows[-1]['rank']} err {rows[-1]['mean_rel_error']:.2g}"
                               for c, rows in hilbert["curves"].items()}
+    if rounding is not None:
+        rr = {"workload": rounding["workload"]}
+        for k, v in rounding["rows"].items():
+            rr[k] = f"{v['ms_per_rounding']:.3g} ms, err {v['mean_rel_error']:.2g}"
+        if rounding.get("cpu_baseline"):
+            rr["cpu_oracle_ms"] = round(rounding["cpu_baseline"]["value"], 1)
+        line["ttn_rounding"] = rr
     return line
 
 
@@ -671,6 +816,9 @@ def main():
 
     if args.hilbert_only:
         print(json.dumps(hilbert_bench(args)))
+        return
+    if args.rounding_only:
+        print(json.dumps(rounding_bench(args)))
         return
 
     import numpy as np
@@ -734,6 +882,11 @@ def main():
     hilbert = None
     if not args.no_hilbert:
         hilbert = hilbert_bench(args)
+    rounding = None
+    if not args.no_rounding:
+        rounding = rounding_bench(args)
+        if not args.no_cpu:
+            rounding["cpu_baseline"] = cpu_baseline_rounding(args)
     serving = None
     if not args.no_serve:
         del T_dev64
@@ -749,9 +902,9 @@ def main():
         print(f"# cpu baseline: {json.dumps(cpu['phases_s'])}", file=sys.stderr, flush=True)
 
     line = compact_line(args, key, results, cpu=cpu, serving=serving, hilbert=hilbert, copy=copy,
-                        traffic=measured_traffic(key))
+                        traffic=measured_traffic(key), rounding=rounding)
     detail = {"line": line, "results": results, "copy_calibration": copy, "serving": serving,
-              "hilbert_6d": hilbert, "input_generation_s": t_gen}
+              "hilbert_6d": hilbert, "ttn_rounding": rounding, "input_generation_s": t_gen}
     if args.detail:
         d = os.path.dirname(os.path.abspath(args.detail))
         os.makedirs(d, exist_ok=True)

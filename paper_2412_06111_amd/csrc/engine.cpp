@@ -837,7 +837,8 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   int max_k = 1, max_r = 1;
   for (int v = 1; v < nn; ++v) {
     const Node& t = P.nodes[v];
-    jl.jobs[jl.n++] = QrJob{t.Om, t.Q, t.Pinv, t.k, t.r};
+    jl.jobs[jl.n] = QrJob{t.Om, t.Q, t.Pinv, t.k, t.r, jl.n};
+    ++jl.n;
     max_k = std::max(max_k, t.k);
     max_r = std::max(max_r, t.r);
   }

@@ -80,12 +80,15 @@ KJob contraction(const double* core, const std::vector<int64_t>& axes, int oax, 
   j.oax = oax;
   j.cols = cols;
   j.out = out;
-  int64_t kred = 1;
+  int64_t kred = 1, n0 = 0;
   for (size_t q = 0; q < axes.size(); ++q) {
     j.size[q] = axes[q];
-    if (static_cast<int>(q) != oax) kred *= axes[q];
+    if (static_cast<int>(q) == oax) continue;
+    if (n0 == 0) n0 = axes[q];                         // the kernel's inner axis: first non-output axis
+    kred *= axes[q];
   }
-  j.G = kr_split(axes[oax], cols, kred);
+  if (n0 == 0) n0 = 1;
+  j.G = kr_split(axes[oax], cols, n0, kred / n0);
   if (j.G > 1) j.part = bump.take(kr_part_elems(j));
   return j;
 }

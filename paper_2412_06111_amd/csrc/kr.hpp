@@ -26,16 +26,17 @@ struct KJob {
   double* part = nullptr;
   int32_t naxes = 0, oax = 0, cols = 0, G = 1;
   // filled by the launcher
-  int64_t kred = 0, colchunks = 0, first_block = 0, fold_first = 0;
+  int64_t kred = 0, colchunks = 0, otiles = 0, first_block = 0, fold_first = 0;
 };
 struct KJobList {
   KJob jobs[kMaxKJobs];
   int n;
 };
 
-// Reduction split of a contraction with so outputs rows, cols columns, kred terms each
-// (a function of the shapes only).
-int kr_split(int64_t so, int cols, int64_t kred);
+// Reduction split of a contraction with so output rows and cols columns whose reduction
+// runs over an inner axis of n0 values and nouter outer combinations (a function of the
+// shapes only).
+int kr_split(int64_t so, int cols, int64_t n0, int64_t nouter);
 // Partial scratch a job needs (0 when G == 1).
 size_t kr_part_elems(const KJob& j);
 // Launch independent jobs (several kernels of at most kMaxKJobs jobs each).

@@ -42,6 +42,19 @@ __device__ inline double group8_sum(double v) {
 
 // Sum over the 64 lanes of a wave in a fixed order, returned to every lane: row sums
 // by DPP, rows combined by row broadcasts into lane 63, then read from lane 63.
+// The same over groups of 4 consecutive lanes (quad sums).
+__device__ inline double group4_sum(double v) {
+  v += dpp64<0xB1>(v);            // quad_perm [1,0,3,2]
+  v += dpp64<0x4E>(v);            // quad_perm [2,3,0,1]
+  return v;
+}
+
+template <int LPC>
+__device__ inline double group_sum(double v) {
+  static_assert(LPC == 4 || LPC == 8, "4 or 8 lanes per column");
+  return LPC == 8 ? group8_sum(v) : group4_sum(v);
+}
+
 __device__ inline double wave_sum64(double v) {
   v += dpp64<0xB1>(v);
   v += dpp64<0x4E>(v);
@@ -83,40 +96,41 @@ __device__ inline void apply_reflector(const double* A, int ld, int k, int j, do
 }
 
 // ---------------------------------------------------------------- register path
-// r <= 32 and k <= 8 TM: column c of Omega lives in the registers of the 8 lanes
-// tid = 8 c .. 8 c + 7 (lane sub holds rows sub + 8 t, t < TM).  A factorization step
+// r <= 256 / LPC and k <= LPC TM: column c of Omega lives in the registers of the LPC
+// lanes tid = LPC c .. LPC c + LPC - 1 (lane sub holds rows sub + LPC t, t < TM); 8
+// lanes per column up to r = 32, 4 up to r = 64.  A factorization step
 // forms the reflector in its column's lanes, broadcasts it through LDS (double
 // buffered) and takes one barrier; every other column applies it in registers.  Q and
 // R^{-1} are then formed column by column from reflectors and R in LDS, with no
 // barrier.  Returns true on the fast path (Q, Pinv = R^{-1}, kept written); otherwise
 // leaves R in W and the identity in V (leading dimension r) for the Jacobi path.
-template <int TM>
+template <int TM, int LPC>
 __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, double* W, double* V,
                         double* vb, double* tau_s, double* red, int* kept) {
   const int k = job.k, r = job.r;
-  const int tid = threadIdx.x, c = tid >> 3, sub = tid & 7;
+  const int tid = threadIdx.x, c = tid / LPC, sub = tid % LPC;
   const bool own = c < r;
   double a[TM];
 #pragma unroll
   for (int t = 0; t < TM; ++t) {
-    const int i = sub + 8 * t;
+    const int i = sub + LPC * t;
     a[t] = (own && i < k) ? job.Om[i + static_cast<int64_t>(k) * c] : 0.0;
   }
   // ---- factorization (LAPACK dlarfg convention, v_j = 1)
   for (int j = 0; j < r; ++j) {
-    double* vj = vb + (j & 1) * 8 * TM;
+    double* vj = vb + (j & 1) * LPC * TM;
     if (c == j) {
       double n0 = 0.0, n1 = 0.0, al = 0.0;
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const int i = sub + 8 * t;
+        const int i = sub + LPC * t;
         const double x = i > j ? a[t] : 0.0;
         if (t & 1) n1 = fma(x, x, n1);
         else n0 = fma(x, x, n0);
         al += i == j ? a[t] : 0.0;
       }
-      const double xnorm2 = group8_sum(n0 + n1);
-      const double alpha = group8_sum(al);
+      const double xnorm2 = group_sum<LPC>(n0 + n1);
+      const double alpha = group_sum<LPC>(al);
       double tau = 0.0, beta = alpha, scale = 0.0;
       if (xnorm2 > 0.0) {
         beta = -copysign(sqrt(alpha * alpha + xnorm2), alpha);
@@ -125,7 +139,7 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
       }
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const int i = sub + 8 * t;
+        const int i = sub + LPC * t;
         const double v = i > j ? a[t] * scale : (i == j ? 1.0 : 0.0);
         vj[i] = v;
         a[t] = i > j ? v : (i == j ? beta : a[t]);
@@ -140,11 +154,11 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
         double w0 = 0.0, w1 = 0.0;
 #pragma unroll
         for (int t = 0; t < TM; ++t) {
-          v[t] = vj[sub + 8 * t];
+          v[t] = vj[sub + LPC * t];
           if (t & 1) w1 = fma(v[t], a[t], w1);
           else w0 = fma(v[t], a[t], w0);
         }
-        const double w = group8_sum(w0 + w1) * tau;
+        const double w = group_sum<LPC>(w0 + w1) * tau;
 #pragma unroll
         for (int t = 0; t < TM; ++t) a[t] = fma(-w, v[t], a[t]);
       }
@@ -154,7 +168,7 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   if (own) {
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      const int i = sub + 8 * t;
+      const int i = sub + LPC * t;
       if (i < k) A[i + ld * c] = a[t];
     }
   }
@@ -165,7 +179,7 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   {
     double q[TM];
 #pragma unroll
-    for (int t = 0; t < TM; ++t) q[t] = (sub + 8 * t) == c ? 1.0 : 0.0;
+    for (int t = 0; t < TM; ++t) q[t] = (sub + LPC * t) == c ? 1.0 : 0.0;
     for (int j = r - 1; j >= 0; --j) {
       const double tau = tau_s[j];
       if (tau == 0.0) continue;
@@ -173,19 +187,19 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
       double w0 = 0.0, w1 = 0.0;
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const int i = sub + 8 * t;
+        const int i = sub + LPC * t;
         v[t] = i > j ? (i < k ? A[i + ld * j] : 0.0) : (i == j ? 1.0 : 0.0);
         if (t & 1) w1 = fma(v[t], q[t], w1);
         else w0 = fma(v[t], q[t], w0);
       }
-      const double w = group8_sum(w0 + w1) * tau;
+      const double w = group_sum<LPC>(w0 + w1) * tau;
 #pragma unroll
       for (int t = 0; t < TM; ++t) q[t] = fma(-w, v[t], q[t]);
     }
     if (own) {
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const int i = sub + 8 * t;
+        const int i = sub + LPC * t;
         if (i < k) job.Q[i + static_cast<int64_t>(k) * c] = sgn * q[t];
       }
     }
@@ -195,7 +209,7 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   double wn = 0.0;
 #pragma unroll
   for (int t = 0; t < TM; ++t) {
-    const int i = sub + 8 * t;
+    const int i = sub + LPC * t;
     double x = 0.0;
     if (own && i <= c) x = A[i + ld * i] < 0.0 ? -a[t] : a[t];
     w[t] = x;
@@ -205,7 +219,7 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   if (own) {
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      const int i = sub + 8 * t;
+      const int i = sub + LPC * t;
       if (i < r) W[i + r * c] = w[t];
     }
   }
@@ -213,36 +227,36 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   // ---- V = W^{-1} column by column: x = W^{-1} e_c, m = r-1 .. 0
   double x[TM];
 #pragma unroll
-  for (int t = 0; t < TM; ++t) x[t] = (sub + 8 * t) == c ? 1.0 : 0.0;
+  for (int t = 0; t < TM; ++t) x[t] = (sub + LPC * t) == c ? 1.0 : 0.0;
   bool nonsingular = true;
   for (int m = r - 1; m >= 0; --m) {
     const double dm = W[m + r * m];
     nonsingular = nonsingular && dm > 0.0;
     double xl = 0.0;
 #pragma unroll
-    for (int t = 0; t < TM; ++t) xl += (sub + 8 * t) == m ? x[t] : 0.0;
-    const double xm = group8_sum(xl) / dm;
+    for (int t = 0; t < TM; ++t) xl += (sub + LPC * t) == m ? x[t] : 0.0;
+    const double xm = group_sum<LPC>(xl) / dm;
 #pragma unroll
     for (int t = 0; t < TM; ++t) {
-      const int i = sub + 8 * t;
+      const int i = sub + LPC * t;
       const double wim = i < m ? W[i + r * m] : 0.0;
       x[t] = i == m ? xm : (i < m ? fma(-xm, wim, x[t]) : x[t]);
     }
   }
   double vn = 0.0;
 #pragma unroll
-  for (int t = 0; t < TM; ++t) vn += (own && (sub + 8 * t) < r) ? x[t] * x[t] : 0.0;
+  for (int t = 0; t < TM; ++t) vn += (own && (sub + LPC * t) < r) ? x[t] * x[t] : 0.0;
   const double inv2 = block_sum(vn, red);
   const bool fast = nonsingular && (sqrt(rnorm2 * inv2) * eps_factor < 0.5);
   if (fast) {
     if (own) {
 #pragma unroll
       for (int t = 0; t < TM; ++t) {
-        const int i = sub + 8 * t;
+        const int i = sub + LPC * t;
         if (i < r) job.Pinv[i + r * c] = x[t];
       }
     }
-    if (tid == 0) kept[blockIdx.x] = r;
+    if (tid == 0) kept[job.slot] = r;
     return true;
   }
   for (int e = tid; e < r * r; e += kThreads) V[e] = ((e % r) == (e / r)) ? 1.0 : 0.0;
@@ -250,6 +264,9 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   return false;
 }
 
+// WIDE: the kernel of the jobs with 32 < r <= 64, k <= 64 (4 lanes per column); kept
+// apart so that its register demand does not lower the occupancy of the narrow paths.
+template <bool WIDE>
 __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double eps_factor, int* kept) {
   extern __shared__ double lds[];
   __shared__ double red[4];
@@ -266,13 +283,15 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   double* W = Qm;                // r x r (after Q is stored): R, then the Jacobi columns
   double* V = A;                 // r x r (after R is extracted): R^{-1}, or right singular vectors
 
-  __shared__ double vb[2 * 8 * 16];
-  const int tm = r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
+  __shared__ double vb[2 * 128];
+  // register path: 8 lanes per column for r <= 32 (k <= 128), 4 for r <= 64 (k <= 64)
+  const int tm = WIDE ? 16 : r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
   if (tm != 0) {
-    const bool f = tm == 4    ? qr_regs<4>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
-                   : tm == 6 ? qr_regs<6>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
-                   : tm == 8 ? qr_regs<8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
-                             : qr_regs<16>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept);
+    const bool f = WIDE       ? qr_regs<16, 4>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                   : tm == 4  ? qr_regs<4, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                   : tm == 6  ? qr_regs<6, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                   : tm == 8  ? qr_regs<8, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+                              : qr_regs<16, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept);
     if (f) return;
   } else {
   for (int e = tid; e < k * r; e += kThreads) A[e % k + ld * (e / k)] = job.Om[e];
@@ -361,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
     __syncthreads();
     if (fast) {
       for (int e = tid; e < r * r; e += kThreads) job.Pinv[e] = V[e];
-      if (tid == 0) kept[blockIdx.x] = r;
+      if (tid == 0) kept[job.slot] = r;
       return;
     }
   }
@@ -369,9 +388,13 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   __syncthreads();
   }
 
-  // ---- one-sided Jacobi on the columns of W (r x r)
+  // ---- one-sided Jacobi on the columns of W (r x r).  A pair is rotated while its
+  // cosine exceeds twice the rounding bound r u of the length-r dot product that measures
+  // it (u = 2^-53): below that the computed cosine is noise, and a threshold under it
+  // keeps rotating noise (columns of tiny norm next to large ones) until the sweep cap.
   const int R2 = r + (r & 1);                 // pad to even with a virtual zero column
   const int npairs = R2 / 2;
+  const double jtol = fmax(1e-15, r * 0x1p-52);
   for (int sweep = 0; sweep < 60; ++sweep) {
     if (tid == 0) any_rot = 0;
     __syncthreads();
@@ -394,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
         al = group8_sum(al);
         be = group8_sum(be);
         ga = group8_sum(ga);
-        if (q < r && ga != 0.0 && fabs(ga) > 1e-15 * sqrt(al * be)) {
+        if (q < r && ga != 0.0 && fabs(ga) > jtol * sqrt(al * be)) {
           const double zeta = (be - al) / (2.0 * ga);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t);
@@ -437,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   if (tid == 0) {
     int cnt = 0;
     for (int p = 0; p < r; ++p) cnt += sig[p] > eps ? 1 : 0;
-    kept[blockIdx.x] = cnt;
+    kept[job.slot] = cnt;
   }
 }
 
@@ -488,16 +511,26 @@ __global__ void diff_norm_final(const double* part, int nb, double* out) {
 
 void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t st) {
   if (jl.n <= 0) return;
-  const size_t lds = static_cast<size_t>(2 * (max_k | 1) * max_r) * sizeof(double);
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(qr_pinv_kernel),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error{TTNN_E_INVALID, "recovery kernel needs " + std::to_string(lds) + " bytes of LDS"};
-    }
+  QrJobList lists[2] = {};
+  for (int i = 0; i < jl.n; ++i) {
+    const QrJob& j = jl.jobs[i];
+    const int w = (j.r > 32 && j.r <= 64 && j.k <= 64) ? 1 : 0;
+    lists[w].jobs[lists[w].n++] = j;
   }
-  hipLaunchKernelGGL(qr_pinv_kernel, dim3(jl.n), dim3(kThreads), lds, st, jl, eps_factor, d_kept);
+  const size_t lds = static_cast<size_t>(2 * (max_k | 1) * max_r) * sizeof(double);
+  auto launch = [&](const void* fn, const QrJobList& l, void (*k)(QrJobList, double, int*)) {
+    if (l.n == 0) return;
+    if (lds > 64 * 1024) {
+      const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error{TTNN_E_INVALID, "recovery kernel needs " + std::to_string(lds) + " bytes of LDS"};
+      }
+    }
+    hipLaunchKernelGGL(k, dim3(l.n), dim3(kThreads), lds, st, l, eps_factor, d_kept);
+  };
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<false>), lists[0], qr_pinv_kernel<false>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<true>), lists[1], qr_pinv_kernel<true>);
 }
 
 void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t st) {
