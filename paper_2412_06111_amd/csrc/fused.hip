@@ -237,9 +237,9 @@ template <int DT, int R, int KP, int B2, int SC, bool TT, bool ZO>
 __global__ __launch_bounds__(kThreadsF) void sttnn_t4_kernel(SttnnArgs a) {
   using P = Pol<DT>;
   using W = Wide<P>;
-  // FP32 Z1-out and TTNN forms at r = 32 (two slabs per tile): the tile's Y_A rows (and
-  // X_B rows) stay resident
-  static constexpr bool YR = (ZO || TT) && DT != TTNN_F64 && R == 32;
+  // FP32 / BF16 Z1-out and TTNN forms at r = 32, and the BF16 Z1-out form at r = 64 (two
+  // slabs per tile, 32-column sub-tiles): the tile's Y_A rows (and X_B rows) stay resident
+  static constexpr bool YR = ((ZO || TT) && DT != TTNN_F64 && R == 32) || (DT == TTNN_BF16 && ZO && !TT && R == 64);
   using Lay = SttnnLayout<DT, R, KP, B2, SC, TT, YR, ZO>;
   using T = typename P::T;
   using Acc = typename P::Acc;
@@ -865,24 +865,27 @@ constexpr int b2_of() {
          : DT == TTNN_F32 ? (R >= 64 || ((ZO || TT) && R == 32) ? 2 : 4)
                           : (R >= 64 || TT ? 2 : 4);
 }
-template <int DT>
+// BF16 Z1-out at r = 64 takes 32-column sub-tiles: with them the FP32 Z1 stash, the
+// resident Y_A rows of both slabs and staged X_A / X_1 rows fit the LDS (at 64 columns
+// the Y_A rows were re-copied every sub-tile and X_A / X_1 read from L2).
+template <int DT, int R = 32, bool ZO = false>
 constexpr int sc_of() {
-  return DT == TTNN_BF16 ? 64 : 32;
+  return DT == TTNN_BF16 ? (ZO && R >= 64 ? 32 : 64) : 32;
 }
 
 Shape shape_for(int dt, int R, bool tt, bool zout) {
-  if (dt == TTNN_BF16) return {R >= 64 ? 2 : (zout || tt) && R == 32 ? 4 : 8, 64};
+  if (dt == TTNN_BF16) return {R >= 64 ? 2 : (zout || tt) && R == 32 ? 4 : 8, zout && !tt && R >= 64 ? 32 : 64};
   if (dt == TTNN_F32) return {R >= 64 || ((zout || tt) && R == 32) ? 2 : 4, 32};
   return {R >= 64 || tt ? 2 : 4, 32};
 }
 
 template <int DT, int R, int KP>
 void launch_sttnn(bool tt, bool zout, const SttnnArgs& a, hipStream_t st) {
-  constexpr int SC = sc_of<DT>();
+  constexpr int SC = sc_of<DT>(), SCZ = sc_of<DT, R, true>();
   constexpr int B2T = b2_of<DT, R, true>(), B2S = b2_of<DT, R, false>(), B2Z = b2_of<DT, R, false, true>();
   const dim3 grid(a.TA * a.TB);
   if (tt) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2T, SC, true, false>), grid, dim3(kThreadsF), 0, st, a);
-  else if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2Z, SC, false, true>), grid, dim3(kThreadsF), 0, st, a);
+  else if (zout) hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2Z, SCZ, false, true>), grid, dim3(kThreadsF), 0, st, a);
   else hipLaunchKernelGGL((sttnn_t4_kernel<DT, R, KP, B2S, SC, false, false>), grid, dim3(kThreadsF), 0, st, a);
 }
 
