@@ -256,8 +256,8 @@ struct QrJobList {
   QrJob jobs[TTNN_MAX_NODES];
   int n;
 };
-// Jobs with 32 < r <= 64 and k <= 64 run in a kernel of their own (4 lanes per column),
-// the others in the kernel of the narrower register paths and the LDS path.
+// Jobs with 32 < r <= 64 and k <= 64, or k <= 96, run in kernels of their own (4 lanes
+// per column), the others in the kernel of the narrower register paths and the LDS path.
 void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t stream);
 // Status of one assembly from its flags (flags[0] non-finite count, flags[1..nn-1] kept
 // singular values per node): *call = 1 if bad else 0, and *sticky |= *call.

@@ -264,9 +264,11 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
   return false;
 }
 
-// WIDE: the kernel of the jobs with 32 < r <= 64, k <= 64 (4 lanes per column); kept
-// apart so that its register demand does not lower the occupancy of the narrow paths.
-template <bool WIDE>
+// WTM: 0 for the narrow register paths (r <= 32) and the LDS path; 16 or 24 for the
+// jobs with 32 < r <= 64 and k <= 64 or k <= 96 (4 lanes per column, WTM rows a lane).
+// Each form is an instance of its own so that its register demand does not lower the
+// occupancy of the others.
+template <int WTM>
 __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double eps_factor, int* kept) {
   extern __shared__ double lds[];
   __shared__ double red[4];
@@ -285,9 +287,9 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
 
   __shared__ double vb[2 * 128];
   // register path: 8 lanes per column for r <= 32 (k <= 128), 4 for r <= 64 (k <= 64)
-  const int tm = WIDE ? 16 : r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
+  const int tm = WTM ? WTM : r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
   if (tm != 0) {
-    const bool f = WIDE       ? qr_regs<16, 4>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
+    const bool f = WTM        ? qr_regs<(WTM ? WTM : 16), 4>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
                    : tm == 4  ? qr_regs<4, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
                    : tm == 6  ? qr_regs<6, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
                    : tm == 8  ? qr_regs<8, 8>(job, eps_factor, A, ld, W, V, vb, tau_s, red, kept)
@@ -511,10 +513,10 @@ __global__ void diff_norm_final(const double* part, int nb, double* out) {
 
 void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t st) {
   if (jl.n <= 0) return;
-  QrJobList lists[2] = {};
+  QrJobList lists[3] = {};
   for (int i = 0; i < jl.n; ++i) {
     const QrJob& j = jl.jobs[i];
-    const int w = (j.r > 32 && j.r <= 64 && j.k <= 64) ? 1 : 0;
+    const int w = (j.r > 32 && j.r <= 64) ? (j.k <= 64 ? 1 : j.k <= 96 ? 2 : 0) : 0;
     lists[w].jobs[lists[w].n++] = j;
   }
   const size_t lds = static_cast<size_t>(2 * (max_k | 1) * max_r) * sizeof(double);
@@ -529,8 +531,9 @@ void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor
     }
     hipLaunchKernelGGL(k, dim3(l.n), dim3(kThreads), lds, st, l, eps_factor, d_kept);
   };
-  launch(reinterpret_cast<const void*>(qr_pinv_kernel<false>), lists[0], qr_pinv_kernel<false>);
-  launch(reinterpret_cast<const void*>(qr_pinv_kernel<true>), lists[1], qr_pinv_kernel<true>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<0>), lists[0], qr_pinv_kernel<0>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<16>), lists[1], qr_pinv_kernel<16>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<24>), lists[2], qr_pinv_kernel<24>);
 }
 
 void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t st) {
