@@ -3,9 +3,9 @@
 // per tree node:
 //   1. Householder QR of Omega_t (k x r, k >= r), reflectors kept in LDS;
 //      Q = H_0 ... H_{r-1} [I; 0];  signs flipped so that diag(R) >= 0.
-//   2. One-sided (Hestenes) Jacobi SVD of the r x r factor R: column pairs are
-//      rotated in round-robin order until every pair is orthogonal to working
-//      precision; sigma_p = ||a_p||, u_p = a_p / sigma_p, V accumulates rotations.
+//   2. One-sided (Hestenes) Jacobi SVD of the r x r factor R, applied to R^T: column
+//      pairs of R^T are rotated in round-robin order until every pair is orthogonal to
+//      working precision; sigma_p = ||w_p||, V accumulates the rotations.
 //   3. R^{+eps} = sum_{sigma_p > eps} v_p u_p^T / sigma_p with eps = eps_factor * max sigma.
 //   When ||R||_F ||R^{-1}||_F < 1/(2 eps_factor) no singular value can fall below
 //   eps, so R^{+eps} = R^{-1} is formed by back substitution and the SVD is skipped.
@@ -390,10 +390,22 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   __syncthreads();
   }
 
-  // ---- one-sided Jacobi on the columns of W (r x r).  A pair is rotated while its
-  // cosine exceeds twice the rounding bound r u of the length-r dot product that measures
-  // it (u = 2^-53): below that the computed cosine is noise, and a threshold under it
-  // keeps rotating noise (columns of tiny norm next to large ones) until the sweep cap.
+  // ---- one-sided Jacobi on the columns of W = R^T (the rows of R): on the graded,
+  // ill-conditioned triangular factors of these sketches the rows converge in about 10
+  // sweeps where the columns take 25 (the preconditioning effect of the QR that
+  // Drmac and Veselic describe for one-sided Jacobi).  W V = U S with V orthogonal gives
+  // R = V S U^T, so R^+ = U S^-1 V^T = sum_p w_p v_p^T / s_p^2.  A pair is rotated while
+  // its cosine exceeds twice the rounding bound r u of the length-r dot product that
+  // measures it (u = 2^-53).
+  for (int e = tid; e < r * r; e += kThreads) {
+    const int i = e % r, c = e / r;
+    if (i < c) {
+      const double t = W[i + r * c];
+      W[i + r * c] = W[c + r * i];
+      W[c + r * i] = t;
+    }
+  }
+  __syncthreads();
   const int R2 = r + (r & 1);                 // pad to even with a virtual zero column
   const int npairs = R2 / 2;
   const double jtol = fmax(1e-15, r * 0x1p-52);
@@ -453,10 +465,10 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   for (int c = 0; c < r; ++c) smax = fmax(smax, sig[c]);
   const double eps = eps_factor * smax;
   for (int e = tid; e < r * r; e += kThreads) {
-    const int i = e % r, j = e / r;            // Pinv(i, j) = sum_p V(i,p) W(j,p) / sigma_p^2
+    const int i = e % r, j = e / r;            // Pinv(i, j) = sum_p W(i,p) V(j,p) / sigma_p^2
     double s = 0.0;
     for (int p = 0; p < r; ++p)
-      if (sig[p] > eps) s += V[i + r * p] * W[j + r * p] / (sig[p] * sig[p]);
+      if (sig[p] > eps) s += W[i + r * p] * V[j + r * p] / (sig[p] * sig[p]);
     job.Pinv[e] = s;
   }
   if (tid == 0) {
