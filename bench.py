@@ -66,6 +66,7 @@ def parse():
                     help="the Poisson load (a fraction of the batched path's closed-loop rate) summarised in the record")
     ap.add_argument("--serve-loads", default="0.25,0.5,0.8", help="Poisson loads run (fractions of the closed-loop rate)")
     ap.add_argument("--no-rounding", action="store_true", help="skip the TTN rounding runs (Khatri-Rao maps)")
+    ap.add_argument("--no-pipeline", action="store_true", help="skip the two-plan throughput runs")
     ap.add_argument("--rounding-only", action="store_true",
                     help="run only the TTN rounding runs and print them as one JSON line")
     ap.add_argument("--round-n", type=int, default=500)
@@ -280,6 +281,50 @@ def run_gpu(args, T_dev64, variant, dtype, rank=None, over=None, keep_sketches=F
     plan.close()
     torch.cuda.empty_cache()
     return res
+
+
+def run_pipelined(args, T_dev64, variant, dtype, nplans=2):
+    """Throughput with `nplans` plans of the same problem taking the steps in turn, each on
+    a stream of its own (reset + whole-tensor update + enqueued assembly, as in run_gpu),
+    so that one step's FP64 tail runs while the next step's sweep starts: ms per step =
+    wall time over the timed steps.  Every step does the whole work of a step."""
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads.serving import T4
+
+    dims = (args.n,) * 4
+    X = T_dev64 if dtype == "f64" else T_dev64.to(torch.float32)
+    if dtype == "bf16":
+        X = X.to(torch.bfloat16)
+    streams = [torch.cuda.Stream() for _ in range(nplans)]
+    plans, cores = [], []
+    for k in range(nplans):
+        with torch.cuda.stream(streams[k]):
+            plans.append(P.Plan(T4, dims, args.rank, args.over, variant=variant, dtype=dtype, seed=1,
+                                stream=streams[k]))
+            cores.append(plans[-1].alloc_cores())
+    torch.cuda.synchronize()
+
+    def run(n):
+        for i in range(n):
+            k = i % nplans
+            with torch.cuda.stream(streams[k]):
+                plans[k].reset(stream=streams[k])
+                plans[k].update(X, stream=streams[k])
+                plans[k].assemble_async(cores[k], stream=streams[k])
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    tic = time.perf_counter()
+    run(args.steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - tic) * 1e3 / args.steps
+    for k in range(nplans):
+        plans[k].assemble_status(stream=streams[k])      # every assembly was numerically sound
+        plans[k].close()
+    del X
+    torch.cuda.empty_cache()
+    return ms
 
 
 # ---------------------------------------------------------------- 6-D Hilbert curves
@@ -877,6 +922,13 @@ def main():
         measure("sttnn", "bf16", rr, rr // 2, f"sttnn:bf16:r{rr}", ref)
 
     key = args.headline if args.headline in results else next(iter(results))
+    pipelined = {}
+    if not args.no_pipeline:
+        for k in ("sttnn:f32", "sttnn:bf16"):
+            if k in results:
+                v, d = k.split(":")
+                pipelined[k] = run_pipelined(args, T_dev64, v, d)
+                print(f"# {k} two plans in turn: {pipelined[k]:.3f} ms/step", file=sys.stderr, flush=True)
     copy = copy_rate()
 
     hilbert = None
@@ -903,8 +955,11 @@ def main():
 
     line = compact_line(args, key, results, cpu=cpu, serving=serving, hilbert=hilbert, copy=copy,
                         traffic=measured_traffic(key), rounding=rounding)
+    if pipelined:
+        line["two_plans_in_turn_ms_per_step"] = {k: round(v, 4) for k, v in pipelined.items()}
     detail = {"line": line, "results": results, "copy_calibration": copy, "serving": serving,
-              "hilbert_6d": hilbert, "ttn_rounding": rounding, "input_generation_s": t_gen}
+              "hilbert_6d": hilbert, "ttn_rounding": rounding, "two_plans_in_turn_ms_per_step": pipelined,
+              "input_generation_s": t_gen}
     if args.detail:
         d = os.path.dirname(os.path.abspath(args.detail))
         os.makedirs(d, exist_ok=True)
