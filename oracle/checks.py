@@ -6,7 +6,8 @@ sketch.py / recover.py.
 
   * projector form of the approximant (Sec. 4, eq. of the projectors and the
     product over levels; Sec. 5, eq. of the sequential projection and the STTNN
-    approximant): T_hat^D = prod_{l=L..1} (kron_k P_{l,k}) T^D, dummies = identity;
+    approximant): T_hat^D = prod_{l=L..1} (kron_k P_{l,k}) T^D, dummies and free
+    modes = identity;
   * stabilised generalised Nystrom for a matrix (Sec. 2, Alg. 1 and the
     eps-pseudoinverse variant);
   * the error-analysis quantities of Lemma 2, Lemma 3 / Theorems 1 and 3, and the
@@ -65,11 +66,16 @@ def contracted_unfolding(T, tree: Tree, D, t, variant):
     Tt = unfold_explicit(T, [m - 1 for m in node.modes])
     if variant == "ttnn":
         return Tt
-    S = tree.S(t)
-    right = 1
-    for m in range(node.last + 1, tree.d + 1):
-        right *= tree.dims[m - 1]
-    K = kron_rev([D.Y[s] for s in S] + [np.eye(right)])
+    # the column index of T^{t} runs over the modes outside t in order: Y_s on each
+    # contracted group of S_t, the identity on every other mode
+    items, covered = [], set()
+    for s in tree.S(t):
+        items.append((tree[s].first, D.Y[s]))
+        covered.update(tree[s].modes)
+    for m in range(1, tree.d + 1):
+        if m not in node.modes and m not in covered:
+            items.append((m, np.eye(tree.dims[m - 1])))
+    K = kron_rev([M for _, M in sorted(items, key=lambda it: it[0])])
     return Tt @ K
 
 
@@ -81,19 +87,24 @@ def projector(T, tree: Tree, D, t, variant, eps_factor=DEFAULT_EPS_FACTOR):
 
 def level_groups(tree: Tree, level):
     """Mode groups at `level` of the extended tree, left to right: real nodes at
-    that level, plus dummy extensions of shallower leaves."""
+    that level, dummy extensions of shallower leaves, and the free modes of
+    shallower nodes (identity groups, ("f", mode))."""
     out = []
     for n in tree.nodes:
         if n.level == level or (n.is_leaf and n.level < level):
-            out.append(n.id)
-    return sorted(out, key=lambda i: tree[i].first)
+            out.append((n.first, n.id))
+        if n.level < level:
+            out += [(m, ("f", m)) for m in n.free]
+    return [g for _, g in sorted(out, key=lambda it: it[0])]
 
 
 def level_operator(tree: Tree, level, mats):
     """kron over the groups of `level` of mats[id] (identity where id not in mats)."""
     facs = []
     for g in level_groups(tree, level):
-        if g in mats and tree[g].level == level:
+        if isinstance(g, tuple):
+            facs.append(np.eye(tree.dims[g[1] - 1]))
+        elif g in mats and tree[g].level == level:
             facs.append(mats[g])
         else:
             facs.append(np.eye(tree.n_of(g)))

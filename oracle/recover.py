@@ -9,6 +9,8 @@ section):
     leaf      B_t = Psi_t Rt_t^{+eps}                               (n_t x r_t)
     internal  B_t = (Q_cm^T kron ... kron Q_c1^T) Psi_t Rt_t^{+eps} (prod r_c x r_t)
     root      B_0 = (Q_cm^T kron ... kron Q_c1^T) Psi_0             (prod r_c)
+    (a free mode of a node takes the identity in place of Q_c^T and its size n_m in
+    place of r_c)
 Cores are stored column-major with the parent's rank index last.
 
 Reconstruction (Def. 5 and its matricised form): U_leaf = B_leaf,
@@ -43,13 +45,15 @@ def eps_pinv(M, eps_factor=DEFAULT_EPS_FACTOR):
 
 
 def _kron_apply(tree: Tree, t, M, mats):
-    """(mats[cm] kron ... kron mats[c1]) applied to the rows of M (child c1 fastest)."""
-    ch = tree[t].children
+    """(mats[cm] kron ... kron mats[c1]) applied to the rows of M (child c1 fastest),
+    the identity at free-mode positions."""
+    pos = tree.positions(t)
     cols = M.shape[1] if M.ndim == 2 else 1
-    sizes = [mats[c].shape[1] for c in ch]
+    sizes = [mats[x].shape[1] if kind == "c" else tree.dims[x - 1] for kind, x in pos]
     Z = M.reshape(sizes + [cols], order="F")
-    for i, c in enumerate(ch):
-        Z = group_product(Z, [i], mats[c].T)
+    for i, (kind, x) in enumerate(pos):
+        if kind == "c":
+            Z = group_product(Z, [i], mats[x].T)
     return Z.reshape((-1, cols), order="F")
 
 
@@ -72,11 +76,12 @@ def assemble(sk, tree: Tree, eps_factor=DEFAULT_EPS_FACTOR):
 
 def core_shape(tree: Tree, t):
     n = tree[t]
+    inner = tuple(tree[x].rank if kind == "c" else tree.dims[x - 1] for kind, x in tree.positions(t))
     if t == 0:
-        return tuple(tree[c].rank for c in n.children)
+        return inner
     if n.is_leaf:
         return (tree.n_of(t), n.rank)
-    return tuple(tree[c].rank for c in n.children) + (n.rank,)
+    return inner + (n.rank,)
 
 
 def reconstruct(cores, tree: Tree):

@@ -75,40 +75,44 @@ def _node_axes(tree, t):
 
 
 def root_sketch(T, tree: Tree, D: DRMs):
-    """Psi at the root: T contracted with Y_c^T over every child group, vectorised."""
+    """Psi at the root: T contracted with Y_c^T over every child group (free modes of
+    the root left as they are), vectorised."""
     Z = T
     pos = 0
-    for c in tree[0].children:
-        width = len(tree[c].modes)
-        Z = group_product(Z, range(pos, pos + width), D.Y[c])
+    for kind, x in tree.positions(0):
+        if kind == "c":
+            width = len(tree[x].modes)
+            Z = group_product(Z, range(pos, pos + width), D.Y[x])
         pos += 1
     return Z.reshape(-1, order="F")
 
 
 def right_sketch(T, tree: Tree, D: DRMs, t: int, variant: str):
-    """R_t of TTNN (S_t empty) or STTNN (S_t from tree.S)."""
+    """R_t of TTNN (S_t empty) or STTNN (S_t from tree.S): T contracted with Y_s^T over
+    every group s of S_t (each collapsed in place to one index), then unfolded at the
+    modes of t and multiplied by X_t (rows over the remaining indices in order)."""
     Z = T
     S = tree.S(t) if variant == "sttnn" else []
-    pos = 0
-    for s in S:                                # S covers the modes left of t, in order
-        width = len(tree[s].modes)
-        Z = group_product(Z, range(pos, pos + width), D.Y[s])
-        pos += 1
-    # after the S-contractions the modes of t sit right after the |S| contracted
-    # indices (S covers exactly the modes left of t); with S empty they keep
-    # their own positions
-    first = pos if S else tree[t].first - 1
-    tax = list(range(first, first + len(tree[t].modes)))
+    labels = list(range(1, tree.d + 1))          # each axis labelled by its first mode
+    for s in S:
+        i, width = labels.index(tree[s].first), len(tree[s].modes)
+        Z = group_product(Z, range(i, i + width), D.Y[s])
+        labels[i:i + width] = [tree[s].first]
+    i = labels.index(tree[t].first)
+    tax = list(range(i, i + len(tree[t].modes)))
     return unfold(Z, tax) @ D.X[t]
 
 
 def psi_internal(tree: Tree, D: DRMs, t: int, R):
-    """(Y_cm^T kron ... kron Y_c1^T) R_t computed as successive group products."""
-    sizes = [tree.n_of(c) for c in tree[t].children]
+    """(Y_cm^T kron ... kron Y_c1^T) R_t computed as successive group products, with
+    the identity at free-mode positions."""
+    pos = tree.positions(t)
+    sizes = [tree.n_of(x) if kind == "c" else tree.dims[x - 1] for kind, x in pos]
     r = R.shape[1]
     Z = R.reshape(sizes + [r], order="F")
-    for i, c in enumerate(tree[t].children):
-        Z = group_product(Z, [i], D.Y[c])
+    for i, (kind, x) in enumerate(pos):
+        if kind == "c":
+            Z = group_product(Z, [i], D.Y[x])
     return Z.reshape((-1, r), order="F")
 
 
@@ -156,6 +160,8 @@ def box_drms(tree: Tree, seed: int, variant: str, offset, ext):
     """The DRM rows a box update touches: Y_s rows over the box for every group that
     is contracted (STTNN reuse sets and root children), X_t rows over the box
     (full range on contracted indices) for every non-root t."""
+    if tree.has_free_modes:
+        raise ValueError("box updates of trees with free modes are not modelled here")
     from .drm import gaussian
     dims = tree.dims
     off = tuple(int(o) for o in offset)

@@ -56,6 +56,8 @@ class KRDRMs:
     """Dense Khatri-Rao maps of every non-root node (the definition)."""
 
     def __init__(self, tree: Tree, X, Y):
+        if tree.has_free_modes:
+            raise ValueError("Khatri-Rao maps are modelled for trees without free modes")
         self.X, self.Y = {}, {}
         for n in tree.nodes[1:]:
             outside = [m - 1 for m in range(1, tree.d + 1) if m not in n.modes]
@@ -124,6 +126,8 @@ def ttn_sketch(cores, tree: Tree, X, Y):
     """Omega_t, Psi_t (R_t for leaves) and Psi_0 of the TTN with the given cores under
     the Khatri-Rao maps of X, Y, by tree contraction (same dict layout as oracle.sketch,
     without R for internal nodes)."""
+    if tree.has_free_modes:
+        raise ValueError("Khatri-Rao maps are modelled for trees without free modes")
     dx = down_vectors(tree, cores, X)
     dy = down_vectors(tree, cores, Y)
     u = up_vectors(tree, cores, dx)

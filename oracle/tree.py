@@ -13,7 +13,13 @@ Follows the paper's definitions:
 
 Tree specs are nested Python tuples of 1-based modes: an int is a one-mode leaf,
 a frozenset of ints a multi-mode leaf, a tuple an internal node whose children are
-listed left to right.  Every node must cover a contiguous interval of modes.
+listed left to right.  A negative int -m inside a tuple is a free mode m of that node
+(Def. 3 allows a node to contain more than the union of its children): it is no node
+of its own; in the sketches and the cores it behaves as a child whose maps, projector
+and core are identities, the convention the paper takes for dummy nodes, so its index
+appears in the node's transfer tensor at its mode position with size n_m.  The
+tensor-train tree of Fig. 4 is (((1, -2), -3), ..., -d).  Every node must cover a
+contiguous interval of modes, its children and free modes listed in mode order.
 """
 
 from dataclasses import dataclass, field
@@ -32,6 +38,7 @@ class Node:
     children: list = field(default_factory=list)
     rank: int = 0         # r_t (unused at the root)
     over: int = 0         # p_t (unused at the root)
+    free: tuple = ()      # free modes (1-based, ascending): in I_t, in no child
 
     @property
     def first(self):
@@ -53,7 +60,7 @@ class Node:
 
 def _modes_of(spec):
     if isinstance(spec, int):
-        return (spec,)
+        return (abs(spec),)
     if isinstance(spec, frozenset):
         return tuple(sorted(spec))
     if isinstance(spec, tuple):
@@ -91,17 +98,24 @@ class Tree:
                 modes = _modes_of(s)
                 if list(modes) != list(range(modes[0], modes[-1] + 1)):
                     raise TreeError(f"node {modes} is not a contiguous interval in order")
+                if isinstance(s, int) and s < 0:
+                    raise TreeError("a free mode must sit inside an internal node")
                 nid = len(self.nodes)
                 node = Node(nid, modes, lev, par)
                 self.nodes.append(node)
                 if par >= 0:
                     self.nodes[par].children.append(nid)
                 if isinstance(s, tuple):
-                    if len(s) < 1:
-                        raise TreeError("internal node without children")
+                    kids = [c for c in s if not (isinstance(c, int) and c < 0)]
+                    node.free = tuple(sorted(-c for c in s if isinstance(c, int) and c < 0))
+                    if not kids:
+                        raise TreeError("internal node without children (a node of free modes only is a leaf)")
                     if len(s) == 1 and lev > 0:
                         raise TreeError("internal node with a single child equal to itself")
-                    for c in s:
+                    firsts = [_modes_of(c)[0] for c in s]
+                    if firsts != sorted(firsts):
+                        raise TreeError(f"children and free modes of {modes} are not in mode order")
+                    for c in kids:
                         nxt.append((c, nid, lev + 1))
             queue = nxt
         # within a level, order is by smallest mode: true by construction, check anyway
@@ -145,6 +159,17 @@ class Tree:
             p = self.nodes[p].parent
         return out
 
+    def positions(self, t):
+        """Row positions of node t's sketches and core, in mode order: ("c", child id)
+        for a child, ("f", mode) for a free mode."""
+        n = self.nodes[t]
+        items = [(self.nodes[c].first, ("c", c)) for c in n.children] + [(m, ("f", m)) for m in n.free]
+        return [it for _, it in sorted(items)]
+
+    @property
+    def has_free_modes(self):
+        return any(n.free for n in self.nodes)
+
     def preceding_siblings(self, t):
         p = self.nodes[t].parent
         if p < 0:
@@ -177,16 +202,16 @@ class Tree:
         tensor except those of I_t, in positional order.
         """
         node = self.nodes[t]
-        sizes = []
+        items = []
         covered = set()
         for s in self.S(t):
-            sizes.append(self.nodes[s].k)
+            items.append((self.nodes[s].first, self.nodes[s].k))
             covered.update(self.nodes[s].modes)
         for m in range(1, self.d + 1):
             if m in node.modes or m in covered:
                 continue
-            sizes.append(self.dims[m - 1])
-        return sizes
+            items.append((m, self.dims[m - 1]))
+        return [size for _, size in sorted(items)]
 
     def x_rows(self, t, variant):
         if variant == "ttnn":
