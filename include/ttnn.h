@@ -103,8 +103,14 @@ typedef enum { TTNN_SK_R = 0, TTNN_SK_OMEGA = 1, TTNN_SK_PSI = 2 } ttnn_sketch_k
 /* The problem of Sec. 4 / Alg. 2 plus the DRM seed and the precision.
  * Tree: node i has parent parent[i] (-1 for exactly one node, the root) and covers
  * the contiguous 0-based mode interval [first_mode[i], last_mode[i]].  The root
- * covers [0, order-1]; every internal node is the disjoint union of its children
- * (Def. 3 with equality).  Children of a node are ordered by first mode.
+ * covers [0, order-1]; the children of a node are disjoint intervals inside its own
+ * (Def. 3: a node contains the union of its children), ordered by first mode.  Modes
+ * of a node in none of its children are its free modes: each acts as a child whose
+ * maps, projector and core are identities (the paper's convention for dummy nodes),
+ * so its index appears in the node's core at its mode position with size n_mu; the
+ * tensor-train chain of the paper's Fig. 4 is {1..d} > {1..d-1} > .. > {1}.  Free modes
+ * have no ids, DRMs, sketches or cores of their own (ttnn_reuse_set lists nodes only);
+ * TTNN_KR plans and ttnn_ttn_dot take trees without them.
  * rank[i] = r_t >= 1 and oversample[i] = p_t >= 0 for non-root nodes (ignored at
  * the root).  eps_factor: the pseudo-inverse keeps singular values of R_t above
  * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52, which suits FP64 sketches.  With FP32
@@ -256,7 +262,8 @@ ttnn_status ttnn_ttn_dot(ttnn_plan_t plan, const double* const* d_a, const int32
 ttnn_status ttnn_read_factor(ttnn_plan_t plan, int32_t mode, int32_t kind, double* d_out, void* stream);
 
 /* Shape of node `node`'s core (column-major, parent rank index last):
- *   leaf (n_t, r_t); internal (r_c1, ..., r_cm, r_t); root (r_c1, ..., r_cm). */
+ *   leaf (n_t, r_t); internal (r_c1, ..., r_cm, r_t); root (r_c1, ..., r_cm), with n_mu
+ *   in place of r_c at the position of a free mode mu. */
 ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64_t* shape);
 
 /* Recovery phase (Sec. 4, Alg. 2; internal nodes at every level >= 1):

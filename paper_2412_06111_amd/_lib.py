@@ -161,7 +161,7 @@ def stream_ptr(stream=None):
 # ---------------------------------------------------------------- trees
 def _modes(spec):
     if isinstance(spec, int):
-        return (spec,)
+        return (abs(spec),)
     if isinstance(spec, frozenset):
         return tuple(sorted(spec))
     out = ()
@@ -172,6 +172,8 @@ def _modes(spec):
 
 def tree_arrays(spec):
     """Nested-tuple tree (1-based modes) -> caller arrays in depth-first order.
+    A negative int -m inside a tuple is a free mode m of that node (no node of its
+    own: the node's interval covers it, no child does).
     Returns (parent, first, last, modes_of_node)."""
     parent, first, last, modes = [], [], [], []
 
@@ -184,7 +186,8 @@ def tree_arrays(spec):
         modes.append(m)
         if isinstance(s, tuple):
             for c in s:
-                walk(c, me)
+                if not (isinstance(c, int) and c < 0):
+                    walk(c, me)
 
     walk(spec, -1)
     return parent, first, last, modes
@@ -363,6 +366,10 @@ class Plan:
                 want = 1
                 for c in kids[i]:
                     want *= rk[c]
+                covered = {m for c in kids[i] for m in self.node_modes[c]}
+                for m in self.node_modes[i]:                  # free modes of the node
+                    if m not in covered:
+                        want *= self.dims[m - 1]
                 want *= rk[i] if i else 1
             else:
                 want = rk[i]

@@ -90,7 +90,7 @@ void dense_updates(const Plan& P) {
 std::vector<int64_t> ttn_ranks(const Plan& P, const int32_t* ranks) {
   if (!ranks) throw Error{TTNN_E_INVALID, "ranks is NULL"};
   std::vector<int64_t> s(P.nodes.size(), 1);
-  for (size_t c = 0; c < P.nodes.size(); ++c) {
+  for (size_t c = 0; c < P.level_of_caller.size(); ++c) {
     const int v = P.level_of_caller[c];
     if (v > 0) s[v] = ranks[c];
   }
@@ -100,7 +100,7 @@ std::vector<int64_t> ttn_ranks(const Plan& P, const int32_t* ranks) {
 std::vector<const double*> ttn_cores(const Plan& P, const double* const* cores) {
   if (!cores) throw Error{TTNN_E_INVALID, "cores is NULL"};
   std::vector<const double*> by_level(P.nodes.size());
-  for (size_t c = 0; c < P.nodes.size(); ++c) {
+  for (size_t c = 0; c < P.level_of_caller.size(); ++c) {
     if (!cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
     by_level[P.level_of_caller[c]] = cores[c];
   }
@@ -333,6 +333,8 @@ ttnn_status ttnn_ttn_dot_work_bytes(ttnn_plan_t plan, const int32_t* ranks_a, co
   Plan* P = get(plan);
   return guard(nullptr, [&]() -> ttnn_status {
     if (!P || !bytes) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (P->nodes.size() != static_cast<size_t>(P->n_real))
+      throw Error{TTNN_E_TREE, "TTN inner products take trees without free modes"};
     *bytes = ttnn::ttn_dot_work_bytes(*P, ttn_ranks(*P, ranks_a), ttn_ranks(*P, ranks_b));
     return TTNN_OK;
   });
@@ -343,6 +345,8 @@ ttnn_status ttnn_ttn_dot(ttnn_plan_t plan, const double* const* d_a, const int32
   Plan* P = get(plan);
   return guard(P, [&]() -> ttnn_status {
     if (!P || !d_out) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (P->nodes.size() != static_cast<size_t>(P->n_real))
+      throw Error{TTNN_E_TREE, "TTN inner products take trees without free modes"};
     const auto sa = ttn_ranks(*P, ranks_a), sb = ttn_ranks(*P, ranks_b);
     const auto a = ttn_cores(*P, d_a), b = ttn_cores(*P, d_b);
     const size_t need = ttnn::ttn_dot_work_bytes(*P, sa, sb);
@@ -384,7 +388,7 @@ ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream
   return guard(P, [&]() -> ttnn_status {
     if (!P || !d_cores) throw Error{TTNN_E_INVALID, "NULL argument"};
     std::vector<double*> by_level(P->nodes.size());
-    for (size_t c = 0; c < P->nodes.size(); ++c) {
+    for (size_t c = 0; c < P->level_of_caller.size(); ++c) {
       if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
       by_level[P->level_of_caller[c]] = d_cores[c];
     }
@@ -400,7 +404,7 @@ ttnn_status ttnn_assemble_async(ttnn_plan_t plan, double* const* d_cores, void* 
   return guard(P, [&]() -> ttnn_status {
     if (!P || !d_cores) throw Error{TTNN_E_INVALID, "NULL argument"};
     std::vector<double*> by_level(P->nodes.size());
-    for (size_t c = 0; c < P->nodes.size(); ++c) {
+    for (size_t c = 0; c < P->level_of_caller.size(); ++c) {
       if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
       by_level[P->level_of_caller[c]] = d_cores[c];
     }
@@ -439,7 +443,7 @@ ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, voi
     if (out_dtype != TTNN_F64 && out_dtype != TTNN_F32) throw Error{TTNN_E_INVALID, "out_dtype must be F64 or F32"};
     if (!P->recon_ok) throw Error{TTNN_E_STATE, "this Khatri-Rao plan sized no dense reconstruction (tensor too large)"};
     std::vector<const double*> by_level(P->nodes.size());
-    for (size_t c = 0; c < P->nodes.size(); ++c) {
+    for (size_t c = 0; c < P->level_of_caller.size(); ++c) {
       if (!d_cores[c]) throw Error{TTNN_E_INVALID, "core pointer is NULL"};
       by_level[P->level_of_caller[c]] = d_cores[c];
     }
@@ -575,8 +579,10 @@ ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32
   return guard(nullptr, [&]() -> ttnn_status {
     if (!P || !count || !ids) throw Error{TTNN_E_INVALID, "NULL argument"};
     const ttnn::Node& t = P->nodes[level_id(*P, node)];
-    *count = static_cast<int32_t>(t.S.size());
-    for (size_t i = 0; i < t.S.size(); ++i) ids[i] = P->nodes[t.S[i]].caller;
+    int32_t cnt = 0;                             // free modes are no nodes of the caller
+    for (int sidx : t.S)
+      if (!P->nodes[sidx].ident) ids[cnt++] = P->nodes[sidx].caller;
+    *count = cnt;
     return TTNN_OK;
   });
 }

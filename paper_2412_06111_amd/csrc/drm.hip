@@ -152,6 +152,23 @@ __global__ void drm_kernel(int64_t rows, int cols, uint64_t seed, uint32_t tag, 
 
 }  // namespace
 
+__global__ void eye_kernel(int64_t n, double* o64, float* o32, uint16_t* o16) {
+  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < n * n;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const bool diag = e / n == e % n;
+    o64[e] = diag ? 1.0 : 0.0;
+    if (o32) o32[e] = diag ? 1.0f : 0.0f;
+    if (o16) o16[e] = diag ? static_cast<uint16_t>(0x3F80) : static_cast<uint16_t>(0);   // BF16 1.0
+  }
+}
+
+void launch_eye(int64_t n, double* o64, float* o32, uint16_t* o16, hipStream_t stream) {
+  if (n <= 0) return;
+  const int64_t want = (n * n + 255) / 256;
+  const int blocks = static_cast<int>(want < 4096 ? want : 4096);
+  hipLaunchKernelGGL(eye_kernel, dim3(blocks), dim3(256), 0, stream, n, o64, o32, o16);
+}
+
 void launch_drm(int64_t rows, int cols, uint64_t seed, uint32_t tag, double* o64, float* o32,
                 uint16_t* o16, hipStream_t stream) {
   const int64_t total = rows * cols;

@@ -281,7 +281,8 @@ void zero_accumulators(Plan& P, hipStream_t st) {
       else s.push(t.Psi, psi_rows(P, static_cast<int>(v)) * t.r);
     }
   } else {
-    for (size_t v = 1; v < P.nodes.size(); ++v) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
+    for (size_t v = 1; v < P.nodes.size(); ++v)
+      if (!P.nodes[v].ident) s.push(P.nodes[v].R, P.nodes[v].n * P.nodes[v].r);
   }
   s.push(P.psi_root, P.psi_root_len);
   launch_zero_list(s, st);
@@ -371,6 +372,7 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
 
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     Node& t = P.nodes[v];
+    if (t.ident) continue;                      // a free mode: no sketch of its own
     const std::vector<int>& pre = t.S;          // empty for TTNN
     const void* in = operand(pre);
     const std::vector<Pos> ps = positions_after(P, pre, off, ext);
@@ -676,6 +678,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     if (std::find(fused_nodes.begin(), fused_nodes.end(), static_cast<int>(v)) != fused_nodes.end()) continue;
     Node& t = P.nodes[v];
+    if (t.ident) continue;                      // a free mode: no sketch of its own
     const std::vector<int>& pre = t.S;          // empty for TTNN
     const void* in = operand(pre);
     const std::vector<Pos> ps = positions_after(P, pre, off, ext);
@@ -763,7 +766,7 @@ void run_epilogue(Plan& P, hipStream_t st) {
   for (int v = 1; v < nn; ++v) maxstep = std::max(maxstep, P.nodes[v].children.size());
   for (int v = 1; v < nn; ++v) {
     Node& t = P.nodes[v];
-    batch.add(left_job(t.R, 1, t.n, t.r, t.Y64, t.k, 1, t.k, t.Om, 0, 1.0));
+    if (!t.ident) batch.add(left_job(t.R, 1, t.n, t.r, t.Y64, t.k, 1, t.k, t.Om, 0, 1.0));
   }
   for (size_t step = 0; step < maxstep; ++step) {
     for (int v = 1; v < nn; ++v) {
@@ -823,6 +826,7 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
     SegList s;
     for (int v = 1; v < nn; ++v) {
       const Node& t = P.nodes[v];
+      if (t.ident) continue;
       if (P.variant != TTNN_KR) s.push(t.R, t.n * t.r);
       else {                                   // the structured accumulators themselves
         s.push(t.Om, t.k * t.r);
@@ -837,6 +841,7 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   int max_k = 1, max_r = 1;
   for (int v = 1; v < nn; ++v) {
     const Node& t = P.nodes[v];
+    if (t.ident) continue;                      // Q = I, no pseudo-inverse
     jl.jobs[jl.n] = QrJob{t.Om, t.Q, t.Pinv, t.k, t.r, jl.n};
     ++jl.n;
     max_k = std::max(max_k, t.k);
@@ -853,7 +858,7 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   for (int v = 0; v < nn; ++v)
     if (!P.nodes[v].leaf()) maxstep = std::max(maxstep, P.nodes[v].children.size() + (v > 0 ? 1 : 0));
   for (int v = 1; v < nn; ++v)
-    if (P.nodes[v].leaf()) {
+    if (P.nodes[v].leaf() && !P.nodes[v].ident) {
       const Node& t = P.nodes[v];
       batch.add(mode_job(t.R, {t.n, t.r}, 1, t.Pinv, 1, t.r, t.r, cores[v]));
     }
@@ -895,7 +900,7 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
     batch.flush();
   }
   batch.flush();
-  launch_status_fold(P.d_flag, nn, P.d_flag + kCallWord, P.d_flag + kStickyWord, st);
+  launch_status_fold(P.d_flag, jl.n + 1, P.d_flag + kCallWord, P.d_flag + kStickyWord, st);
   P.has_cores = true;
 }
 
@@ -935,7 +940,7 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
   int maxlevel = 0;
   for (const Node& t : P.nodes) maxlevel = std::max(maxlevel, t.level);
   for (int v = 1; v < nn; ++v)
-    if (P.nodes[v].leaf()) U[v] = cores[v];
+    if (P.nodes[v].leaf()) U[v] = P.nodes[v].ident ? P.nodes[v].Q : cores[v];   // free mode: U = I
   Batch batch(P, st);
   for (int lev = maxlevel; lev >= 0; --lev) {
     for (int v = nn - 1; v >= 0; --v) {
@@ -1035,6 +1040,7 @@ void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream
   double* w = P.r1 + P.r1_w;
   for (size_t v = 1; v < P.nodes.size(); ++v) {
     const Node& t = P.nodes[v];
+    if (t.ident) continue;                      // a free mode: no sketch of its own
     KronVec kx;
     if (P.variant == TTNN_STTNN) {
       for (int s : t.S) kx.push(g_of(s), P.nodes[s].k);

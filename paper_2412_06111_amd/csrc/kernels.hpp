@@ -10,6 +10,8 @@ namespace ttnn {
 // ---------------------------------------------------------------- DRMs
 void launch_drm(int64_t rows, int cols, uint64_t seed, uint32_t tag, double* o64, float* o32,
                 uint16_t* o16, hipStream_t stream);
+// The n x n identity (the maps of a free mode) in FP64 and, where given, FP32 / BF16.
+void launch_eye(int64_t n, double* o64, float* o32, uint16_t* o16, hipStream_t stream);
 
 // ---------------------------------------------------------------- generic contraction
 // The operand H (dtype th) is viewed as [L][n][Q] column-major (L fastest) and as the

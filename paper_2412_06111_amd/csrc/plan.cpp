@@ -174,17 +174,18 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     std::sort(kids[i].begin(), kids[i].end(),
               [&](int a, int b) { return pr->first_mode[a] < pr->first_mode[b]; });
     if (kids[i].empty()) continue;
+    // children are disjoint intervals inside the node's, in order; modes of the node in
+    // no child are its free modes (Def. 3: a node contains the union of its children)
     int expect = pr->first_mode[i];
     for (int c : kids[i]) {
-      TTNN_REQUIRE(pr->first_mode[c] == expect, TTNN_E_TREE,
-                   "children of node " + std::to_string(i) + " do not tile its interval in order");
+      TTNN_REQUIRE(pr->first_mode[c] >= expect && pr->last_mode[c] <= pr->last_mode[i], TTNN_E_TREE,
+                   "children of node " + std::to_string(i) + " overlap or leave its interval");
       expect = pr->last_mode[c] + 1;
     }
-    TTNN_REQUIRE(expect == pr->last_mode[i] + 1, TTNN_E_TREE,
-                 "children of node " + std::to_string(i) + " do not cover its interval");
     if (i != root)
-      TTNN_REQUIRE(kids[i].size() >= 2, TTNN_E_TREE,
-                   "internal node " + std::to_string(i) + " has a single child equal to itself");
+      TTNN_REQUIRE(kids[i].size() >= 2 || pr->first_mode[kids[i][0]] != pr->first_mode[i] ||
+                       pr->last_mode[kids[i][0]] != pr->last_mode[i],
+                   TTNN_E_TREE, "internal node " + std::to_string(i) + " has a single child equal to itself");
   }
   TTNN_REQUIRE(!kids[root].empty(), TTNN_E_TREE, "the root has no children");
 
@@ -223,6 +224,37 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       nd.p = pr->oversample[c];
       nd.k = nd.r + nd.p;
     }
+  }
+
+  // ---- free modes: one identity leaf per free mode, numbered after the caller's nodes
+  // (so the caller's level-order ids, which seed the maps, do not move).  Its maps,
+  // projector and core are identities (rank n_mu), the convention for dummy nodes.
+  P->n_real = nn;
+  for (int v = 0; v < nn; ++v) {
+    if (P->nodes[v].children.empty()) continue;
+    std::vector<char> covered(P->d, 0);
+    for (int c : P->nodes[v].children)
+      for (int mu = P->nodes[c].first; mu <= P->nodes[c].last; ++mu) covered[mu] = 1;
+    for (int mu = P->nodes[v].first; mu <= P->nodes[v].last; ++mu) {
+      if (covered[mu]) continue;
+      TTNN_REQUIRE(P->variant != TTNN_KR, TTNN_E_TREE, "Khatri-Rao plans take trees without free modes");
+      TTNN_REQUIRE(P->nodes.size() < static_cast<size_t>(TTNN_MAX_NODES), TTNN_E_TREE,
+                   "more than 64 nodes and free modes");
+      Node f;
+      f.ident = true;
+      f.level = P->nodes[v].level + 1;
+      f.parent = v;
+      f.first = f.last = mu;
+      f.n = P->dims[mu];
+      TTNN_REQUIRE(f.n <= 4096, TTNN_E_INVALID, "free modes of size up to 4096 are supported");
+      f.r = f.k = static_cast<int>(f.n);
+      f.m = f.n;
+      const int id = static_cast<int>(P->nodes.size());
+      P->nodes.push_back(f);
+      P->nodes[v].children.push_back(id);
+    }
+    auto& ch = P->nodes[v].children;
+    std::sort(ch.begin(), ch.end(), [&](int a, int b) { return P->nodes[a].first < P->nodes[b].first; });
   }
 
   if (P->variant == TTNN_KR)                 // X_t, Y_t are Khatri-Rao products of shared per-mode factors
@@ -297,9 +329,18 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     nd.Pinv = static_cast<double*>(P->alloc(sizeof(double) * nd.r * nd.r));
     if (!nd.leaf()) {
       int64_t kk = 1;
-      for (int c : nd.children) kk *= P->nodes[c].k;
+      for (int c : nd.children) {
+        check_mul(kk, P->nodes[c].k, "Psi_t size");
+        kk *= P->nodes[c].k;
+      }
       nd.Psi = static_cast<double*>(P->alloc(sizeof(double) * kk * nd.r));
     }
+  }
+  for (size_t v = nn; v < P->nodes.size(); ++v) {   // free modes: Y = Q = the identity
+    Node& nd = P->nodes[v];
+    nd.Y64 = static_cast<double*>(P->alloc(sizeof(double) * nd.n * nd.n));
+    nd.Yc = copy ? P->alloc(cs * nd.n * nd.n) : nd.Y64;
+    nd.Q = nd.Y64;
   }
   P->psi_root_len = 1;
   for (int c : P->nodes[0].children) {
@@ -318,9 +359,9 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   P->work = static_cast<double*>(P->alloc(sizeof(double) * P->work_elems));
   {
     size_t ks = 0, rmax = 1;
-    for (int v = 1; v < nn; ++v) {
+    for (size_t v = 1; v < P->nodes.size(); ++v) {       // g_s of every group, free modes too
       ks += static_cast<size_t>(P->nodes[v].k);
-      rmax = std::max(rmax, static_cast<size_t>(P->nodes[v].r));
+      if (!P->nodes[v].ident) rmax = std::max(rmax, static_cast<size_t>(P->nodes[v].r));
     }
     P->r1_w = ks;
     P->r1 = static_cast<double*>(P->alloc(sizeof(double) * (ks + rmax)));
@@ -328,7 +369,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
 
   // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
   const char* nf = std::getenv("TTNN_DISABLE_FUSED");
-  P->allow_fused = !(nf && nf[0] == '1') && !kr;
+  P->allow_fused = !(nf && nf[0] == '1') && !kr && P->nodes.size() == static_cast<size_t>(nn);
   // transposed DRM copies for whole-tensor right sketches on MFMA (large tensors only,
   // nodes sketched on the raw tensor that the fused kernel does not cover)
   auto plan_xt = [&](bool fill) {
@@ -376,6 +417,11 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     const uint32_t tx = static_cast<uint32_t>(2 * (TTNN_KR_TAG_BASE + mu)), ty = tx + 1;
     launch_drm(P->dims[mu], P->nodes[1].r, P->seed, tx, P->kr_x[mu], nullptr, nullptr, stream);
     launch_drm(P->dims[mu], P->nodes[1].k, P->seed, ty, P->kr_y[mu], nullptr, nullptr, stream);
+  }
+  for (size_t v = nn; v < P->nodes.size(); ++v) {
+    Node& nd = P->nodes[v];
+    launch_eye(nd.n, nd.Y64, P->dtype == TTNN_F32 ? static_cast<float*>(nd.Yc) : nullptr,
+               P->dtype == TTNN_BF16 ? static_cast<uint16_t*>(nd.Yc) : nullptr, stream);
   }
   for (int v = 1; v < nn && !kr; ++v) {
     Node& nd = P->nodes[v];

@@ -22,6 +22,8 @@ struct Node {
   int64_t m = 1;               // rows of X_t
   std::vector<int> S;          // STTNN reuse set (level-order ids, left to right)
   std::vector<int64_t> xpos;   // sizes of the positions indexing the rows of X_t
+  bool ident = false;          // a free mode of the parent: identity maps, projector and core
+                               // (r = k = n); no sketches of its own
   bool leaf() const { return children.empty(); }
 
   // device memory (views into the plan's allocations)
@@ -61,7 +63,8 @@ struct Plan {
   int dtype = TTNN_F64;
   uint64_t seed = 0;
   double eps_factor = 0.0;
-  std::vector<Node> nodes;                 // level order, root = 0
+  std::vector<Node> nodes;                 // level order, root = 0; then the free modes' identity leaves
+  int n_real = 0;                          // the caller's nodes: ids below n_real
   std::vector<int> level_of_caller;        // caller id -> level-order id
   int64_t N = 1;
 

@@ -175,3 +175,22 @@ def test_khatri_rao_plan_sizing_without_device():
     ranks[(4,)] = 12
     with pytest.raises(P.TTNNError, match="one rank"):
         P.footprint_estimate(toy, (500,) * 6, ranks, 10, "kr", "f64")
+
+
+def test_free_mode_trees_without_device():
+    """Trees whose nodes contain more than their children (free modes) are accepted:
+    the tensor-train chain, a free mode between two children, a free mode of the root;
+    a child leaving its parent's interval, or overlapping a sibling, is still refused;
+    Khatri-Rao plans refuse free modes."""
+    import paper_2412_06111_amd as P
+    for spec, dims in [((((1, -2), -3), -4), (8, 9, 10, 11)), (((1, -2, 3), 4), (8, 9, 10, 11)),
+                       (((1, 2), -3, (4, 5)), (4, 5, 6, 7, 8))]:
+        for v in ("ttnn", "sttnn"):
+            assert P.footprint_estimate(spec, dims, 3, 2, v, "f64") > 0
+    with pytest.raises(P.TTNNError, match="free modes"):
+        P.footprint_estimate((((1, -2), -3), -4), (8, 9, 10, 11), 3, 2, "kr", "f64")
+    from paper_2412_06111_amd import _lib
+    pr, keep = _problem(((1, 2), (3, 4)), (2, 2, 2, 2))
+    keep[3][1] = 2                                  # node (1,2) widened to modes 0..2: overlaps (3,4)
+    st, h = _create(pr)
+    assert st == -2 and not h.value and b"interval" in _lib.lib.ttnn_last_error()
