@@ -14,7 +14,9 @@ form of the approximant by explicit Kronecker products, exact recovery of tensor
 of TTN rank <= r, linearity, reduction to stabilised generalised Nystrom for an
 order-2 tree and to MLN for a Tucker tree, Lemma 2 / Lemma 3 inequalities and the
 expected bound of Theorem 2.  Parity unpinned: none of the functions exported
-here; the STTNN set S_t reading is pinned by the nine panels of Fig. 5 only.
+here; the STTNN set S_t reading is pinned by the nine panels of Fig. 5, and the sets
+of other visiting orders by the relabelling to the lexicographic order of a tree with
+its modes renumbered.
 """
 
 from .tree import Tree, TreeError, TOY, T4, T5

@@ -1,19 +1,26 @@
 """Index-tree bookkeeping of the oracle (test infrastructure, never product code).
 
 Follows the paper's definitions:
-  * Def. 3 (index tree): each internal node is the disjoint union of its children
-    (the "contains" of the definition is read as equality; free modes are rejected).
+  * Def. 3 (index tree): the children of a node are disjoint and contained in it;
+    modes of a node in none of its children are its free modes (below).
   * Def. 4 / Def. 5 (dummy nodes): a childless node above the deepest level is a leaf;
     dummies carry identity DRMs and projectors and are never materialised.
   * Fig. 1 labels: nodes are numbered level by level, left to right by smallest mode,
     root = 0.
   * Sec. 5 (STTNN ordering) and Fig. 5: node t reuses the contractions of the set
     S_t = preceding siblings of t together with the preceding siblings of every
-    ancestor of t (the reading that reproduces all nine panels of Fig. 5).
+    ancestor of t (the reading that reproduces all nine panels of Fig. 5).  The paper
+    takes the lexicographic order (level by level, left to right) and notes that the
+    order is a free choice; `visit` gives another one: the children of each node are
+    visited in a chosen order instead of left to right, and "preceding" refers to it.
+    Every such S_t is a set of earlier contractions disjoint from I_t, so each
+    projection keeps the form of the general sequential projection of Sec. 5.
 
 Tree specs are nested Python tuples of 1-based modes: an int is a one-mode leaf,
 a frozenset of ints a multi-mode leaf, a tuple an internal node whose children are
-listed left to right.  A negative int -m inside a tuple is a free mode m of that node
+listed left to right.  A visiting order is given as a second spec over the same nodes
+with the children of each node listed in the order they are visited (each node's free
+modes may stand anywhere among them).  A negative int -m inside a tuple is a free mode m of that node
 (Def. 3 allows a node to contain more than the union of its children): it is no node
 of its own; in the sketches and the cores it behaves as a child whose maps, projector
 and core are identities, the convention the paper takes for dummy nodes, so its index
@@ -36,6 +43,7 @@ class Node:
     level: int
     parent: int           # -1 for the root
     children: list = field(default_factory=list)
+    visit: list = field(default_factory=list)    # children in the STTNN visiting order
     rank: int = 0         # r_t (unused at the root)
     over: int = 0         # p_t (unused at the root)
     free: tuple = ()      # free modes (1-based, ascending): in I_t, in no child
@@ -71,14 +79,34 @@ def _modes_of(spec):
     raise TreeError(f"bad tree spec element {spec!r}")
 
 
+def _visit_lists(spec):
+    """{modes of an internal node: [modes of its children in the listed order]}."""
+    out = {}
+
+    def walk(s):
+        if not isinstance(s, tuple):
+            return
+        kids = [c for c in s if not (isinstance(c, int) and c < 0)]
+        key = tuple(sorted(_modes_of(s)))
+        if key in out:
+            raise TreeError(f"node {key} listed twice in the visiting order")
+        out[key] = [tuple(sorted(_modes_of(c))) for c in kids]
+        for c in kids:
+            walk(c)
+
+    walk(spec)
+    return out
+
+
 class Tree:
     """A validated index tree with level-order numbering.
 
     rank / over may be ints (same for every non-root node) or dicts keyed by the
-    tuple of modes of a node.
+    tuple of modes of a node.  visit: None (lexicographic, the paper's order) or a spec
+    of the same tree listing each node's children in the order STTNN visits them.
     """
 
-    def __init__(self, spec, dims, rank, over):
+    def __init__(self, spec, dims, rank, over, visit=None):
         self.dims = tuple(int(n) for n in dims)
         self.d = len(self.dims)
         if self.d < 2:
@@ -123,6 +151,21 @@ class Tree:
             if a.level == b.level and a.first >= b.first:
                 raise TreeError("level order violated")
         self.depth = max(n.level for n in self.nodes)
+
+        # visiting order of each node's children (default: left to right)
+        for n in self.nodes:
+            n.visit = list(n.children)
+        if visit is not None:
+            order = _visit_lists(visit)
+            for n in self.nodes:
+                if n.is_leaf:
+                    continue
+                want = order.get(n.modes)
+                if want is None or sorted(want) != sorted(self.nodes[c].modes for c in n.children):
+                    raise TreeError(f"the visiting order does not list the children of {n.modes}")
+                n.visit = [self.by_modes(m) for m in want]
+            if len(order) != sum(1 for n in self.nodes if not n.is_leaf):
+                raise TreeError("the visiting order has nodes the tree does not have")
 
         for n in self.nodes[1:]:
             key = n.modes
@@ -171,10 +214,11 @@ class Tree:
         return any(n.free for n in self.nodes)
 
     def preceding_siblings(self, t):
+        """Siblings of t visited before t (left of t in the lexicographic order)."""
         p = self.nodes[t].parent
         if p < 0:
             return []
-        sib = self.nodes[p].children
+        sib = self.nodes[p].visit
         return sib[: sib.index(t)]
 
     def S(self, t):
