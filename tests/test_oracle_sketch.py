@@ -126,12 +126,15 @@ def test_sketch_box_equals_zero_padded(spec, dims, variant):
 
 
 @pytest.mark.parametrize("variant", ["ttnn", "sttnn"])
-@pytest.mark.parametrize("spec,dims", [(O.T4, (5, 4, 3, 6)), (O.T5, (3, 4, 2, 3, 4)), (O.TOY, (2, 3, 2, 3, 2, 2))])
-def test_sampled_entries_match_full_sketch(spec, dims, variant):
-    """The one-entry evaluator used for full-size GPU checks equals the full oracle sketch."""
+@pytest.mark.parametrize("spec,dims,visit", [
+    (O.T4, (5, 4, 3, 6), None), (O.T5, (3, 4, 2, 3, 4), None), (O.TOY, (2, 3, 2, 3, 2, 2), None),
+    (O.T4, (5, 4, 3, 6), ((4, 3), (2, 1))), (O.TOY, (2, 3, 2, 3, 2, 2), ((5, 6), (3, (1, 2)), 4))])
+def test_sampled_entries_match_full_sketch(spec, dims, visit, variant):
+    """The one-entry evaluator used for full-size GPU checks equals the full oracle
+    sketch, in the lexicographic order and in orders whose S_t has groups right of t."""
     from oracle.sampled import right_entry, root_entry
     T = np.random.default_rng(3).standard_normal(dims)
-    tree = O.Tree(spec, dims, 3, 2)
+    tree = O.Tree(spec, dims, 3, 2, visit=visit)
     sk = O.sketch(T, tree, O.DRMs(tree, 9, variant), variant)
     g = np.random.default_rng(4)
     for n in tree.nodes[1:]:
