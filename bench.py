@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--serve-loads", default="0.25,0.5,0.8", help="Poisson loads run (fractions of the closed-loop rate)")
     ap.add_argument("--no-rounding", action="store_true", help="skip the TTN rounding runs (Khatri-Rao maps)")
     ap.add_argument("--no-pipeline", action="store_true", help="skip the two-plan throughput runs")
+    ap.add_argument("--no-order", action="store_true", help="skip the STTNN visiting-order runs")
+    ap.add_argument("--order-only", action="store_true",
+                    help="only the STTNN visiting-order runs (lexicographic against searched)")
     ap.add_argument("--rounding-only", action="store_true",
                     help="run only the TTN rounding runs and print them as one JSON line")
     ap.add_argument("--round-n", type=int, default=500)
@@ -396,6 +399,75 @@ def hilbert_bench(args):
 # ---------------------------------------------------------------- TTN rounding
 ROUND_TTN_RANK, ROUND_P = 70, 10
 ROUND_DECAYS = {"quadratic": lambda i: 1.0 / i ** 2, "cubic": lambda i: 1.0 / i ** 3, "exponential": lambda i: 0.5 ** i}
+
+
+def order_bench(args):
+    """STTNN in the lexicographic visiting order of Sec. 5 and in the order of least
+    modelled cost (ttnn_order_search), on workloads where the order matters: T4 with
+    n_1 << n_2 (FP32) and the 6-D Hilbert tensor on the tree of Fig. 1 (FP64, r = 13,
+    the largest rank of the experiment).  Per order: ms per step (reset + whole-tensor
+    update + assembly, as the headline), sketch ms (HIP events around the update),
+    the model's flops and map entries, the plan footprint, the approximation error."""
+    import numpy as np
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads import hilbert as H
+    from workloads import synth as W
+
+    T4 = ((1, 2), (3, 4))
+    out = {}
+    cases = [("t4_32x512x128x128_r32_f32", T4, (32, 512, 128, 128), 32, 16, "f32"),
+             ("hilbert6d_n20_fig1tree_r13_f64", H.TOY, (20,) * 6, 13, H.P_PAPER, "f64")]
+    stream = torch.cuda.current_stream()
+    for name, spec, dims, r, p, dtype in cases:
+        if name.startswith("hilbert"):
+            X64 = H.hilbert_device(dims[0]).reshape(-1)
+        else:
+            X64 = torch.from_numpy(np.ascontiguousarray(W.flat_colmajor(W.unbalanced_tensor(dims)))).cuda()
+        X = X64 if dtype == "f64" else X64.to(torch.float32)
+        best, _ = P.order_search(spec, dims, r, p)
+        rec = {"searched_order": repr(best)}
+        for label, visit in (("lexicographic", None), ("searched", best)):
+            plan = P.Plan(spec, dims, r, p, variant="sttnn", dtype=dtype, seed=1, visit=visit)
+            cores = plan.alloc_cores()
+
+            def step(ev=None):
+                plan.reset()
+                if ev is not None:
+                    ev[0].record(stream)
+                plan.update(X)
+                if ev is not None:
+                    ev[1].record(stream)
+                plan.assemble_async(cores)
+
+            for _ in range(args.warmup):
+                step()
+            plan.assemble_status()
+            torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            tic = time.perf_counter()
+            for i in range(args.steps):
+                step(evs[i])
+            plan.assemble_status()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - tic) * 1e3 / args.steps
+            e2, n2 = P.diff_norms(plan.reconstruct(cores), X64)
+            rec[label] = {"ms_per_step": ms,
+                          "sketch_ms_avg": sum(a.elapsed_time(b) for a, b in evs) / len(evs),
+                          "model_gflop": P.order_cost(spec, dims, r, p, visit=visit) / 1e9,
+                          "model_map_entries": P.order_cost(spec, dims, r, p, visit=visit, objective="maps"),
+                          "footprint_bytes": plan.footprint(), "approx_rel_error": (e2 / n2) ** 0.5}
+            plan.close()
+            del cores
+            torch.cuda.empty_cache()
+            print(f"# order {name} {label}: {rec[label]['ms_per_step']:.3f} ms/step, "
+                  f"{rec[label]['model_gflop']:.1f} GFLOP (model)", file=sys.stderr, flush=True)
+        rec["speedup"] = rec["lexicographic"]["ms_per_step"] / rec["searched"]["ms_per_step"]
+        out[name] = rec
+        del X, X64
+        torch.cuda.empty_cache()
+    return out
 
 
 def rounding_counts(spec, dims, r, p, s):
@@ -865,6 +937,9 @@ def main():
     if args.rounding_only:
         print(json.dumps(rounding_bench(args)))
         return
+    if args.order_only:
+        print(json.dumps(order_bench(args)))
+        return
 
     import numpy as np
     import torch
@@ -934,6 +1009,9 @@ def main():
     hilbert = None
     if not args.no_hilbert:
         hilbert = hilbert_bench(args)
+    orders = None
+    if not args.no_order:
+        orders = order_bench(args)
     rounding = None
     if not args.no_rounding:
         rounding = rounding_bench(args)
@@ -957,8 +1035,13 @@ def main():
                         traffic=measured_traffic(key), rounding=rounding)
     if pipelined:
         line["two_plans_in_turn_ms_per_step"] = {k: round(v, 4) for k, v in pipelined.items()}
+    if orders:
+        line["sttnn_visiting_order_ms_per_step"] = {
+            k: {"lexicographic": round(v["lexicographic"]["ms_per_step"], 4),
+                "searched": round(v["searched"]["ms_per_step"], 4)} for k, v in orders.items()}
     detail = {"line": line, "results": results, "copy_calibration": copy, "serving": serving,
               "hilbert_6d": hilbert, "ttn_rounding": rounding, "two_plans_in_turn_ms_per_step": pipelined,
+              "sttnn_visiting_order": orders,
               "input_generation_s": t_gen}
     if args.detail:
         d = os.path.dirname(os.path.abspath(args.detail))

@@ -116,7 +116,18 @@ typedef enum { TTNN_SK_R = 0, TTNN_SK_OMEGA = 1, TTNN_SK_PSI = 2 } ttnn_sketch_k
  * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52, which suits FP64 sketches.  With FP32
  * sketches a threshold at the FP32 noise level (about 10 * 2^-23) drops the directions
  * that noise creates and gives markedly smaller errors at ranks where the tensor's
- * spectrum has fallen below it. */
+ * spectrum has fallen below it.
+ * visit: NULL for the lexicographic order of the STTNN sketches (Sec. 5: level by
+ * level, the children of each node left to right), else an array of num_nodes entries
+ * where visit[i] is the place of node i among its siblings in the order they are
+ * visited (0 = first; the root's entry is ignored): a permutation of 0..m-1 over the
+ * m children of every node.  Sec. 5 leaves the order free; node t then reuses the
+ * contractions of S_t = the siblings of t visited before it together with those of
+ * every ancestor of t, so the order changes the shapes of the X_t (their rows run over
+ * the indices of T_{S_t} outside I_t) and the cost of the sketch phase, not the form of
+ * the approximant.  ttnn_order_search picks one.  TTNN and TTNN_KR plans check the
+ * array and ignore it.  The one-pass kernels of STTNN serve the lexicographic order;
+ * other orders take the generic contractions. */
 typedef struct {
   int32_t order;
   const int64_t* dims;
@@ -130,6 +141,7 @@ typedef struct {
   int32_t dtype;     /* ttnn_dtype   */
   uint64_t seed;
   double eps_factor;
+  const int32_t* visit;
 } ttnn_problem;
 
 /* Validate the problem, allocate the plan's device memory, and generate every DRM
@@ -159,6 +171,26 @@ ttnn_status ttnn_plan_create(const ttnn_problem* problem, void* stream, ttnn_pla
  * root Psi as accumulators, takes TTN-format updates only (ttnn_sketch_update_ttn), and
  * its recovery is that of every plan.  It sizes the dense reconstruction only when its
  * intermediates stay below 2^27 doubles (else ttnn_reconstruct returns TTNN_E_STATE). */
+
+/* STTNN visiting orders (Sec. 5 leaves the order of the nodes free and calls the best
+ * one a combinatorial problem).  Cost model of one whole-tensor sketch pass:
+ *   TTNN_COST_FLOPS  2 x (entries of the operand) x (columns of the map) summed over
+ *                    every R_t = (T_{S_t})^{t} X_t and every step of the chains of
+ *                    contractions T x_s Y_s^T that the S_t and the root sketch need
+ *                    (each once; identity maps of free modes cost nothing);
+ *   TTNN_COST_MAPS   entries of every X_t (the maps the sweep streams).
+ * The cost of a subtree is the product of k_s / n_s over the groups contracted before
+ * it times its cost with nothing contracted, so the order of each node's children can
+ * be chosen on its own, deepest nodes first.
+ * ttnn_order_cost: the cost of problem->visit (NULL: lexicographic).
+ * ttnn_order_search: writes to visit (num_nodes entries, host memory) the order of
+ * least cost, a valid problem->visit, and its cost to *cost: exhaustive over the
+ * orders of the children of every node, so the optimum of the model; ties keep the
+ * lexicographic order.  Host-only: nothing is allocated or launched.  Both take STTNN
+ * problems only (TTNN_E_INVALID otherwise) and validate them like ttnn_plan_create. */
+typedef enum { TTNN_COST_FLOPS = 0, TTNN_COST_MAPS = 1 } ttnn_cost;
+ttnn_status ttnn_order_cost(const ttnn_problem* problem, int32_t objective, double* cost);
+ttnn_status ttnn_order_search(const ttnn_problem* problem, int32_t objective, int32_t* visit, double* cost);
 
 /* Device bytes a plan for `problem` needs (its DRMs in FP64 and in the compute dtype,
  * FP64 accumulators, cores' scratch and partial sums), computed on the host without
@@ -330,7 +362,9 @@ ttnn_status ttnn_read_drm(ttnn_plan_t plan, int32_t node, int32_t kind, int32_t 
                           void* d_out, void* stream);
 
 /* Canonical (level-order) id of caller node `node`, and the STTNN reuse set S_t
- * (Sec. 5, Fig. 5) as caller ids, left to right. */
+ * (Sec. 5, Fig. 5) as caller ids (ids: room for num_nodes), in the order its chain of
+ * contractions takes them: the groups of the ancestors' levels first, from the top
+ * down, each level in visiting order (left to right for the lexicographic order). */
 ttnn_status ttnn_level_id(ttnn_plan_t plan, int32_t node, int32_t* level_id);
 ttnn_status ttnn_reuse_set(ttnn_plan_t plan, int32_t node, int32_t* count, int32_t* ids);
 

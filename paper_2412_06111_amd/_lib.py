@@ -37,6 +37,7 @@ class Problem(C.Structure):
         ("first_mode", C.POINTER(C.c_int32)), ("last_mode", C.POINTER(C.c_int32)),
         ("rank", C.POINTER(C.c_int32)), ("oversample", C.POINTER(C.c_int32)),
         ("variant", C.c_int32), ("dtype", C.c_int32), ("seed", C.c_uint64), ("eps_factor", C.c_double),
+        ("visit", C.POINTER(C.c_int32)),
     ]
 
 
@@ -86,6 +87,8 @@ def _load():
         "ttnn_reset": [vp, vp],
         "ttnn_set_timing": [vp, i32],
         "ttnn_footprint_estimate": [C.POINTER(Problem), C.POINTER(C.c_size_t)],
+        "ttnn_order_cost": [C.POINTER(Problem), i32, C.POINTER(dbl)],
+        "ttnn_order_search": [C.POINTER(Problem), i32, P32, C.POINTER(dbl)],
         "ttnn_sweep_time_ms": [vp, C.POINTER(C.c_float)],
     }
     for name, args in sigs.items():
@@ -193,7 +196,58 @@ def tree_arrays(spec):
     return parent, first, last, modes
 
 
-def _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor):
+def _visit_lists(spec):
+    """{modes of an internal node: [modes of its children in the listed order]}."""
+    out = {}
+
+    def walk(s):
+        if not isinstance(s, tuple):
+            return
+        kids = [c for c in s if not (isinstance(c, int) and c < 0)]
+        out[tuple(sorted(_modes(s)))] = [tuple(sorted(_modes(c))) for c in kids]
+        for c in kids:
+            walk(c)
+
+    walk(spec)
+    return out
+
+
+def visit_places(spec, visit):
+    """The caller arrays' `visit` entries of a visiting order given as a spec of the same
+    tree with each node's children listed in the order they are visited."""
+    par, _, _, modes = tree_arrays(spec)
+    lists = _visit_lists(visit)
+    out = []
+    for i, p in enumerate(par):
+        if p < 0:
+            out.append(0)
+            continue
+        sib = lists.get(tuple(sorted(modes[p])))
+        me = tuple(sorted(modes[i]))
+        if sib is None or me not in sib:
+            raise ValueError(f"the visiting order does not list node {modes[i]} under {modes[p]}")
+        out.append(sib.index(me))
+    return out
+
+
+def visit_spec(spec, places):
+    """Inverse of visit_places: the tree spec with each node's children listed in the
+    visiting order (free modes after them)."""
+    it = iter(range(len(places)))
+
+    def walk(s):
+        me = next(it)
+        if not isinstance(s, tuple):
+            return me, s
+        kids = [walk(c) for c in s if not (isinstance(c, int) and c < 0)]
+        free = tuple(c for c in s if isinstance(c, int) and c < 0)
+        kids.sort(key=lambda kc: places[kc[0]])
+        return me, tuple(c for _, c in kids) + free
+
+    return walk(spec)[1]
+
+
+def _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor, visit=None):
     """Marshal a problem; returns (Problem, keep-alive arrays, node modes)."""
     dims = tuple(int(n) for n in dims)
     d = len(dims)
@@ -205,23 +259,48 @@ def _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor):
     ov = [int(over[m] if isinstance(over, dict) else over) if i else 0 for i, m in enumerate(modes)]
     arrays = ((C.c_int64 * d)(*dims), (C.c_int32 * nn)(*par), (C.c_int32 * nn)(*fst),
               (C.c_int32 * nn)(*lst), (C.c_int32 * nn)(*rk), (C.c_int32 * nn)(*ov))
+    if visit is not None:
+        arrays = arrays + ((C.c_int32 * nn)(*visit_places(spec, visit)),)
     a = arrays
     pr = Problem(d, a[0], nn, a[1], a[2], a[3], a[4], a[5], variant, dtype, C.c_uint64(int(seed)),
-                 float(eps_factor))
+                 float(eps_factor), a[6] if visit is not None else None)
     return pr, arrays, modes
 
 
-def footprint_estimate(spec, dims, rank, over, variant="ttnn", dtype="f64"):
+COST_OF_NAME = {"flops": 0, "maps": 1}
+
+
+def order_cost(spec, dims, rank, over, visit=None, objective="flops"):
+    """Cost of one whole-tensor STTNN sketch pass in the visiting order `visit` (a spec of
+    the tree listing children in visiting order; None: lexicographic): leading-order
+    flops, or entries of the X_t maps."""
+    pr, _keep, _ = _problem(spec, dims, rank, over, STTNN, F64, 1, 0.0, visit)
+    out = C.c_double()
+    check(lib.ttnn_order_cost(C.byref(pr), COST_OF_NAME[objective], C.byref(out)))
+    return float(out.value)
+
+
+def order_search(spec, dims, rank, over, objective="flops"):
+    """The STTNN visiting order of least cost under the library's model; returns
+    (visit spec, cost)."""
+    pr, _keep, _ = _problem(spec, dims, rank, over, STTNN, F64, 1, 0.0)
+    places = (C.c_int32 * pr.num_nodes)()
+    out = C.c_double()
+    check(lib.ttnn_order_search(C.byref(pr), COST_OF_NAME[objective], places, C.byref(out)))
+    return visit_spec(spec, list(places)), float(out.value)
+
+
+def footprint_estimate(spec, dims, rank, over, variant="ttnn", dtype="f64", visit=None):
     """Device bytes a plan for this problem would own (host-side sizing, no allocation)."""
-    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0)
+    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0, visit)
     out = C.c_size_t()
     check(lib.ttnn_footprint_estimate(C.byref(pr), C.byref(out)))
     return int(out.value)
 
 
-def workspace_bytes(spec, dims, rank, over, variant="ttnn", dtype="f64"):
+def workspace_bytes(spec, dims, rank, over, variant="ttnn", dtype="f64", visit=None):
     """Size of the device workspace ttnn_plan needs for this problem."""
-    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0)
+    pr, _keep, _ = _problem(spec, dims, rank, over, variant, dtype, 1, 0.0, visit)
     n = int(lib.ttnn_workspace_bytes(C.byref(pr)))
     if n == 0:
         raise TTNNError(-1, (lib.ttnn_last_error() or b"").decode())
@@ -244,15 +323,19 @@ class Plan:
     Device memory: by default a workspace tensor allocated with torch (ttnn_plan; the
     plan's arrays are views into it); `workspace` passes one of the caller's (a CUDA
     uint8 tensor of at least workspace_bytes(...)); pool=True lets the library take a
-    block from its own per-device pool (ttnn_plan_create)."""
+    block from its own per-device pool (ttnn_plan_create).  visit: the STTNN visiting
+    order as a spec of the same tree listing each node's children in the order they are
+    visited (None: lexicographic; order_search finds the cheapest)."""
 
     def __init__(self, spec, dims, rank, over, variant="ttnn", dtype="f64", seed=1, eps_factor=0.0,
-                 stream=None, workspace=None, pool=False):
+                 stream=None, workspace=None, pool=False, visit=None):
         self.spec, self.dims = spec, tuple(int(n) for n in dims)
         self.d = len(self.dims)
         self.variant = VARIANT_OF_NAME[variant] if isinstance(variant, str) else int(variant)
         self.dtype = DTYPE_OF_NAME[dtype] if isinstance(dtype, str) else int(dtype)
-        self.problem, self._arrays, modes = _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor)
+        self.visit = visit
+        self.problem, self._arrays, modes = _problem(spec, dims, rank, over, variant, dtype, seed, eps_factor,
+                                                     visit)
         self.node_modes = modes
         self.node_of_modes = {m: i for i, m in enumerate(modes)}
         self.num_nodes = len(modes)

@@ -9,6 +9,7 @@
 #include "engine.hpp"
 #include "kernels.hpp"
 #include "kr.hpp"
+#include "order.hpp"
 
 struct ttnn_plan_s {
   std::unique_ptr<ttnn::Plan> p;
@@ -298,6 +299,29 @@ ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes) 
     *bytes = 0;
     auto P = ttnn::build_plan(problem, nullptr, /*dry=*/true);
     *bytes = P->footprint;
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_order_cost(const ttnn_problem* problem, int32_t objective, double* cost) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!cost) throw Error{TTNN_E_INVALID, "cost is NULL"};
+    if (objective != TTNN_COST_FLOPS && objective != TTNN_COST_MAPS) throw Error{TTNN_E_INVALID, "bad objective"};
+    auto P = ttnn::build_plan(problem, nullptr, /*dry=*/true);
+    if (P->variant != TTNN_STTNN) throw Error{TTNN_E_INVALID, "visiting orders concern STTNN plans"};
+    *cost = ttnn::order_cost(*P, objective);
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_order_search(const ttnn_problem* problem, int32_t objective, int32_t* visit, double* cost) {
+  return guard(nullptr, [&]() -> ttnn_status {
+    if (!visit || !cost) throw Error{TTNN_E_INVALID, "NULL argument"};
+    if (objective != TTNN_COST_FLOPS && objective != TTNN_COST_MAPS) throw Error{TTNN_E_INVALID, "bad objective"};
+    auto P = ttnn::build_plan(problem, nullptr, /*dry=*/true);
+    if (P->variant != TTNN_STTNN) throw Error{TTNN_E_INVALID, "visiting orders concern STTNN plans"};
+    const std::vector<int> place = ttnn::order_search(*P, objective, cost);
+    for (size_t i = 0; i < place.size(); ++i) visit[i] = place[i];
     return TTNN_OK;
   });
 }

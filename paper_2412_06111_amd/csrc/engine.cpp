@@ -38,17 +38,25 @@ int64_t prod_ext(const std::vector<Pos>& ps, size_t a, size_t b) {
   return p;
 }
 
-// positions of the operand obtained from the box after contracting `prefix`
+// positions of the operand obtained from the box after contracting the groups of
+// `prefix` (disjoint, in any order): in mode order, each contracted group one position
+// of size k at its place
 std::vector<Pos> positions_after(const Plan& P, const std::vector<int>& prefix, const int64_t* off,
                                  const int64_t* ext) {
+  int group_of[TTNN_MAX_ORDER];
+  for (int mu = 0; mu < P.d; ++mu) group_of[mu] = -1;
+  for (int s : prefix)
+    for (int mu = P.nodes[s].first; mu <= P.nodes[s].last; ++mu) group_of[mu] = s;
   std::vector<Pos> ps;
-  int next_mode = 0;
-  for (int s : prefix) {
-    const Node& g = P.nodes[s];
-    ps.push_back(Pos{g.k, 0, g.k, g.first, true});
-    next_mode = g.last + 1;
+  for (int mu = 0; mu < P.d; ++mu) {
+    const int s = group_of[mu];
+    if (s < 0) {
+      ps.push_back(Pos{ext[mu], off[mu], P.dims[mu], mu, false});
+    } else if (mu == P.nodes[s].first) {
+      const Node& g = P.nodes[s];
+      ps.push_back(Pos{g.k, 0, g.k, g.first, true});
+    }
   }
-  for (int mu = next_mode; mu < P.d; ++mu) ps.push_back(Pos{ext[mu], off[mu], P.dims[mu], mu, false});
   return ps;
 }
 
@@ -217,15 +225,21 @@ void size_chain_scratch(Plan& P) {
   };
   if (!kr) {
     for (size_t v = 1; v < P.nodes.size(); ++v) add_prefixes(P.nodes[v].S, P.nodes[v].S.size());
-    const auto& rc = P.nodes[0].children;
+    const auto& rc = P.nodes[0].visit;
     add_prefixes(rc, rc.size() - 1);      // the last root step accumulates into Psi_0
   }
   size_t total = 0;
   for (auto& pf : prefixes) {
     if (P.prefix_offset.count(pf)) continue;
+    // T with the groups of pf contracted: k_s for each group, n_mu for every other mode
+    std::vector<char> covered(P.d, 0);
     int64_t e = 1;
-    for (int s : pf) e *= P.nodes[s].k;
-    for (int mu = P.nodes[pf.back()].last + 1; mu < P.d; ++mu) e *= P.dims[mu];
+    for (int s : pf) {
+      e *= P.nodes[s].k;
+      for (int mu = P.nodes[s].first; mu <= P.nodes[s].last; ++mu) covered[mu] = 1;
+    }
+    for (int mu = 0; mu < P.d; ++mu)
+      if (!covered[mu]) e *= P.dims[mu];
     P.prefix_offset[pf] = total;
     total += static_cast<size_t>(e);
   }
@@ -418,8 +432,9 @@ void record_box(Plan& P, const void* block, const int64_t* off, const int64_t* e
     ops.push_back(op);
   }
 
-  // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0
-  const auto& rc = P.nodes[0].children;
+  // root: T x_{c1} Y_c1^T ... x_{cm} Y_cm^T accumulated into Psi_0 (contracted in the
+  // visiting order; the result keeps the children in mode order, c1 fastest)
+  const auto& rc = P.nodes[0].visit;
   std::vector<int> before(rc.begin(), rc.end() - 1);
   operand(before);
   left(group_args(before, P.nodes[rc.back()]), P.psi_root, 1, alpha);
@@ -631,6 +646,10 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
           } else {
             launch_right_mfma(block, cd, n, Q, 1, g.Yt, n, g.k, chain_ptr(chain), out, st);
           }
+        } else if (before.empty() && whole && mid_mfma_eligible(L, n, Q, g.k, cd)) {
+          // raw tensor, group past mode 1 (a visiting order that contracts a later
+          // group first): the streaming MFMA mode product, written straight to Z
+          launch_mid_mfma(block, cd, L, n, Q, g.Yc, g.k, chain_ptr(chain), st);
         } else {
           left_op(P, a, chain_ptr(chain), 2, 1.0, st);
         }
@@ -644,7 +663,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
   // its last step is an FP64 job that depends only on the chain, so it joins the
   // first batch of node jobs (it runs first; the accumulators are independent).
   auto do_root = [&]() {
-    const auto& rc = P.nodes[0].children;
+    const auto& rc = P.nodes[0].visit;
     std::vector<int> before(rc.begin(), rc.end() - 1);
     const void* in = operand(before);
     const std::vector<Pos> ps = positions_after(P, before, off, ext);
@@ -1007,8 +1026,9 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
 // Rank-1 update H = a_1 o ... o a_d (Sec. 4, streaming by linearity).  With u_I the
 // Kronecker vector of the factors of a mode group (first mode fastest):
 //   R_t += alpha * u_{I_t} (X_t^T v_t)^T,   v_t = kron over the rows of X_t,
-// where the rows run over the modes outside I_t (TTNN) or over the contracted groups
-// S_t, each contributing g_s = Y_s^T u_{I_s}, then the modes after t (STTNN); and
+// where the rows run over the modes outside I_t (TTNN) or over the indices of T_{S_t}
+// outside I_t in mode order, a contracted group s contributing g_s = Y_s^T u_{I_s} and
+// any other mode its factor (STTNN); and
 //   Psi_0 += alpha * kron_c g_c over the root's children.
 // The maps are the ones a box update uses: the compute-dtype copy for a contraction
 // of the raw tensor (a chain's first group, or X_t when S_t is empty), the FP64
@@ -1022,8 +1042,8 @@ void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream
     for (int mu = first; mu <= last; ++mu) kv.push(factors[mu], P.dims[mu]);
     return kv;
   };
-  // chains start at mode 0 (every S_t and the root's children cover a prefix of the
-  // modes), so a group is contracted from the raw tensor exactly when it starts at 0
+  // a group is contracted from the raw tensor exactly when it heads its chains, that is
+  // when its own reuse set is empty (free modes: identity maps, exact in any dtype)
   std::vector<int64_t> goff(P.nodes.size(), -1);
   int64_t used = 0;
   auto g_of = [&](int s) -> const double* {
@@ -1031,7 +1051,7 @@ void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream
       const Node& g = P.nodes[s];
       goff[s] = used;
       used += g.k;
-      const bool raw = g.first == 0;
+      const bool raw = g.S.empty();
       launch_kron_gemv(raw ? g.Yc : static_cast<const void*>(g.Y64), raw ? cd : TTNN_F64, g.n, g.k,
                        modes(g.first, g.last), P.partial, P.partial_elems, P.r1 + goff[s], st);
     }
@@ -1043,8 +1063,16 @@ void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream
     if (t.ident) continue;                      // a free mode: no sketch of its own
     KronVec kx;
     if (P.variant == TTNN_STTNN) {
-      for (int s : t.S) kx.push(g_of(s), P.nodes[s].k);
-      for (int mu = t.last + 1; mu < P.d; ++mu) kx.push(factors[mu], P.dims[mu]);
+      // the rows of X_t: the indices of T_{S_t} outside I_t in mode order
+      std::vector<int> group_of(P.d, -1);
+      for (int s : t.S)
+        for (int mu = P.nodes[s].first; mu <= P.nodes[s].last; ++mu) group_of[mu] = s;
+      for (int mu = 0; mu < P.d; ++mu) {
+        if (mu >= t.first && mu <= t.last) continue;
+        const int s = group_of[mu];
+        if (s < 0) kx.push(factors[mu], P.dims[mu]);
+        else if (mu == P.nodes[s].first) kx.push(g_of(s), P.nodes[s].k);
+      }
     } else {
       for (int mu = 0; mu < P.d; ++mu)
         if (mu < t.first || mu > t.last) kx.push(factors[mu], P.dims[mu]);

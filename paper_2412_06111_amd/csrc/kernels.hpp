@@ -199,6 +199,14 @@ void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const 
 // the chunks are as many as part_elems holds, so with part_elems = n r the single
 // chunk is the result itself.  Throws if part_elems < n r.
 bool right_mfma_eligible(int64_t L, int64_t n, int64_t Q, int r, int dt);
+
+// Mode product of a packed whole tensor H[L][n][Q] (dtype dt, FP32 or FP64) with a
+// map Y (n x k row-major, same dtype) at a group past mode 1, on MFMA:
+// out[l + L (j + k q)] = sum_i H[l + L i + L n q] Y[i][j] (FP64).  Eligible: L > 1 a
+// multiple of the 16-byte vector, k <= 128, and at least 32768 rows L Q.
+bool mid_mfma_eligible(int64_t L, int64_t n, int64_t Q, int k, int dt);
+void launch_mid_mfma(const void* H, int dt, int64_t L, int64_t n, int64_t Q, const void* Y, int k, double* out,
+                     hipStream_t st);
 // Split of such a right sketch over its contraction (pure host arithmetic): nch chunks
 // of kchunk values, each writing an n x r FP64 partial, nch * n * r <= part_elems.
 // Throws TTNN_E_INVALID when the shape is not covered or part_elems cannot hold one

@@ -226,6 +226,24 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
     }
   }
 
+  // ---- STTNN visiting order of the children (Sec. 5 leaves it free; NULL = left to right)
+  for (int v = 0; v < nn; ++v) {
+    Node& nd = P->nodes[v];
+    nd.visit = nd.children;
+    if (!pr->visit) continue;
+    const size_t m = nd.children.size();
+    std::vector<int> slot(m, -1);
+    for (int c : nd.children) {
+      const int32_t q = pr->visit[P->nodes[c].caller];
+      TTNN_REQUIRE(q >= 0 && static_cast<size_t>(q) < m && slot[q] < 0, TTNN_E_TREE,
+                   "visit must number the children of every node 0..m-1 (node " + std::to_string(nd.caller) + ")");
+      slot[q] = c;
+    }
+    if (P->variant != TTNN_STTNN) continue;      // checked, and without effect on TTNN
+    nd.visit = slot;
+    if (nd.visit != nd.children) P->lex = false;
+  }
+
   // ---- free modes: one identity leaf per free mode, numbered after the caller's nodes
   // (so the caller's level-order ids, which seed the maps, do not move).  Its maps,
   // projector and core are identities (rank n_mu), the convention for dummy nodes.
@@ -252,6 +270,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       const int id = static_cast<int>(P->nodes.size());
       P->nodes.push_back(f);
       P->nodes[v].children.push_back(id);
+      P->nodes[v].visit.push_back(id);       // contracted with the identity: last, never a cost
     }
     auto& ch = P->nodes[v].children;
     std::sort(ch.begin(), ch.end(), [&](int a, int b) { return P->nodes[a].first < P->nodes[b].first; });
@@ -266,22 +285,38 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
   for (int v = 1; v < nn; ++v) {
     Node& nd = P->nodes[v];
     if (P->variant == TTNN_STTNN) {
+      // S_t: the siblings visited before t and before each ancestor of t, listed from
+      // the top level down (each level in visiting order), so that the chain of
+      // contractions T x Y_s^T of a node extends its parent's and its earlier siblings'
+      std::vector<std::vector<int>> per_level;
       int cur = v;
       while (P->nodes[cur].parent >= 0) {
         const Node& par = P->nodes[P->nodes[cur].parent];
-        for (int s : par.children) {
+        std::vector<int> pre;
+        for (int s : par.visit) {
           if (s == cur) break;
-          nd.S.push_back(s);
+          pre.push_back(s);
         }
+        per_level.push_back(pre);
         cur = P->nodes[cur].parent;
       }
-      std::sort(nd.S.begin(), nd.S.end(),
-                [&](int a, int b) { return P->nodes[a].first < P->nodes[b].first; });
-      for (int s : nd.S) nd.xpos.push_back(P->nodes[s].k);
-      for (int mu = nd.last + 1; mu < P->d; ++mu) nd.xpos.push_back(P->dims[mu]);
+      for (auto it = per_level.rbegin(); it != per_level.rend(); ++it) nd.S.insert(nd.S.end(), it->begin(), it->end());
+      // X_t rows: the indices of T_{S_t} outside I_t in mode order, each contracted
+      // group one index of size k_s at its place
+      std::vector<int> group_of(P->d, -1);
+      for (int s : nd.S)
+        for (int mu = P->nodes[s].first; mu <= P->nodes[s].last; ++mu) group_of[mu] = s;
+      for (int mu = 0; mu < P->d; ++mu) {
+        if (mu >= nd.first && mu <= nd.last) continue;
+        const int g = group_of[mu];
+        if (g >= 0 && mu != P->nodes[g].first) continue;        // inside a group already placed
+        nd.xpos.push_back(g < 0 ? P->dims[mu] : P->nodes[g].k);
+        if (mu < nd.first) ++nd.xsplit;
+      }
     } else {
       for (int mu = 0; mu < P->d; ++mu)
         if (mu < nd.first || mu > nd.last) nd.xpos.push_back(P->dims[mu]);
+      nd.xsplit = nd.first;
     }
     nd.m = 1;
     for (int64_t s : nd.xpos) {
@@ -369,7 +404,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
 
   // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)
   const char* nf = std::getenv("TTNN_DISABLE_FUSED");
-  P->allow_fused = !(nf && nf[0] == '1') && !kr && P->nodes.size() == static_cast<size_t>(nn);
+  P->allow_fused = !(nf && nf[0] == '1') && !kr && P->nodes.size() == static_cast<size_t>(nn) && P->lex;
   // transposed DRM copies for whole-tensor right sketches on MFMA (large tensors only,
   // nodes sketched on the raw tensor that the fused kernel does not cover)
   auto plan_xt = [&](bool fill) {
@@ -385,13 +420,13 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       }
       if (F.enabled && (v == F.node_A || v == F.node_1 || v == (F.tt ? F.node_B : F.node_2))) continue;
       if (!nd.S.empty()) {
-        // the intermediate T x_{s in S_t} Y_s^T: [prod k_s][n_t][modes after t]; only
+        // the intermediate T x_{s in S_t} Y_s^T: [positions before t][n_t][after]; only
         // large ones (the small ones share batched FP64 launches), and only while the
         // copy stays modest (it doubles the FP64 DRM of the node)
-        int64_t Q = 1;
-        for (int mu = nd.last + 1; mu < P->d; ++mu) Q *= P->dims[mu];
-        const int64_t L = nd.m / Q;
-        if (L * Q == nd.m && L * nd.n * Q >= (int64_t(1) << 22) && nd.m * nd.r <= (int64_t(1) << 26) &&
+        int64_t L = 1;
+        for (int i = 0; i < nd.xsplit; ++i) L *= nd.xpos[i];
+        const int64_t Q = nd.m / L;
+        if (L * nd.n * Q >= (int64_t(1) << 22) && nd.m * nd.r <= (int64_t(1) << 26) &&
             right_mfma_eligible(L, nd.n, Q, nd.r, TTNN_F64)) {
           nd.Xt64 = static_cast<double*>(P->alloc(sizeof(double) * nd.m * nd.r));
           if (fill) copy_layout(nd.X64, nd.Xt64, TTNN_F64, nd.m, nd.r, 1, nd.r, 1, 0, 0, nd.m, stream);

@@ -17,11 +17,14 @@ struct Node {
   int parent = -1;             // level-order id
   int first = 0, last = 0;     // 0-based mode interval
   std::vector<int> children;   // level-order ids, left to right
+  std::vector<int> visit;      // the children in the STTNN visiting order (free modes last)
   int r = 0, p = 0, k = 0;     // rank, oversample, r + p
   int64_t n = 1;               // n_t = prod of dims over the interval
   int64_t m = 1;               // rows of X_t
-  std::vector<int> S;          // STTNN reuse set (level-order ids, left to right)
-  std::vector<int64_t> xpos;   // sizes of the positions indexing the rows of X_t
+  std::vector<int> S;          // STTNN reuse set (level-order ids) in the order its chain of
+                               // contractions takes them: the ancestors' groups first
+  std::vector<int64_t> xpos;   // sizes of the positions indexing the rows of X_t, in order
+  int xsplit = 0;              // how many of them come before the modes of t
   bool ident = false;          // a free mode of the parent: identity maps, projector and core
                                // (r = k = n); no sketches of its own
   bool leaf() const { return children.empty(); }
@@ -103,6 +106,7 @@ struct Plan {
   bool has_cores = false;
   FusedT4 fused;
   bool allow_fused = true;                 // off: every update takes the generic path
+  bool lex = true;                         // STTNN visits the children left to right
   // measurement hook: events around the sweep of the last update (see ttnn_set_timing)
   bool timing = false;
   hipEvent_t sweep_ev[2] = {nullptr, nullptr};

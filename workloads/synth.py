@@ -178,6 +178,16 @@ def config2_tensor(n=128, rank=24, decay=0.8, noise_std=1e-4, seed=0):
     return add_relative_noise(T, noise_std, seed=seed + 1, unit_rms=True)
 
 
+def unbalanced_tensor(dims=(32, 512, 128, 128), rank=24, decay=0.8, noise_std=1e-4, seed=0):
+    """The recipe of config2_tensor on ((1,2),(3,4)) with unequal mode sizes (n_1 << n_2),
+    where the STTNN visiting order changes the sizes of the maps."""
+    spec = ((1, 2), (3, 4))
+    sigma = decay ** np.arange(rank)
+    cores = decaying_ttn_cores(spec, dims, rank, sigma, seed)
+    T = ttn_dense(spec, dims, cores)
+    return add_relative_noise(T, noise_std, seed=seed + 1, unit_rms=True)
+
+
 def small_random_ttn(spec, dims, ranks, seed, noise=0.0):
     cores = gaussian_ttn_cores(spec, dims, ranks, seed)
     T = ttn_dense(spec, dims, cores)
