@@ -864,7 +864,8 @@ def roofline_of(flops, nbytes, ms, dtype):
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
 
 
-def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=None, traffic=None, rounding=None):
+def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=None, traffic=None, rounding=None,
+                 pipelined=None, orders=None):
     """The one JSON record the benchmark prints last (kept well under 4 KB): headline
     value, the sweep kernel's roofline and a step-level one, the CPU baseline and a
     short summary of every other measured configuration."""
@@ -909,14 +910,14 @@ def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=
     if copy is not None:
         line["copy_GBps_read_plus_write"] = round(copy["GBps_read_plus_write"], 1)
     if serving is not None:
-        sv = {}
+        fields = ("updates_per_s", "ingest_GBps", "p50_ms", "p99_ms", "box_device_p99_ms", "rank1_device_p99_ms",
+                  "approx_rel_error")
+        sv = {"fields": list(fields)}
         for name in ("batched_f32_closed_loop", "batched_f32_poisson", "fp64_one_per_launch_closed_loop",
                      "fp64_one_per_launch_poisson", "single_stream_f32"):
             s = serving.get(name)
             if s:
-                sv[name] = {f: float(f"{s[f]:.4g}") for f in ("updates_per_s", "ingest_GBps", "p50_ms", "p99_ms",
-                                                               "box_device_p99_ms", "rank1_device_p99_ms",
-                                                               "approx_rel_error") if f in s}
+                sv[name] = [float(f"{s[f]:.4g}") if s.get(f) is not None else None for f in fields]
         line["serving"] = sv
     if hilbert is not None:
         line["hilbert_6d"] = {c: f"r{rows[-1]['rank']} err {rows[-1]['mean_rel_error']:.2g}"
@@ -928,6 +929,13 @@ def compact_line(args, key, results, cpu=None, serving=None, hilbert=None, copy=
         if rounding.get("cpu_baseline"):
             rr["cpu_oracle_ms"] = round(rounding["cpu_baseline"]["value"], 1)
         line["ttn_rounding"] = rr
+    if pipelined:
+        line["two_plans_in_turn_ms_per_step"] = {k: round(v, 4) for k, v in pipelined.items()}
+    if orders:
+        # ms per step, [lexicographic, searched] visiting order
+        line["sttnn_order_ms"] = {k.split("_r")[0]: [round(v[o]["ms_per_step"], 3) if o in v else None
+                                                   for o in ("lexicographic", "searched")]
+                                  for k, v in orders.items()}
     return line
 
 
@@ -1040,13 +1048,7 @@ def main():
         print(f"# cpu baseline: {json.dumps(cpu['phases_s'])}", file=sys.stderr, flush=True)
 
     line = compact_line(args, key, results, cpu=cpu, serving=serving, hilbert=hilbert, copy=copy,
-                        traffic=measured_traffic(key), rounding=rounding)
-    if pipelined:
-        line["two_plans_in_turn_ms_per_step"] = {k: round(v, 4) for k, v in pipelined.items()}
-    if orders:
-        line["sttnn_visiting_order_ms_per_step"] = {
-            k: {o: round(v[o]["ms_per_step"], 4) for o in ("lexicographic", "searched") if o in v}
-            for k, v in orders.items()}
+                        traffic=measured_traffic(key), rounding=rounding, pipelined=pipelined, orders=orders)
     detail = {"line": line, "results": results, "copy_calibration": copy, "serving": serving,
               "hilbert_6d": hilbert, "ttn_rounding": rounding, "two_plans_in_turn_ms_per_step": pipelined,
               "sttnn_visiting_order": orders,

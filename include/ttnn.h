@@ -334,7 +334,8 @@ ttnn_status ttnn_reconstruct(ttnn_plan_t plan, const double* const* d_cores, voi
 
 /* Squared Frobenius norms ||a - b||^2 and ||b||^2 of two dense arrays of n entries,
  * a of dtype a_dtype, b FP64 (error of a reconstruction).  Deterministic; synchronises
- * `stream` and writes h_out[0..1]. */
+ * `stream` and writes h_out[0..1].  Its 16 KB of partial sums come from the library's
+ * per-device pool, stream ordered. */
 ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b, int64_t n,
                             double* h_out, void* stream);
 

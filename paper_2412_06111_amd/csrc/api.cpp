@@ -483,14 +483,17 @@ ttnn_status ttnn_diff_norms(const void* d_a, int32_t a_dtype, const double* d_b,
     if (!d_a || !d_b || !h_out || n < 0) throw Error{TTNN_E_INVALID, "bad argument"};
     if (a_dtype != TTNN_F64 && a_dtype != TTNN_F32 && a_dtype != TTNN_BF16) throw Error{TTNN_E_INVALID, "bad dtype"};
     hipStream_t st = as_stream(stream);
-    double* d_part = nullptr;
-    TTNN_HIP(hipMalloc(&d_part, sizeof(double) * (2 * ttnn::kNormBlocks + 2)));
+    // partial sums from the library's per-device pool, stream ordered (no device-wide
+    // allocation or free per call)
+    struct Block {                             // returned to the pool in stream order, also on errors
+      void* p;
+      hipStream_t s;
+      ~Block() { ttnn::pool_free(p, s); }
+    } blk{ttnn::pool_alloc(sizeof(double) * (2 * ttnn::kNormBlocks + 2), st), st};
+    double* d_part = static_cast<double*>(blk.p);
     ttnn::launch_diff_norms(d_a, a_dtype, d_b, n, d_part, d_part + 2 * ttnn::kNormBlocks, st);
-    hipError_t e = hipMemcpyAsync(h_out, d_part + 2 * ttnn::kNormBlocks, 2 * sizeof(double),
-                                  hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(d_part);
-    TTNN_HIP(e);
+    TTNN_HIP(hipMemcpyAsync(h_out, d_part + 2 * ttnn::kNormBlocks, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TTNN_HIP(hipStreamSynchronize(st));
     return TTNN_OK;
   });
 }

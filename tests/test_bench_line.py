@@ -37,7 +37,8 @@ def _recorded():
         res[f"sttnn:f64:r{rr}"] = _result("sttnn", "f64", rr, 2)
         res[f"sttnn:bf16:r{rr}"] = _result("sttnn", "bf16", rr, 2)
     st = {"updates": 6614, "wall_s": 0.3456789, "updates_per_s": 19123.456789, "ingest_GBps": 56.123456,
-          "p50_ms": 0.71234567, "p99_ms": 83.1234567, "mean_batch": 40.1234}
+          "p50_ms": 0.71234567, "p99_ms": 83.1234567, "mean_batch": 40.1234, "box_device_p99_ms": 0.1234567,
+          "rank1_device_p99_ms": 0.01234567, "approx_rel_error": 2.51234e-4}
     serving = {k: dict(st) for k in ("batched_f32_closed_loop", "batched_f32_poisson",
                                      "fp64_one_per_launch_closed_loop", "fp64_one_per_launch_poisson")}
     serving["single_stream_f32"] = {"updates_per_s": 3712.3456, "ingest_GBps": 4.2345678, "update_p50_ms": 0.1234567,
@@ -51,14 +52,24 @@ def _recorded():
            "phases_s": {"drm": 12.345, "sketch": 6.789, "assemble": 0.012, "reconstruct": 0.345},
            "cpu_model": "AMD EPYC 9575F 64-Core Processor with a long marketing name",
            "blas": "openblas 0.3.27 x16, openblas 0.3.27 x16"}
-    return res, serving, hilbert, cpu
+    rounding = {"workload": "order-6 TTN, n = 500, TTN ranks 70 on the Fig. 1 tree, Khatri-Rao maps, p = 10",
+                "rows": {f"{d}:r{r}": {"ms_per_rounding": 1.1912345, "mean_rel_error": 1.2345e-3}
+                         for d in ("quadratic", "cubic", "exponential") for r in (16, 32, 48)},
+                "cpu_baseline": {"value": 21.123456}}
+    pipelined = {"sttnn:f32": 0.98512345, "sttnn:bf16": 0.62712345}
+    orders = {"t4_32x512x128x128_r32_f32": {"lexicographic": {"ms_per_step": 2.82212345},
+                                            "searched": {"ms_per_step": 1.62012345}},
+              "hilbert6d_n20_fig1tree_r13_f64": {"lexicographic": {"ms_per_step": 1.32112345},
+                                                 "searched": {"ms_per_step": 1.13212345}}}
+    return res, serving, hilbert, cpu, rounding, pipelined, orders
 
 
 def test_compact_line_parses_and_fits():
-    res, serving, hilbert, cpu = _recorded()
+    res, serving, hilbert, cpu, rounding, pipelined, orders = _recorded()
     args = SimpleNamespace(steps=20, warmup=40, n=128, rank=32, over=16)
     line = bench.compact_line(args, "sttnn:f32", res, cpu=cpu, serving=serving, hilbert=hilbert,
-                              copy={"GBps_read_plus_write": 4567.891}, traffic=1980000000)
+                              copy={"GBps_read_plus_write": 4567.891}, traffic=1980000000, rounding=rounding,
+                              pipelined=pipelined, orders=orders)
     text = json.dumps(line)
     assert "\n" not in text
     assert len(text) < 4096, len(text)
