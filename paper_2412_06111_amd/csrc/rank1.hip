@@ -13,6 +13,7 @@ namespace ttnn {
 namespace {
 
 constexpr int kThreadsR = 256;
+constexpr int kFacCache = 1024;   // factor entries kept in LDS by the GEMV (8 KB)
 
 __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   double w = 1.0;
@@ -25,60 +26,112 @@ __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   return w;
 }
 
-// the same with 32-bit index arithmetic (rows below 2^32)
-__device__ inline double kron_weight32(const KronVec& kv, uint32_t row) {
-  double w = 1.0;
-  for (int p = 0; p < kv.n; ++p) {
-    const uint32_t e = static_cast<uint32_t>(kv.len[p]);
-    const uint32_t q = row / e;
-    w *= kv.v[p][row - q * e];
-    row = q;
-  }
-  return w;
-}
-
 // partial[b][j] = sum over the rows of block b of D[row * ncols + j] * weight(row).  The
-// block's rows are contiguous in D: each step copies RB of them into LDS with coalesced
-// loads (consecutive threads, consecutive elements; rows padded by one element against
-// bank conflicts), then one lane per row forms the row's weight once and accumulates
-// its ncols products in FP64 (NC >= ncols accumulators a lane); a fixed-order reduction
-// over the lanes (shuffles, then the waves in order) ends the block.
-template <typename TD, int NC>
+// block's rows are contiguous in D: each step copies RB of them into LDS with 16-byte
+// loads (consecutive threads, consecutive vectors; rows padded by one element against
+// bank conflicts), then one lane per row forms the row's weight and accumulates its
+// ncols products in FP64 (NC >= ncols accumulators a lane); a fixed-order reduction
+// over the lanes (shuffles, then the waves in order) ends the block.  A lane's row
+// advances by RB a step, so its mixed-radix digits (one per factor) advance by the
+// digits of RB with one carry test each instead of a division per factor and row.
+// rows_per_block is a multiple of RB, so every step but the block's last is whole.
+template <typename TD, int NC, typename DI>
 __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restrict__ D, int64_t rows, int ncols,
-                                                              KronVec kv, int64_t rows_per_block, bool small,
+                                                              KronVec kv, int64_t rows_per_block,
                                                               double* __restrict__ partial) {
   constexpr int RB = sizeof(TD) == 8 ? kThreadsR / 2 : kThreadsR;     // rows a step (LDS <= 66 KB)
+  constexpr int V = 16 / static_cast<int>(sizeof(TD));                // elements a 16-byte load
+  constexpr int PER = (NC * RB + kThreadsR * V - 1) / (kThreadsR * V);  // loads a thread a step
+  typedef TD vec_t __attribute__((ext_vector_type(V)));
   __shared__ TD tile[RB * (NC + 1)];
   __shared__ double red[kThreadsR / 64][NC];
+  __shared__ double fac[kFacCache];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // the factors in LDS when they fit (the usual case: a few hundred entries), so that the
+  // weights never wait on global memory: a wait for a global gather issued after the
+  // next step's loads would also wait for those loads (the counter is in order)
+  int foff[kMaxPos];
+  bool cached;
+  {
+    int64_t tot = 0;
+    for (int p = 0; p < kv.n; ++p) {
+      foff[p] = static_cast<int>(tot < kFacCache ? tot : 0);
+      tot += kv.len[p];
+    }
+    cached = tot <= kFacCache;
+    if (cached)
+      for (int p = 0; p < kv.n; ++p)
+        for (int64_t i = tid; i < kv.len[p]; i += kThreadsR) fac[foff[p] + i] = kv.v[p][i];
+    __syncthreads();
+  }
   const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
   const int ld = ncols + 1;
-  const int dr = kThreadsR / ncols, dc = kThreadsR % ncols;            // a thread's stride in (row, col)
+  // (row, column) of this thread's first element of each load, and the stride between
+  // its loads (kThreadsR * V elements)
+  const int x0 = tid * V;
+  const int row0 = x0 / ncols, col0 = x0 - row0 * ncols;
+  const int dr = (kThreadsR * V) / ncols, dc = (kThreadsR * V) % ncols;
+  // digits of this lane's first row and of the step (DI: 32-bit when every factor is
+  // shorter than 2^30, so that a digit plus a step digit plus a carry cannot overflow)
+  DI dig[kMaxPos], stp[kMaxPos];
+  {
+    int64_t a = r0 + tid, b = RB;
+    for (int p = 0; p < kv.n; ++p) {
+      const int64_t e = kv.len[p];
+      dig[p] = static_cast<DI>(a % e);
+      a /= e;
+      stp[p] = static_cast<DI>(b % e);
+      b /= e;
+    }
+  }
   double acc[NC];
 #pragma unroll
   for (int j = 0; j < NC; ++j) acc[j] = 0.0;
-  // a step's elements: at most RB * NC, i.e. NC * (RB / kThreadsR) per thread
-  constexpr int PER = NC * RB / kThreadsR;
-  TD v[PER];
+  vec_t v[PER];
   auto fetch = [&](int64_t b) {            // the step's loads, all in flight together
     const int64_t nr = r1 - b < RB ? r1 - b : RB;
-    const int total = static_cast<int>(nr) * ncols;
     const TD* src = D + b * ncols;
+    if (nr == RB) {
+      // a whole step: RB * ncols elements, a multiple of V, 16-byte aligned (RB rows);
+      // one predicated vector load each, no dependence between them
+      const int total = RB * ncols;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      const int e = tid + k * kThreadsR;
-      v[k] = e < total ? src[e] : TD(0);
+      for (int k = 0; k < PER; ++k) {
+        const int e = (tid + k * kThreadsR) * V;
+        v[k] = e < total ? *reinterpret_cast<const vec_t*>(src + e) : vec_t{};
+      }
+    } else {
+      // the block's last, partial step: element by element
+      const int total = static_cast<int>(nr) * ncols;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        const int e = (tid + k * kThreadsR) * V;
+        vec_t t{};
+#pragma unroll
+        for (int i = 0; i < V; ++i)
+          if (e + i < total) t[i] = src[e + i];
+        v[k] = t;
+      }
     }
   };
   if (r0 < r1) fetch(r0);
   for (int64_t base = r0; base < r1; base += RB) {
     const int nr = static_cast<int>(r1 - base < RB ? r1 - base : RB);
     const int total = nr * ncols;
-    int rr = tid / ncols, cc = tid % ncols;
+    int rr = row0, cc = col0;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      if (tid + k * kThreadsR < total) tile[rr * ld + cc] = v[k];
+      const int e = (tid + k * kThreadsR) * V;
+      int r = rr, c = cc;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        if (e + i < total) tile[r * ld + c] = v[k][i];
+        if (++c == ncols) {
+          c = 0;
+          ++r;
+        }
+      }
       rr += dr;
       cc += dc;
       if (cc >= ncols) {
@@ -89,12 +142,22 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
     __syncthreads();
     if (base + RB < r1) fetch(base + RB);  // next step's loads overlap this step's products
     if (tid < nr) {
-      const int64_t row = base + tid;
-      const double w = small ? kron_weight32(kv, static_cast<uint32_t>(row)) : kron_weight(kv, row);
-      const TD* p = tile + tid * ld;
+      double w = 1.0;
+      if (cached)
+        for (int p = 0; p < kv.n; ++p) w *= fac[foff[p] + dig[p]];
+      else
+        for (int p = 0; p < kv.n; ++p) w *= kv.v[p][dig[p]];
+      const TD* q = tile + tid * ld;
 #pragma unroll
       for (int j = 0; j < NC; ++j)
-        if (j < ncols) acc[j] += to_f64(p[j]) * w;
+        if (j < ncols) acc[j] += to_f64(q[j]) * w;
+    }
+    DI carry = 0;                            // row += RB in mixed radix
+    for (int p = 0; p < kv.n; ++p) {
+      const DI x = dig[p] + stp[p] + carry;
+      const DI e = static_cast<DI>(kv.len[p]);
+      carry = x >= e;
+      dig[p] = carry ? x - e : x;
     }
     __syncthreads();
   }
@@ -114,20 +177,30 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
   }
 }
 
-template <typename TD>
-void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, bool small, dim3 grid,
+template <typename TD, typename DI>
+void launch_gemv_di(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, dim3 grid,
                     double* partial, hipStream_t st) {
   if (ncols <= 8)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 8>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small, partial);
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 8, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
   else if (ncols <= 16)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 16>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
-                       partial);
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 16, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
+  else if (ncols <= 24)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 24, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
   else if (ncols <= 32)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 32>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
-                       partial);
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 32, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
+  else if (ncols <= 48)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 48, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
   else
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 64>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, small,
-                       partial);
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, 64, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
+}
+
+template <typename TD>
+void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, dim3 grid,
+                    double* partial, hipStream_t st) {
+  bool short_factors = true;
+  for (int p = 0; p < kv.n; ++p) short_factors = short_factors && kv.len[p] < (int64_t(1) << 30);
+  if (short_factors) launch_gemv_di<TD, int>(D, rows, ncols, kv, per, grid, partial, st);
+  else launch_gemv_di<TD, int64_t>(D, rows, ncols, kv, per, grid, partial, st);
 }
 
 // w[j] = sum_b partial[b][j]: one wave per column, lane l summing blocks l, l + 64, ..
@@ -167,18 +240,19 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
   const int64_t cap = static_cast<int64_t>(partial_elems / static_cast<size_t>(ncols));
   if (nb > cap) nb = cap;
   TTNN_REQUIRE(nb >= 1, TTNN_E_INVALID, "rank-1 scratch too small");
-  const int64_t per = (rows + nb - 1) / nb;
+  // rows a block: a multiple of the kernel's step (128 rows for FP64 maps, else 256)
+  const int64_t rb = dt == TTNN_F64 ? kThreadsR / 2 : kThreadsR;
+  int64_t per = (rows + nb - 1) / nb;
+  per = (per + rb - 1) / rb * rb;
+  if (per < rb) per = rb;
   nb = rows > 0 ? (rows + per - 1) / per : 1;
   const dim3 grid(static_cast<unsigned>(nb));
-  const int64_t pr = per > 0 ? per : 1;
-  bool small = rows < (int64_t(1) << 32);
-  for (int p = 0; p < kv.n; ++p) small = small && kv.len[p] < (int64_t(1) << 32);
   if (dt == TTNN_F64)
-    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kv, pr, small, grid, partial, st);
+    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kv, per, grid, partial, st);
   else if (dt == TTNN_F32)
-    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kv, pr, small, grid, partial, st);
+    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kv, per, grid, partial, st);
   else
-    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kv, pr, small, grid, partial, st);
+    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kv, per, grid, partial, st);
   hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols), dim3(64), 0, st, partial, static_cast<int>(nb), ncols, w);
 }
 
