@@ -240,6 +240,15 @@ ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int6
 ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_factors,
                                      double alpha, void* stream);
 
+/* nterms rank-1 updates in one call (streaming by linearity, Sec. 4): d_factors is a
+ * host array of nterms x order device pointers, term-major (term i's factor of mode mu
+ * at d_factors[i * order + mu]), alphas a host array of nterms scales.  Bitwise equal
+ * to nterms calls of ttnn_sketch_update_rank1 in order; up to 8 terms share one read
+ * of each map (a rank-1 update reads every map once, so a batch of terms costs about
+ * one term's map traffic).  nterms = 0 is a no-op. */
+ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, const double* const* d_factors,
+                                             const double* alphas, void* stream);
+
 /* Several box updates, possibly for different plans, in one call (continuous
  * batching of streamed updates, Sec. 4 linearity).  The call works in rounds: a
  * round takes the earliest remaining update of every plan; the box updates of a

@@ -69,6 +69,7 @@ def _load():
         "ttnn_destroy_async": [vp, vp],
         "ttnn_sketch_update": [vp, vp, P64, P64, P64, dbl, vp],
         "ttnn_sketch_update_rank1": [vp, C.POINTER(vp), dbl, vp],
+        "ttnn_sketch_update_rank1_batched": [vp, i32, C.POINTER(vp), C.POINTER(dbl), vp],
         "ttnn_sketch_update_batched": [i32, C.POINTER(UpdateDesc), vp],
         "ttnn_core_shape": [vp, i32, C.POINTER(i32), P64],
         "ttnn_assemble": [vp, C.POINTER(vp), vp],
@@ -418,6 +419,22 @@ class Plan:
             check_block(f, torch.float64, (n,), 1)
         ptrs = (C.c_void_p * self.d)(*[C.c_void_p(f.data_ptr()) for f in factors])
         check(lib.ttnn_sketch_update_rank1(self.handle, ptrs, float(alpha), stream_ptr(stream)))
+
+    def update_rank1_batched(self, terms, alphas, stream=None):
+        """terms: a list of factor lists (each as for update_rank1); alphas: one scale per
+        term.  Bitwise equal to the terms applied one by one in order."""
+        if len(terms) != len(alphas):
+            raise ValueError(f"{len(terms)} terms and {len(alphas)} scales")
+        flat = []
+        for factors in terms:
+            if len(factors) != self.d:
+                raise ValueError(f"{len(factors)} factors for a tensor of order {self.d}")
+            for f, n in zip(factors, self.dims):
+                check_block(f, torch.float64, (n,), 1)
+            flat += [C.c_void_p(f.data_ptr()) for f in factors]
+        ptrs = (C.c_void_p * max(len(flat), 1))(*flat)
+        al = (C.c_double * max(len(alphas), 1))(*[float(a) for a in alphas])
+        check(lib.ttnn_sketch_update_rank1_batched(self.handle, len(terms), ptrs, al, stream_ptr(stream)))
 
     # ------------------------------------------------------------ TTN-format inputs
     def _ranks_list(self, ranks):

@@ -211,7 +211,22 @@ ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_fa
     dense_updates(*P);
     for (int mu = 0; mu < P->d; ++mu)
       if (!d_factors[mu]) throw Error{TTNN_E_INVALID, "factor pointer is NULL"};
-    ttnn::update_rank1(*P, d_factors, alpha, as_stream(stream));
+    ttnn::update_rank1(*P, 1, d_factors, &alpha, as_stream(stream));
+    TTNN_HIP(hipGetLastError());
+    return TTNN_OK;
+  });
+}
+
+ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, const double* const* d_factors,
+                                             const double* alphas, void* stream) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P || nterms < 0 || (nterms > 0 && (!d_factors || !alphas)))
+      throw Error{TTNN_E_INVALID, "plan, factors or alphas is NULL, or nterms < 0"};
+    dense_updates(*P);
+    for (int64_t e = 0; e < static_cast<int64_t>(nterms) * P->d; ++e)
+      if (!d_factors[e]) throw Error{TTNN_E_INVALID, "factor pointer is NULL"};
+    ttnn::update_rank1(*P, nterms, d_factors, alphas, as_stream(stream));
     TTNN_HIP(hipGetLastError());
     return TTNN_OK;
   });

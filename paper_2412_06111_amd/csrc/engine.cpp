@@ -1034,57 +1034,78 @@ void run_reconstruct(Plan& P, const double* const* cores, void* out, int out_dty
 // of the raw tensor (a chain's first group, or X_t when S_t is empty), the FP64
 // master for a contraction of an FP64 intermediate; products and sums are FP64.
 // Reads every row of every X_t once.
-void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t st) {
+void update_rank1(Plan& P, int nterms, const double* const* factors, const double* alphas, hipStream_t st) {
   P.epilogue_valid = false;
   const int cd = P.dtype;
-  auto modes = [&](int first, int last) {
-    KronVec kv;
-    for (int mu = first; mu <= last; ++mu) kv.push(factors[mu], P.dims[mu]);
-    return kv;
-  };
-  // a group is contracted from the raw tensor exactly when it heads its chains, that is
-  // when its own reuse set is empty (free modes: identity maps, exact in any dtype)
-  std::vector<int64_t> goff(P.nodes.size(), -1);
-  int64_t used = 0;
-  auto g_of = [&](int s) -> const double* {
-    if (goff[s] < 0) {
-      const Node& g = P.nodes[s];
-      goff[s] = used;
-      used += g.k;
-      const bool raw = g.S.empty();
-      launch_kron_gemv(raw ? g.Yc : static_cast<const void*>(g.Y64), raw ? cd : TTNN_F64, g.n, g.k,
-                       modes(g.first, g.last), P.partial, P.partial_elems, P.r1 + goff[s], st);
-    }
-    return P.r1 + goff[s];
-  };
-  double* w = P.r1 + P.r1_w;
-  for (size_t v = 1; v < P.nodes.size(); ++v) {
-    const Node& t = P.nodes[v];
-    if (t.ident) continue;                      // a free mode: no sketch of its own
-    KronVec kx;
-    if (P.variant == TTNN_STTNN) {
-      // the rows of X_t: the indices of T_{S_t} outside I_t in mode order
-      std::vector<int> group_of(P.d, -1);
-      for (int s : t.S)
-        for (int mu = P.nodes[s].first; mu <= P.nodes[s].last; ++mu) group_of[mu] = s;
-      for (int mu = 0; mu < P.d; ++mu) {
-        if (mu >= t.first && mu <= t.last) continue;
-        const int s = group_of[mu];
-        if (s < 0) kx.push(factors[mu], P.dims[mu]);
-        else if (mu == P.nodes[s].first) kx.push(g_of(s), P.nodes[s].k);
+  const int d = P.d;
+  // the terms in batches of kRank1Batch: a batch reads each map about once; every
+  // term's arithmetic is that of a batch of one, so the result does not depend on the
+  // batching
+  for (int t0 = 0; t0 < nterms; t0 += kRank1Batch) {
+    const int m = std::min(kRank1Batch, nterms - t0);
+    const double* const* f = factors + static_cast<size_t>(t0) * d;
+    auto modes = [&](int y, int first, int last) {
+      KronVec kv;
+      for (int mu = first; mu <= last; ++mu) kv.push(f[y * d + mu], P.dims[mu]);
+      return kv;
+    };
+    // g_s = Y_s^T u_{I_s} per term, at P.r1 + y * r1_w + goff[s]; a group is contracted
+    // from the raw tensor exactly when it heads its chains, that is when its own reuse
+    // set is empty (free modes: identity maps, exact in any dtype)
+    std::vector<int64_t> goff(P.nodes.size(), -1);
+    int64_t used = 0;
+    auto g_of = [&](int s) {
+      if (goff[s] < 0) {
+        const Node& g = P.nodes[s];
+        goff[s] = used;
+        used += g.k;
+        const bool raw = g.S.empty();
+        KronBatch kb;
+        for (int y = 0; y < m; ++y) kb.push(modes(y, g.first, g.last));
+        launch_kron_gemv(raw ? g.Yc : static_cast<const void*>(g.Y64), raw ? cd : TTNN_F64, g.n, g.k, kb, P.partial,
+                         P.partial_elems, P.r1 + goff[s], P.r1_w, st);
       }
-    } else {
-      for (int mu = 0; mu < P.d; ++mu)
-        if (mu < t.first || mu > t.last) kx.push(factors[mu], P.dims[mu]);
+      return goff[s];
+    };
+    double* w = P.r1 + static_cast<int64_t>(kRank1Batch) * P.r1_w;     // m x rmax
+    const int64_t wstride = P.r1_rmax;
+    for (size_t v = 1; v < P.nodes.size(); ++v) {
+      const Node& t = P.nodes[v];
+      if (t.ident) continue;                    // a free mode: no sketch of its own
+      KronBatch kx, ku;
+      for (int y = 0; y < m; ++y) {
+        KronVec k;
+        if (P.variant == TTNN_STTNN) {
+          // the rows of X_t: the indices of T_{S_t} outside I_t in mode order
+          std::vector<int> group_of(d, -1);
+          for (int s : t.S)
+            for (int mu = P.nodes[s].first; mu <= P.nodes[s].last; ++mu) group_of[mu] = s;
+          for (int mu = 0; mu < d; ++mu) {
+            if (mu >= t.first && mu <= t.last) continue;
+            const int s = group_of[mu];
+            if (s < 0) k.push(f[y * d + mu], P.dims[mu]);
+            else if (mu == P.nodes[s].first) k.push(P.r1 + y * P.r1_w + g_of(s), P.nodes[s].k);
+          }
+        } else {
+          for (int mu = 0; mu < d; ++mu)
+            if (mu < t.first || mu > t.last) k.push(f[y * d + mu], P.dims[mu]);
+        }
+        kx.push(k);
+        ku.push(modes(y, t.first, t.last), alphas[t0 + y]);
+      }
+      const bool raw = t.S.empty();
+      launch_kron_gemv(raw ? t.Xc : static_cast<const void*>(t.X64), raw ? cd : TTNN_F64, t.m, t.r, kx, P.partial,
+                       P.partial_elems, w, wstride, st);
+      launch_outer_acc(t.R, t.n, t.r, ku, w, wstride, st);
     }
-    const bool raw = t.S.empty();
-    launch_kron_gemv(raw ? t.Xc : static_cast<const void*>(t.X64), raw ? cd : TTNN_F64, t.m, t.r, kx, P.partial,
-                     P.partial_elems, w, st);
-    launch_outer_acc(t.R, t.n, t.r, modes(t.first, t.last), w, alpha, st);
+    KronBatch kg;
+    for (int y = 0; y < m; ++y) {
+      KronVec k;
+      for (int c : P.nodes[0].children) k.push(P.r1 + y * P.r1_w + g_of(c), P.nodes[c].k);
+      kg.push(k, alphas[t0 + y]);
+    }
+    launch_outer_acc(P.psi_root, P.psi_root_len, 1, kg, nullptr, 0, st);
   }
-  KronVec kg;
-  for (int c : P.nodes[0].children) kg.push(g_of(c), P.nodes[c].k);
-  launch_outer_acc(P.psi_root, P.psi_root_len, 1, kg, nullptr, alpha, st);
 }
 
 }  // namespace ttnn

@@ -24,7 +24,9 @@ void zero_accumulators(Plan& P, hipStream_t stream);
 // strides: element strides of the block per mode (read in place), or nullptr = packed.
 void update_box(Plan& P, const void* block, const int64_t* off, const int64_t* ext, const int64_t* strides,
                 double alpha, hipStream_t stream);
-void update_rank1(Plan& P, const double* const* factors, double alpha, hipStream_t stream);
+// nterms rank-1 terms: factors holds nterms x order device pointers (term-major),
+// alphas nterms host scales; equal, bitwise, to the terms applied one by one in order.
+void update_rank1(Plan& P, int nterms, const double* const* factors, const double* alphas, hipStream_t stream);
 
 // The steps of a box update that is not the whole tensor, in order.  Plans with equal
 // batch_key() give step lists of equal length whose i-th steps have the same kind, so

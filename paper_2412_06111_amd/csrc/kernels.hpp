@@ -183,13 +183,30 @@ struct KronVec {
     ++n;
   }
 };
-// w[j] = sum_row D[row * ncols + j] * kv(row), D row-major rows x ncols of dtype dt
-// (products and sums in FP64); deterministic (fixed blocks, fixed summation order);
+// Up to kRank1Batch rank-1 terms handled by one launch (their vectors and scales).
+constexpr int kRank1Batch = 8;
+struct KronBatch {
+  int m = 0;
+  KronVec kv[kRank1Batch];
+  double alpha[kRank1Batch] = {};
+  void push(const KronVec& k, double a = 1.0) {
+    kv[m] = k;
+    alpha[m] = a;
+    ++m;
+  }
+};
+// w[y * wstride + j] = sum_row D[row * ncols + j] * kv_y(row) for every term y < kb.m,
+// D row-major rows x ncols of dtype dt (products and sums in FP64); deterministic
+// (fixed blocks, fixed summation order), and each term's result is bitwise the same
+// whatever the batch it is computed in.  The blocks of the terms over one chunk of rows
+// run side by side on one XCD, so the chunk comes from HBM about once per batch.
 // `partial` is scratch.
-void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronVec& kv, double* partial,
-                      size_t partial_elems, double* w, hipStream_t stream);
-// R[i + n j] += alpha * ku(i) * (w ? w[j] : 1), R column-major n x ncols.
-void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const double* w, double alpha,
+void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronBatch& kb, double* partial,
+                      size_t partial_elems, double* w, int64_t wstride, hipStream_t stream);
+// R[i + n j] += alpha_y * ku_y(i) * (w ? w[y * wstride + j] : 1) for y = 0 .. m-1 in that
+// order, R column-major n x ncols (each entry sees the terms' additions in order, as
+// with one launch per term).
+void launch_outer_acc(double* R, int64_t n, int ncols, const KronBatch& ku, const double* w, int64_t wstride,
                       hipStream_t stream);
 
 // ---------------------------------------------------------------- whole-tensor right sketch on MFMA

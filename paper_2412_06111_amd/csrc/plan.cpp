@@ -398,8 +398,10 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       ks += static_cast<size_t>(P->nodes[v].k);
       if (!P->nodes[v].ident) rmax = std::max(rmax, static_cast<size_t>(P->nodes[v].r));
     }
+    // per term of a rank-1 batch: the g_s (ks) and one node's X_t^T v (rmax)
     P->r1_w = ks;
-    P->r1 = static_cast<double*>(P->alloc(sizeof(double) * (ks + rmax)));
+    P->r1_rmax = rmax;
+    P->r1 = static_cast<double*>(P->alloc(sizeof(double) * kRank1Batch * (ks + rmax)));
   }
 
   // TTNN_DISABLE_FUSED=1 routes every update through the generic kernels (parity checks)

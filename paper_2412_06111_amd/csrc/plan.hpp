@@ -86,8 +86,10 @@ struct Plan {
   size_t chain_elems = 0;
   double* partial = nullptr;               // split-K partials
   size_t partial_elems = 0;
-  double* r1 = nullptr;                    // rank-1 updates: g_s vectors, then w (max r)
-  size_t r1_w = 0;                         // offset of w in r1
+  double* r1 = nullptr;                    // rank-1 updates: per batch term the g_s vectors
+                                           // (r1_w each), then per term one X_t^T v (r1_rmax)
+  size_t r1_w = 0;                         // g_s entries of a term (sum of k_s)
+  size_t r1_rmax = 1;                      // largest r_t
   double* work = nullptr;                  // assembly / reconstruction scratch
   size_t work_elems = 0;
   int* d_flag = nullptr;                   // numeric-status flag written by kernels

@@ -35,10 +35,19 @@ __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
 // advances by RB a step, so its mixed-radix digits (one per factor) advance by the
 // digits of RB with one carry test each instead of a division per factor and row.
 // rows_per_block is a multiple of RB, so every step but the block's last is whole.
+// Blocks: the chunks of rows, padded to a multiple of 8, times the terms; block b takes
+// chunk x and term y with the terms of one chunk 8 blocks apart (the same XCD, dispatched
+// together), x = 8 (b / 8m) + b % 8, y = (b % 8m) / 8.  Term y writes partial[y nb + x].
 template <typename TD, int NC, typename DI>
 __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restrict__ D, int64_t rows, int ncols,
-                                                              KronVec kv, int64_t rows_per_block,
+                                                              KronBatch kb, int64_t rows_per_block, int64_t nb,
                                                               double* __restrict__ partial) {
+  const int64_t bx = blockIdx.x, g8 = 8 * static_cast<int64_t>(kb.m);
+  const int64_t chunk = 8 * (bx / g8) + bx % 8;
+  const int term = static_cast<int>((bx % g8) / 8);
+  if (chunk >= nb) return;                 // padding chunks (whole block, before any barrier)
+  const KronVec& kv = kb.kv[term];
+  partial += static_cast<int64_t>(term) * nb * ncols;
   constexpr int RB = sizeof(TD) == 8 ? kThreadsR / 2 : kThreadsR;     // rows a step (LDS <= 66 KB)
   constexpr int V = 16 / static_cast<int>(sizeof(TD));                // elements a 16-byte load
   constexpr int PER = (NC * RB + kThreadsR * V - 1) / (kThreadsR * V);  // loads a thread a step
@@ -64,7 +73,7 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
         for (int64_t i = tid; i < kv.len[p]; i += kThreadsR) fac[foff[p] + i] = kv.v[p][i];
     __syncthreads();
   }
-  const int64_t r0 = static_cast<int64_t>(blockIdx.x) * rows_per_block;
+  const int64_t r0 = chunk * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
   const int ld = ncols + 1;
   // (row, column) of this thread's first element of each load, and the stride between
@@ -173,71 +182,77 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
     double s = red[0][tid];
 #pragma unroll
     for (int q = 1; q < kThreadsR / 64; ++q) s += red[q][tid];
-    partial[static_cast<int64_t>(blockIdx.x) * ncols + tid] = s;
+    partial[chunk * ncols + tid] = s;
   }
 }
 
 template <typename TD, typename DI>
-void launch_gemv_di(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, dim3 grid,
+void launch_gemv_di(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb, dim3 grid,
                     double* partial, hipStream_t st) {
-  if (ncols <= 8)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 8, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
-  else if (ncols <= 16)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 16, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
-  else if (ncols <= 24)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 24, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
-  else if (ncols <= 32)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 32, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
-  else if (ncols <= 48)
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 48, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
-  else
-    hipLaunchKernelGGL((kron_gemv_kernel<TD, 64, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kv, per, partial);
+#define TTNN_GEMV(NCV) \
+  hipLaunchKernelGGL((kron_gemv_kernel<TD, NCV, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kb, per, nb, partial)
+  if (ncols <= 8) TTNN_GEMV(8);
+  else if (ncols <= 16) TTNN_GEMV(16);
+  else if (ncols <= 24) TTNN_GEMV(24);
+  else if (ncols <= 32) TTNN_GEMV(32);
+  else if (ncols <= 48) TTNN_GEMV(48);
+  else TTNN_GEMV(64);
+#undef TTNN_GEMV
 }
 
 template <typename TD>
-void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronVec& kv, int64_t per, dim3 grid,
+void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb, dim3 grid,
                     double* partial, hipStream_t st) {
   bool short_factors = true;
-  for (int p = 0; p < kv.n; ++p) short_factors = short_factors && kv.len[p] < (int64_t(1) << 30);
-  if (short_factors) launch_gemv_di<TD, int>(D, rows, ncols, kv, per, grid, partial, st);
-  else launch_gemv_di<TD, int64_t>(D, rows, ncols, kv, per, grid, partial, st);
+  for (int y = 0; y < kb.m; ++y)
+    for (int p = 0; p < kb.kv[y].n; ++p) short_factors = short_factors && kb.kv[y].len[p] < (int64_t(1) << 30);
+  if (short_factors) launch_gemv_di<TD, int>(D, rows, ncols, kb, per, nb, grid, partial, st);
+  else launch_gemv_di<TD, int64_t>(D, rows, ncols, kb, per, nb, grid, partial, st);
 }
 
-// w[j] = sum_b partial[b][j]: one wave per column, lane l summing blocks l, l + 64, ..
-// in order, the 64 sums combined by a fixed butterfly
+// w[y wstride + j] = sum_b partial[y nb + b][j]: one wave per (column, term), lane l
+// summing blocks l, l + 64, .. in order, the 64 sums combined by a fixed butterfly
 __global__ __launch_bounds__(64) void sum_blocks_kernel(const double* __restrict__ partial, int nb, int ncols,
-                                                        double* __restrict__ w) {
-  const int j = blockIdx.x, l = threadIdx.x;
+                                                        double* __restrict__ w, int64_t wstride) {
+  const int j = blockIdx.x, y = blockIdx.y, l = threadIdx.x;
+  const double* p = partial + static_cast<int64_t>(y) * nb * ncols;
   double s = 0.0;
-  for (int b = l; b < nb; b += 64) s += partial[static_cast<int64_t>(b) * ncols + j];
+  for (int b = l; b < nb; b += 64) s += p[static_cast<int64_t>(b) * ncols + j];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (l == 0) w[j] = s;
+  if (l == 0) w[y * wstride + j] = s;
 }
 
-// R[i + n j] += alpha * weight(i) * (w ? w[j] : 1)
-__global__ void outer_acc_kernel(double* __restrict__ R, int64_t n, int ncols, KronVec ku, const double* __restrict__ w,
-                                 double alpha) {
+// R[i + n j] += alpha_y * weight_y(i) * (w ? w[y wstride + j] : 1), the terms in order
+__global__ void outer_acc_kernel(double* __restrict__ R, int64_t n, int ncols, KronBatch ku,
+                                 const double* __restrict__ w, int64_t wstride) {
   const int64_t total = n * ncols;
   for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t i = e % n;
     const int64_t j = e / n;
-    const double wj = w ? w[j] : 1.0;
-    R[e] += alpha * kron_weight(ku, i) * wj;
+    double r = R[e];
+    for (int y = 0; y < ku.m; ++y) {
+      const double wj = w ? w[y * wstride + j] : 1.0;
+      r += ku.alpha[y] * kron_weight(ku.kv[y], i) * wj;
+    }
+    R[e] = r;
   }
 }
 
 }  // namespace
 
-void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronVec& kv, double* partial,
-                      size_t partial_elems, double* w, hipStream_t st) {
-  if (ncols <= 0) return;
+void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronBatch& kb, double* partial,
+                      size_t partial_elems, double* w, int64_t wstride, hipStream_t st) {
+  if (ncols <= 0 || kb.m <= 0) return;
   TTNN_REQUIRE(ncols <= 64, TTNN_E_INVALID, "rank-1 update with more than 64 map columns");
-  int64_t nb = (rows + 511) / 512;                     // >= 512 rows a block, at most 2048 blocks
+  TTNN_REQUIRE(kb.m <= kRank1Batch, TTNN_E_INVALID, "too many rank-1 terms in one launch");
+  // >= 512 rows a block, at most 2048 blocks a term; the chunking depends on rows and
+  // ncols only, never on the batch, so a term's sums are the same in any batch
+  int64_t nb = (rows + 511) / 512;
   if (nb < 1) nb = 1;
   if (nb > 2048) nb = 2048;
-  const int64_t cap = static_cast<int64_t>(partial_elems / static_cast<size_t>(ncols));
+  const int64_t cap = static_cast<int64_t>(partial_elems / (static_cast<size_t>(ncols) * kRank1Batch));
   if (nb > cap) nb = cap;
   TTNN_REQUIRE(nb >= 1, TTNN_E_INVALID, "rank-1 scratch too small");
   // rows a block: a multiple of the kernel's step (128 rows for FP64 maps, else 256)
@@ -246,24 +261,26 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
   per = (per + rb - 1) / rb * rb;
   if (per < rb) per = rb;
   nb = rows > 0 ? (rows + per - 1) / per : 1;
-  const dim3 grid(static_cast<unsigned>(nb));
+  const int64_t padded = (nb + 7) / 8 * 8;             // chunks padded to the XCD count
+  const dim3 grid(static_cast<unsigned>(padded * kb.m));
   if (dt == TTNN_F64)
-    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kv, per, grid, partial, st);
+    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kb, per, nb, grid, partial, st);
   else if (dt == TTNN_F32)
-    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kv, per, grid, partial, st);
+    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kb, per, nb, grid, partial, st);
   else
-    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kv, per, grid, partial, st);
-  hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols), dim3(64), 0, st, partial, static_cast<int>(nb), ncols, w);
+    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kb, per, nb, grid, partial, st);
+  hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols, kb.m), dim3(64), 0, st, partial, static_cast<int>(nb), ncols, w,
+                     wstride);
 }
 
-void launch_outer_acc(double* R, int64_t n, int ncols, const KronVec& ku, const double* w, double alpha,
+void launch_outer_acc(double* R, int64_t n, int ncols, const KronBatch& ku, const double* w, int64_t wstride,
                       hipStream_t st) {
   const int64_t total = n * ncols;
-  if (total <= 0) return;
+  if (total <= 0 || ku.m <= 0) return;
   int64_t blocks = (total + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(outer_acc_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, R, n, ncols, ku, w,
-                     alpha);
+                     wstride);
 }
 
 }  // namespace ttnn

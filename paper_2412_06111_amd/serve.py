@@ -40,13 +40,14 @@ class Update:
     `extent`; kind 'rank1': `factors` (one FP64 device vector per mode)."""
 
     __slots__ = ("sid", "kind", "block", "offset", "extent", "factors", "alpha", "arrival", "nbytes",
-                 "t_done", "t_launch", "t_gpu", "batch")
+                 "t_done", "t_launch", "t_gpu", "batch", "group")
 
     def __init__(self, sid, kind="box", block=None, offset=None, extent=None, factors=None, alpha=1.0,
                  arrival=0.0, nbytes=0):
         self.sid, self.kind, self.block, self.offset, self.extent = sid, kind, block, offset, extent
         self.factors, self.alpha, self.arrival, self.nbytes = factors, alpha, arrival, nbytes
         self.t_done = None
+        self.group = None                       # rank-1: the terms launched with it (itself first)
         self.t_launch = None                    # host time its batch was launched
         self.t_gpu = None                       # device time of its batch (s)
         self.batch = None
@@ -85,7 +86,11 @@ class LibEngine:
             self.L.update_batched(boxes, stream=self.stream)
         for p, u in items:
             if u.kind == "rank1":
-                p.update_rank1(u.factors, u.alpha, stream=self.stream)
+                if u.group and len(u.group) > 1:          # one read of each map for the group
+                    p.update_rank1_batched([x.factors for x in u.group], [x.alpha for x in u.group],
+                                           stream=self.stream)
+                else:
+                    p.update_rank1(u.factors, u.alpha, stream=self.stream)
 
     def assemble(self, plan):
         """Cores of the plan; reads back the status of every assembly since the last
@@ -152,9 +157,13 @@ class _Stream:
 
 class Server:
     def __init__(self, budget_bytes, max_batch=64, max_inflight=2, assemble_every=0, engine=None,
-                 keep_plans=False, on_close=None):
+                 keep_plans=False, on_close=None, rank1_batch=8):
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
+        # consecutive queued rank-1 updates of one stream launched together (up to this
+        # many, never across an assembly point); the library applies them in order,
+        # bitwise as one by one, reading each map once for the group
+        self.rank1_batch = max(1, int(rank1_batch))
         self.max_inflight = int(max_inflight)
         self.assemble_every = int(assemble_every)
         self.keep_plans = keep_plans
@@ -265,20 +274,30 @@ class Server:
         chosen = self._form_batch()
         if not chosen:
             return 0
-        items, ups = [], []
+        items, ups, counts = [], [], []
         for st in chosen:
             u = st.queue.popleft()
-            u.batch = len(self.batches)
+            group = [u]
+            if u.kind == "rank1" and self.rank1_batch > 1:
+                room = self.rank1_batch
+                if self.assemble_every:
+                    room = min(room, self.assemble_every - st.n_done % self.assemble_every)
+                while len(group) < room and st.queue and st.queue[0].kind == "rank1":
+                    group.append(st.queue.popleft())
+            u.group = group if len(group) > 1 else None
+            for x in group:
+                x.batch = len(self.batches)
+                ups.append(x)
             items.append((st.plan, u))
-            ups.append(u)
+            counts.append(len(group))
             st.inflight += 1
         t_launch = self.now()
         for u in ups:
             u.t_launch = t_launch
         ev0 = self.engine.event()               # the batch's device span: ev0 .. ev
         self.engine.launch(items)
-        for st in chosen:
-            st.n_done += 1
+        for st, cnt in zip(chosen, counts):
+            st.n_done += cnt                    # a group never crosses an assembly point
             if self.assemble_every and st.n_done % self.assemble_every == 0:
                 st.cores = self.engine.assemble_async(st.plan)
         ev = self.engine.event()

@@ -179,3 +179,59 @@ def test_order5_tensor_matches_dense_ttn():
     ref = ref * np.sqrt(ref.size) / np.linalg.norm(ref)
     assert flat.shape == ref.shape
     assert np.allclose(flat, ref, rtol=1e-12, atol=1e-12)
+
+
+def _group_sizes(eng):
+    out = []
+    for b in eng.launches:
+        for _, u in b:
+            out.append(len(u.group) if u.group else 1)
+    return out
+
+
+def _flat_order(eng):
+    out = []
+    for b in eng.launches:
+        for _, u in b:
+            out += [x.offset for x in (u.group or [u])]
+    return out
+
+
+def test_rank1_updates_grouped_in_order():
+    """Consecutive queued rank-1 updates of a stream go out as one group (at most
+    rank1_batch, boxes never grouped), in submission order."""
+    eng = FakeEngine({0: 1})
+    srv = S.Server(budget_bytes=10, engine=eng, rank1_batch=4)
+    srv.open_stream(0, spec(0))
+    kinds = ["box", "rank1", "rank1", "rank1", "box"] + ["rank1"] * 10
+    arr = [S.Update(0, kind=k, arrival=0.0) for k in kinds]
+    for i, u in enumerate(arr):
+        u.offset = i
+    srv.run(arr)
+    assert _group_sizes(eng) == [1, 3, 1, 4, 4, 2]
+    assert _flat_order(eng) == list(range(len(kinds)))
+    assert len(srv.completed) == len(kinds)
+
+
+def test_rank1_groups_stop_at_assembly_points():
+    """A group never crosses a point where the cores are assembled, so the cores after
+    k updates hold exactly the first k."""
+    eng = FakeEngine({0: 1})
+    srv = S.Server(budget_bytes=10, engine=eng, rank1_batch=4, assemble_every=5)
+    srv.open_stream(0, spec(0))
+    kinds = ["box", "rank1", "rank1", "rank1", "box"] + ["rank1"] * 10
+    arr = [S.Update(0, kind=k, arrival=0.0) for k in kinds]
+    for i, u in enumerate(arr):
+        u.offset = i
+    srv.run(arr)
+    assert _group_sizes(eng) == [1, 3, 1, 4, 1, 4, 1]
+    assert eng.assembled == [0, 0, 0, 0]               # after 5, 10, 15, and at close
+    assert _flat_order(eng) == list(range(len(kinds)))
+
+
+def test_rank1_batch_one_launches_singly():
+    eng = FakeEngine({0: 1})
+    srv = S.Server(budget_bytes=10, engine=eng, rank1_batch=1)
+    srv.open_stream(0, spec(0))
+    srv.run([S.Update(0, kind="rank1", arrival=0.0) for _ in range(5)])
+    assert _group_sizes(eng) == [1] * 5
