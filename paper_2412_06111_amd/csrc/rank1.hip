@@ -13,7 +13,7 @@ namespace ttnn {
 namespace {
 
 constexpr int kThreadsR = 256;
-constexpr int kFacCache = 1024;   // factor entries kept in LDS by the GEMV (8 KB)
+constexpr int kFacCache = 2048;   // factor entries of a term group kept in LDS by the GEMV (16 KB)
 
 __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   double w = 1.0;
@@ -26,77 +26,89 @@ __device__ inline double kron_weight(const KronVec& kv, int64_t row) {
   return w;
 }
 
-// partial[b][j] = sum over the rows of block b of D[row * ncols + j] * weight(row).  The
-// block's rows are contiguous in D: each step copies RB of them into LDS with 16-byte
-// loads (consecutive threads, consecutive vectors; rows padded by one element against
-// bank conflicts), then one lane per row forms the row's weight and accumulates its
-// ncols products in FP64 (NC >= ncols accumulators a lane); a fixed-order reduction
-// over the lanes (shuffles, then the waves in order) ends the block.  A lane's row
-// advances by RB a step, so its mixed-radix digits (one per factor) advance by the
-// digits of RB with one carry test each instead of a division per factor and row.
-// rows_per_block is a multiple of RB, so every step but the block's last is whole.
-// Blocks: the chunks of rows, padded to a multiple of 8, times the terms; block b takes
-// chunk x and term y with the terms of one chunk 8 blocks apart (the same XCD, dispatched
-// together), x = 8 (b / 8m) + b % 8, y = (b % 8m) / 8.  Term y writes partial[y nb + x].
-template <typename TD, int NC, typename DI>
+// partial[(y nb + b) ncols + j] = sum over the rows of block b of D[row * ncols + j] *
+// weight_y(row), for the terms y of the batch.  The block's rows are contiguous in D:
+// each step copies RB of them into LDS with 16-byte loads (rows padded by one element
+// against bank conflicts); two lanes take a row, each half of its columns (NCH), two rows
+// RH apart a step, and accumulate the products with the weights of up to MT terms in
+// FP64, so one staged row serves every term of the block's group; a fixed-order reduction (shuffles over the
+// lanes of a half, then the waves in order) ends the block.  A term's sums depend only
+// on its own weights and on the row partition, which the batch does not change, so its
+// result is bitwise the same in any batch.  A lane's row advances by RH at a time, so
+// its mixed-radix digits (one per factor) advance by the digits of RH with one carry
+// test each.  Blocks: the chunks of rows, padded to a multiple of 8, times the groups of MT
+// terms, the groups of one chunk 8 blocks apart (the same XCD, dispatched together):
+// block b takes chunk x = 8 (b / 8G) + b % 8 and group (b % 8G) / 8.  rows_per_block is
+// a multiple of RB, so every step but the block's last is whole.
+template <typename TD, int NCH, int MT, typename DI>
 __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restrict__ D, int64_t rows, int ncols,
                                                               KronBatch kb, int64_t rows_per_block, int64_t nb,
                                                               double* __restrict__ partial) {
-  const int64_t bx = blockIdx.x, g8 = 8 * static_cast<int64_t>(kb.m);
-  const int64_t chunk = 8 * (bx / g8) + bx % 8;
-  const int term = static_cast<int>((bx % g8) / 8);
-  if (chunk >= nb) return;                 // padding chunks (whole block, before any barrier)
-  const KronVec& kv = kb.kv[term];
-  partial += static_cast<int64_t>(term) * nb * ncols;
-  constexpr int RB = sizeof(TD) == 8 ? kThreadsR / 2 : kThreadsR;     // rows a step (LDS <= 66 KB)
+  constexpr int NC = 2 * NCH;
+  constexpr int RH = kThreadsR / 2;                                   // rows at once: two lanes a row
+  constexpr int RB = 2 * RH;                                          // rows a step: two rows a lane pair
   constexpr int V = 16 / static_cast<int>(sizeof(TD));                // elements a 16-byte load
   constexpr int PER = (NC * RB + kThreadsR * V - 1) / (kThreadsR * V);  // loads a thread a step
   typedef TD vec_t __attribute__((ext_vector_type(V)));
-  __shared__ TD tile[RB * (NC + 1)];
-  __shared__ double red[kThreadsR / 64][NC];
+  __shared__ __align__(16) TD tile[RB * (NC + 1)];
+  __shared__ double red[kThreadsR / 64][MT][NC];
   __shared__ double fac[kFacCache];
+  const int G = (kb.m + MT - 1) / MT;
+  const int64_t bx = blockIdx.x, g8 = 8 * static_cast<int64_t>(G);
+  const int64_t chunk = 8 * (bx / g8) + bx % 8;
+  const int t0 = MT * static_cast<int>((bx % g8) / 8);                 // first term of the group
+  if (chunk >= nb) return;                 // padding chunks (whole block, before any barrier)
+  const int mg = kb.m - t0 < MT ? kb.m - t0 : MT;                     // terms of the group
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // the factors in LDS when they fit (the usual case: a few hundred entries), so that the
-  // weights never wait on global memory: a wait for a global gather issued after the
-  // next step's loads would also wait for those loads (the counter is in order)
-  int foff[kMaxPos];
-  bool cached;
-  {
-    int64_t tot = 0;
-    for (int p = 0; p < kv.n; ++p) {
-      foff[p] = static_cast<int>(tot < kFacCache ? tot : 0);
-      tot += kv.len[p];
-    }
-    cached = tot <= kFacCache;
-    if (cached)
-      for (int p = 0; p < kv.n; ++p)
-        for (int64_t i = tid; i < kv.len[p]; i += kThreadsR) fac[foff[p] + i] = kv.v[p][i];
-    __syncthreads();
-  }
+  const int row = tid >> 1, half = tid & 1;
   const int64_t r0 = chunk * rows_per_block;
   const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
   const int ld = ncols + 1;
+  const KronVec& k0 = kb.kv[0];            // every term has the same factor lengths
+  const int np = k0.n;
+  // the group's factors in LDS when they fit (the usual case: a few hundred entries a
+  // term), so that the weights never wait on global memory: a wait for a global gather
+  // issued after the next step's loads would also wait for those loads (the counter is
+  // in order).  Every loop over the factor positions runs to the compile-time maximum
+  // with a guard, so that these small arrays stay in registers.
+  int foff[kMaxPos];
+  int64_t flen = 0;
+#pragma unroll
+  for (int p = 0; p < kMaxPos; ++p) {
+    foff[p] = static_cast<int>(flen < kFacCache ? flen : 0);
+    if (p < np) flen += k0.len[p];
+  }
+  const bool cached = flen * mg <= kFacCache;
+  if (cached)
+    for (int y = 0; y < mg; ++y)
+#pragma unroll
+      for (int p = 0; p < kMaxPos; ++p)
+        if (p < np)
+          for (int64_t i = tid; i < k0.len[p]; i += kThreadsR) fac[y * flen + foff[p] + i] = kb.kv[t0 + y].v[p][i];
   // (row, column) of this thread's first element of each load, and the stride between
   // its loads (kThreadsR * V elements)
   const int x0 = tid * V;
   const int row0 = x0 / ncols, col0 = x0 - row0 * ncols;
   const int dr = (kThreadsR * V) / ncols, dc = (kThreadsR * V) % ncols;
-  // digits of this lane's first row and of the step (DI: 32-bit when every factor is
-  // shorter than 2^30, so that a digit plus a step digit plus a carry cannot overflow)
-  DI dig[kMaxPos], stp[kMaxPos];
+  // digits of this lane's first row and of RH (a lane pair takes rows RH apart)
+  DI dig[kMaxPos], stp[kMaxPos], len[kMaxPos];
   {
-    int64_t a = r0 + tid, b = RB;
-    for (int p = 0; p < kv.n; ++p) {
-      const int64_t e = kv.len[p];
+    int64_t a = r0 + row, b = RH;
+#pragma unroll
+    for (int p = 0; p < kMaxPos; ++p) {
+      const int64_t e = p < np ? k0.len[p] : 1;
+      len[p] = static_cast<DI>(e);
       dig[p] = static_cast<DI>(a % e);
       a /= e;
       stp[p] = static_cast<DI>(b % e);
       b /= e;
     }
   }
-  double acc[NC];
+  double acc[MT][NCH];
 #pragma unroll
-  for (int j = 0; j < NC; ++j) acc[j] = 0.0;
+  for (int y = 0; y < MT; ++y)
+#pragma unroll
+    for (int j = 0; j < NCH; ++j) acc[y][j] = 0.0;
   vec_t v[PER];
   auto fetch = [&](int64_t b) {            // the step's loads, all in flight together
     const int64_t nr = r1 - b < RB ? r1 - b : RB;
@@ -124,6 +136,7 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
       }
     }
   };
+  __syncthreads();                              // the factor cache is written
   if (r0 < r1) fetch(r0);
   for (int64_t base = r0; base < r1; base += RB) {
     const int nr = static_cast<int>(r1 - base < RB ? r1 - base : RB);
@@ -150,64 +163,106 @@ __global__ __launch_bounds__(kThreadsR) void kron_gemv_kernel(const TD* __restri
     }
     __syncthreads();
     if (base + RB < r1) fetch(base + RB);  // next step's loads overlap this step's products
-    if (tid < nr) {
-      double w = 1.0;
-      if (cached)
-        for (int p = 0; p < kv.n; ++p) w *= fac[foff[p] + dig[p]];
-      else
-        for (int p = 0; p < kv.n; ++p) w *= kv.v[p][dig[p]];
-      const TD* q = tile + tid * ld;
 #pragma unroll
-      for (int j = 0; j < NC; ++j)
-        if (j < ncols) acc[j] += to_f64(q[j]) * w;
+    for (int h = 0; h < 2; ++h) {
+    const int rl = row + h * RH;               // this pair's row within the step
+    if (rl < nr) {
+      double w[MT];
+#pragma unroll
+      for (int y = 0; y < MT; ++y) {
+        w[y] = 1.0;
+        if (y < mg) {
+          if (cached) {
+            const int fb = y * static_cast<int>(flen);
+#pragma unroll
+            for (int p = 0; p < kMaxPos; ++p)
+              if (p < np) w[y] *= fac[fb + foff[p] + static_cast<int>(dig[p])];
+          } else {
+#pragma unroll
+            for (int p = 0; p < kMaxPos; ++p)
+              if (p < np) w[y] *= kb.kv[t0 + y].v[p][dig[p]];
+          }
+        }
+      }
+      const TD* q = tile + rl * ld + half * NCH;
+#pragma unroll
+      for (int j = 0; j < NCH; ++j)
+        if (half * NCH + j < ncols) {
+          const double x = to_f64(q[j]);
+#pragma unroll
+          for (int y = 0; y < MT; ++y)
+            if (y < mg) acc[y][j] += x * w[y];
+        }
     }
-    DI carry = 0;                            // row += RB in mixed radix
-    for (int p = 0; p < kv.n; ++p) {
+    DI carry = 0;                            // row += RH in mixed radix
+#pragma unroll
+    for (int p = 0; p < kMaxPos; ++p) {
       const DI x = dig[p] + stp[p] + carry;
-      const DI e = static_cast<DI>(kv.len[p]);
-      carry = x >= e;
-      dig[p] = carry ? x - e : x;
+      carry = x >= len[p];
+      dig[p] = carry ? x - len[p] : x;
+    }
     }
     __syncthreads();
   }
+  // the lanes of one half hold the same columns: add them (lane bits 1..5), then the
+  // waves in order
 #pragma unroll
-  for (int j = 0; j < NC; ++j) {
-    double x = acc[j];
+  for (int y = 0; y < MT; ++y)
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
-    if (lane == 0) red[wave][j] = x;
-  }
+    for (int j = 0; j < NCH; ++j) {
+      double x = acc[y][j];
+#pragma unroll
+      for (int o = 2; o < 64; o <<= 1) x += __shfl_xor(x, o);
+      if (lane < 2) red[wave][y][lane * NCH + j] = x;
+    }
   __syncthreads();
-  if (tid < ncols) {
-    double s = red[0][tid];
+  for (int e = tid; e < mg * ncols; e += kThreadsR) {
+    const int y = e / ncols, j = e - y * ncols;
+    double sum = red[0][y][j];
 #pragma unroll
-    for (int q = 1; q < kThreadsR / 64; ++q) s += red[q][tid];
-    partial[chunk * ncols + tid] = s;
+    for (int q = 1; q < kThreadsR / 64; ++q) sum += red[q][y][j];
+    partial[(static_cast<int64_t>(t0 + y) * nb + chunk) * ncols + j] = sum;
   }
+}
+
+template <typename TD, int NCH, typename DI>
+void launch_gemv_nch(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb,
+                     double* partial, hipStream_t st) {
+  // term slots a block: one for a single term (the fewest registers), else two, or four
+  // where the accumulators fit (up to 24 columns).  A term's arithmetic is the same in
+  // every instance: its slot only repeats the same operations for it.
+  const int mt = kb.m == 1 ? 1 : (kb.m == 2 || NCH > 12) ? 2 : 4;
+  const dim3 grid(static_cast<unsigned>((nb + 7) / 8 * 8 * ((kb.m + mt - 1) / mt)));
+  if (mt == 1)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, NCH, 1, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kb, per, nb,
+                       partial);
+  else if (mt == 2)
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, NCH, 2, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kb, per, nb,
+                       partial);
+  else
+    hipLaunchKernelGGL((kron_gemv_kernel<TD, NCH, (NCH > 12 ? 2 : 4), DI>), grid, dim3(kThreadsR), 0, st, D, rows,
+                       ncols, kb, per, nb, partial);
 }
 
 template <typename TD, typename DI>
-void launch_gemv_di(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb, dim3 grid,
+void launch_gemv_di(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb,
                     double* partial, hipStream_t st) {
-#define TTNN_GEMV(NCV) \
-  hipLaunchKernelGGL((kron_gemv_kernel<TD, NCV, DI>), grid, dim3(kThreadsR), 0, st, D, rows, ncols, kb, per, nb, partial)
-  if (ncols <= 8) TTNN_GEMV(8);
-  else if (ncols <= 16) TTNN_GEMV(16);
-  else if (ncols <= 24) TTNN_GEMV(24);
-  else if (ncols <= 32) TTNN_GEMV(32);
-  else if (ncols <= 48) TTNN_GEMV(48);
-  else TTNN_GEMV(64);
-#undef TTNN_GEMV
+  if (ncols <= 8) launch_gemv_nch<TD, 4, DI>(D, rows, ncols, kb, per, nb, partial, st);
+  else if (ncols <= 16) launch_gemv_nch<TD, 8, DI>(D, rows, ncols, kb, per, nb, partial, st);
+  else if (ncols <= 24) launch_gemv_nch<TD, 12, DI>(D, rows, ncols, kb, per, nb, partial, st);
+  else if (ncols <= 32) launch_gemv_nch<TD, 16, DI>(D, rows, ncols, kb, per, nb, partial, st);
+  else if (ncols <= 48) launch_gemv_nch<TD, 24, DI>(D, rows, ncols, kb, per, nb, partial, st);
+  else launch_gemv_nch<TD, 32, DI>(D, rows, ncols, kb, per, nb, partial, st);
 }
 
 template <typename TD>
-void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb, dim3 grid,
+void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, int64_t per, int64_t nb,
                     double* partial, hipStream_t st) {
   bool short_factors = true;
   for (int y = 0; y < kb.m; ++y)
     for (int p = 0; p < kb.kv[y].n; ++p) short_factors = short_factors && kb.kv[y].len[p] < (int64_t(1) << 30);
-  if (short_factors) launch_gemv_di<TD, int>(D, rows, ncols, kb, per, nb, grid, partial, st);
-  else launch_gemv_di<TD, int64_t>(D, rows, ncols, kb, per, nb, grid, partial, st);
+  if (short_factors) launch_gemv_di<TD, int>(D, rows, ncols, kb, per, nb, partial, st);
+  else launch_gemv_di<TD, int64_t>(D, rows, ncols, kb, per, nb, partial, st);
 }
 
 // w[y wstride + j] = sum_b partial[y nb + b][j]: one wave per (column, term), lane l
@@ -255,20 +310,18 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
   const int64_t cap = static_cast<int64_t>(partial_elems / (static_cast<size_t>(ncols) * kRank1Batch));
   if (nb > cap) nb = cap;
   TTNN_REQUIRE(nb >= 1, TTNN_E_INVALID, "rank-1 scratch too small");
-  // rows a block: a multiple of the kernel's step (128 rows for FP64 maps, else 256)
-  const int64_t rb = dt == TTNN_F64 ? kThreadsR / 2 : kThreadsR;
+  // rows a block: a multiple of the kernel's step (256 rows)
+  const int64_t rb = kThreadsR;
   int64_t per = (rows + nb - 1) / nb;
   per = (per + rb - 1) / rb * rb;
   if (per < rb) per = rb;
   nb = rows > 0 ? (rows + per - 1) / per : 1;
-  const int64_t padded = (nb + 7) / 8 * 8;             // chunks padded to the XCD count
-  const dim3 grid(static_cast<unsigned>(padded * kb.m));
   if (dt == TTNN_F64)
-    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kb, per, nb, grid, partial, st);
+    launch_gemv_dt(static_cast<const double*>(D), rows, ncols, kb, per, nb, partial, st);
   else if (dt == TTNN_F32)
-    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kb, per, nb, grid, partial, st);
+    launch_gemv_dt(static_cast<const float*>(D), rows, ncols, kb, per, nb, partial, st);
   else
-    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kb, per, nb, grid, partial, st);
+    launch_gemv_dt(static_cast<const uint16_t*>(D), rows, ncols, kb, per, nb, partial, st);
   hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols, kb.m), dim3(64), 0, st, partial, static_cast<int>(nb), ncols, w,
                      wstride);
 }
