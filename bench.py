@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--order-only", action="store_true",
                     help="only the STTNN visiting-order runs (lexicographic against searched)")
     ap.add_argument("--order-cases", default="t4,hilbert", help="visiting-order workloads run (t4, hilbert)")
+    ap.add_argument("--rank1-only", action="store_true",
+                    help="only the rank-1 groups on the streaming configuration's plan")
     ap.add_argument("--order-visits", default="lexicographic,searched", help="visiting orders run")
     ap.add_argument("--rounding-only", action="store_true",
                     help="run only the TTN rounding runs and print them as one JSON line")
@@ -475,6 +477,48 @@ def order_bench(args):
         out[name] = rec
         del X, X64
         torch.cuda.empty_cache()
+    return out
+
+
+def rank1_bench(args):
+    """Rank-1 updates on the streaming configuration's plan: 64^5 on (((1,2),3),(4,5)),
+    TTNN, r = 24, p = 12, FP32 maps, in groups of 1, 2, 4 and 8 terms
+    (ttnn_sketch_update_rank1_batched, bitwise equal to the terms one by one).  Per group
+    size: ms a group and a term (stream events), and the maps' bytes a term over its
+    time (every row of every X_t is read once per group)."""
+    import numpy as np
+    import torch
+    import paper_2412_06111_amd as P
+    from workloads.serving import T5
+
+    n = args.single_n
+    dims = (n,) * 5
+    plan = P.Plan(T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=1)
+    map_bytes = 0
+    for i in range(1, plan.num_nodes):
+        rows, cols = plan.drm_shape(i, 0)
+        map_bytes += rows * cols * 4
+    g = np.random.default_rng(5)
+    terms = [[torch.from_numpy(g.standard_normal(k)).cuda() for k in dims] for _ in range(8)]
+    stream = torch.cuda.current_stream()
+    out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTNN, r=24, p=12, FP32 maps", "map_bytes": map_bytes}
+    for m in (1, 2, 4, 8):
+        for _ in range(2):
+            plan.update_rank1_batched(terms[:m], [1.0] * m)
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 2)
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        for _ in range(reps):
+            plan.update_rank1_batched(terms[:m], [1.0] * m)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1) / reps
+        out[f"group{m}"] = {"ms_per_group": ms, "ms_per_term": ms / m,
+                            "map_GBps_per_group": map_bytes / (ms * 1e-3) / 1e9}
+        print(f"# rank-1 group of {m}: {ms:.3f} ms, {ms / m:.3f} ms a term, maps {map_bytes / (ms * 1e-3) / 1e9:.0f} GB/s",
+              file=sys.stderr, flush=True)
+    plan.close()
     return out
 
 
@@ -955,6 +999,9 @@ def main():
         return
     if args.order_only:
         print(json.dumps(order_bench(args)))
+        return
+    if args.rank1_only:
+        print(json.dumps(rank1_bench(args)))
         return
 
     import numpy as np
