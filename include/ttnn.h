@@ -229,8 +229,10 @@ ttnn_status ttnn_footprint_estimate(const ttnn_problem* problem, size_t* bytes);
  * (extent[0] fastest), else the element stride of each mode (>= 1 on modes of extent
  * > 1), so that box entry (i_1, .., i_d) is d_block[sum_mu i_mu strides[mu]]: a slice
  * of a larger resident array is read in place (e.g. strides = the array's packed
- * strides).  A strided block takes the generic contraction kernels; packed whole
- * tensors take the one-pass kernels.  The whole tensor is offset = 0, extent = dims.
+ * strides).  A strided block takes the generic contraction kernels (one of at least
+ * 2^22 entries is first copied, in stream order, into a packed block from the library's
+ * pool, which gives the same bits faster); packed whole tensors take the one-pass
+ * kernels.  The whole tensor is offset = 0, extent = dims.
  * Empty boxes are a no-op. */
 ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int64_t* offset,
                                const int64_t* extent, const int64_t* strides, double alpha, void* stream);

@@ -82,6 +82,31 @@ const int64_t* block_strides(const Plan& P, const int64_t* ext, const int64_t* s
   return packed ? nullptr : strides;
 }
 
+// A large strided block packed into a stream-ordered pool block (returned to the pool in
+// stream order when the holder goes, after the update that reads it is enqueued).
+struct Packed {
+  void* p = nullptr;
+  hipStream_t s = nullptr;
+  Packed() = default;
+  Packed(const Packed&) = delete;
+  Packed(Packed&& o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+  ~Packed() {
+    if (p) ttnn::pool_free(p, s);
+  }
+};
+
+bool pack_large(const Plan& P, const void* block, const int64_t* ext, const int64_t* strides, hipStream_t st,
+                Packed& out) {
+  if (!strides) return false;
+  int64_t entries = 1;
+  for (int mu = 0; mu < P.d; ++mu) entries *= ext[mu];
+  if (entries < ttnn::kPackMinEntries) return false;
+  out.s = st;
+  out.p = ttnn::pool_alloc(static_cast<size_t>(entries) * ttnn::dtype_size(P.dtype), st);
+  ttnn::launch_pack_box(block, P.dtype, P.d, ext, strides, out.p, st);
+  return true;
+}
+
 void dense_updates(const Plan& P) {
   if (P.variant == TTNN_KR)
     throw Error{TTNN_E_STATE, "a Khatri-Rao plan takes TTN-format updates only (ttnn_sketch_update_ttn)"};
@@ -198,7 +223,11 @@ ttnn_status ttnn_sketch_update(ttnn_plan_t plan, const void* d_block, const int6
     if (empty) return TTNN_OK;
     if (!d_block) throw Error{TTNN_E_INVALID, "block is NULL"};
     const int64_t* st = block_strides(*P, extent, strides);
-    ttnn::update_box(*P, d_block, offset, extent, st, alpha, as_stream(stream));
+    Packed pk;
+    if (pack_large(*P, d_block, extent, st, as_stream(stream), pk))
+      ttnn::update_box(*P, pk.p, offset, extent, nullptr, alpha, as_stream(stream));
+    else
+      ttnn::update_box(*P, d_block, offset, extent, st, alpha, as_stream(stream));
     TTNN_HIP(hipGetLastError());
     return TTNN_OK;
   });
@@ -270,14 +299,27 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
           round.push_back(i);
         }
         std::map<std::string, std::vector<int32_t>> buckets;
-        auto strides_of = [&](int32_t i) {
+        // large strided blocks are packed first (held until the round is enqueued)
+        std::map<int32_t, Packed> packed;
+        for (int32_t i : round) {
           const ttnn_update_desc& u = descs[i];
+          const int64_t* s = u.strides[0] != 0 ? block_strides(*get(u.plan), u.extent, u.strides) : nullptr;
+          Packed pk;
+          if (pack_large(*get(u.plan), u.d_block, u.extent, s, st, pk)) packed.emplace(i, std::move(pk));
+        }
+        auto block_of = [&](int32_t i) -> const void* {
+          auto it = packed.find(i);
+          return it != packed.end() ? it->second.p : descs[i].d_block;
+        };
+        auto strides_of = [&](int32_t i) -> const int64_t* {
+          const ttnn_update_desc& u = descs[i];
+          if (packed.count(i)) return nullptr;
           return u.strides[0] != 0 ? block_strides(*get(u.plan), u.extent, u.strides) : nullptr;
         };
         for (int32_t i : round) {
           Plan* P = get(descs[i].plan);
           if (ttnn::whole_tensor(*P, descs[i].offset, descs[i].extent) && !strides_of(i))
-            ttnn::update_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, nullptr, descs[i].alpha, st);
+            ttnn::update_box(*P, block_of(i), descs[i].offset, descs[i].extent, nullptr, descs[i].alpha, st);
           else
             buckets[ttnn::batch_key(*P)].push_back(i);
         }
@@ -289,7 +331,7 @@ ttnn_status ttnn_sketch_update_batched(int32_t n, const ttnn_update_desc* descs,
             const int32_t i = kv.second[b];
             Plan* P = get(descs[i].plan);
             P->epilogue_valid = false;
-            ttnn::record_box(*P, descs[i].d_block, descs[i].offset, descs[i].extent, strides_of(i), descs[i].alpha,
+            ttnn::record_box(*P, block_of(i), descs[i].offset, descs[i].extent, strides_of(i), descs[i].alpha,
                              recs[b]);
             items.push_back(&recs[b]);
             plans.push_back(P);

@@ -183,6 +183,17 @@ struct KronVec {
     ++n;
   }
 };
+// Copy of a strided box (element strides per mode) into dst, packed column-major over
+// ext (first mode fastest); dtype dt, d modes.
+struct PackDims {
+  int64_t ext[TTNN_MAX_ORDER] = {};
+  int64_t stride[TTNN_MAX_ORDER] = {};
+};
+void launch_pack_box(const void* src, int dt, int d, const int64_t* ext, const int64_t* strides, void* dst,
+                     hipStream_t stream);
+// Strided boxes of at least this many entries are packed before their update.
+constexpr int64_t kPackMinEntries = int64_t(1) << 22;
+
 // Up to kRank1Batch rank-1 terms handled by one launch (their vectors and scales).
 constexpr int kRank1Batch = 8;
 struct KronBatch {
