@@ -167,11 +167,12 @@ def _sampled(P, plan, host, tree, seed, tol, g, per_node=3):
 
 
 def test_order_large_unbalanced(P):
-    """((1,2),(3,4)) with n_1 = 32 << n_2 = 512, FP32, 67M entries, in the searched
-    order (mode 2 before mode 1: the lexicographic X_1 would hold as many entries as
-    the tensor): the MFMA right sketches, the chain from the raw tensor at a middle
-    mode and the batched FP64 jobs, sampled against the one-entry oracle."""
-    dims, r, p, seed = (32, 512, 64, 64), 32, 16, 7
+    """((1,2),(3,4)) with n_1 = 32 << n_2 = 512, FP32, 268M entries (the benchmark's
+    visiting-order workload, in its launch configuration), in the searched order (mode 2
+    before mode 1: the lexicographic X_1 would hold as many entries as the tensor): the
+    MFMA right sketches, the streaming mode product at mode 2 and the batched FP64 jobs,
+    sampled against the one-entry oracle."""
+    dims, r, p, seed = (32, 512, 128, 128), 32, 16, 7
     visit, _ = P.order_search(T4, dims, r, p)
     assert visit == ((2, 1), (3, 4))
     print("order large t4 f32", flush=True)
@@ -189,9 +190,9 @@ def test_order_large_unbalanced(P):
 
 def test_order_hilbert_full_size(P):
     """The 6-D Hilbert tensor (n = 20, 64M entries) on the tree of Fig. 1 in its searched
-    order: sampled sketch entries against the one-entry oracle, and the accuracy of the
-    rank-6 approximation against that of the lexicographic order."""
-    n, r, seed = H.N_PAPER, 6, 5
+    order at r = 13 (the benchmark's configuration): sampled sketch entries against the
+    one-entry oracle, and the accuracy of the approximation in both orders."""
+    n, r, seed = H.N_PAPER, 13, 5
     dims = (n,) * 6
     visit, _ = P.order_search(H.TOY, dims, r, H.P_PAPER)
     assert visit != H.TOY
@@ -209,5 +210,5 @@ def test_order_hilbert_full_size(P):
             bad, worst = _sampled(P, plan, host, tree, seed, TOL["f64"], np.random.default_rng(26), per_node=2)
             assert not bad, (bad, worst)
         plan.close()
-    # both orders give an accurate approximation of the smooth tensor at this rank
-    assert errs[visit] < 1e-4 and errs[None] < 1e-4, errs
+    # at r = 13 both orders reach the tensor's FP64 floor (the oracle gives ~1e-12)
+    assert errs[visit] < 1e-10 and errs[None] < 1e-10, errs
