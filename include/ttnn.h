@@ -315,8 +315,10 @@ ttnn_status ttnn_core_shape(ttnn_plan_t plan, int32_t node, int32_t* ndim, int64
  *   root B_0 = (kron Q_c^T) Psi_0.
  * All in FP64 on the GPU.  d_cores: host array of num_nodes device pointers (caller
  * node ids), each with room for prod(core shape) doubles.  Returns TTNN_E_NUMERIC
- * (after writing the cores) if a sketch was not finite; the flag is read back
- * synchronously, so this call synchronises `stream`. */
+ * (after writing the cores) if a sketch was not finite or a node's Omega has numerical
+ * rank 0 (its pseudo-inverse, and so its contribution, is zero: the zero tensor gives
+ * finite cores that reconstruct it exactly); the flag is read back synchronously, so
+ * this call synchronises `stream`. */
 ttnn_status ttnn_assemble(ttnn_plan_t plan, double* const* d_cores, void* stream);
 
 /* The same recovery phase, enqueued on `stream` without waiting: returns TTNN_OK
