@@ -112,7 +112,10 @@ typedef enum { TTNN_SK_R = 0, TTNN_SK_OMEGA = 1, TTNN_SK_PSI = 2 } ttnn_sketch_k
  * have no ids, DRMs, sketches or cores of their own (ttnn_reuse_set lists nodes only);
  * TTNN_KR plans and ttnn_ttn_dot take trees without them.
  * rank[i] = r_t >= 1 and oversample[i] = p_t >= 0 for non-root nodes (ignored at
- * the root).  eps_factor: the pseudo-inverse keeps singular values of R_t above
+ * the root), with r_t <= 64, r_t + p_t <= 256, and the recovery of the node within one
+ * workgroup's LDS, 2 (r_t + p_t, rounded up to odd) r_t doubles next to 4 KB of its
+ * own: every r_t + p_t <= 256 for r_t <= 38, p_t <= 159 at r_t = 48, p_t <= 91 at
+ * r_t = 64 (TTNN_E_INVALID otherwise).  eps_factor: the pseudo-inverse keeps singular values of R_t above
  * eps_factor * ||R_t||_2; 0 selects 10 * 2^-52, which suits FP64 sketches.  With FP32
  * sketches a threshold at the FP32 noise level (about 10 * 2^-23) drops the directions
  * that noise creates and gives markedly smaller errors at ranks where the tensor's

@@ -857,16 +857,13 @@ void enqueue_assemble(Plan& P, double* const* cores, hipStream_t st) {
   }
 
   QrJobList jl{};
-  int max_k = 1, max_r = 1;
   for (int v = 1; v < nn; ++v) {
     const Node& t = P.nodes[v];
     if (t.ident) continue;                      // Q = I, no pseudo-inverse
     jl.jobs[jl.n] = QrJob{t.Om, t.Q, t.Pinv, t.k, t.r, jl.n};
     ++jl.n;
-    max_k = std::max(max_k, t.k);
-    max_r = std::max(max_r, t.r);
   }
-  launch_qr_pinv(jl, max_k, max_r, P.eps_factor, P.d_flag + 1, st);
+  launch_qr_pinv(jl, P.eps_factor, P.d_flag + 1, st);
 
   // cores: leaves B = Psi Pinv; internal nodes and root contract Psi with Q_c^T child by
   // child, then (non-root) apply Pinv.

@@ -296,7 +296,13 @@ struct QrJobList {
 };
 // Jobs with 32 < r <= 64 and k <= 64, or k <= 96, run in kernels of their own (4 lanes
 // per column), the others in the kernel of the narrower register paths and the LDS path.
-void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t stream);
+// Each launch takes the dynamic LDS of its largest job (qr_pinv_lds_bytes).
+void launch_qr_pinv(const QrJobList& jl, double eps_factor, int* d_kept, hipStream_t stream);
+// Dynamic LDS of one job: Omega (then reflectors and R) and Q, (k | 1) x r doubles each.
+size_t qr_pinv_lds_bytes(int k, int r);
+// Whether a job with these k >= r fits the recovery kernel (one workgroup, its LDS);
+// plans check every node at creation.
+bool qr_pinv_fits(int k, int r);
 // Status of one assembly from its flags (flags[0] non-finite count, flags[1..nn-1] kept
 // singular values per node): *call = 1 if bad else 0, and *sticky |= *call.
 void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t stream);

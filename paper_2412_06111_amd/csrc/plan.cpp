@@ -220,6 +220,10 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
                    "ranks must be >= 1 and oversamples >= 0");
       TTNN_REQUIRE(pr->rank[c] <= 64 && pr->rank[c] + pr->oversample[c] <= 256, TTNN_E_INVALID,
                    "rank <= 64 and rank + oversample <= 256 are supported");
+      TTNN_REQUIRE(qr_pinv_fits(pr->rank[c] + pr->oversample[c], pr->rank[c]), TTNN_E_INVALID,
+                   "rank " + std::to_string(pr->rank[c]) + " with oversample " + std::to_string(pr->oversample[c]) +
+                       ": the recovery of a node holds 2 (r + p) r doubles in one workgroup's LDS "
+                       "(at r = 64, p <= 91)");
       nd.r = pr->rank[c];
       nd.p = pr->oversample[c];
       nd.k = nd.r + nd.p;

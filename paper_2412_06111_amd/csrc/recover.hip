@@ -10,6 +10,7 @@
 //   When ||R||_F ||R^{-1}||_F < 1/(2 eps_factor) no singular value can fall below
 //   eps, so R^{+eps} = R^{-1} is formed by back substitution and the SVD is skipped.
 // Also: deterministic squared-norm reductions used for error reporting.
+#include <algorithm>
 #include <mutex>
 
 #include "kernels.hpp"
@@ -268,12 +269,17 @@ __device__ bool qr_regs(const QrJob& job, double eps_factor, double* A, int ld, 
 // jobs with 32 < r <= 64 and k <= 64 or k <= 96 (4 lanes per column, WTM rows a lane).
 // Each form is an instance of its own so that its register demand does not lower the
 // occupancy of the others.
+constexpr int kQrMaxR = 128;   // columns of the per-column arrays below
+// static LDS of qr_pinv_kernel: red, tau_s, sig, vb (doubles) and two flags
+constexpr size_t kQrStaticLds = sizeof(double) * (4 + kQrMaxR + kQrMaxR + 2 * kQrMaxR) + 2 * sizeof(int);
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;
+
 template <int WTM>
 __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double eps_factor, int* kept) {
   extern __shared__ double lds[];
   __shared__ double red[4];
-  __shared__ double tau_s[128];
-  __shared__ double sig[128];
+  __shared__ double tau_s[kQrMaxR];
+  __shared__ double sig[kQrMaxR];
   __shared__ int any_rot;
   __shared__ int fast;
   const QrJob job = jl.jobs[blockIdx.x];
@@ -285,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void qr_pinv_kernel(QrJobList jl, double 
   double* W = Qm;                // r x r (after Q is stored): R, then the Jacobi columns
   double* V = A;                 // r x r (after R is extracted): R^{-1}, or right singular vectors
 
-  __shared__ double vb[2 * 128];
+  __shared__ double vb[2 * kQrMaxR];
   // register path: 8 lanes per column for r <= 32 (k <= 128), 4 for r <= 64 (k <= 64)
   const int tm = WTM ? WTM : r <= 32 ? (k <= 32 ? 4 : k <= 48 ? 6 : k <= 64 ? 8 : k <= 128 ? 16 : 0) : 0;
   if (tm != 0) {
@@ -523,17 +529,30 @@ __global__ void diff_norm_final(const double* part, int nb, double* out) {
 
 }  // namespace
 
-void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor, int* d_kept, hipStream_t st) {
+size_t qr_pinv_lds_bytes(int k, int r) { return static_cast<size_t>(2 * (k | 1)) * r * sizeof(double); }
+
+bool qr_pinv_fits(int k, int r) {
+  return k >= r && r >= 1 && r <= kQrMaxR && k <= 2 * kQrMaxR &&
+         qr_pinv_lds_bytes(k, r) + kQrStaticLds <= kLdsPerWorkgroup;
+}
+
+void launch_qr_pinv(const QrJobList& jl, double eps_factor, int* d_kept, hipStream_t st) {
   if (jl.n <= 0) return;
   QrJobList lists[3] = {};
+  size_t need[3] = {0, 0, 0};                 // dynamic LDS of each launch: its largest job
   for (int i = 0; i < jl.n; ++i) {
     const QrJob& j = jl.jobs[i];
+    if (!qr_pinv_fits(j.k, j.r))
+      throw Error{TTNN_E_INVALID, "recovery job k = " + std::to_string(j.k) + ", r = " + std::to_string(j.r) +
+                                      " exceeds one workgroup's LDS"};
     const int w = (j.r > 32 && j.r <= 64) ? (j.k <= 64 ? 1 : j.k <= 96 ? 2 : 0) : 0;
     lists[w].jobs[lists[w].n++] = j;
+    need[w] = std::max(need[w], qr_pinv_lds_bytes(j.k, j.r));
   }
-  const size_t lds = static_cast<size_t>(2 * (max_k | 1) * max_r) * sizeof(double);
-  auto launch = [&](const void* fn, const QrJobList& l, void (*k)(QrJobList, double, int*)) {
+  auto launch = [&](const void* fn, int w, void (*k)(QrJobList, double, int*)) {
+    const QrJobList& l = lists[w];
     if (l.n == 0) return;
+    const size_t lds = need[w];
     if (lds > 64 * 1024) {
       const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
       if (e != hipSuccess) {
@@ -543,9 +562,9 @@ void launch_qr_pinv(const QrJobList& jl, int max_k, int max_r, double eps_factor
     }
     hipLaunchKernelGGL(k, dim3(l.n), dim3(kThreads), lds, st, l, eps_factor, d_kept);
   };
-  launch(reinterpret_cast<const void*>(qr_pinv_kernel<0>), lists[0], qr_pinv_kernel<0>);
-  launch(reinterpret_cast<const void*>(qr_pinv_kernel<16>), lists[1], qr_pinv_kernel<16>);
-  launch(reinterpret_cast<const void*>(qr_pinv_kernel<24>), lists[2], qr_pinv_kernel<24>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<0>), 0, qr_pinv_kernel<0>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<16>), 1, qr_pinv_kernel<16>);
+  launch(reinterpret_cast<const void*>(qr_pinv_kernel<24>), 2, qr_pinv_kernel<24>);
 }
 
 void launch_status_fold(const int* flags, int nn, int* call, int* sticky, hipStream_t st) {

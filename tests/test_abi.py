@@ -87,6 +87,25 @@ def test_footprint_estimate_without_device():
     assert big > 4 * 64 ** 3 * 6 * 8
 
 
+@pytest.mark.parametrize("r,pmax", [(16, 240), (38, 218), (39, 216), (48, 159), (64, 91)])
+def test_recovery_lds_limit_without_device(r, pmax):
+    """A node's recovery holds 2 (r + p, rounded up to odd) r doubles in one workgroup's
+    160 KB of LDS next to 4,136 bytes of the kernel's own: the plan refuses ranks whose
+    recovery would not fit (host-side, at creation) instead of failing at assembly.
+    Each case is the largest p that fits, and p + 1 (where r + p + 1 <= 256)."""
+    import paper_2412_06111_amd as P
+    spec, dims = ((1, 2), (3, 4)), (8, 8, 8, 8)
+    assert P.footprint_estimate(spec, dims, r, pmax) > 0
+    if r + pmax + 1 <= 256:
+        with pytest.raises(P.TTNNError) as e:
+            P.footprint_estimate(spec, dims, r, pmax + 1)
+        assert e.value.status == -1 and "LDS" in str(e.value)
+    # per node: only the node past the limit is refused
+    over = {(1,): 240, (2,): pmax, (3,): 4, (4,): 4, (1, 2): 8, (3, 4): pmax}
+    rank = {(1,): 16, (2,): r, (3,): 64, (4,): 8, (1, 2): 32, (3, 4): r}
+    assert P.footprint_estimate(spec, dims, rank, over) > 0
+
+
 def test_footprint_estimate_rejects_bad_tree():
     import paper_2412_06111_amd as P
     with pytest.raises(P.TTNNError) as e:
