@@ -106,7 +106,11 @@ struct SttnnLayout {
   // the whole tile (one copy per tile instead of one per sub-tile), after both stages
   static constexpr size_t YRB = YR ? size_t(B2) * YB : 0;
   static constexpr bool STAGE_YA = !YR && 2 * (MS + YB) + Z1 <= BUDGET;
-  static constexpr bool STAGE_X = (STAGE_YA || YR) && 2 * (MS + (STAGE_YA ? YB : 0) + 2 * XB) + Z1 + YRB <= BUDGET;
+  // X_A / X_1 rows are staged where the Y_A rows are (staged or resident), and in FP64,
+  // whose Y_A rows never fit: there every wave would otherwise load the same X fragments
+  // from L2 inside its product loop
+  static constexpr bool STAGE_X = (STAGE_YA || YR || DT == TTNN_F64) &&
+                                  2 * (MS + (STAGE_YA ? YB : 0) + 2 * XB) + Z1 + YRB <= BUDGET;
   static constexpr size_t STAGE = MS + (STAGE_YA ? YB : 0) + (STAGE_X ? 2 * XB : 0);   // one stage
   static constexpr size_t Y1B = size_t(KP) * SY * ESZ;
   static constexpr bool STAGE_Y1 = !TT && 2 * STAGE + Z1 + YRB + Y1B <= BUDGET;
