@@ -905,13 +905,16 @@ int64_t elem_size(int dt) { return dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2; 
 }  // namespace
 
 // ---------------------------------------------------------------- side stream
-void fork_side(Plan& P, hipStream_t st) {
+void fork_side(Plan& P, hipStream_t st, hipEvent_t after) {
   if (!P.side) {
     TTNN_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
     for (hipEvent_t& e : P.side_ev) TTNN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
-  TTNN_HIP(hipEventRecord(P.side_ev[0], st));
-  TTNN_HIP(hipStreamWaitEvent(P.side, P.side_ev[0], 0));
+  if (!after) {
+    TTNN_HIP(hipEventRecord(P.side_ev[0], st));
+    after = P.side_ev[0];
+  }
+  TTNN_HIP(hipStreamWaitEvent(P.side, after, 0));
 }
 
 void join_side(Plan& P, hipStream_t st) {
@@ -1060,7 +1063,7 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
     // Every kernel of this stretch streams from HBM or waits on it, so the overlap gains
     // little at FP32 (the kernels slow each other down); at BF16, where Z1 is half the
     // size, it does.
-    fork_side(P, st);
+    fork_side(P, st, P.timing ? P.sweep_ev[1] : nullptr);   // the sweep's end event, when timed
     const int64_t K = static_cast<int64_t>(F.KP) * F.nB;
     const int zdt = P.dtype == TTNN_BF16 ? TTNN_F32 : P.dtype;      // Z1 and this X_2 copy
     const int nch = launch_right_mfma(F.Z1, zdt, K, F.n2, 1, F.X2, K, F.R, P.partial, P.partial_elems, P.side);

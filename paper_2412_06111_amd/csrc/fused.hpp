@@ -21,7 +21,9 @@ bool try_fused_update(Plan& P, const void* block, const int64_t* off, const int6
 // enqueued so far on `stream`; join_side makes `stream` wait for it (no-op when none
 // is pending).  A fused update leaves its side work pending; the update joins it
 // before returning and before any other launch that shares the partial scratch.
-void fork_side(Plan& P, hipStream_t stream);
+// `after`: an event just recorded on `stream` to fork from instead of recording one
+// (NULL: record the plan's own fork event).
+void fork_side(Plan& P, hipStream_t stream, hipEvent_t after = nullptr);
 void join_side(Plan& P, hipStream_t stream);
 
 }  // namespace ttnn
