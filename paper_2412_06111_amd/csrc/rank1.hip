@@ -271,8 +271,17 @@ __global__ __launch_bounds__(64) void sum_blocks_kernel(const double* __restrict
                                                         double* __restrict__ w, int64_t wstride) {
   const int j = blockIdx.x, y = blockIdx.y, l = threadIdx.x;
   const double* p = partial + static_cast<int64_t>(y) * nb * ncols;
+  // lane l adds blocks l, l + 64, .. in order, eight loads in flight at a time
   double s = 0.0;
-  for (int b = l; b < nb; b += 64) s += p[static_cast<int64_t>(b) * ncols + j];
+  int b = l;
+  for (; b + 7 * 64 < nb; b += 8 * 64) {
+    double v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[static_cast<int64_t>(b + 64 * i) * ncols + j];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) s += v[i];
+  }
+  for (; b < nb; b += 64) s += p[static_cast<int64_t>(b) * ncols + j];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if (l == 0) w[y * wstride + j] = s;
