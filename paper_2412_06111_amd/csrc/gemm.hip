@@ -151,15 +151,20 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
 }
 
 // One output tile (rows row0.., columns j0.., contraction chunk c) of a generic contraction.
+// As in the MFMA tile, the operand and DRM entries of step s + 1 are loaded into
+// registers (and the DRM rows of step s + 2 computed) while step s is multiplied out
+// of LDS; each accumulator takes its products in the same order as without the
+// prefetch.
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                           const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
                                           const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
                                           int64_t kchunk, TO* __restrict__ out, const OutLayout& ol, int64_t row0,
                                           int64_t c, int j0) {
+  constexpr int NA = BR * BK / 256, NB = BK * BJ / 256;
   __shared__ double As[BK][BR + 1];
   __shared__ double Bs[BK][BJ + 1];
-  __shared__ int64_t drow[BK];
+  __shared__ int64_t drow[2][BK];
 
   const int tid = threadIdx.x;
   const int64_t rows_total = RIGHT ? n : L * Q;
@@ -172,29 +177,25 @@ __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t
   const int tc = tid / 16;   // 2 columns each
   double acc[4][2] = {};
 
-  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
-    // DRM rows of this contraction step
-    if (tid < BK) {
-      const int64_t kk = kb + tid;
-      int64_t r = -1;
-      if (kk < k_end) {
-        if (RIGHT) r = amap(kk % L) + bmap(kk / L);
-        else r = amap(kk);
-      }
-      drow[tid] = r;
+  auto drm_row = [&](int64_t kk) -> int64_t {
+    if (kk >= k_end) return -1;
+    return RIGHT ? amap(kk % L) + bmap(kk / L) : amap(kk);
+  };
+  auto a_pos = [&](int e, int& kk, int& rr) {
+    if (kk_contig) {
+      kk = e % BK;
+      rr = e / BK;
+    } else {
+      rr = e % BR;
+      kk = e / BR;
     }
-    // operand tile As[kk][rr] = Hm(m, i)
+  };
+  double ra[NA], rb[NB];
+  auto fetch = [&](int64_t kb, int buf) {
 #pragma unroll
-    for (int s = 0; s < (BR * BK) / 256; ++s) {
-      const int e = tid + 256 * s;
+    for (int s = 0; s < NA; ++s) {
       int kk, rr;
-      if (kk_contig) {
-        kk = e % BK;
-        rr = e / BK;
-      } else {
-        rr = e % BR;
-        kk = e / BR;
-      }
+      a_pos(tid + 256 * s, kk, rr);
       const int64_t kg = kb + kk;
       const int64_t rg = row0 + rr;
       double v = 0.0;
@@ -205,21 +206,41 @@ __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t
         const int64_t q = m / L;
         v = ld(H, hm(l, i, q, L, n));
       }
-      As[kk][rr] = v;
+      ra[s] = v;
     }
-    __syncthreads();
-    // DRM tile Bs[kk][jj]
 #pragma unroll
-    for (int s = 0; s < (BK * BJ) / 256; ++s) {
+    for (int s = 0; s < NB; ++s) {
       const int e = tid + 256 * s;
       const int jj = e % BJ;
       const int kk = e / BJ;
-      const int64_t r = drow[kk];
-      double v = 0.0;
-      if (r >= 0 && j0 + jj < ncols) v = ld(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc);
-      Bs[kk][jj] = v;
+      const int64_t r = drow[buf][kk];
+      rb[s] = (r >= 0 && j0 + jj < ncols) ? ld(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc) : 0.0;
+    }
+  };
+
+  if (tid < BK) {
+    drow[0][tid] = drm_row(k_begin + tid);
+    drow[1][tid] = drm_row(k_begin + BK + tid);
+  }
+  __syncthreads();
+  if (k_begin < k_end) fetch(k_begin, 0);
+  int buf = 0;
+  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
+#pragma unroll
+    for (int s = 0; s < NA; ++s) {
+      int kk, rr;
+      a_pos(tid + 256 * s, kk, rr);
+      As[kk][rr] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int e = tid + 256 * s;
+      Bs[e / BJ][e % BJ] = rb[s];
     }
     __syncthreads();
+    // drow[buf] is free again (its step is staged): it takes the rows of step s + 2
+    if (kb + BK < k_end) fetch(kb + BK, buf ^ 1);
+    if (tid < BK) drow[buf][tid] = drm_row(kb + 2 * BK + tid);
 #pragma unroll
     for (int kk = 0; kk < BK; ++kk) {
       double a[4], b[2];
@@ -233,6 +254,7 @@ __device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t
         for (int v = 0; v < 2; ++v) acc[u][v] = __fma_rn(a[u], b[v], acc[u][v]);
     }
     __syncthreads();
+    buf ^= 1;
   }
 
 #pragma unroll
