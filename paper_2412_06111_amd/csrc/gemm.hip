@@ -30,12 +30,20 @@ template <typename T> __device__ inline double ld(const T* p, int64_t i) { retur
 __device__ inline float ldf(const float* p, int64_t i) { return p[i]; }
 __device__ inline float ldf(const uint16_t* p, int64_t i) { return bf16_bits_to_f32(p[i]); }
 
-// FP32 / BF16 operands: the tile's inner product runs on the FP32 MFMA (16x16x4,
-// FP32 accumulation within the chunk; the chunk partial is written in the output
-// type and chunks are summed in FP64 by the reduction).  Each of the 4 waves owns 16
-// rows and both 16-column blocks.  The VALU form below reads six LDS words per eight
-// FMAs and is bound by LDS bandwidth; an MFMA reads one word a lane per 1024 FMAs.
-template <bool RIGHT, typename TH, typename TD, typename TO>
+// The tile's inner product on the 16x16x4 MFMA of the compute type CT: FP32 for FP32 /
+// BF16 operands (FP32 accumulation within the chunk; the chunk partial is written in
+// the output type and chunks are summed in FP64 by the reduction), FP64 when either
+// operand is FP64.  Each of the 4 waves owns 16 rows and both 16-column blocks.  A VALU
+// form (four rows by two columns a thread) reads six LDS words per eight FMAs and is
+// bound by LDS bandwidth; an MFMA reads one word a lane per 1024 FMAs (FP32) or 512
+// (FP64), and the FP64 MFMA's peak equals the FP64 vector units'.
+template <typename CT> __device__ inline CT ldc(const float* p, int64_t i) { return static_cast<CT>(p[i]); }
+template <typename CT> __device__ inline CT ldc(const uint16_t* p, int64_t i) {
+  return static_cast<CT>(bf16_bits_to_f32(p[i]));
+}
+template <typename CT> __device__ inline CT ldc(const double* p, int64_t i) { return static_cast<CT>(p[i]); }
+
+template <bool RIGHT, typename TH, typename TD, typename TO, typename CT = float>
 __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                                const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
                                                const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
@@ -43,9 +51,10 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
                                                int64_t row0, int64_t c, int j0) {
   // operand and DRM entries of step s + 1 are loaded into registers (and the DRM rows
   // of step s + 2 computed) while step s is multiplied out of LDS
+  using P = Pol<std::is_same_v<CT, double> ? TTNN_F64 : TTNN_F32>;
   constexpr int NA = BR * BK / 256, NB = BK * BJ / 256;
-  __shared__ float As[BK][BR + 4];
-  __shared__ float Bs[BK][BJ + 4];
+  __shared__ CT As[BK][BR + 4];
+  __shared__ CT Bs[BK][BJ + 4];
   __shared__ int64_t drow[2][BK];
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
@@ -55,9 +64,9 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
   const int64_t k_begin = c * kchunk;
   const int64_t k_end = (k_begin + kchunk < K) ? k_begin + kchunk : K;
   const bool kk_contig = RIGHT ? (L > 1) : (L == 1);
-  f32x4_t acc[BJ / 16];
+  typename P::CFrag acc[BJ / 16];
 #pragma unroll
-  for (int cb = 0; cb < BJ / 16; ++cb) acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  for (int cb = 0; cb < BJ / 16; ++cb) acc[cb] = typename P::CFrag{};
 
   auto drm_row = [&](int64_t kk) -> int64_t {
     if (kk >= k_end) return -1;
@@ -72,7 +81,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
       kk = e / BR;
     }
   };
-  float ra[NA], rb[NB];
+  CT ra[NA], rb[NB];
   auto fetch = [&](int64_t kb, int buf) {
 #pragma unroll
     for (int s = 0; s < NA; ++s) {
@@ -80,13 +89,13 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
       a_pos(tid + 256 * s, kk, rr);
       const int64_t kg = kb + kk;
       const int64_t rg = row0 + rr;
-      float v = 0.f;
+      CT v = 0;
       if (kg < k_end && rg < rows_total) {
         const int64_t m = RIGHT ? kg : rg;
         const int64_t i = RIGHT ? rg : kg;
         const int64_t l = m % L;
         const int64_t q = m / L;
-        v = ldf(H, hm(l, i, q, L, n));
+        v = ldc<CT>(H, hm(l, i, q, L, n));
       }
       ra[s] = v;
     }
@@ -96,7 +105,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
       const int jj = e % BJ;
       const int kk = e / BJ;
       const int64_t r = drow[buf][kk];
-      rb[s] = (r >= 0 && j0 + jj < ncols) ? ldf(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc) : 0.f;
+      rb[s] = (r >= 0 && j0 + jj < ncols) ? ldc<CT>(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc) : CT(0);
     }
   };
 
@@ -125,19 +134,18 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
     if (tid < BK) drow[buf][tid] = drm_row(kb + 2 * BK + tid);
 #pragma unroll
     for (int s = 0; s < BK / 4; ++s) {
-      const float a = As[4 * s + lg][16 * wave + l16];
+      const CT a = As[4 * s + lg][16 * wave + l16];
 #pragma unroll
-      for (int cb = 0; cb < BJ / 16; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, Bs[4 * s + lg][16 * cb + l16], acc[cb], 0, 0, 0);
+      for (int cb = 0; cb < BJ / 16; ++cb) acc[cb] = P::mfma(a, Bs[4 * s + lg][16 * cb + l16], acc[cb]);
     }
     __syncthreads();
     buf ^= 1;
   }
 
-  // lane holds C[16 wave + 4 lg + v][16 cb + l16]
+  // lane holds C[16 wave + crow(lane, v)][16 cb + l16]
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    const int64_t row = row0 + 16 * wave + 4 * lg + v;
+    const int64_t row = row0 + 16 * wave + P::crow(lane, v);
     if (row >= rows_total) continue;
 #pragma unroll
     for (int cb = 0; cb < BJ / 16; ++cb) {
@@ -150,129 +158,7 @@ __device__ __forceinline__ void gemm_tile_mfma(const TH* __restrict__ H, int64_t
   }
 }
 
-// One output tile (rows row0.., columns j0.., contraction chunk c) of a generic contraction.
-// As in the MFMA tile, the operand and DRM entries of step s + 1 are loaded into
-// registers (and the DRM rows of step s + 2 computed) while step s is multiplied out
-// of LDS; each accumulator takes its products in the same order as without the
-// prefetch.
-template <bool RIGHT, typename TH, typename TD, typename TO>
-__device__ __forceinline__ void gemm_tile_valu(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
-                                          const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
-                                          const IndexMap& amap, const IndexMap& bmap, const HMap& hm,
-                                          int64_t kchunk, TO* __restrict__ out, const OutLayout& ol, int64_t row0,
-                                          int64_t c, int j0) {
-  constexpr int NA = BR * BK / 256, NB = BK * BJ / 256;
-  __shared__ double As[BK][BR + 1];
-  __shared__ double Bs[BK][BJ + 1];
-  __shared__ int64_t drow[2][BK];
-
-  const int tid = threadIdx.x;
-  const int64_t rows_total = RIGHT ? n : L * Q;
-  const int64_t K = RIGHT ? L * Q : n;
-  const int64_t k_begin = c * kchunk;
-  const int64_t k_end = (k_begin + kchunk < K) ? k_begin + kchunk : K;
-  const bool kk_contig = RIGHT ? (L > 1) : (L == 1);
-
-  const int tr = tid % 16;   // 4 rows each
-  const int tc = tid / 16;   // 2 columns each
-  double acc[4][2] = {};
-
-  auto drm_row = [&](int64_t kk) -> int64_t {
-    if (kk >= k_end) return -1;
-    return RIGHT ? amap(kk % L) + bmap(kk / L) : amap(kk);
-  };
-  auto a_pos = [&](int e, int& kk, int& rr) {
-    if (kk_contig) {
-      kk = e % BK;
-      rr = e / BK;
-    } else {
-      rr = e % BR;
-      kk = e / BR;
-    }
-  };
-  double ra[NA], rb[NB];
-  auto fetch = [&](int64_t kb, int buf) {
-#pragma unroll
-    for (int s = 0; s < NA; ++s) {
-      int kk, rr;
-      a_pos(tid + 256 * s, kk, rr);
-      const int64_t kg = kb + kk;
-      const int64_t rg = row0 + rr;
-      double v = 0.0;
-      if (kg < k_end && rg < rows_total) {
-        const int64_t m = RIGHT ? kg : rg;
-        const int64_t i = RIGHT ? rg : kg;
-        const int64_t l = m % L;
-        const int64_t q = m / L;
-        v = ld(H, hm(l, i, q, L, n));
-      }
-      ra[s] = v;
-    }
-#pragma unroll
-    for (int s = 0; s < NB; ++s) {
-      const int e = tid + 256 * s;
-      const int jj = e % BJ;
-      const int kk = e / BJ;
-      const int64_t r = drow[buf][kk];
-      rb[s] = (r >= 0 && j0 + jj < ncols) ? ld(D, r * sDr + static_cast<int64_t>(j0 + jj) * sDc) : 0.0;
-    }
-  };
-
-  if (tid < BK) {
-    drow[0][tid] = drm_row(k_begin + tid);
-    drow[1][tid] = drm_row(k_begin + BK + tid);
-  }
-  __syncthreads();
-  if (k_begin < k_end) fetch(k_begin, 0);
-  int buf = 0;
-  for (int64_t kb = k_begin; kb < k_end; kb += BK) {
-#pragma unroll
-    for (int s = 0; s < NA; ++s) {
-      int kk, rr;
-      a_pos(tid + 256 * s, kk, rr);
-      As[kk][rr] = ra[s];
-    }
-#pragma unroll
-    for (int s = 0; s < NB; ++s) {
-      const int e = tid + 256 * s;
-      Bs[e / BJ][e % BJ] = rb[s];
-    }
-    __syncthreads();
-    // drow[buf] is free again (its step is staged): it takes the rows of step s + 2
-    if (kb + BK < k_end) fetch(kb + BK, buf ^ 1);
-    if (tid < BK) drow[buf][tid] = drm_row(kb + 2 * BK + tid);
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      double a[4], b[2];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = As[kk][tr * 4 + u];
-#pragma unroll
-      for (int v = 0; v < 2; ++v) b[v] = Bs[kk][tc * 2 + v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 2; ++v) acc[u][v] = __fma_rn(a[u], b[v], acc[u][v]);
-    }
-    __syncthreads();
-    buf ^= 1;
-  }
-
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int64_t row = row0 + tr * 4 + u;
-    if (row >= rows_total) continue;
-#pragma unroll
-    for (int v = 0; v < 2; ++v) {
-      const int j = j0 + tc * 2 + v;
-      if (j >= ncols) continue;
-      const int64_t o = c * ol.cs + (row % ol.Lo) * ol.s0 + static_cast<int64_t>(j) * ol.s1 +
-                        (row / ol.Lo) * ol.s2;
-      out[o] = static_cast<TO>(acc[u][v]);
-    }
-  }
-}
-
-// FP32 / BF16 operands take the MFMA tile, anything with FP64 the VALU tile.
+// FP32 / BF16 operands take the FP32 MFMA tile, anything with FP64 the FP64 MFMA tile.
 template <bool RIGHT, typename TH, typename TD, typename TO>
 __device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, int64_t n, int64_t Q,
                                           const TD* __restrict__ D, int64_t sDr, int64_t sDc, int ncols,
@@ -280,11 +166,11 @@ __device__ __forceinline__ void gemm_tile(const TH* __restrict__ H, int64_t L, i
                                           int64_t kchunk, TO* __restrict__ out, const OutLayout& ol, int64_t row0,
                                           int64_t c, int j0) {
   if constexpr (!std::is_same_v<TH, double> && !std::is_same_v<TD, double>)
-    gemm_tile_mfma<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0, c,
-                                      j0);
+    gemm_tile_mfma<RIGHT, TH, TD, TO, float>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0,
+                                             c, j0);
   else
-    gemm_tile_valu<RIGHT, TH, TD, TO>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0, c,
-                                      j0);
+    gemm_tile_mfma<RIGHT, TH, TD, TO, double>(H, L, n, Q, D, sDr, sDc, ncols, amap, bmap, hm, kchunk, out, ol, row0,
+                                              c, j0);
 }
 
 template <bool RIGHT, typename TH, typename TD, typename TO>
