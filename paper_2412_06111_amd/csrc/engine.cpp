@@ -583,6 +583,7 @@ void update_box_impl(Plan& P, const void* block, const int64_t* off, const int64
     run_box_ops(P, ops, st);
     return;
   }
+  fill_transposed(P, st);                       // the MFMA forms below read them
   std::vector<int> fused_nodes;
   std::vector<std::vector<int>> fused_prefixes;
   if (P.timing) {

@@ -60,6 +60,12 @@ void pool_free(void* p, hipStream_t stream) {
   if (p) (void)hipFreeAsync(p, stream);
 }
 
+void fill_transposed(Plan& P, hipStream_t stream) {
+  for (const Plan::TransposedCopy& c : P.transposed_pending)
+    copy_layout(c.src, c.dst, c.dt, c.rows, c.cols, 1, c.cols, 1, 0, 0, c.rows, stream);
+  P.transposed_pending.clear();
+}
+
 // Device memory of a plan is stream ordered (allocated on the creation stream), so
 // releasing it does not synchronise the device: the blocks return to the pool when
 // the release stream reaches them.
@@ -422,7 +428,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       // of a chain): T viewed as [n_t][N / n_t] with the contraction index contiguous
       if (nd.first == 0 && right_mfma_eligible(nd.n, P->N / nd.n, 1, nd.k, P->dtype)) {
         nd.Yt = P->alloc(dtype_size(P->dtype) * nd.n * nd.k);
-        if (fill) copy_layout(nd.Y64, nd.Yt, P->dtype, nd.n, nd.k, 1, nd.k, 1, 0, 0, nd.n, stream);
+        if (fill) P->transposed_pending.push_back({nd.Y64, nd.Yt, P->dtype, nd.n, nd.k});
       }
       if (F.enabled && (v == F.node_A || v == F.node_1 || v == (F.tt ? F.node_B : F.node_2))) continue;
       if (!nd.S.empty()) {
@@ -435,7 +441,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
         if (L * nd.n * Q >= (int64_t(1) << 22) && nd.m * nd.r <= (int64_t(1) << 26) &&
             right_mfma_eligible(L, nd.n, Q, nd.r, TTNN_F64)) {
           nd.Xt64 = static_cast<double*>(P->alloc(sizeof(double) * nd.m * nd.r));
-          if (fill) copy_layout(nd.X64, nd.Xt64, TTNN_F64, nd.m, nd.r, 1, nd.r, 1, 0, 0, nd.m, stream);
+          if (fill) P->transposed_pending.push_back({nd.X64, nd.Xt64, TTNN_F64, nd.m, nd.r});
         }
         continue;
       }
@@ -444,7 +450,7 @@ std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, boo
       int64_t n = nd.n, Q = nd.m / (L > 0 ? L : 1);
       if (!right_mfma_eligible(L, n, Q, nd.r, P->dtype)) continue;
       nd.Xt = P->alloc(dtype_size(P->dtype) * nd.m * nd.r);
-      if (fill) copy_layout(nd.X64, nd.Xt, P->dtype, nd.m, nd.r, 1, nd.r, 1, 0, 0, nd.m, stream);
+      if (fill) P->transposed_pending.push_back({nd.X64, nd.Xt, P->dtype, nd.m, nd.r});
     }
   };
   if (dry) {

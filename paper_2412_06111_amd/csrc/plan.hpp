@@ -118,6 +118,16 @@ struct Plan {
   hipStream_t side = nullptr;
   hipEvent_t side_ev[2] = {nullptr, nullptr};
   bool side_pending = false;
+  // transposed DRM copies (Xt, Yt, Xt64) for the MFMA forms of whole-tensor updates:
+  // reserved at creation, filled from the FP64 masters by the first whole-tensor update
+  // (plans fed only boxes and rank-1 terms never read them)
+  struct TransposedCopy {
+    const double* src;
+    void* dst;
+    int dt;
+    int64_t rows, cols;
+  };
+  std::vector<TransposedCopy> transposed_pending;
 
   ~Plan();
   void* alloc(size_t bytes);
@@ -130,6 +140,9 @@ struct Plan {
 // allocates one block from the library's per-device pool.
 std::unique_ptr<Plan> build_plan(const ttnn_problem* pr, hipStream_t stream, bool dry = false, void* ws = nullptr,
                                  size_t ws_bytes = 0);
+
+// Fills the transposed DRM copies still pending, on `stream` (no-op once done).
+void fill_transposed(Plan& P, hipStream_t stream);
 
 // Stream-ordered device memory from the library's per-device pool (plans and per-call
 // scratch); throws TTNN_E_NOMEM.
