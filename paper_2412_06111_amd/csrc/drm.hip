@@ -127,11 +127,17 @@ __device__ inline double gaussian(uint64_t seed, uint32_t tag, uint64_t row, uin
 __global__ void drm_kernel(int64_t rows, int cols, uint64_t seed, uint32_t tag, double* __restrict__ o64,
                            float* __restrict__ o32, uint16_t* __restrict__ o16) {
   const int64_t total = rows * cols;
-  for (int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; idx < total;
-       idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t row = static_cast<uint64_t>(idx / cols);
-    const uint32_t col = static_cast<uint32_t>(idx - static_cast<int64_t>(row) * cols);
-    const double z = gaussian(seed, tag, row, col);
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  int64_t idx = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  // (row, column) of idx, advanced by the grid stride with one carry test instead of a
+  // 64-bit division per entry (the generator is bound by its integer and FP64 work)
+  int64_t row = idx / cols;
+  int col = static_cast<int>(idx - row * cols);
+  const int64_t srow = stride / cols;
+  const int scol = static_cast<int>(stride - srow * cols);
+  for (; idx < total; idx += stride) {
+    const double z = gaussian(seed, tag, static_cast<uint64_t>(row), static_cast<uint32_t>(col));
     // a plan of lower precision uses one matrix everywhere: the rounded copy, whose
     // values the FP64 array then holds exactly
     double m = z;
@@ -147,6 +153,12 @@ __global__ void drm_kernel(int64_t rows, int cols, uint64_t seed, uint32_t tag, 
       }
     }
     o64[idx] = m;
+    col += scol;
+    row += srow;
+    if (col >= cols) {
+      col -= cols;
+      ++row;
+    }
   }
 }
 
