@@ -493,32 +493,35 @@ def rank1_bench(args):
 
     n = args.single_n
     dims = (n,) * 5
-    plan = P.Plan(T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=1)
-    map_bytes = 0
-    for i in range(1, plan.num_nodes):
-        rows, cols = plan.drm_shape(i, 0)
-        map_bytes += rows * cols * 4
     g = np.random.default_rng(5)
     terms = [[torch.from_numpy(g.standard_normal(k)).cuda() for k in dims] for _ in range(8)]
     stream = torch.cuda.current_stream()
-    out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTNN, r=24, p=12, FP32 maps", "map_bytes": map_bytes}
-    for m in (1, 2, 4, 8):
-        for _ in range(2):
-            plan.update_rank1_batched(terms[:m], [1.0] * m)
-        torch.cuda.synchronize()
-        reps = max(2, args.steps // 2)
-        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(reps):
-            plan.update_rank1_batched(terms[:m], [1.0] * m)
-        t1.record(stream)
-        torch.cuda.synchronize()
-        ms = t0.elapsed_time(t1) / reps
-        out[f"group{m}"] = {"ms_per_group": ms, "ms_per_term": ms / m,
-                            "map_GBps_per_group": map_bytes / (ms * 1e-3) / 1e9}
-        print(f"# rank-1 group of {m}: {ms:.3f} ms, {ms / m:.3f} ms a term, maps {map_bytes / (ms * 1e-3) / 1e9:.0f} GB/s",
-              file=sys.stderr, flush=True)
-    plan.close()
+    out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTNN, r=24, p=12, FP32 maps"}
+    for form in ("termwise", "grouped"):
+        plan = P.Plan(T5, dims, 24, 12, variant="ttnn", dtype="f32", seed=1)
+        plan.set_rank1_form(form)
+        map_bytes = 0
+        for i in range(1, plan.num_nodes):
+            rows, cols = plan.drm_shape(i, 0)
+            map_bytes += rows * cols * 4
+        out["map_bytes"] = map_bytes
+        for m in (1, 2, 4, 8):
+            for _ in range(2):
+                plan.update_rank1_batched(terms[:m], [1.0] * m)
+            torch.cuda.synchronize()
+            reps = max(2, args.steps // 2)
+            t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0.record(stream)
+            for _ in range(reps):
+                plan.update_rank1_batched(terms[:m], [1.0] * m)
+            t1.record(stream)
+            torch.cuda.synchronize()
+            ms = t0.elapsed_time(t1) / reps
+            out[f"{form}_group{m}"] = {"ms_per_group": ms, "ms_per_term": ms / m,
+                                       "map_GBps_per_group": map_bytes / (ms * 1e-3) / 1e9}
+            print(f"# rank-1 {form} group of {m}: {ms:.3f} ms, {ms / m:.3f} ms a term, maps "
+                  f"{map_bytes / (ms * 1e-3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+        plan.close()
     return out
 
 

@@ -254,6 +254,23 @@ ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_fa
 ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, const double* const* d_factors,
                                              const double* alphas, void* stream);
 
+/* How the plan's rank-1 updates form X_t^T v_t (Sec. 4 linearity; the same sums, in
+ * FP64 products, in a different association):
+ *   TTNN_R1_TERMWISE (default)  a GEMV per term over the map's rows, fastest for terms
+ *                               applied one or two at a time;
+ *   TTNN_R1_GROUPED             where a map has two fastest factor positions of 16..128
+ *                               rows and 4..128 values and at least 1,024 blocks of them,
+ *                               the two positions are contracted on the FP64 MFMA for
+ *                               up to 16 terms at once: in groups of 8 a term costs
+ *                               about half of a term-wise one in the same group and a
+ *                               quarter of a lone term, alone 1.7 times a lone term;
+ *                               other maps keep the per-term form.
+ * Every rank-1 update of a plan takes its plan's form, so a term's result is bitwise
+ * the same in any batch; the two forms agree to FP64 rounding.  Set it before the
+ * plan's first rank-1 update.  TTNN_E_INVALID for another value. */
+typedef enum { TTNN_R1_TERMWISE = 0, TTNN_R1_GROUPED = 1 } ttnn_rank1_form;
+ttnn_status ttnn_set_rank1_form(ttnn_plan_t plan, int32_t form);
+
 /* Several box updates, possibly for different plans, in one call (continuous
  * batching of streamed updates, Sec. 4 linearity).  The call works in rounds: a
  * round takes the earliest remaining update of every plan; the box updates of a

@@ -87,6 +87,7 @@ def _load():
         "ttnn_reuse_set": [vp, i32, C.POINTER(i32), C.POINTER(i32)],
         "ttnn_reset": [vp, vp],
         "ttnn_set_timing": [vp, i32],
+        "ttnn_set_rank1_form": [vp, i32],
         "ttnn_footprint_estimate": [C.POINTER(Problem), C.POINTER(C.c_size_t)],
         "ttnn_order_cost": [C.POINTER(Problem), i32, C.POINTER(dbl)],
         "ttnn_order_search": [C.POINTER(Problem), i32, P32, C.POINTER(dbl)],
@@ -519,6 +520,11 @@ class Plan:
 
     def set_timing(self, on=True):
         check(lib.ttnn_set_timing(self.handle, 1 if on else 0))
+
+    def set_rank1_form(self, form):
+        """"termwise" (default: a GEMV per term) or "grouped" (term groups on the FP64
+        MFMA where the maps allow it; for callers that batch rank-1 terms)."""
+        check(lib.ttnn_set_rank1_form(self.handle, {"termwise": 0, "grouped": 1}[form]))
 
     def sweep_kind(self):
         """0 whole update, 1 STTNN one-pass kernel, 2 STTNN one-pass kernel writing Z1

@@ -687,6 +687,16 @@ ttnn_status ttnn_reset(ttnn_plan_t plan, void* stream) {
   }
 }
 
+ttnn_status ttnn_set_rank1_form(ttnn_plan_t plan, int32_t form) {
+  Plan* P = get(plan);
+  return guard(P, [&]() -> ttnn_status {
+    if (!P) throw Error{TTNN_E_INVALID, "plan is NULL"};
+    if (form != TTNN_R1_TERMWISE && form != TTNN_R1_GROUPED) throw Error{TTNN_E_INVALID, "bad rank-1 form"};
+    P->rank1_form = form;
+    return TTNN_OK;
+  });
+}
+
 ttnn_status ttnn_set_timing(ttnn_plan_t plan, int32_t on) {
   Plan* P = get(plan);
   return guard(P, [&]() -> ttnn_status {

@@ -1061,7 +1061,7 @@ void update_rank1(Plan& P, int nterms, const double* const* factors, const doubl
         KronBatch kb;
         for (int y = 0; y < m; ++y) kb.push(modes(y, g.first, g.last));
         launch_kron_gemv(raw ? g.Yc : static_cast<const void*>(g.Y64), raw ? cd : TTNN_F64, g.n, g.k, kb, P.partial,
-                         P.partial_elems, P.r1 + goff[s], P.r1_w, st);
+                         P.partial_elems, P.r1 + goff[s], P.r1_w, P.rank1_form == TTNN_R1_GROUPED, st);
       }
       return goff[s];
     };
@@ -1093,7 +1093,7 @@ void update_rank1(Plan& P, int nterms, const double* const* factors, const doubl
       }
       const bool raw = t.S.empty();
       launch_kron_gemv(raw ? t.Xc : static_cast<const void*>(t.X64), raw ? cd : TTNN_F64, t.m, t.r, kx, P.partial,
-                       P.partial_elems, w, wstride, st);
+                       P.partial_elems, w, wstride, P.rank1_form == TTNN_R1_GROUPED, st);
       launch_outer_acc(t.R, t.n, t.r, ku, w, wstride, st);
     }
     KronBatch kg;

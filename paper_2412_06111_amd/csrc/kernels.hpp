@@ -212,8 +212,10 @@ struct KronBatch {
 // whatever the batch it is computed in.  The blocks of the terms over one chunk of rows
 // run side by side on one XCD, so the chunk comes from HBM about once per batch.
 // `partial` is scratch.
+// grouped: the term-group form on the FP64 MFMA where the map's shape allows it (the
+// caller keeps one choice for all of a plan's terms).
 void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronBatch& kb, double* partial,
-                      size_t partial_elems, double* w, int64_t wstride, hipStream_t stream);
+                      size_t partial_elems, double* w, int64_t wstride, bool grouped, hipStream_t stream);
 // R[i + n j] += alpha_y * ku_y(i) * (w ? w[y * wstride + j] : 1) for y = 0 .. m-1 in that
 // order, R column-major n x ncols (each entry sees the terms' additions in order, as
 // with one launch per term).

@@ -118,6 +118,7 @@ struct Plan {
   hipStream_t side = nullptr;
   hipEvent_t side_ev[2] = {nullptr, nullptr};
   bool side_pending = false;
+  int rank1_form = TTNN_R1_TERMWISE;       // how rank-1 updates form X_t^T v_t
   // transposed DRM copies (Xt, Yt, Xt64) for the MFMA forms of whole-tensor updates:
   // reserved at creation, filled from the FP64 masters by the first whole-tensor update
   // (plans fed only boxes and rank-1 terms never read them)

@@ -8,6 +8,7 @@
 // GEMV whose vector is never formed: the weight of a row is the product of one
 // factor entry per position, read from the row's mixed-radix digits.
 #include "kernels.hpp"
+#include "mfma.hpp"
 
 namespace ttnn {
 namespace {
@@ -265,6 +266,170 @@ void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, i
   else launch_gemv_di<TD, int64_t>(D, rows, ncols, kb, per, nb, partial, st);
 }
 
+// Kronecker GEMV with the two fastest factor positions (lengths e0, e1) contracted on
+// the FP64 MFMA.  Block b takes the e0 e1 consecutive map rows of its outer index b
+// (the digits of positions 2, 3, ..) and forms for every term y
+//   C_y[j] = sum_{i1 < e1} v1_y[i1] sum_{i0 < e0} v0_y[i0] D[i0 + e0 (i1 + e1 b)][j],
+// the inner sum as a 16 x 16 x 4 MFMA product with the terms as rows (A[y][i0] =
+// v0_y[i0]) and a 16-column block of the map as columns (B[i0][j], K = e0 in steps of
+// 4), then writes partial[(y nb + b) ncols + j] = wrest_y(b) C_y[j], wrest_y the
+// product of the remaining factors at b's digits.  Wave w takes i1 = w, w + 4, ..: it
+// copies its e0 x ncols block of rows (contiguous in the map) into its own LDS buffer
+// from registers loaded one block ahead, so no barrier is needed inside the loop (a
+// wave's LDS accesses are in program order); the four waves' sums are added in wave
+// order at the end.  A term's row of the product does not depend on the other rows,
+// so its partials are the same in any batch.
+constexpr int kKmTile = 8192;     // bytes of one wave's staged block of map rows
+constexpr int kKmE0 = 128;        // largest e0
+constexpr int kKmE1 = 128;        // largest e1
+
+template <typename TD, int NCB>
+__global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D, int ncols, KronBatch kb,
+                                                       int64_t nb, double* __restrict__ partial) {
+  using P = Pol<TTNN_F64>;
+  constexpr int V = 16 / static_cast<int>(sizeof(TD));
+  constexpr int TE = kKmTile / static_cast<int>(sizeof(TD));     // elements of a staged block
+  constexpr int PER = TE / (64 * V);                               // 16-byte loads a lane a block
+  static_assert(PER * 64 * V == TE, "whole loads");
+  static_assert(4 * 16 * 16 * NCB * sizeof(double) <= 4 * kKmTile, "wave sums fit the tiles");
+  typedef TD vec_t __attribute__((ext_vector_type(V)));
+  __shared__ __align__(16) TD tile[4][TE];
+  __shared__ double W0[16][kKmE0];
+  __shared__ double W1[16][kKmE1];
+  __shared__ double wrest[16];
+
+  const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t b = blockIdx.x;
+  const int m = kb.m;
+  const KronVec& k0 = kb.kv[0];             // every term has the same factor lengths
+  const int e0 = static_cast<int>(k0.len[0]), e1 = static_cast<int>(k0.len[1]);
+  const int blk = e0 * ncols;               // elements of one i1 block
+
+  for (int e = tid; e < 16 * kKmE0; e += 256) {
+    const int y = e / kKmE0, i = e % kKmE0;
+    W0[y][i] = (y < m && i < e0) ? kb.kv[y].v[0][i] : 0.0;
+  }
+  for (int e = tid; e < 16 * kKmE1; e += 256) {
+    const int y = e / kKmE1, i = e % kKmE1;
+    W1[y][i] = (y < m && i < e1) ? kb.kv[y].v[1][i] : 0.0;
+  }
+  if (tid < 16) {
+    double w = 0.0;
+    if (tid < m) {
+      w = 1.0;
+      int64_t rem = b;
+      for (int p = 2; p < k0.n; ++p) {
+        const int64_t len = k0.len[p];
+        w *= kb.kv[tid].v[p][rem % len];
+        rem /= len;
+      }
+    }
+    wrest[tid] = w;
+  }
+  __syncthreads();
+
+  const TD* base = D + b * static_cast<int64_t>(e1) * blk;
+  TD* t = tile[wave];
+  // two blocks of loads in flight: the wave's blocks alternate between two register sets
+  vec_t ra0[PER], ra1[PER];
+  auto fetch = [&](int i1, vec_t* ra) {
+    const TD* src = base + static_cast<int64_t>(i1) * blk;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      const int e = (lane + 64 * k) * V;
+      ra[k] = e < blk ? *reinterpret_cast<const vec_t*>(src + e) : vec_t{};
+    }
+  };
+  auto stage = [&](const vec_t* ra) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) *reinterpret_cast<vec_t*>(t + (lane + 64 * k) * V) = ra[k];
+    // the block's reads below stay after its writes (the LDS keeps a wave's accesses in
+    // order; this keeps the compiler from moving them)
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
+  typename P::CFrag acc[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = typename P::CFrag{};
+  // four independent MFMA chains a column block (steps of 4 values taken in turn), added
+  // at the end: a dependent FP64 MFMA waits for the previous one's result
+  auto compute = [&](int i1) {
+    typename P::CFrag c[4][NCB];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) c[h][cb] = typename P::CFrag{};
+    for (int k = 0; k < e0; k += 16) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const int i0 = k + 4 * h + lg;
+        const double a = i0 < e0 ? W0[l16][i0] : 0.0;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const int j = 16 * cb + l16;
+          const double bv = (i0 < e0 && j < ncols) ? to_f64(t[i0 * ncols + j]) : 0.0;
+          c[h][cb] = P::mfma(a, bv, c[h][cb]);
+        }
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double s1 = W1[P::crow(lane, v)][i1];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb][v] += s1 * ((c[0][cb][v] + c[1][cb][v]) + (c[2][cb][v] + c[3][cb][v]));
+    }
+  };
+  if (wave < e1) fetch(wave, ra0);
+  if (wave + 4 < e1) fetch(wave + 4, ra1);
+  for (int i1 = wave; i1 < e1; i1 += 8) {
+    stage(ra0);
+    if (i1 + 8 < e1) fetch(i1 + 8, ra0);
+    compute(i1);
+    if (i1 + 4 >= e1) break;
+    stage(ra1);
+    if (i1 + 12 < e1) fetch(i1 + 12, ra1);
+    compute(i1 + 4);
+  }
+  __syncthreads();                            // every wave is done with its tile
+  double* red = reinterpret_cast<double*>(&tile[0][0]);     // [wave][term][column]
+#pragma unroll
+  for (int v = 0; v < 4; ++v)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) red[(wave * 16 + P::crow(lane, v)) * (16 * NCB) + 16 * cb + l16] = acc[cb][v];
+  __syncthreads();
+  for (int e = tid; e < 16 * ncols; e += 256) {
+    const int y = e / ncols, j = e % ncols;
+    if (y >= m) continue;
+    const int o = y * (16 * NCB) + j, ws = 16 * 16 * NCB;
+    const double sum = ((red[o] + red[o + ws]) + red[o + 2 * ws]) + red[o + 3 * ws];
+    partial[(static_cast<int64_t>(y) * nb + b) * ncols + j] = wrest[y] * sum;
+  }
+}
+
+// Whether the MFMA form covers this map and batch shape (never depends on the number
+// of terms, so a term takes the same form alone and in any batch).
+bool kron_mfma_eligible(int64_t rows, int ncols, const KronVec& k0, size_t esize, size_t partial_elems) {
+  if (k0.n < 2 || ncols > 64) return false;
+  const int64_t e0 = k0.len[0], e1 = k0.len[1];
+  if (e0 < 16 || e0 > kKmE0 || e1 < 4 || e1 > kKmE1) return false;
+  const int64_t bytes = e0 * ncols * static_cast<int64_t>(esize);
+  if (bytes > kKmTile || bytes % 16 != 0) return false;
+  const int64_t nb = rows / (e0 * e1);
+  return nb >= 1024 && nb * e0 * e1 == rows &&
+         static_cast<size_t>(nb) * static_cast<size_t>(ncols) * kRank1Batch <= partial_elems;
+}
+
+template <typename TD>
+void launch_kron_mfma(const TD* D, int ncols, const KronBatch& kb, int64_t nb, double* partial, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(nb));
+  switch ((ncols + 15) / 16) {
+    case 1: hipLaunchKernelGGL((kron_mfma_kernel<TD, 1>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+    case 2: hipLaunchKernelGGL((kron_mfma_kernel<TD, 2>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+    case 3: hipLaunchKernelGGL((kron_mfma_kernel<TD, 3>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+    default: hipLaunchKernelGGL((kron_mfma_kernel<TD, 4>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+  }
+}
+
 // w[y wstride + j] = sum_b partial[y nb + b][j]: one wave per (column, term), lane l
 // summing blocks l, l + 64, .. in order, the 64 sums combined by a fixed butterfly
 __global__ __launch_bounds__(64) void sum_blocks_kernel(const double* __restrict__ partial, int nb, int ncols,
@@ -307,10 +472,20 @@ __global__ void outer_acc_kernel(double* __restrict__ R, int64_t n, int ncols, K
 }  // namespace
 
 void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const KronBatch& kb, double* partial,
-                      size_t partial_elems, double* w, int64_t wstride, hipStream_t st) {
+                      size_t partial_elems, double* w, int64_t wstride, bool grouped, hipStream_t st) {
   if (ncols <= 0 || kb.m <= 0) return;
   TTNN_REQUIRE(ncols <= 64, TTNN_E_INVALID, "rank-1 update with more than 64 map columns");
   TTNN_REQUIRE(kb.m <= kRank1Batch, TTNN_E_INVALID, "too many rank-1 terms in one launch");
+  const size_t esize = dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2;
+  if (grouped && kron_mfma_eligible(rows, ncols, kb.kv[0], esize, partial_elems)) {
+    const int64_t nbm = rows / (kb.kv[0].len[0] * kb.kv[0].len[1]);
+    if (dt == TTNN_F64) launch_kron_mfma(static_cast<const double*>(D), ncols, kb, nbm, partial, st);
+    else if (dt == TTNN_F32) launch_kron_mfma(static_cast<const float*>(D), ncols, kb, nbm, partial, st);
+    else launch_kron_mfma(static_cast<const uint16_t*>(D), ncols, kb, nbm, partial, st);
+    hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols, kb.m), dim3(64), 0, st, partial, static_cast<int>(nbm), ncols,
+                       w, wstride);
+    return;
+  }
   // >= 512 rows a block, at most 2048 blocks a term; the chunking depends on rows and
   // ncols only, never on the batch, so a term's sums are the same in any batch
   int64_t nb = (rows + 511) / 512;

@@ -69,6 +69,7 @@ class LibEngine:
         from . import _lib as L
         self.torch, self.L = torch, L
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.rank1_form = "termwise"            # the server sets "grouped" when it batches terms
         # pinned status words, reused (a pinned allocation costs milliseconds)
         self._pinned = [torch.zeros(1, dtype=torch.int32, pin_memory=True) for _ in range(16)]
 
@@ -76,8 +77,10 @@ class LibEngine:
         return self.L.footprint_estimate(s.spec, s.dims, s.rank, s.over, s.variant, s.dtype)
 
     def create(self, s):
-        return self.L.Plan(s.spec, s.dims, s.rank, s.over, variant=s.variant, dtype=s.dtype, seed=s.seed,
+        plan = self.L.Plan(s.spec, s.dims, s.rank, s.over, variant=s.variant, dtype=s.dtype, seed=s.seed,
                            stream=self.stream)
+        plan.set_rank1_form(self.rank1_form)
+        return plan
 
     def launch(self, items):
         """items: list of (plan, Update) with at most one update per plan."""
@@ -169,6 +172,8 @@ class Server:
         self.keep_plans = keep_plans
         self.on_close = on_close                # on_close(sid, plan, cores) before the plan is released
         self.engine = engine if engine is not None else LibEngine()
+        if self.rank1_batch > 1 and hasattr(self.engine, "rank1_form"):
+            self.engine.rank1_form = "grouped"  # terms come in groups: the group form
         self.used = 0
         self.peak_used = 0                      # largest admitted footprint at any time
         self.create_s = []                      # host time of each plan creation (admission)

@@ -80,3 +80,44 @@ def test_rank1_batched_empty_is_noop(P):
     tree = O.Tree(T4, (6, 7, 5, 4), 3, 2)
     assert all(not np.any(s) for s in _sketches(P, plan, tree))
     plan.close()
+
+
+# leaf maps of 16^5 rows over five factor positions of 16, plans in the grouped rank-1
+# form: the two fastest positions contracted on the FP64 MFMA (4,096 blocks of 256
+# rows); FP32 and BF16 maps,
+# TTNN and STTNN (whose chained nodes' positions are the short contracted groups and
+# take the other form), against the oracle on the same rounded maps at FP64 accuracy
+MFMA_CASES = [("ttnn-f32", "ttnn", "f32"), ("sttnn-f32", "sttnn", "f32"), ("ttnn-bf16", "ttnn", "bf16")]
+
+
+@pytest.mark.parametrize("m", [1, 8])
+@pytest.mark.parametrize("name,variant,dtype", MFMA_CASES, ids=[c[0] for c in MFMA_CASES])
+def test_rank1_mfma_form(P, name, variant, dtype, m):
+    dims, r, p = (16,) * 6, 8, 4
+    print(f"rank1 mfma {name} m={m}", flush=True)
+    g = np.random.default_rng(60 + m)
+    vecs = [[g.standard_normal(n) for n in dims] for _ in range(m)]
+    alphas = [float(a) for a in g.uniform(-2, 2, size=m)]
+    dev = [[torch.from_numpy(v).cuda() for v in term] for term in vecs]
+    one = P.Plan(TOY, dims, r, p, variant=variant, dtype=dtype, seed=6)
+    many = P.Plan(TOY, dims, r, p, variant=variant, dtype=dtype, seed=6)
+    one.set_rank1_form("grouped")
+    many.set_rank1_form("grouped")
+    for term, a in zip(dev, alphas):
+        one.update_rank1(term, alpha=a)
+    many.update_rank1_batched(dev, alphas)
+    torch.cuda.synchronize()
+    tree = O.Tree(TOY, dims, r, p)
+    for a, b in zip(_sketches(P, one, tree), _sketches(P, many, tree)):
+        assert np.array_equal(a.view(np.uint64), b.view(np.uint64))
+    T = np.zeros(dims)
+    for term, a in zip(vecs, alphas):
+        outer = term[0]
+        for v in term[1:]:
+            outer = np.multiply.outer(outer, v)
+        T += a * outer
+    sk = O.sketch(T, tree, O.DRMs(tree, 6, variant, dtype), variant)
+    bad = failures(sketch_errors(many, tree, sk), 1e-10)
+    assert not bad, bad
+    one.close()
+    many.close()
