@@ -494,7 +494,7 @@ def rank1_bench(args):
     n = args.single_n
     dims = (n,) * 5
     g = np.random.default_rng(5)
-    terms = [[torch.from_numpy(g.standard_normal(k)).cuda() for k in dims] for _ in range(8)]
+    terms = [[torch.from_numpy(g.standard_normal(k)).cuda() for k in dims] for _ in range(16)]
     stream = torch.cuda.current_stream()
     out = {"workload": f"{n}^5 on (((1,2),3),(4,5)), TTNN, r=24, p=12, FP32 maps"}
     for form in ("termwise", "grouped"):
@@ -505,7 +505,7 @@ def rank1_bench(args):
             rows, cols = plan.drm_shape(i, 0)
             map_bytes += rows * cols * 4
         out["map_bytes"] = map_bytes
-        for m in (1, 2, 4, 8):
+        for m in (1, 2, 4, 8, 16):
             for _ in range(2):
                 plan.update_rank1_batched(terms[:m], [1.0] * m)
             torch.cuda.synchronize()

@@ -248,9 +248,9 @@ ttnn_status ttnn_sketch_update_rank1(ttnn_plan_t plan, const double* const* d_fa
 /* nterms rank-1 updates in one call (streaming by linearity, Sec. 4): d_factors is a
  * host array of nterms x order device pointers, term-major (term i's factor of mode mu
  * at d_factors[i * order + mu]), alphas a host array of nterms scales.  Bitwise equal
- * to nterms calls of ttnn_sketch_update_rank1 in order; up to 8 terms share one read
+ * to nterms calls of ttnn_sketch_update_rank1 in order; up to 16 terms share one read
  * of each map (a rank-1 update reads every map once, so a batch of terms costs about
- * one term's map traffic).  nterms = 0 is a no-op. */
+ * one term's map traffic; see ttnn_set_rank1_form).  nterms = 0 is a no-op. */
 ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, const double* const* d_factors,
                                              const double* alphas, void* stream);
 
@@ -261,10 +261,10 @@ ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, c
  *   TTNN_R1_GROUPED             where a map has two fastest factor positions of 16..128
  *                               rows and 4..128 values and at least 1,024 blocks of them,
  *                               the two positions are contracted on the FP64 MFMA for
- *                               up to 16 terms at once: in groups of 8 a term costs
- *                               about half of a term-wise one in the same group and a
- *                               quarter of a lone term, alone 1.7 times a lone term;
- *                               other maps keep the per-term form.
+ *                               up to 16 terms at once: in groups of 16 a term costs
+ *                               about 0.3 of a term-wise one in the same group and 0.15
+ *                               of a lone term, alone 1.7 times a lone term; other maps
+ *                               keep the per-term form.
  * Every rank-1 update of a plan takes its plan's form, so a term's result is bitwise
  * the same in any batch; the two forms agree to FP64 rounding.  Set it before the
  * plan's first rank-1 update.  TTNN_E_INVALID for another value. */

@@ -195,7 +195,7 @@ void launch_pack_box(const void* src, int dt, int d, const int64_t* ext, const i
 constexpr int64_t kPackMinEntries = int64_t(1) << 22;
 
 // Up to kRank1Batch rank-1 terms handled by one launch (their vectors and scales).
-constexpr int kRank1Batch = 8;
+constexpr int kRank1Batch = 16;
 struct KronBatch {
   int m = 0;
   KronVec kv[kRank1Batch];

@@ -160,7 +160,7 @@ class _Stream:
 
 class Server:
     def __init__(self, budget_bytes, max_batch=64, max_inflight=2, assemble_every=0, engine=None,
-                 keep_plans=False, on_close=None, rank1_batch=8):
+                 keep_plans=False, on_close=None, rank1_batch=16):
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         # consecutive queued rank-1 updates of one stream launched together (up to this

@@ -1,6 +1,6 @@
 """Batched rank-1 updates on the GPU (streaming by linearity, Sec. 4), through the C ABI:
-ttnn_sketch_update_rank1_batched with 1, 3, 8 and 11 terms (one and two launches of up
-to 8 terms) is bitwise equal to the same terms applied one by one with
+ttnn_sketch_update_rank1_batched with 1, 3, 8, 16 and 19 terms (one and two launches of
+up to 16 terms) is bitwise equal to the same terms applied one by one with
 ttnn_sketch_update_rank1, for TTNN and STTNN (a non-lexicographic order, a free mode) in
 FP64 / FP32 / BF16, and the accumulated sketches match the oracle's sketch of the sum
 of the terms at the dtype tolerance."""
@@ -42,7 +42,7 @@ def _sketches(P, plan, tree):
     return out
 
 
-@pytest.mark.parametrize("m", [1, 3, 8, 11])
+@pytest.mark.parametrize("m", [1, 3, 8, 16, 19])
 @pytest.mark.parametrize("name,spec,visit,dims,variant,dtype", CASES, ids=[c[0] for c in CASES])
 def test_rank1_batched_equals_sequential(P, name, spec, visit, dims, variant, dtype, m):
     print(f"rank1 batch {name} m={m}", flush=True)
@@ -90,7 +90,7 @@ def test_rank1_batched_empty_is_noop(P):
 MFMA_CASES = [("ttnn-f32", "ttnn", "f32"), ("sttnn-f32", "sttnn", "f32"), ("ttnn-bf16", "ttnn", "bf16")]
 
 
-@pytest.mark.parametrize("m", [1, 8])
+@pytest.mark.parametrize("m", [1, 16])
 @pytest.mark.parametrize("name,variant,dtype", MFMA_CASES, ids=[c[0] for c in MFMA_CASES])
 def test_rank1_mfma_form(P, name, variant, dtype, m):
     dims, r, p = (16,) * 6, 8, 4
