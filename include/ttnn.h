@@ -258,13 +258,14 @@ ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, c
  * FP64 products, in a different association):
  *   TTNN_R1_TERMWISE (default)  a GEMV per term over the map's rows, fastest for terms
  *                               applied one or two at a time;
- *   TTNN_R1_GROUPED             where a map has two fastest factor positions of 16..128
- *                               rows and 4..128 values and at least 1,024 blocks of them,
- *                               the two positions are contracted on the FP64 MFMA for
- *                               up to 16 terms at once: in groups of 16 a term costs
- *                               about 0.3 of a term-wise one in the same group and 0.15
- *                               of a lone term, alone 1.7 times a lone term; other maps
- *                               keep the per-term form.
+ *   TTNN_R1_GROUPED             where a map has two fastest factor positions of 16..64
+ *                               and 4..64 values, at most 48 columns, a block of the
+ *                               first position's rows within 6 KB and at least 1,024
+ *                               blocks, the two positions are contracted on the FP64
+ *                               MFMA for up to 16 terms at once: in groups of 16 a term
+ *                               costs about a quarter of a term-wise one in the same
+ *                               group and an eighth of a lone term, alone 1.3 times a
+ *                               lone term; other maps keep the per-term form.
  * Every rank-1 update of a plan takes its plan's form, so a term's result is bitwise
  * the same in any batch; the two forms agree to FP64 rounding.  Set it before the
  * plan's first rank-1 update.  TTNN_E_INVALID for another value. */

@@ -279,9 +279,9 @@ void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, i
 // wave's LDS accesses are in program order); the four waves' sums are added in wave
 // order at the end.  A term's row of the product does not depend on the other rows,
 // so its partials are the same in any batch.
-constexpr int kKmTile = 8192;     // bytes of one wave's staged block of map rows
-constexpr int kKmE0 = 128;        // largest e0
-constexpr int kKmE1 = 128;        // largest e1
+constexpr int kKmTile = 6144;     // bytes of one wave's staged block of map rows
+constexpr int kKmE0 = 64;         // largest e0
+constexpr int kKmE1 = 64;         // largest e1
 
 template <typename TD, int NCB>
 __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D, int ncols, KronBatch kb,
@@ -296,7 +296,6 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
   __shared__ __align__(16) TD tile[4][TE];
   __shared__ double W0[16][kKmE0];
   __shared__ double W1[16][kKmE1];
-  __shared__ double wrest[16];
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -314,26 +313,12 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
     const int y = e / kKmE1, i = e % kKmE1;
     W1[y][i] = (y < m && i < e1) ? kb.kv[y].v[1][i] : 0.0;
   }
-  if (tid < 16) {
-    double w = 0.0;
-    if (tid < m) {
-      w = 1.0;
-      int64_t rem = b;
-      for (int p = 2; p < k0.n; ++p) {
-        const int64_t len = k0.len[p];
-        w *= kb.kv[tid].v[p][rem % len];
-        rem /= len;
-      }
-    }
-    wrest[tid] = w;
-  }
   __syncthreads();
 
   const TD* base = D + b * static_cast<int64_t>(e1) * blk;
   TD* t = tile[wave];
-  // two blocks of loads in flight: the wave's blocks alternate between two register sets
-  vec_t ra0[PER], ra1[PER];
-  auto fetch = [&](int i1, vec_t* ra) {
+  vec_t ra[PER];                            // the next block's loads, in flight under the products
+  auto fetch = [&](int i1) {
     const TD* src = base + static_cast<int64_t>(i1) * blk;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -351,17 +336,18 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
   typename P::CFrag acc[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) acc[cb] = typename P::CFrag{};
-  // four independent MFMA chains a column block (steps of 4 values taken in turn), added
+  // two independent MFMA chains a column block (even and odd steps of 4 values), added
   // at the end: a dependent FP64 MFMA waits for the previous one's result
   auto compute = [&](int i1) {
-    typename P::CFrag c[4][NCB];
+    typename P::CFrag c[2][NCB];
 #pragma unroll
-    for (int h = 0; h < 4; ++h)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) c[h][cb] = typename P::CFrag{};
-    for (int k = 0; k < e0; k += 16) {
+#pragma unroll 2
+    for (int k = 0; k < e0; k += 8) {
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
+      for (int h = 0; h < 2; ++h) {
         const int i0 = k + 4 * h + lg;
         const double a = i0 < e0 ? W0[l16][i0] : 0.0;
 #pragma unroll
@@ -376,19 +362,14 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
     for (int v = 0; v < 4; ++v) {
       const double s1 = W1[P::crow(lane, v)][i1];
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb][v] += s1 * ((c[0][cb][v] + c[1][cb][v]) + (c[2][cb][v] + c[3][cb][v]));
+      for (int cb = 0; cb < NCB; ++cb) acc[cb][v] += s1 * (c[0][cb][v] + c[1][cb][v]);
     }
   };
-  if (wave < e1) fetch(wave, ra0);
-  if (wave + 4 < e1) fetch(wave + 4, ra1);
-  for (int i1 = wave; i1 < e1; i1 += 8) {
-    stage(ra0);
-    if (i1 + 8 < e1) fetch(i1 + 8, ra0);
+  if (wave < e1) fetch(wave);
+  for (int i1 = wave; i1 < e1; i1 += 4) {
+    stage(ra);
+    if (i1 + 4 < e1) fetch(i1 + 4);
     compute(i1);
-    if (i1 + 4 >= e1) break;
-    stage(ra1);
-    if (i1 + 12 < e1) fetch(i1 + 12, ra1);
-    compute(i1 + 4);
   }
   __syncthreads();                            // every wave is done with its tile
   double* red = reinterpret_cast<double*>(&tile[0][0]);     // [wave][term][column]
@@ -402,14 +383,21 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
     if (y >= m) continue;
     const int o = y * (16 * NCB) + j, ws = 16 * 16 * NCB;
     const double sum = ((red[o] + red[o + ws]) + red[o + 2 * ws]) + red[o + 3 * ws];
-    partial[(static_cast<int64_t>(y) * nb + b) * ncols + j] = wrest[y] * sum;
+    double wrest = 1.0;                       // the remaining factors at b's digits
+    int64_t rem = b;
+    for (int p = 2; p < k0.n; ++p) {
+      const int64_t len = k0.len[p];
+      wrest *= kb.kv[y].v[p][rem % len];
+      rem /= len;
+    }
+    partial[(static_cast<int64_t>(y) * nb + b) * ncols + j] = wrest * sum;
   }
 }
 
 // Whether the MFMA form covers this map and batch shape (never depends on the number
 // of terms, so a term takes the same form alone and in any batch).
 bool kron_mfma_eligible(int64_t rows, int ncols, const KronVec& k0, size_t esize, size_t partial_elems) {
-  if (k0.n < 2 || ncols > 64) return false;
+  if (k0.n < 2 || ncols > 48) return false;
   const int64_t e0 = k0.len[0], e1 = k0.len[1];
   if (e0 < 16 || e0 > kKmE0 || e1 < 4 || e1 > kKmE1) return false;
   const int64_t bytes = e0 * ncols * static_cast<int64_t>(esize);
@@ -425,8 +413,7 @@ void launch_kron_mfma(const TD* D, int ncols, const KronBatch& kb, int64_t nb, d
   switch ((ncols + 15) / 16) {
     case 1: hipLaunchKernelGGL((kron_mfma_kernel<TD, 1>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
     case 2: hipLaunchKernelGGL((kron_mfma_kernel<TD, 2>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
-    case 3: hipLaunchKernelGGL((kron_mfma_kernel<TD, 3>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
-    default: hipLaunchKernelGGL((kron_mfma_kernel<TD, 4>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+    default: hipLaunchKernelGGL((kron_mfma_kernel<TD, 3>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
   }
 }
 
