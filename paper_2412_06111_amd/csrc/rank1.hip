@@ -439,20 +439,38 @@ __global__ __launch_bounds__(64) void sum_blocks_kernel(const double* __restrict
   if (l == 0) w[y * wstride + j] = s;
 }
 
-// R[i + n j] += alpha_y * weight_y(i) * (w ? w[y wstride + j] : 1), the terms in order
+// R[i + n j] += alpha_y * weight_y(i) * (w ? w[y wstride + j] : 1), the terms in order.
+// The terms of a batch share their factor lengths (the caller checks), so a thread takes a
+// row i, splits it into factor digits once, forms alpha_y weight_y(i) for every term (each
+// weight multiplied out in factor order) and sweeps the columns j = blockIdx.y,
+// blockIdx.y + gridDim.y, ..; neighbouring lanes take neighbouring rows, so every column
+// access coalesces.
 __global__ void outer_acc_kernel(double* __restrict__ R, int64_t n, int ncols, KronBatch ku,
                                  const double* __restrict__ w, int64_t wstride) {
-  const int64_t total = n * ncols;
-  for (int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t i = e % n;
-    const int64_t j = e / n;
-    double r = R[e];
-    for (int y = 0; y < ku.m; ++y) {
-      const double wj = w ? w[y * wstride + j] : 1.0;
-      r += ku.alpha[y] * kron_weight(ku.kv[y], i) * wj;
+  const int np = ku.kv[0].n;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    double a[kRank1Batch];
+#pragma unroll
+    for (int y = 0; y < kRank1Batch; ++y) a[y] = 1.0;
+    int64_t row = i;
+    for (int p = 0; p < np; ++p) {
+      const int64_t e = ku.kv[0].len[p];
+      const int64_t dgt = row % e;
+      row /= e;
+#pragma unroll
+      for (int y = 0; y < kRank1Batch; ++y)
+        if (y < ku.m) a[y] *= ku.kv[y].v[p][dgt];
     }
-    R[e] = r;
+#pragma unroll
+    for (int y = 0; y < kRank1Batch; ++y) a[y] *= ku.alpha[y];
+    for (int j = blockIdx.y; j < ncols; j += gridDim.y) {
+      double r = R[i + n * j];
+#pragma unroll
+      for (int y = 0; y < kRank1Batch; ++y)
+        if (y < ku.m) r += a[y] * (w ? w[y * wstride + j] : 1.0);
+      R[i + n * j] = r;
+    }
   }
 }
 
@@ -499,12 +517,18 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
 
 void launch_outer_acc(double* R, int64_t n, int ncols, const KronBatch& ku, const double* w, int64_t wstride,
                       hipStream_t st) {
-  const int64_t total = n * ncols;
-  if (total <= 0 || ku.m <= 0) return;
-  int64_t blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(outer_acc_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, R, n, ncols, ku, w,
-                     wstride);
+  if (n <= 0 || ncols <= 0 || ku.m <= 0) return;
+  for (int y = 1; y < ku.m; ++y) {
+    TTNN_REQUIRE(ku.kv[y].n == ku.kv[0].n, TTNN_E_INVALID, "rank-1 terms of one batch differ in factor count");
+    for (int p = 0; p < ku.kv[0].n; ++p)
+      TTNN_REQUIRE(ku.kv[y].len[p] == ku.kv[0].len[p], TTNN_E_INVALID,
+                   "rank-1 terms of one batch differ in factor length");
+  }
+  // column groups enough for about 2^20 threads (the weights are formed once a group)
+  const int64_t cg = std::min<int64_t>(ncols, std::max<int64_t>(1, ((int64_t{1} << 20) + n - 1) / n));
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, std::max<int64_t>(1, 4096 / cg));
+  hipLaunchKernelGGL(outer_acc_kernel, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(cg)), dim3(256), 0,
+                     st, R, n, ncols, ku, w, wstride);
 }
 
 }  // namespace ttnn
