@@ -294,8 +294,10 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
   static_assert(4 * 16 * 16 * NCB * sizeof(double) <= 4 * kKmTile, "wave sums fit the tiles");
   typedef TD vec_t __attribute__((ext_vector_type(V)));
   __shared__ __align__(16) TD tile[4][TE];
-  __shared__ double W0[16][kKmE0];
-  __shared__ double W1[16][kKmE1];
+  // factor tables [position value][term]: the 16 lanes of a group read 16 consecutive
+  // doubles (with [term][value] rows of 512 bytes they hit one bank)
+  __shared__ double W0[kKmE0][16];
+  __shared__ double W1[kKmE1][16];
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -307,11 +309,11 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
 
   for (int e = tid; e < 16 * kKmE0; e += 256) {
     const int y = e / kKmE0, i = e % kKmE0;
-    W0[y][i] = (y < m && i < e0) ? kb.kv[y].v[0][i] : 0.0;
+    W0[i][y] = (y < m && i < e0) ? kb.kv[y].v[0][i] : 0.0;
   }
   for (int e = tid; e < 16 * kKmE1; e += 256) {
     const int y = e / kKmE1, i = e % kKmE1;
-    W1[y][i] = (y < m && i < e1) ? kb.kv[y].v[1][i] : 0.0;
+    W1[i][y] = (y < m && i < e1) ? kb.kv[y].v[1][i] : 0.0;
   }
   __syncthreads();
 
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int i0 = k + 4 * h + lg;
-        const double a = i0 < e0 ? W0[l16][i0] : 0.0;
+        const double a = i0 < e0 ? W0[i0][l16] : 0.0;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           const int j = 16 * cb + l16;
@@ -360,7 +362,7 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double s1 = W1[P::crow(lane, v)][i1];
+      const double s1 = W1[i1][P::crow(lane, v)];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[cb][v] += s1 * (c[0][cb][v] + c[1][cb][v]);
     }
