@@ -260,8 +260,11 @@ ttnn_status ttnn_sketch_update_rank1_batched(ttnn_plan_t plan, int32_t nterms, c
  *                               applied one or two at a time;
  *   TTNN_R1_GROUPED             where a map has two fastest factor positions of 16..64
  *                               and 4..64 values, at most 48 columns, a block of the
- *                               first position's rows within 6 KB and at least 1,024
- *                               blocks, the two positions are contracted on the FP64
+ *                               first position's rows within 6 KB and at least 256
+ *                               workgroups' work (blocks, each split over up to an
+ *                               eighth of the second position's length in workgroups
+ *                               where there are fewer than 1,024 blocks),
+ *                               the two positions are contracted on the FP64
  *                               MFMA for up to 16 terms at once: in groups of 16 a term
  *                               costs about a quarter of a term-wise one in the same
  *                               group and an eighth of a lone term, alone 1.3 times a

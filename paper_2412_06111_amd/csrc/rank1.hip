@@ -272,8 +272,10 @@ void launch_gemv_dt(const TD* D, int64_t rows, int ncols, const KronBatch& kb, i
 //   C_y[j] = sum_{i1 < e1} v1_y[i1] sum_{i0 < e0} v0_y[i0] D[i0 + e0 (i1 + e1 b)][j],
 // the inner sum as a 16 x 16 x 4 MFMA product with the terms as rows (A[y][i0] =
 // v0_y[i0]) and a 16-column block of the map as columns (B[i0][j], K = e0 in steps of
-// 4), then writes partial[(y nb + b) ncols + j] = wrest_y(b) C_y[j], wrest_y the
-// product of the remaining factors at b's digits.  Wave w takes i1 = w, w + 4, ..: it
+// 4), then writes partial[(y nb S + g) ncols + j] = wrest_y(b) C_y[j], wrest_y the
+// product of the remaining factors at b's digits.  A block's i1 range may be split over
+// S workgroups (partial row g = b S + s, written in place of b): wave w of split s
+// takes i1 = 4 s + w, 4 s + w + 4 S, ..; it
 // copies its e0 x ncols block of rows (contiguous in the map) into its own LDS buffer
 // from registers loaded one block ahead, so no barrier is needed inside the loop (a
 // wave's LDS accesses are in program order); the four waves' sums are added in wave
@@ -285,7 +287,7 @@ constexpr int kKmE1 = 64;         // largest e1
 
 template <typename TD, int NCB>
 __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D, int ncols, KronBatch kb,
-                                                       int64_t nb, double* __restrict__ partial) {
+                                                       int64_t nb, int S, double* __restrict__ partial) {
   using P = Pol<TTNN_F64>;
   constexpr int V = 16 / static_cast<int>(sizeof(TD));
   constexpr int TE = kKmTile / static_cast<int>(sizeof(TD));     // elements of a staged block
@@ -301,7 +303,9 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
 
   const int tid = threadIdx.x, lane = tid & 63, l16 = lane & 15, lg = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t b = blockIdx.x;
+  const int64_t g = blockIdx.x;             // partial row g: block b, i1 split s of S
+  const int64_t b = g / S;
+  const int s = static_cast<int>(g - b * S);
   const int m = kb.m;
   const KronVec& k0 = kb.kv[0];             // every term has the same factor lengths
   const int e0 = static_cast<int>(k0.len[0]), e1 = static_cast<int>(k0.len[1]);
@@ -367,10 +371,11 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
       for (int cb = 0; cb < NCB; ++cb) acc[cb][v] += s1 * (c[0][cb][v] + c[1][cb][v]);
     }
   };
-  if (wave < e1) fetch(wave);
-  for (int i1 = wave; i1 < e1; i1 += 4) {
+  const int i1s = 4 * s + wave, step = 4 * S;
+  if (i1s < e1) fetch(i1s);
+  for (int i1 = i1s; i1 < e1; i1 += step) {
     stage(ra);
-    if (i1 + 4 < e1) fetch(i1 + 4);
+    if (i1 + step < e1) fetch(i1 + step);
     compute(i1);
   }
   __syncthreads();                            // every wave is done with its tile
@@ -392,8 +397,18 @@ __global__ __launch_bounds__(256) void kron_mfma_kernel(const TD* __restrict__ D
       wrest *= kb.kv[y].v[p][rem % len];
       rem /= len;
     }
-    partial[(static_cast<int64_t>(y) * nb + b) * ncols + j] = wrest * sum;
+    partial[(static_cast<int64_t>(y) * nb * S + g) * ncols + j] = wrest * sum;
   }
+}
+
+// Workgroups a block's i1 range is split over (a partial row each): one where the map
+// has 1,024 blocks or more, else enough for 1,024 partial rows, each wave keeping at
+// least two steps.  A function of the map's shape only, never of the batch.
+int kron_mfma_split(int64_t nb, int64_t e1) {
+  if (nb >= 1024) return 1;
+  const int64_t want = (1024 + nb - 1) / nb;
+  const int64_t most = std::max<int64_t>(1, e1 / 8);
+  return static_cast<int>(std::min(want, most));
 }
 
 // Whether the MFMA form covers this map and batch shape (never depends on the number
@@ -405,17 +420,19 @@ bool kron_mfma_eligible(int64_t rows, int ncols, const KronVec& k0, size_t esize
   const int64_t bytes = e0 * ncols * static_cast<int64_t>(esize);
   if (bytes > kKmTile || bytes % 16 != 0) return false;
   const int64_t nb = rows / (e0 * e1);
-  return nb >= 1024 && nb * e0 * e1 == rows &&
-         static_cast<size_t>(nb) * static_cast<size_t>(ncols) * kRank1Batch <= partial_elems;
+  if (nb < 1 || nb * e0 * e1 != rows) return false;
+  const int64_t ns = nb * kron_mfma_split(nb, e1);
+  return ns >= 256 && static_cast<size_t>(ns) * static_cast<size_t>(ncols) * kRank1Batch <= partial_elems;
 }
 
 template <typename TD>
-void launch_kron_mfma(const TD* D, int ncols, const KronBatch& kb, int64_t nb, double* partial, hipStream_t st) {
-  const dim3 grid(static_cast<unsigned>(nb));
+void launch_kron_mfma(const TD* D, int ncols, const KronBatch& kb, int64_t nb, int S, double* partial,
+                      hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>(nb * S));
   switch ((ncols + 15) / 16) {
-    case 1: hipLaunchKernelGGL((kron_mfma_kernel<TD, 1>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
-    case 2: hipLaunchKernelGGL((kron_mfma_kernel<TD, 2>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
-    default: hipLaunchKernelGGL((kron_mfma_kernel<TD, 3>), grid, dim3(256), 0, st, D, ncols, kb, nb, partial); break;
+    case 1: hipLaunchKernelGGL((kron_mfma_kernel<TD, 1>), grid, dim3(256), 0, st, D, ncols, kb, nb, S, partial); break;
+    case 2: hipLaunchKernelGGL((kron_mfma_kernel<TD, 2>), grid, dim3(256), 0, st, D, ncols, kb, nb, S, partial); break;
+    default: hipLaunchKernelGGL((kron_mfma_kernel<TD, 3>), grid, dim3(256), 0, st, D, ncols, kb, nb, S, partial); break;
   }
 }
 
@@ -486,11 +503,12 @@ void launch_kron_gemv(const void* D, int dt, int64_t rows, int ncols, const Kron
   const size_t esize = dt == TTNN_F64 ? 8 : dt == TTNN_F32 ? 4 : 2;
   if (grouped && kron_mfma_eligible(rows, ncols, kb.kv[0], esize, partial_elems)) {
     const int64_t nbm = rows / (kb.kv[0].len[0] * kb.kv[0].len[1]);
-    if (dt == TTNN_F64) launch_kron_mfma(static_cast<const double*>(D), ncols, kb, nbm, partial, st);
-    else if (dt == TTNN_F32) launch_kron_mfma(static_cast<const float*>(D), ncols, kb, nbm, partial, st);
-    else launch_kron_mfma(static_cast<const uint16_t*>(D), ncols, kb, nbm, partial, st);
-    hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols, kb.m), dim3(64), 0, st, partial, static_cast<int>(nbm), ncols,
-                       w, wstride);
+    const int S = kron_mfma_split(nbm, kb.kv[0].len[1]);
+    if (dt == TTNN_F64) launch_kron_mfma(static_cast<const double*>(D), ncols, kb, nbm, S, partial, st);
+    else if (dt == TTNN_F32) launch_kron_mfma(static_cast<const float*>(D), ncols, kb, nbm, S, partial, st);
+    else launch_kron_mfma(static_cast<const uint16_t*>(D), ncols, kb, nbm, S, partial, st);
+    hipLaunchKernelGGL(sum_blocks_kernel, dim3(ncols, kb.m), dim3(64), 0, st, partial, static_cast<int>(nbm * S),
+                       ncols, w, wstride);
     return;
   }
   // >= 512 rows a block, at most 2048 blocks a term; the chunking depends on rows and

@@ -84,7 +84,8 @@ def test_rank1_batched_empty_is_noop(P):
 
 # leaf maps of 16^5 rows over five factor positions of 16, plans in the grouped rank-1
 # form: the two fastest positions contracted on the FP64 MFMA (4,096 blocks of 256
-# rows); FP32 and BF16 maps,
+# rows; the maps of 65,536 rows of (1,2) and (5,6), 256 blocks, each block split over
+# two workgroups); FP32 and BF16 maps,
 # TTNN and STTNN (whose chained nodes' positions are the short contracted groups and
 # take the other form), against the oracle on the same rounded maps at FP64 accuracy
 MFMA_CASES = [("ttnn-f32", "ttnn", "f32"), ("sttnn-f32", "sttnn", "f32"), ("ttnn-bf16", "ttnn", "bf16")]
